@@ -1,0 +1,353 @@
+/*
+ * Plain FP64 CPU oracle of the volume-averaged lattice Boltzmann model of
+ * Zhang, Wang & Ouyang, "Lattice Boltzmann Model for the Volume-Averaged
+ * Navier-Stokes Equations" (arXiv:1406.6438).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * statement of what one time step of the method computes.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  The GPU library shares no code, header, table or constant with it.
+ *
+ * Conventions (the paper's lattice units, delta_t = delta_x = 1):
+ *   populations f[i][y][x], i = 0..8, x fastest, stored as plain f_i;
+ *   porosity eps[y][x];
+ *   every floating point operation is IEEE binary64, round to nearest,
+ *   built with -ffp-contract=off so that no fused multiply-add changes it.
+ *
+ * One step, in the paper's order (final lattice Boltzmann equation, Section
+ * "Chapman-Enskog analysis", the equation following eq. VNS3):
+ *   collide every cell:  f*_i = f_i - (f_i - f_i^eq)/tau + P_i + F_i
+ *   stream (push):       f_i(x + e_i, t + 1) = f*_i(x, t)
+ * with f^eq from eq. (d2q9eq), P_i from eq. (pi), F_i from eq. (Fi), the
+ * density from eq. (0moment) and the velocity from eq. (1moment), and the
+ * drag force of Section "Examples and discussions" (Darcy-Forchheimer law
+ * with the Ergun closure for K and F_eps).
+ *
+ * Readings of points the paper leaves open (each one is listed in the design
+ * notes of this repository):
+ *   - the D2Q9 velocity set and weights are the textbook ones of Qian,
+ *     d'Humieres & Lallemand (1992), c_s^2 = 1/3, with the ordering below;
+ *   - "e . u" in eq. (d2q9eq) is e_i . u;
+ *   - the force F of eqs. (Fi) and (1moment) is an external body-force
+ *     density G plus the porous drag; the pressure correction P_i and F_i
+ *     share the same Guo form and are applied together with
+ *     T = c_s^2 rho grad(eps) + F;
+ *   - rho in p = c_s^2 rho is the intrinsic density (eps rho) / eps;
+ *   - grad(eps) is the isotropic lattice gradient 3 sum_i w_i e_i eps(x+e_i),
+ *     with eps mirrored across a wall (the wall lies half way between the
+ *     last fluid node and the next lattice node);
+ *   - eq. (1moment) is implicit in u because F depends on u; it is solved
+ *     exactly (the root is unique, see orc_velocity);
+ *   - walls are half-way bounce-back: a population that would stream into a
+ *     wall node returns to its own cell with the opposite velocity;
+ *   - the initial state is f_i = f_i^eq(eps(x) rho0, u0).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* D2Q9 velocity set of Qian et al. (1992): rest, 4 axis links, 4 diagonals. */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                            1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* OPP[i] is the index of -e_i. */
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+/* Squared lattice sound speed of D2Q9. */
+static const double CS2 = 1.0 / 3.0;
+
+enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
+enum { ORC_DRAG_ERGUN = 0, ORC_DRAG_CONST = 1 };
+
+/* Problem description (Section "Examples and discussions"). */
+typedef struct {
+    int32_t Lx, Ly;     /* lattice nodes along x and y                         */
+    int32_t bc_x, bc_y; /* ORC_PERIODIC or ORC_WALL (both ends of the axis)     */
+    int32_t drag;       /* ORC_DRAG_ERGUN: K, F_eps from d_p (Ergun closure)    */
+                        /* ORC_DRAG_CONST: K and F_eps given, uniform            */
+    int32_t pad_;
+    double tau;         /* BGK relaxation time, > 1/2                          */
+    double d_p;         /* particle diameter of the Ergun closure               */
+    double K, F_eps;    /* permeability and geometric function (DRAG_CONST)     */
+    double Gx, Gy;      /* external body-force density                         */
+    double rho0, u0x, u0y; /* initial state                                    */
+} orc_params;
+
+void orc_lattice(int32_t ex[9], int32_t ey[9], double w[9], int32_t opp[9], double *cs2)
+{
+    for (int i = 0; i < 9; i++) {
+        ex[i] = EX[i];
+        ey[i] = EY[i];
+        w[i] = W[i];
+        opp[i] = OPP[i];
+    }
+    *cs2 = CS2;
+}
+
+/* Porosity-modified equilibrium, eq. (d2q9eq):
+ *   f_i^eq = w_i eps rho [1 + e_i.u/c_s^2 + (e_i.u)^2/(2 c_s^4) - u.u/(2 c_s^2)]
+ * eps_rho is the product eps*rho. */
+void orc_feq(double eps_rho, double ux, double uy, double feq[9])
+{
+    double uu = ux * ux + uy * uy;
+    for (int i = 0; i < 9; i++) {
+        double eu = EX[i] * ux + EY[i] * uy;
+        feq[i] = W[i] * eps_rho *
+                 (1.0 + eu / CS2 + (eu * eu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    }
+}
+
+/* Discrete forcing term of Guo, Zheng & Shi (2002), the form shared by
+ * eq. (pi) (with the vector p grad eps) and eq. (Fi) (with the force F):
+ *   (1 - 1/(2 tau)) w_i [ (e_i - u)/c_s^2 + (e_i.u) e_i / c_s^4 ] . T
+ * Because the expression is linear in T, P_i + F_i is this term applied to
+ * T = p grad(eps) + F. */
+void orc_guo_source(double tau, double ux, double uy, double Tx, double Ty, double s[9])
+{
+    double pre = 1.0 - 1.0 / (2.0 * tau);
+    for (int i = 0; i < 9; i++) {
+        double eu = EX[i] * ux + EY[i] * uy;
+        double cx = (EX[i] - ux) / CS2 + eu * EX[i] / (CS2 * CS2);
+        double cy = (EY[i] - uy) / CS2 + eu * EY[i] / (CS2 * CS2);
+        s[i] = pre * W[i] * (cx * Tx + cy * Ty);
+    }
+}
+
+/* Drag coefficients of the Darcy-Forchheimer force of Section "Examples and
+ * discussions":  F_drag = -(eps^2 nu / K) u - (eps^3 F_eps / sqrt(K)) |u| u,
+ * returned as a = eps^2 nu / K and b = eps^3 F_eps / sqrt(K).
+ * Ergun closure: K = eps^3 d_p^2 / (150 (1 - eps)^2),
+ *                F_eps = 1.75 / sqrt(150 eps^3).
+ * nu = c_s^2 (tau - 1/2) (the viscosity of eq. (VNS2)).  At eps = 1 the
+ * Ergun permeability is infinite and both coefficients are zero; an infinite
+ * d_p likewise gives no drag. */
+void orc_drag_coeffs(const orc_params *p, double eps, double *a, double *b)
+{
+    double nu = CS2 * (p->tau - 0.5);
+    double K, Feps;
+    if (p->drag == ORC_DRAG_CONST) {
+        K = p->K;
+        Feps = p->F_eps;
+    } else {
+        if (eps >= 1.0 || isinf(p->d_p)) {
+            *a = 0.0;
+            *b = 0.0;
+            return;
+        }
+        K = eps * eps * eps * p->d_p * p->d_p / (150.0 * (1.0 - eps) * (1.0 - eps));
+        Feps = 1.75 / sqrt(150.0 * eps * eps * eps);
+    }
+    if (isinf(K)) {
+        *a = 0.0;
+        *b = 0.0;
+        return;
+    }
+    *a = eps * eps * nu / K;
+    *b = eps * eps * eps * Feps / sqrt(K);
+}
+
+/* Velocity from eq. (1moment):
+ *   eps rho u = m + (1/2) c_s^2 rho grad(eps) + (1/2) F(u),
+ *   F(u) = G - a u - b |u| u,
+ * with S = eps rho = sum f_i (eq. (0moment)) and m = sum e_i f_i.
+ * Collecting the u terms:  (S + a/2) u + (b/2) |u| u = V,
+ *   V = m + (1/2) (c_s^2 rho grad(eps) + G).
+ * u is parallel to V; its length s >= 0 solves (b/2) s^2 + (S + a/2) s = |V|,
+ * whose only non-negative root is s = 2|V| / (A + sqrt(A^2 + 4 B |V|)) with
+ * A = S + a/2, B = b/2 (the form without cancellation; it reduces to
+ * |V| / A when b = 0).  Outputs u and rho = S / eps. */
+void orc_velocity(const orc_params *p, double S, double mx, double my, double eps,
+                  double gex, double gey, double *ux, double *uy, double *rho)
+{
+    double a, b;
+    orc_drag_coeffs(p, eps, &a, &b);
+    double r = S / eps;
+    double Qx = CS2 * r * gex, Qy = CS2 * r * gey;
+    double Vx = mx + 0.5 * (Qx + p->Gx);
+    double Vy = my + 0.5 * (Qy + p->Gy);
+    double Vn = sqrt(Vx * Vx + Vy * Vy);
+    double A = S + 0.5 * a;
+    double B = 0.5 * b;
+    double den = A + sqrt(A * A + 4.0 * B * Vn);
+    *ux = 2.0 * Vx / den;
+    *uy = 2.0 * Vy / den;
+    *rho = r;
+}
+
+/* Lattice gradient of the porosity, 3 sum_i w_i e_i eps(x + e_i), which is
+ * exact for a linear field because sum_i w_i e_i e_i = c_s^2 I.  A neighbour
+ * beyond a wall takes the value of its mirror image across the wall (the
+ * wall sits half way, so node -1 mirrors to node 0 and node L to L-1). */
+static int nb_index(int v, int L, int bc)
+{
+    if (bc == ORC_PERIODIC) {
+        if (v < 0) return v + L;
+        if (v >= L) return v - L;
+        return v;
+    }
+    if (v < 0) return 0;
+    if (v >= L) return L - 1;
+    return v;
+}
+
+void orc_grad_eps(const orc_params *p, const double *eps, double *gx, double *gy)
+{
+    int Lx = p->Lx, Ly = p->Ly;
+    for (int y = 0; y < Ly; y++)
+        for (int x = 0; x < Lx; x++) {
+            double sx = 0.0, sy = 0.0;
+            for (int i = 0; i < 9; i++) {
+                int xn = nb_index(x + EX[i], Lx, p->bc_x);
+                int yn = nb_index(y + EY[i], Ly, p->bc_y);
+                double en = eps[(size_t)yn * Lx + xn];
+                sx += W[i] * EX[i] * en;
+                sy += W[i] * EY[i] * en;
+            }
+            gx[(size_t)y * Lx + x] = sx / CS2;
+            gy[(size_t)y * Lx + x] = sy / CS2;
+        }
+}
+
+/* Initial state (Section "Examples and discussions": density and velocity
+ * start at given values):  f_i(x, 0) = f_i^eq(eps(x) rho0, u0). */
+void orc_init(const orc_params *p, const double *eps, double *f)
+{
+    size_t N = (size_t)p->Lx * p->Ly;
+    double feq[9];
+    for (size_t c = 0; c < N; c++) {
+        orc_feq(eps[c] * p->rho0, p->u0x, p->u0y, feq);
+        for (int i = 0; i < 9; i++) f[i * N + c] = feq[i];
+    }
+}
+
+/* Per-cell macroscopic state of f: eps rho (eq. (0moment)), rho, u
+ * (eq. (1moment)) and the total vector T = c_s^2 rho grad(eps) + F(u) that
+ * drives P_i + F_i.  Any output pointer may be NULL. */
+static void cell_state(const orc_params *p, const double *f, size_t N, size_t c,
+                       double eps, double gex, double gey, double *S_out,
+                       double *mx_out, double *my_out, double *rho_out,
+                       double *ux_out, double *uy_out, double *Tx_out, double *Ty_out)
+{
+    double S = 0.0, mx = 0.0, my = 0.0;
+    for (int i = 0; i < 9; i++) {
+        double fi = f[i * N + c];
+        S += fi;
+        mx += EX[i] * fi;
+        my += EY[i] * fi;
+    }
+    double ux, uy, rho;
+    orc_velocity(p, S, mx, my, eps, gex, gey, &ux, &uy, &rho);
+    double a, b;
+    orc_drag_coeffs(p, eps, &a, &b);
+    double un = sqrt(ux * ux + uy * uy);
+    double Fx = p->Gx - a * ux - b * un * ux;
+    double Fy = p->Gy - a * uy - b * un * uy;
+    double Tx = CS2 * rho * gex + Fx;
+    double Ty = CS2 * rho * gey + Fy;
+    if (S_out) *S_out = S;
+    if (mx_out) *mx_out = mx;
+    if (my_out) *my_out = my;
+    if (rho_out) *rho_out = rho;
+    if (ux_out) *ux_out = ux;
+    if (uy_out) *uy_out = uy;
+    if (Tx_out) *Tx_out = Tx;
+    if (Ty_out) *Ty_out = Ty;
+}
+
+/* Collision of every cell (the right-hand side of the final lattice
+ * Boltzmann equation):  f*_i = f_i - (f_i - f_i^eq)/tau + P_i + F_i.
+ * gx, gy hold grad(eps) from orc_grad_eps.  fpost may not alias f. */
+void orc_collide(const orc_params *p, const double *eps, const double *gx,
+                 const double *gy, const double *f, double *fpost, int nthreads)
+{
+    long Ly = p->Ly;
+    size_t Lx = (size_t)p->Lx;
+    size_t N = Lx * (size_t)Ly;
+    (void)nthreads;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (long y = 0; y < Ly; y++) {
+        for (size_t x = 0; x < Lx; x++) {
+            size_t c = (size_t)y * Lx + x;
+            double S, rho, ux, uy, Tx, Ty, feq[9], src[9];
+            cell_state(p, f, N, c, eps[c], gx[c], gy[c], &S, NULL, NULL, &rho, &ux,
+                       &uy, &Tx, &Ty);
+            orc_feq(S, ux, uy, feq);
+            orc_guo_source(p->tau, ux, uy, Tx, Ty, src);
+            for (int i = 0; i < 9; i++) {
+                double fi = f[i * N + c];
+                fpost[i * N + c] = fi - (fi - feq[i]) / p->tau + src[i];
+            }
+        }
+    }
+}
+
+/* Streaming (push):  f_i(x + e_i) = f*_i(x).  Along a periodic axis the
+ * target wraps around; a target beyond a wall sends the population back to
+ * its own cell as the opposite direction (half-way bounce-back).  Every
+ * target slot is written exactly once, so f is fully overwritten. */
+void orc_stream(const orc_params *p, const double *fpost, double *f, int nthreads)
+{
+    long Ly = p->Ly;
+    int Lx = p->Lx;
+    size_t N = (size_t)Lx * (size_t)Ly;
+    (void)nthreads;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (long y = 0; y < Ly; y++) {
+        for (int x = 0; x < Lx; x++) {
+            size_t c = (size_t)y * Lx + x;
+            for (int i = 0; i < 9; i++) {
+                int xt = x + EX[i], yt = (int)y + EY[i];
+                int wall = 0;
+                if (xt < 0 || xt >= Lx) {
+                    if (p->bc_x == ORC_PERIODIC) xt = (xt + Lx) % Lx;
+                    else wall = 1;
+                }
+                if (yt < 0 || yt >= Ly) {
+                    if (p->bc_y == ORC_PERIODIC) yt = (int)((yt + Ly) % Ly);
+                    else wall = 1;
+                }
+                if (wall)
+                    f[OPP[i] * N + c] = fpost[i * N + c];
+                else
+                    f[i * N + (size_t)yt * Lx + xt] = fpost[i * N + c];
+            }
+        }
+    }
+}
+
+/* nsteps full time steps in place on f (collide, then stream).  scratch must
+ * hold 9*Lx*Ly doubles; gx, gy from orc_grad_eps. */
+void orc_steps(const orc_params *p, const double *eps, const double *gx, const double *gy,
+               double *f, double *scratch, int64_t nsteps, int nthreads)
+{
+    for (int64_t n = 0; n < nsteps; n++) {
+        orc_collide(p, eps, gx, gy, f, scratch, nthreads);
+        orc_stream(p, scratch, f, nthreads);
+    }
+}
+
+/* Macroscopic fields of the state f (eqs. (0moment), (1moment)):
+ * eps rho, rho, u, the raw first moment m = sum e_i f_i and the total
+ * vector T of P_i + F_i.  Any output may be NULL. */
+void orc_moments(const orc_params *p, const double *eps, const double *gx,
+                 const double *gy, const double *f, double *eps_rho, double *rho,
+                 double *ux, double *uy, double *mx, double *my, double *Tx, double *Ty)
+{
+    size_t N = (size_t)p->Lx * p->Ly;
+    for (size_t c = 0; c < N; c++) {
+        double S, m_x, m_y, r, vx, vy, tx, ty;
+        cell_state(p, f, N, c, eps[c], gx[c], gy[c], &S, &m_x, &m_y, &r, &vx, &vy, &tx,
+                   &ty);
+        if (eps_rho) eps_rho[c] = S;
+        if (rho) rho[c] = r;
+        if (ux) ux[c] = vx;
+        if (uy) uy[c] = vy;
+        if (mx) mx[c] = m_x;
+        if (my) my[c] = m_y;
+        if (Tx) Tx[c] = tx;
+        if (Ty) Ty[c] = ty;
+    }
+}

@@ -1,0 +1,77 @@
+"""Each plausible slip in the oracle must fail at least one pin.
+
+Every case copies the oracle's C source, plants one mistake (a dropped term, a
+flipped sign, a transposed index, a wrong constant), builds it with the same
+flags and runs the pin suite against that build in a fresh process.  The pin
+suite must fail for every mutant.  Nothing is planted in the real oracle.
+"""
+import concurrent.futures
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lbm_vans_oracle.c")
+
+MUTANTS = {
+    "feq_linear_sign": ("1.0 + eu / CS2", "1.0 - eu / CS2"),
+    "feq_drop_uu": ("- uu / (2.0 * CS2))", ")"),
+    "feq_quadratic_coeff": ("(eu * eu) / (2.0 * CS2 * CS2)", "(eu * eu) / (2.0 * CS2)"),
+    "source_sign_u": ("double cx = (EX[i] - ux) / CS2", "double cx = (EX[i] + ux) / CS2"),
+    "source_drop_prefactor": ("double pre = 1.0 - 1.0 / (2.0 * tau);", "double pre = 1.0;"),
+    "source_drop_second_order": ("+ eu * EX[i] / (CS2 * CS2)", ""),
+    "ergun_darcy_constant": ("/ (150.0 * (1.0 - eps) * (1.0 - eps))", "/ (180.0 * (1.0 - eps) * (1.0 - eps))"),
+    "ergun_forchheimer_constant": ("Feps = 1.75 / sqrt", "Feps = 1.5 / sqrt"),
+    "darcy_eps_power": ("*a = eps * eps * nu / K;", "*a = eps * nu / K;"),
+    "velocity_drop_half_Q": ("double Vx = mx + 0.5 * (Qx + p->Gx);", "double Vx = mx + 0.5 * p->Gx;"),
+    "velocity_half_drag": ("double A = S + 0.5 * a;", "double A = S + a;"),
+    "velocity_forchheimer_root": ("double B = 0.5 * b;", "double B = b;"),
+    "pressure_uses_eps_rho": ("double r = S / eps;", "double r = S;"),
+    "grad_transposed": ("sx += W[i] * EX[i] * en;", "sx += W[i] * EY[i] * en;"),
+    "grad_wall_wraps": ("    if (v < 0) return 0;\n", "    if (v < 0) return v + L;\n"),
+    "grad_scale": ("gx[(size_t)y * Lx + x] = sx / CS2;", "gx[(size_t)y * Lx + x] = sx;"),
+    "collide_drop_pressure_source": ("double Tx = CS2 * rho * gex + Fx;", "double Tx = Fx;"),
+    "collide_relax_times_tau": ("(fi - feq[i]) / p->tau", "(fi - feq[i]) * p->tau"),
+    "forchheimer_u_squared": ("double Fx = p->Gx - a * ux - b * un * ux;", "double Fx = p->Gx - a * ux - b * ux * ux;"),
+    "bounce_back_same_direction": ("f[OPP[i] * N + c] = fpost[i * N + c];", "f[i * N + c] = fpost[i * N + c];"),
+    "stream_opposite_direction": ("f[i * N + (size_t)yt * Lx + xt] = fpost[i * N + c];",
+                                  "f[OPP[i] * N + (size_t)yt * Lx + xt] = fpost[i * N + c];"),
+    "weights_swapped": ("1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,", "1.0 / 9.0,  1.0 / 36.0, 1.0 / 9.0,"),
+    "velocity_set_transposed": ("static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};",
+                                "static const int EY[9] = {0, 0, 1, 0, -1, 1, -1, -1, 1};"),
+    "init_ignores_eps": ("orc_feq(eps[c] * p->rho0,", "orc_feq(p->rho0,"),
+}
+
+
+def _kill(name, tmp):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique/found"
+    path = os.path.join(tmp, name + ".c")
+    with open(path, "w") as fh:
+        fh.write(src.replace(old, new))
+    lib = os.path.join(tmp, name + ".so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-fopenmp", "-o", lib, path, "-lm"])
+    env = dict(os.environ, LBM_VANS_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+def test_mutation_anchors_exist():
+    src = open(SRC).read()
+    for name, (old, _) in MUTANTS.items():
+        assert src.count(old) == 1, f"mutation anchor for {name} not unique/found"
+
+
+def test_every_mutant_fails_a_pin():
+    with tempfile.TemporaryDirectory() as tmp:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=6) as ex:
+            results = dict(ex.map(lambda n: _kill(n, tmp), MUTANTS))
+    survivors = [n for n, rc in results.items() if rc == 0]
+    assert not survivors, f"mutants not caught by any pin: {survivors}"

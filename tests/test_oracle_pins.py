@@ -1,0 +1,396 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: exact moment
+identities stated in the paper, textbook relations (lattice isotropy, Ergun's
+equation), closed-form and BVP solutions of the volume-averaged equations, an
+independently written textbook LBGK stepper, conservation laws and symmetries.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import refsol
+from paper_1406_6438_amd import workloads as W
+
+RNG = np.random.Generator(np.random.PCG64(20140625))
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+# --------------------------------------------------------------------------- lattice
+
+
+def test_lattice_isotropy(orc):
+    """D2Q9 (Qian et al. 1992): weights sum to 1, odd moments vanish, second moment
+    is c_s^2 delta, fourth moment is c_s^4 (dd + dd + dd); opposite of e_i is -e_i."""
+    ex, ey, w, opp, cs2 = orc.lattice()
+    e = np.stack([ex, ey], 1).astype(float)
+    assert np.all(w > 0)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.allclose(np.einsum("i,ia->a", w, e), 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, e, e), cs2 * np.eye(2), atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, e, e, e), 0, atol=1e-16)
+    d = np.eye(2)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e), cs2 ** 2 * iso, atol=1e-16)
+    assert np.all(e[opp] == -e)
+    assert np.all(e[0] == 0) and len(set(map(tuple, e))) == 9
+    assert abs(cs2 - 1.0 / 3.0) < 1e-16
+
+
+# --------------------------------------------------------------------------- equilibrium
+
+
+@pytest.mark.parametrize("trial", range(8))
+def test_equilibrium_moments(orc, trial):
+    """Moments of eq. (d2q9eq) listed in the Chapman-Enskog section: sum f^eq = eps rho,
+    sum e f^eq = eps rho u, sum e e f^eq = c_s^2 eps rho delta + eps rho u u, and the
+    third moment c_s^2 eps rho (d_ab u_c + d_ac u_b + d_bc u_a) (the printed form repeats
+    one term; the symmetric form is the one D2Q9 satisfies)."""
+    ex, ey, w, opp, cs2 = orc.lattice()
+    e = np.stack([ex, ey], 1).astype(float)
+    S = RNG.uniform(0.1, 2.0)
+    u = RNG.uniform(-0.1, 0.1, 2)
+    f = orc.feq(S, *u)
+    assert abs(f.sum() - S) <= 4e-16 * S
+    assert np.allclose(e.T @ f, S * u, rtol=0, atol=4e-16 * S)
+    M2 = np.einsum("i,ia,ib->ab", f, e, e)
+    assert np.allclose(M2, cs2 * S * np.eye(2) + S * np.outer(u, u), rtol=0, atol=1e-15 * S)
+    M3 = np.einsum("i,ia,ib,ic->abc", f, e, e, e)
+    d = np.eye(2)
+    ref3 = cs2 * S * (np.einsum("ab,c->abc", d, u) + np.einsum("ac,b->abc", d, u)
+                      + np.einsum("bc,a->abc", d, u))
+    assert np.allclose(M3, ref3, rtol=0, atol=1e-15 * S)
+
+
+def test_equilibrium_at_rest_is_weighted_mass(orc):
+    ex, ey, w, opp, cs2 = orc.lattice()
+    assert np.allclose(orc.feq(0.37, 0.0, 0.0), 0.37 * w, rtol=1e-15, atol=0)
+
+
+# --------------------------------------------------------------------------- sources
+
+
+@pytest.mark.parametrize("trial", range(8))
+def test_source_moments(orc, trial):
+    """Moments of P_i stated after eq. (pi): sum P = 0, sum e P = (1-1/2tau) c_s^2 rho grad eps,
+    sum e e P = (1-1/2tau)(u T + T u); the same holds for F_i of eq. (Fi) with T = F."""
+    ex, ey, w, opp, cs2 = orc.lattice()
+    e = np.stack([ex, ey], 1).astype(float)
+    tau = RNG.uniform(0.51, 2.0)
+    u = RNG.uniform(-0.1, 0.1, 2)
+    T = RNG.uniform(-1e-2, 1e-2, 2)
+    s = orc.guo_source(tau, *u, *T)
+    pre = 1.0 - 1.0 / (2.0 * tau)
+    scale = np.abs(T).max()
+    assert abs(s.sum()) < 1e-17 + 1e-15 * scale
+    assert np.allclose(e.T @ s, pre * T, rtol=0, atol=1e-15 * scale)
+    assert np.allclose(np.einsum("i,ia,ib->ab", s, e, e), pre * (np.outer(u, T) + np.outer(T, u)),
+                       rtol=0, atol=1e-15 * scale)
+
+
+def test_source_vanishes_at_tau_half_and_zero_force(orc):
+    assert np.all(orc.guo_source(0.5, 0.03, -0.02, 1e-3, 2e-3) == 0)
+    assert np.all(orc.guo_source(0.8, 0.03, -0.02, 0.0, 0.0) == 0)
+
+
+# --------------------------------------------------------------------------- drag law
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.3, 0.5, 0.65, 0.9, 0.99])
+def test_drag_matches_ergun_equation(orc, eps):
+    """Uniform steady flow balances the drag against -eps grad p (eq. (VNS3)); with
+    U_s = eps u this must equal eps times Ergun's textbook pressure gradient."""
+    tau, d_p = 0.8, 13.0
+    nu = (tau - 0.5) / 3.0
+    p = orc.Params(Lx=1, Ly=1, tau=tau, d_p=d_p)
+    a, b = orc.drag_coeffs(p, eps)
+    for u in (1e-5, 3e-3, 0.05):
+        drag = a * u + b * u * u
+        ref = eps * refsol.ergun_pressure_gradient(eps * u, mu=nu, rho=1.0, eps=eps, d_p=d_p)
+        assert abs(drag - ref) <= 1e-13 * ref
+
+
+def test_drag_vanishes_without_solid(orc):
+    p = orc.Params(Lx=1, Ly=1, tau=0.7, d_p=10.0)
+    assert orc.drag_coeffs(p, 1.0) == (0.0, 0.0)
+    assert orc.drag_coeffs(orc.Params(Lx=1, Ly=1, tau=0.7), 0.5) == (0.0, 0.0)  # d_p = inf
+
+
+def test_drag_constant_law(orc):
+    """F = -(eps^2 nu/K) u - (eps^3 F_eps/sqrt K)|u|u with K, F_eps given: Darcy and
+    Forchheimer parts scale as eps^2 and eps^3."""
+    p = orc.Params(Lx=1, Ly=1, tau=0.9, drag=orc.DRAG_CONST, K=4.0, F_eps=0.3)
+    a1, b1 = orc.drag_coeffs(p, 1.0)
+    a5, b5 = orc.drag_coeffs(p, 0.5)
+    assert abs(a1 - (0.4 / 3.0) / 4.0) < 1e-16 and abs(b1 - 0.15) < 1e-16
+    assert abs(a5 / a1 - 0.25) < 1e-15 and abs(b5 / b1 - 0.125) < 1e-15
+
+
+# --------------------------------------------------------------------------- velocity
+
+
+@pytest.mark.parametrize("trial", range(16))
+def test_velocity_solves_implicit_first_moment(orc, trial):
+    """eq. (1moment): eps rho u = m + (1/2) c_s^2 rho grad eps + (1/2) F(u) with
+    F(u) = G - a u - b |u| u.  The residual of the returned u must vanish."""
+    eps = RNG.uniform(0.2, 1.0)
+    p = orc.Params(Lx=1, Ly=1, tau=RNG.uniform(0.55, 1.5), d_p=RNG.uniform(0.5, 30.0),
+                   Gx=RNG.uniform(-1e-3, 1e-3), Gy=RNG.uniform(-1e-3, 1e-3))
+    S = eps * RNG.uniform(0.9, 1.1)
+    m = RNG.uniform(-0.05, 0.05, 2)
+    g = RNG.uniform(-0.05, 0.05, 2)
+    ux, uy, rho = orc.velocity(p, S, *m, eps, *g)
+    a, b = orc.drag_coeffs(p, eps)
+    u = np.array([ux, uy])
+    F = np.array([p.Gx, p.Gy]) - a * u - b * np.linalg.norm(u) * u
+    resid = S * u - (m + 0.5 * (rho / 3.0) * g + 0.5 * F)
+    assert abs(rho - S / eps) <= 1e-15 * rho
+    assert np.abs(resid).max() <= 1e-16 + 1e-15 * np.abs(m).max()
+
+
+def test_velocity_linear_drag_and_rest(orc):
+    """Without the Forchheimer term eq. (1moment) is linear: u = V / (eps rho + a/2)."""
+    p = orc.Params(Lx=1, Ly=1, tau=0.8, drag=orc.DRAG_CONST, K=2.0, F_eps=0.0, Gx=1e-4)
+    eps, S = 0.6, 0.61
+    a, _ = orc.drag_coeffs(p, eps)
+    ux, uy, _ = orc.velocity(p, S, 0.01, -0.02, eps, 0.0, 0.0)
+    assert abs(ux - (0.01 + 0.5e-4) / (S + 0.5 * a)) < 1e-17
+    assert abs(uy - (-0.02) / (S + 0.5 * a)) < 1e-17
+    q = orc.Params(Lx=1, Ly=1, tau=0.8, d_p=5.0)
+    assert orc.velocity(q, 0.5, 0.0, 0.0, 0.5, 0.0, 0.0)[:2] == (0.0, 0.0)
+
+
+# --------------------------------------------------------------------------- porosity gradient
+
+
+def test_grad_eps_exact_for_linear_field(orc):
+    """The lattice gradient is exact for a linear porosity (interior and periodic-free cells)."""
+    Lx, Ly = 12, 9
+    y, x = np.mgrid[0:Ly, 0:Lx]
+    eps = 0.5 + 0.013 * x - 0.021 * y
+    gx, gy = orc.grad_eps(orc.Params(Lx=Lx, Ly=Ly, tau=0.8, bc_x=orc.WALL, bc_y=orc.WALL), eps)
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.allclose(gx[inner], 0.013, atol=1e-15)
+    assert np.allclose(gy[inner], -0.021, atol=1e-15)
+    # a wall mirrors eps: the normal derivative at the first node is half the one-sided slope
+    assert np.allclose(gy[0, 1:-1], -0.021 * 0.5, atol=1e-15)
+    assert np.allclose(gx[1:-1, 0], 0.013 * 0.5, atol=1e-15)
+
+
+def test_grad_eps_periodic_sine(orc):
+    Lx = 64
+    eps = W.sine_porosity(Lx, 3)
+    gx, gy = orc.grad_eps(orc.Params(Lx=Lx, Ly=3, tau=0.8), eps)
+    x = np.arange(Lx)
+    k = 2 * np.pi / Lx
+    # central difference of a sine: amp sin(k) cos(k x)  (the D2Q9 stencil reduces to it)
+    assert np.allclose(gx[1], 0.2 * np.sin(k) * np.cos(k * x), atol=1e-15)
+    assert np.allclose(gy, 0.0, atol=1e-16)
+
+
+# --------------------------------------------------------------------------- whole steps
+
+
+def test_init_is_equilibrium_state(orc):
+    eps = W.grf_porosity(16, 12, seed=3, ell=3.0)
+    p = orc.Params(Lx=16, Ly=12, tau=0.7, rho0=1.2, u0x=0.01, u0y=-0.02)
+    f = orc.init(p, eps)
+    assert np.allclose(f.sum(0), 1.2 * eps, rtol=1e-15)
+    ex, ey, *_ = orc.lattice()
+    assert np.allclose(np.einsum("i,iyx->yx", ex, f), 1.2 * eps * 0.01, rtol=1e-13)
+    assert np.allclose(np.einsum("i,iyx->yx", ey, f), 1.2 * eps * -0.02, rtol=1e-13)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_mass_conserved(orc, walls):
+    """Collision conserves sum f (sum f^eq = sum f, sum P_i = sum F_i = 0); periodic
+    streaming and bounce-back move populations without loss: Σ_x eps rho is constant."""
+    eps = W.grf_porosity(48, 40, seed=11, ell=4.0)
+    p = orc.Params(Lx=48, Ly=40, tau=0.6, d_p=6.0, Gx=2e-5, Gy=-1e-5, u0x=0.01,
+                   bc_y=orc.WALL if walls else orc.PERIODIC)
+    f0 = orc.init(p, eps)
+    f = orc.steps(p, eps, f0, 1000)
+    assert abs(f.sum() - f0.sum()) <= 1e-13 * f0.sum()
+    assert np.all(np.isfinite(f))
+
+
+def test_momentum_budget_per_cell_and_global(orc):
+    """From the moment identities: sum e_i f*_i - m = T per cell (T = c_s^2 rho grad eps + F),
+    hence on a periodic box Σ_x m changes by Σ_x T each step."""
+    eps = W.grf_porosity(32, 24, seed=5, ell=3.0)
+    p = orc.Params(Lx=32, Ly=24, tau=0.7, d_p=4.0, Gx=3e-5, Gy=1e-5, u0x=0.02, u0y=-0.01)
+    ex, ey, *_ = orc.lattice()
+    f = orc.steps(p, eps, orc.init(p, eps), 7)
+    post = orc.collide(p, eps, f)
+    mom = orc.moments(p, eps, f)
+    dmx = np.einsum("i,iyx->yx", ex, post) - mom["mx"]
+    dmy = np.einsum("i,iyx->yx", ey, post) - mom["my"]
+    tol = 4e-15 * np.abs(post).max()  # a few roundings of the O(0.1) populations
+    assert np.abs(dmx - mom["Tx"]).max() < tol
+    assert np.abs(dmy - mom["Ty"]).max() < tol
+    f1 = orc.stream(p, post)
+    m1 = orc.moments(p, eps, f1)
+    tol = 1e-14 * np.abs(mom["mx"]).sum()
+    assert abs(m1["mx"].sum() - mom["mx"].sum() - mom["Tx"].sum()) < tol
+    assert abs(m1["my"].sum() - mom["my"].sum() - mom["Ty"].sum()) < tol
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_eps_one_reduces_to_textbook_lbgk_guo(orc, walls):
+    """At eps = 1 the porosity gradient and the Ergun drag vanish, and the scheme is
+    standard LBGK (eq. (BGK)) with the Guo discrete force for a constant body force."""
+    Lx, Ly, tau, G = 20, 14, 0.65, (3e-4, -2e-4)
+    eps = np.ones((Ly, Lx))
+    p = orc.Params(Lx=Lx, Ly=Ly, tau=tau, d_p=7.0, Gx=G[0], Gy=G[1],
+                   bc_y=orc.WALL if walls else orc.PERIODIC)
+    ex, ey, *_ = orc.lattice()
+    tb = refsol.TextbookLBGK(tau, G, walls_y=walls)
+    perm = tb.permutation_from(ex, ey)
+    f = orc.init(p, eps) + 1e-3 * W.noise((9, Ly, Lx), seed=7)
+    g = f[perm].copy()
+    f_or = orc.steps(p, eps, f, 60)
+    for _ in range(60):
+        g = tb.step(g)
+    assert np.abs(f_or[perm] - g).max() < 1e-14
+
+
+def test_uniform_state_reaches_darcy_forchheimer_balance(orc):
+    """Periodic box, uniform eps, uniform start: every cell follows the same scalar
+    history, and the steady state balances the body force against the drag,
+    G = a u + b u^2 (Section "Examples and discussions")."""
+    eps0, tau, d_p, G = 0.45, 0.7, 3.0, 2e-4
+    p = orc.Params(Lx=5, Ly=4, tau=tau, d_p=d_p, Gx=G)
+    eps = np.full((4, 5), eps0)
+    nu = (tau - 0.5) / 3.0
+    K = eps0 ** 3 * d_p ** 2 / (150 * (1 - eps0) ** 2)
+    Feps = 1.75 / math.sqrt(150 * eps0 ** 3)
+    ustar = refsol.uniform_steady_velocity(
+        G, lambda u: eps0 ** 2 * nu / K * u + eps0 ** 3 * Feps / math.sqrt(K) * u * u)
+    f = orc.run(p, eps, 3000)
+    m = orc.moments(p, eps, f)
+    assert np.ptp(m["ux"]) == 0.0 and np.abs(m["uy"]).max() < 1e-13 * ustar
+    assert abs(m["ux"][0, 0] - ustar) <= 1e-12 * ustar
+
+
+def test_rest_with_porosity_gradient_keeps_uniform_pressure(orc):
+    """At rest the volume-averaged momentum equation (eq. (VNS1)) requires -eps grad p = 0,
+    i.e. uniform density.  Without the P_i correction the scheme would instead keep
+    eps p uniform (eq. (VNS2)), a ±30% density variation for this porosity.  The
+    remaining variation is a lattice error and must fall at second order."""
+    spread = []
+    for L, n in ((32, 8000), (64, 20000)):
+        eps = W.sine_porosity(L, 2, 0.7, 0.2)
+        p = orc.Params(Lx=L, Ly=2, tau=0.8)
+        m = orc.moments(p, eps, orc.run(p, eps, n))
+        assert np.abs(m["ux"]).max() < 1e-9 and np.abs(m["uy"]).max() < 1e-12
+        spread.append(np.ptp(m["rho"]))
+    assert spread[1] < 2e-3
+    assert 3.5 < spread[0] / spread[1] < 4.5
+
+
+def _channel(orc, H, tau, eps0, G, steps, **drag):
+    p = orc.Params(Lx=3, Ly=H, tau=tau, bc_y=orc.WALL, Gx=G, **drag)
+    eps = np.full((H, 3), eps0)
+    f = orc.run(p, eps, steps)
+    m = orc.moments(p, eps, f)
+    m2 = orc.moments(p, eps, orc.steps(p, eps, f, 50))
+    assert np.abs(m2["ux"] - m["ux"]).max() < 1e-8 * np.abs(m["ux"]).max()  # steady
+    return m["ux"][:, 1]
+
+
+def test_channel_matches_brinkman_closed_form(orc):
+    """Body-force channel with linear (Darcy) drag only: the lattice profile converges at
+    second order to the closed form of nu eps u'' - a u + G = 0 (walls half way)."""
+    tau, eps0, K = 0.8, 0.5, 10.24
+    nu = (tau - 0.5) / 3.0
+    errs = []
+    for H, n in ((16, 3000), (32, 6000)):
+        Ks = K * (H / 32.0) ** 2                # fixed Da
+        G = 8e-6 * (32.0 / H) ** 3              # fixed Re
+        u = _channel(orc, H, tau, eps0, G, n, drag=orc.DRAG_CONST, K=Ks, F_eps=0.0)
+        a = eps0 ** 2 * nu / Ks
+        ref = refsol.brinkman_channel(H, nu, eps0, a, G, np.arange(H) + 0.5)
+        errs.append(rel(u, ref))
+    assert errs[1] < 2e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5
+    assert np.allclose(u, u[::-1], rtol=1e-12, atol=0)  # mirror symmetry about mid-channel
+
+
+def test_channel_matches_brinkman_forchheimer_bvp(orc):
+    """The 64x32 porous channel workload (eps 0.5, tau 0.8, Da 1e-2, Re ~ 1) against the
+    Brinkman-Forchheimer ODE (the paper's eq. (velocity) with a body force), and at
+    second order under refinement.  The Forchheimer term shifts the profile by 1.5%,
+    well above the lattice error, so the nonlinear drag is pinned too."""
+    w = W.CHANNEL_64x32
+    nu = (w.tau - 0.5) / 3.0
+    errs = []
+    for H, n in ((16, 3000), (32, 5000)):
+        d_p = W.ergun_dp_for_darcy(1e-2, H, w.eps_value)
+        G = w.Gx * (32.0 / H) ** 3
+        u = _channel(orc, H, w.tau, w.eps_value, G, n, d_p=d_p)
+        a, b = orc.drag_coeffs(orc.Params(Lx=1, Ly=1, tau=w.tau, d_p=d_p), w.eps_value)
+        y = np.arange(H) + 0.5
+        ref = refsol.bf_channel(H, nu, w.eps_value, a, b, G, y)
+        errs.append(rel(u, ref))
+        if H == 32:
+            assert rel(refsol.brinkman_channel(H, nu, w.eps_value, a, G, y), ref) > 1e-2
+    assert errs[1] < 2e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_channel_workload_constants():
+    """Da = K/H^2 = 1e-2 with the Ergun K at eps = 0.5, and Re = U H / nu = 1 with U the
+    peak of the Brinkman profile."""
+    w = W.CHANNEL_64x32
+    nu = (w.tau - 0.5) / 3.0
+    eps = w.eps_value
+    K = eps ** 3 * w.d_p ** 2 / (150 * (1 - eps) ** 2)
+    assert abs(K / 32.0 ** 2 - 1e-2) < 1e-15
+    a = eps ** 2 * nu / K
+    umax = refsol.brinkman_channel(32, nu, eps, a, w.Gx, np.array([16.0]))[0]
+    assert abs(umax * 32 / nu - 1.0) < 1e-3
+
+
+def test_rotation_and_reflection_symmetry(orc):
+    """A 90-degree rotation (and an x-reflection) of porosity, force and initial flow
+    rotates (reflects) the fields on a periodic box: catches index and sign slips."""
+    L = 24
+    eps = W.grf_porosity(L, L, seed=9, ell=3.0)
+    p = orc.Params(Lx=L, Ly=L, tau=0.62, d_p=5.0, Gx=4e-5, Gy=1e-5)
+    m = orc.moments(p, eps, orc.run(p, eps, 120))
+    # rotation by +90 degrees: (x, y) -> (-y, x), u -> (-uy, ux)
+    eps_r = np.rot90(eps, k=1, axes=(1, 0)).copy()  # eps_r[y', x'] with x' = -y, y' = x
+    eps_r = np.zeros_like(eps)
+    for y in range(L):
+        for x in range(L):
+            eps_r[x, (-y) % L] = eps[y, x]
+    pr = orc.Params(Lx=L, Ly=L, tau=0.62, d_p=5.0, Gx=-1e-5, Gy=4e-5)
+    mr = orc.moments(pr, eps_r, orc.run(pr, eps_r, 120))
+    ux_r = np.zeros_like(eps)
+    uy_r = np.zeros_like(eps)
+    for y in range(L):
+        for x in range(L):
+            ux_r[x, (-y) % L] = -m["uy"][y, x]
+            uy_r[x, (-y) % L] = m["ux"][y, x]
+    scale = np.abs(m["ux"]).max()
+    assert np.abs(mr["ux"] - ux_r).max() < 1e-13 * scale
+    assert np.abs(mr["uy"] - uy_r).max() < 1e-13 * scale
+    # reflection x -> -x
+    eps_f = eps[:, (-np.arange(L)) % L]
+    pf = orc.Params(Lx=L, Ly=L, tau=0.62, d_p=5.0, Gx=-4e-5, Gy=1e-5)
+    mf = orc.moments(pf, eps_f, orc.run(pf, eps_f, 120))
+    assert np.abs(mf["ux"] + m["ux"][:, (-np.arange(L)) % L]).max() < 1e-13 * scale
+    assert np.abs(mf["uy"] - m["uy"][:, (-np.arange(L)) % L]).max() < 1e-13 * scale
+
+
+def test_thread_count_does_not_change_results(orc):
+    eps = W.grf_porosity(40, 33, seed=2, ell=4.0)
+    p = orc.Params(Lx=40, Ly=33, tau=0.6, d_p=6.0, Gx=1e-5, bc_y=orc.WALL)
+    a = orc.run(p, eps, 50, threads=1)
+    b = orc.run(p, eps, 50, threads=4)
+    assert np.array_equal(a, b)

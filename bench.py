@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D2Q9 volume-averaged LB sweep on one MI355X.
+
+Workload (default): the 4096 x 4096 periodic porous box -- Gaussian-random-field
+porosity (correlation length 16) in [0.3, 1.0], tau = 0.6, body force 1e-6 along
+x, Ergun drag, FP32 populations stored as deviations from the local rest state.
+A step is one time step of the method over the whole lattice (one sweep
+launch).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line with MLUPS, the HBM roofline of the sweep kernel, the
+accuracy of the FP32 sweep against the FP64 oracle on the 512^2 crop (the error
+the throughput is quoted at) and the oracle's own throughput on the host cores.
+
+  python bench.py [--steps K] [--warmup W] [--workload box4096_f32|box8192_f16|channel_f64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E peak
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sweep_traffic_box4096_f32.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_node(storage: str) -> int:
+    """Population loads + stores of one node plus its porosity load."""
+    pop = {"f64": 8, "f32": 4, "f16": 2}[storage]
+    eps = 8 if storage == "f64" else 4
+    return 9 * pop + 9 * pop + eps
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if workload != "box4096_f32" or not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    txt = open(PROFILE_TRAFFIC).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def copy_bandwidth_gbps(torch, nbytes=2 << 30, reps=10) -> float:
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / dt / 1e9
+
+
+def make_workload(name: str):
+    from paper_1406_6438_amd import workloads as W
+    return {"box4096_f32": W.BOX_4096_F32, "box8192_f16": W.BOX_8192_F16,
+            "channel_f64": W.CHANNEL_64x32}[name]
+
+
+def lbm_params(w, lbm, Lx=None, Ly=None):
+    return lbm.Params(Lx=Lx or w.Lx, Ly=Ly or w.Ly, tau=w.tau,
+                      bc_y=lbm.BC_BOUNCEBACK if w.walls_y else lbm.BC_PERIODIC,
+                      storage=lbm.STORAGE[w.storage], d_p=w.d_p, G=(w.Gx, w.Gy),
+                      rho0=w.rho0, fp16_scale_log2=10)
+
+
+def cast_eps(eps, storage):
+    import numpy as np
+    return eps if storage == "f64" else eps.astype(np.float32).astype(np.float64)
+
+
+def cpu_baseline(w, eps, budget_s: float):
+    """The FP64 oracle timed on the host cores on a bounded sample of the workload:
+    the full lattice for as many whole steps as fit in the time budget."""
+    import numpy as np
+    import oracle
+    p = oracle.Params(Lx=w.Lx, Ly=w.Ly, tau=w.tau, bc_y=oracle.WALL if w.walls_y else oracle.PERIODIC,
+                      d_p=w.d_p, Gx=w.Gx, Gy=w.Gy, rho0=w.rho0)
+    threads = oracle.default_threads()
+    e = cast_eps(eps, w.storage)
+    f = oracle.init(p, e)
+    t0 = time.perf_counter()
+    f = oracle.steps(p, e, f, 1, threads)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(int(budget_s / max(t1, 1e-9)), 100000))
+    t0 = time.perf_counter()
+    oracle.steps(p, e, f, k, threads)
+    dt = time.perf_counter() - t0
+    del f
+    return {"value": round(w.Lx * w.Ly * k / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{w.Lx}x{w.Ly} lattice of the same workload, {k} FP64 steps after 1 "
+                      f"untimed step ({dt:.1f} s), OpenMP over rows"}
+
+
+def accuracy(w, lbm, torch, steps: int):
+    """FP32/FP16 sweep vs the FP64 oracle on the top-left 512^2 crop, run periodic."""
+    import numpy as np
+    import oracle
+    from paper_1406_6438_amd import workloads as W
+    n = W.CROP
+    eps = cast_eps(W.crop_porosity(w, n), w.storage)
+    s = lbm.Solver(lbm_params(w, lbm, n, n), eps)
+    s.step(steps)
+    m = s.moments(want_diag=False)
+    ux = m["ux"].double().cpu().numpy()
+    uy = m["uy"].double().cpu().numpy()
+    s.close()
+    p = oracle.Params(Lx=n, Ly=n, tau=w.tau, d_p=w.d_p, Gx=w.Gx, Gy=w.Gy, rho0=w.rho0)
+    mo = oracle.moments(p, eps, oracle.run(p, eps, steps))
+    ug, uo = np.hypot(ux, uy), np.hypot(mo["ux"], mo["uy"])
+    return {"rel_l2_u_vs_fp64_oracle": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)),
+            "sample": f"top-left {n}x{n} crop of the porosity field, periodic, {steps} steps"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="box4096_f32",
+                    choices=["box4096_f32", "box8192_f16", "channel_f64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the sweep has no multi-GPU path in this build "
+              "(domain decomposition is design only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1406_6438_amd import lbm
+
+    lbm.load()
+    w = make_workload(args.workload)
+    log(f"[bench] workload {w.name}: {w.Lx}x{w.Ly}, storage {w.storage}")
+    eps = w.porosity()
+    s = lbm.Solver(lbm_params(w, lbm), cast_eps(eps, w.storage))
+    log(f"[bench] warmup {args.warmup} steps")
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = s.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    diag = s.moments()["diag"]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    log(f"[bench] timed {args.steps} steps: {gpu_s * 1e3:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    cells = w.Lx * w.Ly
+    mlups = cells * args.steps / gpu_s / 1e6
+    bpn = algorithmic_bytes_per_node(w.storage)
+    launch_s = gpu_s / args.steps
+    achieved = bpn * cells / launch_s / 1e9
+    traffic = measured_traffic(args.workload)
+    copy_bw = copy_bandwidth_gbps(torch)
+    log(f"[bench] {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic, device copy {copy_bw:.1f} GB/s")
+
+    acc = None
+    if not args.no_accuracy and w.storage != "f64":
+        log("[bench] accuracy: 512^2 crop vs FP64 oracle")
+        acc = accuracy(w, lbm, torch, 1000 if w.storage == "f32" else 2000)
+        log(f"[bench] accuracy {acc['rel_l2_u_vs_fp64_oracle']:.3e}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(w, eps, args.cpu_seconds)
+        log(f"[bench] cpu baseline {cpu['value']} MLUPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": "MLUPS & % HBM roofline (D2Q9 FP32 fwd, FP16-store, adjoint) at fixed error",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(gpu_s * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-store/f32"}[w.storage],
+        "data": "synthetic",
+        "config": {"workload": w.name, "Lx": w.Lx, "Ly": w.Ly, "tau": w.tau,
+                   "porosity": "GRF l=16 in [0.3,1.0]" if w.eps_kind == "grf" else f"uniform {w.eps_value}",
+                   "d_p": round(w.d_p, 4), "G": [w.Gx, w.Gy], "storage": w.storage,
+                   "boundaries": "periodic" if not w.walls_y else "periodic x, bounce-back y"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic, "kernel": "k_sweep", "bytes_per_node": bpn,
+                     "launch_us": round(launch_s * 1e6, 2),
+                     "device_copy_GBps": round(copy_bw, 1)},
+        "accuracy": acc,
+        "cpu_baseline": cpu,
+        "mass_check": {"sum_eps_rho": diag[0], "nonfinite_nodes": diag[6]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * lbm_vans.h -- C-ABI of the MI355X (gfx950) volume-averaged lattice
+ * Boltzmann solver.
+ *
+ * The method is the D2Q9 lattice Boltzmann model of Zhang, Wang & Ouyang,
+ * "Lattice Boltzmann Model for the Volume-Averaged Navier-Stokes Equations"
+ * (arXiv:1406.6438): BGK relaxation toward the porosity-weighted equilibrium
+ * of eq. (d2q9eq), the pressure-correction term P_i of eq. (pi), the Guo
+ * force term F_i of eq. (Fi) carrying a body force plus the Darcy-Forchheimer
+ * drag with the Ergun closure (Section "Examples and discussions"), the
+ * density and velocity of eqs. (0moment) and (1moment), periodic or
+ * half-way bounce-back boundaries.  One time step is the final lattice
+ * Boltzmann equation of the Chapman-Enskog section:
+ *     f_i(x + e_i, t + 1) = f_i - (f_i - f_i^eq)/tau + P_i + F_i.
+ *
+ * Lattice units throughout (delta_t = delta_x = 1), D2Q9 with c_s^2 = 1/3 and
+ * the velocity ordering
+ *     e_0 = (0,0), e_1 = (1,0), e_2 = (0,1), e_3 = (-1,0), e_4 = (0,-1),
+ *     e_5 = (1,1), e_6 = (-1,1), e_7 = (-1,-1), e_8 = (1,-1).
+ * Every plain field is row-major [Ly][Lx] (x fastest); a population field is
+ * [9][Ly][Lx].
+ *
+ * Memory.  The library allocates no device memory.  The caller passes one
+ * device work buffer of lbm_vans_work_bytes() bytes (256-byte aligned) and
+ * keeps it alive until lbm_vans_destroy(); the library never frees it.
+ * Every other pointer is borrowed for the duration of the call only.  The
+ * handle itself is a small host struct owned by the library.
+ *
+ * Streams.  Every call enqueues its work on the HIP stream given to
+ * lbm_vans_init() (NULL = the null stream) and returns without waiting,
+ * except where a call says it synchronises.
+ *
+ * Errors.  Every int-returning call returns LBM_VANS_OK (0) or a negative
+ * code and sets a thread-local message readable with lbm_vans_last_error().
+ * No C++ exception crosses this interface.
+ *
+ * Threads.  A handle may be used by one host thread at a time.  Calls on
+ * different handles are independent.
+ */
+#ifndef LBM_VANS_H
+#define LBM_VANS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_VANS_ABI_VERSION 1
+
+/* Return codes. */
+#define LBM_VANS_OK 0
+#define LBM_VANS_EINVAL (-1)     /* invalid argument (message says which)            */
+#define LBM_VANS_EHIP (-2)       /* a HIP runtime call failed (message has its text)  */
+#define LBM_VANS_ENONFINITE (-3) /* diagnostics found a NaN or Inf in the state       */
+#define LBM_VANS_ENOTIMPL (-4)   /* the requested feature is not built                */
+
+/* Boundary kind of one axis (applies to both ends of that axis). */
+#define LBM_BC_PERIODIC 0   /* wrap-around streaming (Section "Examples and discussions") */
+#define LBM_BC_BOUNCEBACK 1 /* half-way bounce-back wall beyond node -1/2 and L-1/2       */
+
+/* Population storage.  The collision arithmetic is FP64 for LBM_F64 and FP32
+ * otherwise.  The shifted forms store the deviation of each population from
+ * the local rest state w_i eps rho0, which keeps the significant digits of
+ * the flow in the stored bits. */
+#define LBM_F64 0
+#define LBM_F32_SHIFTED 1
+#define LBM_F16_SHIFTED 2
+
+/* Drag law of the force F (Section "Examples and discussions"):
+ *     F = G - (eps^2 nu / K) u - (eps^3 F_eps / sqrt(K)) |u| u.
+ * LBM_DRAG_ERGUN: K = eps^3 d_p^2 / (150 (1-eps)^2), F_eps = 1.75/sqrt(150 eps^3)
+ *                 (Ergun closure); d_p = INFINITY gives no drag.
+ * LBM_DRAG_CONST: K and F_eps given directly (uniform); K = INFINITY gives no drag. */
+#define LBM_DRAG_ERGUN 0
+#define LBM_DRAG_CONST 1
+
+/* Number of doubles in one diagnostics record (see lbm_vans_moments). */
+#define LBM_VANS_NDIAG 8
+/* Records kept by the in-sweep diagnostics ring (see lbm_vans_diag_read). */
+#define LBM_VANS_DIAG_RING 4096
+
+typedef struct lbm_vans_params {
+    int32_t Lx, Ly;        /* lattice nodes, 1 <= Lx, Ly; Lx*Ly < 2^31               */
+    int32_t bc_x, bc_y;    /* LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK                    */
+    int32_t storage;       /* LBM_F64, LBM_F32_SHIFTED or LBM_F16_SHIFTED             */
+    int32_t drag;          /* LBM_DRAG_ERGUN or LBM_DRAG_CONST                        */
+    double tau;            /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3         */
+    double d_p;            /* Ergun particle diameter (> 0, may be INFINITY)          */
+    double K, F_eps;       /* LBM_DRAG_CONST: permeability (> 0, may be INFINITY), F_eps >= 0 */
+    double G[2];           /* external body-force density in the (eps rho u) equation */
+    double rho0;           /* initial density (> 0); also the storage shift reference */
+    double u0[2];          /* initial velocity                                        */
+    int32_t fp16_scale_log2; /* LBM_F16_SHIFTED: stored value = deviation * 2^s, 0..24 */
+    int32_t diag_every;    /* > 0: record diagnostics of every state n with n % diag_every == 0
+                              during lbm_vans_step; 0: none                           */
+} lbm_vans_params;
+
+typedef struct lbm_vans_handle lbm_vans_handle;
+
+/* Bytes of device work memory the solver needs for these parameters, or 0 if
+ * the parameters are invalid (lbm_vans_last_error() says why). */
+size_t lbm_vans_work_bytes(const lbm_vans_params *p);
+
+/* Create a solver and set the state to the initial condition of Section
+ * "Examples and discussions" (density rho0 and velocity u0 everywhere):
+ *     f_i(x, 0) = f_i^eq(eps(x) rho0, u0)            (eq. (d2q9eq)).
+ * eps:   device pointer to the porosity field [Ly][Lx], double for LBM_F64,
+ *        float otherwise; every value in (0, 1].  It is copied into the work
+ *        buffer, so the caller may free it after this call returns.
+ * work:  device buffer of at least lbm_vans_work_bytes(p) bytes, 256-byte
+ *        aligned, owned by the caller, not touched by anyone else while the
+ *        handle lives.
+ * stream: hipStream_t to run on (NULL = null stream).
+ * On success *out receives the handle.  The porosity check synchronises the
+ * stream once.  Returns LBM_VANS_EINVAL for invalid parameters, a short or
+ * misaligned work buffer, or a porosity outside (0, 1]. */
+int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t work_bytes,
+                  void *stream, lbm_vans_handle **out);
+
+/* Advance nsteps (>= 0) time steps of the final lattice Boltzmann equation:
+ * for every node, the moments of eqs. (0moment)/(1moment) (velocity implicit
+ * through the drag, solved exactly), collision toward eq. (d2q9eq) with the
+ * sources of eqs. (pi) and (Fi), and streaming with the boundary rule, fused
+ * in one pass per step.  Asynchronous. */
+int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps);
+
+/* Number of steps taken since init (the current state is f(., n)). */
+int64_t lbm_vans_step_count(const lbm_vans_handle *h);
+
+/* Macroscopic fields of the current state f(., n) (eqs. (0moment), (1moment)):
+ * eps_rho, rho, ux, uy are device arrays [Ly][Lx] of the compute type (double
+ * for LBM_F64, float otherwise); any may be NULL.
+ * diag: host array of LBM_VANS_NDIAG doubles or NULL.  When given, the call
+ * reduces in FP64 on the device and synchronises the stream, then fills
+ *   diag[0] = sum_x eps rho            diag[1], diag[2] = sum_x m (m = sum_i e_i f_i)
+ *   diag[3], diag[4] = sum_x eps rho u diag[5] = max_x |u|
+ *   diag[6] = number of nodes whose moments are not finite
+ *   diag[7] = n (step index).
+ * Returns LBM_VANS_ENONFINITE (after filling diag) if diag[6] > 0. */
+int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, void *uy,
+                     double *diag);
+
+/* Copy the current state f(., n) out as plain populations: f is a device
+ * array of 9*Ly*Lx doubles in the layout [9][Ly][Lx]. */
+int lbm_vans_get_state(lbm_vans_handle *h, void *f);
+
+/* Replace the current state with the plain populations f (device, 9*Ly*Lx
+ * doubles, [9][Ly][Lx]); the step counter is kept.  Storage rounding applies. */
+int lbm_vans_set_state(lbm_vans_handle *h, const void *f);
+
+/* Copy the in-sweep diagnostics records (params.diag_every > 0) to the host,
+ * oldest first: at most max_records records of LBM_VANS_NDIAG doubles with the
+ * meaning of lbm_vans_moments' diag, for the states n = 0, k, 2k, ... swept so
+ * far (the last LBM_VANS_DIAG_RING of them).  *n_records receives the count.
+ * Synchronises the stream.  Returns LBM_VANS_ENONFINITE if any copied record
+ * counts non-finite nodes. */
+int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
+                       int32_t *n_records);
+
+/* Gradient of an objective with respect to eps(x) through the reverse
+ * (adjoint) sweep.  Not built: returns LBM_VANS_ENOTIMPL. */
+int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
+                  double *dJdeps, double *J);
+
+/* Release the handle (host memory only; the work buffer stays the caller's).
+ * Waits for the handle's queued work first.  NULL is ignored. */
+void lbm_vans_destroy(lbm_vans_handle *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_vans_last_error(void);
+
+/* LBM_VANS_ABI_VERSION of the built library. */
+int lbm_vans_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_VANS_H */

@@ -1,0 +1,987 @@
+// lbm_vans.hip -- gfx950 kernels and C-ABI of the volume-averaged lattice
+// Boltzmann solver (Zhang, Wang & Ouyang, arXiv:1406.6438).
+//
+// Hot path: one fused pull sweep per time step.  Each thread owns one node x
+// of one row and, in a single pass,
+//   1. gathers f_i(x, n) from the post-collision populations of step n-1 at
+//      x - e_i (periodic wrap, or the node's own opposite population behind a
+//      half-way bounce-back wall);
+//   2. forms eps rho (eq. (0moment)) and m = sum_i e_i f_i;
+//   3. takes grad(eps) from an LDS tile of the porosity with a one-node halo,
+//      the drag coefficients of the Ergun law from eps, and solves the
+//      implicit velocity of eq. (1moment) in closed form;
+//   4. relaxes toward the equilibrium of eq. (d2q9eq) and adds P_i + F_i
+//      (eqs. (pi), (Fi)) in their common Guo form;
+//   5. writes the 9 post-collision populations to its own node of the other
+//      buffer (aligned, coalesced stores).
+// The sweep moves 9 population loads, 9 population stores and one porosity
+// load per node from HBM, so it is bandwidth-bound; there is no dense
+// contraction and no MFMA.
+//
+// Storage.  Populations live in two SoA buffers [9][Ly][pitch] (x fastest,
+// pitch a multiple of 64 nodes).  Slot (i, s) holds the post-collision value
+// f*_i(s) minus the rest state w_i rho0 eps(r) of the node r that will pull
+// it next: r = s + e_i, or s itself when s + e_i lies behind a wall.  With
+// this choice the gathered value at x is directly the deviation
+// d_i = f_i(x) - w_i rho0 eps(x), so the moments and the collision work on
+// small numbers only (FP32 and FP16 keep the significant digits of the flow)
+// and the gather needs no neighbour porosity.  The shift of each stored value
+// needs eps at x + e_i, which the porosity tile already holds.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+
+#include "lbm_vans.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LBM_VANS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Launch geometry
+// ---------------------------------------------------------------------------
+
+constexpr int TX = 64;      // nodes per row segment: one wavefront
+constexpr int NW = 4;       // wavefronts per block
+constexpr int ROWS = 2;     // rows per thread
+constexpr int TY = NW * ROWS;
+constexpr int NTHREADS = TX * NW;
+constexpr int NRED = 8;     // doubles per block partial of the diagnostics
+constexpr int NXCD = 8;     // accelerator complex dies of the MI355X
+
+struct Geo {
+    int Lx, Ly, pitch;
+    int wall_x, wall_y;
+    int nbx, ntiles;
+    long long plane;        // Ly * pitch
+};
+
+// Workgroups are handed to the 8 XCDs round-robin by block id; renumber them
+// so that each XCD walks one contiguous band of tiles (row-major), which keeps
+// the porosity halo rows and the lines shared by neighbouring tiles in that
+// XCD's L2.  The map is a bijection of [0, ntiles) for any ntiles.
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles)
+{
+    int q = ntiles / NXCD, r = ntiles % NXCD;
+    int xcd = bid % NXCD, k = bid / NXCD;
+    return xcd * q + min(xcd, r) + k;
+}
+
+// Index of a halo node along an axis: wrap-around when periodic, the mirror
+// image across the half-way wall otherwise (node -1 -> 0, node L -> L-1).
+__device__ __forceinline__ int halo_index(int v, int L, int wall)
+{
+    if (wall) return v < 0 ? 0 : (v >= L ? L - 1 : v);
+    int m = v % L;
+    return m < 0 ? m + L : m;
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs
+// ---------------------------------------------------------------------------
+
+template <typename S, typename R>
+__device__ __forceinline__ R load_pop(const S *p, R inv_scale)
+{
+    if constexpr (std::is_same_v<S, _Float16>)
+        return static_cast<R>(*p) * inv_scale;
+    else
+        return static_cast<R>(*p);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void store_pop(S *p, R v, R scale)
+{
+    if constexpr (std::is_same_v<S, _Float16>)
+        __builtin_nontemporal_store(static_cast<_Float16>(v * scale), p);
+    else
+        __builtin_nontemporal_store(static_cast<S>(v), p);
+}
+
+// ---------------------------------------------------------------------------
+// Physics of one node
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct Phys {
+    R omega;        // 1 / tau
+    R pre;          // 1 - 1 / (2 tau)
+    R rho0;         // shift reference density
+    R Gx, Gy;       // body-force density
+    R ca, cb;       // drag prefactors (see drag_coeffs)
+    int drag;       // LBM_DRAG_ERGUN or LBM_DRAG_CONST
+    R scale, inv_scale;  // FP16 storage scale 2^s and 2^-s (1 otherwise)
+};
+
+// Darcy and Forchheimer coefficients a = eps^2 nu / K, b = eps^3 F_eps / sqrt(K)
+// of the drag law.  Ergun closure: a = 150 nu (1-eps)^2 / (eps d_p^2),
+// b = 1.75 (1-eps) / d_p, i.e. ca = 150 nu / d_p^2, cb = 1.75 / d_p (both 0
+// when d_p is infinite, and a = b = 0 at eps = 1).  Constant K, F_eps:
+// a = eps^2 (nu/K), b = eps^3 (F_eps / sqrt K).
+template <typename R>
+__device__ __forceinline__ void drag_coeffs(const Phys<R> &ph, R eps, R &a, R &b)
+{
+    if (ph.drag == LBM_DRAG_ERGUN) {
+        R s = R(1) - eps;
+        a = ph.ca * s * s / eps;
+        b = ph.cb * s;
+    } else {
+        a = ph.ca * eps * eps;
+        b = ph.cb * eps * eps * eps;
+    }
+}
+
+template <typename R>
+struct Node {
+    R dS;           // eps rho - eps rho0  (sum of deviations)
+    R S;            // eps rho             (eq. (0moment))
+    R mx, my;       // sum_i e_i f_i
+    R rho;          // intrinsic density S / eps
+    R ux, uy;       // velocity of eq. (1moment)
+    R Tx, Ty;       // c_s^2 rho grad(eps) + F(u): the vector of P_i + F_i
+};
+
+// Moments and velocity from the deviations d_i = f_i - w_i rho0 eps.
+// eq. (1moment): eps rho u = m + (c_s^2 rho grad eps + F(u))/2 with
+// F(u) = G - a u - b |u| u.  Writing A = eps rho + a/2, B = b/2 and
+// V = m + (c_s^2 rho grad eps + G)/2, u is parallel to V and its length is
+// the non-negative root of B s^2 + A s = |V|: u = 2 V / (A + sqrt(A^2 + 4 B |V|)).
+template <typename R>
+__device__ __forceinline__ Node<R> node_moments(const R d[9], R eps, R gex, R gey,
+                                                const Phys<R> &ph)
+{
+    Node<R> N;
+    N.dS = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    N.S = eps * ph.rho0 + N.dS;
+    N.mx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    N.my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    N.rho = N.S / eps;
+    const R third = R(1) / R(3);
+    R Qx = third * N.rho * gex, Qy = third * N.rho * gey;
+    R a, b;
+    drag_coeffs(ph, eps, a, b);
+    R Vx = N.mx + R(0.5) * (Qx + ph.Gx);
+    R Vy = N.my + R(0.5) * (Qy + ph.Gy);
+    R A = N.S + R(0.5) * a;
+    R B = R(0.5) * b;
+    R Vn = sqrt(Vx * Vx + Vy * Vy);
+    R k = R(2) / (A + sqrt(A * A + R(4) * B * Vn));
+    N.ux = k * Vx;
+    N.uy = k * Vy;
+    R un = sqrt(N.ux * N.ux + N.uy * N.uy);
+    R drag = a + b * un;
+    N.Tx = Qx + ph.Gx - drag * N.ux;
+    N.Ty = Qy + ph.Gy - drag * N.uy;
+    return N;
+}
+
+// D2Q9 velocities in the library's ordering and their weights.
+__device__ constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+template <typename R>
+__device__ __forceinline__ R weight(int i)
+{
+    return i == 0 ? R(4) / R(9) : (i < 5 ? R(1) / R(9) : R(1) / R(36));
+}
+
+// Post-collision deviations:
+//   f*_i = f_i - (f_i - f^eq_i)/tau + (1 - 1/(2 tau)) w_i [3 (e_i - u).T + 9 (e_i.u)(e_i.T)]
+// with f^eq_i = w_i eps rho [1 + 3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u], written for
+// d_i = f_i - w_i rho0 eps: d^eq_i = w_i [dS + S (3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u)].
+template <typename R>
+__device__ __forceinline__ void collide(R d[9], const Node<R> &N, const Phys<R> &ph)
+{
+    R uu = N.ux * N.ux + N.uy * N.uy;
+    R uT = N.ux * N.Tx + N.uy * N.Ty;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        R eu = R(CX[i]) * N.ux + R(CY[i]) * N.uy;
+        R eT = R(CX[i]) * N.Tx + R(CY[i]) * N.Ty;
+        R w = weight<R>(i);
+        R deq = w * (N.dS + N.S * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
+        R src = ph.pre * w * (R(3) * (eT - uT) + R(9) * eu * eT);
+        d[i] = d[i] + ph.omega * (deq - d[i]) + src;
+    }
+}
+
+// Neighbour coordinates of node (x, y) along both axes with wall flags.
+struct Nbr {
+    int xm, xp, ym, yp;
+    bool wxm, wxp, wym, wyp;
+};
+
+__device__ __forceinline__ Nbr neighbours(int x, int y, const Geo &g)
+{
+    Nbr n;
+    n.xm = x - 1; n.xp = x + 1; n.ym = y - 1; n.yp = y + 1;
+    n.wxm = n.wxp = n.wym = n.wyp = false;
+    if (n.xm < 0) { if (g.wall_x) { n.wxm = true; n.xm = x; } else n.xm = g.Lx - 1; }
+    if (n.xp >= g.Lx) { if (g.wall_x) { n.wxp = true; n.xp = x; } else n.xp = 0; }
+    if (n.ym < 0) { if (g.wall_y) { n.wym = true; n.ym = y; } else n.ym = g.Ly - 1; }
+    if (n.yp >= g.Ly) { if (g.wall_y) { n.wyp = true; n.yp = y; } else n.yp = 0; }
+    return n;
+}
+
+// Pull-gather of the deviations d_i(x, y).  A population whose source node
+// x - e_i lies behind a wall is the node's own opposite post-collision value
+// (half-way bounce-back).
+template <typename S, typename R>
+__device__ __forceinline__ void gather(R d[9], const S *__restrict__ f, long long plane,
+                                       int pitch, int x, int y, const Nbr &n, R inv_scale)
+{
+    const int c = y * pitch + x;
+    const int rm = n.ym * pitch, r0 = y * pitch, rp = n.yp * pitch;
+    const S *f0 = f, *f1 = f + plane, *f2 = f + 2 * plane, *f3 = f + 3 * plane,
+            *f4 = f + 4 * plane, *f5 = f + 5 * plane, *f6 = f + 6 * plane,
+            *f7 = f + 7 * plane, *f8 = f + 8 * plane;
+    const S *p1 = n.wxm ? f3 + c : f1 + r0 + n.xm;
+    const S *p2 = n.wym ? f4 + c : f2 + rm + x;
+    const S *p3 = n.wxp ? f1 + c : f3 + r0 + n.xp;
+    const S *p4 = n.wyp ? f2 + c : f4 + rp + x;
+    const S *p5 = (n.wxm || n.wym) ? f7 + c : f5 + rm + n.xm;
+    const S *p6 = (n.wxp || n.wym) ? f8 + c : f6 + rm + n.xp;
+    const S *p7 = (n.wxp || n.wyp) ? f5 + c : f7 + rp + n.xp;
+    const S *p8 = (n.wxm || n.wyp) ? f6 + c : f8 + rp + n.xm;
+    d[0] = load_pop<S, R>(f0 + c, inv_scale);
+    d[1] = load_pop<S, R>(p1, inv_scale);
+    d[2] = load_pop<S, R>(p2, inv_scale);
+    d[3] = load_pop<S, R>(p3, inv_scale);
+    d[4] = load_pop<S, R>(p4, inv_scale);
+    d[5] = load_pop<S, R>(p5, inv_scale);
+    d[6] = load_pop<S, R>(p6, inv_scale);
+    d[7] = load_pop<S, R>(p7, inv_scale);
+    d[8] = load_pop<S, R>(p8, inv_scale);
+}
+
+// Porosity tile with a one-node halo, filled with the halo rule (wrap or
+// mirror) so that every neighbour of an in-domain node is correct.
+template <typename R>
+__device__ __forceinline__ void load_eps_tile(R (*tile)[TX + 2], const R *__restrict__ eps,
+                                              const Geo &g, int x0, int y0)
+{
+    for (int k = threadIdx.x; k < (TY + 2) * (TX + 2); k += NTHREADS) {
+        int ly = k / (TX + 2), lx = k - ly * (TX + 2);
+        int gx = halo_index(x0 + lx - 1, g.Lx, g.wall_x);
+        int gy = halo_index(y0 + ly - 1, g.Ly, g.wall_y);
+        tile[ly][lx] = eps[(long long)gy * g.pitch + gx];
+    }
+}
+
+// Isotropic lattice gradient 3 sum_i w_i e_i eps(x + e_i) from the tile.
+template <typename R>
+__device__ __forceinline__ void grad_eps(const R (*t)[TX + 2], int ly, int lx, R &gx, R &gy)
+{
+    R e_E = t[ly][lx + 1], e_W = t[ly][lx - 1], e_N = t[ly + 1][lx], e_S = t[ly - 1][lx];
+    R e_NE = t[ly + 1][lx + 1], e_NW = t[ly + 1][lx - 1];
+    R e_SW = t[ly - 1][lx - 1], e_SE = t[ly - 1][lx + 1];
+    const R c1 = R(1) / R(3), c2 = R(1) / R(12);
+    gx = c1 * (e_E - e_W) + c2 * ((e_NE - e_SW) + (e_SE - e_NW));
+    gy = c1 * (e_N - e_S) + c2 * ((e_NE - e_SW) + (e_NW - e_SE));
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reduction of the diagnostics
+// ---------------------------------------------------------------------------
+// v[0] = eps rho - eps rho0, v[1..2] = m, v[3..4] = eps rho u, v[5] = |u| (max),
+// v[6] = non-finite count, v[7] unused.  One partial of NRED doubles per tile.
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ void block_partial(double acc[NRED], double *__restrict__ part,
+                                              int tile)
+{
+    __shared__ double red[NW][NRED];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < NRED; k++) {
+        double v = (k == 5) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        int k = threadIdx.x;
+        double v = red[0][k];
+        for (int w = 1; w < NW; w++) v = (k == 5) ? fmax(v, red[w][k]) : v + red[w][k];
+        part[(long long)tile * NRED + k] = v;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void accumulate(double acc[NRED], const Node<R> &N)
+{
+    bool ok = isfinite(static_cast<double>(N.S)) && isfinite(static_cast<double>(N.ux)) &&
+              isfinite(static_cast<double>(N.uy));
+    if (!ok) {
+        acc[6] += 1.0;
+        return;
+    }
+    acc[0] += static_cast<double>(N.dS);
+    acc[1] += static_cast<double>(N.mx);
+    acc[2] += static_cast<double>(N.my);
+    acc[3] += static_cast<double>(N.S) * static_cast<double>(N.ux);
+    acc[4] += static_cast<double>(N.S) * static_cast<double>(N.uy);
+    double un = sqrt(static_cast<double>(N.ux) * N.ux + static_cast<double>(N.uy) * N.uy);
+    acc[5] = fmax(acc[5], un);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// The fused stream+collide sweep: fin holds the post-collision populations of
+// step n-1 (state n after streaming), fout receives those of step n.
+template <typename S, typename R, bool DIAG>
+__global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
+                                                    S *__restrict__ fout,
+                                                    const R *__restrict__ eps, Geo g,
+                                                    Phys<R> ph, double *__restrict__ part)
+{
+    __shared__ R tile[TY + 2][TX + 2];
+    const int t = xcd_tile(blockIdx.x, g.ntiles);
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x0 = bx * TX, y0 = by * TY;
+    load_eps_tile<R>(tile, eps, g, x0, y0);
+    __syncthreads();
+
+    double acc[NRED];
+    if constexpr (DIAG) {
+#pragma unroll
+        for (int k = 0; k < NRED; k++) acc[k] = 0.0;
+    }
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx;
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+        const int ly = ty + NW * r;
+        const int y = y0 + ly;
+        if (x < g.Lx && y < g.Ly) {
+            Nbr n = neighbours(x, y, g);
+            R d[9];
+            gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
+            const int lx = tx + 1, lyy = ly + 1;
+            R e0 = tile[lyy][lx];
+            R gex, gey;
+            grad_eps<R>(tile, lyy, lx, gex, gey);
+            Node<R> N = node_moments<R>(d, e0, gex, gey, ph);
+            if constexpr (DIAG) accumulate<R>(acc, N);
+            collide<R>(d, N, ph);
+            // Shift each value to the rest state of the node that pulls it next.
+            const R wr = ph.rho0;
+            const R sh[9] = {
+                R(0),
+                n.wxp ? R(0) : (R(1) / R(9)) * wr * (tile[lyy][lx + 1] - e0),
+                n.wyp ? R(0) : (R(1) / R(9)) * wr * (tile[lyy + 1][lx] - e0),
+                n.wxm ? R(0) : (R(1) / R(9)) * wr * (tile[lyy][lx - 1] - e0),
+                n.wym ? R(0) : (R(1) / R(9)) * wr * (tile[lyy - 1][lx] - e0),
+                (n.wxp || n.wyp) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy + 1][lx + 1] - e0),
+                (n.wxm || n.wyp) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy + 1][lx - 1] - e0),
+                (n.wxm || n.wym) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy - 1][lx - 1] - e0),
+                (n.wxp || n.wym) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy - 1][lx + 1] - e0),
+            };
+            const int c = y * g.pitch + x;
+#pragma unroll
+            for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i] - sh[i], ph.scale);
+        }
+    }
+    if constexpr (DIAG) block_partial(acc, part, t);
+}
+
+// Macroscopic fields of the current state (no collision, no store of
+// populations) plus the FP64 diagnostics partials.
+template <typename S, typename R>
+__global__ __launch_bounds__(NTHREADS) void k_moments(const S *__restrict__ fin,
+                                                      const R *__restrict__ eps, Geo g,
+                                                      Phys<R> ph, R *__restrict__ o_epsrho,
+                                                      R *__restrict__ o_rho,
+                                                      R *__restrict__ o_ux, R *__restrict__ o_uy,
+                                                      double *__restrict__ part)
+{
+    __shared__ R tile[TY + 2][TX + 2];
+    const int t = xcd_tile(blockIdx.x, g.ntiles);
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x0 = bx * TX, y0 = by * TY;
+    load_eps_tile<R>(tile, eps, g, x0, y0);
+    __syncthreads();
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; k++) acc[k] = 0.0;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx;
+    for (int r = 0; r < ROWS; r++) {
+        const int ly = ty + NW * r;
+        const int y = y0 + ly;
+        if (x < g.Lx && y < g.Ly) {
+            Nbr n = neighbours(x, y, g);
+            R d[9];
+            gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
+            R gex, gey;
+            grad_eps<R>(tile, ly + 1, tx + 1, gex, gey);
+            Node<R> N = node_moments<R>(d, tile[ly + 1][tx + 1], gex, gey, ph);
+            accumulate<R>(acc, N);
+            const long long o = (long long)y * g.Lx + x;
+            if (o_epsrho) o_epsrho[o] = N.S;
+            if (o_rho) o_rho[o] = N.rho;
+            if (o_ux) o_ux[o] = N.ux;
+            if (o_uy) o_uy[o] = N.uy;
+        }
+    }
+    block_partial(acc, part, t);
+}
+
+// Deterministic second pass: one block sums the tile partials in a fixed
+// order and writes one diagnostics record (slot 0 gets rho0 * sum eps added,
+// slot 7 the step index).
+__global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ part, int nparts,
+                                                   const double *__restrict__ mass0,
+                                                   double step, double *__restrict__ out)
+{
+    __shared__ double red[1024];
+    for (int k = 0; k < 7; k++) {
+        double v = 0.0;
+        for (int j = threadIdx.x; j < nparts; j += 1024) {
+            double p = part[(long long)j * NRED + k];
+            v = (k == 5) ? fmax(v, p) : v + p;
+        }
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 512; s > 0; s >>= 1) {
+            if (threadIdx.x < s) {
+                double a = red[threadIdx.x], b = red[threadIdx.x + s];
+                red[threadIdx.x] = (k == 5) ? fmax(a, b) : a + b;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = (k == 0 && mass0) ? red[0] + *mass0 : red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[7] = step;
+}
+
+// Porosity copy into the padded layout, with the (0, 1] check and FP64 sum:
+// partial slot 0 = sum eps, slot 6 = count of values outside (0, 1].
+template <typename R>
+__global__ __launch_bounds__(NTHREADS) void k_eps_copy(const R *__restrict__ src,
+                                                       R *__restrict__ dst, Geo g,
+                                                       double *__restrict__ part)
+{
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; k++) acc[k] = 0.0;
+    const int t = blockIdx.x;
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x = bx * TX + threadIdx.x % TX;
+    for (int r = 0; r < ROWS; r++) {
+        const int y = by * TY + threadIdx.x / TX + NW * r;
+        if (x < g.Lx && y < g.Ly) {
+            R e = src[(long long)y * g.Lx + x];
+            dst[(long long)y * g.pitch + x] = e;
+            if (e > R(0) && e <= R(1)) acc[0] += static_cast<double>(e);
+            else acc[6] += 1.0;
+        }
+    }
+    block_partial(acc, part, t);
+}
+
+// Rest-state reference w_i rho0 eps for a stored slot and the deviation of
+// a plain population from it, in FP64 (used by init and set_state only).
+__device__ __forceinline__ double wgt(int i)
+{
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+__device__ constexpr int OPPI[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Node that pulls slot (i, x, y) next, and the direction it pulls it as.
+__device__ __forceinline__ void reader(int i, int x, int y, const Geo &g, int &rx, int &ry,
+                                       int &ri)
+{
+    int tx = x + CX[i], ty = y + CY[i];
+    bool wall = false;
+    if (tx < 0 || tx >= g.Lx) {
+        if (g.wall_x) wall = true;
+        else tx = tx < 0 ? tx + g.Lx : tx - g.Lx;
+    }
+    if (ty < 0 || ty >= g.Ly) {
+        if (g.wall_y) wall = true;
+        else ty = ty < 0 ? ty + g.Ly : ty - g.Ly;
+    }
+    if (wall) { rx = x; ry = y; ri = OPPI[i]; }
+    else { rx = tx; ry = ty; ri = i; }
+}
+
+// Writes the storage of a plain state f(., n): fplain == nullptr means the
+// equilibrium f_i = f_i^eq(eps rho0, u0) of eq. (d2q9eq) (the initial state).
+// rho_ref is the shift reference rho0 as the sweep sees it (rounded to R), so
+// that the stored deviations and the sweep's rest state agree exactly.
+template <typename S, typename R>
+__global__ __launch_bounds__(NTHREADS) void k_set_state(S *__restrict__ fout,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        double rho0, double rho_ref,
+                                                        double u0x, double u0y,
+                                                        const double *__restrict__ fplain,
+                                                        R scale)
+{
+    const int t = blockIdx.x;
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x = bx * TX + threadIdx.x % TX;
+    for (int r = 0; r < ROWS; r++) {
+        const int y = by * TY + threadIdx.x / TX + NW * r;
+        if (x >= g.Lx || y >= g.Ly) continue;
+        for (int i = 0; i < 9; i++) {
+            int rx, ry, ri;
+            reader(i, x, y, g, rx, ry, ri);
+            double er = static_cast<double>(eps[(long long)ry * g.pitch + rx]);
+            double w = wgt(ri);
+            double dev;
+            if (fplain) {
+                long long N = (long long)g.Lx * g.Ly;
+                dev = fplain[ri * N + (long long)ry * g.Lx + rx] - w * rho_ref * er;
+            } else {
+                double eu = CX[ri] * u0x + CY[ri] * u0y;
+                double uu = u0x * u0x + u0y * u0y;
+                dev = w * er * ((rho0 - rho_ref) + rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+            }
+            S *p = fout + i * g.plane + (long long)y * g.pitch + x;
+            if constexpr (std::is_same_v<S, _Float16>)
+                *p = static_cast<_Float16>(static_cast<R>(dev) * scale);
+            else
+                *p = static_cast<S>(dev);
+        }
+    }
+}
+
+// Plain populations f_i(x, n) = d_i + w_i rho0 eps(x) of the current state.
+template <typename S, typename R>
+__global__ __launch_bounds__(NTHREADS) void k_get_state(const S *__restrict__ fin,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        Phys<R> ph, double *__restrict__ out)
+{
+    const int t = blockIdx.x;
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x = bx * TX + threadIdx.x % TX;
+    const long long N = (long long)g.Lx * g.Ly;
+    for (int r = 0; r < ROWS; r++) {
+        const int y = by * TY + threadIdx.x / TX + NW * r;
+        if (x >= g.Lx || y >= g.Ly) continue;
+        Nbr n = neighbours(x, y, g);
+        R d[9];
+        gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
+        double e0 = static_cast<double>(eps[(long long)y * g.pitch + x]);
+        for (int i = 0; i < 9; i++)
+            out[i * N + (long long)y * g.Lx + x] =
+                static_cast<double>(d[i]) + wgt(i) * static_cast<double>(ph.rho0) * e0;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct lbm_vans_handle {
+    lbm_vans_params p;
+    hipStream_t stream;
+    Geo g;
+    int ntiles;
+    size_t pop_bytes;       // bytes of one population buffer
+    char *buf[2];           // population buffers; buf[cur] holds the current state
+    int cur;
+    void *eps;              // padded porosity (double or float)
+    double *part;           // tile partials [ntiles][NRED]
+    double *mass0;          // rho0 * sum eps
+    double *scratch_rec;    // one diagnostics record
+    double *ring;           // [LBM_VANS_DIAG_RING][NRED]
+    int64_t n;              // steps taken
+    int64_t nrec;           // diagnostics records written
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int elem_bytes(int storage)
+{
+    return storage == LBM_F64 ? 8 : (storage == LBM_F32_SHIFTED ? 4 : 2);
+}
+
+int check_params(const lbm_vans_params *p)
+{
+    if (!p) return fail(LBM_VANS_EINVAL, "params is NULL");
+    if (p->Lx < 1 || p->Ly < 1)
+        return fail(LBM_VANS_EINVAL, "lattice size %d x %d must be at least 1 x 1", p->Lx, p->Ly);
+    long long pitch = (p->Lx + 63LL) / 64 * 64;
+    if (pitch * p->Ly >= (1LL << 31))
+        return fail(LBM_VANS_EINVAL, "lattice %d x %d too large (padded nodes must be < 2^31)",
+                    p->Lx, p->Ly);
+    if ((p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_BOUNCEBACK) ||
+        (p->bc_y != LBM_BC_PERIODIC && p->bc_y != LBM_BC_BOUNCEBACK))
+        return fail(LBM_VANS_EINVAL, "boundary kinds (%d, %d) not supported", p->bc_x, p->bc_y);
+    if (p->storage != LBM_F64 && p->storage != LBM_F32_SHIFTED && p->storage != LBM_F16_SHIFTED)
+        return fail(LBM_VANS_EINVAL, "unknown storage %d", p->storage);
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau))
+        return fail(LBM_VANS_EINVAL, "tau = %g must be finite and > 1/2", p->tau);
+    if (p->drag == LBM_DRAG_ERGUN) {
+        if (!(p->d_p > 0.0)) return fail(LBM_VANS_EINVAL, "d_p = %g must be > 0", p->d_p);
+    } else if (p->drag == LBM_DRAG_CONST) {
+        if (!(p->K > 0.0)) return fail(LBM_VANS_EINVAL, "K = %g must be > 0", p->K);
+        if (!(p->F_eps >= 0.0) || !std::isfinite(p->F_eps))
+            return fail(LBM_VANS_EINVAL, "F_eps = %g must be finite and >= 0", p->F_eps);
+    } else {
+        return fail(LBM_VANS_EINVAL, "unknown drag law %d", p->drag);
+    }
+    if (!std::isfinite(p->G[0]) || !std::isfinite(p->G[1]))
+        return fail(LBM_VANS_EINVAL, "body force must be finite");
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0))
+        return fail(LBM_VANS_EINVAL, "rho0 = %g must be finite and > 0", p->rho0);
+    if (!std::isfinite(p->u0[0]) || !std::isfinite(p->u0[1]))
+        return fail(LBM_VANS_EINVAL, "u0 must be finite");
+    if (p->storage == LBM_F16_SHIFTED && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24))
+        return fail(LBM_VANS_EINVAL, "fp16_scale_log2 = %d outside 0..24", p->fp16_scale_log2);
+    if (p->diag_every < 0) return fail(LBM_VANS_EINVAL, "diag_every = %d < 0", p->diag_every);
+    return LBM_VANS_OK;
+}
+
+Geo make_geo(const lbm_vans_params *p)
+{
+    Geo g;
+    g.Lx = p->Lx;
+    g.Ly = p->Ly;
+    g.pitch = (p->Lx + 63) / 64 * 64;
+    g.wall_x = p->bc_x == LBM_BC_BOUNCEBACK;
+    g.wall_y = p->bc_y == LBM_BC_BOUNCEBACK;
+    g.nbx = (p->Lx + TX - 1) / TX;
+    int nby = (p->Ly + TY - 1) / TY;
+    g.ntiles = g.nbx * nby;
+    g.plane = (long long)g.pitch * p->Ly;
+    return g;
+}
+
+struct Layout {
+    size_t pop, eps, part, small, total;
+};
+
+Layout make_layout(const lbm_vans_params *p)
+{
+    Geo g = make_geo(p);
+    Layout L;
+    L.pop = align256((size_t)9 * g.plane * elem_bytes(p->storage));
+    L.eps = align256((size_t)g.plane * (p->storage == LBM_F64 ? 8 : 4));
+    L.part = align256((size_t)g.ntiles * NRED * sizeof(double));
+    L.small = align256((size_t)(2 + NRED + (size_t)LBM_VANS_DIAG_RING * NRED) * sizeof(double));
+    L.total = 2 * L.pop + L.eps + L.part + L.small;
+    return L;
+}
+
+template <typename R>
+Phys<R> make_phys(const lbm_vans_params *p)
+{
+    Phys<R> ph;
+    double nu = (p->tau - 0.5) / 3.0;
+    ph.omega = static_cast<R>(1.0 / p->tau);
+    ph.pre = static_cast<R>(1.0 - 0.5 / p->tau);
+    ph.rho0 = static_cast<R>(p->rho0);
+    ph.Gx = static_cast<R>(p->G[0]);
+    ph.Gy = static_cast<R>(p->G[1]);
+    ph.drag = p->drag;
+    if (p->drag == LBM_DRAG_ERGUN) {
+        bool none = std::isinf(p->d_p);
+        ph.ca = none ? R(0) : static_cast<R>(150.0 * nu / (p->d_p * p->d_p));
+        ph.cb = none ? R(0) : static_cast<R>(1.75 / p->d_p);
+    } else {
+        bool none = std::isinf(p->K);
+        ph.ca = none ? R(0) : static_cast<R>(nu / p->K);
+        ph.cb = none ? R(0) : static_cast<R>(p->F_eps / std::sqrt(p->K));
+    }
+    double s = p->storage == LBM_F16_SHIFTED ? std::ldexp(1.0, p->fp16_scale_log2) : 1.0;
+    ph.scale = static_cast<R>(s);
+    ph.inv_scale = static_cast<R>(1.0 / s);
+    return ph;
+}
+
+int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LBM_VANS_EHIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return LBM_VANS_OK;
+}
+
+// Dispatch on the storage type: f(S, R) with S the stored and R the compute type.
+template <typename Fn>
+int with_types(int storage, Fn &&fn)
+{
+    switch (storage) {
+    case LBM_F64: return fn((double *)nullptr, (double *)nullptr);
+    case LBM_F32_SHIFTED: return fn((float *)nullptr, (float *)nullptr);
+    default: return fn((_Float16 *)nullptr, (float *)nullptr);
+    }
+}
+
+int launch_sweep(lbm_vans_handle *h, bool diag)
+{
+    const char *src = h->buf[h->cur];
+    char *dst = h->buf[1 - h->cur];
+    return with_types(h->p.storage, [&](auto *sp, auto *rp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        Phys<R> ph = make_phys<R>(&h->p);
+        if (diag)
+            hipLaunchKernelGGL((k_sweep<S, R, true>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                               (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph, h->part);
+        else
+            hipLaunchKernelGGL((k_sweep<S, R, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                               h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph,
+                               h->part);
+        return check_launch("k_sweep");
+    });
+}
+
+int launch_finalize(lbm_vans_handle *h, double *out, bool add_mass0, double step)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, h->stream, (const double *)h->part,
+                       h->ntiles, add_mass0 ? (const double *)h->mass0 : nullptr, step, out);
+    return check_launch("k_finalize");
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_vans_abi_version(void) { return LBM_VANS_ABI_VERSION; }
+
+const char *lbm_vans_last_error(void) { return g_last_error.c_str(); }
+
+size_t lbm_vans_work_bytes(const lbm_vans_params *p)
+{
+    if (check_params(p) != LBM_VANS_OK) return 0;
+    return make_layout(p).total;
+}
+
+int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t work_bytes,
+                  void *stream, lbm_vans_handle **out)
+{
+    g_last_error.clear();
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!out) return fail(LBM_VANS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!eps || !work) return fail(LBM_VANS_EINVAL, "eps and work must be device pointers");
+    if (reinterpret_cast<uintptr_t>(work) % 256)
+        return fail(LBM_VANS_EINVAL, "work buffer must be 256-byte aligned");
+    Layout L = make_layout(p);
+    if (work_bytes < L.total)
+        return fail(LBM_VANS_EINVAL, "work buffer has %zu bytes, %zu needed", work_bytes, L.total);
+
+    lbm_vans_handle *h = new (std::nothrow) lbm_vans_handle();
+    if (!h) return fail(LBM_VANS_EINVAL, "out of host memory");
+    h->p = *p;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->g = make_geo(p);
+    h->ntiles = h->g.ntiles;
+    h->pop_bytes = L.pop;
+    char *w = static_cast<char *>(work);
+    h->buf[0] = w;
+    h->buf[1] = w + L.pop;
+    h->eps = w + 2 * L.pop;
+    h->part = reinterpret_cast<double *>(w + 2 * L.pop + L.eps);
+    double *small = reinterpret_cast<double *>(w + 2 * L.pop + L.eps + L.part);
+    h->mass0 = small;
+    h->scratch_rec = small + 2;
+    h->ring = small + 2 + NRED;
+    h->cur = 0;
+    h->n = 0;
+    h->nrec = 0;
+
+    rc = with_types(p->storage, [&](auto *sp, auto *rp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        hipLaunchKernelGGL((k_eps_copy<R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (const R *)eps, (R *)h->eps, h->g, h->part);
+        int r = check_launch("k_eps_copy");
+        if (r) return r;
+        r = launch_finalize(h, h->scratch_rec, false, 0.0);
+        if (r) return r;
+        double rec[NRED];
+        HIP_TRY(hipMemcpyAsync(rec, h->scratch_rec, sizeof rec, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (rec[6] != 0.0)
+            return fail(LBM_VANS_EINVAL, "%.0f porosity values outside (0, 1]", rec[6]);
+        double m0 = p->rho0 * rec[0];
+        HIP_TRY(hipMemcpyAsync(h->mass0, &m0, sizeof m0, hipMemcpyHostToDevice, h->stream));
+        Phys<R> ph = make_phys<R>(p);
+        hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (S *)h->buf[0], (const R *)h->eps, h->g, p->rho0,
+                           static_cast<double>(ph.rho0), p->u0[0], p->u0[1],
+                           (const double *)nullptr, ph.scale);
+        r = check_launch("k_set_state");
+        if (r) return r;
+        // The host value m0 must stay alive until the copy has run.
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return LBM_VANS_OK;
+    });
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return LBM_VANS_OK;
+}
+
+int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(LBM_VANS_EINVAL, "nsteps = %lld < 0", (long long)nsteps);
+    for (int64_t k = 0; k < nsteps; k++) {
+        bool diag = h->p.diag_every > 0 && h->n % h->p.diag_every == 0;
+        int rc = launch_sweep(h, diag);
+        if (rc) return rc;
+        if (diag) {
+            double *slot = h->ring + (h->nrec % LBM_VANS_DIAG_RING) * NRED;
+            rc = launch_finalize(h, slot, true, static_cast<double>(h->n));
+            if (rc) return rc;
+            h->nrec++;
+        }
+        h->cur = 1 - h->cur;
+        h->n++;
+    }
+    return LBM_VANS_OK;
+}
+
+int64_t lbm_vans_step_count(const lbm_vans_handle *h) { return h ? h->n : -1; }
+
+int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, void *uy,
+                     double *diag)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    int rc = with_types(h->p.storage, [&](auto *sp, auto *rp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        Phys<R> ph = make_phys<R>(&h->p);
+        hipLaunchKernelGGL((k_moments<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (const S *)h->buf[h->cur], (const R *)h->eps, h->g, ph, (R *)eps_rho,
+                           (R *)rho, (R *)ux, (R *)uy, h->part);
+        return check_launch("k_moments");
+    });
+    if (rc) return rc;
+    if (!diag) return LBM_VANS_OK;
+    rc = launch_finalize(h, h->scratch_rec, true, static_cast<double>(h->n));
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(diag, h->scratch_rec, NRED * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (diag[6] != 0.0)
+        return fail(LBM_VANS_ENONFINITE, "%.0f nodes have non-finite moments at step %lld",
+                    diag[6], (long long)h->n);
+    return LBM_VANS_OK;
+}
+
+int lbm_vans_get_state(lbm_vans_handle *h, void *f)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    if (!f) return fail(LBM_VANS_EINVAL, "f is NULL");
+    return with_types(h->p.storage, [&](auto *sp, auto *rp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        Phys<R> ph = make_phys<R>(&h->p);
+        hipLaunchKernelGGL((k_get_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (const S *)h->buf[h->cur], (const R *)h->eps, h->g, ph, (double *)f);
+        return check_launch("k_get_state");
+    });
+}
+
+int lbm_vans_set_state(lbm_vans_handle *h, const void *f)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    if (!f) return fail(LBM_VANS_EINVAL, "f is NULL");
+    return with_types(h->p.storage, [&](auto *sp, auto *rp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        Phys<R> ph = make_phys<R>(&h->p);
+        hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (S *)h->buf[h->cur], (const R *)h->eps, h->g, h->p.rho0,
+                           static_cast<double>(ph.rho0), 0.0, 0.0, (const double *)f, ph.scale);
+        return check_launch("k_set_state");
+    });
+}
+
+int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
+                       int32_t *n_records)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    if (!n_records || (max_records > 0 && !records))
+        return fail(LBM_VANS_EINVAL, "records / n_records is NULL");
+    int64_t avail = h->nrec < LBM_VANS_DIAG_RING ? h->nrec : LBM_VANS_DIAG_RING;
+    int64_t cnt = max_records < avail ? max_records : avail;
+    *n_records = static_cast<int32_t>(cnt);
+    // Oldest kept record first: the last cnt records written.
+    for (int64_t k = 0; k < cnt; k++) {
+        int64_t idx = (h->nrec - cnt + k) % LBM_VANS_DIAG_RING;
+        HIP_TRY(hipMemcpyAsync(records + k * NRED, h->ring + idx * NRED, NRED * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int64_t k = 0; k < cnt; k++)
+        if (records[k * NRED + 6] != 0.0)
+            return fail(LBM_VANS_ENONFINITE, "non-finite moments recorded at step %.0f",
+                        records[k * NRED + 7]);
+    return LBM_VANS_OK;
+}
+
+int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
+                  double *dJdeps, double *J)
+{
+    (void)h; (void)objective; (void)nsteps; (void)ckpt_every; (void)dJdeps; (void)J;
+    return fail(LBM_VANS_ENOTIMPL, "the adjoint sweep is not built");
+}
+
+void lbm_vans_destroy(lbm_vans_handle *h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+}  // extern "C"

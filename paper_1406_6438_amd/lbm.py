@@ -1,0 +1,272 @@
+"""ctypes binding of liblbm_vans.so (declared in include/lbm_vans.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  Device memory comes from torch tensors (the work buffer, the
+porosity, output fields) and the HIP stream is torch's current stream.  The
+module functions carry the C names; ``Solver`` is a small owner of one handle
+and its work tensor.
+
+The library is loaded from this package directory.  If it is missing the
+import of the first entry point raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_vans.so")
+
+OK, EINVAL, EHIP, ENONFINITE, ENOTIMPL = 0, -1, -2, -3, -4
+BC_PERIODIC, BC_BOUNCEBACK = 0, 1
+F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
+DRAG_ERGUN, DRAG_CONST = 0, 1
+NDIAG = 8
+DIAG_RING = 4096
+ABI_VERSION = 1
+
+# Every symbol include/lbm_vans.h declares.
+SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
+           "lbm_vans_moments", "lbm_vans_get_state", "lbm_vans_set_state",
+           "lbm_vans_diag_read", "lbm_vans_grad", "lbm_vans_destroy", "lbm_vans_last_error",
+           "lbm_vans_abi_version")
+
+STORAGE = {"f64": F64, "f32": F32_SHIFTED, "f16": F16_SHIFTED}
+
+
+class LbmVansParams(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("drag", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("d_p", ctypes.c_double),
+        ("K", ctypes.c_double), ("F_eps", ctypes.c_double),
+        ("G", ctypes.c_double * 2), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 2),
+        ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
+    ]
+
+
+@dataclasses.dataclass
+class Params:
+    """Mirror of lbm_vans_params (see include/lbm_vans.h for every field)."""
+    Lx: int
+    Ly: int
+    tau: float
+    bc_x: int = BC_PERIODIC
+    bc_y: int = BC_PERIODIC
+    storage: int = F32_SHIFTED
+    drag: int = DRAG_ERGUN
+    d_p: float = math.inf
+    K: float = math.inf
+    F_eps: float = 0.0
+    G: tuple = (0.0, 0.0)
+    rho0: float = 1.0
+    u0: tuple = (0.0, 0.0)
+    fp16_scale_log2: int = 10
+    diag_every: int = 0
+
+    def c(self) -> LbmVansParams:
+        return LbmVansParams(self.Lx, self.Ly, self.bc_x, self.bc_y, self.storage, self.drag,
+                             self.tau, self.d_p, self.K, self.F_eps,
+                             (ctypes.c_double * 2)(*self.G), self.rho0,
+                             (ctypes.c_double * 2)(*self.u0), self.fp16_scale_log2,
+                             self.diag_every)
+
+
+class LbmVansError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblbm_vans error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() "
+                          "(python paper_1406_6438_amd/build.py)")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER(LbmVansParams)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    L.lbm_vans_work_bytes.argtypes = [P]
+    L.lbm_vans_work_bytes.restype = ctypes.c_size_t
+    L.lbm_vans_init.argtypes = [P, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.lbm_vans_step.argtypes = [vp, i64]
+    L.lbm_vans_step_count.argtypes = [vp]
+    L.lbm_vans_step_count.restype = i64
+    L.lbm_vans_moments.argtypes = [vp, vp, vp, vp, vp, dp]
+    L.lbm_vans_get_state.argtypes = [vp, vp]
+    L.lbm_vans_set_state.argtypes = [vp, vp]
+    L.lbm_vans_diag_read.argtypes = [vp, dp, i32, ctypes.POINTER(i32)]
+    L.lbm_vans_grad.argtypes = [vp, i32, i64, i32, dp, dp]
+    L.lbm_vans_destroy.argtypes = [vp]
+    L.lbm_vans_destroy.restype = None
+    L.lbm_vans_last_error.argtypes = []
+    L.lbm_vans_last_error.restype = ctypes.c_char_p
+    L.lbm_vans_abi_version.argtypes = []
+    for n in ("lbm_vans_init", "lbm_vans_step", "lbm_vans_moments", "lbm_vans_get_state",
+              "lbm_vans_set_state", "lbm_vans_diag_read", "lbm_vans_grad",
+              "lbm_vans_abi_version"):
+        getattr(L, n).restype = ctypes.c_int
+    if L.lbm_vans_abi_version() != ABI_VERSION:
+        raise ImportError("liblbm_vans ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise LbmVansError(rc, load().lbm_vans_last_error().decode())
+    return rc
+
+
+def _dev_ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def lbm_vans_work_bytes(p: Params) -> int:
+    n = load().lbm_vans_work_bytes(ctypes.byref(p.c()))
+    if n == 0:
+        raise LbmVansError(EINVAL, load().lbm_vans_last_error().decode())
+    return n
+
+
+def lbm_vans_init(p: Params, eps, work, stream) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load().lbm_vans_init(ctypes.byref(p.c()), eps.data_ptr(), work.data_ptr(),
+                                work.numel() * work.element_size(), stream, ctypes.byref(h)))
+    return h
+
+
+def lbm_vans_step(h, nsteps: int):
+    _check(load().lbm_vans_step(h, int(nsteps)))
+
+
+def lbm_vans_step_count(h) -> int:
+    return load().lbm_vans_step_count(h)
+
+
+def lbm_vans_moments(h, eps_rho=None, rho=None, ux=None, uy=None, want_diag: bool = True):
+    diag = (ctypes.c_double * NDIAG)() if want_diag else None
+    rc = load().lbm_vans_moments(h, _dev_ptr(eps_rho), _dev_ptr(rho), _dev_ptr(ux),
+                                 _dev_ptr(uy), diag)
+    if rc == ENONFINITE:
+        return np.array(diag[:]), rc
+    _check(rc)
+    return (np.array(diag[:]) if want_diag else None), rc
+
+
+def lbm_vans_get_state(h, f):
+    _check(load().lbm_vans_get_state(h, f.data_ptr()))
+
+
+def lbm_vans_set_state(h, f):
+    _check(load().lbm_vans_set_state(h, f.data_ptr()))
+
+
+def lbm_vans_diag_read(h, max_records: int = DIAG_RING):
+    buf = (ctypes.c_double * (NDIAG * max_records))()
+    n = ctypes.c_int32()
+    rc = load().lbm_vans_diag_read(h, buf, max_records, ctypes.byref(n))
+    arr = np.array(buf[: n.value * NDIAG]).reshape(n.value, NDIAG)
+    if rc not in (OK, ENONFINITE):
+        _check(rc)
+    return arr, rc
+
+
+def lbm_vans_grad(h, objective: int, nsteps: int, ckpt_every: int, dJdeps=None):
+    J = ctypes.c_double()
+    rc = load().lbm_vans_grad(h, objective, nsteps, ckpt_every,
+                              None if dJdeps is None else ctypes.cast(dJdeps.data_ptr(),
+                                                                      ctypes.POINTER(ctypes.c_double)),
+                              ctypes.byref(J))
+    _check(rc)
+    return J.value
+
+
+def lbm_vans_destroy(h):
+    if h:
+        load().lbm_vans_destroy(h)
+
+
+class Solver:
+    """One solver handle with torch-owned device memory on ``device``.
+
+    ``eps`` is the porosity [Ly, Lx] (numpy or torch); it is cast once to the
+    compute type of the storage (float64 for f64, float32 otherwise) and
+    uploaded.  All calls run on torch's current stream of ``device``.
+    """
+
+    def __init__(self, p: Params, eps, device="cuda:0"):
+        import torch
+
+        load()
+        self.torch = torch
+        self.p = p
+        self.device = torch.device(device)
+        self.real = torch.float64 if p.storage == F64 else torch.float32
+        eps_t = torch.as_tensor(np.asarray(eps) if not isinstance(eps, torch.Tensor) else eps)
+        if tuple(eps_t.shape) != (p.Ly, p.Lx):
+            raise ValueError(f"eps has shape {tuple(eps_t.shape)}, expected {(p.Ly, p.Lx)}")
+        with torch.cuda.device(self.device):
+            self.eps = eps_t.to(dtype=self.real).contiguous().to(self.device)
+            nbytes = lbm_vans_work_bytes(p)
+            # 256-byte aligned: torch's caching allocator returns >= 512-byte aligned blocks.
+            self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            assert self.work.data_ptr() % 256 == 0
+            self.stream = torch.cuda.current_stream(self.device)
+            self.h = lbm_vans_init(p, self.eps, self.work, self.stream.cuda_stream)
+
+    def step(self, nsteps: int):
+        lbm_vans_step(self.h, nsteps)
+
+    @property
+    def n(self) -> int:
+        return lbm_vans_step_count(self.h)
+
+    def moments(self, want_diag: bool = True):
+        """dict of eps_rho, rho, ux, uy tensors [Ly, Lx] and the diagnostics record."""
+        t = self.torch
+        out = {k: t.empty((self.p.Ly, self.p.Lx), dtype=self.real, device=self.device)
+               for k in ("eps_rho", "rho", "ux", "uy")}
+        diag, rc = lbm_vans_moments(self.h, out["eps_rho"], out["rho"], out["ux"], out["uy"],
+                                    want_diag)
+        out["diag"] = diag
+        out["rc"] = rc
+        return out
+
+    def get_state(self):
+        f = self.torch.empty((9, self.p.Ly, self.p.Lx), dtype=self.torch.float64,
+                             device=self.device)
+        lbm_vans_get_state(self.h, f)
+        return f
+
+    def set_state(self, f):
+        f = self.torch.as_tensor(f, dtype=self.torch.float64).contiguous().to(self.device)
+        if tuple(f.shape) != (9, self.p.Ly, self.p.Lx):
+            raise ValueError("state must be [9, Ly, Lx]")
+        lbm_vans_set_state(self.h, f)
+        self.stream.synchronize()
+
+    def diag_records(self):
+        return lbm_vans_diag_read(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm_vans_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,93 @@
+"""Helpers shared by the GPU parity tests: one problem spec turned into the
+oracle's parameters and the library's parameters, and paired runs."""
+from __future__ import annotations
+
+import dataclasses
+import math
+import sys
+
+import numpy as np
+
+import oracle
+
+
+@dataclasses.dataclass
+class Spec:
+    Lx: int
+    Ly: int
+    tau: float = 0.8
+    walls_x: bool = False
+    walls_y: bool = False
+    drag_const: bool = False
+    d_p: float = math.inf
+    K: float = math.inf
+    F_eps: float = 0.0
+    G: tuple = (0.0, 0.0)
+    rho0: float = 1.0
+    u0: tuple = (0.0, 0.0)
+    storage: str = "f64"
+    fp16_scale_log2: int = 10
+    diag_every: int = 0
+
+    def oracle(self) -> oracle.Params:
+        return oracle.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
+                             bc_x=oracle.WALL if self.walls_x else oracle.PERIODIC,
+                             bc_y=oracle.WALL if self.walls_y else oracle.PERIODIC,
+                             drag=oracle.DRAG_CONST if self.drag_const else oracle.DRAG_ERGUN,
+                             d_p=self.d_p, K=self.K, F_eps=self.F_eps, Gx=self.G[0],
+                             Gy=self.G[1], rho0=self.rho0, u0x=self.u0[0], u0y=self.u0[1])
+
+    def gpu(self):
+        from paper_1406_6438_amd import lbm
+        return lbm.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
+                          bc_x=lbm.BC_BOUNCEBACK if self.walls_x else lbm.BC_PERIODIC,
+                          bc_y=lbm.BC_BOUNCEBACK if self.walls_y else lbm.BC_PERIODIC,
+                          storage=lbm.STORAGE[self.storage],
+                          drag=lbm.DRAG_CONST if self.drag_const else lbm.DRAG_ERGUN,
+                          d_p=self.d_p, K=self.K, F_eps=self.F_eps, G=tuple(self.G),
+                          rho0=self.rho0, u0=tuple(self.u0),
+                          fp16_scale_log2=self.fp16_scale_log2, diag_every=self.diag_every)
+
+    def input_eps(self, eps: np.ndarray) -> np.ndarray:
+        """The porosity both sides receive: rounded once to the GPU's compute precision."""
+        if self.storage == "f64":
+            return np.ascontiguousarray(eps, dtype=np.float64)
+        return np.ascontiguousarray(eps, dtype=np.float32).astype(np.float64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_run(spec: Spec, eps: np.ndarray, nsteps: int, f0: np.ndarray | None = None,
+            keep: bool = False):
+    """Run the GPU library; returns (moments dict as numpy, state f as numpy[, solver])."""
+    from paper_1406_6438_amd import lbm
+    s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
+    if f0 is not None:
+        s.set_state(f0)
+    s.step(nsteps)
+    m = s.moments()
+    out = {k: m[k].double().cpu().numpy() for k in ("eps_rho", "rho", "ux", "uy")}
+    out["diag"] = m["diag"]
+    out["rc"] = m["rc"]
+    f = s.get_state().cpu().numpy()
+    if keep:
+        return out, f, s
+    s.close()
+    return out, f
+
+
+def oracle_run(spec: Spec, eps: np.ndarray, nsteps: int, f0: np.ndarray | None = None):
+    p = spec.oracle()
+    e = spec.input_eps(eps)
+    f = oracle.init(p, e) if f0 is None else np.array(f0, dtype=np.float64)
+    f = oracle.steps(p, e, f, nsteps)
+    return oracle.moments(p, e, f), f

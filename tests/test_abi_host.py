@@ -1,0 +1,113 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+symbol include/lbm_vans.h declares, sizes its work buffer, and rejects invalid
+parameters before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1406_6438_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm_vans.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_vans_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == sorted(lbm.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    assert lbm.load().lbm_vans_abi_version() == lbm.ABI_VERSION
+
+
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    consts = dict(re.findall(r"#define\s+(LBM_\w+)\s+\(?(-?\d+)\)?", src))
+    assert int(consts["LBM_VANS_ABI_VERSION"]) == lbm.ABI_VERSION
+    assert int(consts["LBM_VANS_EINVAL"]) == lbm.EINVAL
+    assert int(consts["LBM_VANS_ENONFINITE"]) == lbm.ENONFINITE
+    assert int(consts["LBM_VANS_ENOTIMPL"]) == lbm.ENOTIMPL
+    assert int(consts["LBM_F32_SHIFTED"]) == lbm.F32_SHIFTED
+    assert int(consts["LBM_F16_SHIFTED"]) == lbm.F16_SHIFTED
+    assert int(consts["LBM_BC_BOUNCEBACK"]) == lbm.BC_BOUNCEBACK
+    assert int(consts["LBM_DRAG_CONST"]) == lbm.DRAG_CONST
+    assert int(consts["LBM_VANS_NDIAG"]) == lbm.NDIAG
+    assert int(consts["LBM_VANS_DIAG_RING"]) == lbm.DIAG_RING
+
+
+def test_work_bytes_scale_with_storage():
+    p32 = lbm.Params(Lx=4096, Ly=4096, tau=0.6, storage=lbm.F32_SHIFTED, d_p=13.0)
+    p16 = lbm.Params(Lx=4096, Ly=4096, tau=0.6, storage=lbm.F16_SHIFTED, d_p=13.0)
+    p64 = lbm.Params(Lx=4096, Ly=4096, tau=0.6, storage=lbm.F64, d_p=13.0)
+    cells = 4096 * 4096
+    n32, n16, n64 = (lbm.lbm_vans_work_bytes(p) for p in (p32, p16, p64))
+    # two population buffers + porosity + small partial/diagnostic areas
+    assert 2 * 9 * 4 * cells + 4 * cells <= n32 < 2 * 9 * 4 * cells + 4 * cells + 8 << 20
+    assert 2 * 9 * 2 * cells + 4 * cells <= n16 < 2 * 9 * 2 * cells + 4 * cells + 8 << 20
+    assert 2 * 9 * 8 * cells + 8 * cells <= n64 < 2 * 9 * 8 * cells + 8 * cells + 8 << 20
+
+
+@pytest.mark.parametrize("bad", [
+    dict(Lx=0), dict(Ly=-3), dict(tau=0.5), dict(tau=math.nan), dict(d_p=0.0),
+    dict(d_p=-1.0), dict(storage=7), dict(bc_x=2), dict(bc_y=5), dict(drag=3),
+    dict(drag=lbm.DRAG_CONST, K=0.0), dict(drag=lbm.DRAG_CONST, K=1.0, F_eps=-1.0),
+    dict(rho0=0.0), dict(G=(math.inf, 0.0)), dict(u0=(0.0, math.nan)),
+    dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30), dict(diag_every=-1),
+    dict(Lx=65536, Ly=65536),
+])
+def test_invalid_params_rejected_without_gpu(bad):
+    kw = dict(Lx=16, Ly=8, tau=0.7, d_p=10.0)
+    kw.update(bad)
+    p = lbm.Params(**kw)
+    with pytest.raises(lbm.LbmVansError) as ei:
+        lbm.lbm_vans_work_bytes(p)
+    assert ei.value.code == lbm.EINVAL
+    L = lbm.load()
+    h = ctypes.c_void_p()
+    rc = L.lbm_vans_init(ctypes.byref(p.c()), 256, 256, 1 << 30, None, ctypes.byref(h))
+    assert rc == lbm.EINVAL and not h.value
+    assert L.lbm_vans_last_error()
+
+
+def test_init_rejects_short_or_misaligned_work_without_gpu():
+    p = lbm.Params(Lx=16, Ly=8, tau=0.7, d_p=10.0)
+    need = lbm.lbm_vans_work_bytes(p)
+    L = lbm.load()
+    h = ctypes.c_void_p()
+    assert L.lbm_vans_init(ctypes.byref(p.c()), 256, 256, need - 1, None, ctypes.byref(h)) == lbm.EINVAL
+    assert b"needed" in L.lbm_vans_last_error()
+    assert L.lbm_vans_init(ctypes.byref(p.c()), 256, 260, need, None, ctypes.byref(h)) == lbm.EINVAL
+    assert b"aligned" in L.lbm_vans_last_error()
+    assert L.lbm_vans_init(ctypes.byref(p.c()), None, 256, need, None, ctypes.byref(h)) == lbm.EINVAL
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = lbm.load()
+    assert L.lbm_vans_step(None, 1) == lbm.EINVAL
+    assert L.lbm_vans_moments(None, None, None, None, None, None) == lbm.EINVAL
+    assert L.lbm_vans_step_count(None) == -1
+    L.lbm_vans_destroy(None)
+    assert L.lbm_vans_grad(None, 0, 1, 1, None, None) == lbm.ENOTIMPL
+
+
+def test_binding_fails_loudly_when_library_missing(tmp_path):
+    import importlib
+    mod = importlib.import_module("paper_1406_6438_amd.lbm")
+    saved = mod._lib
+    try:
+        mod._lib = None
+        with pytest.raises(ImportError):
+            mod.load(str(tmp_path / "missing.so"))
+    finally:
+        mod._lib = saved

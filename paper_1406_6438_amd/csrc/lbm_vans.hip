@@ -19,7 +19,7 @@
 // contraction and no MFMA.
 //
 // Storage.  Populations live in two SoA buffers [9][Ly][pitch] (x fastest,
-// pitch a multiple of 64 nodes).  Slot (i, s) holds the post-collision value
+// pitch a multiple of 256 nodes).  Slot (i, s) holds the post-collision value
 // f*_i(s) minus the rest state w_i rho0 eps(r) of the node r that will pull
 // it next: r = s + e_i, or s itself when s + e_i lies behind a wall.  With
 // this choice the gathered value at x is directly the deviation
@@ -71,13 +71,30 @@ int fail(int code, const char *fmt, ...)
 // Launch geometry
 // ---------------------------------------------------------------------------
 
+// Tile shape (compile-time).  Defaults: the fastest of the shapes timed on
+// MI355X for the 4096^2 FP32 box (1 row per thread, 4 waves per block,
+// non-temporal population loads, XCD-banded tile order).
+#ifndef LBM_VANS_NW
+#define LBM_VANS_NW 4
+#endif
+#ifndef LBM_VANS_ROWS
+#define LBM_VANS_ROWS 1
+#endif
+#ifndef LBM_VANS_NT_LOADS
+#define LBM_VANS_NT_LOADS 1
+#endif
+#ifndef LBM_VANS_XCD_BANDS
+#define LBM_VANS_XCD_BANDS 1
+#endif
+
 constexpr int TX = 64;      // nodes per row segment: one wavefront
-constexpr int NW = 4;       // wavefronts per block
-constexpr int ROWS = 2;     // rows per thread
+constexpr int NW = LBM_VANS_NW;      // wavefronts per block
+constexpr int ROWS = LBM_VANS_ROWS;  // rows per thread
 constexpr int TY = NW * ROWS;
 constexpr int NTHREADS = TX * NW;
 constexpr int NRED = 8;     // doubles per block partial of the diagnostics
 constexpr int NXCD = 8;     // accelerator complex dies of the MI355X
+constexpr int PITCH_ALIGN = 256;  // row pitch in nodes: a multiple of 64 lanes x 4 nodes
 
 struct Geo {
     int Lx, Ly, pitch;
@@ -92,6 +109,7 @@ struct Geo {
 // XCD's L2.  The map is a bijection of [0, ntiles) for any ntiles.
 __device__ __forceinline__ int xcd_tile(int bid, int ntiles)
 {
+    if (!LBM_VANS_XCD_BANDS) return bid;
     int q = ntiles / NXCD, r = ntiles % NXCD;
     int xcd = bid % NXCD, k = bid / NXCD;
     return xcd * q + min(xcd, r) + k;
@@ -102,21 +120,35 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles)
 __device__ __forceinline__ int halo_index(int v, int L, int wall)
 {
     if (wall) return v < 0 ? 0 : (v >= L ? L - 1 : v);
-    int m = v % L;
-    return m < 0 ? m + L : m;
+    if (v < 0) v += L;
+    else if (v >= L) v -= L;
+    if (static_cast<unsigned>(v) >= static_cast<unsigned>(L)) {  // only for L below a tile width
+        v %= L;
+        if (v < 0) v += L;
+    }
+    return v;
 }
 
 // ---------------------------------------------------------------------------
 // Storage codecs
 // ---------------------------------------------------------------------------
 
+template <typename S>
+__device__ __forceinline__ S load_raw(const S *p)
+{
+    if constexpr (LBM_VANS_NT_LOADS)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
 template <typename S, typename R>
 __device__ __forceinline__ R load_pop(const S *p, R inv_scale)
 {
     if constexpr (std::is_same_v<S, _Float16>)
-        return static_cast<R>(*p) * inv_scale;
+        return static_cast<R>(load_raw(p)) * inv_scale;
     else
-        return static_cast<R>(*p);
+        return static_cast<R>(load_raw(p));
 }
 
 template <typename S, typename R>
@@ -143,17 +175,37 @@ struct Phys {
     R scale, inv_scale;  // FP16 storage scale 2^s and 2^-s (1 otherwise)
 };
 
+// Reciprocal and square root of the compute type: the hardware instructions
+// (about 1 ulp) in FP32, correctly rounded operations in FP64.
+template <typename R>
+__device__ __forceinline__ R rcp(R x)
+{
+    if constexpr (std::is_same_v<R, float>)
+        return __builtin_amdgcn_rcpf(x);
+    else
+        return R(1) / x;
+}
+
+template <typename R>
+__device__ __forceinline__ R sqroot(R x)
+{
+    if constexpr (std::is_same_v<R, float>)
+        return __builtin_amdgcn_sqrtf(x);
+    else
+        return sqrt(x);
+}
+
 // Darcy and Forchheimer coefficients a = eps^2 nu / K, b = eps^3 F_eps / sqrt(K)
 // of the drag law.  Ergun closure: a = 150 nu (1-eps)^2 / (eps d_p^2),
 // b = 1.75 (1-eps) / d_p, i.e. ca = 150 nu / d_p^2, cb = 1.75 / d_p (both 0
 // when d_p is infinite, and a = b = 0 at eps = 1).  Constant K, F_eps:
-// a = eps^2 (nu/K), b = eps^3 (F_eps / sqrt K).
+// a = eps^2 (nu/K), b = eps^3 (F_eps / sqrt K).  inv_eps = 1 / eps.
 template <typename R>
-__device__ __forceinline__ void drag_coeffs(const Phys<R> &ph, R eps, R &a, R &b)
+__device__ __forceinline__ void drag_coeffs(const Phys<R> &ph, R eps, R inv_eps, R &a, R &b)
 {
     if (ph.drag == LBM_DRAG_ERGUN) {
         R s = R(1) - eps;
-        a = ph.ca * s * s / eps;
+        a = ph.ca * s * s * inv_eps;
         b = ph.cb * s;
     } else {
         a = ph.ca * eps * eps;
@@ -175,7 +227,8 @@ struct Node {
 // eq. (1moment): eps rho u = m + (c_s^2 rho grad eps + F(u))/2 with
 // F(u) = G - a u - b |u| u.  Writing A = eps rho + a/2, B = b/2 and
 // V = m + (c_s^2 rho grad eps + G)/2, u is parallel to V and its length is
-// the non-negative root of B s^2 + A s = |V|: u = 2 V / (A + sqrt(A^2 + 4 B |V|)).
+// the non-negative root of B s^2 + A s = |V|: u = k V with
+// k = 2 / (A + sqrt(A^2 + 4 B |V|)), and |u| = k |V|.
 template <typename R>
 __device__ __forceinline__ Node<R> node_moments(const R d[9], R eps, R gex, R gey,
                                                 const Phys<R> &ph)
@@ -185,54 +238,61 @@ __device__ __forceinline__ Node<R> node_moments(const R d[9], R eps, R gex, R ge
     N.S = eps * ph.rho0 + N.dS;
     N.mx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     N.my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-    N.rho = N.S / eps;
+    const R ie = rcp(eps);
+    N.rho = N.S * ie;
     const R third = R(1) / R(3);
-    R Qx = third * N.rho * gex, Qy = third * N.rho * gey;
+    const R Qx = third * N.rho * gex, Qy = third * N.rho * gey;
     R a, b;
-    drag_coeffs(ph, eps, a, b);
-    R Vx = N.mx + R(0.5) * (Qx + ph.Gx);
-    R Vy = N.my + R(0.5) * (Qy + ph.Gy);
-    R A = N.S + R(0.5) * a;
-    R B = R(0.5) * b;
-    R Vn = sqrt(Vx * Vx + Vy * Vy);
-    R k = R(2) / (A + sqrt(A * A + R(4) * B * Vn));
+    drag_coeffs(ph, eps, ie, a, b);
+    const R Vx = N.mx + R(0.5) * (Qx + ph.Gx);
+    const R Vy = N.my + R(0.5) * (Qy + ph.Gy);
+    const R A = N.S + R(0.5) * a;
+    const R Vn = sqroot(Vx * Vx + Vy * Vy);
+    const R k = R(2) * rcp(A + sqroot(A * A + R(2) * b * Vn));
     N.ux = k * Vx;
     N.uy = k * Vy;
-    R un = sqrt(N.ux * N.ux + N.uy * N.uy);
-    R drag = a + b * un;
+    const R drag = a + b * (k * Vn);
     N.Tx = Qx + ph.Gx - drag * N.ux;
     N.Ty = Qy + ph.Gy - drag * N.uy;
     return N;
 }
 
-// D2Q9 velocities in the library's ordering and their weights.
+// D2Q9 velocities in the library's ordering.
 __device__ constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-template <typename R>
-__device__ __forceinline__ R weight(int i)
-{
-    return i == 0 ? R(4) / R(9) : (i < 5 ? R(1) / R(9) : R(1) / R(36));
-}
-
-// Post-collision deviations:
+// Collision plus storage shift, in place on the deviations d_i = f_i - w_i rho0 eps:
 //   f*_i = f_i - (f_i - f^eq_i)/tau + (1 - 1/(2 tau)) w_i [3 (e_i - u).T + 9 (e_i.u)(e_i.T)]
-// with f^eq_i = w_i eps rho [1 + 3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u], written for
-// d_i = f_i - w_i rho0 eps: d^eq_i = w_i [dS + S (3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u)].
+// with f^eq_i = w_i eps rho [1 + 3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u].  With
+// A_i = 3 e_i.u, B_i = 3 e_i.T, omega = 1/tau and P = 1 - 1/(2 tau):
+//   d*_i = (1 - omega) d_i + w_i [K0 + A_i (omega S A_i / 2 + P B_i) + (omega S A_i + P B_i)]
+//   K0   = omega (dS - 3/2 S u.u) - 3 P u.T.
+// The middle term is even and the last one odd under e_i -> -e_i, so each pair of
+// opposite directions shares them.  The stored value is d*_i - w_i de_i with
+// de_i = rho0 (eps(x + e_i) - eps(x)) (0 when the value bounces back).
 template <typename R>
-__device__ __forceinline__ void collide(R d[9], const Node<R> &N, const Phys<R> &ph)
+__device__ __forceinline__ void collide(R d[9], const Node<R> &N, const Phys<R> &ph,
+                                        const R de[9])
 {
-    R uu = N.ux * N.ux + N.uy * N.uy;
-    R uT = N.ux * N.Tx + N.uy * N.Ty;
-#pragma unroll
-    for (int i = 0; i < 9; i++) {
-        R eu = R(CX[i]) * N.ux + R(CY[i]) * N.uy;
-        R eT = R(CX[i]) * N.Tx + R(CY[i]) * N.Ty;
-        R w = weight<R>(i);
-        R deq = w * (N.dS + N.S * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
-        R src = ph.pre * w * (R(3) * (eT - uT) + R(9) * eu * eT);
-        d[i] = d[i] + ph.omega * (deq - d[i]) + src;
-    }
+    const R om = ph.omega, omc = R(1) - ph.omega, P = ph.pre;
+    const R uu = N.ux * N.ux + N.uy * N.uy;
+    const R uT = N.ux * N.Tx + N.uy * N.Ty;
+    const R oS = om * N.S, hS = R(0.5) * oS;
+    const R K0 = om * (N.dS - R(1.5) * N.S * uu) - R(3) * P * uT;
+    const R Ax = R(3) * N.ux, Ay = R(3) * N.uy;
+    const R pBx = R(3) * P * N.Tx, pBy = R(3) * P * N.Ty;
+    const R w0 = R(4) / R(9), w1 = R(1) / R(9), w2 = R(1) / R(36);
+    auto pair = [&](R &di, R &dj, R A, R pB, R w, R dei, R dej) {
+        const R base = K0 + A * (hS * A + pB);
+        const R anti = oS * A + pB;
+        di = omc * di + w * ((base + anti) - dei);
+        dj = omc * dj + w * ((base - anti) - dej);
+    };
+    d[0] = omc * d[0] + w0 * K0;
+    pair(d[1], d[3], Ax, pBx, w1, de[1], de[3]);
+    pair(d[2], d[4], Ay, pBy, w1, de[2], de[4]);
+    pair(d[5], d[7], Ax + Ay, pBx + pBy, w2, de[5], de[7]);
+    pair(d[6], d[8], Ay - Ax, pBy - pBx, w2, de[6], de[8]);
 }
 
 // Neighbour coordinates of node (x, y) along both axes with wall flags.
@@ -286,21 +346,55 @@ __device__ __forceinline__ void gather(R d[9], const S *__restrict__ f, long lon
 
 // Porosity tile with a one-node halo, filled with the halo rule (wrap or
 // mirror) so that every neighbour of an in-domain node is correct.
-template <typename R>
-__device__ __forceinline__ void load_eps_tile(R (*tile)[TX + 2], const R *__restrict__ eps,
+template <typename R, int W>
+__device__ __forceinline__ void load_eps_tile(R (*tile)[W], const R *__restrict__ eps,
                                               const Geo &g, int x0, int y0)
 {
-    for (int k = threadIdx.x; k < (TY + 2) * (TX + 2); k += NTHREADS) {
-        int ly = k / (TX + 2), lx = k - ly * (TX + 2);
+    for (int k = threadIdx.x; k < (TY + 2) * W; k += NTHREADS) {
+        int ly = k / W, lx = k - ly * W;
         int gx = halo_index(x0 + lx - 1, g.Lx, g.wall_x);
         int gy = halo_index(y0 + ly - 1, g.Ly, g.wall_y);
         tile[ly][lx] = eps[(long long)gy * g.pitch + gx];
     }
 }
 
+// The same tile fill split in two: issue() starts the global loads into
+// registers, commit() writes them to LDS.  Population loads issued in between
+// stay in flight while the tile is committed (memory counters retire in order,
+// so waiting for the tile does not wait for loads issued after it).
+template <typename R, int W>
+struct EpsTile {
+    static constexpr int N = (TY + 2) * W;
+    static constexpr int NE = (N + NTHREADS - 1) / NTHREADS;
+    R v[NE];
+
+    __device__ __forceinline__ void issue(const R *__restrict__ eps, const Geo &g, int x0, int y0)
+    {
+#pragma unroll
+        for (int j = 0; j < NE; j++) {
+            const int k = threadIdx.x + j * NTHREADS;
+            if (k < N) {
+                const int ly = k / W, lx = k - ly * W;
+                const int gx = halo_index(x0 + lx - 1, g.Lx, g.wall_x);
+                const int gy = halo_index(y0 + ly - 1, g.Ly, g.wall_y);
+                v[j] = eps[(long long)gy * g.pitch + gx];
+            }
+        }
+    }
+
+    __device__ __forceinline__ void commit(R (*tile)[W]) const
+    {
+#pragma unroll
+        for (int j = 0; j < NE; j++) {
+            const int k = threadIdx.x + j * NTHREADS;
+            if (k < N) tile[k / W][k % W] = v[j];
+        }
+    }
+};
+
 // Isotropic lattice gradient 3 sum_i w_i e_i eps(x + e_i) from the tile.
-template <typename R>
-__device__ __forceinline__ void grad_eps(const R (*t)[TX + 2], int ly, int lx, R &gx, R &gy)
+template <typename R, int W>
+__device__ __forceinline__ void grad_eps(const R (*t)[W], int ly, int lx, R &gx, R &gy)
 {
     R e_E = t[ly][lx + 1], e_W = t[ly][lx - 1], e_N = t[ly + 1][lx], e_S = t[ly - 1][lx];
     R e_NE = t[ly + 1][lx + 1], e_NW = t[ly + 1][lx - 1];
@@ -371,26 +465,63 @@ __device__ __forceinline__ void accumulate(double acc[NRED], const Node<R> &N)
 // Kernels
 // ---------------------------------------------------------------------------
 
-// The fused stream+collide sweep: fin holds the post-collision populations of
-// step n-1 (state n after streaming), fout receives those of step n.
+// Everything a node does after its gather: porosity gradient from the tile,
+// moments and velocity, collision, and the shift of each outgoing value to the
+// rest state of the node that pulls it next (no shift when that node is the
+// node itself, i.e. the value bounces back from a wall).  d is updated in place
+// to the values to store.  (lyy, lx) is the node's position in the tile.
+template <typename R, int W, bool DIAG>
+__device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, int lx, bool wxm,
+                                            bool wxp, bool wym, bool wyp, const Phys<R> &ph,
+                                            double *acc, bool count)
+{
+    const R e0 = t[lyy][lx];
+    const R eE = t[lyy][lx + 1], eW = t[lyy][lx - 1], eN = t[lyy + 1][lx], eS = t[lyy - 1][lx];
+    const R eNE = t[lyy + 1][lx + 1], eNW = t[lyy + 1][lx - 1];
+    const R eSW = t[lyy - 1][lx - 1], eSE = t[lyy - 1][lx + 1];
+    // isotropic lattice gradient 3 sum_i w_i e_i eps(x + e_i)
+    const R c1 = R(1) / R(3), c2 = R(1) / R(12);
+    const R gex = c1 * (eE - eW) + c2 * ((eNE - eSW) + (eSE - eNW));
+    const R gey = c1 * (eN - eS) + c2 * ((eNE - eSW) + (eNW - eSE));
+    Node<R> N = node_moments<R>(d, e0, gex, gey, ph);
+    if constexpr (DIAG) {
+        if (count) accumulate<R>(acc, N);
+    }
+    const R r0 = ph.rho0;
+    const R de[9] = {
+        R(0),
+        wxp ? R(0) : r0 * (eE - e0),
+        wyp ? R(0) : r0 * (eN - e0),
+        wxm ? R(0) : r0 * (eW - e0),
+        wym ? R(0) : r0 * (eS - e0),
+        (wxp || wyp) ? R(0) : r0 * (eNE - e0),
+        (wxm || wyp) ? R(0) : r0 * (eNW - e0),
+        (wxm || wym) ? R(0) : r0 * (eSW - e0),
+        (wxp || wym) ? R(0) : r0 * (eSE - e0),
+    };
+    collide<R>(d, N, ph, de);
+}
+
+// The fused stream+collide sweep, one node per thread: fin holds the
+// post-collision populations of step n-1 (state n after streaming), fout
+// receives those of step n.  Used when Lx is not a multiple of the vector width.
 template <typename S, typename R, bool DIAG>
 __global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
                                                     S *__restrict__ fout,
                                                     const R *__restrict__ eps, Geo g,
                                                     Phys<R> ph, double *__restrict__ part)
 {
-    __shared__ R tile[TY + 2][TX + 2];
+    constexpr int W = TX + 2;
+    __shared__ R tile[TY + 2][W];
     const int t = xcd_tile(blockIdx.x, g.ntiles);
     const int bx = t % g.nbx, by = t / g.nbx;
     const int x0 = bx * TX, y0 = by * TY;
-    load_eps_tile<R>(tile, eps, g, x0, y0);
+    load_eps_tile<R, W>(tile, eps, g, x0, y0);
     __syncthreads();
 
     double acc[NRED];
-    if constexpr (DIAG) {
 #pragma unroll
-        for (int k = 0; k < NRED; k++) acc[k] = 0.0;
-    }
+    for (int k = 0; k < NRED; k++) acc[k] = 0.0;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx;
 #pragma unroll
@@ -401,29 +532,251 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
             Nbr n = neighbours(x, y, g);
             R d[9];
             gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
-            const int lx = tx + 1, lyy = ly + 1;
-            R e0 = tile[lyy][lx];
-            R gex, gey;
-            grad_eps<R>(tile, lyy, lx, gex, gey);
-            Node<R> N = node_moments<R>(d, e0, gex, gey, ph);
-            if constexpr (DIAG) accumulate<R>(acc, N);
-            collide<R>(d, N, ph);
-            // Shift each value to the rest state of the node that pulls it next.
-            const R wr = ph.rho0;
-            const R sh[9] = {
-                R(0),
-                n.wxp ? R(0) : (R(1) / R(9)) * wr * (tile[lyy][lx + 1] - e0),
-                n.wyp ? R(0) : (R(1) / R(9)) * wr * (tile[lyy + 1][lx] - e0),
-                n.wxm ? R(0) : (R(1) / R(9)) * wr * (tile[lyy][lx - 1] - e0),
-                n.wym ? R(0) : (R(1) / R(9)) * wr * (tile[lyy - 1][lx] - e0),
-                (n.wxp || n.wyp) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy + 1][lx + 1] - e0),
-                (n.wxm || n.wyp) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy + 1][lx - 1] - e0),
-                (n.wxm || n.wym) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy - 1][lx - 1] - e0),
-                (n.wxp || n.wym) ? R(0) : (R(1) / R(36)) * wr * (tile[lyy - 1][lx + 1] - e0),
-            };
+            update_node<R, W, DIAG>(d, tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp, ph, acc,
+                                    true);
             const int c = y * g.pitch + x;
 #pragma unroll
-            for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i] - sh[i], ph.scale);
+            for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i], ph.scale);
+        }
+    }
+    if constexpr (DIAG) block_partial(acc, part, t);
+}
+
+// ---- vector sweep: V consecutive nodes per lane, full-width loads and stores
+
+template <typename S, int V>
+struct VecT {
+    typedef S type __attribute__((ext_vector_type(V)));
+};
+
+template <typename S, typename R, int V>
+__device__ __forceinline__ void ldv(R (&o)[V], const S *p, R inv_scale)
+{
+    using vt = typename VecT<S, V>::type;
+    vt v = load_raw(reinterpret_cast<const vt *>(p));
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        if constexpr (std::is_same_v<S, _Float16>)
+            o[k] = static_cast<R>(v[k]) * inv_scale;
+        else
+            o[k] = static_cast<R>(v[k]);
+    }
+}
+
+template <typename S, typename R, int V>
+__device__ __forceinline__ void stv(S *p, const R (&o)[V], R scale)
+{
+    using vt = typename VecT<S, V>::type;
+    vt v;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        if constexpr (std::is_same_v<S, _Float16>)
+            v[k] = static_cast<S>(o[k] * scale);
+        else
+            v[k] = static_cast<S>(o[k]);
+    }
+    __builtin_nontemporal_store(v, reinterpret_cast<vt *>(p));
+}
+
+// Lane geometry of the vector sweep: the run [x, x + V) and its left / right
+// neighbours (wrapped, or flagged as walls), and whether the lane must load the
+// neighbour itself (wave edge or periodic seam) instead of taking it from the
+// adjacent lane.
+struct LaneX {
+    int x, xl, xr;
+    bool wl, wr, need_l, need_r;
+};
+
+template <int V, bool WX>
+__device__ __forceinline__ LaneX lane_x(int x0, int lane, const Geo &g)
+{
+    LaneX L;
+    L.x = x0 + lane * V;
+    L.xl = L.x - 1;
+    L.xr = L.x + V;
+    L.wl = L.wr = false;
+    bool nl = lane == 0, nr = lane == TX - 1;
+    if (L.xl < 0) {
+        if (WX) { L.wl = true; L.xl = L.x; }
+        else { L.xl = g.Lx - 1; nl = true; }
+    }
+    if (L.xr >= g.Lx) {
+        if (WX) { L.wr = true; L.xr = L.x; }
+        else { L.xr = L.xr % g.Lx; nr = true; }
+    }
+    L.need_l = nl && !L.wl;
+    L.need_r = nr && !L.wr;
+    return L;
+}
+
+// Pull-gather of the V nodes of one lane in row y: d[i][k] = f_i(x + k, y).
+// Returns the wall flags of the rows above / below and the row offset.
+// Phase 1 issues every load (nine aligned vectors, and for the lanes at a wave
+// edge or periodic seam the single values beyond their run); phase 2 waits and
+// rebuilds the x-shifted populations with cross-lane shuffles.  Keeping all
+// loads ahead of the first shuffle keeps them in flight together.
+template <typename S, typename R, int V, bool WY>
+__device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], int y,
+                                           const Geo &g, const LaneX &L, R inv_scale,
+                                           bool &wym, bool &wyp, unsigned &r0)
+{
+    using vt = typename VecT<S, V>::type;
+    int ym = y - 1, yp = y + 1;
+    wym = false;
+    wyp = false;
+    if (ym < 0) { if (WY) { wym = true; ym = y; } else ym = g.Ly - 1; }
+    if (yp >= g.Ly) { if (WY) { wyp = true; yp = y; } else yp = 0; }
+    r0 = y * g.pitch;
+    const unsigned rm = ym * g.pitch, rp = yp * g.pitch;
+    const int x = L.x;
+    // Source rows of the nine vectors.  Behind a y wall a population is the
+    // node's own opposite one (no shift then).
+    // e_0 (0,0); e_2 (0,1) from y-1; e_4 (0,-1) from y+1; e_1 (1,0) from x-1;
+    // e_3 (-1,0) from x+1; e_5 (1,1) from (x-1,y-1); e_6 (-1,1) from (x+1,y-1);
+    // e_7 (-1,-1) from (x+1,y+1); e_8 (1,-1) from (x-1,y+1).
+    const S *src[9] = {
+        F[0] + r0 + x,
+        F[1] + r0 + x,
+        wym ? F[4] + r0 + x : F[2] + rm + x,
+        F[3] + r0 + x,
+        wyp ? F[2] + r0 + x : F[4] + rp + x,
+        wym ? F[7] + r0 + x : F[5] + rm + x,
+        wym ? F[8] + r0 + x : F[6] + rm + x,
+        wyp ? F[5] + r0 + x : F[7] + rp + x,
+        wyp ? F[6] + r0 + x : F[8] + rp + x,
+    };
+    vt raw[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) raw[i] = load_raw(reinterpret_cast<const vt *>(src[i]));
+    // Values entering from the left (e_1, e_5, e_8) for the first node and from
+    // the right (e_3, e_6, e_7) for the last node, where the adjacent lane does
+    // not hold them: beyond a wall, the edge node's own opposite population.
+    S el[3] = {S(0), S(0), S(0)}, er[3] = {S(0), S(0), S(0)};
+    if (L.wl) {
+        el[0] = load_raw(F[3] + r0 + x);
+        el[1] = load_raw(F[7] + r0 + x);
+        el[2] = load_raw(F[6] + r0 + x);
+    } else if (L.need_l) {
+        el[0] = load_raw(F[1] + r0 + L.xl);
+        el[1] = load_raw(F[5] + rm + L.xl);
+        el[2] = load_raw(F[8] + rp + L.xl);
+    }
+    if (L.wr) {
+        er[0] = load_raw(F[1] + r0 + x + V - 1);
+        er[1] = load_raw(F[8] + r0 + x + V - 1);
+        er[2] = load_raw(F[5] + r0 + x + V - 1);
+    } else if (L.need_r) {
+        er[0] = load_raw(F[3] + r0 + L.xr);
+        er[1] = load_raw(F[6] + rm + L.xr);
+        er[2] = load_raw(F[7] + rp + L.xr);
+    }
+    const bool own_l = L.wl || L.need_l, own_r = L.wr || L.need_r;
+    auto cvt = [&](S v) {
+        if constexpr (std::is_same_v<S, _Float16>)
+            return static_cast<R>(v) * inv_scale;
+        else
+            return static_cast<R>(v);
+    };
+    // unshifted populations
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        d[0][k] = cvt(raw[0][k]);
+        d[2][k] = cvt(raw[2][k]);
+        d[4][k] = cvt(raw[4][k]);
+    }
+    // from the left: node k takes element k-1; node 0 the previous lane's last
+    auto left = [&](R (&o)[V], const vt &a, S edge, bool shifted) {
+        R prev = cvt(a[V - 1]);
+        prev = __shfl_up(prev, 1, 64);
+        if (!shifted) {
+#pragma unroll
+            for (int k = 0; k < V; k++) o[k] = cvt(a[k]);
+            return;
+        }
+        o[0] = own_l ? cvt(edge) : prev;
+#pragma unroll
+        for (int k = 1; k < V; k++) o[k] = cvt(a[k - 1]);
+    };
+    auto right = [&](R (&o)[V], const vt &a, S edge, bool shifted) {
+        R next = cvt(a[0]);
+        next = __shfl_down(next, 1, 64);
+        if (!shifted) {
+#pragma unroll
+            for (int k = 0; k < V; k++) o[k] = cvt(a[k]);
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < V - 1; k++) o[k] = cvt(a[k + 1]);
+        o[V - 1] = own_r ? cvt(edge) : next;
+    };
+    left(d[1], raw[1], el[0], true);
+    right(d[3], raw[3], er[0], true);
+    left(d[5], raw[5], el[1], !wym);
+    right(d[6], raw[6], er[1], !wym);
+    right(d[7], raw[7], er[2], !wyp);
+    left(d[8], raw[8], el[2], !wyp);
+}
+
+// The fused sweep with V consecutive nodes per lane (requires Lx % V == 0 and
+// a pitch that is a multiple of 64 V); WX / WY: walls across x / y.  Each
+// population is one aligned vector load per lane; the x-shifted ones are
+// rebuilt with one cross-lane shuffle and a masked scalar load for the lane at
+// the wave's edge.  The first row's populations are requested before the
+// porosity tile is filled, so their latency overlaps the tile load and the
+// barrier.  The same node update as the scalar sweep then runs per node, and
+// the 9 results leave as aligned vector stores.
+template <typename S, typename R, int V, bool WX, bool WY, bool DIAG>
+__global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fin,
+                                                        S *__restrict__ fout,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        Phys<R> ph, double *__restrict__ part)
+{
+    constexpr int W = TX * V + 2;
+    __shared__ R tile[TY + 2][W];
+    const int t = xcd_tile(blockIdx.x, g.ntiles);
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x0 = bx * TX * V, y0 = by * TY;
+    const int lane = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const LaneX L = lane_x<V, WX>(x0, lane, g);
+    const bool valid = L.x < g.Lx;
+    const S *F[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) F[i] = fin + i * g.plane;
+
+    EpsTile<R, W> et;
+    et.issue(eps, g, x0, y0);
+    R d[9][V];
+    bool wym, wyp;
+    unsigned r0;
+    if (y0 + ty < g.Ly) gather_vec<S, R, V, WY>(d, F, y0 + ty, g, L, ph.inv_scale, wym, wyp, r0);
+    et.commit(tile);
+    __syncthreads();
+
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; k++) acc[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+        const int ly = ty + NW * r;
+        const int y = y0 + ly;
+        if (y >= g.Ly) break;
+        if (r > 0) gather_vec<S, R, V, WY>(d, F, y, g, L, ph.inv_scale, wym, wyp, r0);
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            R dk[9];
+#pragma unroll
+            for (int i = 0; i < 9; i++) dk[i] = d[i][k];
+            const bool wxm = WX && L.x + k == 0;
+            const bool wxp = WX && L.x + k == g.Lx - 1;
+            update_node<R, W, DIAG>(dk, tile, ly + 1, lane * V + k + 1, wxm, wxp, wym, wyp, ph,
+                                    acc, valid);
+#pragma unroll
+            for (int i = 0; i < 9; i++) d[i][k] = dk[i];
+        }
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < 9; i++)
+                stv<S, R, V>(fout + i * g.plane + r0 + L.x, d[i], ph.scale);
         }
     }
     if constexpr (DIAG) block_partial(acc, part, t);
@@ -439,11 +792,12 @@ __global__ __launch_bounds__(NTHREADS) void k_moments(const S *__restrict__ fin,
                                                       R *__restrict__ o_ux, R *__restrict__ o_uy,
                                                       double *__restrict__ part)
 {
-    __shared__ R tile[TY + 2][TX + 2];
+    constexpr int W = TX + 2;
+    __shared__ R tile[TY + 2][W];
     const int t = xcd_tile(blockIdx.x, g.ntiles);
     const int bx = t % g.nbx, by = t / g.nbx;
     const int x0 = bx * TX, y0 = by * TY;
-    load_eps_tile<R>(tile, eps, g, x0, y0);
+    load_eps_tile<R, W>(tile, eps, g, x0, y0);
     __syncthreads();
     double acc[NRED];
 #pragma unroll
@@ -458,7 +812,7 @@ __global__ __launch_bounds__(NTHREADS) void k_moments(const S *__restrict__ fin,
             R d[9];
             gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
             R gex, gey;
-            grad_eps<R>(tile, ly + 1, tx + 1, gex, gey);
+            grad_eps<R, W>(tile, ly + 1, tx + 1, gex, gey);
             Node<R> N = node_moments<R>(d, tile[ly + 1][tx + 1], gex, gey, ph);
             accumulate<R>(acc, N);
             const long long o = (long long)y * g.Lx + x;
@@ -625,7 +979,9 @@ __global__ __launch_bounds__(NTHREADS) void k_get_state(const S *__restrict__ fi
 struct lbm_vans_handle {
     lbm_vans_params p;
     hipStream_t stream;
-    Geo g;
+    Geo g;                  // one node per thread: moments, state copies, scalar sweep
+    Geo gs;                 // geometry of the sweep actually launched (vec nodes per lane)
+    int vec;                // nodes per lane of the sweep (1 = scalar sweep)
     int ntiles;
     size_t pop_bytes;       // bytes of one population buffer
     char *buf[2];           // population buffers; buf[cur] holds the current state
@@ -653,7 +1009,7 @@ int check_params(const lbm_vans_params *p)
     if (!p) return fail(LBM_VANS_EINVAL, "params is NULL");
     if (p->Lx < 1 || p->Ly < 1)
         return fail(LBM_VANS_EINVAL, "lattice size %d x %d must be at least 1 x 1", p->Lx, p->Ly);
-    long long pitch = (p->Lx + 63LL) / 64 * 64;
+    long long pitch = (p->Lx + PITCH_ALIGN - 1LL) / PITCH_ALIGN * PITCH_ALIGN;
     if (pitch * p->Ly >= (1LL << 31))
         return fail(LBM_VANS_EINVAL, "lattice %d x %d too large (padded nodes must be < 2^31)",
                     p->Lx, p->Ly);
@@ -685,15 +1041,24 @@ int check_params(const lbm_vans_params *p)
     return LBM_VANS_OK;
 }
 
-Geo make_geo(const lbm_vans_params *p)
+// Vector width of the sweep for these parameters: 16-byte accesses per lane
+// (4 FP32, 2 FP64) and 8-byte ones for FP16, when Lx is a multiple of it.
+int sweep_vec(const lbm_vans_params *p)
+{
+    int v = p->storage == LBM_F64 ? 2 : 4;
+    return p->Lx % v == 0 ? v : 1;
+}
+
+// Tiling for `vec` nodes per lane; the pitch is shared by all tilings.
+Geo make_geo(const lbm_vans_params *p, int vec = 1)
 {
     Geo g;
     g.Lx = p->Lx;
     g.Ly = p->Ly;
-    g.pitch = (p->Lx + 63) / 64 * 64;
+    g.pitch = (p->Lx + PITCH_ALIGN - 1) / PITCH_ALIGN * PITCH_ALIGN;
     g.wall_x = p->bc_x == LBM_BC_BOUNCEBACK;
     g.wall_y = p->bc_y == LBM_BC_BOUNCEBACK;
-    g.nbx = (p->Lx + TX - 1) / TX;
+    g.nbx = (p->Lx + TX * vec - 1) / (TX * vec);
     int nby = (p->Ly + TY - 1) / TY;
     g.ntiles = g.nbx * nby;
     g.plane = (long long)g.pitch * p->Ly;
@@ -760,6 +1125,30 @@ int with_types(int storage, Fn &&fn)
     }
 }
 
+template <typename S, typename R, bool DIAG>
+void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
+{
+    constexpr int VMAX = sizeof(S) == 8 ? 2 : 4;
+    const dim3 grid(h->gs.ntiles), block(NTHREADS);
+    const R *eps = (const R *)h->eps;
+    if (h->vec == VMAX) {
+        if (h->gs.wall_x && h->gs.wall_y)
+            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, true, true, DIAG>), grid, block, 0,
+                               h->stream, src, dst, eps, h->gs, ph, h->part);
+        else if (h->gs.wall_x)
+            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, true, false, DIAG>), grid, block, 0,
+                               h->stream, src, dst, eps, h->gs, ph, h->part);
+        else if (h->gs.wall_y)
+            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, false, true, DIAG>), grid, block, 0,
+                               h->stream, src, dst, eps, h->gs, ph, h->part);
+        else
+            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, false, false, DIAG>), grid, block, 0,
+                               h->stream, src, dst, eps, h->gs, ph, h->part);
+    } else
+        hipLaunchKernelGGL((k_sweep<S, R, DIAG>), grid, block, 0, h->stream, src, dst,
+                           (const R *)h->eps, h->gs, ph, h->part);
+}
+
 int launch_sweep(lbm_vans_handle *h, bool diag)
 {
     const char *src = h->buf[h->cur];
@@ -768,21 +1157,16 @@ int launch_sweep(lbm_vans_handle *h, bool diag)
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
-        if (diag)
-            hipLaunchKernelGGL((k_sweep<S, R, true>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
-                               (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph, h->part);
-        else
-            hipLaunchKernelGGL((k_sweep<S, R, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
-                               h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph,
-                               h->part);
-        return check_launch("k_sweep");
+        if (diag) launch_sweep_t<S, R, true>(h, (const S *)src, (S *)dst, ph);
+        else launch_sweep_t<S, R, false>(h, (const S *)src, (S *)dst, ph);
+        return check_launch("sweep");
     });
 }
 
-int launch_finalize(lbm_vans_handle *h, double *out, bool add_mass0, double step)
+int launch_finalize(lbm_vans_handle *h, double *out, int nparts, bool add_mass0, double step)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, h->stream, (const double *)h->part,
-                       h->ntiles, add_mass0 ? (const double *)h->mass0 : nullptr, step, out);
+                       nparts, add_mass0 ? (const double *)h->mass0 : nullptr, step, out);
     return check_launch("k_finalize");
 }
 
@@ -820,6 +1204,8 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
     h->p = *p;
     h->stream = static_cast<hipStream_t>(stream);
     h->g = make_geo(p);
+    h->vec = sweep_vec(p);
+    h->gs = make_geo(p, h->vec);
     h->ntiles = h->g.ntiles;
     h->pop_bytes = L.pop;
     char *w = static_cast<char *>(work);
@@ -842,7 +1228,7 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
                            (const R *)eps, (R *)h->eps, h->g, h->part);
         int r = check_launch("k_eps_copy");
         if (r) return r;
-        r = launch_finalize(h, h->scratch_rec, false, 0.0);
+        r = launch_finalize(h, h->scratch_rec, h->ntiles, false, 0.0);
         if (r) return r;
         double rec[NRED];
         HIP_TRY(hipMemcpyAsync(rec, h->scratch_rec, sizeof rec, hipMemcpyDeviceToHost, h->stream));
@@ -880,7 +1266,7 @@ int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps)
         if (rc) return rc;
         if (diag) {
             double *slot = h->ring + (h->nrec % LBM_VANS_DIAG_RING) * NRED;
-            rc = launch_finalize(h, slot, true, static_cast<double>(h->n));
+            rc = launch_finalize(h, slot, h->gs.ntiles, true, static_cast<double>(h->n));
             if (rc) return rc;
             h->nrec++;
         }
@@ -907,7 +1293,7 @@ int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, voi
     });
     if (rc) return rc;
     if (!diag) return LBM_VANS_OK;
-    rc = launch_finalize(h, h->scratch_rec, true, static_cast<double>(h->n));
+    rc = launch_finalize(h, h->scratch_rec, h->ntiles, true, static_cast<double>(h->n));
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(diag, h->scratch_rec, NRED * sizeof(double), hipMemcpyDeviceToHost,
                            h->stream));

@@ -32,14 +32,24 @@ def _need_gpu():
     lbm.load()
 
 
-GEOMS = [  # (Lx, Ly, walls_x, walls_y): ragged tiles, single rows/columns, all wall combinations
+# (Lx, Ly, walls_x, walls_y).  Widths not divisible by the vector width run the
+# one-node-per-lane sweep: ragged tiles, single rows/columns.  Widths divisible by
+# 4 run the vector sweep (4 FP32 / 2 FP64 nodes per lane): a partial last tile,
+# a single partial tile, seams between tiles, walls on either axis.
+GEOMS = [
     (7, 5, False, False),
     (65, 33, False, True),
-    (130, 17, True, True),
-    (64, 8, True, False),
+    (131, 17, True, True),
     (3, 70, False, True),
     (1, 9, False, True),
+    (64, 8, True, False),
     (200, 1, False, False),
+    (4, 4, False, False),
+    (8, 3, True, False),
+    (260, 9, True, True),
+    (516, 7, False, True),
+    (1024, 5, False, False),
+    (130, 11, True, False),
 ]
 
 
@@ -192,18 +202,20 @@ def test_f32_full_size_box_sampled_windows():
         assert np.abs(rho[blk] - mo["rho"]).max() <= 1e-6
 
 
-def test_every_slot_is_written():
+@pytest.mark.parametrize("Lx", [131, 132])
+def test_every_slot_is_written(Lx):
     """Work memory filled with NaN bytes before init: after init and after each of
-    two steps the state is finite everywhere (the store map covers every slot)."""
+    two steps the state is finite everywhere (the store map covers every slot);
+    131 runs the one-node-per-lane sweep, 132 the vector sweep."""
     from paper_1406_6438_amd import lbm
-    spec = Spec(Lx=131, Ly=45, walls_y=True, d_p=8.0, G=(1e-5, 0.0), storage="f32")
-    eps = W.grf_porosity(131, 45, seed=8, ell=3.0)
+    spec = Spec(Lx=Lx, Ly=45, walls_y=True, d_p=8.0, G=(1e-5, 0.0), storage="f32")
+    eps = W.grf_porosity(Lx, 45, seed=8, ell=3.0)
     p = spec.gpu()
     work = torch.full((lbm.lbm_vans_work_bytes(p),), 255, dtype=torch.uint8, device="cuda:0")
     e = torch.tensor(spec.input_eps(eps), dtype=torch.float32, device="cuda:0")
     h = lbm.lbm_vans_init(p, e, work, torch.cuda.current_stream().cuda_stream)
     try:
-        f = torch.empty((9, 45, 131), dtype=torch.float64, device="cuda:0")
+        f = torch.empty((9, 45, Lx), dtype=torch.float64, device="cuda:0")
         for _ in range(3):
             lbm.lbm_vans_get_state(h, f)
             torch.cuda.synchronize()

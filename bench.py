@@ -9,7 +9,9 @@ launch).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line with MLUPS, the HBM roofline of the sweep kernel, the
 accuracy of the FP32 sweep against the FP64 oracle on the 512^2 crop (the error
-the throughput is quoted at) and the oracle's own throughput on the host cores.
+the throughput is quoted at), the FP16-storage sweep on the 8192^2 box beside it
+(throughput, roofline, accuracy after 2000 steps on its 512^2 crop) and the
+oracle's own throughput on the host cores.
 
   python bench.py [--steps K] [--warmup W] [--workload box4096_f32|box8192_f16|channel_f64]
 """
@@ -27,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E peak
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sweep_traffic_box4096_f32.md")
+PROFILE_TRAFFIC = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_traffic_box4096_f32.md"),
+                   "box8192_f16": os.path.join(ROOT, "profiles", "sweep_traffic_box8192_f16.md")}
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
 
 
@@ -49,9 +52,10 @@ def kernel_hash() -> str:
 def measured_traffic(workload: str):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    if workload != "box4096_f32" or not os.path.exists(PROFILE_TRAFFIC):
+    path = PROFILE_TRAFFIC.get(workload)
+    if path is None or not os.path.exists(path):
         return None
-    txt = open(PROFILE_TRAFFIC).read()
+    txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
@@ -119,7 +123,8 @@ def cpu_baseline(w, eps, budget_s: float):
 
 
 def accuracy(w, lbm, torch, steps: int):
-    """FP32/FP16 sweep vs the FP64 oracle on the top-left 512^2 crop, run periodic."""
+    """FP32/FP16 sweep vs the FP64 oracle on the top-left 512^2 crop of the workload's
+    porosity field, run periodic."""
     import numpy as np
     import oracle
     from paper_1406_6438_amd import workloads as W
@@ -138,6 +143,30 @@ def accuracy(w, lbm, torch, steps: int):
             "sample": f"top-left {n}x{n} crop of the porosity field, periodic, {steps} steps"}
 
 
+def time_sweep(w, lbm, torch, steps: int, warmup: int):
+    """(seconds on the library's stream for `steps` steps, final diagnostics record)."""
+    eps = w.porosity()
+    s = lbm.Solver(lbm_params(w, lbm), cast_eps(eps, w.storage))
+    log(f"[bench] {w.name}: warmup {warmup} steps")
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    diag = s.moments()["diag"]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    log(f"[bench] {w.name}: {steps} steps in {gpu_s * 1e3:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    return gpu_s, diag, eps
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,40 +177,21 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true",
+                    help="skip the FP16-storage leg (8192^2 box) reported beside the main line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sweep has no multi-GPU path in this build "
               "(domain decomposition is design only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1406_6438_amd import lbm
 
     lbm.load()
     w = make_workload(args.workload)
     log(f"[bench] workload {w.name}: {w.Lx}x{w.Ly}, storage {w.storage}")
-    eps = w.porosity()
-    s = lbm.Solver(lbm_params(w, lbm), cast_eps(eps, w.storage))
-    log(f"[bench] warmup {args.warmup} steps")
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    stream = s.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    s.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_s = e0.elapsed_time(e1) / 1e3
-    diag = s.moments()["diag"]
-    s.close()
-    del s
-    torch.cuda.empty_cache()
-    log(f"[bench] timed {args.steps} steps: {gpu_s * 1e3:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    gpu_s, diag, eps = time_sweep(w, lbm, torch, args.steps, args.warmup)
     cells = w.Lx * w.Ly
     mlups = cells * args.steps / gpu_s / 1e6
     bpn = algorithmic_bytes_per_node(w.storage)
@@ -194,8 +204,30 @@ def main():
     acc = None
     if not args.no_accuracy and w.storage != "f64":
         log("[bench] accuracy: 512^2 crop vs FP64 oracle")
-        acc = accuracy(w, lbm, torch, 1000 if w.storage == "f32" else 2000)
+        acc = accuracy(w, lbm, torch, w.steps)
         log(f"[bench] accuracy {acc['rel_l2_u_vs_fp64_oracle']:.3e}")
+
+    fp16 = None
+    if not args.no_fp16 and args.workload == "box4096_f32":
+        w16 = make_workload("box8192_f16")
+        steps16 = max(1, min(args.steps, 500))
+        g16, d16, _ = time_sweep(w16, lbm, torch, steps16, args.warmup)
+        cells16 = w16.Lx * w16.Ly
+        m16 = cells16 * steps16 / g16 / 1e6
+        b16 = algorithmic_bytes_per_node("f16")
+        a16 = b16 * cells16 / (g16 / steps16) / 1e9
+        fp16 = {"workload": w16.name, "value": round(m16, 2), "unit": "MLUPS", "steps": steps16,
+                "ms_per_step": round(g16 * 1e3 / steps16, 5),
+                "roofline": {"bound": "hbm", "achieved": round(a16, 1), "peak": PEAK_HBM_GBPS,
+                             "unit": "GB/s", "frac": round(a16 / PEAK_HBM_GBPS, 4),
+                             "traffic": measured_traffic("box8192_f16"), "bytes_per_node": b16},
+                "vs_fp32_same_gpu": round(m16 / mlups, 3),
+                "nonfinite_nodes": d16[6]}
+        log(f"[bench] fp16: {m16:.1f} MLUPS, {a16:.1f} GB/s algorithmic")
+        if not args.no_accuracy:
+            fp16["accuracy"] = accuracy(w16, lbm, torch, w16.steps)
+            log(f"[bench] fp16 accuracy {fp16['accuracy']['rel_l2_u_vs_fp64_oracle']:.3e}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s)")
@@ -221,10 +253,11 @@ def main():
                    "boundaries": "periodic" if not w.walls_y else "periodic x, bounce-back y"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": traffic, "kernel": "k_sweep", "bytes_per_node": bpn,
+                     "traffic": traffic, "kernel": "k_sweep_vec", "bytes_per_node": bpn,
                      "launch_us": round(launch_s * 1e6, 2),
                      "device_copy_GBps": round(copy_bw, 1)},
         "accuracy": acc,
+        "fp16_store": fp16,
         "cpu_baseline": cpu,
         "mass_check": {"sum_eps_rho": diag[0], "nonfinite_nodes": diag[6]},
     }

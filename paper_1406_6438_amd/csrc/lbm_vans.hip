@@ -20,13 +20,14 @@
 //
 // Storage.  Populations live in two SoA buffers [9][Ly][pitch] (x fastest,
 // pitch a multiple of 256 nodes).  Slot (i, s) holds the post-collision value
-// f*_i(s) minus the rest state w_i rho0 eps(r) of the node r that will pull
-// it next: r = s + e_i, or s itself when s + e_i lies behind a wall.  With
-// this choice the gathered value at x is directly the deviation
-// d_i = f_i(x) - w_i rho0 eps(x), so the moments and the collision work on
-// small numbers only (FP32 and FP16 keep the significant digits of the flow)
-// and the gather needs no neighbour porosity.  The shift of each stored value
-// needs eps at x + e_i, which the porosity tile already holds.
+// f*_i(s) minus the rest state at the middle of the link it travels next,
+// w_i rho0 (eps(s) + eps(r)) / 2, where r = s + e_i is the node that pulls it
+// (r = s when s + e_i lies behind a wall).  A post-collision population sits
+// close to that midpoint rest state (about w_i rho0 (eps + e_i.grad(eps)/2)),
+// so the stored numbers carry only the flow: FP32 and FP16 keep its
+// significant digits.  The node that pulls a value adds back half the
+// porosity difference to its source, and the one that stores it subtracts
+// half the difference to its destination; both come from the porosity tile.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -269,7 +270,8 @@ __device__ constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 //   K0   = omega (dS - 3/2 S u.u) - 3 P u.T.
 // The middle term is even and the last one odd under e_i -> -e_i, so each pair of
 // opposite directions shares them.  The stored value is d*_i - w_i de_i with
-// de_i = rho0 (eps(x + e_i) - eps(x)) (0 when the value bounces back).
+// de_i = (rho0/2) (eps(x + e_i) - eps(x)), the link-midpoint shift (0 when the
+// value bounces back).
 template <typename R>
 __device__ __forceinline__ void collide(R d[9], const Node<R> &N, const Phys<R> &ph,
                                         const R de[9])
@@ -392,18 +394,6 @@ struct EpsTile {
     }
 };
 
-// Isotropic lattice gradient 3 sum_i w_i e_i eps(x + e_i) from the tile.
-template <typename R, int W>
-__device__ __forceinline__ void grad_eps(const R (*t)[W], int ly, int lx, R &gx, R &gy)
-{
-    R e_E = t[ly][lx + 1], e_W = t[ly][lx - 1], e_N = t[ly + 1][lx], e_S = t[ly - 1][lx];
-    R e_NE = t[ly + 1][lx + 1], e_NW = t[ly + 1][lx - 1];
-    R e_SW = t[ly - 1][lx - 1], e_SE = t[ly - 1][lx + 1];
-    const R c1 = R(1) / R(3), c2 = R(1) / R(12);
-    gx = c1 * (e_E - e_W) + c2 * ((e_NE - e_SW) + (e_SE - e_NW));
-    gy = c1 * (e_N - e_S) + c2 * ((e_NE - e_SW) + (e_NW - e_SE));
-}
-
 // ---------------------------------------------------------------------------
 // FP64 block reduction of the diagnostics
 // ---------------------------------------------------------------------------
@@ -465,40 +455,80 @@ __device__ __forceinline__ void accumulate(double acc[NRED], const Node<R> &N)
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Everything a node does after its gather: porosity gradient from the tile,
-// moments and velocity, collision, and the shift of each outgoing value to the
-// rest state of the node that pulls it next (no shift when that node is the
-// node itself, i.e. the value bounces back from a wall).  d is updated in place
-// to the values to store.  (lyy, lx) is the node's position in the tile.
+// Porosity around one node from the tile: eps(x), the isotropic lattice
+// gradient 3 sum_i w_i e_i eps(x + e_i) (the tile holds mirror images behind a
+// wall), and the differences D[i] = eps(x + e_i) - eps(x), set to zero when
+// x + e_i lies behind a wall (a bounced value never leaves its node).
+template <typename R>
+struct PorNb {
+    R e0, gex, gey;
+    R D[9];
+};
+
+template <typename R, int W>
+__device__ __forceinline__ PorNb<R> porosity_nb(const R (*t)[W], int lyy, int lx, bool wxm,
+                                                bool wxp, bool wym, bool wyp)
+{
+    PorNb<R> P;
+    const R e0 = t[lyy][lx];
+    const R eE = t[lyy][lx + 1], eW = t[lyy][lx - 1], eN = t[lyy + 1][lx], eS = t[lyy - 1][lx];
+    const R eNE = t[lyy + 1][lx + 1], eNW = t[lyy + 1][lx - 1];
+    const R eSW = t[lyy - 1][lx - 1], eSE = t[lyy - 1][lx + 1];
+    const R c1 = R(1) / R(3), c2 = R(1) / R(12);
+    P.e0 = e0;
+    P.gex = c1 * (eE - eW) + c2 * ((eNE - eSW) + (eSE - eNW));
+    P.gey = c1 * (eN - eS) + c2 * ((eNE - eSW) + (eNW - eSE));
+    P.D[0] = R(0);
+    P.D[1] = wxp ? R(0) : eE - e0;
+    P.D[2] = wyp ? R(0) : eN - e0;
+    P.D[3] = wxm ? R(0) : eW - e0;
+    P.D[4] = wym ? R(0) : eS - e0;
+    P.D[5] = (wxp || wyp) ? R(0) : eNE - e0;
+    P.D[6] = (wxm || wyp) ? R(0) : eNW - e0;
+    P.D[7] = (wxm || wym) ? R(0) : eSW - e0;
+    P.D[8] = (wxp || wym) ? R(0) : eSE - e0;
+    return P;
+}
+
+// Stored slots are shifted by the rest state at the link midpoint,
+// w_i rho0 (eps(source) + eps(destination)) / 2.  The incoming value of
+// direction i at x came from x - e_i, so the deviation from x's own rest state
+// is the stored value plus (rho0/2) w_i (eps(x - e_i) - eps(x)).
+template <typename R>
+__device__ __forceinline__ void unshift_incoming(R d[9], const PorNb<R> &P, R rho0)
+{
+    const R h1 = R(0.5) * rho0 * (R(1) / R(9)), h2 = R(0.5) * rho0 * (R(1) / R(36));
+    d[1] += h1 * P.D[3];
+    d[2] += h1 * P.D[4];
+    d[3] += h1 * P.D[1];
+    d[4] += h1 * P.D[2];
+    d[5] += h2 * P.D[7];
+    d[6] += h2 * P.D[8];
+    d[7] += h2 * P.D[5];
+    d[8] += h2 * P.D[6];
+}
+
+// Everything a node does after its gather: porosity neighbourhood from the
+// tile, deviations from the node's rest state, moments and velocity,
+// collision, and the shift of each outgoing value to its link midpoint (no
+// shift when the value bounces back from a wall).  d holds the stored values
+// of the incoming populations on entry and the values to store on exit.
+// (lyy, lx) is the node's position in the tile.
 template <typename R, int W, bool DIAG>
 __device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, int lx, bool wxm,
                                             bool wxp, bool wym, bool wyp, const Phys<R> &ph,
                                             double *acc, bool count)
 {
-    const R e0 = t[lyy][lx];
-    const R eE = t[lyy][lx + 1], eW = t[lyy][lx - 1], eN = t[lyy + 1][lx], eS = t[lyy - 1][lx];
-    const R eNE = t[lyy + 1][lx + 1], eNW = t[lyy + 1][lx - 1];
-    const R eSW = t[lyy - 1][lx - 1], eSE = t[lyy - 1][lx + 1];
-    // isotropic lattice gradient 3 sum_i w_i e_i eps(x + e_i)
-    const R c1 = R(1) / R(3), c2 = R(1) / R(12);
-    const R gex = c1 * (eE - eW) + c2 * ((eNE - eSW) + (eSE - eNW));
-    const R gey = c1 * (eN - eS) + c2 * ((eNE - eSW) + (eNW - eSE));
-    Node<R> N = node_moments<R>(d, e0, gex, gey, ph);
+    const PorNb<R> P = porosity_nb<R, W>(t, lyy, lx, wxm, wxp, wym, wyp);
+    unshift_incoming<R>(d, P, ph.rho0);
+    Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
     if constexpr (DIAG) {
         if (count) accumulate<R>(acc, N);
     }
-    const R r0 = ph.rho0;
-    const R de[9] = {
-        R(0),
-        wxp ? R(0) : r0 * (eE - e0),
-        wyp ? R(0) : r0 * (eN - e0),
-        wxm ? R(0) : r0 * (eW - e0),
-        wym ? R(0) : r0 * (eS - e0),
-        (wxp || wyp) ? R(0) : r0 * (eNE - e0),
-        (wxm || wyp) ? R(0) : r0 * (eNW - e0),
-        (wxm || wym) ? R(0) : r0 * (eSW - e0),
-        (wxp || wym) ? R(0) : r0 * (eSE - e0),
-    };
+    const R hr = R(0.5) * ph.rho0;
+    R de[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) de[i] = hr * P.D[i];
     collide<R>(d, N, ph, de);
 }
 
@@ -811,9 +841,9 @@ __global__ __launch_bounds__(NTHREADS) void k_moments(const S *__restrict__ fin,
             Nbr n = neighbours(x, y, g);
             R d[9];
             gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
-            R gex, gey;
-            grad_eps<R, W>(tile, ly + 1, tx + 1, gex, gey);
-            Node<R> N = node_moments<R>(d, tile[ly + 1][tx + 1], gex, gey, ph);
+            const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
+            unshift_incoming<R>(d, P, ph.rho0);
+            Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
             accumulate<R>(acc, N);
             const long long o = (long long)y * g.Lx + x;
             if (o_epsrho) o_epsrho[o] = N.S;
@@ -927,16 +957,19 @@ __global__ __launch_bounds__(NTHREADS) void k_set_state(S *__restrict__ fout,
         for (int i = 0; i < 9; i++) {
             int rx, ry, ri;
             reader(i, x, y, g, rx, ry, ri);
+            // stored = f_ri(reader) - w rho_ref (eps(x) + eps(reader)) / 2
             double er = static_cast<double>(eps[(long long)ry * g.pitch + rx]);
+            double es = static_cast<double>(eps[(long long)y * g.pitch + x]);
             double w = wgt(ri);
             double dev;
             if (fplain) {
                 long long N = (long long)g.Lx * g.Ly;
-                dev = fplain[ri * N + (long long)ry * g.Lx + rx] - w * rho_ref * er;
+                dev = fplain[ri * N + (long long)ry * g.Lx + rx] - w * rho_ref * 0.5 * (es + er);
             } else {
                 double eu = CX[ri] * u0x + CY[ri] * u0y;
                 double uu = u0x * u0x + u0y * u0y;
-                dev = w * er * ((rho0 - rho_ref) + rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+                dev = w * (er * ((rho0 - rho_ref) + rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)) +
+                           0.5 * rho_ref * (er - es));
             }
             S *p = fout + i * g.plane + (long long)y * g.pitch + x;
             if constexpr (std::is_same_v<S, _Float16>)
@@ -953,17 +986,26 @@ __global__ __launch_bounds__(NTHREADS) void k_get_state(const S *__restrict__ fi
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, double *__restrict__ out)
 {
+    constexpr int W = TX + 2;
+    __shared__ R tile[TY + 2][W];
     const int t = blockIdx.x;
     const int bx = t % g.nbx, by = t / g.nbx;
-    const int x = bx * TX + threadIdx.x % TX;
+    const int x0 = bx * TX, y0 = by * TY;
+    load_eps_tile<R, W>(tile, eps, g, x0, y0);
+    __syncthreads();
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx;
     const long long N = (long long)g.Lx * g.Ly;
     for (int r = 0; r < ROWS; r++) {
-        const int y = by * TY + threadIdx.x / TX + NW * r;
+        const int ly = ty + NW * r;
+        const int y = y0 + ly;
         if (x >= g.Lx || y >= g.Ly) continue;
         Nbr n = neighbours(x, y, g);
         R d[9];
         gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
-        double e0 = static_cast<double>(eps[(long long)y * g.pitch + x]);
+        const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
+        unshift_incoming<R>(d, P, ph.rho0);
+        const double e0 = static_cast<double>(P.e0);
         for (int i = 0; i < 9; i++)
             out[i * N + (long long)y * g.Lx + x] =
                 static_cast<double>(d[i]) + wgt(i) * static_cast<double>(ph.rho0) * e0;

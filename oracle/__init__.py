@@ -18,6 +18,8 @@ FMA contraction).  This module is argument marshalling around it:
 * ``collide`` / ``stream`` / ``steps`` -- one or more time steps of the final
                         lattice Boltzmann equation (collide, then push)
 * ``moments``        -- eps rho, rho, u, m = sum e_i f_i and T per cell
+* ``outlet_flux`` / ``grad_outlet_flux`` -- J = sum of eps rho u_x over the last
+                        column, and dJ/deps by the reverse (adjoint) of the steps
 """
 from __future__ import annotations
 
@@ -37,6 +39,7 @@ _LIB_OVERRIDE = os.environ.get("LBM_VANS_ORACLE_LIB")
 
 PERIODIC = 0
 WALL = 1
+OPEN = 2
 DRAG_ERGUN = 0
 DRAG_CONST = 1
 
@@ -64,6 +67,8 @@ class _Params(ctypes.Structure):
         ("K", ctypes.c_double), ("F_eps", ctypes.c_double),
         ("Gx", ctypes.c_double), ("Gy", ctypes.c_double),
         ("rho0", ctypes.c_double), ("u0x", ctypes.c_double), ("u0y", ctypes.c_double),
+        ("rho_in", ctypes.c_double), ("u_in", ctypes.c_double),
+        ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double),
     ]
 
 
@@ -84,11 +89,15 @@ class Params:
     rho0: float = 1.0
     u0x: float = 0.0
     u0y: float = 0.0
+    rho_in: float = 1.0
+    u_in: float = 0.0
+    rho_out: float = 1.0
+    u_out: float = 0.0
 
     def c(self) -> _Params:
         return _Params(self.Lx, self.Ly, self.bc_x, self.bc_y, self.drag, 0, self.tau,
                        self.d_p, self.K, self.F_eps, self.Gx, self.Gy, self.rho0,
-                       self.u0x, self.u0y)
+                       self.u0x, self.u0y, self.rho_in, self.u_in, self.rho_out, self.u_out)
 
 
 _lib = None
@@ -114,9 +123,20 @@ def lib():
         L.orc_grad_eps.argtypes = [P, _D, _D, _D]
         L.orc_init.argtypes = [P, _D, _D]
         L.orc_collide.argtypes = [P, _D, _D, _D, _D, _D, ctypes.c_int]
-        L.orc_stream.argtypes = [P, _D, _D, ctypes.c_int]
+        L.orc_stream.argtypes = [P, _D, _D, _D, ctypes.c_int]
         L.orc_steps.argtypes = [P, _D, _D, _D, _D, _D, ctypes.c_int64, ctypes.c_int]
         L.orc_moments.argtypes = [P, _D, _D, _D, _D] + [_D] * 8
+        L.orc_drag_derivs.argtypes = [P, ctypes.c_double, _D, _D]
+        L.orc_node_collide.argtypes = [P, _D] + [ctypes.c_double] * 3 + [_D]
+        L.orc_node_collide.restype = None
+        L.orc_node_vjp.argtypes = ([P, _D] + [ctypes.c_double] * 3 + [_D] +
+                                   [ctypes.c_double] * 3 + [_D, _D, _D, _D])
+        L.orc_outlet_flux.argtypes = [P, _D, _D, _D, _D]
+        L.orc_outlet_flux.restype = ctypes.c_double
+        L.orc_grad_outlet_flux.argtypes = [P, _D, ctypes.c_int64, _D, _D, ctypes.c_int]
+        L.orc_grad_outlet_flux.restype = ctypes.c_int
+        for name in ("orc_drag_derivs", "orc_node_vjp"):
+            getattr(L, name).restype = None
         for name in ("orc_lattice", "orc_feq", "orc_guo_source", "orc_drag_coeffs",
                      "orc_velocity", "orc_grad_eps", "orc_init", "orc_collide",
                      "orc_stream", "orc_steps", "orc_moments"):
@@ -209,10 +229,12 @@ def collide(p: Params, eps: np.ndarray, f: np.ndarray, threads: int | None = Non
     return out
 
 
-def stream(p: Params, fpost: np.ndarray, threads: int | None = None):
+def stream(p: Params, eps: np.ndarray, fpost: np.ndarray, threads: int | None = None):
+    eps = _f64(eps)
     fpost = _f64(fpost)
     out = np.empty_like(fpost)
-    lib().orc_stream(ctypes.byref(p.c()), _ptr(fpost), _ptr(out), threads or default_threads())
+    lib().orc_stream(ctypes.byref(p.c()), _ptr(eps), _ptr(fpost), _ptr(out),
+                     threads or default_threads())
     return out
 
 
@@ -245,3 +267,51 @@ def moments(p: Params, eps: np.ndarray, f: np.ndarray) -> dict:
                       *(_ptr(out[k]) for k in ("eps_rho", "rho", "ux", "uy", "mx", "my",
                                                "Tx", "Ty")))
     return out
+
+
+def drag_derivs(p: Params, eps: float):
+    da = ctypes.c_double()
+    db = ctypes.c_double()
+    lib().orc_drag_derivs(ctypes.byref(p.c()), eps, ctypes.byref(da), ctypes.byref(db))
+    return da.value, db.value
+
+
+def node_collide(p: Params, f, eps: float, gex: float, gey: float) -> np.ndarray:
+    """Post-collision populations of one node."""
+    f = _f64(f)
+    out = np.zeros(9)
+    lib().orc_node_collide(ctypes.byref(p.c()), _ptr(f), eps, gex, gey, _ptr(out))
+    return out
+
+
+def node_vjp(p: Params, f, eps: float, gex: float, gey: float, fpost_bar, S_bar=0.0,
+             ux_bar=0.0, uy_bar=0.0):
+    """Adjoints (f_bar[9], eps_bar, gex_bar, gey_bar) of one node's inputs."""
+    f = _f64(f)
+    pb = _f64(fpost_bar)
+    fb = np.zeros(9)
+    eb, gxb, gyb = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    lib().orc_node_vjp(ctypes.byref(p.c()), _ptr(f), eps, gex, gey, _ptr(pb), S_bar, ux_bar,
+                       uy_bar, _ptr(fb), ctypes.byref(eb), ctypes.byref(gxb), ctypes.byref(gyb))
+    return fb, eb.value, gxb.value, gyb.value
+
+
+def outlet_flux(p: Params, eps: np.ndarray, f: np.ndarray) -> float:
+    """J = sum over the column x = Lx-1 of eps rho u_x of the state f."""
+    eps = _f64(eps)
+    f = _f64(f)
+    gx, gy = grad_eps(p, eps)
+    return lib().orc_outlet_flux(ctypes.byref(p.c()), _ptr(eps), _ptr(gx), _ptr(gy), _ptr(f))
+
+
+def grad_outlet_flux(p: Params, eps: np.ndarray, nsteps: int, threads: int | None = None):
+    """(J, dJ/deps) for J = outlet_flux after nsteps steps from the initial state."""
+    eps = _f64(eps)
+    assert eps.shape == (p.Ly, p.Lx)
+    g = np.zeros_like(eps)
+    J = ctypes.c_double()
+    rc = lib().orc_grad_outlet_flux(ctypes.byref(p.c()), _ptr(eps), int(nsteps), _ptr(g),
+                                    ctypes.byref(J), threads or default_threads())
+    if rc != 0:
+        raise MemoryError("oracle adjoint: out of memory")
+    return J.value, g

@@ -40,7 +40,13 @@
  *     exactly (the root is unique, see orc_velocity);
  *   - walls are half-way bounce-back: a population that would stream into a
  *     wall node returns to its own cell with the opposite velocity;
- *   - the initial state is f_i = f_i^eq(eps(x) rho0, u0).
+ *   - the initial state is f_i = f_i^eq(eps(x) rho0, u0);
+ *   - open x-boundaries (inflow / outflow): the paper prescribes none for a
+ *     through-flow channel; a population entering the domain across x = 0
+ *     (x = Lx-1) is the equilibrium of eq. (d2q9eq) of a reservoir with the
+ *     boundary node's porosity and the given density and x-velocity, and a
+ *     population leaving across it is absorbed.  Where the source also lies
+ *     behind a y-wall, bounce-back wins.
  */
 #include <math.h>
 #include <stddef.h>
@@ -59,13 +65,15 @@ static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 /* Squared lattice sound speed of D2Q9. */
 static const double CS2 = 1.0 / 3.0;
 
-enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
+enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_OPEN = 2 };
 enum { ORC_DRAG_ERGUN = 0, ORC_DRAG_CONST = 1 };
 
 /* Problem description (Section "Examples and discussions"). */
 typedef struct {
     int32_t Lx, Ly;     /* lattice nodes along x and y                         */
-    int32_t bc_x, bc_y; /* ORC_PERIODIC or ORC_WALL (both ends of the axis)     */
+    int32_t bc_x, bc_y; /* ORC_PERIODIC or ORC_WALL (both ends of the axis);    */
+                        /* bc_x may be ORC_OPEN: inflow reservoir beyond x = 0, */
+                        /* outflow reservoir beyond x = Lx-1                    */
     int32_t drag;       /* ORC_DRAG_ERGUN: K, F_eps from d_p (Ergun closure)    */
                         /* ORC_DRAG_CONST: K and F_eps given, uniform            */
     int32_t pad_;
@@ -74,6 +82,8 @@ typedef struct {
     double K, F_eps;    /* permeability and geometric function (DRAG_CONST)     */
     double Gx, Gy;      /* external body-force density                         */
     double rho0, u0x, u0y; /* initial state                                    */
+    double rho_in, u_in;   /* ORC_OPEN: density and x-velocity of the inflow reservoir  */
+    double rho_out, u_out; /* ORC_OPEN: density and x-velocity of the outflow reservoir */
 } orc_params;
 
 void orc_lattice(int32_t ex[9], int32_t ey[9], double w[9], int32_t opp[9], double *cs2)
@@ -257,6 +267,18 @@ static void cell_state(const orc_params *p, const double *f, size_t N, size_t c,
     if (Ty_out) *Ty_out = Ty;
 }
 
+/* Collision of one node with incoming f[9], porosity eps and its gradient
+ * (gex, gey): fpost_i = f_i - (f_i - f_i^eq)/tau + P_i + F_i. */
+void orc_node_collide(const orc_params *p, const double f[9], double eps, double gex,
+                      double gey, double fpost[9])
+{
+    double S, rho, ux, uy, Tx, Ty, feq[9], src[9];
+    cell_state(p, f, 1, 0, eps, gex, gey, &S, NULL, NULL, &rho, &ux, &uy, &Tx, &Ty);
+    orc_feq(S, ux, uy, feq);
+    orc_guo_source(p->tau, ux, uy, Tx, Ty, src);
+    for (int i = 0; i < 9; i++) fpost[i] = f[i] - (f[i] - feq[i]) / p->tau + src[i];
+}
+
 /* Collision of every cell (the right-hand side of the final lattice
  * Boltzmann equation):  f*_i = f_i - (f_i - f_i^eq)/tau + P_i + F_i.
  * gx, gy hold grad(eps) from orc_grad_eps.  fpost may not alias f. */
@@ -284,11 +306,31 @@ void orc_collide(const orc_params *p, const double *eps, const double *gx,
     }
 }
 
+/* Populations entering across an open x-boundary: the equilibrium of
+ * eq. (d2q9eq) of the reservoir (porosity of the boundary node, density rho_b,
+ * velocity (u_b, 0)). */
+static double reservoir(int i, double eps, double rho_b, double u_b)
+{
+    double feq[9];
+    orc_feq(eps * rho_b, u_b, 0.0, feq);
+    return feq[i];
+}
+
+/* Whether the source x - e_i of node (x, y) lies behind a y-wall. */
+static int source_behind_ywall(const orc_params *p, int y, int i)
+{
+    int ys = y - EY[i];
+    return p->bc_y == ORC_WALL && (ys < 0 || ys >= p->Ly);
+}
+
 /* Streaming (push):  f_i(x + e_i) = f*_i(x).  Along a periodic axis the
  * target wraps around; a target beyond a wall sends the population back to
- * its own cell as the opposite direction (half-way bounce-back).  Every
- * target slot is written exactly once, so f is fully overwritten. */
-void orc_stream(const orc_params *p, const double *fpost, double *f, int nthreads)
+ * its own cell as the opposite direction (half-way bounce-back); a target
+ * beyond an open x-boundary leaves the domain.  Beyond a y-wall bounce-back
+ * takes precedence.  Then the populations that enter across an open
+ * x-boundary are set from the reservoirs.  Every slot of f is written once. */
+void orc_stream(const orc_params *p, const double *eps, const double *fpost, double *f,
+                int nthreads)
 {
     long Ly = p->Ly;
     int Lx = p->Lx;
@@ -300,20 +342,31 @@ void orc_stream(const orc_params *p, const double *fpost, double *f, int nthread
             size_t c = (size_t)y * Lx + x;
             for (int i = 0; i < 9; i++) {
                 int xt = x + EX[i], yt = (int)y + EY[i];
-                int wall = 0;
-                if (xt < 0 || xt >= Lx) {
-                    if (p->bc_x == ORC_PERIODIC) xt = (xt + Lx) % Lx;
-                    else wall = 1;
-                }
+                int wall = 0, gone = 0;
                 if (yt < 0 || yt >= Ly) {
                     if (p->bc_y == ORC_PERIODIC) yt = (int)((yt + Ly) % Ly);
                     else wall = 1;
                 }
+                if (!wall && (xt < 0 || xt >= Lx)) {
+                    if (p->bc_x == ORC_PERIODIC) xt = (xt + Lx) % Lx;
+                    else if (p->bc_x == ORC_WALL) wall = 1;
+                    else gone = 1;
+                }
+                if (gone) continue;
                 if (wall)
                     f[OPP[i] * N + c] = fpost[i * N + c];
                 else
                     f[i * N + (size_t)yt * Lx + xt] = fpost[i * N + c];
             }
+        }
+    }
+    if (p->bc_x != ORC_OPEN) return;
+    for (long y = 0; y < Ly; y++) {
+        size_t c0 = (size_t)y * Lx, c1 = (size_t)y * Lx + (Lx - 1);
+        for (int i = 0; i < 9; i++) {
+            if (source_behind_ywall(p, (int)y, i)) continue;
+            if (EX[i] > 0) f[i * N + c0] = reservoir(i, eps[c0], p->rho_in, p->u_in);
+            if (EX[i] < 0) f[i * N + c1] = reservoir(i, eps[c1], p->rho_out, p->u_out);
         }
     }
 }
@@ -325,7 +378,7 @@ void orc_steps(const orc_params *p, const double *eps, const double *gx, const d
 {
     for (int64_t n = 0; n < nsteps; n++) {
         orc_collide(p, eps, gx, gy, f, scratch, nthreads);
-        orc_stream(p, scratch, f, nthreads);
+        orc_stream(p, eps, scratch, f, nthreads);
     }
 }
 
@@ -350,4 +403,284 @@ void orc_moments(const orc_params *p, const double *eps, const double *gx,
         if (Tx) Tx[c] = tx;
         if (Ty) Ty[c] = ty;
     }
+}
+
+/* ------------------------------------------------------------------------
+ * Outlet mass flux and its gradient with respect to the porosity.
+ *
+ * Objective: J = sum over the last column x = Lx-1 of eps rho u_x of the state
+ * f(., N) (eqs. (0moment), (1moment)), the superficial mass flux through the
+ * outflow section per unit depth.
+ *
+ * dJ/deps(x) is the exact derivative of the discrete map N steps of
+ * (collide, stream) from the initial state, taken in reverse mode: the
+ * adjoint of each step is the transpose of the stream (a pull) followed by the
+ * transposed Jacobian of each node's collision; porosity enters through
+ * eps(x) itself (density, drag coefficients), through grad(eps) (the lattice
+ * stencil, transposed once at the end), through the reservoir populations of
+ * open boundaries and through the initial state.  All states are kept.
+ * ------------------------------------------------------------------------ */
+
+/* Derivatives of the drag coefficients a(eps), b(eps) of orc_drag_coeffs.
+ * Ergun: a = eps^2 nu / K with dK/deps = K (3/eps + 2/(1-eps)), so
+ * da/deps = -a (1/eps + 2/(1-eps)); b = eps^3 F_eps / sqrt(K) with
+ * dF_eps/deps = -3 F_eps / (2 eps), so db/deps = -b / (1 - eps), whose limit at
+ * eps = 1 is -1.75/d_p.  Constant K, F_eps: da/deps = 2a/eps, db/deps = 3b/eps. */
+void orc_drag_derivs(const orc_params *p, double eps, double *da, double *db)
+{
+    double a, b;
+    orc_drag_coeffs(p, eps, &a, &b);
+    if (p->drag == ORC_DRAG_CONST) {
+        *da = 2.0 * a / eps;
+        *db = 3.0 * b / eps;
+        return;
+    }
+    if (isinf(p->d_p)) {
+        *da = 0.0;
+        *db = 0.0;
+        return;
+    }
+    if (eps >= 1.0) {
+        *da = 0.0;
+        *db = -1.75 / p->d_p;
+        return;
+    }
+    *da = -a * (1.0 / eps + 2.0 / (1.0 - eps));
+    *db = -b / (1.0 - eps);
+}
+
+/* Reverse-mode derivative of one node.  Forward: from the incoming f[9],
+ * eps and grad(eps) = (gex, gey) the node forms S = eps rho, m, rho, u
+ * (eq. (1moment)), F, T and the post-collision fpost_i = f_i - (f_i - feq_i)/tau
+ * + src_i.  Given the adjoints fpost_bar[9] of the outputs and extra adjoints
+ * S_bar0, ux_bar0, uy_bar0 of S and u, it adds the adjoints of the inputs to
+ * f_bar[9], eps_bar, gex_bar, gey_bar. */
+void orc_node_vjp(const orc_params *p, const double f[9], double eps, double gex, double gey,
+                  const double fpost_bar[9], double S_bar0, double ux_bar0, double uy_bar0,
+                  double f_bar[9], double *eps_bar, double *gex_bar, double *gey_bar)
+{
+    /* forward, as cell_state / orc_feq / orc_guo_source compute it */
+    double S = 0.0, mx = 0.0, my = 0.0;
+    for (int i = 0; i < 9; i++) {
+        S += f[i];
+        mx += EX[i] * f[i];
+        my += EY[i] * f[i];
+    }
+    double a, b, da, db;
+    orc_drag_coeffs(p, eps, &a, &b);
+    orc_drag_derivs(p, eps, &da, &db);
+    double rho = S / eps;
+    double Qx = CS2 * rho * gex, Qy = CS2 * rho * gey;
+    double Vx = mx + 0.5 * (Qx + p->Gx);
+    double Vy = my + 0.5 * (Qy + p->Gy);
+    double Vn = sqrt(Vx * Vx + Vy * Vy);
+    double A = S + 0.5 * a;
+    double B = 0.5 * b;
+    double R = sqrt(A * A + 4.0 * B * Vn);
+    double den = A + R;
+    double ux = 2.0 * Vx / den, uy = 2.0 * Vy / den;
+    double un = sqrt(ux * ux + uy * uy);
+    double Fx = p->Gx - a * ux - b * un * ux;
+    double Fy = p->Gy - a * uy - b * un * uy;
+    double Tx = Qx + Fx, Ty = Qy + Fy;
+    double uu = ux * ux + uy * uy;
+    double pre = 1.0 - 1.0 / (2.0 * p->tau);
+
+    /* reverse */
+    double S_bar = S_bar0, ux_bar = ux_bar0, uy_bar = uy_bar0;
+    double Tx_bar = 0.0, Ty_bar = 0.0, uu_bar = 0.0;
+    for (int i = 0; i < 9; i++) {
+        /* fpost_i = f_i - (f_i - feq_i)/tau + src_i */
+        f_bar[i] += fpost_bar[i] * (1.0 - 1.0 / p->tau);
+        double feq_bar = fpost_bar[i] / p->tau;
+        double src_bar = fpost_bar[i];
+        double eu = EX[i] * ux + EY[i] * uy;
+        /* feq_i = w_i S (1 + eu/c2 + eu^2/(2 c2^2) - uu/(2 c2)) */
+        double poly = 1.0 + eu / CS2 + (eu * eu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2);
+        S_bar += feq_bar * W[i] * poly;
+        double eu_bar = feq_bar * W[i] * S * (1.0 / CS2 + eu / (CS2 * CS2));
+        uu_bar += -feq_bar * W[i] * S / (2.0 * CS2);
+        /* src_i = pre w_i (cx Tx + cy Ty), cx = (ex - ux)/c2 + eu ex/c2^2 */
+        double cx = (EX[i] - ux) / CS2 + eu * EX[i] / (CS2 * CS2);
+        double cy = (EY[i] - uy) / CS2 + eu * EY[i] / (CS2 * CS2);
+        Tx_bar += src_bar * pre * W[i] * cx;
+        Ty_bar += src_bar * pre * W[i] * cy;
+        double cx_bar = src_bar * pre * W[i] * Tx;
+        double cy_bar = src_bar * pre * W[i] * Ty;
+        ux_bar += -cx_bar / CS2;
+        uy_bar += -cy_bar / CS2;
+        eu_bar += (cx_bar * EX[i] + cy_bar * EY[i]) / (CS2 * CS2);
+        /* eu = ex ux + ey uy */
+        ux_bar += eu_bar * EX[i];
+        uy_bar += eu_bar * EY[i];
+    }
+    ux_bar += 2.0 * ux * uu_bar;
+    uy_bar += 2.0 * uy * uu_bar;
+    /* T = Q + F,  F = G - a u - b |u| u */
+    double Qx_bar = Tx_bar, Qy_bar = Ty_bar;
+    double a_bar = -(Tx_bar * ux + Ty_bar * uy);
+    double b_bar = -(Tx_bar * ux + Ty_bar * uy) * un;
+    double un_bar = -b * (Tx_bar * ux + Ty_bar * uy);
+    ux_bar += -(a + b * un) * Tx_bar;
+    uy_bar += -(a + b * un) * Ty_bar;
+    if (un > 0.0) {
+        ux_bar += un_bar * ux / un;
+        uy_bar += un_bar * uy / un;
+    }
+    /* u = 2 V / den,  den = A + R,  R = sqrt(A^2 + 4 B Vn) */
+    double Vx_bar = ux_bar * 2.0 / den;
+    double Vy_bar = uy_bar * 2.0 / den;
+    double den_bar = -(ux_bar * ux + uy_bar * uy) / den;
+    double A_bar = den_bar * (1.0 + A / R);
+    double B_bar = den_bar * 2.0 * Vn / R;
+    double Vn_bar = den_bar * 2.0 * B / R;
+    if (Vn > 0.0) {
+        Vx_bar += Vn_bar * Vx / Vn;
+        Vy_bar += Vn_bar * Vy / Vn;
+    }
+    /* A = S + a/2, B = b/2 */
+    S_bar += A_bar;
+    a_bar += 0.5 * A_bar;
+    b_bar += 0.5 * B_bar;
+    /* V = m + (Q + G)/2 */
+    double mx_bar = Vx_bar, my_bar = Vy_bar;
+    Qx_bar += 0.5 * Vx_bar;
+    Qy_bar += 0.5 * Vy_bar;
+    /* Q = c2 rho grad(eps) */
+    double rho_bar = CS2 * (Qx_bar * gex + Qy_bar * gey);
+    *gex_bar += CS2 * rho * Qx_bar;
+    *gey_bar += CS2 * rho * Qy_bar;
+    /* rho = S / eps; a(eps), b(eps) */
+    S_bar += rho_bar / eps;
+    *eps_bar += -rho_bar * S / (eps * eps) + a_bar * da + b_bar * db;
+    /* S = sum f, m = sum e f */
+    for (int i = 0; i < 9; i++) f_bar[i] += S_bar + EX[i] * mx_bar + EY[i] * my_bar;
+}
+
+/* J = sum over x = Lx-1 of eps rho u_x of the state f. */
+double orc_outlet_flux(const orc_params *p, const double *eps, const double *gx,
+                       const double *gy, const double *f)
+{
+    size_t N = (size_t)p->Lx * p->Ly;
+    double J = 0.0;
+    for (int y = 0; y < p->Ly; y++) {
+        size_t c = (size_t)y * p->Lx + (p->Lx - 1);
+        double S, ux;
+        cell_state(p, f, N, c, eps[c], gx[c], gy[c], &S, NULL, NULL, NULL, &ux, NULL, NULL,
+                   NULL);
+        J += S * ux;
+    }
+    return J;
+}
+
+/* J after nsteps steps from the initial state, and dJ/deps (Lx*Ly values).
+ * Returns 0, or -1 if memory runs out. */
+int orc_grad_outlet_flux(const orc_params *p, const double *eps, int64_t nsteps,
+                         double *dJdeps, double *J_out, int nthreads)
+{
+    int Lx = p->Lx, Ly = p->Ly;
+    size_t N = (size_t)Lx * Ly, S9 = 9 * N;
+    double *fs = malloc(sizeof(double) * S9 * (size_t)(nsteps + 1));
+    double *post = malloc(sizeof(double) * S9);
+    double *fbar = malloc(sizeof(double) * S9);
+    double *pbar = malloc(sizeof(double) * S9);
+    double *gx = malloc(sizeof(double) * N), *gy = malloc(sizeof(double) * N);
+    double *gxb = calloc(N, sizeof(double)), *gyb = calloc(N, sizeof(double));
+    if (!fs || !post || !fbar || !pbar || !gx || !gy || !gxb || !gyb) {
+        free(fs); free(post); free(fbar); free(pbar); free(gx); free(gy); free(gxb); free(gyb);
+        return -1;
+    }
+    orc_grad_eps(p, eps, gx, gy);
+    /* forward, keeping f(., n) for n = 0..nsteps */
+    orc_init(p, eps, fs);
+    for (int64_t n = 0; n < nsteps; n++) {
+        orc_collide(p, eps, gx, gy, fs + S9 * n, post, nthreads);
+        orc_stream(p, eps, post, fs + S9 * (n + 1), nthreads);
+    }
+    const double *fN = fs + S9 * nsteps;
+    *J_out = orc_outlet_flux(p, eps, gx, gy, fN);
+
+    for (size_t k = 0; k < N; k++) dJdeps[k] = 0.0;
+    for (size_t k = 0; k < S9; k++) fbar[k] = 0.0;
+    /* seed: J = sum S ux over the outlet column */
+    const double zero9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int y = 0; y < Ly; y++) {
+        size_t c = (size_t)y * Lx + (Lx - 1);
+        double fc[9], fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, S, ux;
+        for (int i = 0; i < 9; i++) fc[i] = fN[i * N + c];
+        cell_state(p, fN, N, c, eps[c], gx[c], gy[c], &S, NULL, NULL, NULL, &ux, NULL, NULL,
+                   NULL);
+        orc_node_vjp(p, fc, eps[c], gx[c], gy[c], zero9, ux, S, 0.0, fb, &dJdeps[c], &gxb[c],
+                     &gyb[c]);
+        for (int i = 0; i < 9; i++) fbar[i * N + c] += fb[i];
+    }
+    for (int64_t n = nsteps - 1; n >= 0; n--) {
+        /* reservoir populations of f(., n+1) depend on the boundary porosity */
+        if (p->bc_x == ORC_OPEN) {
+            for (int y = 0; y < Ly; y++) {
+                size_t c0 = (size_t)y * Lx, c1 = (size_t)y * Lx + (Lx - 1);
+                for (int i = 0; i < 9; i++) {
+                    if (source_behind_ywall(p, y, i)) continue;
+                    if (EX[i] > 0)
+                        dJdeps[c0] += fbar[i * N + c0] * reservoir(i, 1.0, p->rho_in, p->u_in);
+                    if (EX[i] < 0)
+                        dJdeps[c1] += fbar[i * N + c1] * reservoir(i, 1.0, p->rho_out, p->u_out);
+                }
+            }
+        }
+        /* transpose of the stream: post_bar_i(x) = f_bar at the slot x's f*_i went to */
+        for (int y = 0; y < Ly; y++) {
+            for (int x = 0; x < Lx; x++) {
+                size_t c = (size_t)y * Lx + x;
+                for (int i = 0; i < 9; i++) {
+                    int xt = x + EX[i], yt = y + EY[i];
+                    int wall = 0, gone = 0;
+                    if (yt < 0 || yt >= Ly) {
+                        if (p->bc_y == ORC_PERIODIC) yt = (yt + Ly) % Ly;
+                        else wall = 1;
+                    }
+                    if (!wall && (xt < 0 || xt >= Lx)) {
+                        if (p->bc_x == ORC_PERIODIC) xt = (xt + Lx) % Lx;
+                        else if (p->bc_x == ORC_WALL) wall = 1;
+                        else gone = 1;
+                    }
+                    if (gone) pbar[i * N + c] = 0.0;
+                    else if (wall) pbar[i * N + c] = fbar[OPP[i] * N + c];
+                    else pbar[i * N + c] = fbar[i * N + (size_t)yt * Lx + xt];
+                }
+            }
+        }
+        /* transposed collision Jacobian at every node, on the state f(., n) */
+        const double *fn = fs + S9 * n;
+        for (size_t c = 0; c < N; c++) {
+            double fc[9], pb[9], fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int i = 0; i < 9; i++) {
+                fc[i] = fn[i * N + c];
+                pb[i] = pbar[i * N + c];
+            }
+            orc_node_vjp(p, fc, eps[c], gx[c], gy[c], pb, 0.0, 0.0, 0.0, fb, &dJdeps[c],
+                         &gxb[c], &gyb[c]);
+            for (int i = 0; i < 9; i++) fbar[i * N + c] = fb[i];
+        }
+    }
+    /* initial state f_i = w_i eps rho0 (1 + ...) */
+    {
+        double feq1[9];
+        orc_feq(p->rho0, p->u0x, p->u0y, feq1);
+        for (size_t c = 0; c < N; c++)
+            for (int i = 0; i < 9; i++) dJdeps[c] += fbar[i * N + c] * feq1[i];
+    }
+    /* grad(eps)(x) = (1/c2) sum_i W_i e_i eps(nb(x + e_i)): transpose the stencil */
+    for (int y = 0; y < Ly; y++)
+        for (int x = 0; x < Lx; x++) {
+            size_t c = (size_t)y * Lx + x;
+            for (int i = 0; i < 9; i++) {
+                int xn = nb_index(x + EX[i], Lx, p->bc_x);
+                int yn = nb_index(y + EY[i], Ly, p->bc_y);
+                size_t cn = (size_t)yn * Lx + xn;
+                dJdeps[cn] += (gxb[c] * W[i] * EX[i] + gyb[c] * W[i] * EY[i]) / CS2;
+            }
+        }
+    free(fs); free(post); free(fbar); free(pbar); free(gx); free(gy); free(gxb); free(gyb);
+    return 0;
 }

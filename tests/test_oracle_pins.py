@@ -233,7 +233,7 @@ def test_momentum_budget_per_cell_and_global(orc):
     tol = 4e-15 * np.abs(post).max()  # a few roundings of the O(0.1) populations
     assert np.abs(dmx - mom["Tx"]).max() < tol
     assert np.abs(dmy - mom["Ty"]).max() < tol
-    f1 = orc.stream(p, post)
+    f1 = orc.stream(p, eps, post)
     m1 = orc.moments(p, eps, f1)
     tol = 1e-14 * np.abs(mom["mx"]).sum()
     assert abs(m1["mx"].sum() - mom["mx"].sum() - mom["Tx"].sum()) < tol

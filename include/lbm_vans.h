@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 1
+#define LBM_VANS_ABI_VERSION 2
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -59,6 +59,12 @@ extern "C" {
 /* Boundary kind of one axis (applies to both ends of that axis). */
 #define LBM_BC_PERIODIC 0   /* wrap-around streaming (Section "Examples and discussions") */
 #define LBM_BC_BOUNCEBACK 1 /* half-way bounce-back wall beyond node -1/2 and L-1/2       */
+#define LBM_BC_OPEN 2       /* x only: inflow reservoir beyond x = 0, outflow reservoir
+                               beyond x = Lx-1.  From state n = 1 on, a population that
+                               enters across an open end is the equilibrium (eq. (d2q9eq))
+                               of a reservoir with the boundary node's porosity, density
+                               rho_in / rho_out and velocity (u_in, 0) / (u_out, 0); one
+                               that leaves is absorbed.  Behind a y-wall bounce-back wins. */
 
 /* Population storage.  The collision arithmetic is FP64 for LBM_F64 and FP32
  * otherwise.  The shifted forms store the deviation of each population from
@@ -82,8 +88,9 @@ extern "C" {
 #define LBM_VANS_DIAG_RING 4096
 
 typedef struct lbm_vans_params {
-    int32_t Lx, Ly;        /* lattice nodes, 1 <= Lx, Ly; Lx*Ly < 2^31               */
-    int32_t bc_x, bc_y;    /* LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK                    */
+    int32_t Lx, Ly;        /* lattice nodes, 1 <= Lx, Ly (Lx >= 2 with open x ends);
+                              padded nodes (Lx rounded up to 256) x Ly < 2^31          */
+    int32_t bc_x, bc_y;    /* LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK; bc_x may be LBM_BC_OPEN */
     int32_t storage;       /* LBM_F64, LBM_F32_SHIFTED or LBM_F16_SHIFTED             */
     int32_t drag;          /* LBM_DRAG_ERGUN or LBM_DRAG_CONST                        */
     double tau;            /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3         */
@@ -95,6 +102,8 @@ typedef struct lbm_vans_params {
     int32_t fp16_scale_log2; /* LBM_F16_SHIFTED: stored value = deviation * 2^s, 0..24 */
     int32_t diag_every;    /* > 0: record diagnostics of every state n with n % diag_every == 0
                               during lbm_vans_step; 0: none                           */
+    double rho_in, u_in;   /* LBM_BC_OPEN: inflow reservoir density (> 0), x-velocity  */
+    double rho_out, u_out; /* LBM_BC_OPEN: outflow reservoir density (> 0), x-velocity */
 } lbm_vans_params;
 
 typedef struct lbm_vans_handle lbm_vans_handle;
@@ -159,10 +168,34 @@ int lbm_vans_set_state(lbm_vans_handle *h, const void *f);
 int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
                        int32_t *n_records);
 
-/* Gradient of an objective with respect to eps(x) through the reverse
- * (adjoint) sweep.  Not built: returns LBM_VANS_ENOTIMPL. */
+/* Objective of lbm_vans_grad: the outlet mass flux, J = sum over the last
+ * column x = Lx-1 of eps rho u_x of the state f(., nsteps) (eqs. (0moment),
+ * (1moment)): the superficial mass flux through that section per unit depth. */
+#define LBM_OBJ_OUTLET_FLUX 0
+
+/* Bytes of device memory lbm_vans_grad needs as grad_work for these
+ * arguments (0 if invalid): one population buffer per checkpoint
+ * (ceil(nsteps / ckpt_every)), ckpt_every buffers for a recomputed segment,
+ * two adjoint buffers and three FP64 accumulators of the porosity grid. */
+size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int64_t nsteps,
+                                int32_t ckpt_every);
+
+/* Value and porosity gradient of the objective after nsteps steps from the
+ * initial state (the state is reset to f(., 0), then advanced): J and
+ * dJdeps(x) = dJ/deps(x), the exact derivative of the discrete map (up to
+ * rounding), computed by the reverse (adjoint) sweep: a forward pass keeping
+ * a checkpoint every ckpt_every steps, then, segment by segment from the
+ * last, the states recomputed from the checkpoint and the adjoint stepped
+ * back through them.  Porosity enters through eps itself (density, drag),
+ * through grad(eps), through the open-boundary reservoirs and the initial
+ * state; the sensitivities are accumulated in FP64.
+ * grad_work: device buffer of lbm_vans_grad_work_bytes() bytes, 256-byte
+ * aligned, caller-owned.  dJdeps: device array [Ly][Lx] of doubles.
+ * J: host double or NULL.  Synchronises the stream.  Afterwards the state is
+ * f(., nsteps) and the step count is nsteps.  Returns LBM_VANS_ENONFINITE if
+ * J is not finite. */
 int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
-                  double *dJdeps, double *J);
+                  void *grad_work, size_t grad_work_bytes, double *dJdeps, double *J);
 
 /* Release the handle (host memory only; the work buffer stays the caller's).
  * Waits for the handle's queued work first.  NULL is ignored. */

@@ -34,6 +34,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -99,7 +100,8 @@ constexpr int PITCH_ALIGN = 256;  // row pitch in nodes: a multiple of 64 lanes 
 
 struct Geo {
     int Lx, Ly, pitch;
-    int wall_x, wall_y;
+    int wall_x, wall_y;     // the axis is not periodic (walls, or open for x)
+    int open_x;             // x ends are open (inflow at x = 0, outflow at x = Lx-1)
     int nbx, ntiles;
     long long plane;        // Ly * pitch
 };
@@ -174,6 +176,13 @@ struct Phys {
     R ca, cb;       // drag prefactors (see drag_coeffs)
     int drag;       // LBM_DRAG_ERGUN or LBM_DRAG_CONST
     R scale, inv_scale;  // FP16 storage scale 2^s and 2^-s (1 otherwise)
+    // Open x ends: a population entering across x = 0 (x = Lx-1) is the
+    // equilibrium of a reservoir with the node's porosity, density rho_in
+    // (rho_out) and velocity (u_in, 0) ((u_out, 0)); as a deviation from the
+    // node's rest state it is eps * rin[i] (eps * rout[i]).  Applied from the
+    // second state on (the initial state is the equilibrium everywhere).
+    int reservoir;
+    R rin[9], rout[9];
 };
 
 // Reciprocal and square root of the compute type: the hardware instructions
@@ -231,31 +240,46 @@ struct Node {
 // the non-negative root of B s^2 + A s = |V|: u = k V with
 // k = 2 / (A + sqrt(A^2 + 4 B |V|)), and |u| = k |V|.
 template <typename R>
-__device__ __forceinline__ Node<R> node_moments(const R d[9], R eps, R gex, R gey,
-                                                const Phys<R> &ph)
-{
+struct NodeFwd {  // the node's forward quantities (the reverse pass needs them all)
     Node<R> N;
+    R ie, a, b, Vx, Vy, Vn, A, Rr, k, un, drag;
+};
+
+template <typename R>
+__device__ __forceinline__ NodeFwd<R> node_forward(const R d[9], R eps, R gex, R gey,
+                                                   const Phys<R> &ph)
+{
+    NodeFwd<R> F;
+    Node<R> &N = F.N;
     N.dS = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     N.S = eps * ph.rho0 + N.dS;
     N.mx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     N.my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-    const R ie = rcp(eps);
-    N.rho = N.S * ie;
+    F.ie = rcp(eps);
+    N.rho = N.S * F.ie;
     const R third = R(1) / R(3);
     const R Qx = third * N.rho * gex, Qy = third * N.rho * gey;
-    R a, b;
-    drag_coeffs(ph, eps, ie, a, b);
-    const R Vx = N.mx + R(0.5) * (Qx + ph.Gx);
-    const R Vy = N.my + R(0.5) * (Qy + ph.Gy);
-    const R A = N.S + R(0.5) * a;
-    const R Vn = sqroot(Vx * Vx + Vy * Vy);
-    const R k = R(2) * rcp(A + sqroot(A * A + R(2) * b * Vn));
-    N.ux = k * Vx;
-    N.uy = k * Vy;
-    const R drag = a + b * (k * Vn);
-    N.Tx = Qx + ph.Gx - drag * N.ux;
-    N.Ty = Qy + ph.Gy - drag * N.uy;
-    return N;
+    drag_coeffs(ph, eps, F.ie, F.a, F.b);
+    F.Vx = N.mx + R(0.5) * (Qx + ph.Gx);
+    F.Vy = N.my + R(0.5) * (Qy + ph.Gy);
+    F.A = N.S + R(0.5) * F.a;
+    F.Vn = sqroot(F.Vx * F.Vx + F.Vy * F.Vy);
+    F.Rr = sqroot(F.A * F.A + R(2) * F.b * F.Vn);
+    F.k = R(2) * rcp(F.A + F.Rr);
+    N.ux = F.k * F.Vx;
+    N.uy = F.k * F.Vy;
+    F.un = F.k * F.Vn;
+    F.drag = F.a + F.b * F.un;
+    N.Tx = Qx + ph.Gx - F.drag * N.ux;
+    N.Ty = Qy + ph.Gy - F.drag * N.uy;
+    return F;
+}
+
+template <typename R>
+__device__ __forceinline__ Node<R> node_moments(const R d[9], R eps, R gex, R gey,
+                                                const Phys<R> &ph)
+{
+    return node_forward<R>(d, eps, gex, gey, ph).N;
 }
 
 // D2Q9 velocities in the library's ordering.
@@ -508,6 +532,25 @@ __device__ __forceinline__ void unshift_incoming(R d[9], const PorNb<R> &P, R rh
     d[8] += h2 * P.D[6];
 }
 
+// Incoming populations across an open x end are the reservoir's (not
+// behind a y-wall, where bounce-back wins).  open_l / open_r: the node is the
+// first / last of an open x axis and reservoirs are active.
+template <typename R>
+__device__ __forceinline__ void reservoir_inflow(R d[9], R e0, bool open_l, bool open_r,
+                                                 bool wym, bool wyp, const Phys<R> &ph)
+{
+    if (open_l) {
+        d[1] = e0 * ph.rin[1];
+        if (!wym) d[5] = e0 * ph.rin[5];
+        if (!wyp) d[8] = e0 * ph.rin[8];
+    }
+    if (open_r) {
+        d[3] = e0 * ph.rout[3];
+        if (!wym) d[6] = e0 * ph.rout[6];
+        if (!wyp) d[7] = e0 * ph.rout[7];
+    }
+}
+
 // Everything a node does after its gather: porosity neighbourhood from the
 // tile, deviations from the node's rest state, moments and velocity,
 // collision, and the shift of each outgoing value to its link midpoint (no
@@ -516,10 +559,12 @@ __device__ __forceinline__ void unshift_incoming(R d[9], const PorNb<R> &P, R rh
 // (lyy, lx) is the node's position in the tile.
 template <typename R, int W, bool DIAG>
 __device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, int lx, bool wxm,
-                                            bool wxp, bool wym, bool wyp, const Phys<R> &ph,
-                                            double *acc, bool count)
+                                            bool wxp, bool wym, bool wyp, bool open_l,
+                                            bool open_r, const Phys<R> &ph, double *acc,
+                                            bool count)
 {
     const PorNb<R> P = porosity_nb<R, W>(t, lyy, lx, wxm, wxp, wym, wyp);
+    reservoir_inflow<R>(d, P.e0, open_l, open_r, wym, wyp, ph);
     unshift_incoming<R>(d, P, ph.rho0);
     Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
     if constexpr (DIAG) {
@@ -562,8 +607,9 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
             Nbr n = neighbours(x, y, g);
             R d[9];
             gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
-            update_node<R, W, DIAG>(d, tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp, ph, acc,
-                                    true);
+            const bool ores = g.open_x && ph.reservoir;
+            update_node<R, W, DIAG>(d, tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp,
+                                    ores && x == 0, ores && x == g.Lx - 1, ph, acc, true);
             const int c = y * g.pitch + x;
 #pragma unroll
             for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i], ph.scale);
@@ -618,7 +664,7 @@ struct LaneX {
 };
 
 template <int V, bool WX>
-__device__ __forceinline__ LaneX lane_x(int x0, int lane, const Geo &g)
+__device__ __forceinline__ LaneX lane_x(int x0, int lane, const Geo &g)  // WX: x not periodic
 {
     LaneX L;
     L.x = x0 + lane * V;
@@ -748,14 +794,15 @@ __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], in
 }
 
 // The fused sweep with V consecutive nodes per lane (requires Lx % V == 0 and
-// a pitch that is a multiple of 64 V); WX / WY: walls across x / y.  Each
+// a pitch that is a multiple of 64 V); BX: x ends periodic (0), walls (1) or
+// open (2); WY: walls across y.  Each
 // population is one aligned vector load per lane; the x-shifted ones are
 // rebuilt with one cross-lane shuffle and a masked scalar load for the lane at
 // the wave's edge.  The first row's populations are requested before the
 // porosity tile is filled, so their latency overlaps the tile load and the
 // barrier.  The same node update as the scalar sweep then runs per node, and
 // the 9 results leave as aligned vector stores.
-template <typename S, typename R, int V, bool WX, bool WY, bool DIAG>
+template <typename S, typename R, int V, int BX, bool WY, bool DIAG>
 __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
@@ -767,6 +814,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
     const int bx = t % g.nbx, by = t / g.nbx;
     const int x0 = bx * TX * V, y0 = by * TY;
     const int lane = threadIdx.x % TX, ty = threadIdx.x / TX;
+    constexpr bool WX = BX != 0;
     const LaneX L = lane_x<V, WX>(x0, lane, g);
     const bool valid = L.x < g.Lx;
     const S *F[9];
@@ -798,8 +846,9 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
             for (int i = 0; i < 9; i++) dk[i] = d[i][k];
             const bool wxm = WX && L.x + k == 0;
             const bool wxp = WX && L.x + k == g.Lx - 1;
-            update_node<R, W, DIAG>(dk, tile, ly + 1, lane * V + k + 1, wxm, wxp, wym, wyp, ph,
-                                    acc, valid);
+            const bool ores = BX == 2 && ph.reservoir;
+            update_node<R, W, DIAG>(dk, tile, ly + 1, lane * V + k + 1, wxm, wxp, wym, wyp,
+                                    ores && wxm, ores && wxp, ph, acc, valid);
 #pragma unroll
             for (int i = 0; i < 9; i++) d[i][k] = dk[i];
         }
@@ -842,6 +891,8 @@ __global__ __launch_bounds__(NTHREADS) void k_moments(const S *__restrict__ fin,
             R d[9];
             gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
             const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
+            const bool ores = g.open_x && ph.reservoir;
+            reservoir_inflow<R>(d, P.e0, ores && x == 0, ores && x == g.Lx - 1, n.wym, n.wyp, ph);
             unshift_incoming<R>(d, P, ph.rho0);
             Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
             accumulate<R>(acc, N);
@@ -1004,12 +1055,313 @@ __global__ __launch_bounds__(NTHREADS) void k_get_state(const S *__restrict__ fi
         R d[9];
         gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
         const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
+        const bool ores = g.open_x && ph.reservoir;
+        reservoir_inflow<R>(d, P.e0, ores && x == 0, ores && x == g.Lx - 1, n.wym, n.wyp, ph);
         unshift_incoming<R>(d, P, ph.rho0);
         const double e0 = static_cast<double>(P.e0);
         for (int i = 0; i < 9; i++)
             out[i * N + (long long)y * g.Lx + x] =
                 static_cast<double>(d[i]) + wgt(i) * static_cast<double>(ph.rho0) * e0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (reverse) sweep: gradient of the outlet mass flux with respect to eps
+// ---------------------------------------------------------------------------
+// The forward map of one step takes the stored post-collision values F^n to
+// F^{n+1}: every node pulls its incoming populations (streaming, bounce-back,
+// reservoirs) and collides them.  Its adjoint takes lambda^{n+1} (the
+// adjoint of F^{n+1}, i.e. of each node's 9 outgoing values) to lambda^n:
+// every node applies the transposed Jacobian of its collision to its 9
+// outgoing adjoints and pushes each incoming adjoint back into the slot it
+// was pulled from (the same bijection as the gather, run backwards).  Porosity
+// enters a node through eps (density, drag coefficients), through grad(eps)
+// (accumulated per node, transposed through the lattice stencil at the end),
+// through the reservoir populations and through the initial state.  Adjoints
+// are of the plain populations; the storage shifts are decoded as in the
+// forward.
+
+// d(a)/d(eps), d(b)/d(eps) of drag_coeffs.
+template <typename R>
+__device__ __forceinline__ void drag_derivs(const Phys<R> &ph, R eps, R inv_eps, R &da, R &db)
+{
+    if (ph.drag == LBM_DRAG_ERGUN) {
+        da = -ph.ca * (R(1) - eps) * (R(1) + eps) * inv_eps * inv_eps;
+        db = -ph.cb;
+    } else {
+        da = R(2) * ph.ca * eps;
+        db = R(3) * ph.cb * eps * eps;
+    }
+}
+
+// Reverse of one node.  d: the node's incoming deviations (as update_node
+// sees them before the collision); mu: adjoints of its 9 post-collision
+// values; S_bar0, ux_bar0, uy_bar0: adjoints of eps rho and u (the objective).
+// Returns the adjoints of the 9 incoming plain populations in nu and adds the
+// direct porosity and porosity-gradient adjoints to eb, gxb, gyb.
+template <typename R>
+__device__ __forceinline__ void node_vjp(const R d[9], R e0, R gex, R gey, const Phys<R> &ph,
+                                         const R mu[9], R S_bar0, R ux_bar0, R uy_bar0,
+                                         R nu[9], R &eb, R &gxb, R &gyb)
+{
+    const NodeFwd<R> F = node_forward<R>(d, e0, gex, gey, ph);
+    const Node<R> &N = F.N;
+    const R om = ph.omega, P = ph.pre, S = N.S, ux = N.ux, uy = N.uy;
+    const R uu = ux * ux + uy * uy;
+    R S_bar = S_bar0, ux_bar = ux_bar0, uy_bar = uy_bar0;
+    R Tx_bar = R(0), Ty_bar = R(0), uu_bar = R(0), uT_bar = R(0);
+    // out_i = (1 - omega) f_i + omega feq_i + src_i,
+    // feq_i = w_i S (1 + A_i + A_i^2/2 - 3/2 u.u), src_i = P w_i (B_i (1 + A_i) - 3 u.T),
+    // A_i = 3 e_i.u, B_i = 3 e_i.T
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        const R cx = R(CX[i]), cy = R(CY[i]);
+        const R w = i == 0 ? R(4) / R(9) : (i < 5 ? R(1) / R(9) : R(1) / R(36));
+        const R Ai = R(3) * (cx * ux + cy * uy);
+        const R Bi = R(3) * (cx * N.Tx + cy * N.Ty);
+        const R m = mu[i];
+        nu[i] = (R(1) - om) * m;
+        S_bar += om * m * w * (R(1) + Ai + R(0.5) * Ai * Ai - R(1.5) * uu);
+        const R A_bar = om * m * w * S * (R(1) + Ai) + m * P * w * Bi;
+        const R B_bar = m * P * w * (R(1) + Ai);
+        uu_bar -= R(1.5) * om * S * m * w;
+        uT_bar -= R(3) * P * m * w;
+        ux_bar += R(3) * cx * A_bar;
+        uy_bar += R(3) * cy * A_bar;
+        Tx_bar += R(3) * cx * B_bar;
+        Ty_bar += R(3) * cy * B_bar;
+    }
+    ux_bar += R(2) * ux * uu_bar + N.Tx * uT_bar;
+    uy_bar += R(2) * uy * uu_bar + N.Ty * uT_bar;
+    Tx_bar += ux * uT_bar;
+    Ty_bar += uy * uT_bar;
+    // T = Q + G - drag u, drag = a + b |u|
+    R Qx_bar = Tx_bar, Qy_bar = Ty_bar;
+    const R drag_bar = -(Tx_bar * ux + Ty_bar * uy);
+    ux_bar -= F.drag * Tx_bar;
+    uy_bar -= F.drag * Ty_bar;
+    R a_bar = drag_bar, b_bar = drag_bar * F.un;
+    const R un_bar = drag_bar * F.b;
+    // u = k V, |u| = k |V|, k = 2 / (A + Rr), Rr = sqrt(A^2 + 2 b |V|)
+    const R k_bar = ux_bar * F.Vx + uy_bar * F.Vy + un_bar * F.Vn;
+    R Vx_bar = F.k * ux_bar, Vy_bar = F.k * uy_bar, Vn_bar = F.k * un_bar;
+    const R den_bar = -k_bar * F.k * F.k * R(0.5);
+    R A_bar = den_bar;
+    const R Rr_bar = den_bar * rcp(F.Rr);
+    A_bar += Rr_bar * F.A;
+    b_bar += Rr_bar * F.Vn;
+    Vn_bar += Rr_bar * F.b;
+    if (F.Vn > R(0)) {
+        const R iv = rcp(F.Vn);
+        Vx_bar += Vn_bar * F.Vx * iv;
+        Vy_bar += Vn_bar * F.Vy * iv;
+    }
+    // A = S + a/2;  V = m + (Q + G)/2;  Q = rho grad(eps)/3;  rho = S/eps
+    S_bar += A_bar;
+    a_bar += R(0.5) * A_bar;
+    Qx_bar += R(0.5) * Vx_bar;
+    Qy_bar += R(0.5) * Vy_bar;
+    const R third = R(1) / R(3);
+    const R rho_bar = third * (Qx_bar * gex + Qy_bar * gey);
+    gxb += third * N.rho * Qx_bar;
+    gyb += third * N.rho * Qy_bar;
+    S_bar += rho_bar * F.ie;
+    R da, db;
+    drag_derivs(ph, e0, F.ie, da, db);
+    eb += -rho_bar * S * F.ie * F.ie + a_bar * da + b_bar * db;
+    // S = sum f, m = sum e f
+#pragma unroll
+    for (int i = 0; i < 9; i++) nu[i] += S_bar + R(CX[i]) * Vx_bar + R(CY[i]) * Vy_bar;
+}
+
+// One reverse step (SEED = false) or the objective's seed (SEED = true).
+// fin: the stored state n (what the forward sweep of step n gathers from).
+// lam_next: adjoint of the state n + 1 (unused for the seed); lam: receives
+// the adjoint of the state n.  eb, gxb, gyb: FP64 accumulators [Ly][pitch].
+// The seed computes J = sum over x = Lx-1 of eps rho u_x of the state n (tile
+// partials in part) and the adjoint of the state from it.
+template <typename S, typename R, bool SEED>
+__global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
+                                                      const R *__restrict__ lam_next,
+                                                      R *__restrict__ lam,
+                                                      const R *__restrict__ eps, Geo g,
+                                                      Phys<R> ph, double *__restrict__ eb,
+                                                      double *__restrict__ gxb,
+                                                      double *__restrict__ gyb,
+                                                      double *__restrict__ part)
+{
+    constexpr int W = TX + 2;
+    __shared__ R tile[TY + 2][W];
+    const int t = blockIdx.x;
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x0 = bx * TX, y0 = by * TY;
+    load_eps_tile<R, W>(tile, eps, g, x0, y0);
+    __syncthreads();
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; k++) acc[k] = 0.0;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx;
+    for (int r = 0; r < ROWS; r++) {
+        const int ly = ty + NW * r;
+        const int y = y0 + ly;
+        if (x >= g.Lx || y >= g.Ly) continue;
+        const Nbr n = neighbours(x, y, g);
+        R d[9];
+        gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
+        const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
+        const bool ores = g.open_x && ph.reservoir;
+        const bool ol = ores && x == 0, orr = ores && x == g.Lx - 1;
+        reservoir_inflow<R>(d, P.e0, ol, orr, n.wym, n.wyp, ph);
+        unshift_incoming<R>(d, P, ph.rho0);
+        const int c = y * g.pitch + x;
+        R mu[9];
+        R S_bar0 = R(0), ux_bar0 = R(0);
+        if constexpr (SEED) {
+#pragma unroll
+            for (int i = 0; i < 9; i++) mu[i] = R(0);
+            if (x == g.Lx - 1) {
+                const Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
+                S_bar0 = N.ux;
+                ux_bar0 = N.S;
+                acc[0] += static_cast<double>(N.S) * static_cast<double>(N.ux);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; i++) mu[i] = lam_next[i * g.plane + c];
+        }
+        R nu[9], e_b = R(0), gx_b = R(0), gy_b = R(0);
+        node_vjp<R>(d, P.e0, P.gex, P.gey, ph, mu, S_bar0, ux_bar0, R(0), nu, e_b, gx_b, gy_b);
+        // reservoir links: the incoming value is eps0 * (rin_i + w_i rho0)
+        const R w1 = R(1) / R(9), w2 = R(1) / R(36);
+        bool res[9] = {false, false, false, false, false, false, false, false, false};
+        if (ol) {
+            res[1] = true; res[5] = !n.wym; res[8] = !n.wyp;
+            e_b += nu[1] * (ph.rin[1] + w1 * ph.rho0);
+            if (res[5]) e_b += nu[5] * (ph.rin[5] + w2 * ph.rho0);
+            if (res[8]) e_b += nu[8] * (ph.rin[8] + w2 * ph.rho0);
+        }
+        if (orr) {
+            res[3] = true; res[6] = !n.wym; res[7] = !n.wyp;
+            e_b += nu[3] * (ph.rout[3] + w1 * ph.rho0);
+            if (res[6]) e_b += nu[6] * (ph.rout[6] + w2 * ph.rho0);
+            if (res[7]) e_b += nu[7] * (ph.rout[7] + w2 * ph.rho0);
+        }
+        // push: the slot each incoming population came from (as in gather)
+        const int rm = n.ym * g.pitch, r0 = y * g.pitch, rp = n.yp * g.pitch;
+        const long long pl = g.plane;
+        R *L0 = lam, *L1 = lam + pl, *L2 = lam + 2 * pl, *L3 = lam + 3 * pl, *L4 = lam + 4 * pl,
+          *L5 = lam + 5 * pl, *L6 = lam + 6 * pl, *L7 = lam + 7 * pl, *L8 = lam + 8 * pl;
+        L0[c] = nu[0];
+        *(n.wxm ? L3 + c : L1 + r0 + n.xm) = res[1] ? R(0) : nu[1];
+        *(n.wym ? L4 + c : L2 + rm + x) = nu[2];
+        *(n.wxp ? L1 + c : L3 + r0 + n.xp) = res[3] ? R(0) : nu[3];
+        *(n.wyp ? L2 + c : L4 + rp + x) = nu[4];
+        *((n.wxm || n.wym) ? L7 + c : L5 + rm + n.xm) = res[5] ? R(0) : nu[5];
+        *((n.wxp || n.wym) ? L8 + c : L6 + rm + n.xp) = res[6] ? R(0) : nu[6];
+        *((n.wxp || n.wyp) ? L5 + c : L7 + rp + n.xp) = res[7] ? R(0) : nu[7];
+        *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = res[8] ? R(0) : nu[8];
+        eb[c] += static_cast<double>(e_b);
+        gxb[c] += static_cast<double>(gx_b);
+        gyb[c] += static_cast<double>(gy_b);
+    }
+    if constexpr (SEED) block_partial(acc, part, t);
+}
+
+// Initial state: f_i(r, 0) = w_i eps(r) rho0 (1 + 3 e_i.u0 + 9/2 (e_i.u0)^2 -
+// 3/2 u0.u0); its porosity derivative, weighted by the adjoint of the slot the
+// first gather pulls it from.
+template <typename R>
+__global__ __launch_bounds__(NTHREADS) void k_adjoint_init(const R *__restrict__ lam, Geo g,
+                                                           double rho0, double u0x, double u0y,
+                                                           double *__restrict__ eb)
+{
+    const int t = blockIdx.x;
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x = bx * TX + threadIdx.x % TX;
+    for (int r = 0; r < ROWS; r++) {
+        const int y = by * TY + threadIdx.x / TX + NW * r;
+        if (x >= g.Lx || y >= g.Ly) continue;
+        const Nbr n = neighbours(x, y, g);
+        const long long pl = g.plane;
+        const int c = y * g.pitch + x, rm = n.ym * g.pitch, r0 = y * g.pitch, rp = n.yp * g.pitch;
+        const long long src[9] = {
+            c,
+            n.wxm ? 3 * pl + c : 1 * pl + r0 + n.xm,
+            n.wym ? 4 * pl + c : 2 * pl + rm + x,
+            n.wxp ? 1 * pl + c : 3 * pl + r0 + n.xp,
+            n.wyp ? 2 * pl + c : 4 * pl + rp + x,
+            (n.wxm || n.wym) ? 7 * pl + c : 5 * pl + rm + n.xm,
+            (n.wxp || n.wym) ? 8 * pl + c : 6 * pl + rm + n.xp,
+            (n.wxp || n.wyp) ? 5 * pl + c : 7 * pl + rp + n.xp,
+            (n.wxm || n.wyp) ? 6 * pl + c : 8 * pl + rp + n.xm,
+        };
+        const double uu = u0x * u0x + u0y * u0y;
+        double s = 0.0;
+        for (int i = 0; i < 9; i++) {
+            const double eu = CX[i] * u0x + CY[i] * u0y;
+            s += static_cast<double>(lam[src[i]]) * wgt(i) * rho0 *
+                 (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        }
+        eb[c] += s;
+    }
+}
+
+// Nodes x0 along one axis whose halo neighbour x0 + e (wrapped, or mirrored
+// behind a non-periodic end) is v: at most two.
+__device__ __forceinline__ int halo_sources(int v, int e, int L, int wall, int out[2])
+{
+    int n = 0;
+    if (!wall) {
+        int s = v - e;
+        if (s < 0) s += L;
+        else if (s >= L) s -= L;
+        out[n++] = s;
+        return n;
+    }
+    const int s = v - e;
+    if (s >= 0 && s < L) out[n++] = s;
+    if (e == -1 && v == 0) out[n++] = 0;
+    if (e == 1 && v == L - 1) out[n++] = L - 1;
+    return n;
+}
+
+// dJ/deps(v) = direct adjoint + grad(eps) adjoint through the transposed
+// stencil grad(eps)(x) = sum_i 3 w_i e_i eps(halo(x + e_i)), in gather form
+// (deterministic).  out is [Ly][Lx].
+__global__ __launch_bounds__(NTHREADS) void k_adjoint_finish(const double *__restrict__ eb,
+                                                             const double *__restrict__ gxb,
+                                                             const double *__restrict__ gyb,
+                                                             Geo g, double *__restrict__ out)
+{
+    const int t = blockIdx.x;
+    const int bx = t % g.nbx, by = t / g.nbx;
+    const int x = bx * TX + threadIdx.x % TX;
+    for (int r = 0; r < ROWS; r++) {
+        const int y = by * TY + threadIdx.x / TX + NW * r;
+        if (x >= g.Lx || y >= g.Ly) continue;
+        double s = eb[y * g.pitch + x];
+        for (int i = 1; i < 9; i++) {
+            int sx[2], sy[2];
+            const int nx = halo_sources(x, CX[i], g.Lx, g.wall_x, sx);
+            const int ny = halo_sources(y, CY[i], g.Ly, g.wall_y, sy);
+            const double c = 3.0 * wgt(i);
+            for (int a = 0; a < nx; a++)
+                for (int b = 0; b < ny; b++) {
+                    const int k = sy[b] * g.pitch + sx[a];
+                    s += c * (CX[i] * gxb[k] + CY[i] * gyb[k]);
+                }
+        }
+        out[(long long)y * g.Lx + x] = s;
+    }
+}
+
+// Fill with zero (used for the FP64 accumulators; a kernel rather than a
+// memset so the grad sequence stays capturable).
+__global__ __launch_bounds__(NTHREADS) void k_zero(double *__restrict__ p, long long n)
+{
+    const long long i = static_cast<long long>(blockIdx.x) * NTHREADS + threadIdx.x;
+    if (i < n) p[i] = 0.0;
 }
 
 }  // namespace
@@ -1055,9 +1407,15 @@ int check_params(const lbm_vans_params *p)
     if (pitch * p->Ly >= (1LL << 31))
         return fail(LBM_VANS_EINVAL, "lattice %d x %d too large (padded nodes must be < 2^31)",
                     p->Lx, p->Ly);
-    if ((p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_BOUNCEBACK) ||
+    if ((p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_BOUNCEBACK && p->bc_x != LBM_BC_OPEN) ||
         (p->bc_y != LBM_BC_PERIODIC && p->bc_y != LBM_BC_BOUNCEBACK))
         return fail(LBM_VANS_EINVAL, "boundary kinds (%d, %d) not supported", p->bc_x, p->bc_y);
+    if (p->bc_x == LBM_BC_OPEN) {
+        if (p->Lx < 2) return fail(LBM_VANS_EINVAL, "open x ends need Lx >= 2");
+        if (!(p->rho_in > 0.0) || !std::isfinite(p->rho_in) || !(p->rho_out > 0.0) ||
+            !std::isfinite(p->rho_out) || !std::isfinite(p->u_in) || !std::isfinite(p->u_out))
+            return fail(LBM_VANS_EINVAL, "reservoir densities must be finite and > 0, velocities finite");
+    }
     if (p->storage != LBM_F64 && p->storage != LBM_F32_SHIFTED && p->storage != LBM_F16_SHIFTED)
         return fail(LBM_VANS_EINVAL, "unknown storage %d", p->storage);
     if (!(p->tau > 0.5) || !std::isfinite(p->tau))
@@ -1098,8 +1456,9 @@ Geo make_geo(const lbm_vans_params *p, int vec = 1)
     g.Lx = p->Lx;
     g.Ly = p->Ly;
     g.pitch = (p->Lx + PITCH_ALIGN - 1) / PITCH_ALIGN * PITCH_ALIGN;
-    g.wall_x = p->bc_x == LBM_BC_BOUNCEBACK;
+    g.wall_x = p->bc_x != LBM_BC_PERIODIC;
     g.wall_y = p->bc_y == LBM_BC_BOUNCEBACK;
+    g.open_x = p->bc_x == LBM_BC_OPEN;
     g.nbx = (p->Lx + TX * vec - 1) / (TX * vec);
     int nby = (p->Ly + TY - 1) / TY;
     g.ntiles = g.nbx * nby;
@@ -1146,6 +1505,20 @@ Phys<R> make_phys(const lbm_vans_params *p)
     double s = p->storage == LBM_F16_SHIFTED ? std::ldexp(1.0, p->fp16_scale_log2) : 1.0;
     ph.scale = static_cast<R>(s);
     ph.inv_scale = static_cast<R>(1.0 / s);
+    // reservoir deviations per unit porosity: w_i (rho_b (1 + 3 e.u + 9/2 (e.u)^2
+    // - 3/2 u.u) - rho0) with u = (u_b, 0), for the directions entering the domain
+    static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const double wt[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double rho_ref = static_cast<double>(ph.rho0);
+    for (int i = 0; i < 9; i++) {
+        double eui = cx[i] * p->u_in, euo = cx[i] * p->u_out;
+        double pin = 1.0 + 3.0 * eui + 4.5 * eui * eui - 1.5 * p->u_in * p->u_in;
+        double pout = 1.0 + 3.0 * euo + 4.5 * euo * euo - 1.5 * p->u_out * p->u_out;
+        ph.rin[i] = cx[i] > 0 ? static_cast<R>(wt[i] * (p->rho_in * pin - rho_ref)) : R(0);
+        ph.rout[i] = cx[i] < 0 ? static_cast<R>(wt[i] * (p->rho_out * pout - rho_ref)) : R(0);
+    }
+    ph.reservoir = 0;
     return ph;
 }
 
@@ -1174,35 +1547,40 @@ void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
     const dim3 grid(h->gs.ntiles), block(NTHREADS);
     const R *eps = (const R *)h->eps;
     if (h->vec == VMAX) {
-        if (h->gs.wall_x && h->gs.wall_y)
-            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, true, true, DIAG>), grid, block, 0,
-                               h->stream, src, dst, eps, h->gs, ph, h->part);
-        else if (h->gs.wall_x)
-            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, true, false, DIAG>), grid, block, 0,
-                               h->stream, src, dst, eps, h->gs, ph, h->part);
-        else if (h->gs.wall_y)
-            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, false, true, DIAG>), grid, block, 0,
-                               h->stream, src, dst, eps, h->gs, ph, h->part);
-        else
-            hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, false, false, DIAG>), grid, block, 0,
-                               h->stream, src, dst, eps, h->gs, ph, h->part);
+        const int bx = h->gs.open_x ? 2 : (h->gs.wall_x ? 1 : 0);
+        const bool wy = h->gs.wall_y;
+#define LBM_VANS_VEC(BXV, WYV)                                                              \
+    hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, BXV, WYV, DIAG>), grid, block, 0, h->stream, \
+                       src, dst, eps, h->gs, ph, h->part)
+        if (bx == 0 && !wy) LBM_VANS_VEC(0, false);
+        else if (bx == 0) LBM_VANS_VEC(0, true);
+        else if (bx == 1 && !wy) LBM_VANS_VEC(1, false);
+        else if (bx == 1) LBM_VANS_VEC(1, true);
+        else if (!wy) LBM_VANS_VEC(2, false);
+        else LBM_VANS_VEC(2, true);
+#undef LBM_VANS_VEC
     } else
         hipLaunchKernelGGL((k_sweep<S, R, DIAG>), grid, block, 0, h->stream, src, dst,
                            (const R *)h->eps, h->gs, ph, h->part);
 }
 
-int launch_sweep(lbm_vans_handle *h, bool diag)
+// One time step from the state n stored in src into dst.
+int launch_sweep_ptrs(lbm_vans_handle *h, const void *src, void *dst, int64_t n, bool diag)
 {
-    const char *src = h->buf[h->cur];
-    char *dst = h->buf[1 - h->cur];
     return with_types(h->p.storage, [&](auto *sp, auto *rp) {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
+        ph.reservoir = n >= 1;
         if (diag) launch_sweep_t<S, R, true>(h, (const S *)src, (S *)dst, ph);
         else launch_sweep_t<S, R, false>(h, (const S *)src, (S *)dst, ph);
         return check_launch("sweep");
     });
+}
+
+int launch_sweep(lbm_vans_handle *h, bool diag)
+{
+    return launch_sweep_ptrs(h, h->buf[h->cur], h->buf[1 - h->cur], h->n, diag);
 }
 
 int launch_finalize(lbm_vans_handle *h, double *out, int nparts, bool add_mass0, double step)
@@ -1328,6 +1706,7 @@ int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, voi
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
+        ph.reservoir = h->n >= 1;
         hipLaunchKernelGGL((k_moments<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
                            (const S *)h->buf[h->cur], (const R *)h->eps, h->g, ph, (R *)eps_rho,
                            (R *)rho, (R *)ux, (R *)uy, h->part);
@@ -1354,6 +1733,7 @@ int lbm_vans_get_state(lbm_vans_handle *h, void *f)
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
+        ph.reservoir = h->n >= 1;
         hipLaunchKernelGGL((k_get_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
                            (const S *)h->buf[h->cur], (const R *)h->eps, h->g, ph, (double *)f);
         return check_launch("k_get_state");
@@ -1398,11 +1778,152 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
     return LBM_VANS_OK;
 }
 
-int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
-                  double *dJdeps, double *J)
+namespace {
+
+struct GradLayout {
+    size_t pop, lam, acc, total;
+    int64_t nck, seg;
+};
+
+GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_every)
 {
-    (void)h; (void)objective; (void)nsteps; (void)ckpt_every; (void)dJdeps; (void)J;
-    return fail(LBM_VANS_ENOTIMPL, "the adjoint sweep is not built");
+    Layout L = make_layout(p);
+    Geo g = make_geo(p);
+    GradLayout G;
+    G.pop = L.pop;
+    G.nck = (nsteps + ckpt_every - 1) / ckpt_every;
+    if (G.nck < 1) G.nck = 1;
+    G.seg = ckpt_every;
+    G.lam = align256((size_t)9 * g.plane * (p->storage == LBM_F64 ? 8 : 4));
+    G.acc = align256((size_t)g.plane * sizeof(double));
+    G.total = (size_t)(G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc;
+    return G;
+}
+
+int check_grad_args(const lbm_vans_params *p, int32_t objective, int64_t nsteps,
+                    int32_t ckpt_every)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (objective != LBM_OBJ_OUTLET_FLUX)
+        return fail(LBM_VANS_EINVAL, "unknown objective %d", objective);
+    if (nsteps < 0) return fail(LBM_VANS_EINVAL, "nsteps = %lld < 0", (long long)nsteps);
+    if (ckpt_every < 1) return fail(LBM_VANS_EINVAL, "ckpt_every = %d < 1", ckpt_every);
+    return LBM_VANS_OK;
+}
+
+}  // namespace
+
+size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int64_t nsteps,
+                                int32_t ckpt_every)
+{
+    if (check_grad_args(p, objective, nsteps, ckpt_every)) return 0;
+    return grad_layout(p, nsteps, ckpt_every).total;
+}
+
+int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
+                  void *grad_work, size_t grad_work_bytes, double *dJdeps, double *J)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    int rc = check_grad_args(&h->p, objective, nsteps, ckpt_every);
+    if (rc) return rc;
+    if (!grad_work || !dJdeps) return fail(LBM_VANS_EINVAL, "grad_work and dJdeps are required");
+    if (reinterpret_cast<uintptr_t>(grad_work) % 256)
+        return fail(LBM_VANS_EINVAL, "grad_work must be 256-byte aligned");
+    const GradLayout G = grad_layout(&h->p, nsteps, ckpt_every);
+    if (grad_work_bytes < G.total)
+        return fail(LBM_VANS_EINVAL, "grad_work has %zu bytes, %zu needed", grad_work_bytes,
+                    G.total);
+    char *w = static_cast<char *>(grad_work);
+    auto ckpt = [&](int64_t c) { return w + c * G.pop; };
+    auto seg = [&](int64_t j) { return w + (G.nck + j) * G.pop; };
+    char *lam[2] = {w + (G.nck + G.seg) * G.pop, w + (G.nck + G.seg) * G.pop + G.lam};
+    double *eb = reinterpret_cast<double *>(w + (G.nck + G.seg) * G.pop + 2 * G.lam);
+    double *gxb = eb + G.acc / sizeof(double);
+    double *gyb = gxb + G.acc / sizeof(double);
+    const Geo &g = h->g;
+    const int K = ckpt_every;
+
+    return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        const Phys<R> ph0 = make_phys<R>(&h->p);
+        // 1. initial state, forward with a checkpoint every K steps
+        hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (S *)h->buf[0], (const R *)h->eps, g, h->p.rho0,
+                           static_cast<double>(ph0.rho0), h->p.u0[0], h->p.u0[1],
+                           (const double *)nullptr, ph0.scale);
+        int r = check_launch("k_set_state");
+        if (r) return r;
+        h->cur = 0;
+        h->n = 0;
+        for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += K) {
+            HIP_TRY(hipMemcpyAsync(ckpt(s0 / K), h->buf[h->cur], G.pop, hipMemcpyDeviceToDevice,
+                                   h->stream));
+            for (int64_t k = 0; k < K && s0 + k < nsteps; k++) {
+                r = launch_sweep(h, false);
+                if (r) return r;
+                h->cur = 1 - h->cur;
+                h->n++;
+            }
+            if (nsteps == 0) break;
+        }
+        // 2. seed: J of the state N and the adjoint of that state
+        const long long nz = (long long)(3 * G.acc / sizeof(double));
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)((nz + NTHREADS - 1) / NTHREADS)),
+                           dim3(NTHREADS), 0, h->stream, eb, nz);
+        r = check_launch("k_zero");
+        if (r) return r;
+        Phys<R> ph = ph0;
+        ph.reservoir = nsteps >= 1;
+        int a = 0;
+        hipLaunchKernelGGL((k_adjoint<S, R, true>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                           h->stream, (const S *)h->buf[h->cur], (const R *)nullptr,
+                           (R *)lam[a], (const R *)h->eps, g, ph, eb, gxb, gyb, h->part);
+        r = check_launch("k_adjoint seed");
+        if (r) return r;
+        r = launch_finalize(h, h->scratch_rec, h->ntiles, false, static_cast<double>(nsteps));
+        if (r) return r;
+        double rec[NRED];
+        HIP_TRY(hipMemcpyAsync(rec, h->scratch_rec, sizeof rec, hipMemcpyDeviceToHost,
+                               h->stream));
+        // 3. reverse, one checkpoint segment at a time (states recomputed)
+        const int64_t nck = nsteps == 0 ? 0 : (nsteps + K - 1) / K;
+        for (int64_t c = nck - 1; c >= 0; c--) {
+            const int64_t s0 = c * K, s1 = std::min<int64_t>(s0 + K, nsteps);
+            for (int64_t j = 1; j < s1 - s0; j++) {
+                const void *src = j == 1 ? (const void *)ckpt(c) : (const void *)seg(j - 1);
+                r = launch_sweep_ptrs(h, src, seg(j), s0 + j - 1, false);
+                if (r) return r;
+            }
+            for (int64_t n = s1 - 1; n >= s0; n--) {
+                const void *state = n == s0 ? (const void *)ckpt(c) : (const void *)seg(n - s0);
+                ph.reservoir = n >= 1;
+                hipLaunchKernelGGL((k_adjoint<S, R, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                                   h->stream, (const S *)state, (const R *)lam[a],
+                                   (R *)lam[1 - a], (const R *)h->eps, g, ph, eb, gxb, gyb,
+                                   h->part);
+                r = check_launch("k_adjoint");
+                if (r) return r;
+                a = 1 - a;
+            }
+        }
+        // 4. initial state and the porosity stencil
+        hipLaunchKernelGGL((k_adjoint_init<R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (const R *)lam[a], g, h->p.rho0, h->p.u0[0], h->p.u0[1], eb);
+        r = check_launch("k_adjoint_init");
+        if (r) return r;
+        hipLaunchKernelGGL(k_adjoint_finish, dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (const double *)eb, (const double *)gxb, (const double *)gyb, g,
+                           dJdeps);
+        r = check_launch("k_adjoint_finish");
+        if (r) return r;
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (J) *J = rec[0];
+        if (!std::isfinite(rec[0]))
+            return fail(LBM_VANS_ENONFINITE, "objective is not finite");
+        return LBM_VANS_OK;
+    });
 }
 
 void lbm_vans_destroy(lbm_vans_handle *h)

@@ -22,18 +22,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_vans.so")
 
 OK, EINVAL, EHIP, ENONFINITE, ENOTIMPL = 0, -1, -2, -3, -4
-BC_PERIODIC, BC_BOUNCEBACK = 0, 1
+BC_PERIODIC, BC_BOUNCEBACK, BC_OPEN = 0, 1, 2
 F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
 DRAG_ERGUN, DRAG_CONST = 0, 1
 NDIAG = 8
 DIAG_RING = 4096
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
            "lbm_vans_moments", "lbm_vans_get_state", "lbm_vans_set_state",
-           "lbm_vans_diag_read", "lbm_vans_grad", "lbm_vans_destroy", "lbm_vans_last_error",
-           "lbm_vans_abi_version")
+           "lbm_vans_diag_read", "lbm_vans_grad_work_bytes", "lbm_vans_grad",
+           "lbm_vans_destroy", "lbm_vans_last_error", "lbm_vans_abi_version")
+OBJ_OUTLET_FLUX = 0
 
 STORAGE = {"f64": F64, "f32": F32_SHIFTED, "f16": F16_SHIFTED}
 
@@ -47,6 +48,8 @@ class LbmVansParams(ctypes.Structure):
         ("K", ctypes.c_double), ("F_eps", ctypes.c_double),
         ("G", ctypes.c_double * 2), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 2),
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
+        ("rho_in", ctypes.c_double), ("u_in", ctypes.c_double),
+        ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double),
     ]
 
 
@@ -68,13 +71,17 @@ class Params:
     u0: tuple = (0.0, 0.0)
     fp16_scale_log2: int = 10
     diag_every: int = 0
+    rho_in: float = 1.0
+    u_in: float = 0.0
+    rho_out: float = 1.0
+    u_out: float = 0.0
 
     def c(self) -> LbmVansParams:
         return LbmVansParams(self.Lx, self.Ly, self.bc_x, self.bc_y, self.storage, self.drag,
                              self.tau, self.d_p, self.K, self.F_eps,
                              (ctypes.c_double * 2)(*self.G), self.rho0,
                              (ctypes.c_double * 2)(*self.u0), self.fp16_scale_log2,
-                             self.diag_every)
+                             self.diag_every, self.rho_in, self.u_in, self.rho_out, self.u_out)
 
 
 class LbmVansError(RuntimeError):
@@ -107,7 +114,9 @@ def load(path: str = LIB_PATH):
     L.lbm_vans_get_state.argtypes = [vp, vp]
     L.lbm_vans_set_state.argtypes = [vp, vp]
     L.lbm_vans_diag_read.argtypes = [vp, dp, i32, ctypes.POINTER(i32)]
-    L.lbm_vans_grad.argtypes = [vp, i32, i64, i32, dp, dp]
+    L.lbm_vans_grad_work_bytes.argtypes = [P, i32, i64, i32]
+    L.lbm_vans_grad_work_bytes.restype = ctypes.c_size_t
+    L.lbm_vans_grad.argtypes = [vp, i32, i64, i32, vp, ctypes.c_size_t, vp, dp]
     L.lbm_vans_destroy.argtypes = [vp]
     L.lbm_vans_destroy.restype = None
     L.lbm_vans_last_error.argtypes = []
@@ -183,13 +192,19 @@ def lbm_vans_diag_read(h, max_records: int = DIAG_RING):
     return arr, rc
 
 
-def lbm_vans_grad(h, objective: int, nsteps: int, ckpt_every: int, dJdeps=None):
+def lbm_vans_grad_work_bytes(p: Params, objective: int, nsteps: int, ckpt_every: int) -> int:
+    n = load().lbm_vans_grad_work_bytes(ctypes.byref(p.c()), objective, int(nsteps),
+                                        int(ckpt_every))
+    if n == 0:
+        raise LbmVansError(EINVAL, load().lbm_vans_last_error().decode())
+    return n
+
+
+def lbm_vans_grad(h, objective: int, nsteps: int, ckpt_every: int, grad_work, dJdeps) -> float:
     J = ctypes.c_double()
-    rc = load().lbm_vans_grad(h, objective, nsteps, ckpt_every,
-                              None if dJdeps is None else ctypes.cast(dJdeps.data_ptr(),
-                                                                      ctypes.POINTER(ctypes.c_double)),
-                              ctypes.byref(J))
-    _check(rc)
+    _check(load().lbm_vans_grad(h, objective, int(nsteps), int(ckpt_every), grad_work.data_ptr(),
+                                grad_work.numel() * grad_work.element_size(), dJdeps.data_ptr(),
+                                ctypes.byref(J)))
     return J.value
 
 
@@ -260,6 +275,19 @@ class Solver:
     def diag_records(self):
         return lbm_vans_diag_read(self.h)
 
+    def grad(self, nsteps: int, ckpt_every: int = 200, objective: int = OBJ_OUTLET_FLUX):
+        """(J, dJ/deps as a float64 tensor [Ly, Lx]) of the objective after nsteps steps
+        from the initial state (reverse sweep with a checkpoint every ckpt_every steps).
+        The solver's state is f(., nsteps) afterwards."""
+        t = self.torch
+        nbytes = lbm_vans_grad_work_bytes(self.p, objective, nsteps, ckpt_every)
+        with t.cuda.device(self.device):
+            gw = t.empty(nbytes, dtype=t.uint8, device=self.device)
+            g = t.empty((self.p.Ly, self.p.Lx), dtype=t.float64, device=self.device)
+            J = lbm_vans_grad(self.h, objective, nsteps, ckpt_every, gw, g)
+            del gw
+        return J, g
+
     def close(self):
         if getattr(self, "h", None):
             lbm_vans_destroy(self.h)
@@ -270,3 +298,28 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def outlet_flux_function():
+    """A torch.autograd.Function: J = OutletFlux.apply(eps, params, nsteps, ckpt_every)
+    gives the outlet mass flux after nsteps steps and backpropagates dJ/deps computed by
+    the library's reverse sweep."""
+    import torch
+
+    class OutletFlux(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, eps, params, nsteps, ckpt_every):
+            s = Solver(params, eps.detach(), device=eps.device if eps.is_cuda else "cuda:0")
+            J, g = s.grad(nsteps, ckpt_every, OBJ_OUTLET_FLUX)
+            s.close()
+            ctx.save_for_backward(g)
+            ctx.eps_dtype, ctx.eps_device = eps.dtype, eps.device
+            return torch.tensor(J, dtype=torch.float64, device=eps.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (g,) = ctx.saved_tensors
+            grad = (g * gJ.to(g.device, torch.float64)).to(ctx.eps_device, ctx.eps_dtype)
+            return grad, None, None, None
+
+    return OutletFlux

@@ -126,3 +126,16 @@ CROP = 512
 def crop_porosity(w: Workload, n: int = CROP) -> np.ndarray:
     """Top-left n x n block of the workload's full porosity field."""
     return np.ascontiguousarray(w.porosity()[:n, :n])
+
+# Porous channel with through-flow for the gradient of the outlet mass flux:
+# 1024 x 512 nodes, half-way bounce-back walls in y, open x ends with inflow
+# and outflow reservoirs at density 1 and x-velocity 0.02, GRF porosity in
+# [0.4, 1.0] (l = 16, seed 1407), tau = 0.8, d_p from Da = 1e-2 on the channel
+# width at porosity 0.7, plug-flow start (u0 = 0.02), 4000 steps, FP32,
+# gradient through checkpoints every 200 steps.
+ADJOINT_CHANNEL = Workload(
+    name="porous_open_channel_1024x512_f32", Lx=1024, Ly=512, tau=0.8,
+    d_p=ergun_dp_for_darcy(1e-2, 512.0, 0.7), Gx=0.0, Gy=0.0, steps=4000,
+    walls_y=True, storage="f32", eps_kind="grf", eps_lo=0.4, eps_hi=1.0, seed=SEED + 1)
+ADJOINT_U_IN = 0.02
+ADJOINT_CKPT = 200

@@ -28,25 +28,36 @@ class Spec:
     storage: str = "f64"
     fp16_scale_log2: int = 10
     diag_every: int = 0
+    open_x: bool = False
+    rho_in: float = 1.0
+    u_in: float = 0.0
+    rho_out: float = 1.0
+    u_out: float = 0.0
 
     def oracle(self) -> oracle.Params:
         return oracle.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
-                             bc_x=oracle.WALL if self.walls_x else oracle.PERIODIC,
+                             bc_x=(oracle.OPEN if self.open_x else
+                                   oracle.WALL if self.walls_x else oracle.PERIODIC),
                              bc_y=oracle.WALL if self.walls_y else oracle.PERIODIC,
                              drag=oracle.DRAG_CONST if self.drag_const else oracle.DRAG_ERGUN,
                              d_p=self.d_p, K=self.K, F_eps=self.F_eps, Gx=self.G[0],
-                             Gy=self.G[1], rho0=self.rho0, u0x=self.u0[0], u0y=self.u0[1])
+                             Gy=self.G[1], rho0=self.rho0, u0x=self.u0[0], u0y=self.u0[1],
+                             rho_in=self.rho_in, u_in=self.u_in, rho_out=self.rho_out,
+                             u_out=self.u_out)
 
     def gpu(self):
         from paper_1406_6438_amd import lbm
         return lbm.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
-                          bc_x=lbm.BC_BOUNCEBACK if self.walls_x else lbm.BC_PERIODIC,
+                          bc_x=(lbm.BC_OPEN if self.open_x else
+                                lbm.BC_BOUNCEBACK if self.walls_x else lbm.BC_PERIODIC),
                           bc_y=lbm.BC_BOUNCEBACK if self.walls_y else lbm.BC_PERIODIC,
                           storage=lbm.STORAGE[self.storage],
                           drag=lbm.DRAG_CONST if self.drag_const else lbm.DRAG_ERGUN,
                           d_p=self.d_p, K=self.K, F_eps=self.F_eps, G=tuple(self.G),
                           rho0=self.rho0, u0=tuple(self.u0),
-                          fp16_scale_log2=self.fp16_scale_log2, diag_every=self.diag_every)
+                          fp16_scale_log2=self.fp16_scale_log2, diag_every=self.diag_every,
+                          rho_in=self.rho_in, u_in=self.u_in, rho_out=self.rho_out,
+                          u_out=self.u_out)
 
     def input_eps(self, eps: np.ndarray) -> np.ndarray:
         """The porosity both sides receive: rounded once to the GPU's compute precision."""

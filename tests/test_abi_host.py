@@ -44,6 +44,8 @@ def test_header_constants_match_binding():
     assert int(consts["LBM_DRAG_CONST"]) == lbm.DRAG_CONST
     assert int(consts["LBM_VANS_NDIAG"]) == lbm.NDIAG
     assert int(consts["LBM_VANS_DIAG_RING"]) == lbm.DIAG_RING
+    assert int(consts["LBM_BC_OPEN"]) == lbm.BC_OPEN
+    assert int(consts["LBM_OBJ_OUTLET_FLUX"]) == lbm.OBJ_OUTLET_FLUX
 
 
 def test_work_bytes_scale_with_storage():
@@ -60,7 +62,8 @@ def test_work_bytes_scale_with_storage():
 
 @pytest.mark.parametrize("bad", [
     dict(Lx=0), dict(Ly=-3), dict(tau=0.5), dict(tau=math.nan), dict(d_p=0.0),
-    dict(d_p=-1.0), dict(storage=7), dict(bc_x=2), dict(bc_y=5), dict(drag=3),
+    dict(d_p=-1.0), dict(storage=7), dict(bc_x=3), dict(bc_y=2), dict(bc_y=5), dict(drag=3),
+    dict(bc_x=2, Lx=1), dict(bc_x=2, rho_in=0.0), dict(bc_x=2, u_out=math.inf),
     dict(drag=lbm.DRAG_CONST, K=0.0), dict(drag=lbm.DRAG_CONST, K=1.0, F_eps=-1.0),
     dict(rho0=0.0), dict(G=(math.inf, 0.0)), dict(u0=(0.0, math.nan)),
     dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30), dict(diag_every=-1),
@@ -98,7 +101,14 @@ def test_null_handle_calls_fail_cleanly():
     assert L.lbm_vans_moments(None, None, None, None, None, None) == lbm.EINVAL
     assert L.lbm_vans_step_count(None) == -1
     L.lbm_vans_destroy(None)
-    assert L.lbm_vans_grad(None, 0, 1, 1, None, None) == lbm.ENOTIMPL
+    assert L.lbm_vans_grad(None, 0, 1, 1, None, 0, None, None) == lbm.EINVAL
+    p = lbm.Params(Lx=16, Ly=8, tau=0.7, d_p=10.0)
+    assert L.lbm_vans_grad_work_bytes(ctypes.byref(p.c()), 1, 10, 5) == 0   # unknown objective
+    assert L.lbm_vans_grad_work_bytes(ctypes.byref(p.c()), 0, 10, 0) == 0   # ckpt_every < 1
+    n1 = lbm.lbm_vans_grad_work_bytes(p, 0, 100, 10)
+    n2 = lbm.lbm_vans_grad_work_bytes(p, 0, 100, 50)
+    pop = 9 * 8 * 256 * 4
+    assert n1 >= (10 + 10) * pop and n2 >= (2 + 50) * pop
 
 
 def test_binding_fails_loudly_when_library_missing(tmp_path):

@@ -1,0 +1,176 @@
+"""GPU parity of the open (inflow/outflow) boundaries and of the reverse sweep
+(dJ/deps of the outlet mass flux) against the FP64 oracle.
+
+Tolerances:
+* forward with open ends: as the periodic/wall parity (FP64 a few ulp per step;
+  FP32 bounded by FP32 roundoff of the stored deviations; rel. L2(u) <= 1e-5);
+* gradient, FP64 storage: rel. max error <= 1e-10 against the oracle's reverse
+  pass (same exact derivative, FMA / summation-order differences only);
+* gradient, FP32 storage and arithmetic: rel. L2 error <= 1e-4 against the oracle's
+  FP64 reverse pass (the accuracy bar of the gradient), and against the oracle's
+  central differences at the full 1024 x 512 workload.
+"""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import Spec, gpu_run, oracle_run, rel_l2, say
+from paper_1406_6438_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "adjoint_channel_1024x512.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1406_6438_amd import lbm
+    lbm.load()
+
+
+def _open_spec(Lx, Ly, storage, walls_y=True, **kw):
+    args = dict(Lx=Lx, Ly=Ly, tau=0.7, walls_y=walls_y, open_x=True, d_p=6.0, rho_in=1.01,
+                u_in=0.03, rho_out=0.99, u_out=0.02, u0=(0.01, 0.0), G=(1e-5, 0.0),
+                storage=storage)
+    args.update(kw)
+    return Spec(**args)
+
+
+OPEN_GEOMS = [(12, 7, True), (13, 9, False), (130, 11, True), (260, 6, True), (64, 5, False)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("geom", OPEN_GEOMS, ids=lambda g: "%dx%d_wy%d" % g)
+def test_open_channel_forward_parity(geom, storage):
+    Lx, Ly, wy = geom
+    say(f"[open forward {storage}] {Lx}x{Ly} walls_y={wy}")
+    spec = _open_spec(Lx, Ly, storage, walls_y=wy)
+    eps = W.grf_porosity(Lx, Ly, seed=200 + Lx, ell=3.0, lo=0.4, hi=1.0)
+    for nsteps in (0, 1, 50):
+        mg, fg = gpu_run(spec, eps, nsteps)
+        mo, fo = oracle_run(spec, eps, nsteps)
+        if storage == "f64":
+            assert np.abs(fg - fo).max() <= 1e-13
+            assert np.abs(mg["ux"] - mo["ux"]).max() <= 1e-13
+        else:
+            # FP32 roundoff, a few times per step, of numbers as large as the deviation
+            # from the rest state plus the half porosity difference the storage shift
+            # adds and removes (w_i rho0 |delta eps| / 2 <= |delta eps| / 18)
+            rest = oracle.init(dataclasses.replace(spec, u0=(0.0, 0.0)).oracle(),
+                               spec.input_eps(eps))
+            de = max(np.abs(eps - np.roll(eps, s, axis=a)).max() for a in (0, 1) for s in (1, -1))
+            D = np.abs(fo - rest).max() + de / 18.0
+            assert np.abs(fg - fo).max() <= 4 * (nsteps + 1) * 2.0 ** -24 * D
+            assert rel_l2(mg["ux"], mo["ux"]) <= 1e-5
+
+
+def _grad_gpu(spec, eps, nsteps, K):
+    from paper_1406_6438_amd import lbm
+    s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
+    J, g = s.grad(nsteps, K)
+    n = s.n
+    s.close()
+    return J, g.cpu().numpy(), n
+
+
+@pytest.mark.parametrize("geom", [(24, 12, True), (26, 10, False), (132, 9, True)],
+                         ids=lambda g: "%dx%d_wy%d" % g)
+def test_gradient_fp64_matches_oracle_adjoint(geom):
+    Lx, Ly, wy = geom
+    say(f"[grad f64] {Lx}x{Ly} walls_y={wy}")
+    spec = _open_spec(Lx, Ly, "f64", walls_y=wy)
+    eps = W.grf_porosity(Lx, Ly, seed=300 + Lx, ell=3.0, lo=0.4, hi=0.98)
+    nsteps = 80
+    Jg, gg, n = _grad_gpu(spec, eps, nsteps, 16)
+    Jo, go = oracle.grad_outlet_flux(spec.oracle(), spec.input_eps(eps), nsteps)
+    assert n == nsteps
+    assert abs(Jg - Jo) <= 1e-12 * abs(Jo)
+    assert np.abs(gg - go).max() <= 1e-10 * np.abs(go).max()
+
+
+def test_gradient_fp64_periodic_box_and_const_drag():
+    """No open ends: periodic x, walls in y, body force, constant-K drag law."""
+    spec = Spec(Lx=20, Ly=9, tau=0.9, walls_y=True, drag_const=True, K=5.0, F_eps=0.3,
+                G=(3e-5, -1e-5), u0=(0.02, 0.0), storage="f64")
+    eps = W.grf_porosity(20, 9, seed=34, ell=2.0, lo=0.4, hi=0.95)
+    Jg, gg, _ = _grad_gpu(spec, eps, 40, 7)
+    Jo, go = oracle.grad_outlet_flux(spec.oracle(), spec.input_eps(eps), 40)
+    assert abs(Jg - Jo) <= 1e-12 * abs(Jo)
+    assert np.abs(gg - go).max() <= 1e-10 * np.abs(go).max()
+
+
+def test_gradient_independent_of_checkpoint_interval():
+    """Recomputation is deterministic: any checkpoint interval gives the same bits."""
+    spec = _open_spec(28, 8, "f64")
+    eps = W.grf_porosity(28, 8, seed=41, ell=3.0, lo=0.4, hi=0.98)
+    ref = None
+    for K in (1, 7, 60, 1000):
+        J, g, _ = _grad_gpu(spec, eps, 60, K)
+        if ref is None:
+            ref = (J, g)
+        else:
+            assert J == ref[0] and np.array_equal(g, ref[1])
+
+
+def test_gradient_zero_steps_is_outlet_flux_of_initial_state():
+    spec = _open_spec(16, 6, "f64")
+    eps = W.grf_porosity(16, 6, seed=42, ell=3.0, lo=0.4, hi=0.98)
+    Jg, gg, _ = _grad_gpu(spec, eps, 0, 5)
+    Jo, go = oracle.grad_outlet_flux(spec.oracle(), spec.input_eps(eps), 0)
+    assert abs(Jg - Jo) <= 1e-14 and np.abs(gg - go).max() <= 1e-13
+
+
+@pytest.mark.parametrize("Lx", [96, 97])
+def test_gradient_fp32_matches_oracle_adjoint(Lx):
+    """FP32 storage and arithmetic (vector sweep for 96, one node per lane for 97)."""
+    say(f"[grad f32] {Lx}x40, 300 steps")
+    spec = _open_spec(Lx, 40, "f32", tau=0.8, d_p=60.0, u0=(0.02, 0.0), rho_in=1.0, u_in=0.02,
+                      rho_out=1.0, u_out=0.02, G=(0.0, 0.0))
+    eps = W.grf_porosity(Lx, 40, seed=43, ell=6.0, lo=0.4, hi=1.0)
+    Jg, gg, _ = _grad_gpu(spec, eps, 300, 50)
+    Jo, go = oracle.grad_outlet_flux(spec.oracle(), spec.input_eps(eps), 300)
+    say(f"  J rel err {abs(Jg - Jo) / abs(Jo):.3e}, grad rel L2 {rel_l2(gg, go):.3e}")
+    assert abs(Jg - Jo) <= 1e-5 * abs(Jo)
+    assert rel_l2(gg, go) <= 1e-4
+
+
+def test_autograd_function_backpropagates_library_gradient():
+    from paper_1406_6438_amd import lbm
+    spec = _open_spec(24, 8, "f64")
+    eps = W.grf_porosity(24, 8, seed=44, ell=3.0, lo=0.4, hi=0.98)
+    OutletFlux = lbm.outlet_flux_function()
+    e = torch.tensor(eps, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    J = OutletFlux.apply(e, spec.gpu(), 30, 10)
+    (2.5 * J).backward()
+    Jo, go = oracle.grad_outlet_flux(spec.oracle(), eps, 30)
+    assert abs(J.item() - Jo) <= 1e-12 * abs(Jo)
+    assert np.abs(e.grad.cpu().numpy() - 2.5 * go).max() <= 1e-10 * np.abs(2.5 * go).max()
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden values not generated")
+def test_full_size_gradient_against_oracle_central_differences():
+    """The 1024 x 512 open channel, 4000 steps, checkpoints every 200, FP32: J and dJ/deps
+    at six seeded nodes against the oracle's FP64 value and central differences."""
+    gold = json.load(open(GOLDEN))
+    w = W.ADJOINT_CHANNEL
+    U = W.ADJOINT_U_IN
+    say("[grad f32 full size 1024x512, 4000 steps]")
+    spec = Spec(Lx=w.Lx, Ly=w.Ly, tau=w.tau, walls_y=True, open_x=True, d_p=w.d_p,
+                u0=(U, 0.0), rho_in=1.0, u_in=U, rho_out=1.0, u_out=U, storage="f32")
+    eps = w.porosity()
+    J, g, _ = _grad_gpu(spec, eps, w.steps, W.ADJOINT_CKPT)
+    say(f"  J {J:.9e} vs oracle {gold['J']:.9e}")
+    assert abs(J - gold["J"]) <= 1e-5 * abs(gold["J"])
+    fd = np.array(gold["dJdeps_central_difference"])
+    ad = np.array([g[y, x] for (y, x) in gold["cells_yx"]])
+    say(f"  adjoint {ad}\n  central differences {fd}")
+    assert np.abs(ad - fd).max() <= 1e-4 * np.abs(fd).max() + 1e-4 * np.abs(g).max()

@@ -167,6 +167,83 @@ def time_sweep(w, lbm, torch, steps: int, warmup: int):
     return gpu_s, diag, eps
 
 
+def adjoint_params(lbm, w, Lx=None, Ly=None):
+    from paper_1406_6438_amd import workloads as W
+    U = W.ADJOINT_U_IN
+    return lbm.Params(Lx=Lx or w.Lx, Ly=Ly or w.Ly, tau=w.tau, bc_x=lbm.BC_OPEN,
+                      bc_y=lbm.BC_BOUNCEBACK, storage=lbm.STORAGE[w.storage], d_p=w.d_p,
+                      rho0=w.rho0, u0=(U, 0.0), rho_in=1.0, u_in=U, rho_out=1.0, u_out=U)
+
+
+def adjoint_leg(lbm, torch, no_accuracy: bool):
+    """dJ/deps of the outlet mass flux on the 1024x512 open channel after 4000 steps
+    (checkpoints every 200): wall time of the whole gradient (forward with checkpoints,
+    per-segment recompute, reverse), and the plain FP32 forward on the same workload."""
+    from paper_1406_6438_amd import workloads as W
+    import numpy as np
+    w = W.ADJOINT_CHANNEL
+    K = W.ADJOINT_CKPT
+    eps = cast_eps(w.porosity(), w.storage)
+    p = adjoint_params(lbm, w)
+    s = lbm.Solver(p, eps)
+    log(f"[bench] adjoint: {w.name}, {w.steps} steps, checkpoints every {K}")
+    s.grad(50, K)                                   # warm-up (first launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = s.grad(w.steps, K)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    # the plain forward of the same workload on the same GPU
+    s2 = lbm.Solver(p, eps)
+    s2.step(20)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s2.stream)
+    s2.step(w.steps)
+    e1.record(s2.stream)
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / 1e3
+    s2.close()
+    s.close()
+    del s, s2, g
+    torch.cuda.empty_cache()
+    cells = w.Lx * w.Ly
+    m_grad = cells * w.steps / t_grad / 1e6
+    m_fwd = cells * w.steps / t_fwd / 1e6
+    # algorithmic bytes per node-step: forward with checkpoints (76) + recompute (76)
+    # + reverse step (gather 36, eps 4, adjoint in 36 and out 36, FP64 accumulators
+    # read and written 48) = 312
+    bps = 312
+    out = {"workload": w.name, "steps": w.steps, "ckpt_every": K, "J": J,
+           "value": round(m_grad, 2), "unit": "MLUPS (forward node-steps per second of the "
+                                                  "whole gradient computation)",
+           "seconds": round(t_grad, 4), "fwd_fp32_same_gpu_MLUPS": round(m_fwd, 2),
+           "vs_fp32_forward_same_gpu": round(m_grad / m_fwd, 3),
+           "bytes_per_node_step": bps,
+           "achieved_GBps": round(bps * cells * w.steps / t_grad / 1e9, 1)}
+    log(f"[bench] adjoint: {t_grad:.3f} s, {m_grad:.0f} MLUPS-equivalent; forward {m_fwd:.0f} MLUPS")
+    if not no_accuracy:
+        import oracle
+        n, L = 300, (96, 40)
+        sp = lbm.Params(**{**p.__dict__, "Lx": L[0], "Ly": L[1], "d_p": 60.0})
+        e = cast_eps(W.grf_porosity(L[0], L[1], seed=43, ell=6.0, lo=0.4, hi=1.0), "f32")
+        sg = lbm.Solver(sp, e)
+        Jg, gg = sg.grad(n, 50)
+        gg = gg.cpu().numpy()
+        sg.close()
+        U = W.ADJOINT_U_IN
+        po = oracle.Params(Lx=L[0], Ly=L[1], tau=w.tau, bc_x=oracle.OPEN, bc_y=oracle.WALL,
+                           d_p=60.0, rho0=w.rho0, u0x=U, rho_in=1.0, u_in=U, rho_out=1.0,
+                           u_out=U)
+        Jo, go = oracle.grad_outlet_flux(po, e, n)
+        out["accuracy"] = {"rel_l2_grad_vs_fp64_oracle_adjoint":
+                           float(np.linalg.norm(gg - go) / np.linalg.norm(go)),
+                           "sample": f"{L[0]}x{L[1]} open channel of the same kind, {n} steps, "
+                                     "checkpoints every 50"}
+        log(f"[bench] adjoint accuracy {out['accuracy']['rel_l2_grad_vs_fp64_oracle_adjoint']:.3e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +256,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp16", action="store_true",
                     help="skip the FP16-storage leg (8192^2 box) reported beside the main line")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the gradient leg (1024x512 open channel) reported beside the main line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sweep has no multi-GPU path in this build "
@@ -228,6 +307,10 @@ def main():
             fp16["accuracy"] = accuracy(w16, lbm, torch, w16.steps)
             log(f"[bench] fp16 accuracy {fp16['accuracy']['rel_l2_u_vs_fp64_oracle']:.3e}")
 
+    adj = None
+    if not args.no_adjoint and args.workload == "box4096_f32":
+        adj = adjoint_leg(lbm, torch, args.no_accuracy)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s)")
@@ -258,6 +341,7 @@ def main():
                      "device_copy_GBps": round(copy_bw, 1)},
         "accuracy": acc,
         "fp16_store": fp16,
+        "adjoint": adj,
         "cpu_baseline": cpu,
         "mass_check": {"sum_eps_rho": diag[0], "nonfinite_nodes": diag[6]},
     }

@@ -173,4 +173,6 @@ def test_full_size_gradient_against_oracle_central_differences():
     fd = np.array(gold["dJdeps_central_difference"])
     ad = np.array([g[y, x] for (y, x) in gold["cells_yx"]])
     say(f"  adjoint {ad}\n  central differences {fd}")
-    assert np.abs(ad - fd).max() <= 1e-4 * np.abs(fd).max() + 1e-4 * np.abs(g).max()
+    # the central differences carry J's FP64 rounding noise (~1e-14) over 2h = 2e-5:
+    # ~5e-10 absolute; the FP32 gradient is held to 1e-4 of the largest sampled value
+    assert np.all(np.abs(ad - fd) <= 1e-4 * np.abs(fd).max() + 2e-9)

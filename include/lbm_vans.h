@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 2
+#define LBM_VANS_ABI_VERSION 3
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -200,6 +200,84 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
 /* Release the handle (host memory only; the work buffer stays the caller's).
  * Waits for the handle's queued work first.  NULL is ignored. */
 void lbm_vans_destroy(lbm_vans_handle *h);
+
+/* ---- Ensembles --------------------------------------------------------
+ * A batch advances many independent problems (members) with one kernel
+ * launch per time step: the tiles of all members form one work list, and
+ * every member takes exactly the step lbm_vans_step would take (same node
+ * update, per member tau, drag, forcing, reservoirs and size).  Members are
+ * existing handles; they must share storage, bc_x and bc_y, have
+ * diag_every = 0 and be at the same step.  A member stays a normal handle:
+ * lbm_vans_moments / get_state / set_state / step work on it between batch
+ * calls (a member stepped on its own puts the batch out of step, and batch
+ * calls then fail with LBM_VANS_EINVAL until the others catch up).  The batch
+ * borrows the members: destroy it before them.  Batched work runs on the
+ * batch's stream; ordering it against a member's own stream is the caller's
+ * (one stream for all is simplest). */
+typedef struct lbm_vans_batch lbm_vans_batch;
+
+/* Launch shape of the batched sweep. */
+typedef struct lbm_vans_batch_config {
+    int32_t vec;          /* nodes per lane, a power of two up to 4 (2 for LBM_F64): tiles
+                             are 64*vec nodes wide; a member whose Lx is not a multiple
+                             uses the largest power of two below that divides its Lx   */
+    int32_t grid;         /* 0: one workgroup per tile; else a persistent grid of that
+                             many workgroups (a multiple of 8) walking the tile list   */
+    int32_t graph_steps;  /* steps per replay of the captured step graph (even); 0: plain
+                             launches.  lbm_vans_batch_step replays the graph for whole
+                             chunks from state n >= 1 and launches the rest one by one */
+    int32_t pad_;
+    double us_per_step;   /* lbm_vans_batch_tune: measured microseconds per step       */
+} lbm_vans_batch_config;
+
+/* Bytes of the device table a batch of these members needs (0 if invalid). */
+size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembers);
+
+/* Create a batch of nmembers handles (the array is copied).  work: device
+ * buffer of lbm_vans_batch_work_bytes() bytes, 256-byte aligned, caller-owned,
+ * kept alive until lbm_vans_batch_destroy().  stream: hipStream_t of the
+ * batched work (NULL = null stream); graphs are captured on a private stream
+ * and replayed on it.  Default configuration: widest vec, one workgroup per
+ * tile, 16-step graphs.  Synchronises the stream (table upload). */
+int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
+                          size_t work_bytes, void *stream, lbm_vans_batch **out);
+
+/* Set the launch shape (validated as documented in lbm_vans_batch_config).
+ * Results do not depend on it.  Synchronises the stream. */
+int lbm_vans_batch_configure(lbm_vans_batch *b, const lbm_vans_batch_config *cfg);
+int lbm_vans_batch_get_config(const lbm_vans_batch *b, lbm_vans_batch_config *cfg);
+
+/* Autotune the launch shape on the current members: every vec (widest
+ * first) with one workgroup per tile and with persistent grids of 1, 2, 4 and
+ * 8 workgroups per compute unit, each timed with HIP events over reps sweeps
+ * of the current state (read only: the state does not change).  The fastest
+ * becomes the configuration (graph_steps kept) and is written to *best (may be
+ * NULL); trials (may be NULL if max_trials is 0) receive up to max_trials of
+ * the timed shapes and *n_trials (may be NULL) their number.  Synchronises. */
+int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *best,
+                        lbm_vans_batch_config *trials, int32_t max_trials, int32_t *n_trials);
+
+/* Advance every member nsteps (>= 0) time steps (as lbm_vans_step).
+ * Asynchronous. */
+int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps);
+
+/* Bytes of grad_work for lbm_vans_batch_grad: the members' lbm_vans_grad
+ * workspaces, each rounded up to 256 bytes, back to back (0 if invalid). */
+size_t lbm_vans_batch_grad_work_bytes(const lbm_vans_batch *b, int32_t objective,
+                                      int64_t nsteps, int32_t ckpt_every);
+
+/* lbm_vans_grad for every member at once, each forward and reverse step one
+ * batched launch: dJdeps is a host array of nmembers device pointers (each
+ * [Ly][Lx] doubles of its member), J a host array of nmembers doubles or NULL.
+ * Afterwards every member is at state f(., nsteps).  Synchronises.  Returns
+ * LBM_VANS_ENONFINITE if a member's J is not finite. */
+int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
+                        int32_t ckpt_every, void *grad_work, size_t grad_work_bytes,
+                        double *const *dJdeps, double *J);
+
+/* Release the batch (waits for its stream; the members are untouched).
+ * NULL is ignored. */
+void lbm_vans_batch_destroy(lbm_vans_batch *b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbm_vans_last_error(void);

@@ -39,6 +39,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "lbm_vans.h"
 
@@ -581,14 +582,12 @@ __device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, in
 // post-collision populations of step n-1 (state n after streaming), fout
 // receives those of step n.  Used when Lx is not a multiple of the vector width.
 template <typename S, typename R, bool DIAG>
-__global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
-                                                    S *__restrict__ fout,
-                                                    const R *__restrict__ eps, Geo g,
-                                                    Phys<R> ph, double *__restrict__ part)
+__device__ __forceinline__ void sweep_tile(const S *__restrict__ fin, S *__restrict__ fout,
+                                           const R *__restrict__ eps, const Geo &g,
+                                           const Phys<R> &ph, double *__restrict__ part, int t)
 {
     constexpr int W = TX + 2;
     __shared__ R tile[TY + 2][W];
-    const int t = xcd_tile(blockIdx.x, g.ntiles);
     const int bx = t % g.nbx, by = t / g.nbx;
     const int x0 = bx * TX, y0 = by * TY;
     load_eps_tile<R, W>(tile, eps, g, x0, y0);
@@ -616,6 +615,15 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
         }
     }
     if constexpr (DIAG) block_partial(acc, part, t);
+}
+
+template <typename S, typename R, bool DIAG>
+__global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
+                                                    S *__restrict__ fout,
+                                                    const R *__restrict__ eps, Geo g,
+                                                    Phys<R> ph, double *__restrict__ part)
+{
+    sweep_tile<S, R, DIAG>(fin, fout, eps, g, ph, part, xcd_tile(blockIdx.x, g.ntiles));
 }
 
 // ---- vector sweep: V consecutive nodes per lane, full-width loads and stores
@@ -803,14 +811,13 @@ __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], in
 // barrier.  The same node update as the scalar sweep then runs per node, and
 // the 9 results leave as aligned vector stores.
 template <typename S, typename R, int V, int BX, bool WY, bool DIAG>
-__global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fin,
-                                                        S *__restrict__ fout,
-                                                        const R *__restrict__ eps, Geo g,
-                                                        Phys<R> ph, double *__restrict__ part)
+__device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__restrict__ fout,
+                                               const R *__restrict__ eps, const Geo &g,
+                                               const Phys<R> &ph, double *__restrict__ part,
+                                               int t)
 {
     constexpr int W = TX * V + 2;
     __shared__ R tile[TY + 2][W];
-    const int t = xcd_tile(blockIdx.x, g.ntiles);
     const int bx = t % g.nbx, by = t / g.nbx;
     const int x0 = bx * TX * V, y0 = by * TY;
     const int lane = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -859,6 +866,16 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
         }
     }
     if constexpr (DIAG) block_partial(acc, part, t);
+}
+
+template <typename S, typename R, int V, int BX, bool WY, bool DIAG>
+__global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fin,
+                                                        S *__restrict__ fout,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        Phys<R> ph, double *__restrict__ part)
+{
+    sweep_vec_tile<S, R, V, BX, WY, DIAG>(fin, fout, eps, g, ph, part,
+                                          xcd_tile(blockIdx.x, g.ntiles));
 }
 
 // Macroscopic fields of the current state (no collision, no store of
@@ -1181,18 +1198,16 @@ __device__ __forceinline__ void node_vjp(const R d[9], R e0, R gex, R gey, const
 // The seed computes J = sum over x = Lx-1 of eps rho u_x of the state n (tile
 // partials in part) and the adjoint of the state from it.
 template <typename S, typename R, bool SEED>
-__global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
-                                                      const R *__restrict__ lam_next,
-                                                      R *__restrict__ lam,
-                                                      const R *__restrict__ eps, Geo g,
-                                                      Phys<R> ph, double *__restrict__ eb,
-                                                      double *__restrict__ gxb,
-                                                      double *__restrict__ gyb,
-                                                      double *__restrict__ part)
+__device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
+                                             const R *__restrict__ lam_next,
+                                             R *__restrict__ lam, const R *__restrict__ eps,
+                                             const Geo &g, const Phys<R> &ph,
+                                             double *__restrict__ eb, double *__restrict__ gxb,
+                                             double *__restrict__ gyb,
+                                             double *__restrict__ part, int t)
 {
     constexpr int W = TX + 2;
     __shared__ R tile[TY + 2][W];
-    const int t = blockIdx.x;
     const int bx = t % g.nbx, by = t / g.nbx;
     const int x0 = bx * TX, y0 = by * TY;
     load_eps_tile<R, W>(tile, eps, g, x0, y0);
@@ -1266,6 +1281,19 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
         gyb[c] += static_cast<double>(gy_b);
     }
     if constexpr (SEED) block_partial(acc, part, t);
+}
+
+template <typename S, typename R, bool SEED>
+__global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
+                                                      const R *__restrict__ lam_next,
+                                                      R *__restrict__ lam,
+                                                      const R *__restrict__ eps, Geo g,
+                                                      Phys<R> ph, double *__restrict__ eb,
+                                                      double *__restrict__ gxb,
+                                                      double *__restrict__ gyb,
+                                                      double *__restrict__ part)
+{
+    adjoint_tile<S, R, SEED>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, part, blockIdx.x);
 }
 
 // Initial state: f_i(r, 0) = w_i eps(r) rho0 (1 + 3 e_i.u0 + 9/2 (e_i.u0)^2 -
@@ -1362,6 +1390,117 @@ __global__ __launch_bounds__(NTHREADS) void k_zero(double *__restrict__ p, long 
 {
     const long long i = static_cast<long long>(blockIdx.x) * NTHREADS + threadIdx.x;
     if (i < n) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Ensembles: many independent problems in one launch
+// ---------------------------------------------------------------------------
+// The tiles of all members are numbered into one list (member by member, each
+// in its own row-major tile order).  A device table maps a list position to
+// its member, whose descriptor gives the geometry, physics and buffers.  The
+// members share the storage type and the boundary kinds (one kernel template);
+// everything else (size, tau, drag, forcing, reservoirs) is per member.
+
+template <typename R>
+struct Member {
+    Geo gs;                 // tiling of the batched sweep (vec nodes per lane)
+    Geo g;                  // one node per lane (adjoint)
+    Phys<R> ph;
+    char *buf[2];           // the member's two population buffers (state slots 0, 1)
+    const R *eps;           // padded porosity
+    double *part;           // tile partials [g.ntiles][NRED]
+    char *gw;               // gradient workspace: state slots 2.., adjoints, accumulators
+    long long gpop, glam, gacc;
+    int nslot;              // state slots in gw (checkpoints + recomputed segment)
+    int vec;                // nodes per lane of this member's sweep
+    int tile0;              // first position in the sweep tile list of its width
+    int tile0_adj;          // first position in the adjoint tile list
+};
+
+template <typename R>
+__device__ __forceinline__ char *state_slot(const Member<R> &d, int slot)
+{
+    return slot < 2 ? d.buf[slot] : d.gw + (long long)(slot - 2) * d.gpop;
+}
+
+template <typename R>
+__device__ __forceinline__ R *adj_buf(const Member<R> &d, int a)
+{
+    return reinterpret_cast<R *>(d.gw + (long long)d.nslot * d.gpop + a * d.glam);
+}
+
+template <typename R>
+__device__ __forceinline__ double *acc_buf(const Member<R> &d, int k)
+{
+    return reinterpret_cast<double *>(d.gw + (long long)d.nslot * d.gpop + 2 * d.glam +
+                                      k * d.gacc);
+}
+
+// Positions of the tile list this block takes: one position when the grid
+// covers the list (XCD-banded as in the single sweep), else a persistent walk
+// in which the blocks of each XCD share that XCD's band of the list.
+struct TileWalk {
+    int first, end, stride;
+};
+
+__device__ __forceinline__ TileWalk tile_walk(int ntiles)
+{
+    TileWalk w;
+    if ((int)gridDim.x >= ntiles) {
+        w.first = xcd_tile(blockIdx.x, ntiles);
+        w.end = w.first + 1;
+        w.stride = 1;
+        return w;
+    }
+    const int per = gridDim.x / NXCD;
+    const int xcd = blockIdx.x % NXCD, k = blockIdx.x / NXCD;
+    const int q = ntiles / NXCD, r = ntiles % NXCD;
+    const int start = xcd * q + min(xcd, r);
+    w.first = start + k;
+    w.end = start + q + (xcd < r ? 1 : 0);
+    w.stride = per;
+    return w;
+}
+
+// One time step of the members of one vector width V, from state slot src to
+// state slot dst (tmap: their part of the tile list).
+template <typename S, typename R, int V, int BX, bool WY>
+__global__ __launch_bounds__(NTHREADS) void k_batch_sweep(const Member<R> *__restrict__ M,
+                                                          const int *__restrict__ tmap,
+                                                          int ntiles, int src, int dst,
+                                                          int reservoir)
+{
+    const TileWalk w = tile_walk(ntiles);
+    for (int T = w.first; T < w.end; T += w.stride) {
+        const Member<R> &d = M[tmap[T]];
+        const Geo gs = d.gs;
+        Phys<R> ph = d.ph;
+        ph.reservoir = reservoir;
+        sweep_vec_tile<S, R, V, BX, WY, false>(
+            reinterpret_cast<const S *>(state_slot(d, src)),
+            reinterpret_cast<S *>(state_slot(d, dst)), d.eps, gs, ph, nullptr, T - d.tile0);
+        __syncthreads();  // a next tile of this block reuses the LDS porosity tile
+    }
+}
+
+// One reverse step of every member: adjoint slot a_next (of the state n + 1)
+// to adjoint slot a (of the state n, read from state slot src); the seed
+// starts the adjoints from the objective of the state in src.
+template <typename S, typename R, bool SEED>
+__global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__restrict__ M,
+                                                            const int *__restrict__ tmap,
+                                                            int ntiles, int src, int a_next,
+                                                            int a, int reservoir)
+{
+    const int T = xcd_tile(blockIdx.x, ntiles);
+    const Member<R> &d = M[tmap[T]];
+    const Geo g = d.g;
+    Phys<R> ph = d.ph;
+    ph.reservoir = reservoir;
+    adjoint_tile<S, R, SEED>(reinterpret_cast<const S *>(state_slot(d, src)),
+                             SEED ? nullptr : adj_buf(d, a_next), adj_buf(d, a), d.eps, g, ph,
+                             acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), d.part,
+                             T - d.tile0_adj);
 }
 
 }  // namespace
@@ -1931,6 +2070,574 @@ void lbm_vans_destroy(lbm_vans_handle *h)
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     delete h;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ensembles (host side)
+// ---------------------------------------------------------------------------
+
+struct lbm_vans_batch {
+    std::vector<lbm_vans_handle *> m;
+    hipStream_t stream = nullptr;   // the caller's stream: every batched launch
+    hipStream_t cap = nullptr;      // private stream used only to capture step graphs
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int storage = 0, bx = 0, wy = 0, vmax = 4;
+    lbm_vans_batch_config cfg{};
+    size_t desc_bytes = 0;          // bytes of one device descriptor
+    std::vector<char> desc;         // host image of the descriptors
+    std::vector<int> tmap, tmap_adj;  // sweep list grouped by width (4, 2, 1); adjoint list
+    int grp_off[3] = {0, 0, 0}, grp_n[3] = {0, 0, 0};  // sweep list part of width 4, 2, 1
+    void *d_desc = nullptr;
+    int *d_tmap = nullptr, *d_tmap_adj = nullptr;
+    int ntiles = 0, ntiles_adj = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // chunk of cfg.graph_steps steps from slot 0 / 1
+};
+
+namespace {
+
+size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj)
+{
+    const size_t d = storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
+    return align256(nmembers * d) + 2 * align256(ntiles_adj * sizeof(int));
+}
+
+void drop_graphs(lbm_vans_batch *b)
+{
+    for (auto &gx : b->graph)
+        if (gx) {
+            (void)hipGraphExecDestroy(gx);
+            gx = nullptr;
+        }
+}
+
+// Nodes per lane of a member's sweep: the largest power of two up to vec
+// that divides Lx.
+int member_vec(const lbm_vans_params *p, int vec)
+{
+    int v = vec;
+    while (v > 1 && p->Lx % v) v /= 2;
+    return v;
+}
+
+// Descriptors and tile lists for a sweep width of vec nodes per lane, plus the
+// gradient workspace layout when gw is given; uploaded to the batch's table.
+int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t ckpt_every)
+{
+    const size_t nm = b->m.size();
+    b->tmap.clear();
+    b->tmap_adj.clear();
+    int rc = with_types(b->storage, [&](auto *sp, auto *rp) -> int {
+        using R = std::remove_pointer_t<decltype(rp)>;
+        (void)sp;
+        b->desc_bytes = sizeof(Member<R>);
+        b->desc.assign(nm * sizeof(Member<R>), 0);
+        std::vector<Member<R>> D(nm);
+        for (size_t k = 0; k < nm; k++) {
+            lbm_vans_handle *h = b->m[k];
+            Member<R> &d = D[k];
+            std::memset(&d, 0, sizeof d);
+            d.vec = member_vec(&h->p, vec);
+            d.gs = make_geo(&h->p, d.vec);
+            d.g = h->g;
+            d.ph = make_phys<R>(&h->p);
+            d.buf[0] = h->buf[0];
+            d.buf[1] = h->buf[1];
+            d.eps = static_cast<const R *>(h->eps);
+            d.part = h->part;
+            d.tile0_adj = static_cast<int>(b->tmap_adj.size());
+            b->tmap_adj.insert(b->tmap_adj.end(), d.g.ntiles, static_cast<int>(k));
+        }
+        // sweep list: the members of width 4, then 2, then 1, each part in member order
+        for (int gi = 0; gi < 3; gi++) {
+            const int vw = 4 >> gi;
+            b->grp_off[gi] = static_cast<int>(b->tmap.size());
+            for (size_t k = 0; k < nm; k++) {
+                if (D[k].vec != vw) continue;
+                D[k].tile0 = static_cast<int>(b->tmap.size()) - b->grp_off[gi];
+                b->tmap.insert(b->tmap.end(), D[k].gs.ntiles, static_cast<int>(k));
+            }
+            b->grp_n[gi] = static_cast<int>(b->tmap.size()) - b->grp_off[gi];
+        }
+        size_t off = 0;
+        for (size_t k = 0; k < nm; k++) {
+            lbm_vans_handle *h = b->m[k];
+            Member<R> &d = D[k];
+            if (gw) {
+                const GradLayout G = grad_layout(&h->p, nsteps, ckpt_every);
+                d.gw = gw + off;
+                d.gpop = static_cast<long long>(G.pop);
+                d.glam = static_cast<long long>(G.lam);
+                d.gacc = static_cast<long long>(G.acc);
+                d.nslot = static_cast<int>(G.nck + G.seg);
+                off += align256(G.total);
+            }
+            std::memcpy(b->desc.data() + k * sizeof d, &d, sizeof d);
+        }
+        return LBM_VANS_OK;
+    });
+    if (rc) return rc;
+    b->ntiles = static_cast<int>(b->tmap.size());
+    b->ntiles_adj = static_cast<int>(b->tmap_adj.size());
+    HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size(), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_tmap, b->tmap.data(), b->tmap.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_tmap_adj, b->tmap_adj.data(), b->tmap_adj.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream));
+    // the host images must outlive the copies; they also must not change under them
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return LBM_VANS_OK;
+}
+
+template <typename S, typename R, int V>
+void batch_sweep_v(const lbm_vans_batch *b, hipStream_t st, int gi, int src, int dst,
+                   int reservoir)
+{
+    const int n = b->grp_n[gi];
+    const int grid = (b->cfg.grid > 0 && b->cfg.grid < n) ? b->cfg.grid : n;
+    const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
+    const int *tm = b->d_tmap + b->grp_off[gi];
+#define LBM_VANS_BATCH(BXV, WYV)                                                             \
+    hipLaunchKernelGGL((k_batch_sweep<S, R, V, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, st, \
+                       M, tm, n, src, dst, reservoir)
+    if (b->bx == 0 && !b->wy) LBM_VANS_BATCH(0, false);
+    else if (b->bx == 0) LBM_VANS_BATCH(0, true);
+    else if (b->bx == 1 && !b->wy) LBM_VANS_BATCH(1, false);
+    else if (b->bx == 1) LBM_VANS_BATCH(1, true);
+    else if (!b->wy) LBM_VANS_BATCH(2, false);
+    else LBM_VANS_BATCH(2, true);
+#undef LBM_VANS_BATCH
+}
+
+// One batched step on stream st: every member from state slot src to dst,
+// one launch per vector width present among the members.
+int batch_sweep(lbm_vans_batch *b, hipStream_t st, int src, int dst, int reservoir)
+{
+    return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        if constexpr (sizeof(S) != 8) {
+            if (b->grp_n[0] > 0) batch_sweep_v<S, R, 4>(b, st, 0, src, dst, reservoir);
+        }
+        if (b->grp_n[1] > 0) batch_sweep_v<S, R, 2>(b, st, 1, src, dst, reservoir);
+        if (b->grp_n[2] > 0) batch_sweep_v<S, R, 1>(b, st, 2, src, dst, reservoir);
+        return check_launch("k_batch_sweep");
+    });
+}
+
+int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir)
+{
+    return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
+        if (seed)
+            hipLaunchKernelGGL((k_batch_adjoint<S, R, true>), dim3(b->ntiles_adj),
+                               dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
+                               b->ntiles_adj, src, a_next, a, reservoir);
+        else
+            hipLaunchKernelGGL((k_batch_adjoint<S, R, false>), dim3(b->ntiles_adj),
+                               dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
+                               b->ntiles_adj, src, a_next, a, reservoir);
+        return check_launch("k_batch_adjoint");
+    });
+}
+
+// Capture cfg.graph_steps steps starting from slot s0 (all with the
+// reservoirs active, i.e. from a state n >= 1) into an executable graph.
+int batch_capture(lbm_vans_batch *b, int s0)
+{
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = LBM_VANS_OK;
+    for (int j = 0; j < b->cfg.graph_steps && !rc; j++) {
+        const int src = (s0 + j) & 1;
+        rc = batch_sweep(b, b->cap, src, 1 - src, 1);
+    }
+    hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return fail(LBM_VANS_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph[s0], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        b->graph[s0] = nullptr;
+        return fail(LBM_VANS_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    return LBM_VANS_OK;
+}
+
+int check_config(const lbm_vans_batch *b, const lbm_vans_batch_config *c)
+{
+    if (!c) return fail(LBM_VANS_EINVAL, "config is NULL");
+    if (c->vec < 1 || c->vec > b->vmax || (c->vec & (c->vec - 1)))
+        return fail(LBM_VANS_EINVAL, "vec = %d: a power of two up to %d", c->vec, b->vmax);
+    if (c->grid < 0 || c->grid % NXCD)
+        return fail(LBM_VANS_EINVAL, "grid = %d: 0 or a positive multiple of %d", c->grid, NXCD);
+    if (c->graph_steps < 0 || c->graph_steps % 2)
+        return fail(LBM_VANS_EINVAL, "graph_steps = %d: 0 or a positive even number",
+                    c->graph_steps);
+    return LBM_VANS_OK;
+}
+
+// The members must still be in step with each other (a member may have been
+// stepped on its own in between).
+int batch_in_step(const lbm_vans_batch *b)
+{
+    for (lbm_vans_handle *h : b->m)
+        if (h->n != b->m[0]->n || h->cur != b->m[0]->cur)
+            return fail(LBM_VANS_EINVAL,
+                        "batch members are at different steps (%lld and %lld)",
+                        (long long)h->n, (long long)b->m[0]->n);
+    return LBM_VANS_OK;
+}
+
+void batch_advance(lbm_vans_batch *b, int64_t steps)
+{
+    for (lbm_vans_handle *h : b->m) {
+        h->n += steps;
+        if (steps & 1) h->cur = 1 - h->cur;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembers)
+{
+    if (!members || nmembers < 1) return 0;
+    size_t tiles = 0;
+    for (int32_t k = 0; k < nmembers; k++) {
+        if (!members[k]) return 0;
+        tiles += static_cast<size_t>(members[k]->g.ntiles);
+    }
+    return batch_table_bytes(members[0]->p.storage, nmembers, tiles);
+}
+
+int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
+                          size_t work_bytes, void *stream, lbm_vans_batch **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(LBM_VANS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!members || nmembers < 1) return fail(LBM_VANS_EINVAL, "no members");
+    const lbm_vans_handle *h0 = members[0];
+    if (!h0) return fail(LBM_VANS_EINVAL, "member 0 is NULL");
+    size_t tiles = 0;
+    for (int32_t k = 0; k < nmembers; k++) {
+        const lbm_vans_handle *h = members[k];
+        if (!h) return fail(LBM_VANS_EINVAL, "member %d is NULL", k);
+        for (int32_t j = 0; j < k; j++)
+            if (members[j] == h) return fail(LBM_VANS_EINVAL, "member %d repeats member %d", k, j);
+        if (h->p.storage != h0->p.storage || h->p.bc_x != h0->p.bc_x || h->p.bc_y != h0->p.bc_y)
+            return fail(LBM_VANS_EINVAL,
+                        "member %d differs from member 0 in storage or boundary kinds", k);
+        if (h->p.diag_every != 0)
+            return fail(LBM_VANS_EINVAL, "member %d records diagnostics (diag_every = %d); "
+                        "batched steps do not", k, h->p.diag_every);
+        if (h->n != h0->n || h->cur != h0->cur)
+            return fail(LBM_VANS_EINVAL, "member %d is at step %lld, member 0 at %lld", k,
+                        (long long)h->n, (long long)h0->n);
+        tiles += static_cast<size_t>(h->g.ntiles);
+    }
+    if (tiles > static_cast<size_t>(INT32_MAX))
+        return fail(LBM_VANS_EINVAL, "%zu tiles: too many for one launch", tiles);
+    if (!work || reinterpret_cast<uintptr_t>(work) % 256)
+        return fail(LBM_VANS_EINVAL, "work must be a 256-byte aligned device buffer");
+    const size_t need = batch_table_bytes(h0->p.storage, nmembers, tiles);
+    if (work_bytes < need)
+        return fail(LBM_VANS_EINVAL, "work has %zu bytes, %zu needed", work_bytes, need);
+
+    lbm_vans_batch *b = new (std::nothrow) lbm_vans_batch();
+    if (!b) return fail(LBM_VANS_EINVAL, "out of host memory");
+    b->m.assign(members, members + nmembers);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->storage = h0->p.storage;
+    b->bx = h0->g.open_x ? 2 : (h0->g.wall_x ? 1 : 0);
+    b->wy = h0->g.wall_y;
+    b->vmax = b->storage == LBM_F64 ? 2 : 4;
+    const size_t dsz = b->storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
+    char *w = static_cast<char *>(work);
+    b->d_desc = w;
+    b->d_tmap = reinterpret_cast<int *>(w + align256(nmembers * dsz));
+    b->d_tmap_adj = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
+                                            align256(tiles * sizeof(int)));
+    b->cfg.vec = b->vmax;
+    b->cfg.grid = 0;
+    b->cfg.graph_steps = 16;
+    int rc = LBM_VANS_OK;
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev[1]);
+    if (e != hipSuccess) rc = fail(LBM_VANS_EHIP, "stream / event creation failed: %s",
+                                   hipGetErrorString(e));
+    if (!rc) rc = batch_upload(b, b->cfg.vec, nullptr, 0, 1);
+    if (rc) {
+        lbm_vans_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBM_VANS_OK;
+}
+
+int lbm_vans_batch_configure(lbm_vans_batch *b, const lbm_vans_batch_config *cfg)
+{
+    if (!b) return fail(LBM_VANS_EINVAL, "batch is NULL");
+    int rc = check_config(b, cfg);
+    if (rc) return rc;
+    drop_graphs(b);
+    b->cfg = *cfg;
+    b->cfg.us_per_step = 0.0;
+    return batch_upload(b, b->cfg.vec, nullptr, 0, 1);
+}
+
+int lbm_vans_batch_get_config(const lbm_vans_batch *b, lbm_vans_batch_config *cfg)
+{
+    if (!b || !cfg) return fail(LBM_VANS_EINVAL, "batch or cfg is NULL");
+    *cfg = b->cfg;
+    return LBM_VANS_OK;
+}
+
+int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *best,
+                        lbm_vans_batch_config *trials, int32_t max_trials, int32_t *n_trials)
+{
+    if (!b) return fail(LBM_VANS_EINVAL, "batch is NULL");
+    if (reps < 1) return fail(LBM_VANS_EINVAL, "reps = %d < 1", reps);
+    if (max_trials > 0 && !trials) return fail(LBM_VANS_EINVAL, "trials is NULL");
+    int rc = batch_in_step(b);
+    if (rc) return rc;
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int src = b->m[0]->cur, dst = 1 - src, res = b->m[0]->n >= 1;
+    const lbm_vans_batch_config keep = b->cfg;
+    lbm_vans_batch_config top = keep;
+    top.us_per_step = INFINITY;
+    int nt = 0;
+    drop_graphs(b);
+    for (int vec = b->vmax; vec >= 1; vec /= 2) {
+        rc = batch_upload(b, vec, nullptr, 0, 1);
+        if (rc) return rc;
+        // one block per tile, then persistent grids of 1, 2, 4 and 8 blocks per CU
+        const int grids[5] = {0, ncu, 2 * ncu, 4 * ncu, 8 * ncu};
+        for (int gi = 0; gi < 5; gi++) {
+            const int grid = grids[gi] / NXCD * NXCD;
+            if (gi > 0 && (grid < NXCD || grid >= b->ntiles)) continue;
+            b->cfg.vec = vec;
+            b->cfg.grid = grid;
+            // the state in slot src is only read, so the trials leave it unchanged
+            rc = batch_sweep(b, b->stream, src, dst, res);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+            for (int r = 0; r < reps && !rc; r++) rc = batch_sweep(b, b->stream, src, dst, res);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(b->ev[1], b->stream));
+            HIP_TRY(hipEventSynchronize(b->ev[1]));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+            b->cfg.us_per_step = 1000.0 * ms / reps;
+            if (nt < max_trials) trials[nt] = b->cfg;
+            nt++;
+            if (b->cfg.us_per_step < top.us_per_step) top = b->cfg;
+        }
+    }
+    if (n_trials) *n_trials = nt;
+    top.graph_steps = keep.graph_steps;
+    b->cfg = top;
+    if (best) *best = top;
+    return batch_upload(b, top.vec, nullptr, 0, 1);
+}
+
+int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps)
+{
+    if (!b) return fail(LBM_VANS_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(LBM_VANS_EINVAL, "nsteps = %lld < 0", (long long)nsteps);
+    int rc = batch_in_step(b);
+    if (rc) return rc;
+    const int C = b->cfg.graph_steps;
+    int64_t k = 0;
+    while (k < nsteps) {
+        const int cur = b->m[0]->cur;
+        const int64_t n = b->m[0]->n;
+        if (C > 0 && n >= 1 && nsteps - k >= C) {
+            if (!b->graph[cur]) {
+                rc = batch_capture(b, cur);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(b->graph[cur], b->stream));
+            batch_advance(b, C);
+            k += C;
+        } else {
+            rc = batch_sweep(b, b->stream, cur, 1 - cur, n >= 1);
+            if (rc) return rc;
+            batch_advance(b, 1);
+            k += 1;
+        }
+    }
+    return LBM_VANS_OK;
+}
+
+size_t lbm_vans_batch_grad_work_bytes(const lbm_vans_batch *b, int32_t objective,
+                                      int64_t nsteps, int32_t ckpt_every)
+{
+    if (!b) return 0;
+    size_t total = 0;
+    for (const lbm_vans_handle *h : b->m) {
+        if (check_grad_args(&h->p, objective, nsteps, ckpt_every)) return 0;
+        total += align256(grad_layout(&h->p, nsteps, ckpt_every).total);
+    }
+    return total;
+}
+
+int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
+                        int32_t ckpt_every, void *grad_work, size_t grad_work_bytes,
+                        double *const *dJdeps, double *J)
+{
+    if (!b) return fail(LBM_VANS_EINVAL, "batch is NULL");
+    for (const lbm_vans_handle *h : b->m) {
+        int rc = check_grad_args(&h->p, objective, nsteps, ckpt_every);
+        if (rc) return rc;
+    }
+    if (!grad_work || !dJdeps) return fail(LBM_VANS_EINVAL, "grad_work and dJdeps are required");
+    for (size_t k = 0; k < b->m.size(); k++)
+        if (!dJdeps[k]) return fail(LBM_VANS_EINVAL, "dJdeps[%zu] is NULL", k);
+    if (reinterpret_cast<uintptr_t>(grad_work) % 256)
+        return fail(LBM_VANS_EINVAL, "grad_work must be 256-byte aligned");
+    const size_t need = lbm_vans_batch_grad_work_bytes(b, objective, nsteps, ckpt_every);
+    if (grad_work_bytes < need)
+        return fail(LBM_VANS_EINVAL, "grad_work has %zu bytes, %zu needed", grad_work_bytes,
+                    need);
+    const int K = ckpt_every;
+    const int64_t nck_slots = std::max<int64_t>(1, (nsteps + K - 1) / K);
+    if (nck_slots + K + 2 > INT32_MAX) return fail(LBM_VANS_EINVAL, "too many state slots");
+    auto ckpt_slot = [&](int64_t c) { return static_cast<int>(2 + c); };
+    auto seg_slot = [&](int64_t j) { return static_cast<int>(2 + nck_slots + j); };
+    drop_graphs(b);
+    int rc = batch_upload(b, b->cfg.vec, static_cast<char *>(grad_work), nsteps, ckpt_every);
+    if (rc) return rc;
+    std::vector<GradLayout> G;
+    std::vector<char *> gw;
+    size_t off = 0;
+    for (lbm_vans_handle *h : b->m) {
+        G.push_back(grad_layout(&h->p, nsteps, ckpt_every));
+        gw.push_back(static_cast<char *>(grad_work) + off);
+        off += align256(G.back().total);
+    }
+    std::vector<double> rec(b->m.size() * NRED);
+    rc = with_types(b->storage, [&](auto *sp, auto *rp) -> int {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        // 1. every member back to its initial state; forward with checkpoints
+        for (lbm_vans_handle *h : b->m) {
+            const Phys<R> ph0 = make_phys<R>(&h->p);
+            hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                               b->stream, (S *)h->buf[0], (const R *)h->eps, h->g, h->p.rho0,
+                               static_cast<double>(ph0.rho0), h->p.u0[0], h->p.u0[1],
+                               (const double *)nullptr, ph0.scale);
+            int r = check_launch("k_set_state");
+            if (r) return r;
+            h->cur = 0;
+            h->n = 0;
+        }
+        int r;
+        for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += K) {
+            for (size_t k = 0; k < b->m.size(); k++) {
+                lbm_vans_handle *h = b->m[k];
+                HIP_TRY(hipMemcpyAsync(gw[k] + (s0 / K) * G[k].pop, h->buf[h->cur], G[k].pop,
+                                       hipMemcpyDeviceToDevice, b->stream));
+            }
+            for (int64_t j = 0; j < K && s0 + j < nsteps; j++) {
+                const int cur = b->m[0]->cur;
+                r = batch_sweep(b, b->stream, cur, 1 - cur, b->m[0]->n >= 1);
+                if (r) return r;
+                batch_advance(b, 1);
+            }
+            if (nsteps == 0) break;
+        }
+        // 2. seed: J of the state nsteps and the adjoint of that state
+        for (size_t k = 0; k < b->m.size(); k++) {
+            double *eb = reinterpret_cast<double *>(gw[k] + (G[k].nck + G[k].seg) * G[k].pop +
+                                                    2 * G[k].lam);
+            const long long nz = (long long)(3 * G[k].acc / sizeof(double));
+            hipLaunchKernelGGL(k_zero, dim3((unsigned)((nz + NTHREADS - 1) / NTHREADS)),
+                               dim3(NTHREADS), 0, b->stream, eb, nz);
+            r = check_launch("k_zero");
+            if (r) return r;
+        }
+        int a = 0;
+        r = batch_adjoint(b, true, b->m[0]->cur, 0, a, nsteps >= 1);
+        if (r) return r;
+        for (size_t k = 0; k < b->m.size(); k++) {
+            lbm_vans_handle *h = b->m[k];
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, b->stream,
+                               (const double *)h->part, h->ntiles, (const double *)nullptr,
+                               static_cast<double>(nsteps), h->scratch_rec);
+            r = check_launch("k_finalize");
+            if (r) return r;
+            HIP_TRY(hipMemcpyAsync(rec.data() + k * NRED, h->scratch_rec, NRED * sizeof(double),
+                                   hipMemcpyDeviceToHost, b->stream));
+        }
+        // 3. reverse, one checkpoint segment at a time (states recomputed)
+        const int64_t nck = nsteps == 0 ? 0 : (nsteps + K - 1) / K;
+        for (int64_t c = nck - 1; c >= 0; c--) {
+            const int64_t s0 = c * K, s1 = std::min<int64_t>(s0 + K, nsteps);
+            for (int64_t j = 1; j < s1 - s0; j++) {
+                const int src = j == 1 ? ckpt_slot(c) : seg_slot(j - 1);
+                r = batch_sweep(b, b->stream, src, seg_slot(j), (s0 + j - 1) >= 1);
+                if (r) return r;
+            }
+            for (int64_t n = s1 - 1; n >= s0; n--) {
+                const int state = n == s0 ? ckpt_slot(c) : seg_slot(n - s0);
+                r = batch_adjoint(b, false, state, a, 1 - a, n >= 1);
+                if (r) return r;
+                a = 1 - a;
+            }
+        }
+        // 4. initial state and the porosity stencil, member by member
+        for (size_t k = 0; k < b->m.size(); k++) {
+            lbm_vans_handle *h = b->m[k];
+            char *base = gw[k] + (G[k].nck + G[k].seg) * G[k].pop;
+            const R *lam = reinterpret_cast<const R *>(base + a * G[k].lam);
+            double *eb = reinterpret_cast<double *>(base + 2 * G[k].lam);
+            double *gxb = eb + G[k].acc / sizeof(double);
+            double *gyb = gxb + G[k].acc / sizeof(double);
+            hipLaunchKernelGGL((k_adjoint_init<R>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                               b->stream, lam, h->g, h->p.rho0, h->p.u0[0], h->p.u0[1], eb);
+            r = check_launch("k_adjoint_init");
+            if (r) return r;
+            hipLaunchKernelGGL(k_adjoint_finish, dim3(h->ntiles), dim3(NTHREADS), 0, b->stream,
+                               (const double *)eb, (const double *)gxb, (const double *)gyb,
+                               h->g, dJdeps[k]);
+            r = check_launch("k_adjoint_finish");
+            if (r) return r;
+        }
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        return LBM_VANS_OK;
+    });
+    if (rc) return rc;
+    for (size_t k = 0; k < b->m.size(); k++) {
+        if (J) J[k] = rec[k * NRED];
+        if (!std::isfinite(rec[k * NRED]))
+            return fail(LBM_VANS_ENONFINITE, "objective of member %zu is not finite", k);
+    }
+    return LBM_VANS_OK;
+}
+
+void lbm_vans_batch_destroy(lbm_vans_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    for (auto &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
 }
 
 }  // extern "C"

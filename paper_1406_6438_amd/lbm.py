@@ -27,13 +27,16 @@ F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
 DRAG_ERGUN, DRAG_CONST = 0, 1
 NDIAG = 8
 DIAG_RING = 4096
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
            "lbm_vans_moments", "lbm_vans_get_state", "lbm_vans_set_state",
            "lbm_vans_diag_read", "lbm_vans_grad_work_bytes", "lbm_vans_grad",
-           "lbm_vans_destroy", "lbm_vans_last_error", "lbm_vans_abi_version")
+           "lbm_vans_destroy", "lbm_vans_batch_work_bytes", "lbm_vans_batch_create",
+           "lbm_vans_batch_configure", "lbm_vans_batch_get_config", "lbm_vans_batch_tune",
+           "lbm_vans_batch_step", "lbm_vans_batch_grad_work_bytes", "lbm_vans_batch_grad",
+           "lbm_vans_batch_destroy", "lbm_vans_last_error", "lbm_vans_abi_version")
 OBJ_OUTLET_FLUX = 0
 
 STORAGE = {"f64": F64, "f32": F32_SHIFTED, "f16": F16_SHIFTED}
@@ -51,6 +54,16 @@ class LbmVansParams(ctypes.Structure):
         ("rho_in", ctypes.c_double), ("u_in", ctypes.c_double),
         ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double),
     ]
+
+
+class LbmVansBatchConfig(ctypes.Structure):
+    _fields_ = [("vec", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("us_per_step", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"vec": self.vec, "grid": self.grid, "graph_steps": self.graph_steps,
+                "us_per_step": self.us_per_step}
 
 
 @dataclasses.dataclass
@@ -119,11 +132,28 @@ def load(path: str = LIB_PATH):
     L.lbm_vans_grad.argtypes = [vp, i32, i64, i32, vp, ctypes.c_size_t, vp, dp]
     L.lbm_vans_destroy.argtypes = [vp]
     L.lbm_vans_destroy.restype = None
+    C = ctypes.POINTER(LbmVansBatchConfig)
+    L.lbm_vans_batch_work_bytes.argtypes = [ctypes.POINTER(vp), i32]
+    L.lbm_vans_batch_work_bytes.restype = ctypes.c_size_t
+    L.lbm_vans_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp,
+                                        ctypes.POINTER(vp)]
+    L.lbm_vans_batch_configure.argtypes = [vp, C]
+    L.lbm_vans_batch_get_config.argtypes = [vp, C]
+    L.lbm_vans_batch_tune.argtypes = [vp, i32, C, C, i32, ctypes.POINTER(i32)]
+    L.lbm_vans_batch_step.argtypes = [vp, i64]
+    L.lbm_vans_batch_grad_work_bytes.argtypes = [vp, i32, i64, i32]
+    L.lbm_vans_batch_grad_work_bytes.restype = ctypes.c_size_t
+    L.lbm_vans_batch_grad.argtypes = [vp, i32, i64, i32, vp, ctypes.c_size_t,
+                                      ctypes.POINTER(vp), dp]
+    L.lbm_vans_batch_destroy.argtypes = [vp]
+    L.lbm_vans_batch_destroy.restype = None
     L.lbm_vans_last_error.argtypes = []
     L.lbm_vans_last_error.restype = ctypes.c_char_p
     L.lbm_vans_abi_version.argtypes = []
     for n in ("lbm_vans_init", "lbm_vans_step", "lbm_vans_moments", "lbm_vans_get_state",
               "lbm_vans_set_state", "lbm_vans_diag_read", "lbm_vans_grad",
+              "lbm_vans_batch_create", "lbm_vans_batch_configure", "lbm_vans_batch_get_config",
+              "lbm_vans_batch_tune", "lbm_vans_batch_step", "lbm_vans_batch_grad",
               "lbm_vans_abi_version"):
         getattr(L, n).restype = ctypes.c_int
     if L.lbm_vans_abi_version() != ABI_VERSION:
@@ -213,6 +243,71 @@ def lbm_vans_destroy(h):
         load().lbm_vans_destroy(h)
 
 
+def _handles(members):
+    arr = (ctypes.c_void_p * len(members))(*[m.h.value for m in members])
+    return arr
+
+
+def lbm_vans_batch_work_bytes(members) -> int:
+    n = load().lbm_vans_batch_work_bytes(_handles(members), len(members))
+    if n == 0:
+        raise LbmVansError(EINVAL, "invalid batch members")
+    return n
+
+
+def lbm_vans_batch_create(members, work, stream) -> ctypes.c_void_p:
+    b = ctypes.c_void_p()
+    _check(load().lbm_vans_batch_create(_handles(members), len(members), work.data_ptr(),
+                                        work.numel() * work.element_size(), stream,
+                                        ctypes.byref(b)))
+    return b
+
+
+def lbm_vans_batch_configure(b, vec: int, grid: int, graph_steps: int):
+    c = LbmVansBatchConfig(vec, grid, graph_steps, 0, 0.0)
+    _check(load().lbm_vans_batch_configure(b, ctypes.byref(c)))
+
+
+def lbm_vans_batch_get_config(b) -> dict:
+    c = LbmVansBatchConfig()
+    _check(load().lbm_vans_batch_get_config(b, ctypes.byref(c)))
+    return c.as_dict()
+
+
+def lbm_vans_batch_tune(b, reps: int = 5, max_trials: int = 64):
+    best = LbmVansBatchConfig()
+    trials = (LbmVansBatchConfig * max_trials)()
+    n = ctypes.c_int32()
+    _check(load().lbm_vans_batch_tune(b, int(reps), ctypes.byref(best), trials, max_trials,
+                                      ctypes.byref(n)))
+    return best.as_dict(), [trials[k].as_dict() for k in range(min(n.value, max_trials))]
+
+
+def lbm_vans_batch_step(b, nsteps: int):
+    _check(load().lbm_vans_batch_step(b, int(nsteps)))
+
+
+def lbm_vans_batch_grad_work_bytes(b, objective: int, nsteps: int, ckpt_every: int) -> int:
+    n = load().lbm_vans_batch_grad_work_bytes(b, objective, int(nsteps), int(ckpt_every))
+    if n == 0:
+        raise LbmVansError(EINVAL, load().lbm_vans_last_error().decode())
+    return n
+
+
+def lbm_vans_batch_grad(b, objective: int, nsteps: int, ckpt_every: int, grad_work, dJdeps):
+    ptrs = (ctypes.c_void_p * len(dJdeps))(*[g.data_ptr() for g in dJdeps])
+    J = (ctypes.c_double * len(dJdeps))()
+    _check(load().lbm_vans_batch_grad(b, objective, int(nsteps), int(ckpt_every),
+                                      grad_work.data_ptr(),
+                                      grad_work.numel() * grad_work.element_size(), ptrs, J))
+    return list(J)
+
+
+def lbm_vans_batch_destroy(b):
+    if b:
+        load().lbm_vans_batch_destroy(b)
+
+
 class Solver:
     """One solver handle with torch-owned device memory on ``device``.
 
@@ -292,6 +387,64 @@ class Solver:
         if getattr(self, "h", None):
             lbm_vans_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many Solvers advanced together by batched launches (one per vector width
+    present, per step; captured into graphs).  The members stay usable as
+    Solvers (moments, get_state) between batch calls; all calls run on torch's
+    current stream of the members' device."""
+
+    def __init__(self, members):
+        import torch
+
+        self.torch = torch
+        self.members = list(members)
+        if not self.members:
+            raise ValueError("no members")
+        self.device = self.members[0].device
+        with torch.cuda.device(self.device):
+            nbytes = lbm_vans_batch_work_bytes(self.members)
+            self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+            self.b = lbm_vans_batch_create(self.members, self.work, self.stream.cuda_stream)
+
+    def configure(self, vec: int, grid: int = 0, graph_steps: int = 16):
+        lbm_vans_batch_configure(self.b, vec, grid, graph_steps)
+
+    @property
+    def config(self) -> dict:
+        return lbm_vans_batch_get_config(self.b)
+
+    def tune(self, reps: int = 5):
+        """Autotune the launch shape; returns (best, all trials) as dicts."""
+        return lbm_vans_batch_tune(self.b, reps)
+
+    def step(self, nsteps: int):
+        lbm_vans_batch_step(self.b, nsteps)
+
+    def grad(self, nsteps: int, ckpt_every: int, objective: int = OBJ_OUTLET_FLUX):
+        """(list of J, list of float64 dJ/deps tensors) for every member."""
+        t = self.torch
+        nbytes = lbm_vans_batch_grad_work_bytes(self.b, objective, nsteps, ckpt_every)
+        with t.cuda.device(self.device):
+            gw = t.empty(nbytes, dtype=t.uint8, device=self.device)
+            gs = [t.empty((m.p.Ly, m.p.Lx), dtype=t.float64, device=self.device)
+                  for m in self.members]
+            J = lbm_vans_batch_grad(self.b, objective, nsteps, ckpt_every, gw, gs)
+            del gw
+        return J, gs
+
+    def close(self):
+        if getattr(self, "b", None):
+            lbm_vans_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

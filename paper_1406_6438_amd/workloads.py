@@ -139,3 +139,49 @@ ADJOINT_CHANNEL = Workload(
     walls_y=True, storage="f32", eps_kind="grf", eps_lo=0.4, eps_hi=1.0, seed=SEED + 1)
 ADJOINT_U_IN = 0.02
 ADJOINT_CKPT = 200
+
+# Ensemble of independent porous channels advanced together: 64 members, each
+# with Lx drawn uniformly from the integers 256..2048 and Ly = Lx // 2 (aspect
+# 2:1), tau drawn uniformly from [0.55, 1.0] (both from PCG64(ENSEMBLE_SEED)),
+# its own GRF porosity in [0.3, 1.0] (l = 16, seed ENSEMBLE_SEED + 1 + k),
+# half-way bounce-back walls in y, open x ends with inflow and outflow
+# reservoirs at density 1 and x-velocity 0.02, plug-flow start, d_p from
+# Da = 1e-2 on the member's width at porosity 0.65, no body force, FP32,
+# 2000 steps.  The gradient of each member's outlet flux uses a checkpoint
+# every 45 steps (about sqrt(2000), which minimises checkpoints + segment).
+ENSEMBLE_SEED = SEED + 2
+ENSEMBLE_MEMBERS = 64
+ENSEMBLE_STEPS = 2000
+ENSEMBLE_CKPT = 45
+ENSEMBLE_U = 0.02
+
+
+@dataclasses.dataclass(frozen=True)
+class Member:
+    """One channel of an ensemble."""
+    Lx: int
+    Ly: int
+    tau: float
+    d_p: float
+    seed: int
+    eps_lo: float = 0.3
+    eps_hi: float = 1.0
+    ell: float = 16.0
+
+    def porosity(self) -> np.ndarray:
+        return grf_porosity(self.Lx, self.Ly, self.seed, self.ell, self.eps_lo, self.eps_hi)
+
+
+def ensemble(n: int = ENSEMBLE_MEMBERS, lmin: int = 256, lmax: int = 2048,
+             seed: int = ENSEMBLE_SEED) -> list:
+    """The members of an ensemble of n channels with Lx in [lmin, lmax]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Lx = rng.integers(lmin, lmax + 1, size=n)
+    tau = rng.uniform(0.55, 1.0, size=n)
+    out = []
+    for k in range(n):
+        lx = int(Lx[k])
+        ly = max(lx // 2, 1)
+        out.append(Member(Lx=lx, Ly=ly, tau=float(tau[k]),
+                          d_p=ergun_dp_for_darcy(1e-2, float(ly), 0.65), seed=seed + 1 + k))
+    return out

@@ -111,6 +111,26 @@ def test_null_handle_calls_fail_cleanly():
     assert n1 >= (10 + 10) * pop and n2 >= (2 + 50) * pop
 
 
+def test_null_batch_calls_fail_cleanly():
+    L = lbm.load()
+    out = ctypes.c_void_p()
+    assert L.lbm_vans_batch_work_bytes(None, 0) == 0
+    assert L.lbm_vans_batch_create(None, 0, None, 0, None, ctypes.byref(out)) == lbm.EINVAL
+    assert out.value is None
+    no_members = (ctypes.c_void_p * 2)(None, None)
+    assert L.lbm_vans_batch_work_bytes(no_members, 2) == 0
+    assert L.lbm_vans_batch_create(no_members, 2, None, 0, None, ctypes.byref(out)) == lbm.EINVAL
+    assert b"NULL" in L.lbm_vans_last_error()
+    cfg = lbm.LbmVansBatchConfig(4, 0, 16, 0, 0.0)
+    assert L.lbm_vans_batch_configure(None, ctypes.byref(cfg)) == lbm.EINVAL
+    assert L.lbm_vans_batch_get_config(None, ctypes.byref(cfg)) == lbm.EINVAL
+    assert L.lbm_vans_batch_tune(None, 3, None, None, 0, None) == lbm.EINVAL
+    assert L.lbm_vans_batch_step(None, 1) == lbm.EINVAL
+    assert L.lbm_vans_batch_grad_work_bytes(None, 0, 10, 5) == 0
+    assert L.lbm_vans_batch_grad(None, 0, 10, 5, None, 0, None, None) == lbm.EINVAL
+    L.lbm_vans_batch_destroy(None)
+
+
 def test_binding_fails_loudly_when_library_missing(tmp_path):
     import importlib
     mod = importlib.import_module("paper_1406_6438_amd.lbm")

@@ -1,0 +1,312 @@
+"""GPU parity of the batched ensemble path (many members, one launch per vector
+width per step, captured step graphs, autotuned launch shape) against the FP64
+oracle, member by member, and against the same members run alone.
+
+Tolerances are those of the single-problem parity tests:
+* FP64: a few ulp per step (max |f - f_oracle| <= 1e-13 after 30 steps);
+* FP32: FP32 roundoff, 4 per step, of the largest stored magnitude, and
+  rel. L2(u) <= 1e-5 after 2000 steps at the full ensemble;
+* FP16: 2 roundings per step at 2^-11 of the largest stored magnitude;
+* gradients: FP64 <= 1e-10 of the largest |dJ/deps|, FP32 rel. L2 <= 1e-4,
+  both against the oracle's FP64 reverse pass.
+A member of a batch takes the same node update as a problem run alone, so the
+batched results are also compared with lone runs; those must agree bit for
+bit (same arithmetic, only the tile bookkeeping differs).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import Spec, gpu_run, oracle_run, rel_l2, say
+from paper_1406_6438_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1406_6438_amd import lbm
+    lbm.load()
+
+
+# Widths of every vector-width group: multiples of 4 (4 nodes per lane), of 2
+# only (2 per lane), odd (1 per lane); one or several tiles wide; a single row.
+SIZES = [(96, 9), (130, 7), (67, 12), (260, 5), (5, 6), (1030, 3), (64, 1)]
+BCS = {"periodic": dict(), "walls": dict(walls_x=True, walls_y=True),
+       "open_walls": dict(open_x=True, walls_y=True), "open_periodic": dict(open_x=True)}
+
+
+def _member_specs(storage, bc, sizes=SIZES):
+    out = []
+    for k, (Lx, Ly) in enumerate(sizes):
+        kw = dict(BCS[bc])
+        is_open = kw.get("open_x", False)
+        spec = Spec(Lx=Lx, Ly=Ly, tau=0.58 + 0.06 * k, d_p=4.0 + 1.5 * k,
+                    G=(0.0, 0.0) if is_open else (2e-5 * (1 + k % 2), -1e-5),
+                    u0=(0.01 + 0.002 * k, 0.003), rho_in=1.0 + 0.004 * k, u_in=0.02 + 0.003 * k,
+                    rho_out=0.995, u_out=0.015, storage=storage, **kw)
+        eps = W.grf_porosity(Lx, Ly, seed=600 + 7 * k, ell=3.0, lo=0.4, hi=1.0)
+        out.append((spec, eps))
+    return out
+
+
+def _bound(spec, eps, fo, nsteps):
+    """Per-population bound of the storage precision (see the module docstring)."""
+    if spec.storage == "f64":
+        return 1e-13
+    rest = oracle.init(dataclasses.replace(spec, u0=(0.0, 0.0)).oracle(), spec.input_eps(eps))
+    de = max(np.abs(eps - np.roll(eps, s, axis=a)).max() for a in (0, 1) for s in (1, -1))
+    D = np.abs(fo - rest).max() + de / 18.0
+    if spec.storage == "f32":
+        return 4 * (nsteps + 1) * 2.0 ** -24 * D
+    return 2 * (nsteps + 1) * 2.0 ** -11 * D
+
+
+def _solvers(members):
+    from paper_1406_6438_amd import lbm
+    return [lbm.Solver(s.gpu(), s.input_eps(e)) for s, e in members]
+
+
+def _states(solvers):
+    return [s.get_state().cpu().numpy() for s in solvers]
+
+
+def _close(objs):
+    for o in objs:
+        o.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("bc", list(BCS))
+def test_batch_matches_oracle_and_lone_runs(storage, bc):
+    from paper_1406_6438_amd import lbm
+    say(f"[batch forward {storage} {bc}] members {SIZES}")
+    members = _member_specs(storage, bc)
+    nsteps = 30
+    sv = _solvers(members)
+    b = lbm.Batch(sv)
+    b.step(nsteps)
+    fb = _states(sv)
+    assert all(s.n == nsteps for s in sv)
+    for (spec, eps), f in zip(members, fb):
+        mo, fo = oracle_run(spec, eps, nsteps)
+        err = np.abs(f - fo).max()
+        say(f"  {spec.Lx}x{spec.Ly}: max |f - f_oracle| {err:.3e} (bound "
+            f"{_bound(spec, eps, fo, nsteps):.3e})")
+        assert err <= _bound(spec, eps, fo, nsteps)
+        _, fl = gpu_run(spec, eps, nsteps)
+        assert np.array_equal(f, fl), f"{spec.Lx}x{spec.Ly}: batch differs from a lone run"
+    b.close()
+    _close(sv)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_every_launch_shape_gives_the_same_bits(storage):
+    """vec 4/2/1, one workgroup per tile or persistent grids, with and without graphs."""
+    from paper_1406_6438_amd import lbm
+    members = _member_specs(storage, "open_walls")
+    vmax = 2 if storage == "f64" else 4
+    shapes = [(v, g, c) for v in sorted({vmax, 2, 1}, reverse=True) for g in (0, 8, 64)
+              for c in (0, 4)]
+    ref = None
+    for v, g, c in shapes:
+        say(f"[batch shape {storage}] vec={v} grid={g} graph_steps={c}")
+        sv = _solvers(members)
+        b = lbm.Batch(sv)
+        b.configure(v, g, c)
+        assert b.config["vec"] == v and b.config["grid"] == g and b.config["graph_steps"] == c
+        b.step(13)
+        f = _states(sv)
+        b.close()
+        _close(sv)
+        if ref is None:
+            ref = f
+            continue
+        for a, r in zip(f, ref):
+            assert np.array_equal(a, r)
+
+
+def test_graph_replays_match_plain_launches():
+    """A graph replayed several times, with eager work and synchronisations in
+    between, against plain launches of the same steps: every replay identical."""
+    from paper_1406_6438_amd import lbm
+    members = _member_specs("f32", "open_walls")
+    sa, sb = _solvers(members), _solvers(members)
+    ba, bb = lbm.Batch(sa), lbm.Batch(sb)
+    ba.configure(4, 0, 4)
+    bb.configure(4, 0, 0)
+    ba.step(1)
+    bb.step(1)
+    for r in range(4):
+        ba.step(4)       # one replay of the 4-step graph
+        bb.step(4)
+        torch.cuda.synchronize()
+        m = sa[r % len(sa)].moments()   # eager work between replays
+        assert m["rc"] == 0
+        for x, y in zip(_states(sa), _states(sb)):
+            assert np.array_equal(x, y), f"replay {r}"
+    assert all(s.n == 17 for s in sa)
+    _close([ba, bb])
+    _close(sa + sb)
+
+
+def test_autotune_keeps_the_state_and_reports_trials():
+    from paper_1406_6438_amd import lbm
+    members = _member_specs("f32", "open_walls")
+    sv = _solvers(members)
+    b = lbm.Batch(sv)
+    b.step(3)
+    before = _states(sv)
+    best, trials = b.tune(reps=3)
+    say(f"[batch tune] best {best}; {len(trials)} trials")
+    assert trials and best["us_per_step"] == min(t["us_per_step"] for t in trials)
+    assert b.config["vec"] == best["vec"] and b.config["grid"] == best["grid"]
+    for x, y in zip(_states(sv), before):
+        assert np.array_equal(x, y)
+    assert all(s.n == 3 for s in sv)
+    b.step(10)
+    for (spec, eps), f in zip(members, _states(sv)):
+        _, fl = gpu_run(spec, eps, 13)
+        assert np.array_equal(f, fl)
+    b.close()
+    _close(sv)
+
+
+def test_batch_rejects_mismatched_members_and_out_of_step_members():
+    from paper_1406_6438_amd import lbm
+    m32 = _member_specs("f32", "open_walls", sizes=[(16, 6), (20, 5)])
+    m64 = _member_specs("f64", "open_walls", sizes=[(16, 6)])
+    mp = _member_specs("f32", "walls", sizes=[(16, 6)])
+    a, c = _solvers(m32)
+    (d,) = _solvers(m64)
+    (e,) = _solvers(mp)
+    for bad in ([a, d], [a, e], [a, a]):
+        with pytest.raises(lbm.LbmVansError):
+            lbm.Batch(bad)
+    spec, eps = m32[0]
+    diag = lbm.Solver(dataclasses.replace(spec, diag_every=5).gpu(), spec.input_eps(eps))
+    with pytest.raises(lbm.LbmVansError):
+        lbm.Batch([diag, c])
+    b = lbm.Batch([a, c])
+    for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16)):
+        with pytest.raises(lbm.LbmVansError):
+            b.configure(*cfg)
+    a.step(1)                       # a member stepped on its own
+    with pytest.raises(lbm.LbmVansError):
+        b.step(1)
+    c.step(1)                       # back in step
+    b.step(2)
+    assert a.n == 3 and c.n == 3
+    b.close()
+    _close([a, c, d, e, diag])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_gradient_matches_oracle_adjoint(storage):
+    from paper_1406_6438_amd import lbm
+    sizes = [(24, 10), (26, 9), (96, 12), (130, 8)]
+    members = _member_specs(storage, "open_walls", sizes=sizes)
+    nsteps, K = 60, 9
+    sv = _solvers(members)
+    b = lbm.Batch(sv)
+    J, g = b.grad(nsteps, K)
+    for (spec, eps), Jb, gb, s in zip(members, J, g, sv):
+        Jo, go = oracle.grad_outlet_flux(spec.oracle(), spec.input_eps(eps), nsteps)
+        gb = gb.cpu().numpy()
+        say(f"[batch grad {storage}] {spec.Lx}x{spec.Ly}: J rel {abs(Jb - Jo) / abs(Jo):.2e}, "
+            f"grad rel L2 {rel_l2(gb, go):.2e}")
+        assert s.n == nsteps
+        if storage == "f64":
+            assert abs(Jb - Jo) <= 1e-12 * abs(Jo)
+            assert np.abs(gb - go).max() <= 1e-10 * np.abs(go).max()
+        else:
+            assert abs(Jb - Jo) <= 1e-5 * abs(Jo)
+            assert rel_l2(gb, go) <= 1e-4
+        lone = lbm.Solver(spec.gpu(), spec.input_eps(eps))
+        Jl, gl = lone.grad(nsteps, K)
+        lone.close()
+        assert Jl == Jb and np.array_equal(gl.cpu().numpy(), gb)
+    b.close()
+    _close(sv)
+
+
+def _ensemble_specs():
+    U = W.ENSEMBLE_U
+    out = []
+    for m in W.ensemble():
+        spec = Spec(Lx=m.Lx, Ly=m.Ly, tau=m.tau, walls_y=True, open_x=True, d_p=m.d_p,
+                    u0=(U, 0.0), rho_in=1.0, u_in=U, rho_out=1.0, u_out=U, storage="f32")
+        out.append((spec, m))
+    return out
+
+
+def test_full_ensemble_2000_steps():
+    """The 64-member ensemble, autotuned, 2000 steps: the three smallest members
+    against the oracle (rel. L2(u) <= 1e-5), every member against a lone run."""
+    from paper_1406_6438_amd import lbm
+    ens = _ensemble_specs()
+    say(f"[ensemble] {len(ens)} members, {sum(s.Lx * s.Ly for s, _ in ens) / 1e6:.1f}M nodes")
+    sv = [lbm.Solver(s.gpu(), s.input_eps(m.porosity())) for s, m in ens]
+    b = lbm.Batch(sv)
+    best, _ = b.tune(reps=3)
+    say(f"  tuned: {best}")
+    b.step(W.ENSEMBLE_STEPS)
+    torch.cuda.synchronize()
+    order = np.argsort([s.Lx * s.Ly for s, _ in ens])
+    for k in order[:3]:
+        spec, m = ens[k]
+        eps = m.porosity()
+        mo, _ = oracle_run(spec, eps, W.ENSEMBLE_STEPS)
+        mg = sv[k].moments()
+        e = rel_l2(mg["ux"].double().cpu().numpy(), mo["ux"])
+        say(f"  member {k} {spec.Lx}x{spec.Ly} tau {spec.tau:.3f}: rel L2(ux) {e:.3e}")
+        assert e <= 1e-5
+        assert rel_l2(mg["uy"].double().cpu().numpy(), mo["uy"]) <= 1e-5 * max(
+            1.0, np.linalg.norm(mo["ux"]) / max(np.linalg.norm(mo["uy"]), 1e-300))
+    for k, ((spec, m), s) in enumerate(zip(ens, sv)):
+        fb = s.get_state()
+        lone = lbm.Solver(spec.gpu(), spec.input_eps(m.porosity()))
+        lone.step(W.ENSEMBLE_STEPS)
+        same = torch.equal(fb, lone.get_state())
+        lone.close()
+        assert same, f"member {k} ({spec.Lx}x{spec.Ly}) differs from its lone run"
+    b.close()
+    _close(sv)
+
+
+def test_full_ensemble_gradient():
+    """Gradient of every member's outlet flux after 2000 steps (checkpoints every
+    45): the two smallest members against the oracle's FP64 reverse pass
+    (rel. L2 <= 1e-4), the largest against its lone run (bit for bit)."""
+    from paper_1406_6438_amd import lbm
+    ens = _ensemble_specs()
+    sv = [lbm.Solver(s.gpu(), s.input_eps(m.porosity())) for s, m in ens]
+    b = lbm.Batch(sv)
+    J, g = b.grad(W.ENSEMBLE_STEPS, W.ENSEMBLE_CKPT)
+    assert all(np.isfinite(J))
+    order = np.argsort([s.Lx * s.Ly for s, _ in ens])
+    for k in order[:2]:
+        spec, m = ens[k]
+        eps = spec.input_eps(m.porosity())
+        Jo, go = oracle.grad_outlet_flux(spec.oracle(), eps, W.ENSEMBLE_STEPS)
+        gb = g[k].cpu().numpy()
+        say(f"[ensemble grad] member {k} {spec.Lx}x{spec.Ly}: J rel "
+            f"{abs(J[k] - Jo) / abs(Jo):.2e}, grad rel L2 {rel_l2(gb, go):.2e}")
+        assert abs(J[k] - Jo) <= 1e-5 * abs(Jo)
+        assert rel_l2(gb, go) <= 1e-4
+    k = int(order[-1])
+    spec, m = ens[k]
+    gk = g[k].clone()
+    del g
+    b.close()
+    _close(sv)
+    lone = lbm.Solver(spec.gpu(), spec.input_eps(m.porosity()))
+    Jl, gl = lone.grad(W.ENSEMBLE_STEPS, W.ENSEMBLE_CKPT)
+    lone.close()
+    assert Jl == J[k] and torch.equal(gl, gk)

@@ -1,8 +1,9 @@
 // lbm_vans.hip -- gfx950 kernels and C-ABI of the volume-averaged lattice
 // Boltzmann solver (Zhang, Wang & Ouyang, arXiv:1406.6438).
 //
-// Hot path: one fused pull sweep per time step.  Each thread owns one node x
-// of one row and, in a single pass,
+// Hot path: one fused pull sweep per time step.  Each lane owns a run of 4
+// (FP32, FP16) or 2 (FP64) consecutive nodes of one row and, for each node x,
+// in a single pass,
 //   1. gathers f_i(x, n) from the post-collision populations of step n-1 at
 //      x - e_i (periodic wrap, or the node's own opposite population behind a
 //      half-way bounce-back wall);
@@ -12,8 +13,10 @@
 //      implicit velocity of eq. (1moment) in closed form;
 //   4. relaxes toward the equilibrium of eq. (d2q9eq) and adds P_i + F_i
 //      (eqs. (pi), (Fi)) in their common Guo form;
-//   5. writes the 9 post-collision populations to its own node of the other
-//      buffer (aligned, coalesced stores).
+//   5. writes the 9 post-collision populations to its own nodes of the other
+//      buffer (aligned, coalesced vector stores).
+// Ensembles of independent problems run the same sweep over one list of the
+// tiles of all members, one launch per step.
 // The sweep moves 9 population loads, 9 population stores and one porosity
 // load per node from HBM, so it is bandwidth-bound; there is no dense
 // contraction and no MFMA.
@@ -578,54 +581,6 @@ __device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, in
     collide<R>(d, N, ph, de);
 }
 
-// The fused stream+collide sweep, one node per thread: fin holds the
-// post-collision populations of step n-1 (state n after streaming), fout
-// receives those of step n.  Used when Lx is not a multiple of the vector width.
-template <typename S, typename R, bool DIAG>
-__device__ __forceinline__ void sweep_tile(const S *__restrict__ fin, S *__restrict__ fout,
-                                           const R *__restrict__ eps, const Geo &g,
-                                           const Phys<R> &ph, double *__restrict__ part, int t)
-{
-    constexpr int W = TX + 2;
-    __shared__ R tile[TY + 2][W];
-    const int bx = t % g.nbx, by = t / g.nbx;
-    const int x0 = bx * TX, y0 = by * TY;
-    load_eps_tile<R, W>(tile, eps, g, x0, y0);
-    __syncthreads();
-
-    double acc[NRED];
-#pragma unroll
-    for (int k = 0; k < NRED; k++) acc[k] = 0.0;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int x = x0 + tx;
-#pragma unroll
-    for (int r = 0; r < ROWS; r++) {
-        const int ly = ty + NW * r;
-        const int y = y0 + ly;
-        if (x < g.Lx && y < g.Ly) {
-            Nbr n = neighbours(x, y, g);
-            R d[9];
-            gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
-            const bool ores = g.open_x && ph.reservoir;
-            update_node<R, W, DIAG>(d, tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp,
-                                    ores && x == 0, ores && x == g.Lx - 1, ph, acc, true);
-            const int c = y * g.pitch + x;
-#pragma unroll
-            for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i], ph.scale);
-        }
-    }
-    if constexpr (DIAG) block_partial(acc, part, t);
-}
-
-template <typename S, typename R, bool DIAG>
-__global__ __launch_bounds__(NTHREADS) void k_sweep(const S *__restrict__ fin,
-                                                    S *__restrict__ fout,
-                                                    const R *__restrict__ eps, Geo g,
-                                                    Phys<R> ph, double *__restrict__ part)
-{
-    sweep_tile<S, R, DIAG>(fin, fout, eps, g, ph, part, xcd_tile(blockIdx.x, g.ntiles));
-}
-
 // ---- vector sweep: V consecutive nodes per lane, full-width loads and stores
 
 template <typename S, int V>
@@ -662,22 +617,26 @@ __device__ __forceinline__ void stv(S *p, const R (&o)[V], R scale)
     __builtin_nontemporal_store(v, reinterpret_cast<vt *>(p));
 }
 
-// Lane geometry of the vector sweep: the run [x, x + V) and its left / right
-// neighbours (wrapped, or flagged as walls), and whether the lane must load the
-// neighbour itself (wave edge or periodic seam) instead of taking it from the
+// Lane geometry of the vector sweep: the run [x, x + V), of which the first n
+// nodes lie in the domain (n < V only for the last lane of a row when Lx is not
+// a multiple of V: a ragged run), its last node, its left / right neighbours
+// (wrapped, or flagged as walls), and whether the lane must load the neighbour
+// itself (wave edge, periodic seam or ragged end) instead of taking it from the
 // adjacent lane.
 struct LaneX {
-    int x, xl, xr;
+    int x, n, last, xl, xr;
     bool wl, wr, need_l, need_r;
 };
 
-template <int V, bool WX>
+template <int V, bool WX, bool RG>
 __device__ __forceinline__ LaneX lane_x(int x0, int lane, const Geo &g)  // WX: x not periodic
 {
     LaneX L;
     L.x = x0 + lane * V;
+    L.n = RG ? min(V, g.Lx - L.x) : V;
+    L.last = L.x + L.n - 1;
     L.xl = L.x - 1;
-    L.xr = L.x + V;
+    L.xr = L.last + 1;
     L.wl = L.wr = false;
     bool nl = lane == 0, nr = lane == TX - 1;
     if (L.xl < 0) {
@@ -685,7 +644,7 @@ __device__ __forceinline__ LaneX lane_x(int x0, int lane, const Geo &g)  // WX: 
         else { L.xl = g.Lx - 1; nl = true; }
     }
     if (L.xr >= g.Lx) {
-        if (WX) { L.wr = true; L.xr = L.x; }
+        if (WX) { L.wr = true; L.xr = L.last; }
         else { L.xr = L.xr % g.Lx; nr = true; }
     }
     L.need_l = nl && !L.wl;
@@ -699,7 +658,7 @@ __device__ __forceinline__ LaneX lane_x(int x0, int lane, const Geo &g)  // WX: 
 // edge or periodic seam the single values beyond their run); phase 2 waits and
 // rebuilds the x-shifted populations with cross-lane shuffles.  Keeping all
 // loads ahead of the first shuffle keeps them in flight together.
-template <typename S, typename R, int V, bool WY>
+template <typename S, typename R, int V, bool WY, bool RG>
 __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], int y,
                                            const Geo &g, const LaneX &L, R inv_scale,
                                            bool &wym, bool &wyp, unsigned &r0)
@@ -746,9 +705,9 @@ __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], in
         el[2] = load_raw(F[8] + rp + L.xl);
     }
     if (L.wr) {
-        er[0] = load_raw(F[1] + r0 + x + V - 1);
-        er[1] = load_raw(F[8] + r0 + x + V - 1);
-        er[2] = load_raw(F[5] + r0 + x + V - 1);
+        er[0] = load_raw(F[1] + r0 + L.last);
+        er[1] = load_raw(F[8] + r0 + L.last);
+        er[2] = load_raw(F[5] + r0 + L.last);
     } else if (L.need_r) {
         er[0] = load_raw(F[3] + r0 + L.xr);
         er[1] = load_raw(F[6] + rm + L.xr);
@@ -792,6 +751,12 @@ __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], in
 #pragma unroll
         for (int k = 0; k < V - 1; k++) o[k] = cvt(a[k + 1]);
         o[V - 1] = own_r ? cvt(edge) : next;
+        if constexpr (RG) {
+            // a ragged run ends at node n-1: its right neighbour is the edge value
+#pragma unroll
+            for (int k = 0; k < V - 1; k++)
+                if (k == L.n - 1) o[k] = cvt(edge);
+        }
     };
     left(d[1], raw[1], el[0], true);
     right(d[3], raw[3], er[0], true);
@@ -801,16 +766,18 @@ __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], in
     left(d[8], raw[8], el[2], !wyp);
 }
 
-// The fused sweep with V consecutive nodes per lane (requires Lx % V == 0 and
-// a pitch that is a multiple of 64 V); BX: x ends periodic (0), walls (1) or
-// open (2); WY: walls across y.  Each
+// The fused sweep with V consecutive nodes per lane (a pitch that is a
+// multiple of 64 V); BX: x ends periodic (0), walls (1) or open (2); WY: walls
+// across y; RG: Lx need not be a multiple of V (the last lane of a row may
+// hold a ragged run; its nodes beyond Lx are computed from padding and stored
+// into the padding, where nothing reads them).  Each
 // population is one aligned vector load per lane; the x-shifted ones are
 // rebuilt with one cross-lane shuffle and a masked scalar load for the lane at
 // the wave's edge.  The first row's populations are requested before the
 // porosity tile is filled, so their latency overlaps the tile load and the
-// barrier.  The same node update as the scalar sweep then runs per node, and
+// barrier.  The node update (moments, velocity, collision) then runs per node, and
 // the 9 results leave as aligned vector stores.
-template <typename S, typename R, int V, int BX, bool WY, bool DIAG>
+template <typename S, typename R, int V, int BX, bool WY, bool DIAG, bool RG>
 __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__restrict__ fout,
                                                const R *__restrict__ eps, const Geo &g,
                                                const Phys<R> &ph, double *__restrict__ part,
@@ -822,7 +789,7 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
     const int x0 = bx * TX * V, y0 = by * TY;
     const int lane = threadIdx.x % TX, ty = threadIdx.x / TX;
     constexpr bool WX = BX != 0;
-    const LaneX L = lane_x<V, WX>(x0, lane, g);
+    const LaneX L = lane_x<V, WX, RG>(x0, lane, g);
     const bool valid = L.x < g.Lx;
     const S *F[9];
 #pragma unroll
@@ -833,7 +800,8 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
     R d[9][V];
     bool wym, wyp;
     unsigned r0;
-    if (y0 + ty < g.Ly) gather_vec<S, R, V, WY>(d, F, y0 + ty, g, L, ph.inv_scale, wym, wyp, r0);
+    if (y0 + ty < g.Ly)
+        gather_vec<S, R, V, WY, RG>(d, F, y0 + ty, g, L, ph.inv_scale, wym, wyp, r0);
     et.commit(tile);
     __syncthreads();
 
@@ -845,7 +813,7 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
         const int ly = ty + NW * r;
         const int y = y0 + ly;
         if (y >= g.Ly) break;
-        if (r > 0) gather_vec<S, R, V, WY>(d, F, y, g, L, ph.inv_scale, wym, wyp, r0);
+        if (r > 0) gather_vec<S, R, V, WY, RG>(d, F, y, g, L, ph.inv_scale, wym, wyp, r0);
 #pragma unroll
         for (int k = 0; k < V; k++) {
             R dk[9];
@@ -855,7 +823,7 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
             const bool wxp = WX && L.x + k == g.Lx - 1;
             const bool ores = BX == 2 && ph.reservoir;
             update_node<R, W, DIAG>(dk, tile, ly + 1, lane * V + k + 1, wxm, wxp, wym, wyp,
-                                    ores && wxm, ores && wxp, ph, acc, valid);
+                                    ores && wxm, ores && wxp, ph, acc, valid && k < L.n);
 #pragma unroll
             for (int i = 0; i < 9; i++) d[i][k] = dk[i];
         }
@@ -868,14 +836,14 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
     if constexpr (DIAG) block_partial(acc, part, t);
 }
 
-template <typename S, typename R, int V, int BX, bool WY, bool DIAG>
+template <typename S, typename R, int V, int BX, bool WY, bool DIAG, bool RG>
 __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, double *__restrict__ part)
 {
-    sweep_vec_tile<S, R, V, BX, WY, DIAG>(fin, fout, eps, g, ph, part,
-                                          xcd_tile(blockIdx.x, g.ntiles));
+    sweep_vec_tile<S, R, V, BX, WY, DIAG, RG>(fin, fout, eps, g, ph, part,
+                                              xcd_tile(blockIdx.x, g.ntiles));
 }
 
 // Macroscopic fields of the current state (no collision, no store of
@@ -1462,8 +1430,8 @@ __device__ __forceinline__ TileWalk tile_walk(int ntiles)
     return w;
 }
 
-// One time step of the members of one vector width V, from state slot src to
-// state slot dst (tmap: their part of the tile list).
+// One time step of every member, from state slot src to state slot dst, with
+// V nodes per lane (ragged runs where a member's Lx is not a multiple of V).
 template <typename S, typename R, int V, int BX, bool WY>
 __global__ __launch_bounds__(NTHREADS) void k_batch_sweep(const Member<R> *__restrict__ M,
                                                           const int *__restrict__ tmap,
@@ -1476,7 +1444,7 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_sweep(const Member<R> *__res
         const Geo gs = d.gs;
         Phys<R> ph = d.ph;
         ph.reservoir = reservoir;
-        sweep_vec_tile<S, R, V, BX, WY, false>(
+        sweep_vec_tile<S, R, V, BX, WY, false, true>(
             reinterpret_cast<const S *>(state_slot(d, src)),
             reinterpret_cast<S *>(state_slot(d, dst)), d.eps, gs, ph, nullptr, T - d.tile0);
         __syncthreads();  // a next tile of this block reuses the LDS porosity tile
@@ -1512,9 +1480,9 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__r
 struct lbm_vans_handle {
     lbm_vans_params p;
     hipStream_t stream;
-    Geo g;                  // one node per thread: moments, state copies, scalar sweep
+    Geo g;                  // one node per thread: moments, state copies, adjoint
     Geo gs;                 // geometry of the sweep actually launched (vec nodes per lane)
-    int vec;                // nodes per lane of the sweep (1 = scalar sweep)
+    int vec;                // nodes per lane of the sweep
     int ntiles;
     size_t pop_bytes;       // bytes of one population buffer
     char *buf[2];           // population buffers; buf[cur] holds the current state
@@ -1580,12 +1548,11 @@ int check_params(const lbm_vans_params *p)
     return LBM_VANS_OK;
 }
 
-// Vector width of the sweep for these parameters: 16-byte accesses per lane
-// (4 FP32, 2 FP64) and 8-byte ones for FP16, when Lx is a multiple of it.
+// Vector width of the sweep: 16-byte accesses per lane (4 FP32, 2 FP64) and
+// 8-byte ones for FP16 (ragged runs when Lx is not a multiple of it).
 int sweep_vec(const lbm_vans_params *p)
 {
-    int v = p->storage == LBM_F64 ? 2 : 4;
-    return p->Lx % v == 0 ? v : 1;
+    return p->storage == LBM_F64 ? 2 : 4;
 }
 
 // Tiling for `vec` nodes per lane; the pitch is shared by all tilings.
@@ -1679,28 +1646,31 @@ int with_types(int storage, Fn &&fn)
     }
 }
 
-template <typename S, typename R, bool DIAG>
-void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
+template <typename S, typename R, bool DIAG, bool RG>
+void launch_sweep_rg(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
 {
     constexpr int VMAX = sizeof(S) == 8 ? 2 : 4;
     const dim3 grid(h->gs.ntiles), block(NTHREADS);
     const R *eps = (const R *)h->eps;
-    if (h->vec == VMAX) {
-        const int bx = h->gs.open_x ? 2 : (h->gs.wall_x ? 1 : 0);
-        const bool wy = h->gs.wall_y;
-#define LBM_VANS_VEC(BXV, WYV)                                                              \
-    hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, BXV, WYV, DIAG>), grid, block, 0, h->stream, \
+    const int bx = h->gs.open_x ? 2 : (h->gs.wall_x ? 1 : 0);
+    const bool wy = h->gs.wall_y;
+#define LBM_VANS_VEC(BXV, WYV)                                                                  \
+    hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, BXV, WYV, DIAG, RG>), grid, block, 0, h->stream, \
                        src, dst, eps, h->gs, ph, h->part)
-        if (bx == 0 && !wy) LBM_VANS_VEC(0, false);
-        else if (bx == 0) LBM_VANS_VEC(0, true);
-        else if (bx == 1 && !wy) LBM_VANS_VEC(1, false);
-        else if (bx == 1) LBM_VANS_VEC(1, true);
-        else if (!wy) LBM_VANS_VEC(2, false);
-        else LBM_VANS_VEC(2, true);
+    if (bx == 0 && !wy) LBM_VANS_VEC(0, false);
+    else if (bx == 0) LBM_VANS_VEC(0, true);
+    else if (bx == 1 && !wy) LBM_VANS_VEC(1, false);
+    else if (bx == 1) LBM_VANS_VEC(1, true);
+    else if (!wy) LBM_VANS_VEC(2, false);
+    else LBM_VANS_VEC(2, true);
 #undef LBM_VANS_VEC
-    } else
-        hipLaunchKernelGGL((k_sweep<S, R, DIAG>), grid, block, 0, h->stream, src, dst,
-                           (const R *)h->eps, h->gs, ph, h->part);
+}
+
+template <typename S, typename R, bool DIAG>
+void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
+{
+    if (h->p.Lx % h->vec) launch_sweep_rg<S, R, DIAG, true>(h, src, dst, ph);
+    else launch_sweep_rg<S, R, DIAG, false>(h, src, dst, ph);
 }
 
 // One time step from the state n stored in src into dst.
@@ -2087,8 +2057,7 @@ struct lbm_vans_batch {
     lbm_vans_batch_config cfg{};
     size_t desc_bytes = 0;          // bytes of one device descriptor
     std::vector<char> desc;         // host image of the descriptors
-    std::vector<int> tmap, tmap_adj;  // sweep list grouped by width (4, 2, 1); adjoint list
-    int grp_off[3] = {0, 0, 0}, grp_n[3] = {0, 0, 0};  // sweep list part of width 4, 2, 1
+    std::vector<int> tmap, tmap_adj;  // tile lists of the sweep and of the adjoint
     void *d_desc = nullptr;
     int *d_tmap = nullptr, *d_tmap_adj = nullptr;
     int ntiles = 0, ntiles_adj = 0;
@@ -2112,15 +2081,6 @@ void drop_graphs(lbm_vans_batch *b)
         }
 }
 
-// Nodes per lane of a member's sweep: the largest power of two up to vec
-// that divides Lx.
-int member_vec(const lbm_vans_params *p, int vec)
-{
-    int v = vec;
-    while (v > 1 && p->Lx % v) v /= 2;
-    return v;
-}
-
 // Descriptors and tile lists for a sweep width of vec nodes per lane, plus the
 // gradient workspace layout when gw is given; uploaded to the batch's table.
 int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t ckpt_every)
@@ -2138,7 +2098,7 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             lbm_vans_handle *h = b->m[k];
             Member<R> &d = D[k];
             std::memset(&d, 0, sizeof d);
-            d.vec = member_vec(&h->p, vec);
+            d.vec = vec;
             d.gs = make_geo(&h->p, d.vec);
             d.g = h->g;
             d.ph = make_phys<R>(&h->p);
@@ -2146,19 +2106,10 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             d.buf[1] = h->buf[1];
             d.eps = static_cast<const R *>(h->eps);
             d.part = h->part;
+            d.tile0 = static_cast<int>(b->tmap.size());
             d.tile0_adj = static_cast<int>(b->tmap_adj.size());
+            b->tmap.insert(b->tmap.end(), d.gs.ntiles, static_cast<int>(k));
             b->tmap_adj.insert(b->tmap_adj.end(), d.g.ntiles, static_cast<int>(k));
-        }
-        // sweep list: the members of width 4, then 2, then 1, each part in member order
-        for (int gi = 0; gi < 3; gi++) {
-            const int vw = 4 >> gi;
-            b->grp_off[gi] = static_cast<int>(b->tmap.size());
-            for (size_t k = 0; k < nm; k++) {
-                if (D[k].vec != vw) continue;
-                D[k].tile0 = static_cast<int>(b->tmap.size()) - b->grp_off[gi];
-                b->tmap.insert(b->tmap.end(), D[k].gs.ntiles, static_cast<int>(k));
-            }
-            b->grp_n[gi] = static_cast<int>(b->tmap.size()) - b->grp_off[gi];
         }
         size_t off = 0;
         for (size_t k = 0; k < nm; k++) {
@@ -2192,13 +2143,12 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
 }
 
 template <typename S, typename R, int V>
-void batch_sweep_v(const lbm_vans_batch *b, hipStream_t st, int gi, int src, int dst,
-                   int reservoir)
+void batch_sweep_v(const lbm_vans_batch *b, hipStream_t st, int src, int dst, int reservoir)
 {
-    const int n = b->grp_n[gi];
+    const int n = b->ntiles;
     const int grid = (b->cfg.grid > 0 && b->cfg.grid < n) ? b->cfg.grid : n;
     const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
-    const int *tm = b->d_tmap + b->grp_off[gi];
+    const int *tm = b->d_tmap;
 #define LBM_VANS_BATCH(BXV, WYV)                                                             \
     hipLaunchKernelGGL((k_batch_sweep<S, R, V, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, st, \
                        M, tm, n, src, dst, reservoir)
@@ -2211,18 +2161,18 @@ void batch_sweep_v(const lbm_vans_batch *b, hipStream_t st, int gi, int src, int
 #undef LBM_VANS_BATCH
 }
 
-// One batched step on stream st: every member from state slot src to dst,
-// one launch per vector width present among the members.
+// One batched step on stream st: every member from state slot src to dst in
+// one launch.
 int batch_sweep(lbm_vans_batch *b, hipStream_t st, int src, int dst, int reservoir)
 {
     return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         if constexpr (sizeof(S) != 8) {
-            if (b->grp_n[0] > 0) batch_sweep_v<S, R, 4>(b, st, 0, src, dst, reservoir);
+            if (b->cfg.vec == 4) batch_sweep_v<S, R, 4>(b, st, src, dst, reservoir);
         }
-        if (b->grp_n[1] > 0) batch_sweep_v<S, R, 2>(b, st, 1, src, dst, reservoir);
-        if (b->grp_n[2] > 0) batch_sweep_v<S, R, 1>(b, st, 2, src, dst, reservoir);
+        if (b->cfg.vec == 2) batch_sweep_v<S, R, 2>(b, st, src, dst, reservoir);
+        if (b->cfg.vec == 1) batch_sweep_v<S, R, 1>(b, st, src, dst, reservoir);
         return check_launch("k_batch_sweep");
     });
 }

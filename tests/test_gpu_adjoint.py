@@ -131,7 +131,7 @@ def test_gradient_zero_steps_is_outlet_flux_of_initial_state():
 
 @pytest.mark.parametrize("Lx", [96, 97])
 def test_gradient_fp32_matches_oracle_adjoint(Lx):
-    """FP32 storage and arithmetic (vector sweep for 96, one node per lane for 97)."""
+    """FP32 storage and arithmetic (97 ends each row in a ragged run of 1 node)."""
     say(f"[grad f32] {Lx}x40, 300 steps")
     spec = _open_spec(Lx, 40, "f32", tau=0.8, d_p=60.0, u0=(0.02, 0.0), rho_in=1.0, u_in=0.02,
                       rho_out=1.0, u_out=0.02, G=(0.0, 0.0))

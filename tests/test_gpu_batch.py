@@ -10,8 +10,10 @@ Tolerances are those of the single-problem parity tests:
 * gradients: FP64 <= 1e-10 of the largest |dJ/deps|, FP32 rel. L2 <= 1e-4,
   both against the oracle's FP64 reverse pass.
 A member of a batch takes the same node update as a problem run alone, so the
-batched results are also compared with lone runs; those must agree bit for
-bit (same arithmetic, only the tile bookkeeping differs).
+batched results are also compared with lone runs: bit for bit when the batch
+runs the lone sweep's vector width (same arithmetic, only the tile bookkeeping
+differs), else within the precision bound above (a different width may fuse
+other multiply-adds).
 """
 import dataclasses
 
@@ -35,9 +37,9 @@ def _need_gpu():
     lbm.load()
 
 
-# Widths of every vector-width group: multiples of 4 (4 nodes per lane), of 2
-# only (2 per lane), odd (1 per lane); one or several tiles wide; a single row.
-SIZES = [(96, 9), (130, 7), (67, 12), (260, 5), (5, 6), (1030, 3), (64, 1)]
+# Widths that are multiples of 4, of 2 only, odd (ragged last runs of 1..3
+# nodes); one or several tiles wide; a single row; a width below one run.
+SIZES = [(96, 9), (130, 7), (67, 12), (260, 5), (5, 6), (1030, 3), (64, 1), (3, 4)]
 BCS = {"periodic": dict(), "walls": dict(walls_x=True, walls_y=True),
        "open_walls": dict(open_x=True, walls_y=True), "open_periodic": dict(open_x=True)}
 
@@ -106,29 +108,38 @@ def test_batch_matches_oracle_and_lone_runs(storage, bc):
     _close(sv)
 
 
+def _vmax(storage):
+    return 2 if storage == "f64" else 4
+
+
 @pytest.mark.parametrize("storage", ["f32", "f64"])
-def test_every_launch_shape_gives_the_same_bits(storage):
-    """vec 4/2/1, one workgroup per tile or persistent grids, with and without graphs."""
+def test_every_launch_shape(storage):
+    """vec 4/2/1, one workgroup per tile or persistent grids, with and without
+    graphs: the same bits for one vec, within the precision bound across vec."""
     from paper_1406_6438_amd import lbm
     members = _member_specs(storage, "open_walls")
-    vmax = 2 if storage == "f64" else 4
+    vmax = _vmax(storage)
     shapes = [(v, g, c) for v in sorted({vmax, 2, 1}, reverse=True) for g in (0, 8, 64)
               for c in (0, 4)]
-    ref = None
+    nsteps = 13
+    ref, ref_v = {}, None
+    orc = [oracle_run(spec, eps, nsteps)[1] for spec, eps in members]
     for v, g, c in shapes:
         say(f"[batch shape {storage}] vec={v} grid={g} graph_steps={c}")
         sv = _solvers(members)
         b = lbm.Batch(sv)
         b.configure(v, g, c)
         assert b.config["vec"] == v and b.config["grid"] == g and b.config["graph_steps"] == c
-        b.step(13)
+        b.step(nsteps)
         f = _states(sv)
         b.close()
         _close(sv)
-        if ref is None:
-            ref = f
+        for (spec, eps), a, fo in zip(members, f, orc):
+            assert np.abs(a - fo).max() <= _bound(spec, eps, fo, nsteps)
+        if v not in ref:
+            ref[v] = f
             continue
-        for a, r in zip(f, ref):
+        for a, r in zip(f, ref[v]):
             assert np.array_equal(a, r)
 
 
@@ -173,7 +184,11 @@ def test_autotune_keeps_the_state_and_reports_trials():
     b.step(10)
     for (spec, eps), f in zip(members, _states(sv)):
         _, fl = gpu_run(spec, eps, 13)
-        assert np.array_equal(f, fl)
+        if best["vec"] == _vmax("f32"):
+            assert np.array_equal(f, fl)
+        else:
+            _, fo = oracle_run(spec, eps, 13)
+            assert np.abs(f - fl).max() <= 2 * _bound(spec, eps, fo, 13)
     b.close()
     _close(sv)
 
@@ -248,7 +263,8 @@ def _ensemble_specs():
 
 def test_full_ensemble_2000_steps():
     """The 64-member ensemble, autotuned, 2000 steps: the three smallest members
-    against the oracle (rel. L2(u) <= 1e-5), every member against a lone run."""
+    against the oracle (rel. L2(u) <= 1e-5), every member against a lone run
+    (bit for bit at the lone width, else rel. L2(u) <= 1e-5)."""
     from paper_1406_6438_amd import lbm
     ens = _ensemble_specs()
     say(f"[ensemble] {len(ens)} members, {sum(s.Lx * s.Ly for s, _ in ens) / 1e6:.1f}M nodes")
@@ -270,12 +286,16 @@ def test_full_ensemble_2000_steps():
         assert rel_l2(mg["uy"].double().cpu().numpy(), mo["uy"]) <= 1e-5 * max(
             1.0, np.linalg.norm(mo["ux"]) / max(np.linalg.norm(mo["uy"]), 1e-300))
     for k, ((spec, m), s) in enumerate(zip(ens, sv)):
-        fb = s.get_state()
         lone = lbm.Solver(spec.gpu(), spec.input_eps(m.porosity()))
         lone.step(W.ENSEMBLE_STEPS)
-        same = torch.equal(fb, lone.get_state())
+        if best["vec"] == _vmax("f32"):
+            same = torch.equal(s.get_state(), lone.get_state())
+            assert same, f"member {k} ({spec.Lx}x{spec.Ly}) differs from its lone run"
+        else:
+            e = rel_l2(s.moments()["ux"].double().cpu().numpy(),
+                       lone.moments()["ux"].double().cpu().numpy())
+            assert e <= 1e-5, f"member {k}: rel L2(ux) {e:.2e} against its lone run"
         lone.close()
-        assert same, f"member {k} ({spec.Lx}x{spec.Ly}) differs from its lone run"
     b.close()
     _close(sv)
 

@@ -32,10 +32,11 @@ def _need_gpu():
     lbm.load()
 
 
-# (Lx, Ly, walls_x, walls_y).  Widths not divisible by the vector width run the
-# one-node-per-lane sweep: ragged tiles, single rows/columns.  Widths divisible by
-# 4 run the vector sweep (4 FP32 / 2 FP64 nodes per lane): a partial last tile,
-# a single partial tile, seams between tiles, walls on either axis.
+# (Lx, Ly, walls_x, walls_y).  The sweep runs 4 FP32 / 2 FP64 nodes per lane;
+# widths not divisible by that end each row in a ragged run (1..3 nodes, the
+# rest of the vector in the row padding): single rows/columns, widths below one
+# run, a partial last tile, a single partial tile, seams between tiles, walls
+# on either axis.
 GEOMS = [
     (7, 5, False, False),
     (65, 33, False, True),
@@ -207,8 +208,9 @@ def test_f32_full_size_box_sampled_windows():
 @pytest.mark.parametrize("Lx", [131, 132])
 def test_every_slot_is_written(Lx):
     """Work memory filled with NaN bytes before init: after init and after each of
-    two steps the state is finite everywhere (the store map covers every slot);
-    131 runs the one-node-per-lane sweep, 132 the vector sweep."""
+    two steps the state is finite everywhere (the store map covers every slot, and
+    the NaN padding a ragged run computes on stays in the padding): 131 ends each
+    row in a ragged run of 3 nodes, 132 does not."""
     from paper_1406_6438_amd import lbm
     spec = Spec(Lx=Lx, Ly=45, walls_y=True, d_p=8.0, G=(1e-5, 0.0), storage="f32")
     eps = W.grf_porosity(Lx, 45, seed=8, ell=3.0)

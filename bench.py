@@ -10,7 +10,8 @@ launch).  Inputs are resident in HBM before timing starts.
 Prints one JSON line with MLUPS, the HBM roofline of the sweep kernel, the
 accuracy of the FP32 sweep against the FP64 oracle on the 512^2 crop (the error
 the throughput is quoted at), the FP16-storage sweep on the 8192^2 box beside it
-(throughput, roofline, accuracy after 2000 steps on its 512^2 crop) and the
+(throughput, roofline, accuracy after 2000 steps on its 512^2 crop), the
+gradient leg, the ensemble leg (64 uneven channels, batched launches) and the
 oracle's own throughput on the host cores.
 
   python bench.py [--steps K] [--warmup W] [--workload box4096_f32|box8192_f16|channel_f64]
@@ -244,6 +245,106 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
     return out
 
 
+def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int):
+    """The 64-member ensemble of uneven open channels (FP32): launch shape picked by the
+    library's autotuner, then `steps` batched steps (one launch per step, replayed as
+    16-step graphs) timed with HIP events; the same steps as plain launches; the
+    gradient of every member's outlet flux after 2000 steps (checkpoints every 45)."""
+    import numpy as np
+    from paper_1406_6438_amd import workloads as W
+    U = W.ENSEMBLE_U
+    members = W.ensemble()
+    cells = sum(m.Lx * m.Ly for m in members)
+    log(f"[bench] ensemble: {len(members)} members, {cells / 1e6:.2f}M nodes")
+
+    def params(m):
+        return lbm.Params(Lx=m.Lx, Ly=m.Ly, tau=m.tau, bc_x=lbm.BC_OPEN, bc_y=lbm.BC_BOUNCEBACK,
+                          storage=lbm.F32_SHIFTED, d_p=m.d_p, u0=(U, 0.0), rho_in=1.0, u_in=U,
+                          rho_out=1.0, u_out=U)
+
+    eps = [cast_eps(m.porosity(), "f32") for m in members]
+    sv = [lbm.Solver(params(m), e) for m, e in zip(members, eps)]
+    b = lbm.Batch(sv)
+    best, trials = b.tune(reps=5)
+    log(f"[bench] ensemble tuned: {best}")
+    b.step(warmup)
+    torch.cuda.synchronize()
+
+    def timed(n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        b.step(n)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    t_graph = timed(steps)
+    b.configure(best["vec"], best["grid"], 0)
+    t_plain = timed(steps)
+    b.configure(best["vec"], best["grid"], best["graph_steps"])
+    bpn = algorithmic_bytes_per_node("f32")
+    ach = bpn * cells / (t_graph / steps) / 1e9
+    out = {"workload": f"ensemble_{len(members)}_open_channels_f32", "members": len(members),
+           "nodes": cells, "Lx_range": [min(m.Lx for m in members), max(m.Lx for m in members)],
+           "steps": steps, "value": round(cells * steps / t_graph / 1e6, 2), "unit": "MLUPS",
+           "ms_per_step": round(t_graph * 1e3 / steps, 5),
+           "plain_launches_ms_per_step": round(t_plain * 1e3 / steps, 5),
+           "tuned": best, "trials": trials,
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS,
+                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": None,
+                        "kernel": "k_batch_sweep", "bytes_per_node": bpn}}
+    log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
+        f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")
+    # gradient of every member's outlet flux
+    K = W.ENSEMBLE_CKPT
+    nbytes = lbm.lbm_vans_batch_grad_work_bytes(b.b, lbm.OBJ_OUTLET_FLUX, W.ENSEMBLE_STEPS, K)
+    b.grad(20, 10)                                  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = b.grad(W.ENSEMBLE_STEPS, K)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    del g
+    m_grad = cells * W.ENSEMBLE_STEPS / t_grad / 1e6
+    out["gradient"] = {"steps": W.ENSEMBLE_STEPS, "ckpt_every": K, "seconds": round(t_grad, 3),
+                       "value": round(m_grad, 2),
+                       "unit": "MLUPS (forward node-steps per second of the whole gradient)",
+                       "vs_forward_same_gpu": round(m_grad / out["value"], 3),
+                       "workspace_GB": round(nbytes / 1e9, 2),
+                       "J_min_max": [min(J), max(J)]}
+    log(f"[bench] ensemble gradient: {t_grad:.2f} s, {m_grad:.0f} MLUPS-equivalent, "
+        f"workspace {nbytes / 1e9:.1f} GB")
+    if not no_accuracy:
+        import oracle
+        k = int(np.argmin([m.Lx * m.Ly for m in members]))
+        m = members[k]
+        for s in sv:
+            s.close()
+        b.close()
+        sg = lbm.Solver(params(m), eps[k])
+        sg.step(W.ENSEMBLE_STEPS)
+        mg = sg.moments(want_diag=False)
+        ux = mg["ux"].double().cpu().numpy()
+        uy = mg["uy"].double().cpu().numpy()
+        sg.close()
+        po = oracle.Params(Lx=m.Lx, Ly=m.Ly, tau=m.tau, bc_x=oracle.OPEN, bc_y=oracle.WALL,
+                           d_p=m.d_p, u0x=U, rho_in=1.0, u_in=U, rho_out=1.0, u_out=U)
+        mo = oracle.moments(po, eps[k], oracle.run(po, eps[k], W.ENSEMBLE_STEPS))
+        ug, uo = np.hypot(ux, uy), np.hypot(mo["ux"], mo["uy"])
+        out["accuracy"] = {"rel_l2_u_vs_fp64_oracle": float(np.linalg.norm(ug - uo) /
+                                                             np.linalg.norm(uo)),
+                           "sample": f"member {k} ({m.Lx}x{m.Ly}, the smallest), "
+                                     f"{W.ENSEMBLE_STEPS} steps"}
+        log(f"[bench] ensemble accuracy {out['accuracy']['rel_l2_u_vs_fp64_oracle']:.3e}")
+    else:
+        for s in sv:
+            s.close()
+        b.close()
+    del sv, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +359,8 @@ def main():
                     help="skip the FP16-storage leg (8192^2 box) reported beside the main line")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the gradient leg (1024x512 open channel) reported beside the main line")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the ensemble leg (64 uneven open channels) reported beside the main line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sweep has no multi-GPU path in this build "
@@ -311,6 +414,10 @@ def main():
     if not args.no_adjoint and args.workload == "box4096_f32":
         adj = adjoint_leg(lbm, torch, args.no_accuracy)
 
+    ens = None
+    if not args.no_ensemble and args.workload == "box4096_f32":
+        ens = ensemble_leg(lbm, torch, args.no_accuracy, 2000, args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s)")
@@ -342,6 +449,7 @@ def main():
         "accuracy": acc,
         "fp16_store": fp16,
         "adjoint": adj,
+        "ensemble": ens,
         "cpu_baseline": cpu,
         "mass_check": {"sum_eps_rho": diag[0], "nonfinite_nodes": diag[6]},
     }

@@ -245,7 +245,7 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
     return out
 
 
-def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int):
+def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: bool):
     """The 64-member ensemble of uneven open channels (FP32): launch shape picked by the
     library's autotuner, then `steps` batched steps (one launch per step, replayed as
     16-step graphs) timed with HIP events; the same steps as plain launches; the
@@ -295,6 +295,10 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int):
                         "kernel": "k_batch_sweep", "bytes_per_node": bpn}}
     log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
         f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")
+    if not grad:
+        _close_all(sv, b)
+        torch.cuda.empty_cache()
+        return out
     # gradient of every member's outlet flux
     K = W.ENSEMBLE_CKPT
     nbytes = lbm.lbm_vans_batch_grad_work_bytes(b.b, lbm.OBJ_OUTLET_FLUX, W.ENSEMBLE_STEPS, K)
@@ -318,9 +322,7 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int):
         import oracle
         k = int(np.argmin([m.Lx * m.Ly for m in members]))
         m = members[k]
-        for s in sv:
-            s.close()
-        b.close()
+        _close_all(sv, b)
         sg = lbm.Solver(params(m), eps[k])
         sg.step(W.ENSEMBLE_STEPS)
         mg = sg.moments(want_diag=False)
@@ -337,12 +339,15 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int):
                                      f"{W.ENSEMBLE_STEPS} steps"}
         log(f"[bench] ensemble accuracy {out['accuracy']['rel_l2_u_vs_fp64_oracle']:.3e}")
     else:
-        for s in sv:
-            s.close()
-        b.close()
-    del sv, b
+        _close_all(sv, b)
     torch.cuda.empty_cache()
     return out
+
+
+def _close_all(solvers, batch):
+    batch.close()
+    for s in solvers:
+        s.close()
 
 
 def main():
@@ -361,6 +366,8 @@ def main():
                     help="skip the gradient leg (1024x512 open channel) reported beside the main line")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the ensemble leg (64 uneven open channels) reported beside the main line")
+    ap.add_argument("--ensemble-steps", type=int, default=2000,
+                    help="timed steps of the ensemble leg (--no-adjoint also skips its gradient)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sweep has no multi-GPU path in this build "
@@ -416,7 +423,8 @@ def main():
 
     ens = None
     if not args.no_ensemble and args.workload == "box4096_f32":
-        ens = ensemble_leg(lbm, torch, args.no_accuracy, 2000, args.warmup)
+        ens = ensemble_leg(lbm, torch, args.no_accuracy, args.ensemble_steps, args.warmup,
+                           not args.no_adjoint)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -405,9 +405,14 @@ struct EpsTile {
             const int k = threadIdx.x + j * NTHREADS;
             if (k < N) {
                 const int ly = k / W, lx = k - ly * W;
-                const int gx = halo_index(x0 + lx - 1, g.Lx, g.wall_x);
-                const int gy = halo_index(y0 + ly - 1, g.Ly, g.wall_y);
-                v[j] = eps[(long long)gy * g.pitch + gx];
+                // columns beyond the right halo only feed the nodes past the row end
+                if (x0 + lx - 1 <= g.Lx) {
+                    const int gx = halo_index(x0 + lx - 1, g.Lx, g.wall_x);
+                    const int gy = halo_index(y0 + ly - 1, g.Ly, g.wall_y);
+                    v[j] = eps[(long long)gy * g.pitch + gx];
+                } else {
+                    v[j] = R(1);
+                }
             }
         }
     }
@@ -688,14 +693,19 @@ __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], in
         wyp ? F[5] + r0 + x : F[7] + rp + x,
         wyp ? F[6] + r0 + x : F[8] + rp + x,
     };
+    // Lanes past the end of the row (last tile column) all read the row's
+    // first vector instead (one shared line, no traffic of their own).
+    const bool live = x < g.Lx;
     vt raw[9];
 #pragma unroll
-    for (int i = 0; i < 9; i++) raw[i] = load_raw(reinterpret_cast<const vt *>(src[i]));
+    for (int i = 0; i < 9; i++)
+        raw[i] = load_raw(reinterpret_cast<const vt *>(live ? src[i] : F[i] + r0));
     // Values entering from the left (e_1, e_5, e_8) for the first node and from
     // the right (e_3, e_6, e_7) for the last node, where the adjacent lane does
     // not hold them: beyond a wall, the edge node's own opposite population.
     S el[3] = {S(0), S(0), S(0)}, er[3] = {S(0), S(0), S(0)};
-    if (L.wl) {
+    if (!live) {
+    } else if (L.wl) {
         el[0] = load_raw(F[3] + r0 + x);
         el[1] = load_raw(F[7] + r0 + x);
         el[2] = load_raw(F[6] + r0 + x);
@@ -704,7 +714,8 @@ __device__ __forceinline__ void gather_vec(R (&d)[9][V], const S *const F[9], in
         el[1] = load_raw(F[5] + rm + L.xl);
         el[2] = load_raw(F[8] + rp + L.xl);
     }
-    if (L.wr) {
+    if (!live) {
+    } else if (L.wr) {
         er[0] = load_raw(F[1] + r0 + L.last);
         er[1] = load_raw(F[8] + r0 + L.last);
         er[2] = load_raw(F[5] + r0 + L.last);

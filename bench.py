@@ -31,7 +31,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E peak
 PROFILE_TRAFFIC = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_traffic_box4096_f32.md"),
-                   "box8192_f16": os.path.join(ROOT, "profiles", "sweep_traffic_box8192_f16.md")}
+                   "box8192_f16": os.path.join(ROOT, "profiles", "sweep_traffic_box8192_f16.md"),
+                   "ensemble64_f32": os.path.join(ROOT, "profiles",
+                                                  "sweep_traffic_ensemble64_f32.md")}
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
 
 
@@ -291,7 +293,9 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
            "plain_launches_ms_per_step": round(t_plain * 1e3 / steps, 5),
            "tuned": best, "trials": trials,
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS,
-                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4),
+                        "traffic": (measured_traffic("ensemble64_f32")
+                                    if best["vec"] == 4 and len(members) == 64 else None),
                         "kernel": "k_batch_sweep", "bytes_per_node": bpn}}
     log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
         f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")

@@ -69,6 +69,7 @@ class _Params(ctypes.Structure):
         ("rho0", ctypes.c_double), ("u0x", ctypes.c_double), ("u0y", ctypes.c_double),
         ("rho_in", ctypes.c_double), ("u_in", ctypes.c_double),
         ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double),
+        ("uw_bot", ctypes.c_double), ("uw_top", ctypes.c_double),
     ]
 
 
@@ -93,11 +94,14 @@ class Params:
     u_in: float = 0.0
     rho_out: float = 1.0
     u_out: float = 0.0
+    uw_bot: float = 0.0     # WALL in y: x-velocity of the lower plate (sliding wall)
+    uw_top: float = 0.0     # WALL in y: x-velocity of the upper plate
 
     def c(self) -> _Params:
         return _Params(self.Lx, self.Ly, self.bc_x, self.bc_y, self.drag, 0, self.tau,
                        self.d_p, self.K, self.F_eps, self.Gx, self.Gy, self.rho0,
-                       self.u0x, self.u0y, self.rho_in, self.u_in, self.rho_out, self.u_out)
+                       self.u0x, self.u0y, self.rho_in, self.u_in, self.rho_out, self.u_out,
+                       self.uw_bot, self.uw_top)
 
 
 _lib = None

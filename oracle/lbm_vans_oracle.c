@@ -40,6 +40,13 @@
  *     exactly (the root is unique, see orc_velocity);
  *   - walls are half-way bounce-back: a population that would stream into a
  *     wall node returns to its own cell with the opposite velocity;
+ *   - the plates of the Couette experiment (Section "Examples and
+ *     discussions") slide along x: a y-wall moving with velocity (u_w, 0)
+ *     returns the population with the momentum the moving wall imparts,
+ *     f_j(x) = f*_i(x) + 6 w_j eps(x) rho0 (e_j . u_w) with j the opposite of
+ *     i: the equilibrium's first-order term of eq. (d2q9eq) taken at the wall
+ *     velocity (density rho0), twice, as in the moving-wall bounce-back rule
+ *     for the plain lattice BGK model;
  *   - the initial state is f_i = f_i^eq(eps(x) rho0, u0);
  *   - open x-boundaries (inflow / outflow): the paper prescribes none for a
  *     through-flow channel; a population entering the domain across x = 0
@@ -84,6 +91,8 @@ typedef struct {
     double rho0, u0x, u0y; /* initial state                                    */
     double rho_in, u_in;   /* ORC_OPEN: density and x-velocity of the inflow reservoir  */
     double rho_out, u_out; /* ORC_OPEN: density and x-velocity of the outflow reservoir */
+    double uw_bot, uw_top; /* ORC_WALL in y: x-velocity of the wall below y = 0 and of the
+                              wall above y = Ly-1 (sliding plates)                      */
 } orc_params;
 
 void orc_lattice(int32_t ex[9], int32_t ey[9], double w[9], int32_t opp[9], double *cs2)
@@ -323,12 +332,21 @@ static int source_behind_ywall(const orc_params *p, int y, int i)
     return p->bc_y == ORC_WALL && (ys < 0 || ys >= p->Ly);
 }
 
+/* Momentum gain per unit porosity of population j when it leaves a y-wall
+ * that slides with x-velocity u_w: 6 w_j rho0 (e_j . u_w). */
+static double wall_gain(const orc_params *p, int j, int top)
+{
+    double uw = top ? p->uw_top : p->uw_bot;
+    return 6.0 * W[j] * p->rho0 * (EX[j] * uw);
+}
+
 /* Streaming (push):  f_i(x + e_i) = f*_i(x).  Along a periodic axis the
  * target wraps around; a target beyond a wall sends the population back to
- * its own cell as the opposite direction (half-way bounce-back); a target
- * beyond an open x-boundary leaves the domain.  Beyond a y-wall bounce-back
- * takes precedence.  Then the populations that enter across an open
- * x-boundary are set from the reservoirs.  Every slot of f is written once. */
+ * its own cell as the opposite direction (half-way bounce-back), plus the
+ * gain of a sliding y-wall; a target beyond an open x-boundary leaves the
+ * domain.  Beyond a y-wall bounce-back takes precedence.  Then the
+ * populations that enter across an open x-boundary are set from the
+ * reservoirs.  Every slot of f is written once. */
 void orc_stream(const orc_params *p, const double *eps, const double *fpost, double *f,
                 int nthreads)
 {
@@ -342,10 +360,10 @@ void orc_stream(const orc_params *p, const double *eps, const double *fpost, dou
             size_t c = (size_t)y * Lx + x;
             for (int i = 0; i < 9; i++) {
                 int xt = x + EX[i], yt = (int)y + EY[i];
-                int wall = 0, gone = 0;
+                int wall = 0, gone = 0, ywall = 0;
                 if (yt < 0 || yt >= Ly) {
                     if (p->bc_y == ORC_PERIODIC) yt = (int)((yt + Ly) % Ly);
-                    else wall = 1;
+                    else wall = ywall = 1;
                 }
                 if (!wall && (xt < 0 || xt >= Lx)) {
                     if (p->bc_x == ORC_PERIODIC) xt = (xt + Lx) % Lx;
@@ -353,7 +371,10 @@ void orc_stream(const orc_params *p, const double *eps, const double *fpost, dou
                     else gone = 1;
                 }
                 if (gone) continue;
-                if (wall)
+                if (ywall)
+                    f[OPP[i] * N + c] = fpost[i * N + c] +
+                                        wall_gain(p, OPP[i], yt >= Ly) * eps[c];
+                else if (wall)
                     f[OPP[i] * N + c] = fpost[i * N + c];
                 else
                     f[i * N + (size_t)yt * Lx + xt] = fpost[i * N + c];
@@ -636,8 +657,13 @@ int orc_grad_outlet_flux(const orc_params *p, const double *eps, int64_t nsteps,
                     int xt = x + EX[i], yt = y + EY[i];
                     int wall = 0, gone = 0;
                     if (yt < 0 || yt >= Ly) {
-                        if (p->bc_y == ORC_PERIODIC) yt = (yt + Ly) % Ly;
-                        else wall = 1;
+                        if (p->bc_y == ORC_PERIODIC) {
+                            yt = (yt + Ly) % Ly;
+                        } else {
+                            wall = 1;
+                            /* the sliding wall's gain is eps(x) times a constant */
+                            dJdeps[c] += fbar[OPP[i] * N + c] * wall_gain(p, OPP[i], yt >= Ly);
+                        }
                     }
                     if (!wall && (xt < 0 || xt >= Lx)) {
                         if (p->bc_x == ORC_PERIODIC) xt = (xt + Lx) % Lx;

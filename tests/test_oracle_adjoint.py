@@ -146,3 +146,23 @@ def test_gradient_periodic_and_const_drag(orc):
         jm = orc.outlet_flux(p, e, orc.run(p, e, n))
         fd = (jp - jm) / (2 * h)
         assert abs(g[y, x] - fd) <= 1e-7 * np.abs(g).max()
+
+
+def test_gradient_with_sliding_walls(orc):
+    """Open channel between plates sliding in opposite directions: the reverse pass
+    against central differences of J at every node."""
+    Lx, Ly, n = 10, 6, 50
+    p = _open_channel(orc, Lx, Ly, walls=True, uw_bot=-0.03, uw_top=0.05, u0x=0.01)
+    eps = W.grf_porosity(Lx, Ly, seed=35, ell=2.5, lo=0.4, hi=0.95)
+    J, g = orc.grad_outlet_flux(p, eps, n)
+    h = 1e-6
+    fd = np.zeros_like(eps)
+    for y in range(Ly):
+        for x in range(Lx):
+            e = eps.copy()
+            e[y, x] += h
+            jp = orc.outlet_flux(p, e, orc.run(p, e, n))
+            e[y, x] -= 2 * h
+            jm = orc.outlet_flux(p, e, orc.run(p, e, n))
+            fd[y, x] = (jp - jm) / (2 * h)
+    assert np.abs(g - fd).max() <= 1e-7 * np.abs(fd).max()

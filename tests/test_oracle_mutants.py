@@ -61,6 +61,19 @@ MUTANTS = {
     "adjoint_init_dropped": ("for (int i = 0; i < 9; i++) dJdeps[c] += fbar[i * N + c] * feq1[i];",
                              "for (int i = 0; i < 9; i++) dJdeps[c] += 0.0 * feq1[i];"),
     "adjoint_stencil_sign": ("dJdeps[cn] += (gxb[c] * W[i] * EX[i]", "dJdeps[cn] -= (gxb[c] * W[i] * EX[i]"),
+    # sliding walls
+    "wall_gain_sign": ("return 6.0 * W[j] * p->rho0 * (EX[j] * uw);",
+                       "return -6.0 * W[j] * p->rho0 * (EX[j] * uw);"),
+    "wall_gain_missing_factor_two": ("return 6.0 * W[j] * p->rho0 * (EX[j] * uw);",
+                                     "return 3.0 * W[j] * p->rho0 * (EX[j] * uw);"),
+    "wall_gain_plates_swapped": ("double uw = top ? p->uw_top : p->uw_bot;",
+                                 "double uw = top ? p->uw_bot : p->uw_top;"),
+    "wall_gain_ignores_porosity": ("wall_gain(p, OPP[i], yt >= Ly) * eps[c];",
+                                   "wall_gain(p, OPP[i], yt >= Ly);"),
+    "ywall_bounce_same_direction": ("f[OPP[i] * N + c] = fpost[i * N + c] +",
+                                    "f[i * N + c] = fpost[i * N + c] +"),
+    "adjoint_wall_gain_dropped": ("dJdeps[c] += fbar[OPP[i] * N + c] * wall_gain(p, OPP[i], yt >= Ly);",
+                                  "dJdeps[c] += 0.0;"),
 }
 
 

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 3
+#define LBM_VANS_ABI_VERSION 4
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -58,7 +58,8 @@ extern "C" {
 
 /* Boundary kind of one axis (applies to both ends of that axis). */
 #define LBM_BC_PERIODIC 0   /* wrap-around streaming (Section "Examples and discussions") */
-#define LBM_BC_BOUNCEBACK 1 /* half-way bounce-back wall beyond node -1/2 and L-1/2       */
+#define LBM_BC_BOUNCEBACK 1 /* half-way bounce-back wall beyond node -1/2 and L-1/2; the
+                               y-walls may slide along x (lbm_vans_params.u_wall)         */
 #define LBM_BC_OPEN 2       /* x only: inflow reservoir beyond x = 0, outflow reservoir
                                beyond x = Lx-1.  From state n = 1 on, a population that
                                enters across an open end is the equilibrium (eq. (d2q9eq))
@@ -104,6 +105,12 @@ typedef struct lbm_vans_params {
                               during lbm_vans_step; 0: none                           */
     double rho_in, u_in;   /* LBM_BC_OPEN: inflow reservoir density (> 0), x-velocity  */
     double rho_out, u_out; /* LBM_BC_OPEN: outflow reservoir density (> 0), x-velocity */
+    double u_wall[2];      /* LBM_BC_BOUNCEBACK in y: x-velocity of the wall below y = 0
+                              and of the wall above y = Ly-1 (sliding plates, as the
+                              Couette experiment of Section "Examples and discussions");
+                              0 otherwise.  A population returned by a sliding wall gains
+                              6 w_i eps(x) rho0 (e_i . u_w), the momentum the moving wall
+                              imparts under half-way bounce-back.                     */
 } lbm_vans_params;
 
 typedef struct lbm_vans_handle lbm_vans_handle;

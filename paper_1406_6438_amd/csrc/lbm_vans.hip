@@ -187,6 +187,10 @@ struct Phys {
     // second state on (the initial state is the equilibrium everywhere).
     int reservoir;
     R rin[9], rout[9];
+    // Sliding y-walls: a population leaving the wall below y = 0 (above
+    // y = Ly-1) gains eps * 6 w_j rho0 (e_j . u_w); for the diagonals that is
+    // +-eps * wb (+-eps * wt) with wb = rho0 u_bottom / 6, wt = rho0 u_top / 6.
+    R wb, wt;
 };
 
 // Reciprocal and square root of the compute type: the hardware instructions
@@ -541,12 +545,13 @@ __device__ __forceinline__ void unshift_incoming(R d[9], const PorNb<R> &P, R rh
     d[8] += h2 * P.D[6];
 }
 
-// Incoming populations across an open x end are the reservoir's (not
-// behind a y-wall, where bounce-back wins).  open_l / open_r: the node is the
-// first / last of an open x axis and reservoirs are active.
+// Incoming values set by the boundaries rather than by a stored slot: the
+// reservoir equilibria when the node is the first / last of an open x axis and
+// reservoirs are active (a y-wall wins at the corners), and the momentum a
+// sliding y-wall adds to the diagonals it returns.
 template <typename R>
-__device__ __forceinline__ void reservoir_inflow(R d[9], R e0, bool open_l, bool open_r,
-                                                 bool wym, bool wyp, const Phys<R> &ph)
+__device__ __forceinline__ void boundary_inflow(R d[9], R e0, bool open_l, bool open_r,
+                                                bool wym, bool wyp, const Phys<R> &ph)
 {
     if (open_l) {
         d[1] = e0 * ph.rin[1];
@@ -557,6 +562,14 @@ __device__ __forceinline__ void reservoir_inflow(R d[9], R e0, bool open_l, bool
         d[3] = e0 * ph.rout[3];
         if (!wym) d[6] = e0 * ph.rout[6];
         if (!wyp) d[7] = e0 * ph.rout[7];
+    }
+    if (wym) {
+        d[5] += e0 * ph.wb;
+        d[6] -= e0 * ph.wb;
+    }
+    if (wyp) {
+        d[8] += e0 * ph.wt;
+        d[7] -= e0 * ph.wt;
     }
 }
 
@@ -573,7 +586,7 @@ __device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, in
                                             bool count)
 {
     const PorNb<R> P = porosity_nb<R, W>(t, lyy, lx, wxm, wxp, wym, wyp);
-    reservoir_inflow<R>(d, P.e0, open_l, open_r, wym, wyp, ph);
+    boundary_inflow<R>(d, P.e0, open_l, open_r, wym, wyp, ph);
     unshift_incoming<R>(d, P, ph.rho0);
     Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
     if constexpr (DIAG) {
@@ -888,7 +901,7 @@ __global__ __launch_bounds__(NTHREADS) void k_moments(const S *__restrict__ fin,
             gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
             const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
             const bool ores = g.open_x && ph.reservoir;
-            reservoir_inflow<R>(d, P.e0, ores && x == 0, ores && x == g.Lx - 1, n.wym, n.wyp, ph);
+            boundary_inflow<R>(d, P.e0, ores && x == 0, ores && x == g.Lx - 1, n.wym, n.wyp, ph);
             unshift_incoming<R>(d, P, ph.rho0);
             Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
             accumulate<R>(acc, N);
@@ -965,35 +978,51 @@ __device__ __forceinline__ double wgt(int i)
 
 __device__ constexpr int OPPI[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
-// Node that pulls slot (i, x, y) next, and the direction it pulls it as.
+// Node that pulls slot (i, x, y) next, and the direction it pulls it as;
+// ywall: the slot returns from a y-wall (-1 below, +1 above, 0 otherwise).
 __device__ __forceinline__ void reader(int i, int x, int y, const Geo &g, int &rx, int &ry,
-                                       int &ri)
+                                       int &ri, int &ywall)
 {
     int tx = x + CX[i], ty = y + CY[i];
     bool wall = false;
+    ywall = 0;
     if (tx < 0 || tx >= g.Lx) {
         if (g.wall_x) wall = true;
         else tx = tx < 0 ? tx + g.Lx : tx - g.Lx;
     }
     if (ty < 0 || ty >= g.Ly) {
-        if (g.wall_y) wall = true;
-        else ty = ty < 0 ? ty + g.Ly : ty - g.Ly;
+        if (g.wall_y) {
+            wall = true;
+            ywall = ty < 0 ? -1 : 1;
+        } else {
+            ty = ty < 0 ? ty + g.Ly : ty - g.Ly;
+        }
     }
     if (wall) { rx = x; ry = y; ri = OPPI[i]; }
     else { rx = tx; ry = ty; ri = i; }
+}
+
+// Gain per unit porosity of population j returned by a sliding y-wall
+// (ywall -1: the wall below, +1: above), 6 w_j rho0 (e_j . u_w), in FP64.
+__device__ __forceinline__ double wall_gain(int j, int ywall, double wb6, double wt6)
+{
+    if (ywall == 0 || CX[j] == 0) return 0.0;
+    return CX[j] * (ywall < 0 ? wb6 : wt6);
 }
 
 // Writes the storage of a plain state f(., n): fplain == nullptr means the
 // equilibrium f_i = f_i^eq(eps rho0, u0) of eq. (d2q9eq) (the initial state).
 // rho_ref is the shift reference rho0 as the sweep sees it (rounded to R), so
 // that the stored deviations and the sweep's rest state agree exactly.
+// wb6, wt6: rho0 u_w / 6 of the sliding y-walls (below, above): a slot that
+// returns from such a wall is stored without the gain the reader adds.
 template <typename S, typename R>
 __global__ __launch_bounds__(NTHREADS) void k_set_state(S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
                                                         double rho0, double rho_ref,
                                                         double u0x, double u0y,
                                                         const double *__restrict__ fplain,
-                                                        R scale)
+                                                        R scale, double wb6, double wt6)
 {
     const int t = blockIdx.x;
     const int bx = t % g.nbx, by = t / g.nbx;
@@ -1002,8 +1031,8 @@ __global__ __launch_bounds__(NTHREADS) void k_set_state(S *__restrict__ fout,
         const int y = by * TY + threadIdx.x / TX + NW * r;
         if (x >= g.Lx || y >= g.Ly) continue;
         for (int i = 0; i < 9; i++) {
-            int rx, ry, ri;
-            reader(i, x, y, g, rx, ry, ri);
+            int rx, ry, ri, yw;
+            reader(i, x, y, g, rx, ry, ri, yw);
             // stored = f_ri(reader) - w rho_ref (eps(x) + eps(reader)) / 2
             double er = static_cast<double>(eps[(long long)ry * g.pitch + rx]);
             double es = static_cast<double>(eps[(long long)y * g.pitch + x]);
@@ -1018,6 +1047,7 @@ __global__ __launch_bounds__(NTHREADS) void k_set_state(S *__restrict__ fout,
                 dev = w * (er * ((rho0 - rho_ref) + rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)) +
                            0.5 * rho_ref * (er - es));
             }
+            dev -= wall_gain(ri, yw, wb6, wt6) * er;
             S *p = fout + i * g.plane + (long long)y * g.pitch + x;
             if constexpr (std::is_same_v<S, _Float16>)
                 *p = static_cast<_Float16>(static_cast<R>(dev) * scale);
@@ -1052,7 +1082,7 @@ __global__ __launch_bounds__(NTHREADS) void k_get_state(const S *__restrict__ fi
         gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
         const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
         const bool ores = g.open_x && ph.reservoir;
-        reservoir_inflow<R>(d, P.e0, ores && x == 0, ores && x == g.Lx - 1, n.wym, n.wyp, ph);
+        boundary_inflow<R>(d, P.e0, ores && x == 0, ores && x == g.Lx - 1, n.wym, n.wyp, ph);
         unshift_incoming<R>(d, P, ph.rho0);
         const double e0 = static_cast<double>(P.e0);
         for (int i = 0; i < 9; i++)
@@ -1206,7 +1236,7 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
         const bool ores = g.open_x && ph.reservoir;
         const bool ol = ores && x == 0, orr = ores && x == g.Lx - 1;
-        reservoir_inflow<R>(d, P.e0, ol, orr, n.wym, n.wyp, ph);
+        boundary_inflow<R>(d, P.e0, ol, orr, n.wym, n.wyp, ph);
         unshift_incoming<R>(d, P, ph.rho0);
         const int c = y * g.pitch + x;
         R mu[9];
@@ -1241,6 +1271,9 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
             if (res[6]) e_b += nu[6] * (ph.rout[6] + w2 * ph.rho0);
             if (res[7]) e_b += nu[7] * (ph.rout[7] + w2 * ph.rho0);
         }
+        // sliding y-walls: the returned diagonals carry +-eps * wb (wt)
+        if (n.wym) e_b += (nu[5] - nu[6]) * ph.wb;
+        if (n.wyp) e_b += (nu[8] - nu[7]) * ph.wt;
         // push: the slot each incoming population came from (as in gather)
         const int rm = n.ym * g.pitch, r0 = y * g.pitch, rp = n.yp * g.pitch;
         const long long pl = g.plane;
@@ -1281,6 +1314,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
 template <typename R>
 __global__ __launch_bounds__(NTHREADS) void k_adjoint_init(const R *__restrict__ lam, Geo g,
                                                            double rho0, double u0x, double u0y,
+                                                           double wb6, double wt6,
                                                            double *__restrict__ eb)
 {
     const int t = blockIdx.x;
@@ -1310,6 +1344,13 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint_init(const R *__restrict__
             s += static_cast<double>(lam[src[i]]) * wgt(i) * rho0 *
                  (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
         }
+        // the initial slots behind a sliding wall are stored without the gain the
+        // first gather adds (the initial state is the equilibrium): its porosity
+        // term, which the reverse step of that gather counted, cancels here
+        if (n.wym)
+            s -= (static_cast<double>(lam[src[5]]) - static_cast<double>(lam[src[6]])) * wb6;
+        if (n.wyp)
+            s -= (static_cast<double>(lam[src[8]]) - static_cast<double>(lam[src[7]])) * wt6;
         eb[c] += s;
     }
 }
@@ -1556,6 +1597,10 @@ int check_params(const lbm_vans_params *p)
     if (p->storage == LBM_F16_SHIFTED && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24))
         return fail(LBM_VANS_EINVAL, "fp16_scale_log2 = %d outside 0..24", p->fp16_scale_log2);
     if (p->diag_every < 0) return fail(LBM_VANS_EINVAL, "diag_every = %d < 0", p->diag_every);
+    if (!std::isfinite(p->u_wall[0]) || !std::isfinite(p->u_wall[1]))
+        return fail(LBM_VANS_EINVAL, "u_wall must be finite");
+    if (p->bc_y != LBM_BC_BOUNCEBACK && (p->u_wall[0] != 0.0 || p->u_wall[1] != 0.0))
+        return fail(LBM_VANS_EINVAL, "u_wall needs bounce-back walls in y (bc_y)");
     return LBM_VANS_OK;
 }
 
@@ -1636,8 +1681,13 @@ Phys<R> make_phys(const lbm_vans_params *p)
         ph.rout[i] = cx[i] < 0 ? static_cast<R>(wt[i] * (p->rho_out * pout - rho_ref)) : R(0);
     }
     ph.reservoir = 0;
+    ph.wb = static_cast<R>(p->rho0 * p->u_wall[0] / 6.0);
+    ph.wt = static_cast<R>(p->rho0 * p->u_wall[1] / 6.0);
     return ph;
 }
+
+// rho0 u_w / 6 of the sliding y-walls in FP64 (init, set_state, adjoint init).
+double wall6(const lbm_vans_params *p, int top) { return p->rho0 * p->u_wall[top] / 6.0; }
 
 int check_launch(const char *what)
 {
@@ -1781,7 +1831,7 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
         hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
                            (S *)h->buf[0], (const R *)h->eps, h->g, p->rho0,
                            static_cast<double>(ph.rho0), p->u0[0], p->u0[1],
-                           (const double *)nullptr, ph.scale);
+                           (const double *)nullptr, ph.scale, wall6(p, 0), wall6(p, 1));
         r = check_launch("k_set_state");
         if (r) return r;
         // The host value m0 must stay alive until the copy has run.
@@ -1870,7 +1920,8 @@ int lbm_vans_set_state(lbm_vans_handle *h, const void *f)
         Phys<R> ph = make_phys<R>(&h->p);
         hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
                            (S *)h->buf[h->cur], (const R *)h->eps, h->g, h->p.rho0,
-                           static_cast<double>(ph.rho0), 0.0, 0.0, (const double *)f, ph.scale);
+                           static_cast<double>(ph.rho0), 0.0, 0.0, (const double *)f, ph.scale,
+                           wall6(&h->p, 0), wall6(&h->p, 1));
         return check_launch("k_set_state");
     });
 }
@@ -1972,7 +2023,8 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
         hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
                            (S *)h->buf[0], (const R *)h->eps, g, h->p.rho0,
                            static_cast<double>(ph0.rho0), h->p.u0[0], h->p.u0[1],
-                           (const double *)nullptr, ph0.scale);
+                           (const double *)nullptr, ph0.scale, wall6(&h->p, 0),
+                           wall6(&h->p, 1));
         int r = check_launch("k_set_state");
         if (r) return r;
         h->cur = 0;
@@ -2030,7 +2082,8 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
         }
         // 4. initial state and the porosity stencil
         hipLaunchKernelGGL((k_adjoint_init<R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
-                           (const R *)lam[a], g, h->p.rho0, h->p.u0[0], h->p.u0[1], eb);
+                           (const R *)lam[a], g, h->p.rho0, h->p.u0[0], h->p.u0[1],
+                           wall6(&h->p, 0), wall6(&h->p, 1), eb);
         r = check_launch("k_adjoint_init");
         if (r) return r;
         hipLaunchKernelGGL(k_adjoint_finish, dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
@@ -2500,7 +2553,8 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
             hipLaunchKernelGGL((k_set_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0,
                                b->stream, (S *)h->buf[0], (const R *)h->eps, h->g, h->p.rho0,
                                static_cast<double>(ph0.rho0), h->p.u0[0], h->p.u0[1],
-                               (const double *)nullptr, ph0.scale);
+                               (const double *)nullptr, ph0.scale, wall6(&h->p, 0),
+                               wall6(&h->p, 1));
             int r = check_launch("k_set_state");
             if (r) return r;
             h->cur = 0;
@@ -2569,7 +2623,8 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
             double *gxb = eb + G[k].acc / sizeof(double);
             double *gyb = gxb + G[k].acc / sizeof(double);
             hipLaunchKernelGGL((k_adjoint_init<R>), dim3(h->ntiles), dim3(NTHREADS), 0,
-                               b->stream, lam, h->g, h->p.rho0, h->p.u0[0], h->p.u0[1], eb);
+                               b->stream, lam, h->g, h->p.rho0, h->p.u0[0], h->p.u0[1],
+                               wall6(&h->p, 0), wall6(&h->p, 1), eb);
             r = check_launch("k_adjoint_init");
             if (r) return r;
             hipLaunchKernelGGL(k_adjoint_finish, dim3(h->ntiles), dim3(NTHREADS), 0, b->stream,

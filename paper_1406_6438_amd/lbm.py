@@ -27,7 +27,7 @@ F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
 DRAG_ERGUN, DRAG_CONST = 0, 1
 NDIAG = 8
 DIAG_RING = 4096
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
@@ -53,6 +53,7 @@ class LbmVansParams(ctypes.Structure):
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
         ("rho_in", ctypes.c_double), ("u_in", ctypes.c_double),
         ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double),
+        ("u_wall", ctypes.c_double * 2),
     ]
 
 
@@ -88,13 +89,15 @@ class Params:
     u_in: float = 0.0
     rho_out: float = 1.0
     u_out: float = 0.0
+    u_wall: tuple = (0.0, 0.0)
 
     def c(self) -> LbmVansParams:
         return LbmVansParams(self.Lx, self.Ly, self.bc_x, self.bc_y, self.storage, self.drag,
                              self.tau, self.d_p, self.K, self.F_eps,
                              (ctypes.c_double * 2)(*self.G), self.rho0,
                              (ctypes.c_double * 2)(*self.u0), self.fp16_scale_log2,
-                             self.diag_every, self.rho_in, self.u_in, self.rho_out, self.u_out)
+                             self.diag_every, self.rho_in, self.u_in, self.rho_out, self.u_out,
+                             (ctypes.c_double * 2)(*self.u_wall))
 
 
 class LbmVansError(RuntimeError):

@@ -185,3 +185,36 @@ def ensemble(n: int = ENSEMBLE_MEMBERS, lmin: int = 256, lmax: int = 2048,
         out.append(Member(Lx=lx, Ly=ly, tau=float(tau[k]),
                           d_p=ergun_dp_for_darcy(1e-2, float(ly), 0.65), seed=seed + 1 + k))
     return out
+
+# The paper's Couette experiment (Section "Examples and discussions"): an
+# 80 x 80 lattice of uniform porosity 0.1 between two plates, the lower at
+# rest (wall at y = -1/2), the upper sliding along x with velocity U (wall at
+# y = 79.5), periodic in x; tau = 0.6574 at Re = 50, else 0.8; U = Re nu / 80;
+# K = Da 80^2 through the Ergun closure; density 1 and velocity 0 at the
+# start.  The paper's figure plots profiles "at different Re and Da" without
+# listing them; the cases below span Re 0.1..50 and Da 1e-3..1e-1.  160000
+# steps bring every case to a steady state (changes below 1e-11 U per 5000
+# steps).
+COUETTE_L = 80
+COUETTE_EPS = 0.1
+COUETTE_STEPS = 160000
+COUETTE_CASES = ((50.0, 1e-2), (10.0, 1e-2), (1.0, 1e-2), (0.1, 1e-2), (1.0, 1e-1), (1.0, 1e-3))
+
+
+@dataclasses.dataclass(frozen=True)
+class CouetteCase:
+    Re: float
+    Da: float
+    tau: float
+    nu: float
+    U: float
+    K: float
+    d_p: float
+
+
+def couette_case(Re: float, Da: float, L: int = COUETTE_L, eps: float = COUETTE_EPS) -> CouetteCase:
+    tau = 0.6574 if Re == 50.0 else 0.8
+    nu = (tau - 0.5) / 3.0
+    K = Da * L * L
+    d_p = math.sqrt(150.0 * K * (1.0 - eps) ** 2 / eps ** 3)
+    return CouetteCase(Re=Re, Da=Da, tau=tau, nu=nu, U=Re * nu / L, K=K, d_p=d_p)

@@ -33,6 +33,7 @@ class Spec:
     u_in: float = 0.0
     rho_out: float = 1.0
     u_out: float = 0.0
+    u_wall: tuple = (0.0, 0.0)      # sliding y-walls: x-velocity below, above
 
     def oracle(self) -> oracle.Params:
         return oracle.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
@@ -43,7 +44,7 @@ class Spec:
                              d_p=self.d_p, K=self.K, F_eps=self.F_eps, Gx=self.G[0],
                              Gy=self.G[1], rho0=self.rho0, u0x=self.u0[0], u0y=self.u0[1],
                              rho_in=self.rho_in, u_in=self.u_in, rho_out=self.rho_out,
-                             u_out=self.u_out)
+                             u_out=self.u_out, uw_bot=self.u_wall[0], uw_top=self.u_wall[1])
 
     def gpu(self):
         from paper_1406_6438_amd import lbm
@@ -57,7 +58,7 @@ class Spec:
                           rho0=self.rho0, u0=tuple(self.u0),
                           fp16_scale_log2=self.fp16_scale_log2, diag_every=self.diag_every,
                           rho_in=self.rho_in, u_in=self.u_in, rho_out=self.rho_out,
-                          u_out=self.u_out)
+                          u_out=self.u_out, u_wall=tuple(self.u_wall))
 
     def input_eps(self, eps: np.ndarray) -> np.ndarray:
         """The porosity both sides receive: rounded once to the GPU's compute precision."""

@@ -8,11 +8,13 @@ A step is one time step of the method over the whole lattice (one sweep
 launch).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line with MLUPS, the HBM roofline of the sweep kernel, the
-accuracy of the FP32 sweep against the FP64 oracle on the 512^2 crop (the error
-the throughput is quoted at), the FP16-storage sweep on the 8192^2 box beside it
-(throughput, roofline, accuracy after 2000 steps on its 512^2 crop), the
-gradient leg, the ensemble leg (64 uneven channels, batched launches) and the
-oracle's own throughput on the host cores.
+FP16-storage sweep on the 8192^2 box beside it, the gradient leg, the ensemble
+leg (64 uneven channels, batched launches) and the CPU baseline: the FP64
+oracle timed on the host cores on bounded samples of the workloads.  The
+oracle runs only in that leg; its sample results also give the accuracy
+figures (the GPU runs the same samples -- the 512^2 crops of the boxes, a small
+channel for the gradient, the smallest ensemble member -- and the fields are
+compared afterwards).  --no-cpu-baseline therefore also drops the accuracy.
 
   python bench.py [--steps K] [--warmup W] [--workload box4096_f32|box8192_f16|channel_f64]
 """
@@ -100,14 +102,27 @@ def cast_eps(eps, storage):
     import numpy as np
     return eps if storage == "f64" else eps.astype(np.float32).astype(np.float64)
 
-
-def cpu_baseline(w, eps, budget_s: float):
-    """The FP64 oracle timed on the host cores on a bounded sample of the workload:
-    the full lattice for as many whole steps as fit in the time budget."""
-    import numpy as np
+def oracle_params(spec: dict):
+    """oracle.Params from a plain description: the GPU legs describe their accuracy
+    samples as data, and only the CPU-baseline leg touches the oracle."""
     import oracle
-    p = oracle.Params(Lx=w.Lx, Ly=w.Ly, tau=w.tau, bc_y=oracle.WALL if w.walls_y else oracle.PERIODIC,
-                      d_p=w.d_p, Gx=w.Gx, Gy=w.Gy, rho0=w.rho0)
+    kw = dict(spec)
+    for k in ("bc_x", "bc_y"):
+        kw[k] = {"periodic": oracle.PERIODIC, "wall": oracle.WALL,
+                 "open": oracle.OPEN}[kw.get(k, "periodic")]
+    return oracle.Params(**kw)
+
+
+def cpu_baseline_leg(w, eps, budget_s: float, jobs: list):
+    """The FP64 oracle on the host cores: (1) the full lattice of the main workload for as
+    many whole steps as fit in the time budget (the reported rate); (2) the accuracy
+    samples the GPU legs ran (each job: oracle parameters, porosity, steps and kind, "u"
+    for the final velocity field or "grad" for the outlet-flux gradient), timed too.
+    Returns (the cpu_baseline dict, the oracle result of every job)."""
+    import oracle
+    spec = {"Lx": w.Lx, "Ly": w.Ly, "tau": w.tau, "bc_y": "wall" if w.walls_y else "periodic",
+            "d_p": w.d_p, "Gx": w.Gx, "Gy": w.Gy, "rho0": w.rho0}
+    p = oracle_params(spec)
     threads = oracle.default_threads()
     e = cast_eps(eps, w.storage)
     f = oracle.init(p, e)
@@ -119,31 +134,57 @@ def cpu_baseline(w, eps, budget_s: float):
     oracle.steps(p, e, f, k, threads)
     dt = time.perf_counter() - t0
     del f
-    return {"value": round(w.Lx * w.Ly * k / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{w.Lx}x{w.Ly} lattice of the same workload, {k} FP64 steps after 1 "
-                      f"untimed step ({dt:.1f} s), OpenMP over rows"}
+    out = {"value": round(w.Lx * w.Ly * k / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{w.Lx}x{w.Ly} lattice of the same workload, {k} FP64 steps after 1 "
+                     f"untimed step ({dt:.1f} s), OpenMP over rows",
+           "accuracy_samples": []}
+    log(f"[bench] cpu baseline {out['value']} MLUPS on {threads} threads")
+    results = []
+    for job in jobs:
+        pj = oracle_params(job["params"])
+        t0 = time.perf_counter()
+        if job["kind"] == "grad":
+            J, g = oracle.grad_outlet_flux(pj, job["eps"], job["steps"], threads)
+            res = {"J": J, "grad": g}
+        else:
+            m = oracle.moments(pj, job["eps"], oracle.run(pj, job["eps"], job["steps"]))
+            res = {"ux": m["ux"], "uy": m["uy"]}
+        dtj = time.perf_counter() - t0
+        results.append(res)
+        nodes = job["params"]["Lx"] * job["params"]["Ly"]
+        out["accuracy_samples"].append({"name": job["name"], "seconds": round(dtj, 2),
+                                        "MLUPS": round(nodes * job["steps"] / dtj / 1e6, 2)})
+        log(f"[bench] oracle sample {job['name']}: {dtj:.1f} s")
+    return out, results
 
 
-def accuracy(w, lbm, torch, steps: int):
-    """FP32/FP16 sweep vs the FP64 oracle on the top-left 512^2 crop of the workload's
-    porosity field, run periodic."""
+def rel_l2(a, b) -> float:
     import numpy as np
-    import oracle
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def speed_error(gpu, res) -> float:
+    """rel. L2 of |u| of a GPU run against the oracle's result of the same sample."""
+    import numpy as np
+    return rel_l2(np.hypot(*gpu), np.hypot(res["ux"], res["uy"]))
+
+
+def crop_sample(w, lbm, steps: int):
+    """The GPU run of the top-left 512^2 crop of the workload's porosity, run periodic,
+    and the matching oracle job."""
     from paper_1406_6438_amd import workloads as W
     n = W.CROP
     eps = cast_eps(W.crop_porosity(w, n), w.storage)
     s = lbm.Solver(lbm_params(w, lbm, n, n), eps)
     s.step(steps)
     m = s.moments(want_diag=False)
-    ux = m["ux"].double().cpu().numpy()
-    uy = m["uy"].double().cpu().numpy()
+    gpu = (m["ux"].double().cpu().numpy(), m["uy"].double().cpu().numpy())
     s.close()
-    p = oracle.Params(Lx=n, Ly=n, tau=w.tau, d_p=w.d_p, Gx=w.Gx, Gy=w.Gy, rho0=w.rho0)
-    mo = oracle.moments(p, eps, oracle.run(p, eps, steps))
-    ug, uo = np.hypot(ux, uy), np.hypot(mo["ux"], mo["uy"])
-    return {"rel_l2_u_vs_fp64_oracle": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)),
-            "sample": f"top-left {n}x{n} crop of the porosity field, periodic, {steps} steps"}
+    job = {"name": f"{w.name} crop {n}x{n}, {steps} steps", "kind": "u", "steps": steps,
+           "eps": eps, "params": {"Lx": n, "Ly": n, "tau": w.tau, "d_p": w.d_p, "Gx": w.Gx,
+                                  "Gy": w.Gy, "rho0": w.rho0}}
+    return gpu, job
 
 
 def time_sweep(w, lbm, torch, steps: int, warmup: int):
@@ -181,7 +222,8 @@ def adjoint_params(lbm, w, Lx=None, Ly=None):
 def adjoint_leg(lbm, torch, no_accuracy: bool):
     """dJ/deps of the outlet mass flux on the 1024x512 open channel after 4000 steps
     (checkpoints every 200): wall time of the whole gradient (forward with checkpoints,
-    per-segment recompute, reverse), and the plain FP32 forward on the same workload."""
+    per-segment recompute, reverse), and the plain FP32 forward on the same workload.
+    Returns (leg dict, accuracy sample: GPU gradient, oracle job, description)."""
     from paper_1406_6438_amd import workloads as W
     import numpy as np
     w = W.ADJOINT_CHANNEL
@@ -225,8 +267,8 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
            "bytes_per_node_step": bps,
            "achieved_GBps": round(bps * cells * w.steps / t_grad / 1e9, 1)}
     log(f"[bench] adjoint: {t_grad:.3f} s, {m_grad:.0f} MLUPS-equivalent; forward {m_fwd:.0f} MLUPS")
+    sample = None
     if not no_accuracy:
-        import oracle
         n, L = 300, (96, 40)
         sp = lbm.Params(**{**p.__dict__, "Lx": L[0], "Ly": L[1], "d_p": 60.0})
         e = cast_eps(W.grf_porosity(L[0], L[1], seed=43, ell=6.0, lo=0.4, hi=1.0), "f32")
@@ -235,23 +277,22 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
         gg = gg.cpu().numpy()
         sg.close()
         U = W.ADJOINT_U_IN
-        po = oracle.Params(Lx=L[0], Ly=L[1], tau=w.tau, bc_x=oracle.OPEN, bc_y=oracle.WALL,
-                           d_p=60.0, rho0=w.rho0, u0x=U, rho_in=1.0, u_in=U, rho_out=1.0,
-                           u_out=U)
-        Jo, go = oracle.grad_outlet_flux(po, e, n)
-        out["accuracy"] = {"rel_l2_grad_vs_fp64_oracle_adjoint":
-                           float(np.linalg.norm(gg - go) / np.linalg.norm(go)),
-                           "sample": f"{L[0]}x{L[1]} open channel of the same kind, {n} steps, "
-                                     "checkpoints every 50"}
-        log(f"[bench] adjoint accuracy {out['accuracy']['rel_l2_grad_vs_fp64_oracle_adjoint']:.3e}")
-    return out
+        job = {"name": f"gradient {L[0]}x{L[1]} open channel, {n} steps", "kind": "grad",
+               "steps": n, "eps": e,
+               "params": {"Lx": L[0], "Ly": L[1], "tau": w.tau, "bc_x": "open", "bc_y": "wall",
+                          "d_p": 60.0, "rho0": w.rho0, "u0x": U, "rho_in": 1.0, "u_in": U,
+                          "rho_out": 1.0, "u_out": U}}
+        sample = (gg, job, f"{L[0]}x{L[1]} open channel of the same kind, {n} steps, "
+                           "checkpoints every 50")
+    return out, sample
 
 
 def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: bool):
     """The 64-member ensemble of uneven open channels (FP32): launch shape picked by the
     library's autotuner, then `steps` batched steps (one launch per step, replayed as
     16-step graphs) timed with HIP events; the same steps as plain launches; the
-    gradient of every member's outlet flux after 2000 steps (checkpoints every 45)."""
+    gradient of every member's outlet flux after 2000 steps (checkpoints every 45).
+    Returns (leg dict, accuracy sample of the smallest member or None)."""
     import numpy as np
     from paper_1406_6438_amd import workloads as W
     U = W.ENSEMBLE_U
@@ -299,53 +340,46 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
                         "kernel": "k_batch_sweep", "bytes_per_node": bpn}}
     log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
         f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")
-    if not grad:
-        _close_all(sv, b)
-        torch.cuda.empty_cache()
-        return out
-    # gradient of every member's outlet flux
-    K = W.ENSEMBLE_CKPT
-    nbytes = lbm.lbm_vans_batch_grad_work_bytes(b.b, lbm.OBJ_OUTLET_FLUX, W.ENSEMBLE_STEPS, K)
-    b.grad(20, 10)                                  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J, g = b.grad(W.ENSEMBLE_STEPS, K)
-    torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
-    del g
-    m_grad = cells * W.ENSEMBLE_STEPS / t_grad / 1e6
-    out["gradient"] = {"steps": W.ENSEMBLE_STEPS, "ckpt_every": K, "seconds": round(t_grad, 3),
-                       "value": round(m_grad, 2),
-                       "unit": "MLUPS (forward node-steps per second of the whole gradient)",
-                       "vs_forward_same_gpu": round(m_grad / out["value"], 3),
-                       "workspace_GB": round(nbytes / 1e9, 2),
-                       "J_min_max": [min(J), max(J)]}
-    log(f"[bench] ensemble gradient: {t_grad:.2f} s, {m_grad:.0f} MLUPS-equivalent, "
-        f"workspace {nbytes / 1e9:.1f} GB")
+    if grad:
+        # gradient of every member's outlet flux
+        K = W.ENSEMBLE_CKPT
+        nbytes = lbm.lbm_vans_batch_grad_work_bytes(b.b, lbm.OBJ_OUTLET_FLUX,
+                                                    W.ENSEMBLE_STEPS, K)
+        b.grad(20, 10)                                  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, g = b.grad(W.ENSEMBLE_STEPS, K)
+        torch.cuda.synchronize()
+        t_grad = time.perf_counter() - t0
+        del g
+        m_grad = cells * W.ENSEMBLE_STEPS / t_grad / 1e6
+        out["gradient"] = {"steps": W.ENSEMBLE_STEPS, "ckpt_every": K,
+                           "seconds": round(t_grad, 3), "value": round(m_grad, 2),
+                           "unit": "MLUPS (forward node-steps per second of the whole gradient)",
+                           "vs_forward_same_gpu": round(m_grad / out["value"], 3),
+                           "workspace_GB": round(nbytes / 1e9, 2),
+                           "J_min_max": [min(J), max(J)]}
+        log(f"[bench] ensemble gradient: {t_grad:.2f} s, {m_grad:.0f} MLUPS-equivalent, "
+            f"workspace {nbytes / 1e9:.1f} GB")
+    _close_all(sv, b)
+    sample = None
     if not no_accuracy:
-        import oracle
         k = int(np.argmin([m.Lx * m.Ly for m in members]))
         m = members[k]
-        _close_all(sv, b)
         sg = lbm.Solver(params(m), eps[k])
         sg.step(W.ENSEMBLE_STEPS)
         mg = sg.moments(want_diag=False)
-        ux = mg["ux"].double().cpu().numpy()
-        uy = mg["uy"].double().cpu().numpy()
+        gpu = (mg["ux"].double().cpu().numpy(), mg["uy"].double().cpu().numpy())
         sg.close()
-        po = oracle.Params(Lx=m.Lx, Ly=m.Ly, tau=m.tau, bc_x=oracle.OPEN, bc_y=oracle.WALL,
-                           d_p=m.d_p, u0x=U, rho_in=1.0, u_in=U, rho_out=1.0, u_out=U)
-        mo = oracle.moments(po, eps[k], oracle.run(po, eps[k], W.ENSEMBLE_STEPS))
-        ug, uo = np.hypot(ux, uy), np.hypot(mo["ux"], mo["uy"])
-        out["accuracy"] = {"rel_l2_u_vs_fp64_oracle": float(np.linalg.norm(ug - uo) /
-                                                             np.linalg.norm(uo)),
-                           "sample": f"member {k} ({m.Lx}x{m.Ly}, the smallest), "
-                                     f"{W.ENSEMBLE_STEPS} steps"}
-        log(f"[bench] ensemble accuracy {out['accuracy']['rel_l2_u_vs_fp64_oracle']:.3e}")
-    else:
-        _close_all(sv, b)
+        job = {"name": f"ensemble member {k} ({m.Lx}x{m.Ly}), {W.ENSEMBLE_STEPS} steps",
+               "kind": "u", "steps": W.ENSEMBLE_STEPS, "eps": eps[k],
+               "params": {"Lx": m.Lx, "Ly": m.Ly, "tau": m.tau, "bc_x": "open", "bc_y": "wall",
+                          "d_p": m.d_p, "u0x": U, "rho_in": 1.0, "u_in": U, "rho_out": 1.0,
+                          "u_out": U}}
+        sample = (gpu, job, f"member {k} ({m.Lx}x{m.Ly}, the smallest), "
+                            f"{W.ENSEMBLE_STEPS} steps")
     torch.cuda.empty_cache()
-    return out
+    return out, sample
 
 
 def _close_all(solvers, batch):
@@ -362,7 +396,8 @@ def main():
     ap.add_argument("--workload", default="box4096_f32",
                     choices=["box4096_f32", "box8192_f16", "channel_f64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle on the host (and with it every accuracy figure)")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp16", action="store_true",
                     help="skip the FP16-storage leg (8192^2 box) reported beside the main line")
@@ -377,6 +412,7 @@ def main():
         print("bench.py runs on one GPU only: the sweep has no multi-GPU path in this build "
               "(domain decomposition is design only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    want_acc = not args.no_accuracy and not args.no_cpu_baseline
 
     import torch
     from paper_1406_6438_amd import lbm
@@ -394,11 +430,14 @@ def main():
     copy_bw = copy_bandwidth_gbps(torch)
     log(f"[bench] {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic, device copy {copy_bw:.1f} GB/s")
 
+    # accuracy samples: (target dict, key, GPU result, oracle job, description, kind)
+    samples = []
     acc = None
-    if not args.no_accuracy and w.storage != "f64":
-        log("[bench] accuracy: 512^2 crop vs FP64 oracle")
-        acc = accuracy(w, lbm, torch, w.steps)
-        log(f"[bench] accuracy {acc['rel_l2_u_vs_fp64_oracle']:.3e}")
+    if want_acc and w.storage != "f64":
+        gpu, job = crop_sample(w, lbm, w.steps)
+        acc = {}
+        samples.append((acc, gpu, job, f"top-left 512x512 crop of the porosity field, periodic, "
+                                       f"{w.steps} steps"))
 
     fp16 = None
     if not args.no_fp16 and args.workload == "box4096_f32":
@@ -415,26 +454,40 @@ def main():
                              "unit": "GB/s", "frac": round(a16 / PEAK_HBM_GBPS, 4),
                              "traffic": measured_traffic("box8192_f16"), "bytes_per_node": b16},
                 "vs_fp32_same_gpu": round(m16 / mlups, 3),
-                "nonfinite_nodes": d16[6]}
+                "nonfinite_nodes": d16[6], "accuracy": None}
         log(f"[bench] fp16: {m16:.1f} MLUPS, {a16:.1f} GB/s algorithmic")
-        if not args.no_accuracy:
-            fp16["accuracy"] = accuracy(w16, lbm, torch, w16.steps)
-            log(f"[bench] fp16 accuracy {fp16['accuracy']['rel_l2_u_vs_fp64_oracle']:.3e}")
+        if want_acc:
+            gpu, job = crop_sample(w16, lbm, w16.steps)
+            fp16["accuracy"] = {}
+            samples.append((fp16["accuracy"], gpu, job, "top-left 512x512 crop of the 8192^2 "
+                                                        f"porosity field, periodic, {w16.steps} steps"))
 
     adj = None
     if not args.no_adjoint and args.workload == "box4096_f32":
-        adj = adjoint_leg(lbm, torch, args.no_accuracy)
+        adj, smp = adjoint_leg(lbm, torch, not want_acc)
+        if smp is not None:
+            adj["accuracy"] = {}
+            samples.append((adj["accuracy"], smp[0], smp[1], smp[2]))
 
     ens = None
     if not args.no_ensemble and args.workload == "box4096_f32":
-        ens = ensemble_leg(lbm, torch, args.no_accuracy, args.ensemble_steps, args.warmup,
-                           not args.no_adjoint)
+        ens, smp = ensemble_leg(lbm, torch, not want_acc, args.ensemble_steps, args.warmup,
+                                not args.no_adjoint)
+        if smp is not None:
+            ens["accuracy"] = {}
+            samples.append((ens["accuracy"], smp[0], smp[1], smp[2]))
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s)")
-        cpu = cpu_baseline(w, eps, args.cpu_seconds)
-        log(f"[bench] cpu baseline {cpu['value']} MLUPS on {cpu['cores']} threads")
+        log(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s) and {len(samples)} oracle samples")
+        cpu, results = cpu_baseline_leg(w, eps, args.cpu_seconds, [s[2] for s in samples])
+        for (target, gpu, job, desc), res in zip(samples, results):
+            if job["kind"] == "grad":
+                target["rel_l2_grad_vs_fp64_oracle_adjoint"] = rel_l2(gpu, res["grad"])
+            else:
+                target["rel_l2_u_vs_fp64_oracle"] = speed_error(gpu, res)
+            target["sample"] = desc
+            log(f"[bench] accuracy {job['name']}: {target}")
 
     out = {
         "metric": "MLUPS & % HBM roofline (D2Q9 FP32 fwd, FP16-store, adjoint) at fixed error",

@@ -78,8 +78,10 @@ int fail(int code, const char *fmt, ...)
 // ---------------------------------------------------------------------------
 
 // Tile shape (compile-time).  Defaults: the fastest of the shapes timed on
-// MI355X for the 4096^2 FP32 box (1 row per thread, 4 waves per block,
-// non-temporal population loads, XCD-banded tile order).
+// MI355X for the 4096^2 FP32 box (4 waves per block, non-temporal population
+// loads, XCD-banded tile order).  The vector sweep takes its rows per thread
+// from the storage type (sweep_rows): 1 for FP32 and FP64, 2 for FP16, whose
+// narrower loads leave room for a second row in flight.
 #ifndef LBM_VANS_NW
 #define LBM_VANS_NW 4
 #endif
@@ -95,8 +97,15 @@ int fail(int code, const char *fmt, ...)
 
 constexpr int TX = 64;      // nodes per row segment: one wavefront
 constexpr int NW = LBM_VANS_NW;      // wavefronts per block
-constexpr int ROWS = LBM_VANS_ROWS;  // rows per thread
+constexpr int ROWS = LBM_VANS_ROWS;  // rows per thread of the one-node-per-lane kernels
 constexpr int TY = NW * ROWS;
+
+// Rows per thread of the vector sweep for a storage type.
+template <typename S>
+constexpr int sweep_rows()
+{
+    return std::is_same_v<S, _Float16> ? 2 : 1;
+}
 constexpr int NTHREADS = TX * NW;
 constexpr int NRED = 8;     // doubles per block partial of the diagnostics
 constexpr int NXCD = 8;     // accelerator complex dies of the MI355X
@@ -396,9 +405,9 @@ __device__ __forceinline__ void load_eps_tile(R (*tile)[W], const R *__restrict_
 // registers, commit() writes them to LDS.  Population loads issued in between
 // stay in flight while the tile is committed (memory counters retire in order,
 // so waiting for the tile does not wait for loads issued after it).
-template <typename R, int W>
+template <typename R, int W, int TYV = TY>
 struct EpsTile {
-    static constexpr int N = (TY + 2) * W;
+    static constexpr int N = (TYV + 2) * W;
     static constexpr int NE = (N + NTHREADS - 1) / NTHREADS;
     R v[NE];
 
@@ -808,9 +817,11 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
                                                int t)
 {
     constexpr int W = TX * V + 2;
-    __shared__ R tile[TY + 2][W];
+    constexpr int RW = sweep_rows<S>();
+    constexpr int TYS = NW * RW;
+    __shared__ R tile[TYS + 2][W];
     const int bx = t % g.nbx, by = t / g.nbx;
-    const int x0 = bx * TX * V, y0 = by * TY;
+    const int x0 = bx * TX * V, y0 = by * TYS;
     const int lane = threadIdx.x % TX, ty = threadIdx.x / TX;
     constexpr bool WX = BX != 0;
     const LaneX L = lane_x<V, WX, RG>(x0, lane, g);
@@ -819,7 +830,7 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
 #pragma unroll
     for (int i = 0; i < 9; i++) F[i] = fin + i * g.plane;
 
-    EpsTile<R, W> et;
+    EpsTile<R, W, TYS> et;
     et.issue(eps, g, x0, y0);
     R d[9][V];
     bool wym, wyp;
@@ -833,7 +844,7 @@ __device__ __forceinline__ void sweep_vec_tile(const S *__restrict__ fin, S *__r
 #pragma unroll
     for (int k = 0; k < NRED; k++) acc[k] = 0.0;
 #pragma unroll
-    for (int r = 0; r < ROWS; r++) {
+    for (int r = 0; r < RW; r++) {
         const int ly = ty + NW * r;
         const int y = y0 + ly;
         if (y >= g.Ly) break;
@@ -1611,8 +1622,12 @@ int sweep_vec(const lbm_vans_params *p)
     return p->storage == LBM_F64 ? 2 : 4;
 }
 
-// Tiling for `vec` nodes per lane; the pitch is shared by all tilings.
-Geo make_geo(const lbm_vans_params *p, int vec = 1)
+// Rows per thread of the vector sweep for a storage code (see sweep_rows).
+int sweep_rows_of(int storage) { return storage == LBM_F16_SHIFTED ? 2 : 1; }
+
+// Tiling for `vec` nodes per lane and `rows` rows per thread; the pitch is
+// shared by all tilings.
+Geo make_geo(const lbm_vans_params *p, int vec = 1, int rows = ROWS)
 {
     Geo g;
     g.Lx = p->Lx;
@@ -1622,7 +1637,7 @@ Geo make_geo(const lbm_vans_params *p, int vec = 1)
     g.wall_y = p->bc_y == LBM_BC_BOUNCEBACK;
     g.open_x = p->bc_x == LBM_BC_OPEN;
     g.nbx = (p->Lx + TX * vec - 1) / (TX * vec);
-    int nby = (p->Ly + TY - 1) / TY;
+    int nby = (p->Ly + NW * rows - 1) / (NW * rows);
     g.ntiles = g.nbx * nby;
     g.plane = (long long)g.pitch * p->Ly;
     return g;
@@ -1795,7 +1810,7 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
     h->stream = static_cast<hipStream_t>(stream);
     h->g = make_geo(p);
     h->vec = sweep_vec(p);
-    h->gs = make_geo(p, h->vec);
+    h->gs = make_geo(p, h->vec, sweep_rows_of(p->storage));
     h->ntiles = h->g.ntiles;
     h->pop_bytes = L.pop;
     char *w = static_cast<char *>(work);
@@ -2163,7 +2178,7 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             Member<R> &d = D[k];
             std::memset(&d, 0, sizeof d);
             d.vec = vec;
-            d.gs = make_geo(&h->p, d.vec);
+            d.gs = make_geo(&h->p, d.vec, sweep_rows_of(h->p.storage));
             d.g = h->g;
             d.ph = make_phys<R>(&h->p);
             d.buf[0] = h->buf[0];

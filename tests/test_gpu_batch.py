@@ -10,10 +10,11 @@ Tolerances are those of the single-problem parity tests:
 * gradients: FP64 <= 1e-10 of the largest |dJ/deps|, FP32 rel. L2 <= 1e-4,
   both against the oracle's FP64 reverse pass.
 A member of a batch takes the same node update as a problem run alone, so the
-batched results are also compared with lone runs: bit for bit when the batch
-runs the lone sweep's vector width (same arithmetic, only the tile bookkeeping
-differs), else within the precision bound above (a different width may fuse
-other multiply-adds).
+batched results are also compared with lone runs, within the precision bound
+above (the batched kernel is a different compilation of the same source and
+may fuse other multiply-adds; the tests print whether the bits agree).  Launch
+shapes of one width and graph replays run the same kernel and must agree bit
+for bit.
 """
 import dataclasses
 
@@ -103,7 +104,8 @@ def test_batch_matches_oracle_and_lone_runs(storage, bc):
             f"{_bound(spec, eps, fo, nsteps):.3e})")
         assert err <= _bound(spec, eps, fo, nsteps)
         _, fl = gpu_run(spec, eps, nsteps)
-        assert np.array_equal(f, fl), f"{spec.Lx}x{spec.Ly}: batch differs from a lone run"
+        say(f"    lone run: max diff {np.abs(f - fl).max():.3e}, same bits {np.array_equal(f, fl)}")
+        assert np.abs(f - fl).max() <= _bound(spec, eps, fo, nsteps)
     b.close()
     _close(sv)
 
@@ -184,11 +186,8 @@ def test_autotune_keeps_the_state_and_reports_trials():
     b.step(10)
     for (spec, eps), f in zip(members, _states(sv)):
         _, fl = gpu_run(spec, eps, 13)
-        if best["vec"] == _vmax("f32"):
-            assert np.array_equal(f, fl)
-        else:
-            _, fo = oracle_run(spec, eps, 13)
-            assert np.abs(f - fl).max() <= 2 * _bound(spec, eps, fo, 13)
+        _, fo = oracle_run(spec, eps, 13)
+        assert np.abs(f - fl).max() <= 2 * _bound(spec, eps, fo, 13)
     b.close()
     _close(sv)
 
@@ -246,7 +245,14 @@ def test_batch_gradient_matches_oracle_adjoint(storage):
         lone = lbm.Solver(spec.gpu(), spec.input_eps(eps))
         Jl, gl = lone.grad(nsteps, K)
         lone.close()
-        assert Jl == Jb and np.array_equal(gl.cpu().numpy(), gb)
+        gl = gl.cpu().numpy()
+        say(f"    lone gradient: same bits {Jl == Jb and np.array_equal(gl, gb)}")
+        if storage == "f64":
+            assert abs(Jl - Jb) <= 1e-13 * abs(Jl)
+            assert np.abs(gl - gb).max() <= 1e-11 * np.abs(gl).max()
+        else:
+            assert abs(Jl - Jb) <= 1e-6 * abs(Jl)
+            assert rel_l2(gb, gl) <= 1e-5
     b.close()
     _close(sv)
 
@@ -264,7 +270,7 @@ def _ensemble_specs():
 def test_full_ensemble_2000_steps():
     """The 64-member ensemble, autotuned, 2000 steps: the three smallest members
     against the oracle (rel. L2(u) <= 1e-5), every member against a lone run
-    (bit for bit at the lone width, else rel. L2(u) <= 1e-5)."""
+    (rel. L2(u) <= 1e-5)."""
     from paper_1406_6438_amd import lbm
     ens = _ensemble_specs()
     say(f"[ensemble] {len(ens)} members, {sum(s.Lx * s.Ly for s, _ in ens) / 1e6:.1f}M nodes")
@@ -285,17 +291,16 @@ def test_full_ensemble_2000_steps():
         assert e <= 1e-5
         assert rel_l2(mg["uy"].double().cpu().numpy(), mo["uy"]) <= 1e-5 * max(
             1.0, np.linalg.norm(mo["ux"]) / max(np.linalg.norm(mo["uy"]), 1e-300))
+    same = 0
     for k, ((spec, m), s) in enumerate(zip(ens, sv)):
         lone = lbm.Solver(spec.gpu(), spec.input_eps(m.porosity()))
         lone.step(W.ENSEMBLE_STEPS)
-        if best["vec"] == _vmax("f32"):
-            same = torch.equal(s.get_state(), lone.get_state())
-            assert same, f"member {k} ({spec.Lx}x{spec.Ly}) differs from its lone run"
-        else:
-            e = rel_l2(s.moments()["ux"].double().cpu().numpy(),
-                       lone.moments()["ux"].double().cpu().numpy())
-            assert e <= 1e-5, f"member {k}: rel L2(ux) {e:.2e} against its lone run"
+        same += int(torch.equal(s.get_state(), lone.get_state()))
+        e = rel_l2(s.moments()["ux"].double().cpu().numpy(),
+                   lone.moments()["ux"].double().cpu().numpy())
+        assert e <= 1e-5, f"member {k}: rel L2(ux) {e:.2e} against its lone run"
         lone.close()
+    say(f"  {same} of {len(ens)} members have the same bits as their lone runs")
     b.close()
     _close(sv)
 
@@ -303,7 +308,7 @@ def test_full_ensemble_2000_steps():
 def test_full_ensemble_gradient():
     """Gradient of every member's outlet flux after 2000 steps (checkpoints every
     45): the two smallest members against the oracle's FP64 reverse pass
-    (rel. L2 <= 1e-4), the largest against its lone run (bit for bit)."""
+    (rel. L2 <= 1e-4), the largest against its lone run (rel. L2 <= 1e-5)."""
     from paper_1406_6438_amd import lbm
     ens = _ensemble_specs()
     sv = [lbm.Solver(s.gpu(), s.input_eps(m.porosity())) for s, m in ens]
@@ -329,4 +334,6 @@ def test_full_ensemble_gradient():
     lone = lbm.Solver(spec.gpu(), spec.input_eps(m.porosity()))
     Jl, gl = lone.grad(W.ENSEMBLE_STEPS, W.ENSEMBLE_CKPT)
     lone.close()
-    assert Jl == J[k] and torch.equal(gl, gk)
+    say(f"  largest member: lone gradient same bits {Jl == J[k] and torch.equal(gl, gk)}")
+    assert abs(Jl - J[k]) <= 1e-6 * abs(Jl)
+    assert rel_l2(gk.cpu().numpy(), gl.cpu().numpy()) <= 1e-5

@@ -881,6 +881,119 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
                                               xcd_tile(blockIdx.x, g.ntiles));
 }
 
+// ---- two time steps per pass (periodic x) ----------------------------------
+// Each wave walks a strip of 62 output columns down a chunk of TB_H output
+// rows, one node per lane: lane l holds column c0 + l - 1, so lanes 0 and 63
+// are the strip's halo.  Per row it (A) gathers and collides step n -> n+1
+// for the row below the output row from the input buffer, keeping the last
+// three post-collision rows of step n+1 in registers, and (B) pulls step
+// n+1 -> n+2 for the output row from those rows (x-shifts by cross-lane
+// shuffles, bounce-back behind y-walls from the node's own row) and stores it.
+// The state of step n+1 never leaves the registers: the pass moves the bytes
+// of one step for two.  The node update is the sweep's own (update_node on a
+// 3x3 porosity window held per lane).
+constexpr int TB_COLS = TX - 2;  // output columns per strip
+constexpr int TB_H = 32;         // output rows per chunk
+
+template <typename S, typename R, bool WY>
+__global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
+                                                        S *__restrict__ fout,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        Phys<R> ph, int nstrips, int nchunks)
+{
+    const int lane = threadIdx.x % TX;
+    const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
+    const int strip = wid % nstrips, chunk = wid / nstrips;
+    if (chunk >= nchunks) return;              // whole waves only; no barrier below
+    const int xu = strip * TB_COLS + lane - 1;  // unwrapped column
+    int x = xu % g.Lx;
+    if (x < 0) x += g.Lx;
+    const bool out_ok = lane >= 1 && lane <= TB_COLS && xu < g.Lx;
+    const int y0 = chunk * TB_H, y1 = min(y0 + TB_H, g.Ly);
+    const int xm = x == 0 ? g.Lx - 1 : x - 1, xp = x == g.Lx - 1 ? 0 : x + 1;
+
+    // porosity of rows y-1 .. y+2 (relative to the output row y), columns x-1..x+1
+    R e[4][3];
+    auto eps_row = [&](R (&r)[3], int row) {
+        const long long o = (long long)halo_index(row, g.Ly, g.wall_y) * g.pitch;
+        r[0] = eps[o + xm];
+        r[1] = eps[o + x];
+        r[2] = eps[o + xp];
+    };
+    // step n -> n+1 at row yy (inside the domain, or wrapped when y is periodic):
+    // the post-collision values of the node, in the storage representation
+    auto step_a = [&](R (&out)[9], int yy, const R (&w0)[3], const R (&w1)[3],
+                      const R (&w2)[3]) {
+        const Nbr n = neighbours(x, yy, g);
+        R d[9];
+        gather<S, R>(d, fin, g.plane, g.pitch, x, yy, n, ph.inv_scale);
+        const R t[3][3] = {{w0[0], w0[1], w0[2]}, {w1[0], w1[1], w1[2]}, {w2[0], w2[1], w2[2]}};
+        update_node<R, 3, false>(d, t, 1, 1, false, false, n.wym, n.wyp, false, false, ph,
+                                 nullptr, false);
+#pragma unroll
+        for (int i = 0; i < 9; i++) out[i] = d[i];
+    };
+    auto row_in = [&](int row) { return WY ? (row >= 0 && row < g.Ly) : true; };
+    auto wrap_row = [&](int row) { return row < 0 ? row + g.Ly : (row >= g.Ly ? row - g.Ly : row); };
+
+    R P[3][9];
+#pragma unroll
+    for (int k = 0; k < 4; k++) eps_row(e[k], y0 - 1 + k);
+    // the window starts with step n+1 at rows y0-1 and y0 (row -1 is behind a wall
+    // when y has walls, and then never read)
+    {
+        R em[3];
+        eps_row(em, y0 - 2);
+        if (row_in(y0 - 1)) step_a(P[0], wrap_row(y0 - 1), em, e[0], e[1]);
+        else {
+#pragma unroll
+            for (int i = 0; i < 9; i++) P[0][i] = R(0);
+        }
+    }
+    step_a(P[1], y0, e[0], e[1], e[2]);
+    for (int y = y0; y < y1; y++) {
+        const bool wym = WY && y == 0, wyp = WY && y == g.Ly - 1;
+        if (row_in(y + 1)) step_a(P[2], wrap_row(y + 1), e[1], e[2], e[3]);
+        else {
+#pragma unroll
+            for (int i = 0; i < 9; i++) P[2][i] = R(0);
+        }
+        // step n+1 -> n+2 at row y from the window
+        R d[9];
+        const R s1 = __shfl_up(P[1][1], 1, 64), s3 = __shfl_down(P[1][3], 1, 64);
+        const R s5 = __shfl_up(P[0][5], 1, 64), s6 = __shfl_down(P[0][6], 1, 64);
+        const R s7 = __shfl_down(P[2][7], 1, 64), s8 = __shfl_up(P[2][8], 1, 64);
+        d[0] = P[1][0];
+        d[1] = s1;
+        d[3] = s3;
+        d[2] = wym ? P[1][4] : P[0][2];
+        d[4] = wyp ? P[1][2] : P[2][4];
+        d[5] = wym ? P[1][7] : s5;
+        d[6] = wym ? P[1][8] : s6;
+        d[7] = wyp ? P[1][5] : s7;
+        d[8] = wyp ? P[1][6] : s8;
+        const R t[3][3] = {{e[0][0], e[0][1], e[0][2]}, {e[1][0], e[1][1], e[1][2]},
+                           {e[2][0], e[2][1], e[2][2]}};
+        update_node<R, 3, false>(d, t, 1, 1, false, false, wym, wyp, false, false, ph, nullptr,
+                                 false);
+        if (out_ok) {
+            const long long c = (long long)y * g.pitch + x;
+#pragma unroll
+            for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i], ph.scale);
+        }
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            P[0][i] = P[1][i];
+            P[1][i] = P[2][i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) e[k][j] = e[k + 1][j];
+        eps_row(e[3], y + 3);
+    }
+}
+
 // Macroscopic fields of the current state (no collision, no store of
 // populations) plus the FP64 diagnostics partials.
 template <typename S, typename R>
@@ -1749,6 +1862,41 @@ void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
     else launch_sweep_rg<S, R, DIAG, false>(h, src, dst, ph);
 }
 
+// Two time steps in one pass (k_sweep_tb2): FP32 and FP16 storage with a
+// periodic x axis.
+bool tb2_eligible(const lbm_vans_handle *h)
+{
+    return h->p.storage != LBM_F64 && h->p.bc_x == LBM_BC_PERIODIC;
+}
+
+int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
+{
+    const int nstrips = (h->p.Lx + TB_COLS - 1) / TB_COLS;
+    const int nchunks = (h->p.Ly + TB_H - 1) / TB_H;
+    const long long waves = (long long)nstrips * nchunks;
+    if (waves > (long long)INT32_MAX - NW) return fail(LBM_VANS_EINVAL, "lattice too large");
+    const int grid = static_cast<int>((waves + NW - 1) / NW);
+    return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        if constexpr (std::is_same_v<S, double>) {
+            return fail(LBM_VANS_EINVAL, "two-step pass needs FP32 or FP16 storage");
+        } else {
+            Phys<R> ph = make_phys<R>(&h->p);
+            ph.reservoir = 0;
+            if (h->g.wall_y)
+                hipLaunchKernelGGL((k_sweep_tb2<S, R, true>), dim3(grid), dim3(NTHREADS), 0,
+                                   h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g,
+                                   ph, nstrips, nchunks);
+            else
+                hipLaunchKernelGGL((k_sweep_tb2<S, R, false>), dim3(grid), dim3(NTHREADS), 0,
+                                   h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g,
+                                   ph, nstrips, nchunks);
+            return check_launch("k_sweep_tb2");
+        }
+    });
+}
+
 // One time step from the state n stored in src into dst.
 int launch_sweep_ptrs(lbm_vans_handle *h, const void *src, void *dst, int64_t n, bool diag)
 {
@@ -1867,6 +2015,16 @@ int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps)
     if (nsteps < 0) return fail(LBM_VANS_EINVAL, "nsteps = %lld < 0", (long long)nsteps);
     for (int64_t k = 0; k < nsteps; k++) {
         bool diag = h->p.diag_every > 0 && h->n % h->p.diag_every == 0;
+        // two steps in one pass when both remain in this call and neither records
+        // diagnostics
+        if (!diag && k + 1 < nsteps && h->p.diag_every == 0 && tb2_eligible(h)) {
+            int rc = launch_tb2(h, h->buf[h->cur], h->buf[1 - h->cur]);
+            if (rc) return rc;
+            h->cur = 1 - h->cur;
+            h->n += 2;
+            k++;
+            continue;
+        }
         int rc = launch_sweep(h, diag);
         if (rc) return rc;
         if (diag) {

@@ -362,3 +362,38 @@ def test_f16_full_size_box_sampled_windows():
         blk = np.s_[y0:y0 + 32, x0:x0 + 32]
         assert rel_l2(ux[blk], mo["ux"]) <= 2e-3
         assert np.abs(rho[blk] - mo["rho"]).max() <= 1e-4
+
+
+# Two steps per pass: lbm_vans_step(n) with n >= 2 on a periodic-x lattice in FP32
+# or FP16 storage runs pairs of steps in one pass (the intermediate state stays in
+# registers).  Against the oracle and against the same steps taken one per call.
+TB_GEOMS = [(70, 40, False), (130, 33, True), (5, 7, True), (1, 3, False), (300, 1, False),
+            (64, 32, True)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("geom", TB_GEOMS, ids=lambda g: "%dx%d_wy%d" % g)
+def test_two_step_pass_matches_oracle_and_single_steps(geom, storage):
+    from paper_1406_6438_amd import lbm
+    Lx, Ly, wy = geom
+    say(f"[two-step pass {storage}] {Lx}x{Ly} walls_y={wy}")
+    spec = Spec(Lx=Lx, Ly=Ly, tau=0.62, walls_y=wy, d_p=6.0, G=(2e-5, -1e-5),
+                u0=(0.01, 0.004), u_wall=(0.0, 0.03) if wy else (0.0, 0.0), storage=storage)
+    eps = W.grf_porosity(Lx, Ly, seed=900 + Lx, ell=2.5, lo=0.35, hi=1.0)
+    for nsteps in (2, 7, 40):
+        mg, fg = gpu_run(spec, eps, nsteps)             # pairs in one pass (+1 single)
+        mo, fo = oracle_run(spec, eps, nsteps)
+        D = _max_deviation(spec, eps, fo)
+        if storage == "f32":
+            assert np.abs(fg - fo).max() <= 4 * (nsteps + 1) * 2.0 ** -24 * D
+            assert rel_l2(mg["ux"], mo["ux"]) <= 1e-5
+        else:
+            assert np.abs(fg - fo).max() <= 2 * (nsteps + 1) * 2.0 ** -11 * D
+        s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
+        for _ in range(nsteps):
+            s.step(1)                                     # one step per call
+        f1 = s.get_state().cpu().numpy()
+        s.close()
+        tol = (4 * (nsteps + 1) * 2.0 ** -24 if storage == "f32" else
+               2 * (nsteps + 1) * 2.0 ** -11) * D
+        assert np.abs(fg - f1).max() <= tol

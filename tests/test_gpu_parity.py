@@ -384,16 +384,15 @@ def test_two_step_pass_matches_oracle_and_single_steps(geom, storage):
         mg, fg = gpu_run(spec, eps, nsteps)             # pairs in one pass (+1 single)
         mo, fo = oracle_run(spec, eps, nsteps)
         D = _max_deviation(spec, eps, fo)
-        if storage == "f32":
-            assert np.abs(fg - fo).max() <= 4 * (nsteps + 1) * 2.0 ** -24 * D
-            assert rel_l2(mg["ux"], mo["ux"]) <= 1e-5
-        else:
-            assert np.abs(fg - fo).max() <= 2 * (nsteps + 1) * 2.0 ** -11 * D
+        # per population: the storage bound of the single-step tests; the velocity: six
+        # unit-weight terms of that size over eps rho >= 0.35
+        tol = (4 * (nsteps + 1) * 2.0 ** -24 if storage == "f32" else
+               2 * (nsteps + 1) * 2.0 ** -11) * D
+        assert np.abs(fg - fo).max() <= tol
+        assert np.abs(mg["ux"] - mo["ux"]).max() <= 6 * tol / 0.35
         s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
         for _ in range(nsteps):
             s.step(1)                                     # one step per call
         f1 = s.get_state().cpu().numpy()
         s.close()
-        tol = (4 * (nsteps + 1) * 2.0 ** -24 if storage == "f32" else
-               2 * (nsteps + 1) * 2.0 ** -11) * D
         assert np.abs(fg - f1).max() <= tol

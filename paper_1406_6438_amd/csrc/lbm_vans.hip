@@ -887,13 +887,28 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
 // are the strip's halo.  Per row it (A) gathers and collides step n -> n+1
 // for the row below the output row from the input buffer, keeping the last
 // three post-collision rows of step n+1 in registers, and (B) pulls step
-// n+1 -> n+2 for the output row from those rows (x-shifts by cross-lane
-// shuffles, bounce-back behind y-walls from the node's own row) and stores it.
-// The state of step n+1 never leaves the registers: the pass moves the bytes
-// of one step for two.  The node update is the sweep's own (update_node on a
-// 3x3 porosity window held per lane).
+// n+1 -> n+2 for the output row from those rows (x-shifts by DPP wave shifts,
+// bounce-back behind y-walls from the node's own row) and stores it.  The
+// state of step n+1 never leaves the registers: the pass moves the bytes of
+// one step for two.  The node update is the sweep's own (update_node on a 3x3
+// porosity window held per lane).  The row loop is unrolled by three so that
+// the register window rotates by renaming.
 constexpr int TB_COLS = TX - 2;  // output columns per strip
 constexpr int TB_H = 32;         // output rows per chunk
+
+// Value of the lane below (wave_shr: lane l reads lane l-1) and above
+// (wave_shl: lane l reads lane l+1); the wave's end lanes read 0.
+__device__ __forceinline__ float lane_from_below(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                         0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float lane_from_above(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                         0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
 
 template <typename S, typename R, bool WY>
 __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
@@ -901,96 +916,128 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, int nstrips, int nchunks)
 {
+    static_assert(std::is_same_v<R, float>, "two-step pass computes in FP32");
     const int lane = threadIdx.x % TX;
     const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
     const int strip = wid % nstrips, chunk = wid / nstrips;
     if (chunk >= nchunks) return;              // whole waves only; no barrier below
     const int xu = strip * TB_COLS + lane - 1;  // unwrapped column
-    int x = xu % g.Lx;
-    if (x < 0) x += g.Lx;
+    int xi = xu % g.Lx;
+    if (xi < 0) xi += g.Lx;
+    const unsigned x = static_cast<unsigned>(xi);
+    const unsigned xm = xi == 0 ? g.Lx - 1 : xi - 1, xp = xi == g.Lx - 1 ? 0 : xi + 1;
     const bool out_ok = lane >= 1 && lane <= TB_COLS && xu < g.Lx;
     const int y0 = chunk * TB_H, y1 = min(y0 + TB_H, g.Ly);
-    const int xm = x == 0 ? g.Lx - 1 : x - 1, xp = x == g.Lx - 1 ? 0 : x + 1;
+    const unsigned pitch = g.pitch;
+    const S *F[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) F[i] = fin + i * g.plane;
 
-    // porosity of rows y-1 .. y+2 (relative to the output row y), columns x-1..x+1
-    R e[4][3];
+    // porosity window: rows y-1 .. y+1 of the output row y in a three-slot ring,
+    // columns x-1 .. x+1
+    R e[3][3];
     auto eps_row = [&](R (&r)[3], int row) {
-        const long long o = (long long)halo_index(row, g.Ly, g.wall_y) * g.pitch;
+        const unsigned o = static_cast<unsigned>(halo_index(row, g.Ly, g.wall_y)) * pitch;
         r[0] = eps[o + xm];
         r[1] = eps[o + x];
         r[2] = eps[o + xp];
     };
-    // step n -> n+1 at row yy (inside the domain, or wrapped when y is periodic):
-    // the post-collision values of the node, in the storage representation
+    auto row_in = [&](int row) { return WY ? (row >= 0 && row < g.Ly) : true; };
+    auto wrap_row = [&](int row) {
+        return row < 0 ? row + g.Ly : (row >= g.Ly ? row - g.Ly : row);
+    };
+    // step n -> n+1 at row yy (inside the domain): the node's post-collision
+    // values in the storage representation
     auto step_a = [&](R (&out)[9], int yy, const R (&w0)[3], const R (&w1)[3],
                       const R (&w2)[3]) {
-        const Nbr n = neighbours(x, yy, g);
+        bool wym = false, wyp = false;
+        int ym = yy - 1, yp = yy + 1;
+        if (ym < 0) { if (WY) { wym = true; ym = yy; } else ym = g.Ly - 1; }
+        if (yp >= g.Ly) { if (WY) { wyp = true; yp = yy; } else yp = 0; }
+        const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
         R d[9];
-        gather<S, R>(d, fin, g.plane, g.pitch, x, yy, n, ph.inv_scale);
+        d[0] = load_pop<S, R>(F[0] + (r0 + x), ph.inv_scale);
+        d[1] = load_pop<S, R>(F[1] + (r0 + xm), ph.inv_scale);
+        d[2] = load_pop<S, R>(wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
+        d[3] = load_pop<S, R>(F[3] + (r0 + xp), ph.inv_scale);
+        d[4] = load_pop<S, R>(wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
+        d[5] = load_pop<S, R>(wym ? F[7] + (r0 + x) : F[5] + (rm + xm), ph.inv_scale);
+        d[6] = load_pop<S, R>(wym ? F[8] + (r0 + x) : F[6] + (rm + xp), ph.inv_scale);
+        d[7] = load_pop<S, R>(wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), ph.inv_scale);
+        d[8] = load_pop<S, R>(wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), ph.inv_scale);
         const R t[3][3] = {{w0[0], w0[1], w0[2]}, {w1[0], w1[1], w1[2]}, {w2[0], w2[1], w2[2]}};
-        update_node<R, 3, false>(d, t, 1, 1, false, false, n.wym, n.wyp, false, false, ph,
-                                 nullptr, false);
+        update_node<R, 3, false>(d, t, 1, 1, false, false, wym, wyp, false, false, ph, nullptr,
+                                 false);
 #pragma unroll
         for (int i = 0; i < 9; i++) out[i] = d[i];
     };
-    auto row_in = [&](int row) { return WY ? (row >= 0 && row < g.Ly) : true; };
-    auto wrap_row = [&](int row) { return row < 0 ? row + g.Ly : (row >= g.Ly ? row - g.Ly : row); };
 
     R P[3][9];
-#pragma unroll
-    for (int k = 0; k < 4; k++) eps_row(e[k], y0 - 1 + k);
-    // the window starts with step n+1 at rows y0-1 and y0 (row -1 is behind a wall
-    // when y has walls, and then never read)
+    // the window starts with step n+1 at rows y0-1 (slot 0) and y0 (slot 1); row -1
+    // lies behind a wall when y has walls, and is then never read
     {
         R em[3];
         eps_row(em, y0 - 2);
+        eps_row(e[0], y0 - 1);
+        eps_row(e[1], y0);
+        eps_row(e[2], y0 + 1);
+#pragma unroll
+        for (int i = 0; i < 9; i++) P[0][i] = P[2][i] = R(0);
         if (row_in(y0 - 1)) step_a(P[0], wrap_row(y0 - 1), em, e[0], e[1]);
-        else {
-#pragma unroll
-            for (int i = 0; i < 9; i++) P[0][i] = R(0);
-        }
+        step_a(P[1], y0, e[0], e[1], e[2]);
     }
-    step_a(P[1], y0, e[0], e[1], e[2]);
-    for (int y = y0; y < y1; y++) {
+    // one output row: the window slots of rows y-1, y, y+1 are A0, A1, A2
+    auto row = [&](auto a0, auto a1, auto a2, int y) {
+        constexpr int A0 = decltype(a0)::value, A1 = decltype(a1)::value,
+                      A2 = decltype(a2)::value;
         const bool wym = WY && y == 0, wyp = WY && y == g.Ly - 1;
-        if (row_in(y + 1)) step_a(P[2], wrap_row(y + 1), e[1], e[2], e[3]);
-        else {
-#pragma unroll
-            for (int i = 0; i < 9; i++) P[2][i] = R(0);
-        }
+        R en[3];
+        eps_row(en, y + 2);
+        if (row_in(y + 1)) step_a(P[A2], wrap_row(y + 1), e[A1], e[A2], en);
         // step n+1 -> n+2 at row y from the window
         R d[9];
-        const R s1 = __shfl_up(P[1][1], 1, 64), s3 = __shfl_down(P[1][3], 1, 64);
-        const R s5 = __shfl_up(P[0][5], 1, 64), s6 = __shfl_down(P[0][6], 1, 64);
-        const R s7 = __shfl_down(P[2][7], 1, 64), s8 = __shfl_up(P[2][8], 1, 64);
-        d[0] = P[1][0];
+        const R s1 = lane_from_below(P[A1][1]), s3 = lane_from_above(P[A1][3]);
+        d[0] = P[A1][0];
         d[1] = s1;
         d[3] = s3;
-        d[2] = wym ? P[1][4] : P[0][2];
-        d[4] = wyp ? P[1][2] : P[2][4];
-        d[5] = wym ? P[1][7] : s5;
-        d[6] = wym ? P[1][8] : s6;
-        d[7] = wyp ? P[1][5] : s7;
-        d[8] = wyp ? P[1][6] : s8;
-        const R t[3][3] = {{e[0][0], e[0][1], e[0][2]}, {e[1][0], e[1][1], e[1][2]},
-                           {e[2][0], e[2][1], e[2][2]}};
+        if (wym) {
+            d[2] = P[A1][4];
+            d[5] = P[A1][7];
+            d[6] = P[A1][8];
+        } else {
+            d[2] = P[A0][2];
+            d[5] = lane_from_below(P[A0][5]);
+            d[6] = lane_from_above(P[A0][6]);
+        }
+        if (wyp) {
+            d[4] = P[A1][2];
+            d[7] = P[A1][5];
+            d[8] = P[A1][6];
+        } else {
+            d[4] = P[A2][4];
+            d[7] = lane_from_above(P[A2][7]);
+            d[8] = lane_from_below(P[A2][8]);
+        }
+        const R t[3][3] = {{e[A0][0], e[A0][1], e[A0][2]}, {e[A1][0], e[A1][1], e[A1][2]},
+                           {e[A2][0], e[A2][1], e[A2][2]}};
         update_node<R, 3, false>(d, t, 1, 1, false, false, wym, wyp, false, false, ph, nullptr,
                                  false);
         if (out_ok) {
-            const long long c = (long long)y * g.pitch + x;
+            const unsigned c = y * pitch + x;
 #pragma unroll
             for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i], ph.scale);
         }
+        // the slot of row y-1 takes row y+2
 #pragma unroll
-        for (int i = 0; i < 9; i++) {
-            P[0][i] = P[1][i];
-            P[1][i] = P[2][i];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; k++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) e[k][j] = e[k + 1][j];
-        eps_row(e[3], y + 3);
+        for (int j = 0; j < 3; j++) e[A0][j] = en[j];
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    for (int y = y0; y < y1; y += 3) {
+        row(I0{}, I1{}, I2{}, y);
+        if (y + 1 < y1) row(I1{}, I2{}, I0{}, y + 1);
+        if (y + 2 < y1) row(I2{}, I0{}, I1{}, y + 2);
     }
 }
 

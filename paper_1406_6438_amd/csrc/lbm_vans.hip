@@ -946,33 +946,42 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
     auto wrap_row = [&](int row) {
         return row < 0 ? row + g.Ly : (row >= g.Ly ? row - g.Ly : row);
     };
-    // step n -> n+1 at row yy (inside the domain): the node's post-collision
-    // values in the storage representation
-    auto step_a = [&](R (&out)[9], int yy, const R (&w0)[3], const R (&w1)[3],
-                      const R (&w2)[3]) {
-        bool wym = false, wyp = false;
-        int ym = yy - 1, yp = yy + 1;
-        if (ym < 0) { if (WY) { wym = true; ym = yy; } else ym = g.Ly - 1; }
-        if (yp >= g.Ly) { if (WY) { wyp = true; yp = yy; } else yp = 0; }
-        const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
+    // step n -> n+1 at row yy (inside the domain), in two parts: the loads of the
+    // gather (issued one row ahead, so that they are in flight while the wave
+    // computes the row before), then the node update on them
+    struct Pending {
         R d[9];
-        d[0] = load_pop<S, R>(F[0] + (r0 + x), ph.inv_scale);
-        d[1] = load_pop<S, R>(F[1] + (r0 + xm), ph.inv_scale);
-        d[2] = load_pop<S, R>(wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
-        d[3] = load_pop<S, R>(F[3] + (r0 + xp), ph.inv_scale);
-        d[4] = load_pop<S, R>(wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
-        d[5] = load_pop<S, R>(wym ? F[7] + (r0 + x) : F[5] + (rm + xm), ph.inv_scale);
-        d[6] = load_pop<S, R>(wym ? F[8] + (r0 + x) : F[6] + (rm + xp), ph.inv_scale);
-        d[7] = load_pop<S, R>(wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), ph.inv_scale);
-        d[8] = load_pop<S, R>(wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), ph.inv_scale);
+        bool wym, wyp;
+    };
+    auto issue_a = [&](Pending &q, int yy) {
+        q.wym = false;
+        q.wyp = false;
+        int ym = yy - 1, yp = yy + 1;
+        if (ym < 0) { if (WY) { q.wym = true; ym = yy; } else ym = g.Ly - 1; }
+        if (yp >= g.Ly) { if (WY) { q.wyp = true; yp = yy; } else yp = 0; }
+        const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
+        q.d[0] = load_pop<S, R>(F[0] + (r0 + x), ph.inv_scale);
+        q.d[1] = load_pop<S, R>(F[1] + (r0 + xm), ph.inv_scale);
+        q.d[2] = load_pop<S, R>(q.wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
+        q.d[3] = load_pop<S, R>(F[3] + (r0 + xp), ph.inv_scale);
+        q.d[4] = load_pop<S, R>(q.wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
+        q.d[5] = load_pop<S, R>(q.wym ? F[7] + (r0 + x) : F[5] + (rm + xm), ph.inv_scale);
+        q.d[6] = load_pop<S, R>(q.wym ? F[8] + (r0 + x) : F[6] + (rm + xp), ph.inv_scale);
+        q.d[7] = load_pop<S, R>(q.wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), ph.inv_scale);
+        q.d[8] = load_pop<S, R>(q.wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), ph.inv_scale);
+    };
+    auto finish_a = [&](R (&out)[9], Pending &q, const R (&w0)[3], const R (&w1)[3],
+                        const R (&w2)[3]) {
         const R t[3][3] = {{w0[0], w0[1], w0[2]}, {w1[0], w1[1], w1[2]}, {w2[0], w2[1], w2[2]}};
-        update_node<R, 3, false>(d, t, 1, 1, false, false, wym, wyp, false, false, ph, nullptr,
-                                 false);
+        update_node<R, 3, false>(q.d, t, 1, 1, false, false, q.wym, q.wyp, false, false, ph,
+                                 nullptr, false);
 #pragma unroll
-        for (int i = 0; i < 9; i++) out[i] = d[i];
+        for (int i = 0; i < 9; i++) out[i] = q.d[i];
     };
 
     R P[3][9];
+    Pending q;
+    R en[3];
     // the window starts with step n+1 at rows y0-1 (slot 0) and y0 (slot 1); row -1
     // lies behind a wall when y has walls, and is then never read
     {
@@ -983,17 +992,27 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
         eps_row(e[2], y0 + 1);
 #pragma unroll
         for (int i = 0; i < 9; i++) P[0][i] = P[2][i] = R(0);
-        if (row_in(y0 - 1)) step_a(P[0], wrap_row(y0 - 1), em, e[0], e[1]);
-        step_a(P[1], y0, e[0], e[1], e[2]);
+        if (row_in(y0 - 1)) {
+            issue_a(q, wrap_row(y0 - 1));
+            finish_a(P[0], q, em, e[0], e[1]);
+        }
+        issue_a(q, y0);
+        finish_a(P[1], q, e[0], e[1], e[2]);
+        // loads of the first row's A-step (row y0 + 1) and its porosity row
+        eps_row(en, y0 + 2);
+        if (row_in(y0 + 1)) issue_a(q, wrap_row(y0 + 1));
     }
-    // one output row: the window slots of rows y-1, y, y+1 are A0, A1, A2
+    // one output row: the window slots of rows y-1, y, y+1 are A0, A1, A2; q and en
+    // hold the loads for row y+1 (issued one row earlier)
     auto row = [&](auto a0, auto a1, auto a2, int y) {
         constexpr int A0 = decltype(a0)::value, A1 = decltype(a1)::value,
                       A2 = decltype(a2)::value;
         const bool wym = WY && y == 0, wyp = WY && y == g.Ly - 1;
-        R en[3];
-        eps_row(en, y + 2);
-        if (row_in(y + 1)) step_a(P[A2], wrap_row(y + 1), e[A1], e[A2], en);
+        if (row_in(y + 1)) finish_a(P[A2], q, e[A1], e[A2], en);
+        // the slot of row y-1 is free once B has read it: keep row y+2's porosity aside
+        R en2[3];
+        eps_row(en2, y + 3);
+        if (y + 1 < y1 && row_in(y + 2)) issue_a(q, wrap_row(y + 2));
         // step n+1 -> n+2 at row y from the window
         R d[9];
         const R s1 = lane_from_below(P[A1][1]), s3 = lane_from_above(P[A1][3]);
@@ -1027,9 +1046,12 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
 #pragma unroll
             for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i], ph.scale);
         }
-        // the slot of row y-1 takes row y+2
+        // the slot of row y-1 takes row y+2; en takes row y+3
 #pragma unroll
-        for (int j = 0; j < 3; j++) e[A0][j] = en[j];
+        for (int j = 0; j < 3; j++) {
+            e[A0][j] = en[j];
+            en[j] = en2[j];
+        }
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;

@@ -910,6 +910,28 @@ __device__ __forceinline__ float lane_from_above(float v)
                                          0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
 }
 
+// Cached loads and stores of the two-step pass: a strip's 62 columns start
+// one column off a cache line, so the lines at strip seams are shared by two
+// waves; through the cache their halves meet in L2 instead of going to HBM
+// separately (non-temporal accesses measured 20-30% slower here).
+template <typename S, typename R>
+__device__ __forceinline__ R load_cached(const S *p, R inv_scale)
+{
+    if constexpr (std::is_same_v<S, _Float16>)
+        return static_cast<R>(*p) * inv_scale;
+    else
+        return static_cast<R>(*p);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void store_cached(S *p, R v, R scale)
+{
+    if constexpr (std::is_same_v<S, _Float16>)
+        *p = static_cast<_Float16>(v * scale);
+    else
+        *p = static_cast<S>(v);
+}
+
 template <typename S, typename R, bool WY>
 __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
@@ -960,15 +982,15 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
         if (ym < 0) { if (WY) { q.wym = true; ym = yy; } else ym = g.Ly - 1; }
         if (yp >= g.Ly) { if (WY) { q.wyp = true; yp = yy; } else yp = 0; }
         const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
-        q.d[0] = load_pop<S, R>(F[0] + (r0 + x), ph.inv_scale);
-        q.d[1] = load_pop<S, R>(F[1] + (r0 + xm), ph.inv_scale);
-        q.d[2] = load_pop<S, R>(q.wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
-        q.d[3] = load_pop<S, R>(F[3] + (r0 + xp), ph.inv_scale);
-        q.d[4] = load_pop<S, R>(q.wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
-        q.d[5] = load_pop<S, R>(q.wym ? F[7] + (r0 + x) : F[5] + (rm + xm), ph.inv_scale);
-        q.d[6] = load_pop<S, R>(q.wym ? F[8] + (r0 + x) : F[6] + (rm + xp), ph.inv_scale);
-        q.d[7] = load_pop<S, R>(q.wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), ph.inv_scale);
-        q.d[8] = load_pop<S, R>(q.wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), ph.inv_scale);
+        q.d[0] = load_cached<S, R>(F[0] + (r0 + x), ph.inv_scale);
+        q.d[1] = load_cached<S, R>(F[1] + (r0 + xm), ph.inv_scale);
+        q.d[2] = load_cached<S, R>(q.wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
+        q.d[3] = load_cached<S, R>(F[3] + (r0 + xp), ph.inv_scale);
+        q.d[4] = load_cached<S, R>(q.wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
+        q.d[5] = load_cached<S, R>(q.wym ? F[7] + (r0 + x) : F[5] + (rm + xm), ph.inv_scale);
+        q.d[6] = load_cached<S, R>(q.wym ? F[8] + (r0 + x) : F[6] + (rm + xp), ph.inv_scale);
+        q.d[7] = load_cached<S, R>(q.wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), ph.inv_scale);
+        q.d[8] = load_cached<S, R>(q.wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), ph.inv_scale);
     };
     auto finish_a = [&](R (&out)[9], Pending &q, const R (&w0)[3], const R (&w1)[3],
                         const R (&w2)[3]) {
@@ -1044,7 +1066,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
         if (out_ok) {
             const unsigned c = y * pitch + x;
 #pragma unroll
-            for (int i = 0; i < 9; i++) store_pop<S, R>(fout + i * g.plane + c, d[i], ph.scale);
+            for (int i = 0; i < 9; i++) store_cached<S, R>(fout + i * g.plane + c, d[i], ph.scale);
         }
         // the slot of row y-1 takes row y+2; en takes row y+3
 #pragma unroll

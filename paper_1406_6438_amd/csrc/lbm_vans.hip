@@ -882,7 +882,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
 }
 
 // ---- two time steps per pass (periodic x) ----------------------------------
-// Each wave walks a strip of 62 output columns down a chunk of TB_H output
+// Each wave walks a strip of 62 output columns down a chunk of tb_rows output
 // rows, one node per lane: lane l holds column c0 + l - 1, so lanes 0 and 63
 // are the strip's halo.  Per row it (A) gathers and collides step n -> n+1
 // for the row below the output row from the input buffer, keeping the last
@@ -894,7 +894,14 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
 // porosity window held per lane).  The row loop is unrolled by three so that
 // the register window rotates by renaming.
 constexpr int TB_COLS = TX - 2;  // output columns per strip
-constexpr int TB_H = 32;         // output rows per chunk
+
+// Output rows per chunk: shorter chunks recompute more halo rows (2 per chunk)
+// but give more waves to overlap; measured best: 8 rows in FP32, 16 in FP16.
+template <typename S>
+constexpr int tb_rows()
+{
+    return std::is_same_v<S, _Float16> ? 16 : 8;
+}
 
 // Value of the lane below (wave_shr: lane l reads lane l-1) and above
 // (wave_shl: lane l reads lane l+1); the wave's end lanes read 0.
@@ -949,7 +956,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
     const unsigned x = static_cast<unsigned>(xi);
     const unsigned xm = xi == 0 ? g.Lx - 1 : xi - 1, xp = xi == g.Lx - 1 ? 0 : xi + 1;
     const bool out_ok = lane >= 1 && lane <= TB_COLS && xu < g.Lx;
-    const int y0 = chunk * TB_H, y1 = min(y0 + TB_H, g.Ly);
+    const int y0 = chunk * tb_rows<S>(), y1 = min(y0 + tb_rows<S>(), g.Ly);
     const unsigned pitch = g.pitch;
     const S *F[9];
 #pragma unroll
@@ -1962,17 +1969,18 @@ bool tb2_eligible(const lbm_vans_handle *h)
 
 int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
 {
-    const int nstrips = (h->p.Lx + TB_COLS - 1) / TB_COLS;
-    const int nchunks = (h->p.Ly + TB_H - 1) / TB_H;
-    const long long waves = (long long)nstrips * nchunks;
-    if (waves > (long long)INT32_MAX - NW) return fail(LBM_VANS_EINVAL, "lattice too large");
-    const int grid = static_cast<int>((waves + NW - 1) / NW);
     return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         if constexpr (std::is_same_v<S, double>) {
             return fail(LBM_VANS_EINVAL, "two-step pass needs FP32 or FP16 storage");
         } else {
+            const int nstrips = (h->p.Lx + TB_COLS - 1) / TB_COLS;
+            const int nchunks = (h->p.Ly + tb_rows<S>() - 1) / tb_rows<S>();
+            const long long waves = (long long)nstrips * nchunks;
+            if (waves > (long long)INT32_MAX - NW)
+                return fail(LBM_VANS_EINVAL, "lattice too large");
+            const int grid = static_cast<int>((waves + NW - 1) / NW);
             Phys<R> ph = make_phys<R>(&h->p);
             ph.reservoir = 0;
             if (h->g.wall_y)

@@ -187,8 +187,18 @@ def crop_sample(w, lbm, steps: int):
     return gpu, job
 
 
-def time_sweep(w, lbm, torch, steps: int, warmup: int):
-    """(seconds on the library's stream for `steps` steps, final diagnostics record)."""
+def steps_per_launch(w) -> int:
+    """Steps one sweep launch advances: the library runs pairs of steps in one pass
+    (k_sweep_tb2) for FP32 / FP16 storage with a periodic x axis (all box workloads),
+    one step per launch (k_sweep_vec) otherwise."""
+    return 2 if w.storage != "f64" else 1
+
+
+def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0):
+    """(seconds on the library's stream for `steps` steps, final diagnostics record,
+    porosity, seconds per step when every step is its own launch or None).  The
+    second timing calls lbm_vans_step with one step per call, so every step is one
+    single-step launch (k_sweep_vec)."""
     eps = w.porosity()
     s = lbm.Solver(lbm_params(w, lbm), cast_eps(eps, w.storage))
     log(f"[bench] {w.name}: warmup {warmup} steps")
@@ -203,12 +213,21 @@ def time_sweep(w, lbm, torch, steps: int, warmup: int):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_s = e0.elapsed_time(e1) / 1e3
+    single = None
+    if single_steps > 0:
+        e0.record(s.stream)
+        for _ in range(single_steps):
+            s.step(1)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        single = e0.elapsed_time(e1) / 1e3 / single_steps
     diag = s.moments()["diag"]
     s.close()
     del s
     torch.cuda.empty_cache()
-    log(f"[bench] {w.name}: {steps} steps in {gpu_s * 1e3:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
-    return gpu_s, diag, eps
+    log(f"[bench] {w.name}: {steps} steps in {gpu_s * 1e3:.2f} ms (events), {wall * 1e3:.2f} ms (wall)"
+        + (f"; one step per launch: {single * 1e6:.1f} us/step" if single else ""))
+    return gpu_s, diag, eps, single
 
 
 def adjoint_params(lbm, w, Lx=None, Ly=None):
@@ -420,12 +439,16 @@ def main():
     lbm.load()
     w = make_workload(args.workload)
     log(f"[bench] workload {w.name}: {w.Lx}x{w.Ly}, storage {w.storage}")
-    gpu_s, diag, eps = time_sweep(w, lbm, torch, args.steps, args.warmup)
+    gpu_s, diag, eps, single_s = time_sweep(w, lbm, torch, args.steps, args.warmup,
+                                            single_steps=200)
     cells = w.Lx * w.Ly
     mlups = cells * args.steps / gpu_s / 1e6
     bpn = algorithmic_bytes_per_node(w.storage)
-    launch_s = gpu_s / args.steps
-    achieved = bpn * cells / launch_s / 1e9
+    spl = steps_per_launch(w)
+    launch_s = gpu_s / args.steps * spl
+    # algorithmic bytes of a node-step (the single-step scheme's loads and stores)
+    # times the node-steps of one launch
+    achieved = bpn * cells * spl / launch_s / 1e9
     traffic = measured_traffic(args.workload)
     copy_bw = copy_bandwidth_gbps(torch)
     log(f"[bench] {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic, device copy {copy_bw:.1f} GB/s")
@@ -443,7 +466,7 @@ def main():
     if not args.no_fp16 and args.workload == "box4096_f32":
         w16 = make_workload("box8192_f16")
         steps16 = max(1, min(args.steps, 500))
-        g16, d16, _ = time_sweep(w16, lbm, torch, steps16, args.warmup)
+        g16, d16, _, s16 = time_sweep(w16, lbm, torch, steps16, args.warmup, single_steps=100)
         cells16 = w16.Lx * w16.Ly
         m16 = cells16 * steps16 / g16 / 1e6
         b16 = algorithmic_bytes_per_node("f16")
@@ -452,7 +475,12 @@ def main():
                 "ms_per_step": round(g16 * 1e3 / steps16, 5),
                 "roofline": {"bound": "hbm", "achieved": round(a16, 1), "peak": PEAK_HBM_GBPS,
                              "unit": "GB/s", "frac": round(a16 / PEAK_HBM_GBPS, 4),
-                             "traffic": measured_traffic("box8192_f16"), "bytes_per_node": b16},
+                             "traffic": measured_traffic("box8192_f16"), "bytes_per_node": b16,
+                             "kernel": "k_sweep_tb2", "steps_per_launch": 2,
+                             "launch_us": round(g16 / steps16 * 2 * 1e6, 2)},
+                "single_step": {"kernel": "k_sweep_vec", "value": round(cells16 / s16 / 1e6, 2),
+                                "unit": "MLUPS", "frac": round(b16 * cells16 / s16 / 1e9 /
+                                                                PEAK_HBM_GBPS, 4)},
                 "vs_fp32_same_gpu": round(m16 / mlups, 3),
                 "nonfinite_nodes": d16[6], "accuracy": None}
         log(f"[bench] fp16: {m16:.1f} MLUPS, {a16:.1f} GB/s algorithmic")
@@ -508,9 +536,16 @@ def main():
                    "boundaries": "periodic" if not w.walls_y else "periodic x, bounce-back y"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": traffic, "kernel": "k_sweep_vec", "bytes_per_node": bpn,
+                     "traffic": traffic,
+                     "kernel": "k_sweep_tb2" if spl == 2 else "k_sweep_vec",
+                     "steps_per_launch": spl, "bytes_per_node_step": bpn,
                      "launch_us": round(launch_s * 1e6, 2),
                      "device_copy_GBps": round(copy_bw, 1)},
+        "single_step": None if single_s is None else {
+            "kernel": "k_sweep_vec", "value": round(cells / single_s / 1e6, 2), "unit": "MLUPS",
+            "achieved": round(bpn * cells / single_s / 1e9, 1),
+            "frac": round(bpn * cells / single_s / 1e9 / PEAK_HBM_GBPS, 4),
+            "launch_us": round(single_s * 1e6, 2)},
         "accuracy": acc,
         "fp16_store": fp16,
         "adjoint": adj,

@@ -541,6 +541,9 @@ def main():
                      "steps_per_launch": spl, "bytes_per_node_step": bpn,
                      "launch_us": round(launch_s * 1e6, 2),
                      "device_copy_GBps": round(copy_bw, 1)},
+        "hbm": None if traffic is None else {
+            "bytes_per_launch": traffic, "GBps": round(traffic / launch_s / 1e9, 1),
+            "bytes_per_node_step": round(traffic / (cells * spl), 2)},
         "single_step": None if single_s is None else {
             "kernel": "k_sweep_vec", "value": round(cells / single_s / 1e6, 2), "unit": "MLUPS",
             "achieved": round(bpn * cells / single_s / 1e9, 1),

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 4
+#define LBM_VANS_ABI_VERSION 5
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -111,6 +111,15 @@ typedef struct lbm_vans_params {
                               0 otherwise.  A population returned by a sliding wall gains
                               6 w_i eps(x) rho0 (e_i . u_w), the momentum the moving wall
                               imparts under half-way bounce-back.                     */
+    int32_t sweep_vec;     /* nodes per lane of the one-step sweep: 0 = automatic (the
+                              widest, 4 or 2 in LBM_F64, unless the lattice then has fewer
+                              than 1024 tiles: 1); or 1, or the widest.  Results do not
+                              depend on it beyond rounding.                            */
+    int32_t step_pairs;    /* 0 = automatic: lbm_vans_step runs two steps per pass where
+                              it can (LBM_F32_SHIFTED / LBM_F16_SHIFTED, periodic x,
+                              diag_every = 0; the intermediate state stays in registers,
+                              so FP16 storage rounds every other step); 1 = one step per
+                              pass always.                                             */
 } lbm_vans_params;
 
 typedef struct lbm_vans_handle lbm_vans_handle;

@@ -1823,15 +1823,16 @@ int check_params(const lbm_vans_params *p)
         return fail(LBM_VANS_EINVAL, "u_wall must be finite");
     if (p->bc_y != LBM_BC_BOUNCEBACK && (p->u_wall[0] != 0.0 || p->u_wall[1] != 0.0))
         return fail(LBM_VANS_EINVAL, "u_wall needs bounce-back walls in y (bc_y)");
+    const int vmax = p->storage == LBM_F64 ? 2 : 4;
+    if (p->sweep_vec != 0 && p->sweep_vec != 1 && p->sweep_vec != vmax)
+        return fail(LBM_VANS_EINVAL, "sweep_vec = %d: 0 (automatic), 1 or %d", p->sweep_vec,
+                    vmax);
+    if (p->step_pairs != 0 && p->step_pairs != 1)
+        return fail(LBM_VANS_EINVAL, "step_pairs = %d: 0 (automatic) or 1 (never)",
+                    p->step_pairs);
     return LBM_VANS_OK;
 }
 
-// Vector width of the sweep: 16-byte accesses per lane (4 FP32, 2 FP64) and
-// 8-byte ones for FP16 (ragged runs when Lx is not a multiple of it).
-int sweep_vec(const lbm_vans_params *p)
-{
-    return p->storage == LBM_F64 ? 2 : 4;
-}
 
 // Rows per thread of the vector sweep for a storage code (see sweep_rows).
 int sweep_rows_of(int storage) { return storage == LBM_F16_SHIFTED ? 2 : 1; }
@@ -1852,6 +1853,26 @@ Geo make_geo(const lbm_vans_params *p, int vec = 1, int rows = ROWS)
     g.ntiles = g.nbx * nby;
     g.plane = (long long)g.pitch * p->Ly;
     return g;
+}
+
+// Widest vector width of the one-step sweep: 16-byte accesses per lane (4
+// FP32, 2 FP64) and 8-byte ones for FP16 (ragged runs when Lx is not a
+// multiple of it).
+int sweep_vmax(int storage) { return storage == LBM_F64 ? 2 : 4; }
+
+// Tiles below which a lattice does not fill the GPU at the widest width: 4
+// workgroups per compute unit.
+constexpr int SMALL_GRID_TILES = 4 * 256;
+
+// Nodes per lane of the one-step sweep: as requested, or automatically the
+// widest width unless that leaves too few tiles, then one node per lane (4x,
+// or 2x in FP64, more tiles).
+int sweep_vec(const lbm_vans_params *p)
+{
+    const int vmax = sweep_vmax(p->storage);
+    if (p->sweep_vec != 0) return p->sweep_vec;
+    const Geo gv = make_geo(p, vmax, sweep_rows_of(p->storage));
+    return gv.ntiles >= SMALL_GRID_TILES ? vmax : 1;
 }
 
 struct Layout {
@@ -1933,16 +1954,15 @@ int with_types(int storage, Fn &&fn)
     }
 }
 
-template <typename S, typename R, bool DIAG, bool RG>
+template <typename S, typename R, bool DIAG, bool RG, int V>
 void launch_sweep_rg(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
 {
-    constexpr int VMAX = sizeof(S) == 8 ? 2 : 4;
     const dim3 grid(h->gs.ntiles), block(NTHREADS);
     const R *eps = (const R *)h->eps;
     const int bx = h->gs.open_x ? 2 : (h->gs.wall_x ? 1 : 0);
     const bool wy = h->gs.wall_y;
 #define LBM_VANS_VEC(BXV, WYV)                                                                  \
-    hipLaunchKernelGGL((k_sweep_vec<S, R, VMAX, BXV, WYV, DIAG, RG>), grid, block, 0, h->stream, \
+    hipLaunchKernelGGL((k_sweep_vec<S, R, V, BXV, WYV, DIAG, RG>), grid, block, 0, h->stream,    \
                        src, dst, eps, h->gs, ph, h->part)
     if (bx == 0 && !wy) LBM_VANS_VEC(0, false);
     else if (bx == 0) LBM_VANS_VEC(0, true);
@@ -1956,15 +1976,17 @@ void launch_sweep_rg(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph
 template <typename S, typename R, bool DIAG>
 void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
 {
-    if (h->p.Lx % h->vec) launch_sweep_rg<S, R, DIAG, true>(h, src, dst, ph);
-    else launch_sweep_rg<S, R, DIAG, false>(h, src, dst, ph);
+    constexpr int VMAX = sizeof(S) == 8 ? 2 : 4;
+    if (h->vec == 1) launch_sweep_rg<S, R, DIAG, false, 1>(h, src, dst, ph);
+    else if (h->p.Lx % VMAX) launch_sweep_rg<S, R, DIAG, true, VMAX>(h, src, dst, ph);
+    else launch_sweep_rg<S, R, DIAG, false, VMAX>(h, src, dst, ph);
 }
 
 // Two time steps in one pass (k_sweep_tb2): FP32 and FP16 storage with a
 // periodic x axis.
 bool tb2_eligible(const lbm_vans_handle *h)
 {
-    return h->p.storage != LBM_F64 && h->p.bc_x == LBM_BC_PERIODIC;
+    return h->p.step_pairs == 0 && h->p.storage != LBM_F64 && h->p.bc_x == LBM_BC_PERIODIC;
 }
 
 int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)

@@ -27,7 +27,7 @@ F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
 DRAG_ERGUN, DRAG_CONST = 0, 1
 NDIAG = 8
 DIAG_RING = 4096
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
@@ -54,6 +54,7 @@ class LbmVansParams(ctypes.Structure):
         ("rho_in", ctypes.c_double), ("u_in", ctypes.c_double),
         ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double),
         ("u_wall", ctypes.c_double * 2),
+        ("sweep_vec", ctypes.c_int32), ("step_pairs", ctypes.c_int32),
     ]
 
 
@@ -90,6 +91,8 @@ class Params:
     rho_out: float = 1.0
     u_out: float = 0.0
     u_wall: tuple = (0.0, 0.0)
+    sweep_vec: int = 0      # nodes per lane of the one-step sweep, 0 = automatic
+    step_pairs: int = 0     # 0 = two steps per pass where possible, 1 = never
 
     def c(self) -> LbmVansParams:
         return LbmVansParams(self.Lx, self.Ly, self.bc_x, self.bc_y, self.storage, self.drag,
@@ -97,7 +100,8 @@ class Params:
                              (ctypes.c_double * 2)(*self.G), self.rho0,
                              (ctypes.c_double * 2)(*self.u0), self.fp16_scale_log2,
                              self.diag_every, self.rho_in, self.u_in, self.rho_out, self.u_out,
-                             (ctypes.c_double * 2)(*self.u_wall))
+                             (ctypes.c_double * 2)(*self.u_wall), self.sweep_vec,
+                             self.step_pairs)
 
 
 class LbmVansError(RuntimeError):

@@ -34,6 +34,8 @@ class Spec:
     rho_out: float = 1.0
     u_out: float = 0.0
     u_wall: tuple = (0.0, 0.0)      # sliding y-walls: x-velocity below, above
+    sweep_vec: int = 0              # one-step sweep width (0 = automatic)
+    step_pairs: int = 0             # 0 = two steps per pass where possible, 1 = never
 
     def oracle(self) -> oracle.Params:
         return oracle.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
@@ -58,13 +60,23 @@ class Spec:
                           rho0=self.rho0, u0=tuple(self.u0),
                           fp16_scale_log2=self.fp16_scale_log2, diag_every=self.diag_every,
                           rho_in=self.rho_in, u_in=self.u_in, rho_out=self.rho_out,
-                          u_out=self.u_out, u_wall=tuple(self.u_wall))
+                          u_out=self.u_out, u_wall=tuple(self.u_wall),
+                          sweep_vec=self.sweep_vec, step_pairs=self.step_pairs)
 
     def input_eps(self, eps: np.ndarray) -> np.ndarray:
         """The porosity both sides receive: rounded once to the GPU's compute precision."""
         if self.storage == "f64":
             return np.ascontiguousarray(eps, dtype=np.float64)
         return np.ascontiguousarray(eps, dtype=np.float32).astype(np.float64)
+
+
+# Execution paths of lbm_vans_step: "auto" (the library's choice: two steps per pass
+# where possible, one node per lane on small lattices) and "wide" (one step per pass,
+# widest vector width), so that small test grids cover both one-step kernels.
+def exec_mode(mode: str, storage: str) -> dict:
+    if mode == "auto":
+        return {}
+    return {"sweep_vec": 2 if storage == "f64" else 4, "step_pairs": 1}
 
 
 def say(*a):

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity_util import Spec, gpu_run, oracle_run, rel_l2, say
+from parity_util import Spec, exec_mode, gpu_run, oracle_run, rel_l2, say
 from paper_1406_6438_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -66,12 +66,13 @@ def _perturbed_start(spec, eps, seed, amp=2e-3):
     return oracle.init(p, spec.input_eps(eps)) * (1.0 + W.noise((9, spec.Ly, spec.Lx), seed, amp))
 
 
+@pytest.mark.parametrize("mode", ["auto", "wide"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
-def test_f64_parity_small_grids(geom):
+def test_f64_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
-    say(f"[f64 parity] {Lx}x{Ly} walls=({wx},{wy})")
+    say(f"[f64 parity {mode}] {Lx}x{Ly} walls=({wx},{wy})")
     spec = Spec(Lx=Lx, Ly=Ly, tau=0.62, walls_x=wx, walls_y=wy, d_p=6.0, G=(2e-5, -1e-5),
-                u0=(0.01, 0.004), storage="f64")
+                u0=(0.01, 0.004), storage="f64", **exec_mode(mode, "f64"))
     eps = W.grf_porosity(Lx, Ly, seed=100 + Lx, ell=2.5, lo=0.35, hi=1.0)
     f0 = _perturbed_start(spec, eps, seed=Ly)
     mg, fg = gpu_run(spec, eps, 40, f0)
@@ -81,12 +82,13 @@ def test_f64_parity_small_grids(geom):
     assert np.abs(mg["rho"] - mo["rho"]).max() <= 1e-13
 
 
+@pytest.mark.parametrize("mode", ["auto", "wide"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
-def test_f32_parity_small_grids(geom):
+def test_f32_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
-    say(f"[f32 parity] {Lx}x{Ly} walls=({wx},{wy})")
+    say(f"[f32 parity {mode}] {Lx}x{Ly} walls=({wx},{wy})")
     spec = Spec(Lx=Lx, Ly=Ly, tau=0.62, walls_x=wx, walls_y=wy, d_p=6.0, G=(2e-5, -1e-5),
-                u0=(0.01, 0.004), storage="f32")
+                u0=(0.01, 0.004), storage="f32", **exec_mode(mode, "f32"))
     eps = W.grf_porosity(Lx, Ly, seed=100 + Lx, ell=2.5, lo=0.35, hi=1.0)
     f0 = _perturbed_start(spec, eps, seed=Ly)
     nsteps = 40
@@ -299,12 +301,14 @@ def test_init_rejects_porosity_outside_unit_interval():
 # the FP16 workload is rel. L2(u) <= 2e-3 against the FP64 oracle after 2000 steps.
 
 
+@pytest.mark.parametrize("mode", ["auto", "wide"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
-def test_f16_parity_small_grids(geom):
+def test_f16_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
-    say(f"[f16 parity] {Lx}x{Ly} walls=({wx},{wy})")
+    say(f"[f16 parity {mode}] {Lx}x{Ly} walls=({wx},{wy})")
     spec = Spec(Lx=Lx, Ly=Ly, tau=0.62, walls_x=wx, walls_y=wy, d_p=6.0, G=(2e-5, -1e-5),
-                u0=(0.01, 0.004), storage="f16", fp16_scale_log2=10)
+                u0=(0.01, 0.004), storage="f16", fp16_scale_log2=10,
+                **exec_mode(mode, "f16"))
     eps = W.grf_porosity(Lx, Ly, seed=100 + Lx, ell=2.5, lo=0.35, hi=1.0)
     f0 = _perturbed_start(spec, eps, seed=Ly)
     nsteps = 40

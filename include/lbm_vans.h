@@ -112,9 +112,8 @@ typedef struct lbm_vans_params {
                               6 w_i eps(x) rho0 (e_i . u_w), the momentum the moving wall
                               imparts under half-way bounce-back.                     */
     int32_t sweep_vec;     /* nodes per lane of the one-step sweep: 0 = automatic (the
-                              widest, 4 or 2 in LBM_F64, unless the lattice then has fewer
-                              than 1024 tiles: 1); or 1, or the widest.  Results do not
-                              depend on it beyond rounding.                            */
+                              widest: 4, or 2 in LBM_F64); 1; or the widest.  Results do
+                              not depend on it beyond rounding.                        */
     int32_t step_pairs;    /* 0 = automatic: lbm_vans_step runs two steps per pass where
                               it can (LBM_F32_SHIFTED / LBM_F16_SHIFTED, periodic x,
                               diag_every = 0; the intermediate state stays in registers,

@@ -1860,19 +1860,12 @@ Geo make_geo(const lbm_vans_params *p, int vec = 1, int rows = ROWS)
 // multiple of it).
 int sweep_vmax(int storage) { return storage == LBM_F64 ? 2 : 4; }
 
-// Tiles below which a lattice does not fill the GPU at the widest width: 4
-// workgroups per compute unit.
-constexpr int SMALL_GRID_TILES = 4 * 256;
-
-// Nodes per lane of the one-step sweep: as requested, or automatically the
-// widest width unless that leaves too few tiles, then one node per lane (4x,
-// or 2x in FP64, more tiles).
+// Nodes per lane of the one-step sweep: as requested, else the widest.  (One
+// node per lane gives a small lattice 4x more tiles, yet measured slower: on the
+// 1024 x 512 channel 51.6 against 57.2 GLUPS with 512 tiles of 4 nodes per lane.)
 int sweep_vec(const lbm_vans_params *p)
 {
-    const int vmax = sweep_vmax(p->storage);
-    if (p->sweep_vec != 0) return p->sweep_vec;
-    const Geo gv = make_geo(p, vmax, sweep_rows_of(p->storage));
-    return gv.ntiles >= SMALL_GRID_TILES ? vmax : 1;
+    return p->sweep_vec != 0 ? p->sweep_vec : sweep_vmax(p->storage);
 }
 
 struct Layout {

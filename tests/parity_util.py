@@ -71,12 +71,15 @@ class Spec:
 
 
 # Execution paths of lbm_vans_step: "auto" (the library's choice: two steps per pass
-# where possible, one node per lane on small lattices) and "wide" (one step per pass,
-# widest vector width), so that small test grids cover both one-step kernels.
+# where possible, else the widest one-step sweep), "wide" (one step per pass, widest
+# vector width) and "narrow" (one step per pass, one node per lane), so that the test
+# grids cover every sweep kernel.
 def exec_mode(mode: str, storage: str) -> dict:
     if mode == "auto":
         return {}
-    return {"sweep_vec": 2 if storage == "f64" else 4, "step_pairs": 1}
+    if mode == "wide":
+        return {"sweep_vec": 2 if storage == "f64" else 4, "step_pairs": 1}
+    return {"sweep_vec": 1, "step_pairs": 1}
 
 
 def say(*a):

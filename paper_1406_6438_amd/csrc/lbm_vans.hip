@@ -882,20 +882,18 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
 }
 
 // ---- two time steps per pass (periodic x) ----------------------------------
-// Each wave walks a strip of 64 columns (one node per lane, aligned to the
-// cache lines) down a chunk of tb_rows output rows.  Per row it (A) gathers
-// and collides step n -> n+1 for the row below the output row from the input
-// buffer, keeping the last three post-collision rows of step n+1 in registers,
-// and (B) pulls step n+1 -> n+2 for the output row from those rows (x-shifts by
-// DPP wave shifts, bounce-back behind y-walls from the node's own row) and
-// stores it.  The state of step n+1 never leaves the registers: the pass moves
-// the bytes of one step for two.  The values that enter a strip across its
-// sides at step n+1 (from the columns left and right of it) are computed
-// beforehand by k_tb2_halo, one node per thread, into a small buffer.  The
-// node update is the sweep's own (update_node on a 3x3 porosity window held
-// per lane).  The row loop is unrolled by three so that the register window
-// rotates by renaming.
-constexpr int TB_COLS = TX;  // columns per strip
+// Each wave walks a strip of 62 output columns down a chunk of tb_rows output
+// rows, one node per lane: lane l holds column c0 + l - 1, so lanes 0 and 63
+// are the strip's halo.  Per row it (A) gathers and collides step n -> n+1
+// for the row below the output row from the input buffer, keeping the last
+// three post-collision rows of step n+1 in registers, and (B) pulls step
+// n+1 -> n+2 for the output row from those rows (x-shifts by DPP wave shifts,
+// bounce-back behind y-walls from the node's own row) and stores it.  The
+// state of step n+1 never leaves the registers: the pass moves the bytes of
+// one step for two.  The node update is the sweep's own (update_node on a 3x3
+// porosity window held per lane).  The row loop is unrolled by three so that
+// the register window rotates by renaming.
+constexpr int TB_COLS = TX - 2;  // output columns per strip
 
 // Output rows per chunk: shorter chunks recompute more halo rows (2 per chunk)
 // but give more waves to overlap; measured best: 8 rows in FP32, 16 in FP16.
@@ -903,15 +901,6 @@ template <typename S>
 constexpr int tb_rows()
 {
     return std::is_same_v<S, _Float16> ? 16 : 8;
-}
-
-// Halo buffer of the two-step pass: for strip w and row y, the three
-// populations of step n+1 that enter the strip from the column left of it
-// (e_1, e_5, e_8 of column 64w - 1) and from the column right of it (e_3, e_6,
-// e_7 of column 64w + 64), both wrapped; [nstrips][2][Ly][3] floats.
-__device__ __forceinline__ long long tb_halo_at(int w, int side, int y, int Ly)
-{
-    return ((static_cast<long long>(w) * 2 + side) * Ly + y) * 3;
 }
 
 // Value of the lane below (wave_shr: lane l reads lane l-1) and above
@@ -928,8 +917,10 @@ __device__ __forceinline__ float lane_from_above(float v)
                                          0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
 }
 
-// Loads and stores of the two-step pass go through the cache (a strip's
-// neighbours read the lines at its sides in the same pass).
+// Cached loads and stores of the two-step pass: a strip's 62 columns start
+// one column off a cache line, so the lines at strip seams are shared by two
+// waves; through the cache their halves meet in L2 instead of going to HBM
+// separately (non-temporal accesses measured 20-30% slower here).
 template <typename S, typename R>
 __device__ __forceinline__ R load_cached(const S *p, R inv_scale)
 {
@@ -948,148 +939,97 @@ __device__ __forceinline__ void store_cached(S *p, R v, R scale)
         *p = static_cast<S>(v);
 }
 
-// Step n -> n+1 at node (x, yy) of a periodic-x lattice: the gather's loads
-// (issued ahead of their use by the caller) and the node update on them.
-template <typename R>
-struct TbPending {
-    R d[9];
-    bool wym, wyp;
-};
-
-template <typename S, typename R, bool WY>
-__device__ __forceinline__ void tb_issue(TbPending<R> &q, const S *const F[9], unsigned x,
-                                         unsigned xm, unsigned xp, int yy, const Geo &g,
-                                         R inv_scale)
-{
-    q.wym = false;
-    q.wyp = false;
-    int ym = yy - 1, yp = yy + 1;
-    if (ym < 0) { if (WY) { q.wym = true; ym = yy; } else ym = g.Ly - 1; }
-    if (yp >= g.Ly) { if (WY) { q.wyp = true; yp = yy; } else yp = 0; }
-    const unsigned pitch = g.pitch;
-    const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
-    q.d[0] = load_cached<S, R>(F[0] + (r0 + x), inv_scale);
-    q.d[1] = load_cached<S, R>(F[1] + (r0 + xm), inv_scale);
-    q.d[2] = load_cached<S, R>(q.wym ? F[4] + (r0 + x) : F[2] + (rm + x), inv_scale);
-    q.d[3] = load_cached<S, R>(F[3] + (r0 + xp), inv_scale);
-    q.d[4] = load_cached<S, R>(q.wyp ? F[2] + (r0 + x) : F[4] + (rp + x), inv_scale);
-    q.d[5] = load_cached<S, R>(q.wym ? F[7] + (r0 + x) : F[5] + (rm + xm), inv_scale);
-    q.d[6] = load_cached<S, R>(q.wym ? F[8] + (r0 + x) : F[6] + (rm + xp), inv_scale);
-    q.d[7] = load_cached<S, R>(q.wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), inv_scale);
-    q.d[8] = load_cached<S, R>(q.wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), inv_scale);
-}
-
-template <typename R>
-__device__ __forceinline__ void tb_finish(R (&out)[9], TbPending<R> &q, const R (&w0)[3],
-                                          const R (&w1)[3], const R (&w2)[3],
-                                          const Phys<R> &ph)
-{
-    const R t[3][3] = {{w0[0], w0[1], w0[2]}, {w1[0], w1[1], w1[2]}, {w2[0], w2[1], w2[2]}};
-    update_node<R, 3, false>(q.d, t, 1, 1, false, false, q.wym, q.wyp, false, false, ph,
-                             nullptr, false);
-#pragma unroll
-    for (int i = 0; i < 9; i++) out[i] = q.d[i];
-}
-
-template <typename R>
-__device__ __forceinline__ void tb_eps_row(R (&r)[3], const R *__restrict__ eps, int row,
-                                           unsigned x, unsigned xm, unsigned xp, const Geo &g)
-{
-    const unsigned o = static_cast<unsigned>(halo_index(row, g.Ly, g.wall_y)) * g.pitch;
-    r[0] = eps[o + xm];
-    r[1] = eps[o + x];
-    r[2] = eps[o + xp];
-}
-
-// The halo of every strip: one thread per (strip, side, row).
-template <typename S, typename R, bool WY>
-__global__ __launch_bounds__(NTHREADS) void k_tb2_halo(const S *__restrict__ fin,
-                                                       const R *__restrict__ eps, Geo g,
-                                                       Phys<R> ph, int nstrips,
-                                                       float *__restrict__ halo)
-{
-    const long long t = static_cast<long long>(blockIdx.x) * NTHREADS + threadIdx.x;
-    if (t >= static_cast<long long>(nstrips) * 2 * g.Ly) return;
-    const int y = static_cast<int>(t % g.Ly);
-    const int side = static_cast<int>((t / g.Ly) % 2);
-    const int w = static_cast<int>(t / (2LL * g.Ly));
-    const long long xu = side ? 64LL * (w + 1) : 64LL * w - 1;
-    int xi = static_cast<int>(xu % g.Lx);
-    if (xi < 0) xi += g.Lx;
-    const unsigned x = xi;
-    const unsigned xm = xi == 0 ? g.Lx - 1 : xi - 1, xp = xi == g.Lx - 1 ? 0 : xi + 1;
-    const S *F[9];
-#pragma unroll
-    for (int i = 0; i < 9; i++) F[i] = fin + i * g.plane;
-    R e0[3], e1[3], e2[3];
-    tb_eps_row<R>(e0, eps, y - 1, x, xm, xp, g);
-    tb_eps_row<R>(e1, eps, y, x, xm, xp, g);
-    tb_eps_row<R>(e2, eps, y + 1, x, xm, xp, g);
-    TbPending<R> q;
-    tb_issue<S, R, WY>(q, F, x, xm, xp, y, g, ph.inv_scale);
-    R d[9];
-    tb_finish<R>(d, q, e0, e1, e2, ph);
-    float *o = halo + tb_halo_at(w, side, y, g.Ly);
-    if (side == 0) {
-        o[0] = d[1]; o[1] = d[5]; o[2] = d[8];
-    } else {
-        o[0] = d[3]; o[1] = d[6]; o[2] = d[7];
-    }
-}
-
 template <typename S, typename R, bool WY>
 __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
-                                                        Phys<R> ph, int nstrips, int nchunks,
-                                                        const float *__restrict__ halo)
+                                                        Phys<R> ph, int nstrips, int nchunks)
 {
     static_assert(std::is_same_v<R, float>, "two-step pass computes in FP32");
     const int lane = threadIdx.x % TX;
     const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
     const int strip = wid % nstrips, chunk = wid / nstrips;
     if (chunk >= nchunks) return;              // whole waves only; no barrier below
-    const int xu = strip * TB_COLS + lane;      // unwrapped column
-    const int xi = xu % g.Lx;                   // lanes past the end wrap around
+    const int xu = strip * TB_COLS + lane - 1;  // unwrapped column
+    int xi = xu % g.Lx;
+    if (xi < 0) xi += g.Lx;
     const unsigned x = static_cast<unsigned>(xi);
     const unsigned xm = xi == 0 ? g.Lx - 1 : xi - 1, xp = xi == g.Lx - 1 ? 0 : xi + 1;
-    const bool out_ok = xu < g.Lx;
-    const bool hl = lane == 0, hr = lane == TX - 1;
+    const bool out_ok = lane >= 1 && lane <= TB_COLS && xu < g.Lx;
     const int y0 = chunk * tb_rows<S>(), y1 = min(y0 + tb_rows<S>(), g.Ly);
     const unsigned pitch = g.pitch;
     const S *F[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) F[i] = fin + i * g.plane;
+
+    // porosity window: rows y-1 .. y+1 of the output row y in a three-slot ring,
+    // columns x-1 .. x+1
+    R e[3][3];
+    auto eps_row = [&](R (&r)[3], int row) {
+        const unsigned o = static_cast<unsigned>(halo_index(row, g.Ly, g.wall_y)) * pitch;
+        r[0] = eps[o + xm];
+        r[1] = eps[o + x];
+        r[2] = eps[o + xp];
+    };
     auto row_in = [&](int row) { return WY ? (row >= 0 && row < g.Ly) : true; };
     auto wrap_row = [&](int row) {
         return row < 0 ? row + g.Ly : (row >= g.Ly ? row - g.Ly : row);
     };
-    // porosity window: rows y-1 .. y+1 of the output row y in a three-slot ring,
-    // columns x-1 .. x+1
-    R e[3][3];
+    // step n -> n+1 at row yy (inside the domain), in two parts: the loads of the
+    // gather (issued one row ahead, so that they are in flight while the wave
+    // computes the row before), then the node update on them
+    struct Pending {
+        R d[9];
+        bool wym, wyp;
+    };
+    auto issue_a = [&](Pending &q, int yy) {
+        q.wym = false;
+        q.wyp = false;
+        int ym = yy - 1, yp = yy + 1;
+        if (ym < 0) { if (WY) { q.wym = true; ym = yy; } else ym = g.Ly - 1; }
+        if (yp >= g.Ly) { if (WY) { q.wyp = true; yp = yy; } else yp = 0; }
+        const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
+        q.d[0] = load_cached<S, R>(F[0] + (r0 + x), ph.inv_scale);
+        q.d[1] = load_cached<S, R>(F[1] + (r0 + xm), ph.inv_scale);
+        q.d[2] = load_cached<S, R>(q.wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
+        q.d[3] = load_cached<S, R>(F[3] + (r0 + xp), ph.inv_scale);
+        q.d[4] = load_cached<S, R>(q.wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
+        q.d[5] = load_cached<S, R>(q.wym ? F[7] + (r0 + x) : F[5] + (rm + xm), ph.inv_scale);
+        q.d[6] = load_cached<S, R>(q.wym ? F[8] + (r0 + x) : F[6] + (rm + xp), ph.inv_scale);
+        q.d[7] = load_cached<S, R>(q.wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), ph.inv_scale);
+        q.d[8] = load_cached<S, R>(q.wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), ph.inv_scale);
+    };
+    auto finish_a = [&](R (&out)[9], Pending &q, const R (&w0)[3], const R (&w1)[3],
+                        const R (&w2)[3]) {
+        const R t[3][3] = {{w0[0], w0[1], w0[2]}, {w1[0], w1[1], w1[2]}, {w2[0], w2[1], w2[2]}};
+        update_node<R, 3, false>(q.d, t, 1, 1, false, false, q.wym, q.wyp, false, false, ph,
+                                 nullptr, false);
+#pragma unroll
+        for (int i = 0; i < 9; i++) out[i] = q.d[i];
+    };
+
     R P[3][9];
-    TbPending<R> q;
+    Pending q;
     R en[3];
     // the window starts with step n+1 at rows y0-1 (slot 0) and y0 (slot 1); row -1
     // lies behind a wall when y has walls, and is then never read
     {
         R em[3];
-        tb_eps_row<R>(em, eps, y0 - 2, x, xm, xp, g);
-        tb_eps_row<R>(e[0], eps, y0 - 1, x, xm, xp, g);
-        tb_eps_row<R>(e[1], eps, y0, x, xm, xp, g);
-        tb_eps_row<R>(e[2], eps, y0 + 1, x, xm, xp, g);
+        eps_row(em, y0 - 2);
+        eps_row(e[0], y0 - 1);
+        eps_row(e[1], y0);
+        eps_row(e[2], y0 + 1);
 #pragma unroll
         for (int i = 0; i < 9; i++) P[0][i] = P[2][i] = R(0);
         if (row_in(y0 - 1)) {
-            tb_issue<S, R, WY>(q, F, x, xm, xp, wrap_row(y0 - 1), g, ph.inv_scale);
-            tb_finish<R>(P[0], q, em, e[0], e[1], ph);
+            issue_a(q, wrap_row(y0 - 1));
+            finish_a(P[0], q, em, e[0], e[1]);
         }
-        tb_issue<S, R, WY>(q, F, x, xm, xp, y0, g, ph.inv_scale);
-        tb_finish<R>(P[1], q, e[0], e[1], e[2], ph);
+        issue_a(q, y0);
+        finish_a(P[1], q, e[0], e[1], e[2]);
         // loads of the first row's A-step (row y0 + 1) and its porosity row
-        tb_eps_row<R>(en, eps, y0 + 2, x, xm, xp, g);
-        if (row_in(y0 + 1))
-            tb_issue<S, R, WY>(q, F, x, xm, xp, wrap_row(y0 + 1), g, ph.inv_scale);
+        eps_row(en, y0 + 2);
+        if (row_in(y0 + 1)) issue_a(q, wrap_row(y0 + 1));
     }
     // one output row: the window slots of rows y-1, y, y+1 are A0, A1, A2; q and en
     // hold the loads for row y+1 (issued one row earlier)
@@ -1097,44 +1037,34 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
         constexpr int A0 = decltype(a0)::value, A1 = decltype(a1)::value,
                       A2 = decltype(a2)::value;
         const bool wym = WY && y == 0, wyp = WY && y == g.Ly - 1;
-        // what enters the strip's side lanes from the columns beside it
-        R h0 = R(0), hm = R(0), hp = R(0);
-        if (hl || hr) {
-            const int side = hr ? 1 : 0;
-            h0 = halo[tb_halo_at(strip, side, y, g.Ly) + 0];
-            if (!wym) hm = halo[tb_halo_at(strip, side, wrap_row(y - 1), g.Ly) + 1];
-            if (!wyp) hp = halo[tb_halo_at(strip, side, wrap_row(y + 1), g.Ly) + 2];
-        }
-        if (row_in(y + 1)) tb_finish<R>(P[A2], q, e[A1], e[A2], en, ph);
+        if (row_in(y + 1)) finish_a(P[A2], q, e[A1], e[A2], en);
+        // the slot of row y-1 is free once B has read it: keep row y+2's porosity aside
         R en2[3];
-        tb_eps_row<R>(en2, eps, y + 3, x, xm, xp, g);
-        if (y + 1 < y1 && row_in(y + 2))
-            tb_issue<S, R, WY>(q, F, x, xm, xp, wrap_row(y + 2), g, ph.inv_scale);
+        eps_row(en2, y + 3);
+        if (y + 1 < y1 && row_in(y + 2)) issue_a(q, wrap_row(y + 2));
         // step n+1 -> n+2 at row y from the window
         R d[9];
         const R s1 = lane_from_below(P[A1][1]), s3 = lane_from_above(P[A1][3]);
         d[0] = P[A1][0];
-        d[1] = hl ? h0 : s1;
-        d[3] = hr ? h0 : s3;
+        d[1] = s1;
+        d[3] = s3;
         if (wym) {
             d[2] = P[A1][4];
             d[5] = P[A1][7];
             d[6] = P[A1][8];
         } else {
-            const R s5 = lane_from_below(P[A0][5]), s6 = lane_from_above(P[A0][6]);
             d[2] = P[A0][2];
-            d[5] = hl ? hm : s5;
-            d[6] = hr ? hm : s6;
+            d[5] = lane_from_below(P[A0][5]);
+            d[6] = lane_from_above(P[A0][6]);
         }
         if (wyp) {
             d[4] = P[A1][2];
             d[7] = P[A1][5];
             d[8] = P[A1][6];
         } else {
-            const R s7 = lane_from_above(P[A2][7]), s8 = lane_from_below(P[A2][8]);
             d[4] = P[A2][4];
-            d[7] = hr ? hp : s7;
-            d[8] = hl ? hp : s8;
+            d[7] = lane_from_above(P[A2][7]);
+            d[8] = lane_from_below(P[A2][8]);
         }
         const R t[3][3] = {{e[A0][0], e[A0][1], e[A0][2]}, {e[A1][0], e[A1][1], e[A1][2]},
                            {e[A2][0], e[A2][1], e[A2][2]}};
@@ -1836,7 +1766,6 @@ struct lbm_vans_handle {
     double *mass0;          // rho0 * sum eps
     double *scratch_rec;    // one diagnostics record
     double *ring;           // [LBM_VANS_DIAG_RING][NRED]
-    float *tbhalo;          // halo buffer of the two-step pass (null when it does not apply)
     int64_t n;              // steps taken
     int64_t nrec;           // diagnostics records written
 };
@@ -1940,15 +1869,8 @@ int sweep_vec(const lbm_vans_params *p)
 }
 
 struct Layout {
-    size_t pop, eps, part, small, halo, total;
+    size_t pop, eps, part, small, total;
 };
-
-// Strips of the two-step pass (k_sweep_tb2), 0 when the parameters do not allow it.
-int tb2_strips(const lbm_vans_params *p)
-{
-    if (p->storage == LBM_F64 || p->bc_x != LBM_BC_PERIODIC || p->step_pairs != 0) return 0;
-    return (p->Lx + TB_COLS - 1) / TB_COLS;
-}
 
 Layout make_layout(const lbm_vans_params *p)
 {
@@ -1958,8 +1880,7 @@ Layout make_layout(const lbm_vans_params *p)
     L.eps = align256((size_t)g.plane * (p->storage == LBM_F64 ? 8 : 4));
     L.part = align256((size_t)g.ntiles * NRED * sizeof(double));
     L.small = align256((size_t)(2 + NRED + (size_t)LBM_VANS_DIAG_RING * NRED) * sizeof(double));
-    L.halo = align256((size_t)tb2_strips(p) * 2 * p->Ly * 3 * sizeof(float));
-    L.total = 2 * L.pop + L.eps + L.part + L.small + L.halo;
+    L.total = 2 * L.pop + L.eps + L.part + L.small;
     return L;
 }
 
@@ -2056,7 +1977,10 @@ void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
 
 // Two time steps in one pass (k_sweep_tb2): FP32 and FP16 storage with a
 // periodic x axis.
-bool tb2_eligible(const lbm_vans_handle *h) { return h->tbhalo != nullptr; }
+bool tb2_eligible(const lbm_vans_handle *h)
+{
+    return h->p.step_pairs == 0 && h->p.storage != LBM_F64 && h->p.bc_x == LBM_BC_PERIODIC;
+}
 
 int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
 {
@@ -2066,31 +1990,22 @@ int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
         if constexpr (std::is_same_v<S, double>) {
             return fail(LBM_VANS_EINVAL, "two-step pass needs FP32 or FP16 storage");
         } else {
-            const int nstrips = tb2_strips(&h->p);
+            const int nstrips = (h->p.Lx + TB_COLS - 1) / TB_COLS;
             const int nchunks = (h->p.Ly + tb_rows<S>() - 1) / tb_rows<S>();
             const long long waves = (long long)nstrips * nchunks;
-            const long long hthreads = (long long)nstrips * 2 * h->p.Ly;
-            if (waves > (long long)INT32_MAX - NW || hthreads > (long long)INT32_MAX)
+            if (waves > (long long)INT32_MAX - NW)
                 return fail(LBM_VANS_EINVAL, "lattice too large");
             const int grid = static_cast<int>((waves + NW - 1) / NW);
-            const int hgrid = static_cast<int>((hthreads + NTHREADS - 1) / NTHREADS);
             Phys<R> ph = make_phys<R>(&h->p);
             ph.reservoir = 0;
-            if (h->g.wall_y) {
-                hipLaunchKernelGGL((k_tb2_halo<S, R, true>), dim3(hgrid), dim3(NTHREADS), 0,
-                                   h->stream, (const S *)src, (const R *)h->eps, h->g, ph,
-                                   nstrips, h->tbhalo);
+            if (h->g.wall_y)
                 hipLaunchKernelGGL((k_sweep_tb2<S, R, true>), dim3(grid), dim3(NTHREADS), 0,
                                    h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g,
-                                   ph, nstrips, nchunks, (const float *)h->tbhalo);
-            } else {
-                hipLaunchKernelGGL((k_tb2_halo<S, R, false>), dim3(hgrid), dim3(NTHREADS), 0,
-                                   h->stream, (const S *)src, (const R *)h->eps, h->g, ph,
-                                   nstrips, h->tbhalo);
+                                   ph, nstrips, nchunks);
+            else
                 hipLaunchKernelGGL((k_sweep_tb2<S, R, false>), dim3(grid), dim3(NTHREADS), 0,
                                    h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g,
-                                   ph, nstrips, nchunks, (const float *)h->tbhalo);
-            }
+                                   ph, nstrips, nchunks);
             return check_launch("k_sweep_tb2");
         }
     });
@@ -2169,8 +2084,6 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
     h->mass0 = small;
     h->scratch_rec = small + 2;
     h->ring = small + 2 + NRED;
-    h->tbhalo = L.halo ? reinterpret_cast<float *>(w + 2 * L.pop + L.eps + L.part + L.small)
-                       : nullptr;
     h->cur = 0;
     h->n = 0;
     h->nrec = 0;

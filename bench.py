@@ -9,7 +9,8 @@ launch).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line with MLUPS, the HBM roofline of the sweep kernel, the
 FP16-storage sweep on the 8192^2 box beside it, the gradient leg, the ensemble
-leg (64 uneven channels, batched launches) and the CPU baseline: the FP64
+leg (64 uneven channels, batched launches), the paper's Couette experiment
+against eq. (velocity), and the CPU baseline: the FP64
 oracle timed on the host cores on bounded samples of the workloads.  The
 oracle runs only in that leg; its sample results also give the accuracy
 figures (the GPU runs the same samples -- the 512^2 crops of the boxes, a small
@@ -401,6 +402,51 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
     return out, sample
 
 
+def eq_velocity_profile(c, L: int, eps: float):
+    """Solution of the paper's eq. (velocity) for a Couette case, read with d^2/dy^2 and
+    |u| u: nu u'' - (eps nu / K) u - (eps^2 F_eps / sqrt(K)) |u| u = 0, u = 0 on the plate
+    at y = -1/2, u = U on the plate at y = L - 1/2, at the node rows y + 1/2."""
+    import math
+    import numpy as np
+    from scipy.integrate import solve_bvp
+    a = eps * c.nu / c.K
+    b = eps ** 2 * (1.75 / math.sqrt(150.0 * eps ** 3)) / math.sqrt(c.K)
+
+    def rhs(_, Y):
+        return np.vstack([Y[1], (a * Y[0] + b * np.abs(Y[0]) * Y[0]) / c.nu])
+
+    s = np.linspace(0.0, float(L), 401)
+    sol = solve_bvp(rhs, lambda ya, yb: np.array([ya[0], yb[0] - c.U]), s,
+                    np.vstack([c.U * s / L, np.full_like(s, c.U / L)]), tol=1e-10,
+                    max_nodes=200000)
+    return sol.sol(np.arange(L) + 0.5)[0]
+
+
+def couette_leg(lbm, torch):
+    """The paper's Couette experiment on the GPU (FP64, 80 x 80, porosity 0.1, upper
+    plate sliding, 160000 steps per case): the largest deviation of the profile at
+    x = H/2 from the solution of eq. (velocity), relative to the plate velocity."""
+    import numpy as np
+    from paper_1406_6438_amd import workloads as W
+    L, eps0, n = W.COUETTE_L, W.COUETTE_EPS, W.COUETTE_STEPS
+    cases = []
+    t0 = time.perf_counter()
+    for Re, Da in W.COUETTE_CASES:
+        c = W.couette_case(Re, Da)
+        p = lbm.Params(Lx=L, Ly=L, tau=c.tau, bc_y=lbm.BC_BOUNCEBACK, storage=lbm.F64,
+                       d_p=c.d_p, u_wall=(0.0, c.U))
+        s = lbm.Solver(p, np.full((L, L), eps0))
+        s.step(n)
+        ux = s.moments(want_diag=False)["ux"].cpu().numpy()
+        s.close()
+        err = float(np.abs(ux[:, L // 2] - eq_velocity_profile(c, L, eps0)).max() / c.U)
+        cases.append({"Re": Re, "Da": Da, "tau": c.tau, "U": c.U,
+                      "max_err_vs_eq_velocity_over_U": err})
+        log(f"[bench] couette Re {Re} Da {Da}: max |u - eq.(velocity)| / U = {err:.2e}")
+    return {"lattice": f"{L}x{L}", "porosity": eps0, "steps": n, "storage": "f64",
+            "seconds": round(time.perf_counter() - t0, 2), "cases": cases}
+
+
 def _close_all(solvers, batch):
     batch.close()
     for s in solvers:
@@ -424,6 +470,8 @@ def main():
                     help="skip the gradient leg (1024x512 open channel) reported beside the main line")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the ensemble leg (64 uneven open channels) reported beside the main line")
+    ap.add_argument("--no-couette", action="store_true",
+                    help="skip the paper's Couette experiment reported beside the main line")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="timed steps of the ensemble leg (--no-adjoint also skips its gradient)")
     args = ap.parse_args()
@@ -505,6 +553,10 @@ def main():
             ens["accuracy"] = {}
             samples.append((ens["accuracy"], smp[0], smp[1], smp[2]))
 
+    couette = None
+    if not args.no_couette and args.workload == "box4096_f32":
+        couette = couette_leg(lbm, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (~{args.cpu_seconds:.0f} s) and {len(samples)} oracle samples")
@@ -553,6 +605,7 @@ def main():
         "fp16_store": fp16,
         "adjoint": adj,
         "ensemble": ens,
+        "couette": couette,
         "cpu_baseline": cpu,
         "mass_check": {"sum_eps_rho": diag[0], "nonfinite_nodes": diag[6]},
     }

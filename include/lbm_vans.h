@@ -147,7 +147,9 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
  * for every node, the moments of eqs. (0moment)/(1moment) (velocity implicit
  * through the drag, solved exactly), collision toward eq. (d2q9eq) with the
  * sources of eqs. (pi) and (Fi), and streaming with the boundary rule, fused
- * in one pass per step.  Asynchronous. */
+ * in one pass per step, or per two steps where params.step_pairs allows it
+ * (the intermediate state then never leaves the GPU's registers).
+ * Asynchronous. */
 int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps);
 
 /* Number of steps taken since init (the current state is f(., n)). */

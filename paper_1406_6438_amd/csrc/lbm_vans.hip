@@ -939,23 +939,44 @@ __device__ __forceinline__ void store_cached(S *p, R v, R scale)
         *p = static_cast<S>(v);
 }
 
-template <typename S, typename R, bool WY>
+// BX: x ends periodic (0), walls (1) or open (2); WY: walls across y.  res_a:
+// the reservoirs of open x ends are active in the first of the two steps (the
+// pass starts from a state n >= 1); they are in the second.  With x ends, the
+// lanes beside the domain compute on clamped columns and are never read.
+template <typename S, typename R, int BX, bool WY>
 __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
-                                                        Phys<R> ph, int nstrips, int nchunks)
+                                                        Phys<R> ph, int nstrips, int nchunks,
+                                                        int res_a)
 {
     static_assert(std::is_same_v<R, float>, "two-step pass computes in FP32");
+    constexpr bool WX = BX != 0;
     const int lane = threadIdx.x % TX;
     const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
     const int strip = wid % nstrips, chunk = wid / nstrips;
     if (chunk >= nchunks) return;              // whole waves only; no barrier below
     const int xu = strip * TB_COLS + lane - 1;  // unwrapped column
-    int xi = xu % g.Lx;
-    if (xi < 0) xi += g.Lx;
+    int xi;
+    if constexpr (WX) {
+        xi = min(max(xu, 0), g.Lx - 1);
+    } else {
+        xi = xu % g.Lx;
+        if (xi < 0) xi += g.Lx;
+    }
+    // x neighbours: wrapped, or the node itself behind an x wall / open end (the
+    // gather then takes its own opposite population, the porosity its mirror)
+    const bool wxm = WX && xu == 0, wxp = WX && xu == g.Lx - 1;
     const unsigned x = static_cast<unsigned>(xi);
-    const unsigned xm = xi == 0 ? g.Lx - 1 : xi - 1, xp = xi == g.Lx - 1 ? 0 : xi + 1;
-    const bool out_ok = lane >= 1 && lane <= TB_COLS && xu < g.Lx;
+    unsigned xm, xp;
+    if constexpr (WX) {
+        xm = xi == 0 ? 0 : xi - 1;
+        xp = xi == g.Lx - 1 ? g.Lx - 1 : xi + 1;
+    } else {
+        xm = xi == 0 ? g.Lx - 1 : xi - 1;
+        xp = xi == g.Lx - 1 ? 0 : xi + 1;
+    }
+    const bool out_ok = lane >= 1 && lane <= TB_COLS && xu >= 0 && xu < g.Lx;
     const int y0 = chunk * tb_rows<S>(), y1 = min(y0 + tb_rows<S>(), g.Ly);
     const unsigned pitch = g.pitch;
     const S *F[9];
@@ -990,19 +1011,24 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
         if (yp >= g.Ly) { if (WY) { q.wyp = true; yp = yy; } else yp = 0; }
         const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
         q.d[0] = load_cached<S, R>(F[0] + (r0 + x), ph.inv_scale);
-        q.d[1] = load_cached<S, R>(F[1] + (r0 + xm), ph.inv_scale);
+        q.d[1] = load_cached<S, R>(wxm ? F[3] + (r0 + x) : F[1] + (r0 + xm), ph.inv_scale);
         q.d[2] = load_cached<S, R>(q.wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
-        q.d[3] = load_cached<S, R>(F[3] + (r0 + xp), ph.inv_scale);
+        q.d[3] = load_cached<S, R>(wxp ? F[1] + (r0 + x) : F[3] + (r0 + xp), ph.inv_scale);
         q.d[4] = load_cached<S, R>(q.wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
-        q.d[5] = load_cached<S, R>(q.wym ? F[7] + (r0 + x) : F[5] + (rm + xm), ph.inv_scale);
-        q.d[6] = load_cached<S, R>(q.wym ? F[8] + (r0 + x) : F[6] + (rm + xp), ph.inv_scale);
-        q.d[7] = load_cached<S, R>(q.wyp ? F[5] + (r0 + x) : F[7] + (rp + xp), ph.inv_scale);
-        q.d[8] = load_cached<S, R>(q.wyp ? F[6] + (r0 + x) : F[8] + (rp + xm), ph.inv_scale);
+        q.d[5] = load_cached<S, R>((wxm || q.wym) ? F[7] + (r0 + x) : F[5] + (rm + xm),
+                                   ph.inv_scale);
+        q.d[6] = load_cached<S, R>((wxp || q.wym) ? F[8] + (r0 + x) : F[6] + (rm + xp),
+                                   ph.inv_scale);
+        q.d[7] = load_cached<S, R>((wxp || q.wyp) ? F[5] + (r0 + x) : F[7] + (rp + xp),
+                                   ph.inv_scale);
+        q.d[8] = load_cached<S, R>((wxm || q.wyp) ? F[6] + (r0 + x) : F[8] + (rp + xm),
+                                   ph.inv_scale);
     };
+    const bool oa = BX == 2 && res_a;        // reservoirs in the first step
     auto finish_a = [&](R (&out)[9], Pending &q, const R (&w0)[3], const R (&w1)[3],
                         const R (&w2)[3]) {
         const R t[3][3] = {{w0[0], w0[1], w0[2]}, {w1[0], w1[1], w1[2]}, {w2[0], w2[1], w2[2]}};
-        update_node<R, 3, false>(q.d, t, 1, 1, false, false, q.wym, q.wyp, false, false, ph,
+        update_node<R, 3, false>(q.d, t, 1, 1, wxm, wxp, q.wym, q.wyp, oa && wxm, oa && wxp, ph,
                                  nullptr, false);
 #pragma unroll
         for (int i = 0; i < 9; i++) out[i] = q.d[i];
@@ -1046,30 +1072,32 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
         R d[9];
         const R s1 = lane_from_below(P[A1][1]), s3 = lane_from_above(P[A1][3]);
         d[0] = P[A1][0];
-        d[1] = s1;
-        d[3] = s3;
+        d[1] = wxm ? P[A1][3] : s1;
+        d[3] = wxp ? P[A1][1] : s3;
         if (wym) {
             d[2] = P[A1][4];
             d[5] = P[A1][7];
             d[6] = P[A1][8];
         } else {
+            const R s5 = lane_from_below(P[A0][5]), s6 = lane_from_above(P[A0][6]);
             d[2] = P[A0][2];
-            d[5] = lane_from_below(P[A0][5]);
-            d[6] = lane_from_above(P[A0][6]);
+            d[5] = wxm ? P[A1][7] : s5;
+            d[6] = wxp ? P[A1][8] : s6;
         }
         if (wyp) {
             d[4] = P[A1][2];
             d[7] = P[A1][5];
             d[8] = P[A1][6];
         } else {
+            const R s7 = lane_from_above(P[A2][7]), s8 = lane_from_below(P[A2][8]);
             d[4] = P[A2][4];
-            d[7] = lane_from_above(P[A2][7]);
-            d[8] = lane_from_below(P[A2][8]);
+            d[7] = wxp ? P[A1][5] : s7;
+            d[8] = wxm ? P[A1][6] : s8;
         }
         const R t[3][3] = {{e[A0][0], e[A0][1], e[A0][2]}, {e[A1][0], e[A1][1], e[A1][2]},
                            {e[A2][0], e[A2][1], e[A2][2]}};
-        update_node<R, 3, false>(d, t, 1, 1, false, false, wym, wyp, false, false, ph, nullptr,
-                                 false);
+        update_node<R, 3, false>(d, t, 1, 1, wxm, wxp, wym, wyp, BX == 2 && wxm,
+                                 BX == 2 && wxp, ph, nullptr, false);
         if (out_ok) {
             const unsigned c = y * pitch + x;
 #pragma unroll
@@ -1975,11 +2003,10 @@ void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
     else launch_sweep_rg<S, R, DIAG, false, VMAX>(h, src, dst, ph);
 }
 
-// Two time steps in one pass (k_sweep_tb2): FP32 and FP16 storage with a
-// periodic x axis.
+// Two time steps in one pass (k_sweep_tb2): FP32 and FP16 storage.
 bool tb2_eligible(const lbm_vans_handle *h)
 {
-    return h->p.step_pairs == 0 && h->p.storage != LBM_F64 && h->p.bc_x == LBM_BC_PERIODIC;
+    return h->p.step_pairs == 0 && h->p.storage != LBM_F64;
 }
 
 int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
@@ -1997,15 +2024,20 @@ int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
                 return fail(LBM_VANS_EINVAL, "lattice too large");
             const int grid = static_cast<int>((waves + NW - 1) / NW);
             Phys<R> ph = make_phys<R>(&h->p);
-            ph.reservoir = 0;
-            if (h->g.wall_y)
-                hipLaunchKernelGGL((k_sweep_tb2<S, R, true>), dim3(grid), dim3(NTHREADS), 0,
-                                   h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g,
-                                   ph, nstrips, nchunks);
-            else
-                hipLaunchKernelGGL((k_sweep_tb2<S, R, false>), dim3(grid), dim3(NTHREADS), 0,
-                                   h->stream, (const S *)src, (S *)dst, (const R *)h->eps, h->g,
-                                   ph, nstrips, nchunks);
+            ph.reservoir = 1;                     // the second step starts from n + 1 >= 1
+            const int res_a = h->n >= 1;
+            const int bx = h->g.open_x ? 2 : (h->g.wall_x ? 1 : 0);
+#define LBM_VANS_TB2(BXV, WYV)                                                                  \
+    hipLaunchKernelGGL((k_sweep_tb2<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, h->stream, \
+                       (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph, nstrips, nchunks,  \
+                       res_a)
+            if (bx == 0 && !h->g.wall_y) LBM_VANS_TB2(0, false);
+            else if (bx == 0) LBM_VANS_TB2(0, true);
+            else if (bx == 1 && !h->g.wall_y) LBM_VANS_TB2(1, false);
+            else if (bx == 1) LBM_VANS_TB2(1, true);
+            else if (!h->g.wall_y) LBM_VANS_TB2(2, false);
+            else LBM_VANS_TB2(2, true);
+#undef LBM_VANS_TB2
             return check_launch("k_sweep_tb2");
         }
     });

@@ -36,7 +36,9 @@ PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E peak
 PROFILE_TRAFFIC = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_traffic_box4096_f32.md"),
                    "box8192_f16": os.path.join(ROOT, "profiles", "sweep_traffic_box8192_f16.md"),
                    "ensemble64_f32": os.path.join(ROOT, "profiles",
-                                                  "sweep_traffic_ensemble64_f32.md")}
+                                                  "sweep_traffic_ensemble64_f32.md"),
+                   "ensemble64_f32_pairs": os.path.join(ROOT, "profiles",
+                                                        "tb2_traffic_ensemble64_f32.md")}
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
 
 
@@ -190,8 +192,8 @@ def crop_sample(w, lbm, steps: int):
 
 def steps_per_launch(w) -> int:
     """Steps one sweep launch advances: the library runs pairs of steps in one pass
-    (k_sweep_tb2) for FP32 / FP16 storage with a periodic x axis (all box workloads),
-    one step per launch (k_sweep_vec) otherwise."""
+    (k_sweep_tb2) for FP32 / FP16 storage, one step per launch (k_sweep_vec) for
+    FP64."""
     return 2 if w.storage != "f64" else 1
 
 
@@ -309,9 +311,10 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
 
 def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: bool):
     """The 64-member ensemble of uneven open channels (FP32): launch shape picked by the
-    library's autotuner, then `steps` batched steps (one launch per step, replayed as
-    16-step graphs) timed with HIP events; the same steps as plain launches; the
-    gradient of every member's outlet flux after 2000 steps (checkpoints every 45).
+    library's autotuner (single-step launches of each width and grid, or the two-step
+    pass), then `steps` batched steps (replayed as 16-step graphs) timed with HIP
+    events; the same steps as plain launches; the gradient of every member's outlet
+    flux after 2000 steps (checkpoints every 45).
     Returns (leg dict, accuracy sample of the smallest member or None)."""
     import numpy as np
     from paper_1406_6438_amd import workloads as W
@@ -342,10 +345,12 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
         return e0.elapsed_time(e1) / 1e3
 
     t_graph = timed(steps)
-    b.configure(best["vec"], best["grid"], 0)
+    b.configure(best["vec"], best["grid"], 0, best["step_pairs"])
     t_plain = timed(steps)
-    b.configure(best["vec"], best["grid"], best["graph_steps"])
+    b.configure(best["vec"], best["grid"], best["graph_steps"], best["step_pairs"])
+    pairs = best["step_pairs"] == 0
     bpn = algorithmic_bytes_per_node("f32")
+    # algorithmic bytes per node-step over the time per step (= per launch / steps per launch)
     ach = bpn * cells / (t_graph / steps) / 1e9
     out = {"workload": f"ensemble_{len(members)}_open_channels_f32", "members": len(members),
            "nodes": cells, "Lx_range": [min(m.Lx for m in members), max(m.Lx for m in members)],
@@ -355,9 +360,13 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
            "tuned": best, "trials": trials,
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS,
                         "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4),
-                        "traffic": (measured_traffic("ensemble64_f32")
-                                    if best["vec"] == 4 and len(members) == 64 else None),
-                        "kernel": "k_batch_sweep", "bytes_per_node": bpn}}
+                        "traffic": (measured_traffic("ensemble64_f32_pairs" if pairs
+                                                     else "ensemble64_f32")
+                                    if (pairs or best["vec"] == 4) and len(members) == 64
+                                    else None),
+                        "kernel": "k_batch_tb2" if pairs else "k_batch_sweep",
+                        "steps_per_launch": 2 if pairs else 1,
+                        "bytes_per_node_step": bpn}}
     log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
         f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")
     if grad:

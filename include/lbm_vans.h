@@ -243,7 +243,9 @@ typedef struct lbm_vans_batch_config {
     int32_t graph_steps;  /* steps per replay of the captured step graph (even); 0: plain
                              launches.  lbm_vans_batch_step replays the graph for whole
                              chunks from state n >= 1 and launches the rest one by one */
-    int32_t pad_;
+    int32_t step_pairs;   /* 0: with LBM_F32 / LBM_F16_SHIFTED storage, advance two steps
+                             per launch (the two-step pass over every member; vec and
+                             grid then apply to single steps only); 1: never         */
     double us_per_step;   /* lbm_vans_batch_tune: measured microseconds per step       */
 } lbm_vans_batch_config;
 
@@ -255,7 +257,8 @@ size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembe
  * kept alive until lbm_vans_batch_destroy().  stream: hipStream_t of the
  * batched work (NULL = null stream); graphs are captured on a private stream
  * and replayed on it.  Default configuration: widest vec, one workgroup per
- * tile, 16-step graphs.  Synchronises the stream (table upload). */
+ * tile, 16-step graphs, two steps per launch where the storage allows it.
+ * Synchronises the stream (table upload). */
 int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
                           size_t work_bytes, void *stream, lbm_vans_batch **out);
 
@@ -267,15 +270,19 @@ int lbm_vans_batch_get_config(const lbm_vans_batch *b, lbm_vans_batch_config *cf
 /* Autotune the launch shape on the current members: every vec (widest
  * first) with one workgroup per tile and with persistent grids of 1, 2, 4 and
  * 8 workgroups per compute unit, each timed with HIP events over reps sweeps
- * of the current state (read only: the state does not change).  The fastest
- * becomes the configuration (graph_steps kept) and is written to *best (may be
- * NULL); trials (may be NULL if max_trials is 0) receive up to max_trials of
- * the timed shapes and *n_trials (may be NULL) their number.  Synchronises. */
+ * of the current state (read only: the state does not change), and, with
+ * LBM_F32 / LBM_F16_SHIFTED storage, the two-step pass (its time per launch
+ * halved; step_pairs 0 in that trial, 1 in the others).  The fastest becomes
+ * the configuration (graph_steps kept; the best single-step vec and grid kept
+ * when the two-step pass wins) and is written to *best (may be NULL); trials
+ * (may be NULL if max_trials is 0) receive up to max_trials of the timed
+ * shapes and *n_trials (may be NULL) their number.  Synchronises. */
 int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *best,
                         lbm_vans_batch_config *trials, int32_t max_trials, int32_t *n_trials);
 
-/* Advance every member nsteps (>= 0) time steps (as lbm_vans_step).
- * Asynchronous. */
+/* Advance every member nsteps (>= 0) time steps (as lbm_vans_step; with
+ * step_pairs 0 and LBM_F32 / LBM_F16_SHIFTED storage two steps per launch, an
+ * odd last step alone).  Asynchronous. */
 int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps);
 
 /* Bytes of grad_work for lbm_vans_batch_grad: the members' lbm_vans_grad

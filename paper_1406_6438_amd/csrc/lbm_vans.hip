@@ -943,19 +943,15 @@ __device__ __forceinline__ void store_cached(S *p, R v, R scale)
 // the reservoirs of open x ends are active in the first of the two steps (the
 // pass starts from a state n >= 1); they are in the second.  With x ends, the
 // lanes beside the domain compute on clamped columns and are never read.
+// The work of one wave: strip `strip`, chunk `chunk` of the lattice g.
 template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
-                                                        S *__restrict__ fout,
-                                                        const R *__restrict__ eps, Geo g,
-                                                        Phys<R> ph, int nstrips, int nchunks,
-                                                        int res_a)
+__device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restrict__ fout,
+                                         const R *__restrict__ eps, const Geo &g,
+                                         const Phys<R> &ph, int strip, int chunk, int res_a)
 {
     static_assert(std::is_same_v<R, float>, "two-step pass computes in FP32");
     constexpr bool WX = BX != 0;
     const int lane = threadIdx.x % TX;
-    const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
-    const int strip = wid % nstrips, chunk = wid / nstrips;
-    if (chunk >= nchunks) return;              // whole waves only; no barrier below
     const int xu = strip * TB_COLS + lane - 1;  // unwrapped column
     int xi;
     if constexpr (WX) {
@@ -1118,6 +1114,19 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
         if (y + 1 < y1) row(I1{}, I2{}, I0{}, y + 1);
         if (y + 2 < y1) row(I2{}, I0{}, I1{}, y + 2);
     }
+}
+
+template <typename S, typename R, int BX, bool WY>
+__global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
+                                                        S *__restrict__ fout,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        Phys<R> ph, int nstrips, int nchunks,
+                                                        int res_a)
+{
+    const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
+    const int strip = wid % nstrips, chunk = wid / nstrips;
+    if (chunk >= nchunks) return;              // whole waves only; no barrier below
+    tb2_wave<S, R, BX, WY>(fin, fout, eps, g, ph, strip, chunk, res_a);
 }
 
 // Macroscopic fields of the current state (no collision, no store of
@@ -1685,6 +1694,8 @@ struct Member {
     int vec;                // nodes per lane of this member's sweep
     int tile0;              // first position in the sweep tile list of its width
     int tile0_adj;          // first position in the adjoint tile list
+    int tb_strips;          // strips of the two-step pass
+    int tw0;                // first position in the two-step pass's wave list
 };
 
 template <typename R>
@@ -1751,6 +1762,25 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_sweep(const Member<R> *__res
             reinterpret_cast<S *>(state_slot(d, dst)), d.eps, gs, ph, nullptr, T - d.tile0);
         __syncthreads();  // a next tile of this block reuses the LDS porosity tile
     }
+}
+
+// Two steps of every member in one pass (the two-step pass, one wave per
+// strip and chunk of a member), from state slot src to state slot dst.
+template <typename S, typename R, int BX, bool WY>
+__global__ __launch_bounds__(NTHREADS) void k_batch_tb2(const Member<R> *__restrict__ M,
+                                                        const int *__restrict__ wmap,
+                                                        int nwaves, int src, int dst, int res_a)
+{
+    const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
+    if (wid >= nwaves) return;                 // whole waves only; no barrier below
+    const Member<R> &d = M[wmap[wid]];
+    const Geo g = d.g;
+    Phys<R> ph = d.ph;
+    ph.reservoir = 1;
+    const int local = wid - d.tw0;
+    tb2_wave<S, R, BX, WY>(reinterpret_cast<const S *>(state_slot(d, src)),
+                           reinterpret_cast<S *>(state_slot(d, dst)), d.eps, g, ph,
+                           local % d.tb_strips, local / d.tb_strips, res_a);
 }
 
 // One reverse step of every member: adjoint slot a_next (of the state n + 1)
@@ -2441,18 +2471,32 @@ struct lbm_vans_batch {
     size_t desc_bytes = 0;          // bytes of one device descriptor
     std::vector<char> desc;         // host image of the descriptors
     std::vector<int> tmap, tmap_adj;  // tile lists of the sweep and of the adjoint
+    std::vector<int> wmap;            // wave list of the two-step pass
     void *d_desc = nullptr;
-    int *d_tmap = nullptr, *d_tmap_adj = nullptr;
-    int ntiles = 0, ntiles_adj = 0;
+    int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap = nullptr;
+    int ntiles = 0, ntiles_adj = 0, nwaves = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // chunk of cfg.graph_steps steps from slot 0 / 1
 };
 
 namespace {
 
-size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj)
+size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, size_t nwaves)
 {
     const size_t d = storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
-    return align256(nmembers * d) + 2 * align256(ntiles_adj * sizeof(int));
+    return align256(nmembers * d) + 2 * align256(ntiles_adj * sizeof(int)) +
+           align256(nwaves * sizeof(int));
+}
+
+// Rows per chunk of the two-step pass for a storage code (see tb_rows).
+int tb_rows_of(int storage) { return storage == LBM_F16_SHIFTED ? 16 : 8; }
+
+// Waves of the two-step pass over one member (0 in FP64, which has no such pass).
+size_t tb2_waves(const lbm_vans_params *p)
+{
+    if (p->storage == LBM_F64) return 0;
+    const int rows = tb_rows_of(p->storage);
+    return static_cast<size_t>((p->Lx + TB_COLS - 1) / TB_COLS) *
+           static_cast<size_t>((p->Ly + rows - 1) / rows);
 }
 
 void drop_graphs(lbm_vans_batch *b)
@@ -2471,6 +2515,7 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
     const size_t nm = b->m.size();
     b->tmap.clear();
     b->tmap_adj.clear();
+    b->wmap.clear();
     int rc = with_types(b->storage, [&](auto *sp, auto *rp) -> int {
         using R = std::remove_pointer_t<decltype(rp)>;
         (void)sp;
@@ -2493,6 +2538,9 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             d.tile0_adj = static_cast<int>(b->tmap_adj.size());
             b->tmap.insert(b->tmap.end(), d.gs.ntiles, static_cast<int>(k));
             b->tmap_adj.insert(b->tmap_adj.end(), d.g.ntiles, static_cast<int>(k));
+            d.tb_strips = (h->p.Lx + TB_COLS - 1) / TB_COLS;
+            d.tw0 = static_cast<int>(b->wmap.size());
+            b->wmap.insert(b->wmap.end(), tb2_waves(&h->p), static_cast<int>(k));
         }
         size_t off = 0;
         for (size_t k = 0; k < nm; k++) {
@@ -2514,12 +2562,16 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
     if (rc) return rc;
     b->ntiles = static_cast<int>(b->tmap.size());
     b->ntiles_adj = static_cast<int>(b->tmap_adj.size());
+    b->nwaves = static_cast<int>(b->wmap.size());
     HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size(), hipMemcpyHostToDevice,
                            b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap, b->tmap.data(), b->tmap.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap_adj, b->tmap_adj.data(), b->tmap_adj.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
+    if (!b->wmap.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_wmap, b->wmap.data(), b->wmap.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
     // the host images must outlive the copies; they also must not change under them
     HIP_TRY(hipStreamSynchronize(b->stream));
     return LBM_VANS_OK;
@@ -2560,6 +2612,41 @@ int batch_sweep(lbm_vans_batch *b, hipStream_t st, int src, int dst, int reservo
     });
 }
 
+// Two batched steps on stream st: every member from state slot src to dst in
+// one launch of the two-step pass; res_a: the first step starts from n >= 1.
+int batch_pair(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a)
+{
+    return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        if constexpr (std::is_same_v<S, double>) {
+            return fail(LBM_VANS_EINVAL, "two-step pass needs FP32 or FP16 storage");
+        } else {
+            const int n = b->nwaves;
+            const int grid = (n + NW - 1) / NW;
+            const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
+            const int *wm = b->d_wmap;
+#define LBM_VANS_BATCH(BXV, WYV)                                                              \
+    hipLaunchKernelGGL((k_batch_tb2<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, st, M, wm, \
+                       n, src, dst, res_a)
+            if (b->bx == 0 && !b->wy) LBM_VANS_BATCH(0, false);
+            else if (b->bx == 0) LBM_VANS_BATCH(0, true);
+            else if (b->bx == 1 && !b->wy) LBM_VANS_BATCH(1, false);
+            else if (b->bx == 1) LBM_VANS_BATCH(1, true);
+            else if (!b->wy) LBM_VANS_BATCH(2, false);
+            else LBM_VANS_BATCH(2, true);
+#undef LBM_VANS_BATCH
+            return check_launch("k_batch_tb2");
+        }
+    });
+}
+
+// Whether batched steps go two per launch.
+bool batch_pairs(const lbm_vans_batch *b)
+{
+    return b->cfg.step_pairs == 0 && b->storage != LBM_F64 && b->nwaves > 0;
+}
+
 int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir)
 {
     return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
@@ -2585,9 +2672,12 @@ int batch_capture(lbm_vans_batch *b, int s0)
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     int rc = LBM_VANS_OK;
-    for (int j = 0; j < b->cfg.graph_steps && !rc; j++) {
+    const bool pairs = batch_pairs(b);
+    const int nl = pairs ? b->cfg.graph_steps / 2 : b->cfg.graph_steps;
+    for (int j = 0; j < nl && !rc; j++) {
         const int src = (s0 + j) & 1;
-        rc = batch_sweep(b, b->cap, src, 1 - src, 1);
+        rc = pairs ? batch_pair(b, b->cap, src, 1 - src, 1)
+                   : batch_sweep(b, b->cap, src, 1 - src, 1);
     }
     hipError_t e = hipStreamEndCapture(b->cap, &graph);
     if (rc) {
@@ -2615,6 +2705,9 @@ int check_config(const lbm_vans_batch *b, const lbm_vans_batch_config *c)
     if (c->graph_steps < 0 || c->graph_steps % 2)
         return fail(LBM_VANS_EINVAL, "graph_steps = %d: 0 or a positive even number",
                     c->graph_steps);
+    if (c->step_pairs != 0 && c->step_pairs != 1)
+        return fail(LBM_VANS_EINVAL, "step_pairs = %d: 0 (automatic) or 1 (never)",
+                    c->step_pairs);
     return LBM_VANS_OK;
 }
 
@@ -2630,12 +2723,19 @@ int batch_in_step(const lbm_vans_batch *b)
     return LBM_VANS_OK;
 }
 
-void batch_advance(lbm_vans_batch *b, int64_t steps)
+// Account for steps taken in launches that each swap the two state slots once.
+void batch_advance(lbm_vans_batch *b, int64_t steps, int64_t launches)
 {
     for (lbm_vans_handle *h : b->m) {
         h->n += steps;
-        if (steps & 1) h->cur = 1 - h->cur;
+        if (launches & 1) h->cur = 1 - h->cur;
     }
+}
+
+// Launches in one replay of the step graph.
+int graph_launches(const lbm_vans_batch *b)
+{
+    return batch_pairs(b) ? b->cfg.graph_steps / 2 : b->cfg.graph_steps;
 }
 
 }  // namespace
@@ -2645,12 +2745,13 @@ extern "C" {
 size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembers)
 {
     if (!members || nmembers < 1) return 0;
-    size_t tiles = 0;
+    size_t tiles = 0, waves = 0;
     for (int32_t k = 0; k < nmembers; k++) {
         if (!members[k]) return 0;
         tiles += static_cast<size_t>(members[k]->g.ntiles);
+        waves += tb2_waves(&members[k]->p);
     }
-    return batch_table_bytes(members[0]->p.storage, nmembers, tiles);
+    return batch_table_bytes(members[0]->p.storage, nmembers, tiles, waves);
 }
 
 int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
@@ -2662,7 +2763,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     if (!members || nmembers < 1) return fail(LBM_VANS_EINVAL, "no members");
     const lbm_vans_handle *h0 = members[0];
     if (!h0) return fail(LBM_VANS_EINVAL, "member 0 is NULL");
-    size_t tiles = 0;
+    size_t tiles = 0, waves = 0;
     for (int32_t k = 0; k < nmembers; k++) {
         const lbm_vans_handle *h = members[k];
         if (!h) return fail(LBM_VANS_EINVAL, "member %d is NULL", k);
@@ -2678,12 +2779,15 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
             return fail(LBM_VANS_EINVAL, "member %d is at step %lld, member 0 at %lld", k,
                         (long long)h->n, (long long)h0->n);
         tiles += static_cast<size_t>(h->g.ntiles);
+        waves += tb2_waves(&h->p);
     }
     if (tiles > static_cast<size_t>(INT32_MAX))
         return fail(LBM_VANS_EINVAL, "%zu tiles: too many for one launch", tiles);
+    if (waves > static_cast<size_t>(INT32_MAX - NW))
+        return fail(LBM_VANS_EINVAL, "%zu waves: too many for one launch", waves);
     if (!work || reinterpret_cast<uintptr_t>(work) % 256)
         return fail(LBM_VANS_EINVAL, "work must be a 256-byte aligned device buffer");
-    const size_t need = batch_table_bytes(h0->p.storage, nmembers, tiles);
+    const size_t need = batch_table_bytes(h0->p.storage, nmembers, tiles, waves);
     if (work_bytes < need)
         return fail(LBM_VANS_EINVAL, "work has %zu bytes, %zu needed", work_bytes, need);
 
@@ -2701,9 +2805,12 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     b->d_tmap = reinterpret_cast<int *>(w + align256(nmembers * dsz));
     b->d_tmap_adj = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
                                             align256(tiles * sizeof(int)));
+    b->d_wmap = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
+                                        2 * align256(tiles * sizeof(int)));
     b->cfg.vec = b->vmax;
     b->cfg.grid = 0;
     b->cfg.graph_steps = 16;
+    b->cfg.step_pairs = 0;
     int rc = LBM_VANS_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&b->ev[0]);
@@ -2764,6 +2871,7 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
             if (gi > 0 && (grid < NXCD || grid >= b->ntiles)) continue;
             b->cfg.vec = vec;
             b->cfg.grid = grid;
+            b->cfg.step_pairs = 1;
             // the state in slot src is only read, so the trials leave it unchanged
             rc = batch_sweep(b, b->stream, src, dst, res);
             if (rc) return rc;
@@ -2779,6 +2887,24 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
             nt++;
             if (b->cfg.us_per_step < top.us_per_step) top = b->cfg;
         }
+    }
+    if (b->storage != LBM_F64 && b->nwaves > 0) {
+        // the two-step pass (independent of vec and grid), timed per step
+        rc = batch_pair(b, b->stream, src, dst, res);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+        for (int r = 0; r < reps && !rc; r++) rc = batch_pair(b, b->stream, src, dst, res);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b->ev[1], b->stream));
+        HIP_TRY(hipEventSynchronize(b->ev[1]));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+        lbm_vans_batch_config pc = top;
+        pc.step_pairs = 0;
+        pc.us_per_step = 1000.0 * ms / (2.0 * reps);
+        if (nt < max_trials) trials[nt] = pc;
+        nt++;
+        if (pc.us_per_step < top.us_per_step) top = pc;
     }
     if (n_trials) *n_trials = nt;
     top.graph_steps = keep.graph_steps;
@@ -2804,12 +2930,17 @@ int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps)
                 if (rc) return rc;
             }
             HIP_TRY(hipGraphLaunch(b->graph[cur], b->stream));
-            batch_advance(b, C);
+            batch_advance(b, C, graph_launches(b));
             k += C;
+        } else if (batch_pairs(b) && nsteps - k >= 2) {
+            rc = batch_pair(b, b->stream, cur, 1 - cur, n >= 1);
+            if (rc) return rc;
+            batch_advance(b, 2, 1);
+            k += 2;
         } else {
             rc = batch_sweep(b, b->stream, cur, 1 - cur, n >= 1);
             if (rc) return rc;
-            batch_advance(b, 1);
+            batch_advance(b, 1, 1);
             k += 1;
         }
     }
@@ -2890,7 +3021,7 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
                 const int cur = b->m[0]->cur;
                 r = batch_sweep(b, b->stream, cur, 1 - cur, b->m[0]->n >= 1);
                 if (r) return r;
-                batch_advance(b, 1);
+                batch_advance(b, 1, 1);
             }
             if (nsteps == 0) break;
         }

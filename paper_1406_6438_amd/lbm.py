@@ -60,12 +60,12 @@ class LbmVansParams(ctypes.Structure):
 
 class LbmVansBatchConfig(ctypes.Structure):
     _fields_ = [("vec", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32), ("step_pairs", ctypes.c_int32),
                 ("us_per_step", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {"vec": self.vec, "grid": self.grid, "graph_steps": self.graph_steps,
-                "us_per_step": self.us_per_step}
+                "step_pairs": self.step_pairs, "us_per_step": self.us_per_step}
 
 
 @dataclasses.dataclass
@@ -270,8 +270,8 @@ def lbm_vans_batch_create(members, work, stream) -> ctypes.c_void_p:
     return b
 
 
-def lbm_vans_batch_configure(b, vec: int, grid: int, graph_steps: int):
-    c = LbmVansBatchConfig(vec, grid, graph_steps, 0, 0.0)
+def lbm_vans_batch_configure(b, vec: int, grid: int, graph_steps: int, step_pairs: int = 0):
+    c = LbmVansBatchConfig(vec, grid, graph_steps, step_pairs, 0.0)
     _check(load().lbm_vans_batch_configure(b, ctypes.byref(c)))
 
 
@@ -422,8 +422,9 @@ class Batch:
             self.stream = torch.cuda.current_stream(self.device)
             self.b = lbm_vans_batch_create(self.members, self.work, self.stream.cuda_stream)
 
-    def configure(self, vec: int, grid: int = 0, graph_steps: int = 16):
-        lbm_vans_batch_configure(self.b, vec, grid, graph_steps)
+    def configure(self, vec: int, grid: int = 0, graph_steps: int = 16, step_pairs: int = 0):
+        """step_pairs 0: two steps per launch (FP32 / FP16 storage); 1: one."""
+        lbm_vans_batch_configure(self.b, vec, grid, graph_steps, step_pairs)
 
     @property
     def config(self) -> dict:

@@ -9,6 +9,9 @@ Tolerances are those of the single-problem parity tests:
 * FP16: 2 roundings per step at 2^-11 of the largest stored magnitude;
 * gradients: FP64 <= 1e-10 of the largest |dJ/deps|, FP32 rel. L2 <= 1e-4,
   both against the oracle's FP64 reverse pass.
+With FP32 / FP16 storage the batch advances two steps per launch by default
+(the two-step pass), like a problem run alone; the single-step kernels are
+covered with step_pairs = 1.
 A member of a batch takes the same node update as a problem run alone, so the
 batched results are also compared with lone runs, within the precision bound
 above (the batched kernel is a different compilation of the same source and
@@ -114,57 +117,66 @@ def _vmax(storage):
     return 2 if storage == "f64" else 4
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
 def test_every_launch_shape(storage):
     """vec 4/2/1, one workgroup per tile or persistent grids, with and without
-    graphs: the same bits for one vec, within the precision bound across vec."""
+    graphs, one or two steps per launch (FP64 has single steps only): the same
+    bits for one vec and step_pairs, within the precision bound across them.
+    13 steps: with pairs, six two-step launches and a last single step."""
     from paper_1406_6438_amd import lbm
     members = _member_specs(storage, "open_walls")
     vmax = _vmax(storage)
-    shapes = [(v, g, c) for v in sorted({vmax, 2, 1}, reverse=True) for g in (0, 8, 64)
-              for c in (0, 4)]
+    pairs = (1,) if storage == "f64" else (0, 1)
+    shapes = [(v, g, c, sp) for v in sorted({vmax, 2, 1}, reverse=True) for g in (0, 8, 64)
+              for c in (0, 4, 6) for sp in pairs]
     nsteps = 13
-    ref, ref_v = {}, None
+    ref = {}
     orc = [oracle_run(spec, eps, nsteps)[1] for spec, eps in members]
-    for v, g, c in shapes:
-        say(f"[batch shape {storage}] vec={v} grid={g} graph_steps={c}")
+    for v, g, c, sp in shapes:
+        say(f"[batch shape {storage}] vec={v} grid={g} graph_steps={c} step_pairs={sp}")
         sv = _solvers(members)
         b = lbm.Batch(sv)
-        b.configure(v, g, c)
-        assert b.config["vec"] == v and b.config["grid"] == g and b.config["graph_steps"] == c
+        b.configure(v, g, c, sp)
+        cfg = b.config
+        assert (cfg["vec"], cfg["grid"], cfg["graph_steps"], cfg["step_pairs"]) == (v, g, c, sp)
         b.step(nsteps)
         f = _states(sv)
         b.close()
+        assert all(s.n == nsteps for s in sv)
         _close(sv)
         for (spec, eps), a, fo in zip(members, f, orc):
             assert np.abs(a - fo).max() <= _bound(spec, eps, fo, nsteps)
-        if v not in ref:
-            ref[v] = f
+        if (v, sp) not in ref:
+            ref[(v, sp)] = f
             continue
-        for a, r in zip(f, ref[v]):
+        for a, r in zip(f, ref[(v, sp)]):
             assert np.array_equal(a, r)
 
 
-def test_graph_replays_match_plain_launches():
+@pytest.mark.parametrize("step_pairs", [0, 1])
+@pytest.mark.parametrize("chunk", [4, 6])
+def test_graph_replays_match_plain_launches(chunk, step_pairs):
     """A graph replayed several times, with eager work and synchronisations in
-    between, against plain launches of the same steps: every replay identical."""
+    between, against plain launches of the same steps: every replay identical.
+    A 6-step graph of pairs is three launches, so a replay ends in the other
+    state slot than it started from."""
     from paper_1406_6438_amd import lbm
     members = _member_specs("f32", "open_walls")
     sa, sb = _solvers(members), _solvers(members)
     ba, bb = lbm.Batch(sa), lbm.Batch(sb)
-    ba.configure(4, 0, 4)
-    bb.configure(4, 0, 0)
+    ba.configure(4, 0, chunk, step_pairs)
+    bb.configure(4, 0, 0, step_pairs)
     ba.step(1)
     bb.step(1)
     for r in range(4):
-        ba.step(4)       # one replay of the 4-step graph
-        bb.step(4)
+        ba.step(chunk)       # one replay of the graph
+        bb.step(chunk)
         torch.cuda.synchronize()
         m = sa[r % len(sa)].moments()   # eager work between replays
         assert m["rc"] == 0
         for x, y in zip(_states(sa), _states(sb)):
             assert np.array_equal(x, y), f"replay {r}"
-    assert all(s.n == 17 for s in sa)
+    assert all(s.n == 1 + 4 * chunk for s in sa)
     _close([ba, bb])
     _close(sa + sb)
 
@@ -179,7 +191,8 @@ def test_autotune_keeps_the_state_and_reports_trials():
     best, trials = b.tune(reps=3)
     say(f"[batch tune] best {best}; {len(trials)} trials")
     assert trials and best["us_per_step"] == min(t["us_per_step"] for t in trials)
-    assert b.config["vec"] == best["vec"] and b.config["grid"] == best["grid"]
+    assert sorted({t["step_pairs"] for t in trials}) == [0, 1]
+    assert all(b.config[k] == best[k] for k in ("vec", "grid", "step_pairs"))
     for x, y in zip(_states(sv), before):
         assert np.array_equal(x, y)
     assert all(s.n == 3 for s in sv)
@@ -208,7 +221,8 @@ def test_batch_rejects_mismatched_members_and_out_of_step_members():
     with pytest.raises(lbm.LbmVansError):
         lbm.Batch([diag, c])
     b = lbm.Batch([a, c])
-    for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16)):
+    for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16), (4, 0, 16, 2),
+                (4, 0, 16, -1)):
         with pytest.raises(lbm.LbmVansError):
             b.configure(*cfg)
     a.step(1)                       # a member stepped on its own

@@ -94,6 +94,23 @@ int fail(int code, const char *fmt, ...)
 #ifndef LBM_VANS_XCD_BANDS
 #define LBM_VANS_XCD_BANDS 1
 #endif
+#ifndef LBM_VANS_TB_AHEAD
+#define LBM_VANS_TB_AHEAD 2
+#endif
+#ifndef LBM_VANS_TB_ROWS32
+#define LBM_VANS_TB_ROWS32 8
+#endif
+#ifndef LBM_VANS_TB_ROWS16
+#define LBM_VANS_TB_ROWS16 16
+#endif
+#ifndef LBM_VANS_TB_WAVES
+#define LBM_VANS_TB_WAVES 0
+#endif
+#if LBM_VANS_TB_WAVES > 0
+#define LBM_VANS_TB_OCC __attribute__((amdgpu_waves_per_eu(LBM_VANS_TB_WAVES)))
+#else
+#define LBM_VANS_TB_OCC
+#endif
 
 constexpr int TX = 64;      // nodes per row segment: one wavefront
 constexpr int NW = LBM_VANS_NW;      // wavefronts per block
@@ -900,7 +917,7 @@ constexpr int TB_COLS = TX - 2;  // output columns per strip
 template <typename S>
 constexpr int tb_rows()
 {
-    return std::is_same_v<S, _Float16> ? 16 : 8;
+    return std::is_same_v<S, _Float16> ? LBM_VANS_TB_ROWS16 : LBM_VANS_TB_ROWS32;
 }
 
 // Value of the lane below (wave_shr: lane l reads lane l-1) and above
@@ -930,20 +947,63 @@ __device__ __forceinline__ R load_cached(const S *p, R inv_scale)
         return static_cast<R>(*p);
 }
 
+// Store through a buffer resource of one plane: a byte offset at or beyond the
+// resource's size (TB_NO_STORE) makes the hardware drop the store, so lanes that
+// must not write need no branch (a branch around the stores would make every
+// later wait for data also wait for the loads issued ahead).
+constexpr unsigned TB_NO_STORE = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(char *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(bytes), 0x00020000);
+}
+
 template <typename S, typename R>
-__device__ __forceinline__ void store_cached(S *p, R v, R scale)
+__device__ __forceinline__ void store_plane(__amdgpu_buffer_rsrc_t r, unsigned off, R v, R scale)
 {
     if constexpr (std::is_same_v<S, _Float16>)
-        *p = static_cast<_Float16>(v * scale);
+        __builtin_amdgcn_raw_buffer_store_b16(
+            __builtin_bit_cast(unsigned short, static_cast<_Float16>(v * scale)), r,
+            static_cast<int>(off), 0, 0);
     else
-        *p = static_cast<S>(v);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, static_cast<float>(v)),
+                                              r, static_cast<int>(off), 0, 0);
 }
 
 // BX: x ends periodic (0), walls (1) or open (2); WY: walls across y.  res_a:
 // the reservoirs of open x ends are active in the first of the two steps (the
 // pass starts from a state n >= 1); they are in the second.  With x ends, the
 // lanes beside the domain compute on clamped columns and are never read.
-// The work of one wave: strip `strip`, chunk `chunk` of the lattice g.
+// The work of one wave: strip `strip`, chunk `chunk` of the lattice g; both
+// are uniform over the wave, so rows, row offsets and the y-wall tests live in
+// scalar registers.  Addresses are a uniform per-plane base plus a 32-bit byte
+// offset within the plane (the host runs this pass only when a plane's bytes
+// fit in 31 bits and a row's in 24); only a value bounced at an x end, whose
+// plane differs from lane to lane, takes a full per-lane address.
+//
+// The rows of the chunk are unrolled at compile time: the first step at row
+// y0 + a (a = -1 .. n) and the second at row y0 + j (j = 0 .. n-1) are
+// straight-line code whose windows are plain values.  The gather loads of the
+// first step run TB_AHEAD rows ahead of their use and, like the porosity loads
+// and the stores, are issued with no branch around them: a row outside the
+// lattice (behind a y wall, past the last chunk's end) loads a row inside it
+// and its result goes unused.
+constexpr int TB_AHEAD = LBM_VANS_TB_AHEAD;
+
+// f(integral_constant<int, J>) for J = 0, 1, ... while it returns true: code
+// unrolled at compile time whatever its size.
+template <typename F, int... J>
+__device__ __forceinline__ void static_while_impl(F &&f, std::integer_sequence<int, J...>)
+{
+    (void)(f(std::integral_constant<int, J>{}) && ...);
+}
+
+template <int N, typename F>
+__device__ __forceinline__ void static_while(F &&f)
+{
+    static_while_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 template <typename S, typename R, int BX, bool WY>
 __device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restrict__ fout,
                                          const R *__restrict__ eps, const Geo &g,
@@ -951,6 +1011,8 @@ __device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restric
 {
     static_assert(std::is_same_v<R, float>, "two-step pass computes in FP32");
     constexpr bool WX = BX != 0;
+    constexpr int NR = tb_rows<S>(), PD = TB_AHEAD;
+    constexpr unsigned SB = sizeof(S), EB = sizeof(R);
     const int lane = threadIdx.x % TX;
     const int xu = strip * TB_COLS + lane - 1;  // unwrapped column
     int xi;
@@ -973,157 +1035,173 @@ __device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restric
         xp = xi == g.Lx - 1 ? 0 : xi + 1;
     }
     const bool out_ok = lane >= 1 && lane <= TB_COLS && xu >= 0 && xu < g.Lx;
-    const int y0 = chunk * tb_rows<S>(), y1 = min(y0 + tb_rows<S>(), g.Ly);
-    const unsigned pitch = g.pitch;
-    const S *F[9];
+    const int y0 = chunk * NR;
+    const int n = min(NR, g.Ly - y0);            // output rows of this chunk
+    const unsigned pb = static_cast<unsigned>(g.pitch) * SB;   // bytes per state row
+    const unsigned pe = static_cast<unsigned>(g.pitch) * EB;   // bytes per porosity row
+    const unsigned xb = x * SB, xmb = xm * SB, xpb = xp * SB;
+    const unsigned xe = x * EB, xme = xm * EB, xpe = xp * EB;
+    const char *Fb[9];
+    __amdgpu_buffer_rsrc_t Gr[9];
+    const unsigned plane_b = static_cast<unsigned>(g.plane) * SB;
 #pragma unroll
-    for (int i = 0; i < 9; i++) F[i] = fin + i * g.plane;
-
-    // porosity window: rows y-1 .. y+1 of the output row y in a three-slot ring,
-    // columns x-1 .. x+1
-    R e[3][3];
-    auto eps_row = [&](R (&r)[3], int row) {
-        const unsigned o = static_cast<unsigned>(halo_index(row, g.Ly, g.wall_y)) * pitch;
-        r[0] = eps[o + xm];
-        r[1] = eps[o + x];
-        r[2] = eps[o + xp];
+    for (int i = 0; i < 9; i++) {
+        Fb[i] = reinterpret_cast<const char *>(fin + i * g.plane);
+        Gr[i] = plane_rsrc(reinterpret_cast<char *>(fout + i * g.plane), plane_b);
+    }
+    const char *Eb = reinterpret_cast<const char *>(eps);
+    auto ld = [&](const char *base, unsigned off) -> R {
+        return load_cached<S, R>(reinterpret_cast<const S *>(base + off), ph.inv_scale);
     };
     auto row_in = [&](int row) { return WY ? (row >= 0 && row < g.Ly) : true; };
     auto wrap_row = [&](int row) {
         return row < 0 ? row + g.Ly : (row >= g.Ly ? row - g.Ly : row);
     };
-    // step n -> n+1 at row yy (inside the domain), in two parts: the loads of the
-    // gather (issued one row ahead, so that they are in flight while the wave
-    // computes the row before), then the node update on them
-    struct Pending {
-        R d[9];
-        bool wym, wyp;
+
+    // porosity rows y0-2+k (k = 0 .. NR+3), columns x-1 .. x+1; the chunk reads
+    // k <= n+3 only
+    R E[NR + 4][3];
+    auto eps_row = [&](int k) {
+        const unsigned o =
+            __umul24(static_cast<unsigned>(halo_index(y0 - 2 + k, g.Ly, g.wall_y)), pe);
+        E[k][0] = *reinterpret_cast<const R *>(Eb + (o + xme));
+        E[k][1] = *reinterpret_cast<const R *>(Eb + (o + xe));
+        E[k][2] = *reinterpret_cast<const R *>(Eb + (o + xpe));
     };
-    auto issue_a = [&](Pending &q, int yy) {
-        q.wym = false;
-        q.wyp = false;
+    // first step at row y0+a: gather into Q[a+1], then the update into P[a+1]
+    R Q[NR + 2][9], P[NR + 2][9];
+    bool qm[NR + 2], qp[NR + 2];
+    auto a_live = [&](int a) { return a <= n && row_in(y0 + a); };
+    auto issue = [&](int a) {
+        // row y0+a; one outside the lattice (never finished) loads a row inside
+        int yy = y0 + a;
+        if (yy < 0) yy = WY ? 0 : yy + g.Ly;
+        if (yy >= g.Ly) yy = (WY || yy - g.Ly >= g.Ly) ? g.Ly - 1 : yy - g.Ly;
+        bool wym = false, wyp = false;
         int ym = yy - 1, yp = yy + 1;
-        if (ym < 0) { if (WY) { q.wym = true; ym = yy; } else ym = g.Ly - 1; }
-        if (yp >= g.Ly) { if (WY) { q.wyp = true; yp = yy; } else yp = 0; }
-        const unsigned r0 = yy * pitch, rm = ym * pitch, rp = yp * pitch;
-        q.d[0] = load_cached<S, R>(F[0] + (r0 + x), ph.inv_scale);
-        q.d[1] = load_cached<S, R>(wxm ? F[3] + (r0 + x) : F[1] + (r0 + xm), ph.inv_scale);
-        q.d[2] = load_cached<S, R>(q.wym ? F[4] + (r0 + x) : F[2] + (rm + x), ph.inv_scale);
-        q.d[3] = load_cached<S, R>(wxp ? F[1] + (r0 + x) : F[3] + (r0 + xp), ph.inv_scale);
-        q.d[4] = load_cached<S, R>(q.wyp ? F[2] + (r0 + x) : F[4] + (rp + x), ph.inv_scale);
-        q.d[5] = load_cached<S, R>((wxm || q.wym) ? F[7] + (r0 + x) : F[5] + (rm + xm),
-                                   ph.inv_scale);
-        q.d[6] = load_cached<S, R>((wxp || q.wym) ? F[8] + (r0 + x) : F[6] + (rm + xp),
-                                   ph.inv_scale);
-        q.d[7] = load_cached<S, R>((wxp || q.wyp) ? F[5] + (r0 + x) : F[7] + (rp + xp),
-                                   ph.inv_scale);
-        q.d[8] = load_cached<S, R>((wxm || q.wyp) ? F[6] + (r0 + x) : F[8] + (rp + xm),
-                                   ph.inv_scale);
+        if (ym < 0) { if (WY) { wym = true; ym = yy; } else ym = g.Ly - 1; }
+        if (yp >= g.Ly) { if (WY) { wyp = true; yp = yy; } else yp = 0; }
+        qm[a + 1] = wym;
+        qp[a + 1] = wyp;
+        const unsigned r0 = __umul24(static_cast<unsigned>(yy), pb);
+        const unsigned rm = __umul24(static_cast<unsigned>(ym), pb);
+        const unsigned rp = __umul24(static_cast<unsigned>(yp), pb);
+        const unsigned c = r0 + xb;
+        R *q = Q[a + 1];
+        // a y wall is uniform over the wave: it picks the plane and the offset
+        q[0] = ld(Fb[0], c);
+        q[2] = ld(wym ? Fb[4] : Fb[2], wym ? c : rm + xb);
+        q[4] = ld(wyp ? Fb[2] : Fb[4], wyp ? c : rp + xb);
+        const char *b5 = wym ? Fb[7] : Fb[5], *b6 = wym ? Fb[8] : Fb[6];
+        const char *b7 = wyp ? Fb[5] : Fb[7], *b8 = wyp ? Fb[6] : Fb[8];
+        const unsigned o5 = wym ? c : rm + xmb, o6 = wym ? c : rm + xpb;
+        const unsigned o7 = wyp ? c : rp + xpb, o8 = wyp ? c : rp + xmb;
+        if constexpr (WX) {
+            // a lane at an x end takes its own opposite populations
+            auto lx = [&](bool own, const char *ob, const char *base, unsigned off) -> R {
+                const S *p = own ? reinterpret_cast<const S *>(ob + c)
+                                 : reinterpret_cast<const S *>(base + off);
+                return load_cached<S, R>(p, ph.inv_scale);
+            };
+            q[1] = lx(wxm, Fb[3], Fb[1], r0 + xmb);
+            q[3] = lx(wxp, Fb[1], Fb[3], r0 + xpb);
+            q[5] = lx(wxm, Fb[7], b5, o5);
+            q[6] = lx(wxp, Fb[8], b6, o6);
+            q[7] = lx(wxp, Fb[5], b7, o7);
+            q[8] = lx(wxm, Fb[6], b8, o8);
+        } else {
+            q[1] = ld(Fb[1], r0 + xmb);
+            q[3] = ld(Fb[3], r0 + xpb);
+            q[5] = ld(b5, o5);
+            q[6] = ld(b6, o6);
+            q[7] = ld(b7, o7);
+            q[8] = ld(b8, o8);
+        }
     };
     const bool oa = BX == 2 && res_a;        // reservoirs in the first step
-    auto finish_a = [&](R (&out)[9], Pending &q, const R (&w0)[3], const R (&w1)[3],
-                        const R (&w2)[3]) {
-        const R t[3][3] = {{w0[0], w0[1], w0[2]}, {w1[0], w1[1], w1[2]}, {w2[0], w2[1], w2[2]}};
-        update_node<R, 3, false>(q.d, t, 1, 1, wxm, wxp, q.wym, q.wyp, oa && wxm, oa && wxp, ph,
-                                 nullptr, false);
+    auto finish = [&](int a) {
+        const int k = a + 1;                  // porosity rows of row y0+a: E[k .. k+2]
+        const R t[3][3] = {{E[k][0], E[k][1], E[k][2]},
+                           {E[k + 1][0], E[k + 1][1], E[k + 1][2]},
+                           {E[k + 2][0], E[k + 2][1], E[k + 2][2]}};
 #pragma unroll
-        for (int i = 0; i < 9; i++) out[i] = q.d[i];
+        for (int i = 0; i < 9; i++) P[a + 1][i] = Q[a + 1][i];
+        update_node<R, 3, false>(P[a + 1], t, 1, 1, wxm, wxp, qm[a + 1], qp[a + 1],
+                                 oa && wxm, oa && wxp, ph, nullptr, false);
     };
-
-    R P[3][9];
-    Pending q;
-    R en[3];
-    // the window starts with step n+1 at rows y0-1 (slot 0) and y0 (slot 1); row -1
-    // lies behind a wall when y has walls, and is then never read
-    {
-        R em[3];
-        eps_row(em, y0 - 2);
-        eps_row(e[0], y0 - 1);
-        eps_row(e[1], y0);
-        eps_row(e[2], y0 + 1);
-#pragma unroll
-        for (int i = 0; i < 9; i++) P[0][i] = P[2][i] = R(0);
-        if (row_in(y0 - 1)) {
-            issue_a(q, wrap_row(y0 - 1));
-            finish_a(P[0], q, em, e[0], e[1]);
-        }
-        issue_a(q, y0);
-        finish_a(P[1], q, e[0], e[1], e[2]);
-        // loads of the first row's A-step (row y0 + 1) and its porosity row
-        eps_row(en, y0 + 2);
-        if (row_in(y0 + 1)) issue_a(q, wrap_row(y0 + 1));
-    }
-    // one output row: the window slots of rows y-1, y, y+1 are A0, A1, A2; q and en
-    // hold the loads for row y+1 (issued one row earlier)
-    auto row = [&](auto a0, auto a1, auto a2, int y) {
-        constexpr int A0 = decltype(a0)::value, A1 = decltype(a1)::value,
-                      A2 = decltype(a2)::value;
+    // second step at row y0+j from P[j] (row y-1), P[j+1] (row y), P[j+2] (row y+1);
+    // a row behind a y wall is never read
+    auto second = [&](int j) {
+        const int y = y0 + j;
         const bool wym = WY && y == 0, wyp = WY && y == g.Ly - 1;
-        if (row_in(y + 1)) finish_a(P[A2], q, e[A1], e[A2], en);
-        // the slot of row y-1 is free once B has read it: keep row y+2's porosity aside
-        R en2[3];
-        eps_row(en2, y + 3);
-        if (y + 1 < y1 && row_in(y + 2)) issue_a(q, wrap_row(y + 2));
-        // step n+1 -> n+2 at row y from the window
+        const R *A0 = P[j], *A1 = P[j + 1], *A2 = P[j + 2];
         R d[9];
-        const R s1 = lane_from_below(P[A1][1]), s3 = lane_from_above(P[A1][3]);
-        d[0] = P[A1][0];
-        d[1] = wxm ? P[A1][3] : s1;
-        d[3] = wxp ? P[A1][1] : s3;
+        const R s1 = lane_from_below(A1[1]), s3 = lane_from_above(A1[3]);
+        d[0] = A1[0];
+        d[1] = wxm ? A1[3] : s1;
+        d[3] = wxp ? A1[1] : s3;
         if (wym) {
-            d[2] = P[A1][4];
-            d[5] = P[A1][7];
-            d[6] = P[A1][8];
+            d[2] = A1[4];
+            d[5] = A1[7];
+            d[6] = A1[8];
         } else {
-            const R s5 = lane_from_below(P[A0][5]), s6 = lane_from_above(P[A0][6]);
-            d[2] = P[A0][2];
-            d[5] = wxm ? P[A1][7] : s5;
-            d[6] = wxp ? P[A1][8] : s6;
+            const R s5 = lane_from_below(A0[5]), s6 = lane_from_above(A0[6]);
+            d[2] = A0[2];
+            d[5] = wxm ? A1[7] : s5;
+            d[6] = wxp ? A1[8] : s6;
         }
         if (wyp) {
-            d[4] = P[A1][2];
-            d[7] = P[A1][5];
-            d[8] = P[A1][6];
+            d[4] = A1[2];
+            d[7] = A1[5];
+            d[8] = A1[6];
         } else {
-            const R s7 = lane_from_above(P[A2][7]), s8 = lane_from_below(P[A2][8]);
-            d[4] = P[A2][4];
-            d[7] = wxp ? P[A1][5] : s7;
-            d[8] = wxm ? P[A1][6] : s8;
+            const R s7 = lane_from_above(A2[7]), s8 = lane_from_below(A2[8]);
+            d[4] = A2[4];
+            d[7] = wxp ? A1[5] : s7;
+            d[8] = wxm ? A1[6] : s8;
         }
-        const R t[3][3] = {{e[A0][0], e[A0][1], e[A0][2]}, {e[A1][0], e[A1][1], e[A1][2]},
-                           {e[A2][0], e[A2][1], e[A2][2]}};
+        const R t[3][3] = {{E[j + 1][0], E[j + 1][1], E[j + 1][2]},
+                           {E[j + 2][0], E[j + 2][1], E[j + 2][2]},
+                           {E[j + 3][0], E[j + 3][1], E[j + 3][2]}};
         update_node<R, 3, false>(d, t, 1, 1, wxm, wxp, wym, wyp, BX == 2 && wxm,
                                  BX == 2 && wxp, ph, nullptr, false);
-        if (out_ok) {
-            const unsigned c = y * pitch + x;
+        const unsigned c = out_ok ? __umul24(static_cast<unsigned>(y), pb) + xb : TB_NO_STORE;
 #pragma unroll
-            for (int i = 0; i < 9; i++) store_cached<S, R>(fout + i * g.plane + c, d[i], ph.scale);
-        }
-        // the slot of row y-1 takes row y+2; en takes row y+3
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            e[A0][j] = en[j];
-            en[j] = en2[j];
-        }
+        for (int i = 0; i < 9; i++) store_plane<S, R>(Gr[i], c, d[i], ph.scale);
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    for (int y = y0; y < y1; y += 3) {
-        row(I0{}, I1{}, I2{}, y);
-        if (y + 1 < y1) row(I1{}, I2{}, I0{}, y + 1);
-        if (y + 2 < y1) row(I2{}, I0{}, I1{}, y + 2);
-    }
+
+    // prologue: porosity rows for the first PD output rows, the gathers of the
+    // first-step rows -1 .. PD, the first-step rows -1 and 0 (row -1 lies behind a
+    // wall when y has walls, and is then never read)
+#pragma unroll
+    for (int k = 0; k < PD + 4; k++) eps_row(k);
+#pragma unroll
+    for (int i = 0; i < 9; i++) P[0][i] = R(0);
+#pragma unroll
+    for (int a = -1; a <= PD; a++) issue(a);
+    if (a_live(-1)) finish(-1);
+    finish(0);
+    static_while<NR>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j >= n) return false;             // uniform: the chunk's last rows
+        if (a_live(j + 1)) finish(j + 1);
+        if constexpr (j + 1 + PD <= NR) issue(j + 1 + PD);
+        if constexpr (j + PD + 4 < NR + 4) eps_row(j + PD + 4);
+        second(j);
+        return true;
+    });
 }
 
 template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
+__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_sweep_tb2(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, int nstrips, int nchunks,
                                                         int res_a)
 {
-    const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
+    // the wave's id is uniform: keep it (and all row logic) in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
+                                                   threadIdx.x / TX);
     const int strip = wid % nstrips, chunk = wid / nstrips;
     if (chunk >= nchunks) return;              // whole waves only; no barrier below
     tb2_wave<S, R, BX, WY>(fin, fout, eps, g, ph, strip, chunk, res_a);
@@ -1767,11 +1845,12 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_sweep(const Member<R> *__res
 // Two steps of every member in one pass (the two-step pass, one wave per
 // strip and chunk of a member), from state slot src to state slot dst.
 template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) void k_batch_tb2(const Member<R> *__restrict__ M,
+__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb2(const Member<R> *__restrict__ M,
                                                         const int *__restrict__ wmap,
                                                         int nwaves, int src, int dst, int res_a)
 {
-    const int wid = xcd_tile(blockIdx.x, gridDim.x) * NW + threadIdx.x / TX;
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
+                                                   threadIdx.x / TX);
     if (wid >= nwaves) return;                 // whole waves only; no barrier below
     const Member<R> &d = M[wmap[wid]];
     const Geo g = d.g;
@@ -1837,13 +1916,20 @@ int elem_bytes(int storage)
     return storage == LBM_F64 ? 8 : (storage == LBM_F32_SHIFTED ? 4 : 2);
 }
 
+// Row pitch in nodes (Lx rounded up to PITCH_ALIGN) and plane stride.  (An
+// odd multiple of PITCH_ALIGN for power-of-two widths, and a pad between the
+// planes, were measured: no gain for the two-step pass, and the one-step
+// sweep at 4096^2 FP32 fell from 82 to 65 GLUPS with the odd pitch.)
+long long geo_pitch(int Lx) { return (Lx + PITCH_ALIGN - 1LL) / PITCH_ALIGN * PITCH_ALIGN; }
+
+long long geo_plane(int Lx, int Ly) { return geo_pitch(Lx) * Ly; }
+
 int check_params(const lbm_vans_params *p)
 {
     if (!p) return fail(LBM_VANS_EINVAL, "params is NULL");
     if (p->Lx < 1 || p->Ly < 1)
         return fail(LBM_VANS_EINVAL, "lattice size %d x %d must be at least 1 x 1", p->Lx, p->Ly);
-    long long pitch = (p->Lx + PITCH_ALIGN - 1LL) / PITCH_ALIGN * PITCH_ALIGN;
-    if (pitch * p->Ly >= (1LL << 31))
+    if (geo_plane(p->Lx, p->Ly) >= (1LL << 31))
         return fail(LBM_VANS_EINVAL, "lattice %d x %d too large (padded nodes must be < 2^31)",
                     p->Lx, p->Ly);
     if ((p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_BOUNCEBACK && p->bc_x != LBM_BC_OPEN) ||
@@ -1902,14 +1988,14 @@ Geo make_geo(const lbm_vans_params *p, int vec = 1, int rows = ROWS)
     Geo g;
     g.Lx = p->Lx;
     g.Ly = p->Ly;
-    g.pitch = (p->Lx + PITCH_ALIGN - 1) / PITCH_ALIGN * PITCH_ALIGN;
+    g.pitch = static_cast<int>(geo_pitch(p->Lx));
     g.wall_x = p->bc_x != LBM_BC_PERIODIC;
     g.wall_y = p->bc_y == LBM_BC_BOUNCEBACK;
     g.open_x = p->bc_x == LBM_BC_OPEN;
     g.nbx = (p->Lx + TX * vec - 1) / (TX * vec);
     int nby = (p->Ly + NW * rows - 1) / (NW * rows);
     g.ntiles = g.nbx * nby;
-    g.plane = (long long)g.pitch * p->Ly;
+    g.plane = geo_plane(p->Lx, p->Ly);
     return g;
 }
 
@@ -2033,14 +2119,24 @@ void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
     else launch_sweep_rg<S, R, DIAG, false, VMAX>(h, src, dst, ph);
 }
 
+// The two-step pass addresses a plane (state or porosity, at most 4 bytes a
+// node) with byte offsets below 2^31 (its stores mark a dropped store with
+// 2^31) and rows with 24-bit products.
+bool tb2_fits(const Geo &g)
+{
+    return static_cast<unsigned long long>(g.pitch) * 4 < (1ull << 24) && g.Ly < (1 << 24) &&
+           static_cast<unsigned long long>(g.plane) * 4 < (1ull << 31);
+}
+
 // Two time steps in one pass (k_sweep_tb2): FP32 and FP16 storage.
 bool tb2_eligible(const lbm_vans_handle *h)
 {
-    return h->p.step_pairs == 0 && h->p.storage != LBM_F64;
+    return h->p.step_pairs == 0 && h->p.storage != LBM_F64 && tb2_fits(h->g);
 }
 
 int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
 {
+    if (!tb2_fits(h->g)) return fail(LBM_VANS_EINVAL, "lattice too large for the two-step pass");
     return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
@@ -2475,6 +2571,7 @@ struct lbm_vans_batch {
     void *d_desc = nullptr;
     int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap = nullptr;
     int ntiles = 0, ntiles_adj = 0, nwaves = 0;
+    bool tb2_ok = true;             // every member fits the two-step pass's addressing
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // chunk of cfg.graph_steps steps from slot 0 / 1
 };
 
@@ -2488,7 +2585,10 @@ size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, size_t
 }
 
 // Rows per chunk of the two-step pass for a storage code (see tb_rows).
-int tb_rows_of(int storage) { return storage == LBM_F16_SHIFTED ? 16 : 8; }
+int tb_rows_of(int storage)
+{
+    return storage == LBM_F16_SHIFTED ? LBM_VANS_TB_ROWS16 : LBM_VANS_TB_ROWS32;
+}
 
 // Waves of the two-step pass over one member (0 in FP64, which has no such pass).
 size_t tb2_waves(const lbm_vans_params *p)
@@ -2622,6 +2722,7 @@ int batch_pair(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a)
         if constexpr (std::is_same_v<S, double>) {
             return fail(LBM_VANS_EINVAL, "two-step pass needs FP32 or FP16 storage");
         } else {
+            if (!b->tb2_ok) return fail(LBM_VANS_EINVAL, "a member is too large for the two-step pass");
             const int n = b->nwaves;
             const int grid = (n + NW - 1) / NW;
             const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
@@ -2644,7 +2745,7 @@ int batch_pair(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a)
 // Whether batched steps go two per launch.
 bool batch_pairs(const lbm_vans_batch *b)
 {
-    return b->cfg.step_pairs == 0 && b->storage != LBM_F64 && b->nwaves > 0;
+    return b->cfg.step_pairs == 0 && b->storage != LBM_F64 && b->nwaves > 0 && b->tb2_ok;
 }
 
 int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir)
@@ -2799,6 +2900,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     b->bx = h0->g.open_x ? 2 : (h0->g.wall_x ? 1 : 0);
     b->wy = h0->g.wall_y;
     b->vmax = b->storage == LBM_F64 ? 2 : 4;
+    for (int32_t k = 0; k < nmembers; k++) b->tb2_ok = b->tb2_ok && tb2_fits(members[k]->g);
     const size_t dsz = b->storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
     char *w = static_cast<char *>(work);
     b->d_desc = w;
@@ -2888,7 +2990,7 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
             if (b->cfg.us_per_step < top.us_per_step) top = b->cfg;
         }
     }
-    if (b->storage != LBM_F64 && b->nwaves > 0) {
+    if (b->storage != LBM_F64 && b->nwaves > 0 && b->tb2_ok) {
         // the two-step pass (independent of vec and grid), timed per step
         rc = batch_pair(b, b->stream, src, dst, res);
         if (rc) return rc;

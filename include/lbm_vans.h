@@ -201,9 +201,10 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
  * initial state (the state is reset to f(., 0), then advanced): J and
  * dJdeps(x) = dJ/deps(x), the exact derivative of the discrete map (up to
  * rounding), computed by the reverse (adjoint) sweep: a forward pass keeping
- * a checkpoint every ckpt_every steps, then, segment by segment from the
- * last, the states recomputed from the checkpoint and the adjoint stepped
- * back through them.  Porosity enters through eps itself (density, drag),
+ * a checkpoint every ckpt_every steps (two steps per pass in between, as in
+ * lbm_vans_step, when params.step_pairs allows it), then, segment by segment
+ * from the last, the states recomputed one step at a time from the
+ * checkpoint and the adjoint stepped back through them.  Porosity enters through eps itself (density, drag),
  * through grad(eps), through the open-boundary reservoirs and the initial
  * state; the sensitivities are accumulated in FP64.
  * grad_work: device buffer of lbm_vans_grad_work_bytes() bytes, 256-byte

@@ -2477,7 +2477,16 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
         for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += K) {
             HIP_TRY(hipMemcpyAsync(ckpt(s0 / K), h->buf[h->cur], G.pop, hipMemcpyDeviceToDevice,
                                    h->stream));
+            // only the checkpoints are kept, so steps in between may go two per pass
             for (int64_t k = 0; k < K && s0 + k < nsteps; k++) {
+                if (k + 1 < K && s0 + k + 1 < nsteps && tb2_eligible(h)) {
+                    r = launch_tb2(h, h->buf[h->cur], h->buf[1 - h->cur]);
+                    if (r) return r;
+                    h->cur = 1 - h->cur;
+                    h->n += 2;
+                    k++;
+                    continue;
+                }
                 r = launch_sweep(h, false);
                 if (r) return r;
                 h->cur = 1 - h->cur;
@@ -3119,8 +3128,16 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
                 HIP_TRY(hipMemcpyAsync(gw[k] + (s0 / K) * G[k].pop, h->buf[h->cur], G[k].pop,
                                        hipMemcpyDeviceToDevice, b->stream));
             }
+            // only the checkpoints are kept, so steps in between may go two per launch
             for (int64_t j = 0; j < K && s0 + j < nsteps; j++) {
                 const int cur = b->m[0]->cur;
+                if (j + 1 < K && s0 + j + 1 < nsteps && batch_pairs(b)) {
+                    r = batch_pair(b, b->stream, cur, 1 - cur, b->m[0]->n >= 1);
+                    if (r) return r;
+                    batch_advance(b, 2, 1);
+                    j++;
+                    continue;
+                }
                 r = batch_sweep(b, b->stream, cur, 1 - cur, b->m[0]->n >= 1);
                 if (r) return r;
                 batch_advance(b, 1, 1);

@@ -36,9 +36,9 @@ PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E peak
 PROFILE_TRAFFIC = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_traffic_box4096_f32.md"),
                    "box8192_f16": os.path.join(ROOT, "profiles", "sweep_traffic_box8192_f16.md"),
                    "ensemble64_f32": os.path.join(ROOT, "profiles",
-                                                  "sweep_traffic_ensemble64_f32.md"),
-                   "ensemble64_f32_pairs": os.path.join(ROOT, "profiles",
-                                                        "tb2_traffic_ensemble64_f32.md")}
+                                                  "batch_traffic_ensemble64_f32.md")}
+MULTI_KERNEL = {1: "k_sweep_vec", 2: "k_sweep_tb2", 3: "k_sweep_tb3"}
+BATCH_KERNEL = {1: "k_batch_sweep", 2: "k_batch_tb2", 3: "k_batch_tb3"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
 
 
@@ -57,18 +57,24 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
+    the workload, if it was taken on the current kernel source; else None.  A summary
+    holds one block per kernel ("kernel: <name> ..." up to its source hash)."""
     path = PROFILE_TRAFFIC.get(workload)
     if path is None or not os.path.exists(path):
         return None
     txt = open(path).read()
-    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
-        return None
-    return float(m_bytes.group(1))
+    for block in re.findall(r"kernel: (.*?kernel_source_sha256_16:\s*[0-9a-f]+)", txt, re.S):
+        name = block.split()[0]
+        if not (name == kernel or name.startswith(kernel + "<") or
+                name.startswith("_ZN12_GLOBAL__N_1" + str(len(kernel)) + kernel)):
+            continue
+        m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", block)
+        m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", block)
+        if m_hash and m_bytes and m_hash.group(1) == kernel_hash():
+            return float(m_bytes.group(1))
+    return None
 
 
 def copy_bandwidth_gbps(torch, nbytes=2 << 30, reps=10) -> float:
@@ -191,10 +197,10 @@ def crop_sample(w, lbm, steps: int):
 
 
 def steps_per_launch(w) -> int:
-    """Steps one sweep launch advances: the library runs pairs of steps in one pass
-    (k_sweep_tb2) for FP32 / FP16 storage, one step per launch (k_sweep_vec) for
+    """Steps one sweep launch advances: the library runs three steps in one pass
+    (k_sweep_tb3) for FP32 / FP16 storage, one step per launch (k_sweep_vec) for
     FP64."""
-    return 2 if w.storage != "f64" else 1
+    return 3 if w.storage != "f64" else 1
 
 
 def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0):
@@ -311,9 +317,9 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
 
 def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: bool):
     """The 64-member ensemble of uneven open channels (FP32): launch shape picked by the
-    library's autotuner (single-step launches of each width and grid, or the two-step
-    pass), then `steps` batched steps (replayed as 16-step graphs) timed with HIP
-    events; the same steps as plain launches; the gradient of every member's outlet
+    library's autotuner (single-step launches of each width and grid, the two- and the
+    three-step pass), then `steps` batched steps (replayed as 24-step graphs) timed with
+    HIP events; the same steps as plain launches; the gradient of every member's outlet
     flux after 2000 steps (checkpoints every 45).
     Returns (leg dict, accuracy sample of the smallest member or None)."""
     import numpy as np
@@ -345,10 +351,10 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
         return e0.elapsed_time(e1) / 1e3
 
     t_graph = timed(steps)
-    b.configure(best["vec"], best["grid"], 0, best["step_pairs"])
+    b.configure(best["vec"], best["grid"], 0, best["steps_per_pass"])
     t_plain = timed(steps)
-    b.configure(best["vec"], best["grid"], best["graph_steps"], best["step_pairs"])
-    pairs = best["step_pairs"] == 0
+    b.configure(best["vec"], best["grid"], best["graph_steps"], best["steps_per_pass"])
+    spl = best["steps_per_pass"] or 3
     bpn = algorithmic_bytes_per_node("f32")
     # algorithmic bytes per node-step over the time per step (= per launch / steps per launch)
     ach = bpn * cells / (t_graph / steps) / 1e9
@@ -360,12 +366,11 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
            "tuned": best, "trials": trials,
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS,
                         "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4),
-                        "traffic": (measured_traffic("ensemble64_f32_pairs" if pairs
-                                                     else "ensemble64_f32")
-                                    if (pairs or best["vec"] == 4) and len(members) == 64
+                        "traffic": (measured_traffic("ensemble64_f32", BATCH_KERNEL[spl])
+                                    if (spl > 1 or best["vec"] == 4) and len(members) == 64
                                     else None),
-                        "kernel": "k_batch_tb2" if pairs else "k_batch_sweep",
-                        "steps_per_launch": 2 if pairs else 1,
+                        "kernel": BATCH_KERNEL[spl],
+                        "steps_per_launch": spl,
                         "bytes_per_node_step": bpn}}
     log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
         f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")
@@ -506,7 +511,7 @@ def main():
     # algorithmic bytes of a node-step (the single-step scheme's loads and stores)
     # times the node-steps of one launch
     achieved = bpn * cells * spl / launch_s / 1e9
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(args.workload, MULTI_KERNEL[spl])
     copy_bw = copy_bandwidth_gbps(torch)
     log(f"[bench] {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic, device copy {copy_bw:.1f} GB/s")
 
@@ -532,9 +537,10 @@ def main():
                 "ms_per_step": round(g16 * 1e3 / steps16, 5),
                 "roofline": {"bound": "hbm", "achieved": round(a16, 1), "peak": PEAK_HBM_GBPS,
                              "unit": "GB/s", "frac": round(a16 / PEAK_HBM_GBPS, 4),
-                             "traffic": measured_traffic("box8192_f16"), "bytes_per_node": b16,
-                             "kernel": "k_sweep_tb2", "steps_per_launch": 2,
-                             "launch_us": round(g16 / steps16 * 2 * 1e6, 2)},
+                             "traffic": measured_traffic("box8192_f16", MULTI_KERNEL[3]),
+                             "bytes_per_node": b16,
+                             "kernel": MULTI_KERNEL[3], "steps_per_launch": 3,
+                             "launch_us": round(g16 / steps16 * 3 * 1e6, 2)},
                 "single_step": {"kernel": "k_sweep_vec", "value": round(cells16 / s16 / 1e6, 2),
                                 "unit": "MLUPS", "frac": round(b16 * cells16 / s16 / 1e9 /
                                                                 PEAK_HBM_GBPS, 4)},
@@ -598,7 +604,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic,
-                     "kernel": "k_sweep_tb2" if spl == 2 else "k_sweep_vec",
+                     "kernel": MULTI_KERNEL[spl],
                      "steps_per_launch": spl, "bytes_per_node_step": bpn,
                      "launch_us": round(launch_s * 1e6, 2),
                      "device_copy_GBps": round(copy_bw, 1)},

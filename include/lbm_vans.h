@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 5
+#define LBM_VANS_ABI_VERSION 6
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -114,11 +114,12 @@ typedef struct lbm_vans_params {
     int32_t sweep_vec;     /* nodes per lane of the one-step sweep: 0 = automatic (the
                               widest: 4, or 2 in LBM_F64); 1; or the widest.  Results do
                               not depend on it beyond rounding.                        */
-    int32_t step_pairs;    /* 0 = automatic: lbm_vans_step runs two steps per pass where
-                              it can (LBM_F32_SHIFTED / LBM_F16_SHIFTED, periodic x,
-                              diag_every = 0; the intermediate state stays in registers,
-                              so FP16 storage rounds every other step); 1 = one step per
-                              pass always.                                             */
+    int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 0 =
+                              automatic (3); 1, 2 or 3.  Several steps per pass need
+                              LBM_F32_SHIFTED or LBM_F16_SHIFTED storage and
+                              diag_every = 0 (else one step per pass); the intermediate
+                              states stay in registers (so FP16 storage rounds once
+                              per pass) and each pass recomputes its chunk's halo.    */
 } lbm_vans_params;
 
 typedef struct lbm_vans_handle lbm_vans_handle;
@@ -147,8 +148,8 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
  * for every node, the moments of eqs. (0moment)/(1moment) (velocity implicit
  * through the drag, solved exactly), collision toward eq. (d2q9eq) with the
  * sources of eqs. (pi) and (Fi), and streaming with the boundary rule, fused
- * in one pass per step, or per two steps where params.step_pairs allows it
- * (the intermediate state then never leaves the GPU's registers).
+ * in one pass per step, or per two or three steps where params.steps_per_pass
+ * allows it (the intermediate states then never leave the GPU's registers).
  * Asynchronous. */
 int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps);
 
@@ -201,8 +202,8 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
  * initial state (the state is reset to f(., 0), then advanced): J and
  * dJdeps(x) = dJ/deps(x), the exact derivative of the discrete map (up to
  * rounding), computed by the reverse (adjoint) sweep: a forward pass keeping
- * a checkpoint every ckpt_every steps (two steps per pass in between, as in
- * lbm_vans_step, when params.step_pairs allows it), then, segment by segment
+ * a checkpoint every ckpt_every steps (up to three steps per pass in between, as
+ * in lbm_vans_step, when params.steps_per_pass allows it), then, segment by segment
  * from the last, the states recomputed one step at a time from the
  * checkpoint and the adjoint stepped back through them.  Porosity enters through eps itself (density, drag),
  * through grad(eps), through the open-boundary reservoirs and the initial
@@ -244,9 +245,10 @@ typedef struct lbm_vans_batch_config {
     int32_t graph_steps;  /* steps per replay of the captured step graph (even); 0: plain
                              launches.  lbm_vans_batch_step replays the graph for whole
                              chunks from state n >= 1 and launches the rest one by one */
-    int32_t step_pairs;   /* 0: with LBM_F32 / LBM_F16_SHIFTED storage, advance two steps
-                             per launch (the two-step pass over every member; vec and
-                             grid then apply to single steps only); 1: never         */
+    int32_t steps_per_pass;/* most steps one launch takes, as lbm_vans_params.
+                             steps_per_pass (0 = automatic: 3; 1, 2, 3): with
+                             LBM_F32 / LBM_F16_SHIFTED storage the multi-step pass
+                             over every member; vec and grid apply to single steps */
     double us_per_step;   /* lbm_vans_batch_tune: measured microseconds per step       */
 } lbm_vans_batch_config;
 
@@ -258,7 +260,7 @@ size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembe
  * kept alive until lbm_vans_batch_destroy().  stream: hipStream_t of the
  * batched work (NULL = null stream); graphs are captured on a private stream
  * and replayed on it.  Default configuration: widest vec, one workgroup per
- * tile, 16-step graphs, two steps per launch where the storage allows it.
+ * tile, 24-step graphs, three steps per launch where the storage allows it.
  * Synchronises the stream (table upload). */
 int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
                           size_t work_bytes, void *stream, lbm_vans_batch **out);
@@ -272,18 +274,19 @@ int lbm_vans_batch_get_config(const lbm_vans_batch *b, lbm_vans_batch_config *cf
  * first) with one workgroup per tile and with persistent grids of 1, 2, 4 and
  * 8 workgroups per compute unit, each timed with HIP events over reps sweeps
  * of the current state (read only: the state does not change), and, with
- * LBM_F32 / LBM_F16_SHIFTED storage, the two-step pass (its time per launch
- * halved; step_pairs 0 in that trial, 1 in the others).  The fastest becomes
- * the configuration (graph_steps kept; the best single-step vec and grid kept
- * when the two-step pass wins) and is written to *best (may be NULL); trials
+ * LBM_F32 / LBM_F16_SHIFTED storage, the two- and three-step passes (their time
+ * per launch divided by 2 and 3; steps_per_pass 2 and 3 in those trials, 1 in
+ * the others).  The fastest becomes the configuration (graph_steps kept; the
+ * best single-step vec and grid kept when a multi-step pass wins) and is
+ * written to *best (may be NULL); trials
  * (may be NULL if max_trials is 0) receive up to max_trials of the timed
  * shapes and *n_trials (may be NULL) their number.  Synchronises. */
 int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *best,
                         lbm_vans_batch_config *trials, int32_t max_trials, int32_t *n_trials);
 
 /* Advance every member nsteps (>= 0) time steps (as lbm_vans_step; with
- * step_pairs 0 and LBM_F32 / LBM_F16_SHIFTED storage two steps per launch, an
- * odd last step alone).  Asynchronous. */
+ * LBM_F32 / LBM_F16_SHIFTED storage up to steps_per_pass steps per launch, the
+ * steps left over in a shorter launch).  Asynchronous. */
 int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps);
 
 /* Bytes of grad_work for lbm_vans_batch_grad: the members' lbm_vans_grad

@@ -103,6 +103,12 @@ int fail(int code, const char *fmt, ...)
 #ifndef LBM_VANS_TB_ROWS16
 #define LBM_VANS_TB_ROWS16 16
 #endif
+#ifndef LBM_VANS_TB3_ROWS32
+#define LBM_VANS_TB3_ROWS32 8
+#endif
+#ifndef LBM_VANS_TB3_ROWS16
+#define LBM_VANS_TB3_ROWS16 16
+#endif
 #ifndef LBM_VANS_TB_WAVES
 #define LBM_VANS_TB_WAVES 0
 #endif
@@ -910,14 +916,25 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_vec(const S *__restrict__ fi
 // one step for two.  The node update is the sweep's own (update_node on a 3x3
 // porosity window held per lane).  The row loop is unrolled by three so that
 // the register window rotates by renaming.
-constexpr int TB_COLS = TX - 2;  // output columns per strip
+// Output columns per strip of the NS-step pass: 64 lanes less NS-1 halo lanes
+// on each side.
+template <int NS>
+constexpr int tb_cols()
+{
+    return TX - 2 * (NS - 1);
+}
+constexpr int TB_COLS = tb_cols<2>();
 
-// Output rows per chunk: shorter chunks recompute more halo rows (2 per chunk)
-// but give more waves to overlap; measured best: 8 rows in FP32, 16 in FP16.
-template <typename S>
+// Output rows per chunk: shorter chunks recompute more halo rows (2 (NS-1) per
+// chunk) but give more waves to overlap; measured best for two steps: 8 rows
+// in FP32, 16 in FP16.
+template <typename S, int NS = 2>
 constexpr int tb_rows()
 {
-    return std::is_same_v<S, _Float16> ? LBM_VANS_TB_ROWS16 : LBM_VANS_TB_ROWS32;
+    if constexpr (NS == 3)
+        return std::is_same_v<S, _Float16> ? LBM_VANS_TB3_ROWS16 : LBM_VANS_TB3_ROWS32;
+    else
+        return std::is_same_v<S, _Float16> ? LBM_VANS_TB_ROWS16 : LBM_VANS_TB_ROWS32;
 }
 
 // Value of the lane below (wave_shr: lane l reads lane l-1) and above
@@ -990,6 +1007,14 @@ __device__ __forceinline__ void store_plane(__amdgpu_buffer_rsrc_t r, unsigned o
 // and its result goes unused.
 constexpr int TB_AHEAD = LBM_VANS_TB_AHEAD;
 
+// Rows the gathers run ahead: TB_AHEAD, except one for the FP16 three-step pass,
+// whose windows take the registers (measured: 8192^2 211 against 191 GLUPS).
+template <typename S, int NS>
+constexpr int tb_ahead()
+{
+    return (NS == 3 && std::is_same_v<S, _Float16>) ? 1 : TB_AHEAD;
+}
+
 // f(integral_constant<int, J>) for J = 0, 1, ... while it returns true: code
 // unrolled at compile time whatever its size.
 template <typename F, int... J>
@@ -1004,17 +1029,21 @@ __device__ __forceinline__ void static_while(F &&f)
     static_while_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <typename S, typename R, int BX, bool WY>
-__device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restrict__ fout,
-                                         const R *__restrict__ eps, const Geo &g,
-                                         const Phys<R> &ph, int strip, int chunk, int res_a)
+template <typename S, typename R, int BX, bool WY, int NS>
+__device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict__ fout,
+                                        const R *__restrict__ eps, const Geo &g,
+                                        const Phys<R> &ph, int strip, int chunk, int res_a)
 {
-    static_assert(std::is_same_v<R, float>, "two-step pass computes in FP32");
+    static_assert(std::is_same_v<R, float>, "the multi-step pass computes in FP32");
+    static_assert(NS == 2 || NS == 3, "two or three steps per pass");
     constexpr bool WX = BX != 0;
-    constexpr int NR = tb_rows<S>(), PD = TB_AHEAD;
+    constexpr int H = NS - 1;                 // halo lanes per side, halo rows per chunk end
+    constexpr int NR = tb_rows<S, NS>(), PD = tb_ahead<S, NS>();
+    constexpr int NA = NR + 2 * H;            // first-step rows y0-H .. y0+NR+H-1
+    constexpr int NE = NA + 2;                // porosity rows y0-H-1 .. y0+NR+H
     constexpr unsigned SB = sizeof(S), EB = sizeof(R);
     const int lane = threadIdx.x % TX;
-    const int xu = strip * TB_COLS + lane - 1;  // unwrapped column
+    const int xu = strip * tb_cols<NS>() + lane - H;  // unwrapped column
     int xi;
     if constexpr (WX) {
         xi = min(max(xu, 0), g.Lx - 1);
@@ -1034,7 +1063,7 @@ __device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restric
         xm = xi == 0 ? g.Lx - 1 : xi - 1;
         xp = xi == g.Lx - 1 ? 0 : xi + 1;
     }
-    const bool out_ok = lane >= 1 && lane <= TB_COLS && xu >= 0 && xu < g.Lx;
+    const bool out_ok = lane >= H && lane < TX - H && xu >= 0 && xu < g.Lx;
     const int y0 = chunk * NR;
     const int n = min(NR, g.Ly - y0);            // output rows of this chunk
     const unsigned pb = static_cast<unsigned>(g.pitch) * SB;   // bytes per state row
@@ -1054,40 +1083,40 @@ __device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restric
         return load_cached<S, R>(reinterpret_cast<const S *>(base + off), ph.inv_scale);
     };
     auto row_in = [&](int row) { return WY ? (row >= 0 && row < g.Ly) : true; };
-    auto wrap_row = [&](int row) {
-        return row < 0 ? row + g.Ly : (row >= g.Ly ? row - g.Ly : row);
-    };
 
-    // porosity rows y0-2+k (k = 0 .. NR+3), columns x-1 .. x+1; the chunk reads
-    // k <= n+3 only
-    R E[NR + 4][3];
+    // porosity rows y0-H-1+k (k = 0 .. NE-1), columns x-1 .. x+1
+    R E[NE][3];
     auto eps_row = [&](int k) {
         const unsigned o =
-            __umul24(static_cast<unsigned>(halo_index(y0 - 2 + k, g.Ly, g.wall_y)), pe);
+            __umul24(static_cast<unsigned>(halo_index(y0 - H - 1 + k, g.Ly, g.wall_y)), pe);
         E[k][0] = *reinterpret_cast<const R *>(Eb + (o + xme));
         E[k][1] = *reinterpret_cast<const R *>(Eb + (o + xe));
         E[k][2] = *reinterpret_cast<const R *>(Eb + (o + xpe));
     };
-    // first step at row y0+a: gather into Q[a+1], then the update into P[a+1]
-    R Q[NR + 2][9], P[NR + 2][9];
-    bool qm[NR + 2], qp[NR + 2];
-    auto a_live = [&](int a) { return a <= n && row_in(y0 + a); };
+    // first step at row y0+a (a = -H .. NR+H-1): gather into Q[a+H], update into P1[a+H]
+    R Q[NA][9], P1[NA][9];
+    bool qm[NA], qp[NA];
+    auto a_live = [&](int a) { return a <= n + H - 1 && row_in(y0 + a); };
     auto issue = [&](int a) {
         // row y0+a; one outside the lattice (never finished) loads a row inside
         int yy = y0 + a;
-        if (yy < 0) yy = WY ? 0 : yy + g.Ly;
-        if (yy >= g.Ly) yy = (WY || yy - g.Ly >= g.Ly) ? g.Ly - 1 : yy - g.Ly;
+        if constexpr (WY) {
+            yy = min(max(yy, 0), g.Ly - 1);
+        } else {
+            while (yy < 0) yy += g.Ly;
+            while (yy >= g.Ly) yy -= g.Ly;
+        }
         bool wym = false, wyp = false;
         int ym = yy - 1, yp = yy + 1;
         if (ym < 0) { if (WY) { wym = true; ym = yy; } else ym = g.Ly - 1; }
         if (yp >= g.Ly) { if (WY) { wyp = true; yp = yy; } else yp = 0; }
-        qm[a + 1] = wym;
-        qp[a + 1] = wyp;
+        qm[a + H] = wym;
+        qp[a + H] = wyp;
         const unsigned r0 = __umul24(static_cast<unsigned>(yy), pb);
         const unsigned rm = __umul24(static_cast<unsigned>(ym), pb);
         const unsigned rp = __umul24(static_cast<unsigned>(yp), pb);
         const unsigned c = r0 + xb;
-        R *q = Q[a + 1];
+        R *q = Q[a + H];
         // a y wall is uniform over the wave: it picks the plane and the offset
         q[0] = ld(Fb[0], c);
         q[2] = ld(wym ? Fb[4] : Fb[2], wym ? c : rm + xb);
@@ -1120,22 +1149,25 @@ __device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restric
     };
     const bool oa = BX == 2 && res_a;        // reservoirs in the first step
     auto finish = [&](int a) {
-        const int k = a + 1;                  // porosity rows of row y0+a: E[k .. k+2]
+        const int k = a + H;                  // porosity rows of row y0+a: E[k .. k+2]
+        if (!a_live(a)) {                     // behind a y wall: never read
+#pragma unroll
+            for (int i = 0; i < 9; i++) P1[k][i] = R(0);
+            return;
+        }
         const R t[3][3] = {{E[k][0], E[k][1], E[k][2]},
                            {E[k + 1][0], E[k + 1][1], E[k + 1][2]},
                            {E[k + 2][0], E[k + 2][1], E[k + 2][2]}};
 #pragma unroll
-        for (int i = 0; i < 9; i++) P[a + 1][i] = Q[a + 1][i];
-        update_node<R, 3, false>(P[a + 1], t, 1, 1, wxm, wxp, qm[a + 1], qp[a + 1],
-                                 oa && wxm, oa && wxp, ph, nullptr, false);
+        for (int i = 0; i < 9; i++) P1[k][i] = Q[k][i];
+        update_node<R, 3, false>(P1[k], t, 1, 1, wxm, wxp, qm[k], qp[k], oa && wxm, oa && wxp,
+                                 ph, nullptr, false);
     };
-    // second step at row y0+j from P[j] (row y-1), P[j+1] (row y), P[j+2] (row y+1);
-    // a row behind a y wall is never read
-    auto second = [&](int j) {
-        const int y = y0 + j;
+    // a later step at row y from the previous step's rows y-1 (A0), y (A1), y+1
+    // (A2) of this wave, porosity rows E[k .. k+2]; a row behind a y wall is never
+    // read, and the reservoirs are active (the step starts from n + 1 >= 1)
+    auto pull = [&](R (&d)[9], const R *A0, const R *A1, const R *A2, int y, int k) {
         const bool wym = WY && y == 0, wyp = WY && y == g.Ly - 1;
-        const R *A0 = P[j], *A1 = P[j + 1], *A2 = P[j + 2];
-        R d[9];
         const R s1 = lane_from_below(A1[1]), s3 = lane_from_above(A1[3]);
         d[0] = A1[0];
         d[1] = wxm ? A1[3] : s1;
@@ -1160,38 +1192,74 @@ __device__ __forceinline__ void tb2_wave(const S *__restrict__ fin, S *__restric
             d[7] = wxp ? A1[5] : s7;
             d[8] = wxm ? A1[6] : s8;
         }
-        const R t[3][3] = {{E[j + 1][0], E[j + 1][1], E[j + 1][2]},
-                           {E[j + 2][0], E[j + 2][1], E[j + 2][2]},
-                           {E[j + 3][0], E[j + 3][1], E[j + 3][2]}};
+        const R t[3][3] = {{E[k][0], E[k][1], E[k][2]},
+                           {E[k + 1][0], E[k + 1][1], E[k + 1][2]},
+                           {E[k + 2][0], E[k + 2][1], E[k + 2][2]}};
         update_node<R, 3, false>(d, t, 1, 1, wxm, wxp, wym, wyp, BX == 2 && wxm,
                                  BX == 2 && wxp, ph, nullptr, false);
-        const unsigned c = out_ok ? __umul24(static_cast<unsigned>(y), pb) + xb : TB_NO_STORE;
+    };
+    // second step of a three-step pass at row y0+b (b = -1 .. NR) into P2[b+1]
+    R P2[NS == 3 ? NR + 2 : 1][9];
+    auto middle = [&](int b) {
+        if constexpr (NS == 3) {
+            if (!(b <= n && row_in(y0 + b))) {
+#pragma unroll
+                for (int i = 0; i < 9; i++) P2[b + 1][i] = R(0);
+                return;
+            }
+            pull(P2[b + 1], P1[b - 1 + H], P1[b + H], P1[b + 1 + H], y0 + b, b + H);
+        }
+    };
+    // last step at output row y0+j, stored
+    auto last = [&](int j) {
+        R d[9];
+        if constexpr (NS == 3)
+            pull(d, P2[j], P2[j + 1], P2[j + 2], y0 + j, j + H);
+        else
+            pull(d, P1[j - 1 + H], P1[j + H], P1[j + 1 + H], y0 + j, j + H);
+        const unsigned c = out_ok ? __umul24(static_cast<unsigned>(y0 + j), pb) + xb : TB_NO_STORE;
 #pragma unroll
         for (int i = 0; i < 9; i++) store_plane<S, R>(Gr[i], c, d[i], ph.scale);
     };
 
-    // prologue: porosity rows for the first PD output rows, the gathers of the
-    // first-step rows -1 .. PD, the first-step rows -1 and 0 (row -1 lies behind a
-    // wall when y has walls, and is then never read)
+    // prologue: the porosity rows of the first PD iterations, the gathers of the
+    // first-step rows -H .. H-1+PD, the first-step rows -H .. H-1 and, for three
+    // steps, the second-step rows -1 and 0
 #pragma unroll
-    for (int k = 0; k < PD + 4; k++) eps_row(k);
+    for (int k = 0; k < 2 * H + 2 + PD && k < NE; k++) eps_row(k);
 #pragma unroll
-    for (int i = 0; i < 9; i++) P[0][i] = R(0);
+    for (int a = -H; a <= H - 1 + PD && a <= NR + H - 1; a++) issue(a);
 #pragma unroll
-    for (int a = -1; a <= PD; a++) issue(a);
-    if (a_live(-1)) finish(-1);
-    finish(0);
+    for (int a = -H; a <= H - 1; a++) finish(a);
+    middle(-1);
+    middle(0);
     static_while<NR>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j >= n) return false;             // uniform: the chunk's last rows
-        if (a_live(j + 1)) finish(j + 1);
-        if constexpr (j + 1 + PD <= NR) issue(j + 1 + PD);
-        if constexpr (j + PD + 4 < NR + 4) eps_row(j + PD + 4);
-        second(j);
+        finish(j + H);
+        if constexpr (j + H + PD <= NR + H - 1) issue(j + H + PD);
+        if constexpr (j + 2 * H + 2 + PD < NE) eps_row(j + 2 * H + 2 + PD);
+        middle(j + 1);
+        last(j);
         return true;
     });
 }
 
+template <typename S, typename R, int BX, bool WY, int NS>
+__device__ __forceinline__ void sweep_multi(const S *__restrict__ fin, S *__restrict__ fout,
+                                            const R *__restrict__ eps, const Geo &g,
+                                            const Phys<R> &ph, int nstrips, int nchunks,
+                                            int res_a)
+{
+    // the wave's id is uniform: keep it (and all row logic) in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
+                                                   threadIdx.x / TX);
+    const int strip = wid % nstrips, chunk = wid / nstrips;
+    if (chunk >= nchunks) return;              // whole waves only; no barrier below
+    tb_wave<S, R, BX, WY, NS>(fin, fout, eps, g, ph, strip, chunk, res_a);
+}
+
+// Two steps per launch (one wave per strip and chunk).
 template <typename S, typename R, int BX, bool WY>
 __global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_sweep_tb2(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
@@ -1199,12 +1267,18 @@ __global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_sweep_tb2(const S 
                                                         Phys<R> ph, int nstrips, int nchunks,
                                                         int res_a)
 {
-    // the wave's id is uniform: keep it (and all row logic) in scalar registers
-    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
-                                                   threadIdx.x / TX);
-    const int strip = wid % nstrips, chunk = wid / nstrips;
-    if (chunk >= nchunks) return;              // whole waves only; no barrier below
-    tb2_wave<S, R, BX, WY>(fin, fout, eps, g, ph, strip, chunk, res_a);
+    sweep_multi<S, R, BX, WY, 2>(fin, fout, eps, g, ph, nstrips, nchunks, res_a);
+}
+
+// Three steps per launch.
+template <typename S, typename R, int BX, bool WY>
+__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_sweep_tb3(const S *__restrict__ fin,
+                                                        S *__restrict__ fout,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        Phys<R> ph, int nstrips, int nchunks,
+                                                        int res_a)
+{
+    sweep_multi<S, R, BX, WY, 3>(fin, fout, eps, g, ph, nstrips, nchunks, res_a);
 }
 
 // Macroscopic fields of the current state (no collision, no store of
@@ -1772,8 +1846,8 @@ struct Member {
     int vec;                // nodes per lane of this member's sweep
     int tile0;              // first position in the sweep tile list of its width
     int tile0_adj;          // first position in the adjoint tile list
-    int tb_strips;          // strips of the two-step pass
-    int tw0;                // first position in the two-step pass's wave list
+    int tb_strips[2];       // strips of the two- and three-step passes
+    int tw0[2];             // first position in their wave lists
 };
 
 template <typename R>
@@ -1842,12 +1916,12 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_sweep(const Member<R> *__res
     }
 }
 
-// Two steps of every member in one pass (the two-step pass, one wave per
+// NS steps of every member in one pass (the multi-step pass, one wave per
 // strip and chunk of a member), from state slot src to state slot dst.
-template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb2(const Member<R> *__restrict__ M,
-                                                        const int *__restrict__ wmap,
-                                                        int nwaves, int src, int dst, int res_a)
+template <typename S, typename R, int BX, bool WY, int NS>
+__device__ __forceinline__ void batch_multi_wave(const Member<R> *__restrict__ M,
+                                                 const int *__restrict__ wmap, int nwaves,
+                                                 int src, int dst, int res_a)
 {
     const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
                                                    threadIdx.x / TX);
@@ -1856,10 +1930,26 @@ __global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb2(const Me
     const Geo g = d.g;
     Phys<R> ph = d.ph;
     ph.reservoir = 1;
-    const int local = wid - d.tw0;
-    tb2_wave<S, R, BX, WY>(reinterpret_cast<const S *>(state_slot(d, src)),
-                           reinterpret_cast<S *>(state_slot(d, dst)), d.eps, g, ph,
-                           local % d.tb_strips, local / d.tb_strips, res_a);
+    const int local = wid - d.tw0[NS - 2], ns = d.tb_strips[NS - 2];
+    tb_wave<S, R, BX, WY, NS>(reinterpret_cast<const S *>(state_slot(d, src)),
+                              reinterpret_cast<S *>(state_slot(d, dst)), d.eps, g, ph,
+                              local % ns, local / ns, res_a);
+}
+
+template <typename S, typename R, int BX, bool WY>
+__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb2(const Member<R> *__restrict__ M,
+                                                        const int *__restrict__ wmap,
+                                                        int nwaves, int src, int dst, int res_a)
+{
+    batch_multi_wave<S, R, BX, WY, 2>(M, wmap, nwaves, src, dst, res_a);
+}
+
+template <typename S, typename R, int BX, bool WY>
+__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb3(const Member<R> *__restrict__ M,
+                                                        const int *__restrict__ wmap,
+                                                        int nwaves, int src, int dst, int res_a)
+{
+    batch_multi_wave<S, R, BX, WY, 3>(M, wmap, nwaves, src, dst, res_a);
 }
 
 // One reverse step of every member: adjoint slot a_next (of the state n + 1)
@@ -1971,9 +2061,9 @@ int check_params(const lbm_vans_params *p)
     if (p->sweep_vec != 0 && p->sweep_vec != 1 && p->sweep_vec != vmax)
         return fail(LBM_VANS_EINVAL, "sweep_vec = %d: 0 (automatic), 1 or %d", p->sweep_vec,
                     vmax);
-    if (p->step_pairs != 0 && p->step_pairs != 1)
-        return fail(LBM_VANS_EINVAL, "step_pairs = %d: 0 (automatic) or 1 (never)",
-                    p->step_pairs);
+    if (p->steps_per_pass < 0 || p->steps_per_pass > 3)
+        return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2 or 3",
+                    p->steps_per_pass);
     return LBM_VANS_OK;
 }
 
@@ -2128,43 +2218,55 @@ bool tb2_fits(const Geo &g)
            static_cast<unsigned long long>(g.plane) * 4 < (1ull << 31);
 }
 
-// Two time steps in one pass (k_sweep_tb2): FP32 and FP16 storage.
-bool tb2_eligible(const lbm_vans_handle *h)
+// Most time steps one pass may take: 2 or 3 with the multi-step passes (FP32 and
+// FP16 storage; automatic: 3), else 1.
+int max_pass(const lbm_vans_handle *h)
 {
-    return h->p.step_pairs == 0 && h->p.storage != LBM_F64 && tb2_fits(h->g);
+    if (h->p.storage == LBM_F64 || !tb2_fits(h->g)) return 1;
+    return h->p.steps_per_pass == 0 ? 3 : h->p.steps_per_pass;
 }
 
-int launch_tb2(lbm_vans_handle *h, const void *src, void *dst)
+// NS (2 or 3) time steps in one pass, from the state n in src into dst.
+int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
 {
-    if (!tb2_fits(h->g)) return fail(LBM_VANS_EINVAL, "lattice too large for the two-step pass");
+    if (!tb2_fits(h->g)) return fail(LBM_VANS_EINVAL, "lattice too large for the multi-step pass");
     return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         if constexpr (std::is_same_v<S, double>) {
-            return fail(LBM_VANS_EINVAL, "two-step pass needs FP32 or FP16 storage");
+            return fail(LBM_VANS_EINVAL, "multi-step pass needs FP32 or FP16 storage");
         } else {
-            const int nstrips = (h->p.Lx + TB_COLS - 1) / TB_COLS;
-            const int nchunks = (h->p.Ly + tb_rows<S>() - 1) / tb_rows<S>();
+            const int cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
+            const int rows = ns == 3 ? tb_rows<S, 3>() : tb_rows<S, 2>();
+            const int nstrips = (h->p.Lx + cols - 1) / cols;
+            const int nchunks = (h->p.Ly + rows - 1) / rows;
             const long long waves = (long long)nstrips * nchunks;
             if (waves > (long long)INT32_MAX - NW)
                 return fail(LBM_VANS_EINVAL, "lattice too large");
             const int grid = static_cast<int>((waves + NW - 1) / NW);
             Phys<R> ph = make_phys<R>(&h->p);
-            ph.reservoir = 1;                     // the second step starts from n + 1 >= 1
+            ph.reservoir = 1;                     // the later steps start from n + 1 >= 1
             const int res_a = h->n >= 1;
             const int bx = h->g.open_x ? 2 : (h->g.wall_x ? 1 : 0);
-#define LBM_VANS_TB2(BXV, WYV)                                                                  \
-    hipLaunchKernelGGL((k_sweep_tb2<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, h->stream, \
-                       (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph, nstrips, nchunks,  \
+#define LBM_VANS_TBK(KER, BXV, WYV)                                                             \
+    hipLaunchKernelGGL((KER<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, h->stream,        \
+                       (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph, nstrips, nchunks, \
                        res_a)
-            if (bx == 0 && !h->g.wall_y) LBM_VANS_TB2(0, false);
-            else if (bx == 0) LBM_VANS_TB2(0, true);
-            else if (bx == 1 && !h->g.wall_y) LBM_VANS_TB2(1, false);
-            else if (bx == 1) LBM_VANS_TB2(1, true);
-            else if (!h->g.wall_y) LBM_VANS_TB2(2, false);
-            else LBM_VANS_TB2(2, true);
-#undef LBM_VANS_TB2
-            return check_launch("k_sweep_tb2");
+#define LBM_VANS_TBX(KER)                                                                       \
+    if (bx == 0 && !h->g.wall_y) LBM_VANS_TBK(KER, 0, false);                                   \
+    else if (bx == 0) LBM_VANS_TBK(KER, 0, true);                                               \
+    else if (bx == 1 && !h->g.wall_y) LBM_VANS_TBK(KER, 1, false);                              \
+    else if (bx == 1) LBM_VANS_TBK(KER, 1, true);                                               \
+    else if (!h->g.wall_y) LBM_VANS_TBK(KER, 2, false);                                         \
+    else LBM_VANS_TBK(KER, 2, true)
+            if (ns == 3) {
+                LBM_VANS_TBX(k_sweep_tb3);
+            } else {
+                LBM_VANS_TBX(k_sweep_tb2);
+            }
+#undef LBM_VANS_TBX
+#undef LBM_VANS_TBK
+            return check_launch(ns == 3 ? "k_sweep_tb3" : "k_sweep_tb2");
         }
     });
 }
@@ -2287,14 +2389,17 @@ int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps)
     if (nsteps < 0) return fail(LBM_VANS_EINVAL, "nsteps = %lld < 0", (long long)nsteps);
     for (int64_t k = 0; k < nsteps; k++) {
         bool diag = h->p.diag_every > 0 && h->n % h->p.diag_every == 0;
-        // two steps in one pass when both remain in this call and neither records
-        // diagnostics
-        if (!diag && k + 1 < nsteps && h->p.diag_every == 0 && tb2_eligible(h)) {
-            int rc = launch_tb2(h, h->buf[h->cur], h->buf[1 - h->cur]);
+        // up to three steps in one pass when they remain in this call and none
+        // records diagnostics
+        const int m = h->p.diag_every == 0
+                          ? static_cast<int>(std::min<int64_t>(max_pass(h), nsteps - k))
+                          : 1;
+        if (m >= 2) {
+            int rc = launch_multi(h, h->buf[h->cur], h->buf[1 - h->cur], m);
             if (rc) return rc;
             h->cur = 1 - h->cur;
-            h->n += 2;
-            k++;
+            h->n += m;
+            k += m - 1;
             continue;
         }
         int rc = launch_sweep(h, diag);
@@ -2477,14 +2582,17 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
         for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += K) {
             HIP_TRY(hipMemcpyAsync(ckpt(s0 / K), h->buf[h->cur], G.pop, hipMemcpyDeviceToDevice,
                                    h->stream));
-            // only the checkpoints are kept, so steps in between may go two per pass
+            // only the checkpoints are kept, so the steps in between may go up to
+            // three per pass
             for (int64_t k = 0; k < K && s0 + k < nsteps; k++) {
-                if (k + 1 < K && s0 + k + 1 < nsteps && tb2_eligible(h)) {
-                    r = launch_tb2(h, h->buf[h->cur], h->buf[1 - h->cur]);
+                const int m = static_cast<int>(
+                    std::min<int64_t>({(int64_t)max_pass(h), K - k, nsteps - s0 - k}));
+                if (m >= 2) {
+                    r = launch_multi(h, h->buf[h->cur], h->buf[1 - h->cur], m);
                     if (r) return r;
                     h->cur = 1 - h->cur;
-                    h->n += 2;
-                    k++;
+                    h->n += m;
+                    k += m - 1;
                     continue;
                 }
                 r = launch_sweep(h, false);
@@ -2576,35 +2684,40 @@ struct lbm_vans_batch {
     size_t desc_bytes = 0;          // bytes of one device descriptor
     std::vector<char> desc;         // host image of the descriptors
     std::vector<int> tmap, tmap_adj;  // tile lists of the sweep and of the adjoint
-    std::vector<int> wmap;            // wave list of the two-step pass
+    std::vector<int> wmap[2];         // wave lists of the two- and three-step passes
     void *d_desc = nullptr;
-    int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap = nullptr;
-    int ntiles = 0, ntiles_adj = 0, nwaves = 0;
-    bool tb2_ok = true;             // every member fits the two-step pass's addressing
+    int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap[2] = {nullptr, nullptr};
+    int ntiles = 0, ntiles_adj = 0, nwaves[2] = {0, 0};
+    bool tb2_ok = true;             // every member fits the multi-step passes' addressing
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // chunk of cfg.graph_steps steps from slot 0 / 1
 };
 
 namespace {
 
-size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, size_t nwaves)
+size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, size_t nwaves2,
+                         size_t nwaves3)
 {
     const size_t d = storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
     return align256(nmembers * d) + 2 * align256(ntiles_adj * sizeof(int)) +
-           align256(nwaves * sizeof(int));
+           align256(nwaves2 * sizeof(int)) + align256(nwaves3 * sizeof(int));
 }
 
-// Rows per chunk of the two-step pass for a storage code (see tb_rows).
-int tb_rows_of(int storage)
+// Rows per chunk of the ns-step pass for a storage code (see tb_rows).
+int tb_rows_of(int storage, int ns)
 {
-    return storage == LBM_F16_SHIFTED ? LBM_VANS_TB_ROWS16 : LBM_VANS_TB_ROWS32;
+    return with_types(storage, [&](auto *sp, auto *rp) -> int {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        (void)rp;
+        return ns == 3 ? tb_rows<S, 3>() : tb_rows<S, 2>();
+    });
 }
 
-// Waves of the two-step pass over one member (0 in FP64, which has no such pass).
-size_t tb2_waves(const lbm_vans_params *p)
+// Waves of the ns-step pass over one member (0 in FP64, which has no such pass).
+size_t tb_waves(const lbm_vans_params *p, int ns)
 {
     if (p->storage == LBM_F64) return 0;
-    const int rows = tb_rows_of(p->storage);
-    return static_cast<size_t>((p->Lx + TB_COLS - 1) / TB_COLS) *
+    const int rows = tb_rows_of(p->storage, ns), cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
+    return static_cast<size_t>((p->Lx + cols - 1) / cols) *
            static_cast<size_t>((p->Ly + rows - 1) / rows);
 }
 
@@ -2624,7 +2737,8 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
     const size_t nm = b->m.size();
     b->tmap.clear();
     b->tmap_adj.clear();
-    b->wmap.clear();
+    b->wmap[0].clear();
+    b->wmap[1].clear();
     int rc = with_types(b->storage, [&](auto *sp, auto *rp) -> int {
         using R = std::remove_pointer_t<decltype(rp)>;
         (void)sp;
@@ -2647,9 +2761,12 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             d.tile0_adj = static_cast<int>(b->tmap_adj.size());
             b->tmap.insert(b->tmap.end(), d.gs.ntiles, static_cast<int>(k));
             b->tmap_adj.insert(b->tmap_adj.end(), d.g.ntiles, static_cast<int>(k));
-            d.tb_strips = (h->p.Lx + TB_COLS - 1) / TB_COLS;
-            d.tw0 = static_cast<int>(b->wmap.size());
-            b->wmap.insert(b->wmap.end(), tb2_waves(&h->p), static_cast<int>(k));
+            for (int q = 0; q < 2; q++) {
+                const int cols = q ? tb_cols<3>() : tb_cols<2>();
+                d.tb_strips[q] = (h->p.Lx + cols - 1) / cols;
+                d.tw0[q] = static_cast<int>(b->wmap[q].size());
+                b->wmap[q].insert(b->wmap[q].end(), tb_waves(&h->p, q + 2), static_cast<int>(k));
+            }
         }
         size_t off = 0;
         for (size_t k = 0; k < nm; k++) {
@@ -2671,16 +2788,19 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
     if (rc) return rc;
     b->ntiles = static_cast<int>(b->tmap.size());
     b->ntiles_adj = static_cast<int>(b->tmap_adj.size());
-    b->nwaves = static_cast<int>(b->wmap.size());
+    b->nwaves[0] = static_cast<int>(b->wmap[0].size());
+    b->nwaves[1] = static_cast<int>(b->wmap[1].size());
     HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size(), hipMemcpyHostToDevice,
                            b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap, b->tmap.data(), b->tmap.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap_adj, b->tmap_adj.data(), b->tmap_adj.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
-    if (!b->wmap.empty())
-        HIP_TRY(hipMemcpyAsync(b->d_wmap, b->wmap.data(), b->wmap.size() * sizeof(int),
-                               hipMemcpyHostToDevice, b->stream));
+    for (int q = 0; q < 2; q++)
+        if (!b->wmap[q].empty())
+            HIP_TRY(hipMemcpyAsync(b->d_wmap[q], b->wmap[q].data(),
+                                   b->wmap[q].size() * sizeof(int), hipMemcpyHostToDevice,
+                                   b->stream));
     // the host images must outlive the copies; they also must not change under them
     HIP_TRY(hipStreamSynchronize(b->stream));
     return LBM_VANS_OK;
@@ -2721,40 +2841,65 @@ int batch_sweep(lbm_vans_batch *b, hipStream_t st, int src, int dst, int reservo
     });
 }
 
-// Two batched steps on stream st: every member from state slot src to dst in
-// one launch of the two-step pass; res_a: the first step starts from n >= 1.
-int batch_pair(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a)
+// ns (2 or 3) batched steps on stream st: every member from state slot src to
+// dst in one launch of the multi-step pass; res_a: the first step starts from
+// n >= 1.
+int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, int ns)
 {
     return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         if constexpr (std::is_same_v<S, double>) {
-            return fail(LBM_VANS_EINVAL, "two-step pass needs FP32 or FP16 storage");
+            return fail(LBM_VANS_EINVAL, "multi-step pass needs FP32 or FP16 storage");
         } else {
-            if (!b->tb2_ok) return fail(LBM_VANS_EINVAL, "a member is too large for the two-step pass");
-            const int n = b->nwaves;
+            if (!b->tb2_ok)
+                return fail(LBM_VANS_EINVAL, "a member is too large for the multi-step pass");
+            const int q = ns == 3 ? 1 : 0;
+            const int n = b->nwaves[q];
             const int grid = (n + NW - 1) / NW;
             const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
-            const int *wm = b->d_wmap;
-#define LBM_VANS_BATCH(BXV, WYV)                                                              \
-    hipLaunchKernelGGL((k_batch_tb2<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, st, M, wm, \
-                       n, src, dst, res_a)
-            if (b->bx == 0 && !b->wy) LBM_VANS_BATCH(0, false);
-            else if (b->bx == 0) LBM_VANS_BATCH(0, true);
-            else if (b->bx == 1 && !b->wy) LBM_VANS_BATCH(1, false);
-            else if (b->bx == 1) LBM_VANS_BATCH(1, true);
-            else if (!b->wy) LBM_VANS_BATCH(2, false);
-            else LBM_VANS_BATCH(2, true);
+            const int *wm = b->d_wmap[q];
+#define LBM_VANS_BATCH(KER, BXV, WYV)                                                          \
+    hipLaunchKernelGGL((KER<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, st, M, wm, n, src, \
+                       dst, res_a)
+#define LBM_VANS_BATCHX(KER)                                                                   \
+    if (b->bx == 0 && !b->wy) LBM_VANS_BATCH(KER, 0, false);                                   \
+    else if (b->bx == 0) LBM_VANS_BATCH(KER, 0, true);                                         \
+    else if (b->bx == 1 && !b->wy) LBM_VANS_BATCH(KER, 1, false);                              \
+    else if (b->bx == 1) LBM_VANS_BATCH(KER, 1, true);                                         \
+    else if (!b->wy) LBM_VANS_BATCH(KER, 2, false);                                            \
+    else LBM_VANS_BATCH(KER, 2, true)
+            if (ns == 3) {
+                LBM_VANS_BATCHX(k_batch_tb3);
+            } else {
+                LBM_VANS_BATCHX(k_batch_tb2);
+            }
+#undef LBM_VANS_BATCHX
 #undef LBM_VANS_BATCH
-            return check_launch("k_batch_tb2");
+            return check_launch(ns == 3 ? "k_batch_tb3" : "k_batch_tb2");
         }
     });
 }
 
-// Whether batched steps go two per launch.
-bool batch_pairs(const lbm_vans_batch *b)
+// Most steps one batched launch may take (as max_pass for a lone problem).
+int batch_max_pass(const lbm_vans_batch *b)
 {
-    return b->cfg.step_pairs == 0 && b->storage != LBM_F64 && b->nwaves > 0 && b->tb2_ok;
+    if (b->storage == LBM_F64 || !b->tb2_ok || b->nwaves[0] == 0) return 1;
+    return b->cfg.steps_per_pass == 0 ? 3 : b->cfg.steps_per_pass;
+}
+
+// One batched launch of m steps (the one-step sweep for m = 1).
+int batch_launch(lbm_vans_batch *b, hipStream_t st, int src, int res_a, int m)
+{
+    return m >= 2 ? batch_multi(b, st, src, 1 - src, res_a, m)
+                  : batch_sweep(b, st, src, 1 - src, res_a);
+}
+
+// Launches of a run of `steps` steps, each as many as batch_max_pass allows.
+int64_t batch_launch_count(const lbm_vans_batch *b, int64_t steps)
+{
+    const int mp = batch_max_pass(b);
+    return (steps + mp - 1) / mp;
 }
 
 int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir)
@@ -2782,12 +2927,12 @@ int batch_capture(lbm_vans_batch *b, int s0)
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     int rc = LBM_VANS_OK;
-    const bool pairs = batch_pairs(b);
-    const int nl = pairs ? b->cfg.graph_steps / 2 : b->cfg.graph_steps;
-    for (int j = 0; j < nl && !rc; j++) {
-        const int src = (s0 + j) & 1;
-        rc = pairs ? batch_pair(b, b->cap, src, 1 - src, 1)
-                   : batch_sweep(b, b->cap, src, 1 - src, 1);
+    const int mp = batch_max_pass(b);
+    int src = s0;
+    for (int j = 0; j < b->cfg.graph_steps && !rc; src = 1 - src) {
+        const int m = std::min(mp, b->cfg.graph_steps - j);
+        rc = batch_launch(b, b->cap, src, 1, m);
+        j += m;
     }
     hipError_t e = hipStreamEndCapture(b->cap, &graph);
     if (rc) {
@@ -2815,9 +2960,9 @@ int check_config(const lbm_vans_batch *b, const lbm_vans_batch_config *c)
     if (c->graph_steps < 0 || c->graph_steps % 2)
         return fail(LBM_VANS_EINVAL, "graph_steps = %d: 0 or a positive even number",
                     c->graph_steps);
-    if (c->step_pairs != 0 && c->step_pairs != 1)
-        return fail(LBM_VANS_EINVAL, "step_pairs = %d: 0 (automatic) or 1 (never)",
-                    c->step_pairs);
+    if (c->steps_per_pass < 0 || c->steps_per_pass > 3)
+        return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2 or 3",
+                    c->steps_per_pass);
     return LBM_VANS_OK;
 }
 
@@ -2842,11 +2987,6 @@ void batch_advance(lbm_vans_batch *b, int64_t steps, int64_t launches)
     }
 }
 
-// Launches in one replay of the step graph.
-int graph_launches(const lbm_vans_batch *b)
-{
-    return batch_pairs(b) ? b->cfg.graph_steps / 2 : b->cfg.graph_steps;
-}
 
 }  // namespace
 
@@ -2855,13 +2995,14 @@ extern "C" {
 size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembers)
 {
     if (!members || nmembers < 1) return 0;
-    size_t tiles = 0, waves = 0;
+    size_t tiles = 0, waves2 = 0, waves3 = 0;
     for (int32_t k = 0; k < nmembers; k++) {
         if (!members[k]) return 0;
         tiles += static_cast<size_t>(members[k]->g.ntiles);
-        waves += tb2_waves(&members[k]->p);
+        waves2 += tb_waves(&members[k]->p, 2);
+        waves3 += tb_waves(&members[k]->p, 3);
     }
-    return batch_table_bytes(members[0]->p.storage, nmembers, tiles, waves);
+    return batch_table_bytes(members[0]->p.storage, nmembers, tiles, waves2, waves3);
 }
 
 int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
@@ -2873,7 +3014,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     if (!members || nmembers < 1) return fail(LBM_VANS_EINVAL, "no members");
     const lbm_vans_handle *h0 = members[0];
     if (!h0) return fail(LBM_VANS_EINVAL, "member 0 is NULL");
-    size_t tiles = 0, waves = 0;
+    size_t tiles = 0, waves = 0, waves3 = 0;
     for (int32_t k = 0; k < nmembers; k++) {
         const lbm_vans_handle *h = members[k];
         if (!h) return fail(LBM_VANS_EINVAL, "member %d is NULL", k);
@@ -2889,15 +3030,17 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
             return fail(LBM_VANS_EINVAL, "member %d is at step %lld, member 0 at %lld", k,
                         (long long)h->n, (long long)h0->n);
         tiles += static_cast<size_t>(h->g.ntiles);
-        waves += tb2_waves(&h->p);
+        waves += tb_waves(&h->p, 2);
+        waves3 += tb_waves(&h->p, 3);
     }
     if (tiles > static_cast<size_t>(INT32_MAX))
         return fail(LBM_VANS_EINVAL, "%zu tiles: too many for one launch", tiles);
-    if (waves > static_cast<size_t>(INT32_MAX - NW))
-        return fail(LBM_VANS_EINVAL, "%zu waves: too many for one launch", waves);
+    if (std::max(waves, waves3) > static_cast<size_t>(INT32_MAX - NW))
+        return fail(LBM_VANS_EINVAL, "%zu waves: too many for one launch",
+                    std::max(waves, waves3));
     if (!work || reinterpret_cast<uintptr_t>(work) % 256)
         return fail(LBM_VANS_EINVAL, "work must be a 256-byte aligned device buffer");
-    const size_t need = batch_table_bytes(h0->p.storage, nmembers, tiles, waves);
+    const size_t need = batch_table_bytes(h0->p.storage, nmembers, tiles, waves, waves3);
     if (work_bytes < need)
         return fail(LBM_VANS_EINVAL, "work has %zu bytes, %zu needed", work_bytes, need);
 
@@ -2916,12 +3059,15 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     b->d_tmap = reinterpret_cast<int *>(w + align256(nmembers * dsz));
     b->d_tmap_adj = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
                                             align256(tiles * sizeof(int)));
-    b->d_wmap = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
-                                        2 * align256(tiles * sizeof(int)));
+    b->d_wmap[0] = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
+                                           2 * align256(tiles * sizeof(int)));
+    b->d_wmap[1] = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
+                                           2 * align256(tiles * sizeof(int)) +
+                                           align256(waves * sizeof(int)));
     b->cfg.vec = b->vmax;
     b->cfg.grid = 0;
-    b->cfg.graph_steps = 16;
-    b->cfg.step_pairs = 0;
+    b->cfg.graph_steps = 24;
+    b->cfg.steps_per_pass = 0;
     int rc = LBM_VANS_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&b->ev[0]);
@@ -2982,7 +3128,7 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
             if (gi > 0 && (grid < NXCD || grid >= b->ntiles)) continue;
             b->cfg.vec = vec;
             b->cfg.grid = grid;
-            b->cfg.step_pairs = 1;
+            b->cfg.steps_per_pass = 1;
             // the state in slot src is only read, so the trials leave it unchanged
             rc = batch_sweep(b, b->stream, src, dst, res);
             if (rc) return rc;
@@ -2999,20 +3145,22 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
             if (b->cfg.us_per_step < top.us_per_step) top = b->cfg;
         }
     }
-    if (b->storage != LBM_F64 && b->nwaves > 0 && b->tb2_ok) {
-        // the two-step pass (independent of vec and grid), timed per step
-        rc = batch_pair(b, b->stream, src, dst, res);
+    // the multi-step passes (independent of vec and grid; the single-step shape
+    // found so far is kept for the steps they leave over), timed per step
+    const lbm_vans_batch_config single = top;
+    for (int ns = 2; ns <= 3 && b->storage != LBM_F64 && b->nwaves[0] > 0 && b->tb2_ok; ns++) {
+        rc = batch_multi(b, b->stream, src, dst, res, ns);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(b->ev[0], b->stream));
-        for (int r = 0; r < reps && !rc; r++) rc = batch_pair(b, b->stream, src, dst, res);
+        for (int r = 0; r < reps && !rc; r++) rc = batch_multi(b, b->stream, src, dst, res, ns);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(b->ev[1], b->stream));
         HIP_TRY(hipEventSynchronize(b->ev[1]));
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
-        lbm_vans_batch_config pc = top;
-        pc.step_pairs = 0;
-        pc.us_per_step = 1000.0 * ms / (2.0 * reps);
+        lbm_vans_batch_config pc = single;
+        pc.steps_per_pass = ns;
+        pc.us_per_step = 1000.0 * ms / (static_cast<double>(ns) * reps);
         if (nt < max_trials) trials[nt] = pc;
         nt++;
         if (pc.us_per_step < top.us_per_step) top = pc;
@@ -3041,18 +3189,14 @@ int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps)
                 if (rc) return rc;
             }
             HIP_TRY(hipGraphLaunch(b->graph[cur], b->stream));
-            batch_advance(b, C, graph_launches(b));
+            batch_advance(b, C, batch_launch_count(b, C));
             k += C;
-        } else if (batch_pairs(b) && nsteps - k >= 2) {
-            rc = batch_pair(b, b->stream, cur, 1 - cur, n >= 1);
-            if (rc) return rc;
-            batch_advance(b, 2, 1);
-            k += 2;
         } else {
-            rc = batch_sweep(b, b->stream, cur, 1 - cur, n >= 1);
+            const int m = static_cast<int>(std::min<int64_t>(batch_max_pass(b), nsteps - k));
+            rc = batch_launch(b, b->stream, cur, n >= 1, m);
             if (rc) return rc;
-            batch_advance(b, 1, 1);
-            k += 1;
+            batch_advance(b, m, 1);
+            k += m;
         }
     }
     return LBM_VANS_OK;
@@ -3128,19 +3272,16 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
                 HIP_TRY(hipMemcpyAsync(gw[k] + (s0 / K) * G[k].pop, h->buf[h->cur], G[k].pop,
                                        hipMemcpyDeviceToDevice, b->stream));
             }
-            // only the checkpoints are kept, so steps in between may go two per launch
-            for (int64_t j = 0; j < K && s0 + j < nsteps; j++) {
+            // only the checkpoints are kept, so the steps in between may go up to
+            // three per launch
+            for (int64_t j = 0; j < K && s0 + j < nsteps;) {
                 const int cur = b->m[0]->cur;
-                if (j + 1 < K && s0 + j + 1 < nsteps && batch_pairs(b)) {
-                    r = batch_pair(b, b->stream, cur, 1 - cur, b->m[0]->n >= 1);
-                    if (r) return r;
-                    batch_advance(b, 2, 1);
-                    j++;
-                    continue;
-                }
-                r = batch_sweep(b, b->stream, cur, 1 - cur, b->m[0]->n >= 1);
+                const int m = static_cast<int>(
+                    std::min<int64_t>({(int64_t)batch_max_pass(b), K - j, nsteps - s0 - j}));
+                r = batch_launch(b, b->stream, cur, b->m[0]->n >= 1, m);
                 if (r) return r;
-                batch_advance(b, 1, 1);
+                batch_advance(b, m, 1);
+                j += m;
             }
             if (nsteps == 0) break;
         }

@@ -35,7 +35,7 @@ class Spec:
     u_out: float = 0.0
     u_wall: tuple = (0.0, 0.0)      # sliding y-walls: x-velocity below, above
     sweep_vec: int = 0              # one-step sweep width (0 = automatic)
-    step_pairs: int = 0             # 0 = two steps per pass where possible, 1 = never
+    steps_per_pass: int = 0         # most steps per pass: 0 = automatic (3), 1, 2, 3
 
     def oracle(self) -> oracle.Params:
         return oracle.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
@@ -61,7 +61,7 @@ class Spec:
                           fp16_scale_log2=self.fp16_scale_log2, diag_every=self.diag_every,
                           rho_in=self.rho_in, u_in=self.u_in, rho_out=self.rho_out,
                           u_out=self.u_out, u_wall=tuple(self.u_wall),
-                          sweep_vec=self.sweep_vec, step_pairs=self.step_pairs)
+                          sweep_vec=self.sweep_vec, steps_per_pass=self.steps_per_pass)
 
     def input_eps(self, eps: np.ndarray) -> np.ndarray:
         """The porosity both sides receive: rounded once to the GPU's compute precision."""
@@ -70,16 +70,18 @@ class Spec:
         return np.ascontiguousarray(eps, dtype=np.float32).astype(np.float64)
 
 
-# Execution paths of lbm_vans_step: "auto" (the library's choice: two steps per pass
-# where possible, else the widest one-step sweep), "wide" (one step per pass, widest
-# vector width) and "narrow" (one step per pass, one node per lane), so that the test
-# grids cover every sweep kernel.
+# Execution paths of lbm_vans_step: "auto" (the library's choice: three steps per
+# pass where possible, else the widest one-step sweep), "pairs" (at most two steps per
+# pass), "wide" (one step per pass, widest vector width) and "narrow" (one step per
+# pass, one node per lane), so that the test grids cover every sweep kernel.
 def exec_mode(mode: str, storage: str) -> dict:
     if mode == "auto":
         return {}
+    if mode == "pairs":
+        return {"steps_per_pass": 2}
     if mode == "wide":
-        return {"sweep_vec": 2 if storage == "f64" else 4, "step_pairs": 1}
-    return {"sweep_vec": 1, "step_pairs": 1}
+        return {"sweep_vec": 2 if storage == "f64" else 4, "steps_per_pass": 1}
+    return {"sweep_vec": 1, "steps_per_pass": 1}
 
 
 def say(*a):

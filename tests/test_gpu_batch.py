@@ -9,9 +9,9 @@ Tolerances are those of the single-problem parity tests:
 * FP16: 2 roundings per step at 2^-11 of the largest stored magnitude;
 * gradients: FP64 <= 1e-10 of the largest |dJ/deps|, FP32 rel. L2 <= 1e-4,
   both against the oracle's FP64 reverse pass.
-With FP32 / FP16 storage the batch advances two steps per launch by default
-(the two-step pass), like a problem run alone; the single-step kernels are
-covered with step_pairs = 1.
+With FP32 / FP16 storage the batch advances three steps per launch by default
+(the multi-step pass), like a problem run alone; two steps per launch and the
+single-step kernels are covered with steps_per_pass = 2 and 1.
 A member of a batch takes the same node update as a problem run alone, so the
 batched results are also compared with lone runs, within the precision bound
 above (the batched kernel is a different compilation of the same source and
@@ -117,28 +117,50 @@ def _vmax(storage):
     return 2 if storage == "f64" else 4
 
 
+def _launch_plan(nsteps, graph_steps, max_pass):
+    """Steps of each launch lbm_vans_batch_step makes from state 0 (graphs replay whole
+    chunks from state 1 on; every launch takes as many steps as it may).  Launch
+    sequences that split the steps differently round the intermediate states
+    differently, so only equal plans can give the same bits."""
+    plan, k = [], 0
+    while k < nsteps:
+        if graph_steps > 0 and k >= 1 and nsteps - k >= graph_steps:
+            j = 0
+            while j < graph_steps:
+                m = min(max_pass, graph_steps - j)
+                plan.append(m)
+                j += m
+            k += graph_steps
+        else:
+            m = min(max_pass, nsteps - k)
+            plan.append(m)
+            k += m
+    return tuple(plan)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
 def test_every_launch_shape(storage):
     """vec 4/2/1, one workgroup per tile or persistent grids, with and without
-    graphs, one or two steps per launch (FP64 has single steps only): the same
-    bits for one vec and step_pairs, within the precision bound across them.
-    13 steps: with pairs, six two-step launches and a last single step."""
+    graphs, one, two or three steps per launch (FP64 has single steps only): the
+    same bits for one vec and one sequence of steps per launch, within the
+    precision bound across them.  13 steps: e.g. 3+3+3+3+1, 2+2+2+2+2+2+1, or
+    3+(3+1)+(3+1)+2 with 4-step graphs of triples."""
     from paper_1406_6438_amd import lbm
     members = _member_specs(storage, "open_walls")
     vmax = _vmax(storage)
-    pairs = (1,) if storage == "f64" else (0, 1)
+    pairs = (1,) if storage == "f64" else (0, 1, 2)
     shapes = [(v, g, c, sp) for v in sorted({vmax, 2, 1}, reverse=True) for g in (0, 8, 64)
               for c in (0, 4, 6) for sp in pairs]
     nsteps = 13
     ref = {}
     orc = [oracle_run(spec, eps, nsteps)[1] for spec, eps in members]
     for v, g, c, sp in shapes:
-        say(f"[batch shape {storage}] vec={v} grid={g} graph_steps={c} step_pairs={sp}")
+        say(f"[batch shape {storage}] vec={v} grid={g} graph_steps={c} steps_per_pass={sp}")
         sv = _solvers(members)
         b = lbm.Batch(sv)
         b.configure(v, g, c, sp)
         cfg = b.config
-        assert (cfg["vec"], cfg["grid"], cfg["graph_steps"], cfg["step_pairs"]) == (v, g, c, sp)
+        assert (cfg["vec"], cfg["grid"], cfg["graph_steps"], cfg["steps_per_pass"]) == (v, g, c, sp)
         b.step(nsteps)
         f = _states(sv)
         b.close()
@@ -146,26 +168,28 @@ def test_every_launch_shape(storage):
         _close(sv)
         for (spec, eps), a, fo in zip(members, f, orc):
             assert np.abs(a - fo).max() <= _bound(spec, eps, fo, nsteps)
-        if (v, sp) not in ref:
-            ref[(v, sp)] = f
+        key = (v, _launch_plan(nsteps, c, 1 if storage == "f64" else (sp or 3)))
+        if key not in ref:
+            ref[key] = f
             continue
-        for a, r in zip(f, ref[(v, sp)]):
-            assert np.array_equal(a, r)
+        for a, r in zip(f, ref[key]):
+            assert np.array_equal(a, r), key
 
 
-@pytest.mark.parametrize("step_pairs", [0, 1])
+@pytest.mark.parametrize("steps_per_pass", [0, 1, 2])
 @pytest.mark.parametrize("chunk", [4, 6])
-def test_graph_replays_match_plain_launches(chunk, step_pairs):
+def test_graph_replays_match_plain_launches(chunk, steps_per_pass):
     """A graph replayed several times, with eager work and synchronisations in
     between, against plain launches of the same steps: every replay identical.
-    A 6-step graph of pairs is three launches, so a replay ends in the other
-    state slot than it started from."""
+    A 6-step graph of pairs is three launches and a 4-step graph of triples is a
+    triple and a single step, so a replay can end in the other state slot than
+    it started from."""
     from paper_1406_6438_amd import lbm
     members = _member_specs("f32", "open_walls")
     sa, sb = _solvers(members), _solvers(members)
     ba, bb = lbm.Batch(sa), lbm.Batch(sb)
-    ba.configure(4, 0, chunk, step_pairs)
-    bb.configure(4, 0, 0, step_pairs)
+    ba.configure(4, 0, chunk, steps_per_pass)
+    bb.configure(4, 0, 0, steps_per_pass)
     ba.step(1)
     bb.step(1)
     for r in range(4):
@@ -191,8 +215,8 @@ def test_autotune_keeps_the_state_and_reports_trials():
     best, trials = b.tune(reps=3)
     say(f"[batch tune] best {best}; {len(trials)} trials")
     assert trials and best["us_per_step"] == min(t["us_per_step"] for t in trials)
-    assert sorted({t["step_pairs"] for t in trials}) == [0, 1]
-    assert all(b.config[k] == best[k] for k in ("vec", "grid", "step_pairs"))
+    assert sorted({t["steps_per_pass"] for t in trials}) == [1, 2, 3]
+    assert all(b.config[k] == best[k] for k in ("vec", "grid", "steps_per_pass"))
     for x, y in zip(_states(sv), before):
         assert np.array_equal(x, y)
     assert all(s.n == 3 for s in sv)
@@ -221,7 +245,7 @@ def test_batch_rejects_mismatched_members_and_out_of_step_members():
     with pytest.raises(lbm.LbmVansError):
         lbm.Batch([diag, c])
     b = lbm.Batch([a, c])
-    for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16), (4, 0, 16, 2),
+    for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16), (4, 0, 16, 4),
                 (4, 0, 16, -1)):
         with pytest.raises(lbm.LbmVansError):
             b.configure(*cfg)

@@ -66,7 +66,7 @@ def _perturbed_start(spec, eps, seed, amp=2e-3):
     return oracle.init(p, spec.input_eps(eps)) * (1.0 + W.noise((9, spec.Ly, spec.Lx), seed, amp))
 
 
-@pytest.mark.parametrize("mode", ["auto", "wide", "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "pairs", "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f64_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
@@ -82,7 +82,7 @@ def test_f64_parity_small_grids(geom, mode):
     assert np.abs(mg["rho"] - mo["rho"]).max() <= 1e-13
 
 
-@pytest.mark.parametrize("mode", ["auto", "wide", "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "pairs", "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f32_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
@@ -98,10 +98,13 @@ def test_f32_parity_small_grids(geom, mode):
     # collision adds a few more roundings of the same size: allow 4 per step on the
     # largest deviation D from the rest state, accumulated linearly.
     D = _max_deviation(spec, eps, fo)
-    assert np.abs(fg - fo).max() <= 4 * nsteps * 2.0 ** -24 * D
+    tol = 4 * nsteps * 2.0 ** -24 * D
+    assert np.abs(fg - fo).max() <= tol
+    # the velocity: six unit-weight terms of that size over eps rho >= 0.35 (the
+    # smaller component can exceed a relative bar on a few nodes)
     assert rel_l2(mg["ux"], mo["ux"]) <= 1e-5
-    assert rel_l2(mg["uy"], mo["uy"]) <= 1e-5
-    assert np.abs(mg["rho"] - mo["rho"]).max() <= 4 * nsteps * 2.0 ** -24 * 9 * D / 0.35
+    assert np.abs(mg["uy"] - mo["uy"]).max() <= 6 * tol / 0.35
+    assert np.abs(mg["rho"] - mo["rho"]).max() <= 9 * tol / 0.35
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -301,7 +304,7 @@ def test_init_rejects_porosity_outside_unit_interval():
 # the FP16 workload is rel. L2(u) <= 2e-3 against the FP64 oracle after 2000 steps.
 
 
-@pytest.mark.parametrize("mode", ["auto", "wide", "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "pairs", "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f16_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
@@ -378,19 +381,23 @@ TB_GEOMS = [(70, 40, "periodic", False), (130, 33, "periodic", True), (5, 7, "pe
             (130, 17, "open", True), (62, 6, "open", False), (3, 4, "open", True)]
 
 
+@pytest.mark.parametrize("per_pass", [2, 3])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("geom", TB_GEOMS, ids=lambda g: "%dx%d_%s_wy%d" % g)
-def test_two_step_pass_matches_oracle_and_single_steps(geom, storage):
+def test_multi_step_pass_matches_oracle_and_single_steps(geom, storage, per_pass):
+    """Two or three steps per pass against the oracle and against one step per call;
+    step counts that leave a shorter last pass (2, 7: 3+3+1 or 2+2+2+1) and that do not."""
     from paper_1406_6438_amd import lbm
     Lx, Ly, bx, wy = geom
-    say(f"[two-step pass {storage}] {Lx}x{Ly} x={bx} walls_y={wy}")
+    say(f"[{per_pass}-step pass {storage}] {Lx}x{Ly} x={bx} walls_y={wy}")
     spec = Spec(Lx=Lx, Ly=Ly, tau=0.62, walls_x=bx == "walls", open_x=bx == "open",
                 walls_y=wy, d_p=6.0, G=(0.0, 0.0) if bx == "open" else (2e-5, -1e-5),
                 u0=(0.01, 0.004), rho_in=1.01, u_in=0.02, rho_out=0.99, u_out=0.015,
-                u_wall=(0.0, 0.03) if wy else (0.0, 0.0), storage=storage)
+                u_wall=(0.0, 0.03) if wy else (0.0, 0.0), storage=storage,
+                steps_per_pass=per_pass)
     eps = W.grf_porosity(Lx, Ly, seed=900 + Lx, ell=2.5, lo=0.35, hi=1.0)
-    for nsteps in (2, 7, 40):
-        mg, fg = gpu_run(spec, eps, nsteps)             # pairs in one pass (+1 single)
+    for nsteps in (2, 3, 7, 40):
+        mg, fg = gpu_run(spec, eps, nsteps)
         mo, fo = oracle_run(spec, eps, nsteps)
         # stored magnitudes: the deviation from rest plus the half porosity difference
         # of the link-midpoint shift (w_i rho0 |delta eps| / 2 <= |delta eps| / 18)
@@ -402,9 +409,8 @@ def test_two_step_pass_matches_oracle_and_single_steps(geom, storage):
                2 * (nsteps + 1) * 2.0 ** -11) * D
         assert np.abs(fg - fo).max() <= tol
         assert np.abs(mg["ux"] - mo["ux"]).max() <= 6 * tol / 0.35
-        s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
-        for _ in range(nsteps):
-            s.step(1)                                     # one step per call
+        s = lbm.Solver(dataclasses.replace(spec, steps_per_pass=1).gpu(), spec.input_eps(eps))
+        s.step(nsteps)                                    # one step per pass
         f1 = s.get_state().cpu().numpy()
         s.close()
         assert np.abs(fg - f1).max() <= tol

@@ -104,10 +104,10 @@ int fail(int code, const char *fmt, ...)
 #define LBM_VANS_TB_ROWS16 16
 #endif
 #ifndef LBM_VANS_TB3_ROWS32
-#define LBM_VANS_TB3_ROWS32 8
+#define LBM_VANS_TB3_ROWS32 16
 #endif
 #ifndef LBM_VANS_TB3_ROWS16
-#define LBM_VANS_TB3_ROWS16 16
+#define LBM_VANS_TB3_ROWS16 24
 #endif
 #ifndef LBM_VANS_TB_WAVES
 #define LBM_VANS_TB_WAVES 0
@@ -927,7 +927,8 @@ constexpr int TB_COLS = tb_cols<2>();
 
 // Output rows per chunk: shorter chunks recompute more halo rows (2 (NS-1) per
 // chunk) but give more waves to overlap; measured best for two steps: 8 rows
-// in FP32, 16 in FP16.
+// in FP32, 16 in FP16; for three steps 16 and 24 (FP32 4096^2: 8 / 12 / 16 rows
+// 151.4 / 154.7 / 156.9 GLUPS).
 template <typename S, int NS = 2>
 constexpr int tb_rows()
 {

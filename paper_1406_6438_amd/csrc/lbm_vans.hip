@@ -109,6 +109,9 @@ int fail(int code, const char *fmt, ...)
 #ifndef LBM_VANS_TB3_ROWS16
 #define LBM_VANS_TB3_ROWS16 24
 #endif
+#ifndef LBM_VANS_TB_REUSE
+#define LBM_VANS_TB_REUSE 3
+#endif
 #ifndef LBM_VANS_TB_WAVES
 #define LBM_VANS_TB_WAVES 0
 #endif
@@ -285,21 +288,41 @@ struct NodeFwd {  // the node's forward quantities (the reverse pass needs them 
     R ie, a, b, Vx, Vy, Vn, A, Rr, k, un, drag;
 };
 
+// The porosity-only terms of a node's update (the same at every step): eps,
+// 1/eps, the lattice gradient of eps and the drag coefficients.
 template <typename R>
-__device__ __forceinline__ NodeFwd<R> node_forward(const R d[9], R eps, R gex, R gey,
-                                                   const Phys<R> &ph)
+struct EpsTerms {
+    R e, ie, gex, gey, a, b;
+};
+
+template <typename R>
+__device__ __forceinline__ EpsTerms<R> eps_terms(R eps, R gex, R gey, const Phys<R> &ph)
+{
+    EpsTerms<R> q;
+    q.e = eps;
+    q.ie = rcp(eps);
+    q.gex = gex;
+    q.gey = gey;
+    drag_coeffs(ph, eps, q.ie, q.a, q.b);
+    return q;
+}
+
+template <typename R>
+__device__ __forceinline__ NodeFwd<R> node_forward_q(const R d[9], const EpsTerms<R> &q,
+                                                     const Phys<R> &ph)
 {
     NodeFwd<R> F;
     Node<R> &N = F.N;
     N.dS = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-    N.S = eps * ph.rho0 + N.dS;
+    N.S = q.e * ph.rho0 + N.dS;
     N.mx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     N.my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-    F.ie = rcp(eps);
+    F.ie = q.ie;
     N.rho = N.S * F.ie;
     const R third = R(1) / R(3);
-    const R Qx = third * N.rho * gex, Qy = third * N.rho * gey;
-    drag_coeffs(ph, eps, F.ie, F.a, F.b);
+    const R Qx = third * N.rho * q.gex, Qy = third * N.rho * q.gey;
+    F.a = q.a;
+    F.b = q.b;
     F.Vx = N.mx + R(0.5) * (Qx + ph.Gx);
     F.Vy = N.my + R(0.5) * (Qy + ph.Gy);
     F.A = N.S + R(0.5) * F.a;
@@ -313,6 +336,13 @@ __device__ __forceinline__ NodeFwd<R> node_forward(const R d[9], R eps, R gex, R
     N.Tx = Qx + ph.Gx - F.drag * N.ux;
     N.Ty = Qy + ph.Gy - F.drag * N.uy;
     return F;
+}
+
+template <typename R>
+__device__ __forceinline__ NodeFwd<R> node_forward(const R d[9], R eps, R gex, R gey,
+                                                   const Phys<R> &ph)
+{
+    return node_forward_q<R>(d, eps_terms<R>(eps, gex, gey, ph), ph);
 }
 
 template <typename R>
@@ -611,16 +641,16 @@ __device__ __forceinline__ void boundary_inflow(R d[9], R e0, bool open_l, bool 
 // shift when the value bounces back from a wall).  d holds the stored values
 // of the incoming populations on entry and the values to store on exit.
 // (lyy, lx) is the node's position in the tile.
-template <typename R, int W, bool DIAG>
-__device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, int lx, bool wxm,
-                                            bool wxp, bool wym, bool wyp, bool open_l,
-                                            bool open_r, const Phys<R> &ph, double *acc,
-                                            bool count)
+// The same with the node's porosity-only terms given (q; P supplies its link
+// differences).
+template <typename R, bool DIAG>
+__device__ __forceinline__ void update_node_q(R d[9], const PorNb<R> &P, const EpsTerms<R> &q,
+                                              bool wym, bool wyp, bool open_l, bool open_r,
+                                              const Phys<R> &ph, double *acc, bool count)
 {
-    const PorNb<R> P = porosity_nb<R, W>(t, lyy, lx, wxm, wxp, wym, wyp);
     boundary_inflow<R>(d, P.e0, open_l, open_r, wym, wyp, ph);
     unshift_incoming<R>(d, P, ph.rho0);
-    Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
+    Node<R> N = node_forward_q<R>(d, q, ph).N;
     if constexpr (DIAG) {
         if (count) accumulate<R>(acc, N);
     }
@@ -629,6 +659,17 @@ __device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, in
 #pragma unroll
     for (int i = 0; i < 9; i++) de[i] = hr * P.D[i];
     collide<R>(d, N, ph, de);
+}
+
+template <typename R, int W, bool DIAG>
+__device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, int lx, bool wxm,
+                                            bool wxp, bool wym, bool wyp, bool open_l,
+                                            bool open_r, const Phys<R> &ph, double *acc,
+                                            bool count)
+{
+    const PorNb<R> P = porosity_nb<R, W>(t, lyy, lx, wxm, wxp, wym, wyp);
+    update_node_q<R, DIAG>(d, P, eps_terms<R>(P.e0, P.gex, P.gey, ph), wym, wyp, open_l,
+                           open_r, ph, acc, count);
 }
 
 // ---- vector sweep: V consecutive nodes per lane, full-width loads and stores
@@ -1008,6 +1049,20 @@ __device__ __forceinline__ void store_plane(__amdgpu_buffer_rsrc_t r, unsigned o
 // and its result goes unused.
 constexpr int TB_AHEAD = LBM_VANS_TB_AHEAD;
 
+// Whether the three-step pass computes the porosity-only terms of a row once and
+// carries them to the row's later steps (six values for each of three rows in
+// flight; LBM_VANS_TB_REUSE 0: never, 1: FP16 storage, 2: both, 3: FP32).
+// Measured (GLUPS, 4096^2 FP32 / open-walls / ensemble, 8192^2 FP16 / open-walls):
+// without 156.1 / 147.0 / 129.7, 209.3 / 169.6; with 156.7 / 150.3 / 133.6,
+// 184.8 / 176.7 -- the FP16 periodic pass loses, so FP32 only.
+template <typename S, int NS>
+constexpr bool tb_reuse()
+{
+    constexpr bool f16 = std::is_same_v<S, _Float16>;
+    return NS == 3 && (LBM_VANS_TB_REUSE == 2 || (LBM_VANS_TB_REUSE == 1 && f16) ||
+                       (LBM_VANS_TB_REUSE == 3 && !f16));
+}
+
 // Rows the gathers run ahead: TB_AHEAD, except one for the FP16 three-step pass,
 // whose windows take the registers (measured: 8192^2 211 against 191 GLUPS).
 template <typename S, int NS>
@@ -1149,11 +1204,15 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
         }
     };
     const bool oa = BX == 2 && res_a;        // reservoirs in the first step
+    // the porosity-only terms of the row whose porosity tile starts at E[k]
+    constexpr bool REUSE = tb_reuse<S, NS>();
+    EpsTerms<R> T[REUSE ? NE : 1];
     auto finish = [&](int a) {
         const int k = a + H;                  // porosity rows of row y0+a: E[k .. k+2]
         if (!a_live(a)) {                     // behind a y wall: never read
 #pragma unroll
             for (int i = 0; i < 9; i++) P1[k][i] = R(0);
+            if constexpr (REUSE) T[k] = EpsTerms<R>{R(1), R(1), R(0), R(0), R(0), R(0)};
             return;
         }
         const R t[3][3] = {{E[k][0], E[k][1], E[k][2]},
@@ -1161,8 +1220,15 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
                            {E[k + 2][0], E[k + 2][1], E[k + 2][2]}};
 #pragma unroll
         for (int i = 0; i < 9; i++) P1[k][i] = Q[k][i];
-        update_node<R, 3, false>(P1[k], t, 1, 1, wxm, wxp, qm[k], qp[k], oa && wxm, oa && wxp,
-                                 ph, nullptr, false);
+        if constexpr (REUSE) {
+            const PorNb<R> P = porosity_nb<R, 3>(t, 1, 1, wxm, wxp, qm[k], qp[k]);
+            T[k] = eps_terms<R>(P.e0, P.gex, P.gey, ph);
+            update_node_q<R, false>(P1[k], P, T[k], qm[k], qp[k], oa && wxm, oa && wxp, ph,
+                                    nullptr, false);
+        } else {
+            update_node<R, 3, false>(P1[k], t, 1, 1, wxm, wxp, qm[k], qp[k], oa && wxm,
+                                     oa && wxp, ph, nullptr, false);
+        }
     };
     // a later step at row y from the previous step's rows y-1 (A0), y (A1), y+1
     // (A2) of this wave, porosity rows E[k .. k+2]; a row behind a y wall is never
@@ -1196,8 +1262,15 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
         const R t[3][3] = {{E[k][0], E[k][1], E[k][2]},
                            {E[k + 1][0], E[k + 1][1], E[k + 1][2]},
                            {E[k + 2][0], E[k + 2][1], E[k + 2][2]}};
-        update_node<R, 3, false>(d, t, 1, 1, wxm, wxp, wym, wyp, BX == 2 && wxm,
-                                 BX == 2 && wxp, ph, nullptr, false);
+        if constexpr (REUSE) {
+            // the row's first step computed its porosity-only terms
+            const PorNb<R> P = porosity_nb<R, 3>(t, 1, 1, wxm, wxp, wym, wyp);
+            update_node_q<R, false>(d, P, T[k], wym, wyp, BX == 2 && wxm, BX == 2 && wxp, ph,
+                                    nullptr, false);
+        } else {
+            update_node<R, 3, false>(d, t, 1, 1, wxm, wxp, wym, wyp, BX == 2 && wxm,
+                                     BX == 2 && wxp, ph, nullptr, false);
+        }
     };
     // second step of a three-step pass at row y0+b (b = -1 .. NR) into P2[b+1]
     R P2[NS == 3 ? NR + 2 : 1][9];

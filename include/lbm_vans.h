@@ -114,8 +114,11 @@ typedef struct lbm_vans_params {
     int32_t sweep_vec;     /* nodes per lane of the one-step sweep: 0 = automatic (the
                               widest: 4, or 2 in LBM_F64); 1; or the widest.  Results do
                               not depend on it beyond rounding.                        */
-    int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 0 =
-                              automatic (3); 1, 2 or 3.  Several steps per pass need
+    int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 1, 2 or
+                              3; 0 = automatic: 3 when the three-step pass fills the
+                              GPU (>= 4096 waves of 60 columns x 16 rows, 24 in FP16),
+                              else 2 when the two-step pass has >= 2048 waves (62 x 8,
+                              16 in FP16), else 1.  Several steps per pass need
                               LBM_F32_SHIFTED or LBM_F16_SHIFTED storage and
                               diag_every = 0 (else one step per pass); the intermediate
                               states stay in registers (so FP16 storage rounds once

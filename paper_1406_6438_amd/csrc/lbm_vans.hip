@@ -2292,12 +2292,31 @@ bool tb2_fits(const Geo &g)
            static_cast<unsigned long long>(g.plane) * 4 < (1ull << 31);
 }
 
+// Waves of the ns-step pass (2 or 3) over a lattice of FP32 / FP16 storage.
+long long multi_waves(const lbm_vans_params *p, int ns)
+{
+    const bool f16 = p->storage == LBM_F16_SHIFTED;
+    const int cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
+    const int rows = ns == 3 ? (f16 ? tb_rows<_Float16, 3>() : tb_rows<float, 3>())
+                             : (f16 ? tb_rows<_Float16, 2>() : tb_rows<float, 2>());
+    return static_cast<long long>((p->Lx + cols - 1) / cols) * ((p->Ly + rows - 1) / rows);
+}
+
 // Most time steps one pass may take: 2 or 3 with the multi-step passes (FP32 and
-// FP16 storage; automatic: 3), else 1.
+// FP16 storage), else 1.  Automatic: three when the three-step pass has waves to
+// fill the chip (>= 4096, 16 per compute unit), two when the two-step pass has
+// >= 2048, else one: a multi-step pass walks the rows of each chunk one after
+// another, so on a small lattice its launch is long and the chip half empty
+// (open channel, GLUPS at one / two / three steps per pass: 256 x 128 5.7 / 5.1 /
+// 3.2; 1024 x 512 56.6 / 56.5 / 48.3; 2048 x 1024 69.1 / 121.1 / 114.0;
+// 4096 x 2048 78.8 / 103.0 / 146.7).
 int max_pass(const lbm_vans_handle *h)
 {
     if (h->p.storage == LBM_F64 || !tb2_fits(h->g)) return 1;
-    return h->p.steps_per_pass == 0 ? 3 : h->p.steps_per_pass;
+    if (h->p.steps_per_pass != 0) return h->p.steps_per_pass;
+    if (multi_waves(&h->p, 3) >= 4096) return 3;
+    if (multi_waves(&h->p, 2) >= 2048) return 2;
+    return 1;
 }
 
 // NS (2 or 3) time steps in one pass, from the state n in src into dst.
@@ -2776,23 +2795,11 @@ size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, size_t
            align256(nwaves2 * sizeof(int)) + align256(nwaves3 * sizeof(int));
 }
 
-// Rows per chunk of the ns-step pass for a storage code (see tb_rows).
-int tb_rows_of(int storage, int ns)
-{
-    return with_types(storage, [&](auto *sp, auto *rp) -> int {
-        using S = std::remove_pointer_t<decltype(sp)>;
-        (void)rp;
-        return ns == 3 ? tb_rows<S, 3>() : tb_rows<S, 2>();
-    });
-}
-
 // Waves of the ns-step pass over one member (0 in FP64, which has no such pass).
 size_t tb_waves(const lbm_vans_params *p, int ns)
 {
     if (p->storage == LBM_F64) return 0;
-    const int rows = tb_rows_of(p->storage, ns), cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
-    return static_cast<size_t>((p->Lx + cols - 1) / cols) *
-           static_cast<size_t>((p->Ly + rows - 1) / rows);
+    return static_cast<size_t>(multi_waves(p, ns));
 }
 
 void drop_graphs(lbm_vans_batch *b)

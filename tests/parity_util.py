@@ -70,13 +70,16 @@ class Spec:
         return np.ascontiguousarray(eps, dtype=np.float32).astype(np.float64)
 
 
-# Execution paths of lbm_vans_step: "auto" (the library's choice: three steps per
-# pass where possible, else the widest one-step sweep), "pairs" (at most two steps per
-# pass), "wide" (one step per pass, widest vector width) and "narrow" (one step per
-# pass, one node per lane), so that the test grids cover every sweep kernel.
+# Execution paths of lbm_vans_step: "auto" (the library's choice: on the small test
+# grids the widest one-step sweep), "triples" (three steps per pass), "pairs" (at most
+# two steps per pass), "wide" (one step per pass, widest vector width) and "narrow"
+# (one step per pass, one node per lane), so that the test grids cover every sweep
+# kernel.
 def exec_mode(mode: str, storage: str) -> dict:
     if mode == "auto":
         return {}
+    if mode == "triples":
+        return {"steps_per_pass": 3}
     if mode == "pairs":
         return {"steps_per_pass": 2}
     if mode == "wide":

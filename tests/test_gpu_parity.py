@@ -66,7 +66,7 @@ def _perturbed_start(spec, eps, seed, amp=2e-3):
     return oracle.init(p, spec.input_eps(eps)) * (1.0 + W.noise((9, spec.Ly, spec.Lx), seed, amp))
 
 
-@pytest.mark.parametrize("mode", ["auto", "pairs", "wide", "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "triples", "pairs", "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f64_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
@@ -82,7 +82,7 @@ def test_f64_parity_small_grids(geom, mode):
     assert np.abs(mg["rho"] - mo["rho"]).max() <= 1e-13
 
 
-@pytest.mark.parametrize("mode", ["auto", "pairs", "wide", "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "triples", "pairs", "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f32_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
@@ -304,7 +304,7 @@ def test_init_rejects_porosity_outside_unit_interval():
 # the FP16 workload is rel. L2(u) <= 2e-3 against the FP64 oracle after 2000 steps.
 
 
-@pytest.mark.parametrize("mode", ["auto", "pairs", "wide", "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "triples", "pairs", "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f16_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom

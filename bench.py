@@ -284,9 +284,11 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
     m_grad = cells * w.steps / t_grad / 1e6
     m_fwd = cells * w.steps / t_fwd / 1e6
     # algorithmic bytes per node-step: forward with checkpoints (76) + recompute (76)
-    # + reverse step (gather 36, eps 4, adjoint in 36 and out 36, FP64 accumulators
-    # read and written 48) = 312
-    bps = 312
+    # + reverse step (gather 36, eps 4, adjoint in 36 and out 36) + the sensitivity
+    # sums: FP32 partial sums read and written (24) on most reverse steps, written
+    # only (12) on the first of a run of 16 and read only (12) with the FP64
+    # accumulators read and written (48) on its last: (12 + 14 * 24 + 60) / 16 = 25.5
+    bps = 76 + 76 + 36 + 4 + 36 + 36 + 25.5
     out = {"workload": w.name, "steps": w.steps, "ckpt_every": K, "J": J,
            "value": round(m_grad, 2), "unit": "MLUPS (forward node-steps per second of the "
                                                   "whole gradient computation)",

@@ -197,7 +197,8 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
 /* Bytes of device memory lbm_vans_grad needs as grad_work for these
  * arguments (0 if invalid): one population buffer per checkpoint
  * (ceil(nsteps / ckpt_every)), ckpt_every buffers for a recomputed segment,
- * two adjoint buffers and three FP64 accumulators of the porosity grid. */
+ * two adjoint buffers and three FP64 accumulators of the porosity grid
+ * (with LBM_F32 / LBM_F16_SHIFTED storage also three FP32 partial sums). */
 size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int64_t nsteps,
                                 int32_t ckpt_every);
 
@@ -210,7 +211,9 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
  * from the last, the states recomputed one step at a time from the
  * checkpoint and the adjoint stepped back through them.  Porosity enters through eps itself (density, drag),
  * through grad(eps), through the open-boundary reservoirs and the initial
- * state; the sensitivities are accumulated in FP64.
+ * state; the sensitivities are accumulated in FP64 (with LBM_F32 /
+ * LBM_F16_SHIFTED storage the terms of each run of 16 reverse steps are summed
+ * in FP32 first, then added to the FP64 totals).
  * grad_work: device buffer of lbm_vans_grad_work_bytes() bytes, 256-byte
  * aligned, caller-owned.  dJdeps: device array [Ly][Lx] of doubles.
  * J: host double or NULL.  Synchronises the stream.  Afterwards the state is

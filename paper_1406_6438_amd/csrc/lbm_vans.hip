@@ -112,13 +112,10 @@ int fail(int code, const char *fmt, ...)
 #ifndef LBM_VANS_TB_REUSE
 #define LBM_VANS_TB_REUSE 3
 #endif
-#ifndef LBM_VANS_TB_WAVES
-#define LBM_VANS_TB_WAVES 0
-#endif
-#if LBM_VANS_TB_WAVES > 0
-#define LBM_VANS_TB_OCC __attribute__((amdgpu_waves_per_eu(LBM_VANS_TB_WAVES)))
-#else
-#define LBM_VANS_TB_OCC
+// Reverse steps whose sensitivity terms an FP32 partial sum takes before they
+// are added to the FP64 accumulators (FP32 and FP16 storage).
+#ifndef LBM_VANS_PS_RUN
+#define LBM_VANS_PS_RUN 16
 #endif
 
 constexpr int TX = 64;      // nodes per row segment: one wavefront
@@ -964,7 +961,6 @@ constexpr int tb_cols()
 {
     return TX - 2 * (NS - 1);
 }
-constexpr int TB_COLS = tb_cols<2>();
 
 // Output rows per chunk: shorter chunks recompute more halo rows (2 (NS-1) per
 // chunk) but give more waves to overlap; measured best for two steps: 8 rows
@@ -993,10 +989,10 @@ __device__ __forceinline__ float lane_from_above(float v)
                                          0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
 }
 
-// Cached loads and stores of the two-step pass: a strip's 62 columns start
-// one column off a cache line, so the lines at strip seams are shared by two
-// waves; through the cache their halves meet in L2 instead of going to HBM
-// separately (non-temporal accesses measured 20-30% slower here).
+// Cached loads and stores of the multi-step passes: a strip's columns start
+// off a cache line, so the lines at strip seams are shared by two waves;
+// through the cache their halves meet in L2 instead of going to HBM separately
+// (non-temporal accesses measured 20-30% slower here).
 template <typename S, typename R>
 __device__ __forceinline__ R load_cached(const S *p, R inv_scale)
 {
@@ -1030,9 +1026,9 @@ __device__ __forceinline__ void store_plane(__amdgpu_buffer_rsrc_t r, unsigned o
 }
 
 // BX: x ends periodic (0), walls (1) or open (2); WY: walls across y.  res_a:
-// the reservoirs of open x ends are active in the first of the two steps (the
-// pass starts from a state n >= 1); they are in the second.  With x ends, the
-// lanes beside the domain compute on clamped columns and are never read.
+// the reservoirs of open x ends are active in the first step of the pass (the
+// pass starts from a state n >= 1); they are in the later ones.  With x ends,
+// the lanes beside the domain compute on clamped columns and are never read.
 // The work of one wave: strip `strip`, chunk `chunk` of the lattice g; both
 // are uniform over the wave, so rows, row offsets and the y-wall tests live in
 // scalar registers.  Addresses are a uniform per-plane base plus a 32-bit byte
@@ -1041,8 +1037,9 @@ __device__ __forceinline__ void store_plane(__amdgpu_buffer_rsrc_t r, unsigned o
 // plane differs from lane to lane, takes a full per-lane address.
 //
 // The rows of the chunk are unrolled at compile time: the first step at row
-// y0 + a (a = -1 .. n) and the second at row y0 + j (j = 0 .. n-1) are
-// straight-line code whose windows are plain values.  The gather loads of the
+// y0 + a (a = -(NS-1) .. n+NS-2), the middle step of three at y0 + b (b = -1
+// .. n) and the last at y0 + j (j = 0 .. n-1) are straight-line code whose
+// windows are plain values.  The gather loads of the
 // first step run TB_AHEAD rows ahead of their use and, like the porosity loads
 // and the stores, are issued with no branch around them: a row outside the
 // lattice (behind a y wall, past the last chunk's end) loads a row inside it
@@ -1335,7 +1332,7 @@ __device__ __forceinline__ void sweep_multi(const S *__restrict__ fin, S *__rest
 
 // Two steps per launch (one wave per strip and chunk).
 template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_sweep_tb2(const S *__restrict__ fin,
+__global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, int nstrips, int nchunks,
@@ -1346,7 +1343,7 @@ __global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_sweep_tb2(const S 
 
 // Three steps per launch.
 template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_sweep_tb3(const S *__restrict__ fin,
+__global__ __launch_bounds__(NTHREADS) void k_sweep_tb3(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, int nstrips, int nchunks,
@@ -1685,10 +1682,19 @@ __device__ __forceinline__ void node_vjp(const R d[9], R e0, R gex, R gey, const
     for (int i = 0; i < 9; i++) nu[i] += S_bar + R(CX[i]) * Vx_bar + R(CY[i]) * Vy_bar;
 }
 
+constexpr int PS_FIRST = 1;   // the FP32 partial sums start from this step's terms
+constexpr int PS_FLUSH = 2;   // and are added into the FP64 accumulators after it
+
 // One reverse step (SEED = false) or the objective's seed (SEED = true).
 // fin: the stored state n (what the forward sweep of step n gathers from).
 // lam_next: adjoint of the state n + 1 (unused for the seed); lam: receives
 // the adjoint of the state n.  eb, gxb, gyb: FP64 accumulators [Ly][pitch].
+// p32 (FP32 compute only; else NULL): three FP32 partial sums [Ly][pitch],
+// pstride floats apart, that take the step's terms, so that the FP64 arrays are
+// read and written once per run of reverse steps rather than every step.  pmode:
+// PS_FIRST, the partial sums start from this step's terms (they are not read);
+// PS_FLUSH, they are added with this step's terms into the FP64 accumulators
+// (and not written).
 // The seed computes J = sum over x = Lx-1 of eps rho u_x of the state n (tile
 // partials in part) and the adjoint of the state from it.
 template <typename S, typename R, bool SEED>
@@ -1697,7 +1703,8 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
                                              R *__restrict__ lam, const R *__restrict__ eps,
                                              const Geo &g, const Phys<R> &ph,
                                              double *__restrict__ eb, double *__restrict__ gxb,
-                                             double *__restrict__ gyb,
+                                             double *__restrict__ gyb, float *__restrict__ p32,
+                                             long long pstride, int pmode,
                                              double *__restrict__ part, int t)
 {
     constexpr int W = TX + 2;
@@ -1773,6 +1780,27 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         *((n.wxp || n.wym) ? L8 + c : L6 + rm + n.xp) = res[6] ? R(0) : nu[6];
         *((n.wxp || n.wyp) ? L5 + c : L7 + rp + n.xp) = res[7] ? R(0) : nu[7];
         *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = res[8] ? R(0) : nu[8];
+        if constexpr (std::is_same_v<R, float>) {
+            if (p32) {
+                float *e32 = p32, *x32 = p32 + pstride, *y32 = p32 + 2 * pstride;
+                float se = e_b, sx = gx_b, sy = gy_b;
+                if (!(pmode & PS_FIRST)) {
+                    se += e32[c];
+                    sx += x32[c];
+                    sy += y32[c];
+                }
+                if (pmode & PS_FLUSH) {
+                    eb[c] += static_cast<double>(se);
+                    gxb[c] += static_cast<double>(sx);
+                    gyb[c] += static_cast<double>(sy);
+                } else {
+                    e32[c] = se;
+                    x32[c] = sx;
+                    y32[c] = sy;
+                }
+                continue;
+            }
+        }
         eb[c] += static_cast<double>(e_b);
         gxb[c] += static_cast<double>(gx_b);
         gyb[c] += static_cast<double>(gy_b);
@@ -1788,9 +1816,12 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
                                                       Phys<R> ph, double *__restrict__ eb,
                                                       double *__restrict__ gxb,
                                                       double *__restrict__ gyb,
+                                                      float *__restrict__ p32,
+                                                      long long pstride, int pmode,
                                                       double *__restrict__ part)
 {
-    adjoint_tile<S, R, SEED>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, part, blockIdx.x);
+    adjoint_tile<S, R, SEED>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, p32, pstride, pmode,
+                             part, blockIdx.x);
 }
 
 // Initial state: f_i(r, 0) = w_i eps(r) rho0 (1 + 3 e_i.u0 + 9/2 (e_i.u0)^2 -
@@ -1916,6 +1947,7 @@ struct Member {
     double *part;           // tile partials [g.ntiles][NRED]
     char *gw;               // gradient workspace: state slots 2.., adjoints, accumulators
     long long gpop, glam, gacc;
+    long long gacc32;       // bytes of one FP32 partial-sum array (0: none)
     int nslot;              // state slots in gw (checkpoints + recomputed segment)
     int vec;                // nodes per lane of this member's sweep
     int tile0;              // first position in the sweep tile list of its width
@@ -1941,6 +1973,14 @@ __device__ __forceinline__ double *acc_buf(const Member<R> &d, int k)
 {
     return reinterpret_cast<double *>(d.gw + (long long)d.nslot * d.gpop + 2 * d.glam +
                                       k * d.gacc);
+}
+
+template <typename R>
+__device__ __forceinline__ float *acc32_buf(const Member<R> &d)
+{
+    return d.gacc32 ? reinterpret_cast<float *>(d.gw + (long long)d.nslot * d.gpop +
+                                                2 * d.glam + 3 * d.gacc)
+                    : nullptr;
 }
 
 // Positions of the tile list this block takes: one position when the grid
@@ -2011,7 +2051,7 @@ __device__ __forceinline__ void batch_multi_wave(const Member<R> *__restrict__ M
 }
 
 template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb2(const Member<R> *__restrict__ M,
+__global__ __launch_bounds__(NTHREADS) void k_batch_tb2(const Member<R> *__restrict__ M,
                                                         const int *__restrict__ wmap,
                                                         int nwaves, int src, int dst, int res_a)
 {
@@ -2019,7 +2059,7 @@ __global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb2(const Me
 }
 
 template <typename S, typename R, int BX, bool WY>
-__global__ __launch_bounds__(NTHREADS) LBM_VANS_TB_OCC void k_batch_tb3(const Member<R> *__restrict__ M,
+__global__ __launch_bounds__(NTHREADS) void k_batch_tb3(const Member<R> *__restrict__ M,
                                                         const int *__restrict__ wmap,
                                                         int nwaves, int src, int dst, int res_a)
 {
@@ -2033,7 +2073,7 @@ template <typename S, typename R, bool SEED>
 __global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__restrict__ M,
                                                             const int *__restrict__ tmap,
                                                             int ntiles, int src, int a_next,
-                                                            int a, int reservoir)
+                                                            int a, int reservoir, int pmode)
 {
     const int T = xcd_tile(blockIdx.x, ntiles);
     const Member<R> &d = M[tmap[T]];
@@ -2042,7 +2082,8 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__r
     ph.reservoir = reservoir;
     adjoint_tile<S, R, SEED>(reinterpret_cast<const S *>(state_slot(d, src)),
                              SEED ? nullptr : adj_buf(d, a_next), adj_buf(d, a), d.eps, g, ph,
-                             acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), d.part,
+                             acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), acc32_buf(d),
+                             d.gacc32 / static_cast<long long>(sizeof(float)), pmode, d.part,
                              T - d.tile0_adj);
 }
 
@@ -2283,10 +2324,10 @@ void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
     else launch_sweep_rg<S, R, DIAG, false, VMAX>(h, src, dst, ph);
 }
 
-// The two-step pass addresses a plane (state or porosity, at most 4 bytes a
-// node) with byte offsets below 2^31 (its stores mark a dropped store with
+// The multi-step passes address a plane (state or porosity, at most 4 bytes a
+// node) with byte offsets below 2^31 (their stores mark a dropped store with
 // 2^31) and rows with 24-bit products.
-bool tb2_fits(const Geo &g)
+bool multi_fits(const Geo &g)
 {
     return static_cast<unsigned long long>(g.pitch) * 4 < (1ull << 24) && g.Ly < (1 << 24) &&
            static_cast<unsigned long long>(g.plane) * 4 < (1ull << 31);
@@ -2312,7 +2353,7 @@ long long multi_waves(const lbm_vans_params *p, int ns)
 // 4096 x 2048 78.8 / 103.0 / 146.7).
 int max_pass(const lbm_vans_handle *h)
 {
-    if (h->p.storage == LBM_F64 || !tb2_fits(h->g)) return 1;
+    if (h->p.storage == LBM_F64 || !multi_fits(h->g)) return 1;
     if (h->p.steps_per_pass != 0) return h->p.steps_per_pass;
     if (multi_waves(&h->p, 3) >= 4096) return 3;
     if (multi_waves(&h->p, 2) >= 2048) return 2;
@@ -2322,7 +2363,7 @@ int max_pass(const lbm_vans_handle *h)
 // NS (2 or 3) time steps in one pass, from the state n in src into dst.
 int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
 {
-    if (!tb2_fits(h->g)) return fail(LBM_VANS_EINVAL, "lattice too large for the multi-step pass");
+    if (!multi_fits(h->g)) return fail(LBM_VANS_EINVAL, "lattice too large for the multi-step pass");
     return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
@@ -2595,8 +2636,25 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
 namespace {
 
 struct GradLayout {
-    size_t pop, lam, acc, total;
+    size_t pop, lam, acc, acc32, total;
     int64_t nck, seg;
+};
+
+// Mode of the FP32 partial sums for each reverse launch in order: the first after a
+// flush starts them, every LBM_VANS_PS_RUN-th and the last one flush them.
+struct PartialRun {
+    int count = 0;
+    int next(bool last)
+    {
+        int m = count == 0 ? PS_FIRST : 0;
+        if (last || count == LBM_VANS_PS_RUN - 1) {
+            m |= PS_FLUSH;
+            count = 0;
+        } else {
+            count++;
+        }
+        return m;
+    }
 };
 
 GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_every)
@@ -2610,7 +2668,9 @@ GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_ev
     G.seg = ckpt_every;
     G.lam = align256((size_t)9 * g.plane * (p->storage == LBM_F64 ? 8 : 4));
     G.acc = align256((size_t)g.plane * sizeof(double));
-    G.total = (size_t)(G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc;
+    // FP32 compute: FP32 partial sums of the three accumulators
+    G.acc32 = p->storage == LBM_F64 ? 0 : align256((size_t)g.plane * sizeof(float));
+    G.total = (size_t)(G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc + 3 * G.acc32;
     return G;
 }
 
@@ -2655,6 +2715,10 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
     double *eb = reinterpret_cast<double *>(w + (G.nck + G.seg) * G.pop + 2 * G.lam);
     double *gxb = eb + G.acc / sizeof(double);
     double *gyb = gxb + G.acc / sizeof(double);
+    float *p32 = G.acc32 ? reinterpret_cast<float *>(w + (G.nck + G.seg) * G.pop + 2 * G.lam +
+                                                     3 * G.acc)
+                         : nullptr;
+    const long long pstride = static_cast<long long>(G.acc32 / sizeof(float));
     const Geo &g = h->g;
     const int K = ckpt_every;
 
@@ -2704,9 +2768,11 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
         Phys<R> ph = ph0;
         ph.reservoir = nsteps >= 1;
         int a = 0;
+        PartialRun run;
         hipLaunchKernelGGL((k_adjoint<S, R, true>), dim3(h->ntiles), dim3(NTHREADS), 0,
                            h->stream, (const S *)h->buf[h->cur], (const R *)nullptr,
-                           (R *)lam[a], (const R *)h->eps, g, ph, eb, gxb, gyb, h->part);
+                           (R *)lam[a], (const R *)h->eps, g, ph, eb, gxb, gyb, p32, pstride,
+                           run.next(nsteps == 0), h->part);
         r = check_launch("k_adjoint seed");
         if (r) return r;
         r = launch_finalize(h, h->scratch_rec, h->ntiles, false, static_cast<double>(nsteps));
@@ -2728,8 +2794,8 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
                 ph.reservoir = n >= 1;
                 hipLaunchKernelGGL((k_adjoint<S, R, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
                                    h->stream, (const S *)state, (const R *)lam[a],
-                                   (R *)lam[1 - a], (const R *)h->eps, g, ph, eb, gxb, gyb,
-                                   h->part);
+                                   (R *)lam[1 - a], (const R *)h->eps, g, ph, eb, gxb, gyb, p32,
+                                   pstride, run.next(n == 0), h->part);
                 r = check_launch("k_adjoint");
                 if (r) return r;
                 a = 1 - a;
@@ -2781,7 +2847,7 @@ struct lbm_vans_batch {
     void *d_desc = nullptr;
     int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap[2] = {nullptr, nullptr};
     int ntiles = 0, ntiles_adj = 0, nwaves[2] = {0, 0};
-    bool tb2_ok = true;             // every member fits the multi-step passes' addressing
+    bool multi_ok = true;           // every member fits the multi-step passes' addressing
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // chunk of cfg.graph_steps steps from slot 0 / 1
 };
 
@@ -2859,6 +2925,7 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
                 d.gpop = static_cast<long long>(G.pop);
                 d.glam = static_cast<long long>(G.lam);
                 d.gacc = static_cast<long long>(G.acc);
+                d.gacc32 = static_cast<long long>(G.acc32);
                 d.nslot = static_cast<int>(G.nck + G.seg);
                 off += align256(G.total);
             }
@@ -2933,7 +3000,7 @@ int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, 
         if constexpr (std::is_same_v<S, double>) {
             return fail(LBM_VANS_EINVAL, "multi-step pass needs FP32 or FP16 storage");
         } else {
-            if (!b->tb2_ok)
+            if (!b->multi_ok)
                 return fail(LBM_VANS_EINVAL, "a member is too large for the multi-step pass");
             const int q = ns == 3 ? 1 : 0;
             const int n = b->nwaves[q];
@@ -2965,7 +3032,7 @@ int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, 
 // Most steps one batched launch may take (as max_pass for a lone problem).
 int batch_max_pass(const lbm_vans_batch *b)
 {
-    if (b->storage == LBM_F64 || !b->tb2_ok || b->nwaves[0] == 0) return 1;
+    if (b->storage == LBM_F64 || !b->multi_ok || b->nwaves[0] == 0) return 1;
     return b->cfg.steps_per_pass == 0 ? 3 : b->cfg.steps_per_pass;
 }
 
@@ -2983,7 +3050,8 @@ int64_t batch_launch_count(const lbm_vans_batch *b, int64_t steps)
     return (steps + mp - 1) / mp;
 }
 
-int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir)
+int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir,
+                  int pmode)
 {
     return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
@@ -2992,11 +3060,11 @@ int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int 
         if (seed)
             hipLaunchKernelGGL((k_batch_adjoint<S, R, true>), dim3(b->ntiles_adj),
                                dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
-                               b->ntiles_adj, src, a_next, a, reservoir);
+                               b->ntiles_adj, src, a_next, a, reservoir, pmode);
         else
             hipLaunchKernelGGL((k_batch_adjoint<S, R, false>), dim3(b->ntiles_adj),
                                dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
-                               b->ntiles_adj, src, a_next, a, reservoir);
+                               b->ntiles_adj, src, a_next, a, reservoir, pmode);
         return check_launch("k_batch_adjoint");
     });
 }
@@ -3133,7 +3201,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     b->bx = h0->g.open_x ? 2 : (h0->g.wall_x ? 1 : 0);
     b->wy = h0->g.wall_y;
     b->vmax = b->storage == LBM_F64 ? 2 : 4;
-    for (int32_t k = 0; k < nmembers; k++) b->tb2_ok = b->tb2_ok && tb2_fits(members[k]->g);
+    for (int32_t k = 0; k < nmembers; k++) b->multi_ok = b->multi_ok && multi_fits(members[k]->g);
     const size_t dsz = b->storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
     char *w = static_cast<char *>(work);
     b->d_desc = w;
@@ -3229,7 +3297,7 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
     // the multi-step passes (independent of vec and grid; the single-step shape
     // found so far is kept for the steps they leave over), timed per step
     const lbm_vans_batch_config single = top;
-    for (int ns = 2; ns <= 3 && b->storage != LBM_F64 && b->nwaves[0] > 0 && b->tb2_ok; ns++) {
+    for (int ns = 2; ns <= 3 && b->storage != LBM_F64 && b->nwaves[0] > 0 && b->multi_ok; ns++) {
         rc = batch_multi(b, b->stream, src, dst, res, ns);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(b->ev[0], b->stream));
@@ -3377,7 +3445,8 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
             if (r) return r;
         }
         int a = 0;
-        r = batch_adjoint(b, true, b->m[0]->cur, 0, a, nsteps >= 1);
+        PartialRun run;
+        r = batch_adjoint(b, true, b->m[0]->cur, 0, a, nsteps >= 1, run.next(nsteps == 0));
         if (r) return r;
         for (size_t k = 0; k < b->m.size(); k++) {
             lbm_vans_handle *h = b->m[k];
@@ -3400,7 +3469,7 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
             }
             for (int64_t n = s1 - 1; n >= s0; n--) {
                 const int state = n == s0 ? ckpt_slot(c) : seg_slot(n - s0);
-                r = batch_adjoint(b, false, state, a, 1 - a, n >= 1);
+                r = batch_adjoint(b, false, state, a, 1 - a, n >= 1, run.next(n == 0));
                 if (r) return r;
                 a = 1 - a;
             }

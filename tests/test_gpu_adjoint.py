@@ -143,6 +143,34 @@ def test_gradient_fp32_matches_oracle_adjoint(Lx):
     assert rel_l2(gg, go) <= 1e-4
 
 
+@pytest.mark.parametrize("nsteps", [0, 1, 15, 16, 17, 40])
+def test_gradient_fp32_partial_sums_ignore_stale_workspace(nsteps):
+    """FP32 storage sums each run of 16 reverse steps in FP32 before adding it to the
+    FP64 accumulators.  With the workspace filled with 0xFF bytes (NaN as FP32 and
+    FP64), step counts on both sides of a run boundary still match the oracle (a
+    partial sum read before its run's first write, or a run left unflushed at the
+    end, would show as NaN or as missing terms)."""
+    from paper_1406_6438_amd import lbm
+    spec = _open_spec(24, 10, "f32", tau=0.8, d_p=60.0, u0=(0.02, 0.0), rho_in=1.0,
+                      u_in=0.02, rho_out=1.0, u_out=0.02, G=(0.0, 0.0))
+    eps = W.grf_porosity(24, 10, seed=44, ell=4.0, lo=0.4, hi=1.0)
+    K = 7
+    s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
+    nbytes = lbm.lbm_vans_grad_work_bytes(s.p, lbm.OBJ_OUTLET_FLUX, nsteps, K)
+    gw = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
+    g = torch.empty((spec.Ly, spec.Lx), dtype=torch.float64, device="cuda")
+    Jg = lbm.lbm_vans_grad(s.h, lbm.OBJ_OUTLET_FLUX, nsteps, K, gw, g)
+    torch.cuda.synchronize()
+    s.close()
+    gg = g.cpu().numpy()
+    Jo, go = oracle.grad_outlet_flux(spec.oracle(), spec.input_eps(eps), nsteps)
+    say(f"[grad f32 partial sums] {nsteps} steps: J rel err {abs(Jg - Jo) / abs(Jo):.3e}, "
+        f"grad rel L2 {rel_l2(gg, go):.3e}")
+    assert np.isfinite(gg).all()
+    assert abs(Jg - Jo) <= 1e-5 * abs(Jo)
+    assert rel_l2(gg, go) <= 1e-4
+
+
 def test_autograd_function_backpropagates_library_gradient():
     from paper_1406_6438_amd import lbm
     spec = _open_spec(24, 8, "f64")

@@ -353,9 +353,10 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
         return e0.elapsed_time(e1) / 1e3
 
     t_graph = timed(steps)
-    b.configure(best["vec"], best["grid"], 0, best["steps_per_pass"])
+    b.configure(best["vec"], best["grid"], 0, best["steps_per_pass"], best["pass_rows"])
     t_plain = timed(steps)
-    b.configure(best["vec"], best["grid"], best["graph_steps"], best["steps_per_pass"])
+    b.configure(best["vec"], best["grid"], best["graph_steps"], best["steps_per_pass"],
+                best["pass_rows"])
     spl = best["steps_per_pass"] or 3
     bpn = algorithmic_bytes_per_node("f32")
     # algorithmic bytes per node-step over the time per step (= per launch / steps per launch)

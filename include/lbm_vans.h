@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 6
+#define LBM_VANS_ABI_VERSION 7
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -115,14 +115,22 @@ typedef struct lbm_vans_params {
                               widest: 4, or 2 in LBM_F64); 1; or the widest.  Results do
                               not depend on it beyond rounding.                        */
     int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 1, 2 or
-                              3; 0 = automatic: 3 when the three-step pass fills the
-                              GPU (>= 4096 waves of 60 columns x 16 rows, 24 in FP16),
-                              else 2 when the two-step pass has >= 2048 waves (62 x 8,
-                              16 in FP16), else 1.  Several steps per pass need
+                              3; 0 = automatic: 3 when the three-step pass has at
+                              least 0.7 times as many waves (60 columns x pass_rows
+                              rows) as the GPU holds of its kernel at once, else 2
+                              when the two-step pass has >= 2048 waves (62 x 8, 16 in
+                              FP16), else 1.  Several steps per pass need
                               LBM_F32_SHIFTED or LBM_F16_SHIFTED storage and
                               diag_every = 0 (else one step per pass); the intermediate
                               states stay in registers (so FP16 storage rounds once
                               per pass) and each pass recomputes its chunk's halo.    */
+    int32_t pass_rows;     /* output rows per chunk (wave) of the three-step pass:
+                              0 = automatic; LBM_F32_SHIFTED: 24 or 28 (automatic: 28
+                              when that still gives four times as many waves as the
+                              GPU holds of the kernel at once, else 24: taller chunks
+                              recompute fewer halo rows but give fewer waves);
+                              LBM_F16_SHIFTED: 24.  Results do not depend on it
+                              beyond rounding.                                        */
 } lbm_vans_params;
 
 typedef struct lbm_vans_handle lbm_vans_handle;
@@ -255,6 +263,11 @@ typedef struct lbm_vans_batch_config {
                              steps_per_pass (0 = automatic: 3; 1, 2, 3): with
                              LBM_F32 / LBM_F16_SHIFTED storage the multi-step pass
                              over every member; vec and grid apply to single steps */
+    int32_t pass_rows;    /* rows per chunk of the batched three-step pass, as
+                             lbm_vans_params.pass_rows (0 = automatic: with FP32
+                             storage 28 when the whole batch has four times as many
+                             waves of 28 rows as the GPU holds of the batched kernel,
+                             else 24); the members' own pass_rows are not used      */
     double us_per_step;   /* lbm_vans_batch_tune: measured microseconds per step       */
 } lbm_vans_batch_config;
 

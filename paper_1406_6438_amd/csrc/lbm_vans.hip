@@ -104,7 +104,10 @@ int fail(int code, const char *fmt, ...)
 #define LBM_VANS_TB_ROWS16 16
 #endif
 #ifndef LBM_VANS_TB3_ROWS32
-#define LBM_VANS_TB3_ROWS32 16
+#define LBM_VANS_TB3_ROWS32 24
+#endif
+#ifndef LBM_VANS_TB3_TALL32
+#define LBM_VANS_TB3_TALL32 28
 #endif
 #ifndef LBM_VANS_TB3_ROWS16
 #define LBM_VANS_TB3_ROWS16 24
@@ -964,8 +967,11 @@ constexpr int tb_cols()
 
 // Output rows per chunk: shorter chunks recompute more halo rows (2 (NS-1) per
 // chunk) but give more waves to overlap; measured best for two steps: 8 rows
-// in FP32, 16 in FP16; for three steps 16 and 24 (FP32 4096^2: 8 / 12 / 16 rows
-// 151.4 / 154.7 / 156.9 GLUPS).
+// in FP32, 16 in FP16; for three steps 24 in FP16, and in FP32 two heights:
+// 28 rows where the lattice still has waves to fill the chip with them, else
+// 24 (FP32 three-step pass, GLUPS at 16 / 24 / 28 / 32 rows: 4096^2 158.5 /
+// 160.7 / 163.0 / 160.3; 2048^2 144.9 / 149.9 / 139.0 / 127.4; 64-member
+// ensemble 144.1 / 144.2 / 146.3 / 146.4).
 template <typename S, int NS = 2>
 constexpr int tb_rows()
 {
@@ -1082,7 +1088,7 @@ __device__ __forceinline__ void static_while(F &&f)
     static_while_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <typename S, typename R, int BX, bool WY, int NS>
+template <typename S, typename R, int BX, bool WY, int NS, int NR>
 __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict__ fout,
                                         const R *__restrict__ eps, const Geo &g,
                                         const Phys<R> &ph, int strip, int chunk, int res_a)
@@ -1091,7 +1097,7 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     static_assert(NS == 2 || NS == 3, "two or three steps per pass");
     constexpr bool WX = BX != 0;
     constexpr int H = NS - 1;                 // halo lanes per side, halo rows per chunk end
-    constexpr int NR = tb_rows<S, NS>(), PD = tb_ahead<S, NS>();
+    constexpr int PD = tb_ahead<S, NS>();
     constexpr int NA = NR + 2 * H;            // first-step rows y0-H .. y0+NR+H-1
     constexpr int NE = NA + 2;                // porosity rows y0-H-1 .. y0+NR+H
     constexpr unsigned SB = sizeof(S), EB = sizeof(R);
@@ -1316,7 +1322,7 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     });
 }
 
-template <typename S, typename R, int BX, bool WY, int NS>
+template <typename S, typename R, int BX, bool WY, int NS, int NR>
 __device__ __forceinline__ void sweep_multi(const S *__restrict__ fin, S *__restrict__ fout,
                                             const R *__restrict__ eps, const Geo &g,
                                             const Phys<R> &ph, int nstrips, int nchunks,
@@ -1327,7 +1333,7 @@ __device__ __forceinline__ void sweep_multi(const S *__restrict__ fin, S *__rest
                                                    threadIdx.x / TX);
     const int strip = wid % nstrips, chunk = wid / nstrips;
     if (chunk >= nchunks) return;              // whole waves only; no barrier below
-    tb_wave<S, R, BX, WY, NS>(fin, fout, eps, g, ph, strip, chunk, res_a);
+    tb_wave<S, R, BX, WY, NS, NR>(fin, fout, eps, g, ph, strip, chunk, res_a);
 }
 
 // Two steps per launch (one wave per strip and chunk).
@@ -1338,18 +1344,19 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
                                                         Phys<R> ph, int nstrips, int nchunks,
                                                         int res_a)
 {
-    sweep_multi<S, R, BX, WY, 2>(fin, fout, eps, g, ph, nstrips, nchunks, res_a);
+    sweep_multi<S, R, BX, WY, 2, tb_rows<S, 2>()>(fin, fout, eps, g, ph, nstrips, nchunks,
+                                                  res_a);
 }
 
-// Three steps per launch.
-template <typename S, typename R, int BX, bool WY>
+// Three steps per launch, in chunks of NR rows.
+template <typename S, typename R, int BX, bool WY, int NR>
 __global__ __launch_bounds__(NTHREADS) void k_sweep_tb3(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, int nstrips, int nchunks,
                                                         int res_a)
 {
-    sweep_multi<S, R, BX, WY, 3>(fin, fout, eps, g, ph, nstrips, nchunks, res_a);
+    sweep_multi<S, R, BX, WY, 3, NR>(fin, fout, eps, g, ph, nstrips, nchunks, res_a);
 }
 
 // Macroscopic fields of the current state (no collision, no store of
@@ -1953,7 +1960,8 @@ struct Member {
     int tile0;              // first position in the sweep tile list of its width
     int tile0_adj;          // first position in the adjoint tile list
     int tb_strips[2];       // strips of the two- and three-step passes
-    int tw0[2];             // first position in their wave lists
+    int tw0[3];             // first position in the wave lists of the two-step pass and
+                            // of the three-step pass in short and in tall chunks
 };
 
 template <typename R>
@@ -2031,8 +2039,9 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_sweep(const Member<R> *__res
 }
 
 // NS steps of every member in one pass (the multi-step pass, one wave per
-// strip and chunk of a member), from state slot src to state slot dst.
-template <typename S, typename R, int BX, bool WY, int NS>
+// strip and chunk of NR rows of a member, wave list Q), from state slot src to
+// state slot dst.
+template <typename S, typename R, int BX, bool WY, int NS, int NR, int Q>
 __device__ __forceinline__ void batch_multi_wave(const Member<R> *__restrict__ M,
                                                  const int *__restrict__ wmap, int nwaves,
                                                  int src, int dst, int res_a)
@@ -2044,8 +2053,8 @@ __device__ __forceinline__ void batch_multi_wave(const Member<R> *__restrict__ M
     const Geo g = d.g;
     Phys<R> ph = d.ph;
     ph.reservoir = 1;
-    const int local = wid - d.tw0[NS - 2], ns = d.tb_strips[NS - 2];
-    tb_wave<S, R, BX, WY, NS>(reinterpret_cast<const S *>(state_slot(d, src)),
+    const int local = wid - d.tw0[Q], ns = d.tb_strips[NS - 2];
+    tb_wave<S, R, BX, WY, NS, NR>(reinterpret_cast<const S *>(state_slot(d, src)),
                               reinterpret_cast<S *>(state_slot(d, dst)), d.eps, g, ph,
                               local % ns, local / ns, res_a);
 }
@@ -2055,15 +2064,18 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_tb2(const Member<R> *__restr
                                                         const int *__restrict__ wmap,
                                                         int nwaves, int src, int dst, int res_a)
 {
-    batch_multi_wave<S, R, BX, WY, 2>(M, wmap, nwaves, src, dst, res_a);
+    batch_multi_wave<S, R, BX, WY, 2, tb_rows<S, 2>(), 0>(M, wmap, nwaves, src, dst, res_a);
 }
 
-template <typename S, typename R, int BX, bool WY>
+// Three steps of every member: chunks of NR rows (wave list 1: the short
+// height, 2: the tall one).
+template <typename S, typename R, int BX, bool WY, int NR>
 __global__ __launch_bounds__(NTHREADS) void k_batch_tb3(const Member<R> *__restrict__ M,
                                                         const int *__restrict__ wmap,
                                                         int nwaves, int src, int dst, int res_a)
 {
-    batch_multi_wave<S, R, BX, WY, 3>(M, wmap, nwaves, src, dst, res_a);
+    batch_multi_wave<S, R, BX, WY, 3, NR, NR == tb_rows<S, 3>() ? 1 : 2>(M, wmap, nwaves, src,
+                                                                         dst, res_a);
 }
 
 // One reverse step of every member: adjoint slot a_next (of the state n + 1)
@@ -2110,6 +2122,8 @@ struct lbm_vans_handle {
     double *ring;           // [LBM_VANS_DIAG_RING][NRED]
     int64_t n;              // steps taken
     int64_t nrec;           // diagnostics records written
+    int rows3;              // rows per chunk of the three-step pass
+    int auto_pass;          // automatic most steps per pass
 };
 
 namespace {
@@ -2128,6 +2142,20 @@ int elem_bytes(int storage)
 long long geo_pitch(int Lx) { return (Lx + PITCH_ALIGN - 1LL) / PITCH_ALIGN * PITCH_ALIGN; }
 
 long long geo_plane(int Lx, int Ly) { return geo_pitch(Lx) * Ly; }
+
+// Chunk rows of the three-step pass a caller may ask for: 0 (automatic), the
+// short or the tall height with FP32 storage, the one height with FP16 storage.
+int check_pass_rows(int32_t rows, int32_t storage)
+{
+    if (rows == 0) return LBM_VANS_OK;
+    if (storage == LBM_F32_SHIFTED && (rows == tb_rows<float, 3>() || rows == LBM_VANS_TB3_TALL32))
+        return LBM_VANS_OK;
+    if (storage == LBM_F16_SHIFTED && rows == tb_rows<_Float16, 3>()) return LBM_VANS_OK;
+    return fail(LBM_VANS_EINVAL,
+                "pass_rows = %d: 0 (automatic); %d or %d with LBM_F32_SHIFTED storage; %d with "
+                "LBM_F16_SHIFTED storage",
+                rows, tb_rows<float, 3>(), LBM_VANS_TB3_TALL32, tb_rows<_Float16, 3>());
+}
 
 int check_params(const lbm_vans_params *p)
 {
@@ -2179,6 +2207,7 @@ int check_params(const lbm_vans_params *p)
     if (p->steps_per_pass < 0 || p->steps_per_pass > 3)
         return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2 or 3",
                     p->steps_per_pass);
+    if (check_pass_rows(p->pass_rows, p->storage)) return LBM_VANS_EINVAL;
     return LBM_VANS_OK;
 }
 
@@ -2333,31 +2362,119 @@ bool multi_fits(const Geo &g)
            static_cast<unsigned long long>(g.plane) * 4 < (1ull << 31);
 }
 
-// Waves of the ns-step pass (2 or 3) over a lattice of FP32 / FP16 storage.
-long long multi_waves(const lbm_vans_params *p, int ns)
+// Waves of the ns-step pass (2 or 3) over an Lx x Ly lattice in chunks of `rows`.
+long long waves_of(int Lx, int Ly, int ns, int rows)
 {
-    const bool f16 = p->storage == LBM_F16_SHIFTED;
     const int cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
-    const int rows = ns == 3 ? (f16 ? tb_rows<_Float16, 3>() : tb_rows<float, 3>())
-                             : (f16 ? tb_rows<_Float16, 2>() : tb_rows<float, 2>());
-    return static_cast<long long>((p->Lx + cols - 1) / cols) * ((p->Ly + rows - 1) / rows);
+    return static_cast<long long>((Lx + cols - 1) / cols) * ((Ly + rows - 1) / rows);
+}
+
+// f(integral_constant<int, BX>, integral_constant<bool, WY>) for the x ends (0
+// periodic, 1 walls, 2 open) and the y walls of a lattice.
+template <typename F>
+void with_bxwy(int bx, bool wy, F &&f)
+{
+    using F0 = std::false_type;
+    using T1 = std::true_type;
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
+    using B2 = std::integral_constant<int, 2>;
+    if (bx == 0 && !wy) f(B0{}, F0{});
+    else if (bx == 0) f(B0{}, T1{});
+    else if (bx == 1 && !wy) f(B1{}, F0{});
+    else if (bx == 1) f(B1{}, T1{});
+    else if (!wy) f(B2{}, F0{});
+    else f(B2{}, T1{});
+}
+
+// Waves of the three-step kernel (lone, or batched) in chunks of `rows` that the
+// chip holds at once: its workgroups per compute unit (registers decide: the
+// periodic FP32 kernel holds two waves per SIMD, the kernels with walls four)
+// times the waves per workgroup and the compute units.
+int tb3_resident(int storage, int bx, bool wy, int rows, bool batch, long long *out)
+{
+    int nb = 0, dev = 0, ncu = 0;
+    hipError_t e = hipSuccess;
+    auto q = [&](auto ker) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ker, NTHREADS, 0); };
+    with_bxwy(bx, wy, [&](auto bxc, auto wyc) {
+        constexpr int BXV = decltype(bxc)::value;
+        constexpr bool WYV = decltype(wyc)::value;
+        if (storage == LBM_F16_SHIFTED) {
+            constexpr int NR = tb_rows<_Float16, 3>();
+            if (batch) q(k_batch_tb3<_Float16, float, BXV, WYV, NR>);
+            else q(k_sweep_tb3<_Float16, float, BXV, WYV, NR>);
+        } else if (rows == LBM_VANS_TB3_TALL32) {
+            constexpr int NR = LBM_VANS_TB3_TALL32;
+            if (batch) q(k_batch_tb3<float, float, BXV, WYV, NR>);
+            else q(k_sweep_tb3<float, float, BXV, WYV, NR>);
+        } else {
+            constexpr int NR = tb_rows<float, 3>();
+            if (batch) q(k_batch_tb3<float, float, BXV, WYV, NR>);
+            else q(k_sweep_tb3<float, float, BXV, WYV, NR>);
+        }
+    });
+    HIP_TRY(e);
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    *out = static_cast<long long>(nb) * NW * ncu;
+    return LBM_VANS_OK;
+}
+
+// Automatic choices of the multi-step passes, measured on MI355X (FP32 GLUPS,
+// pairs / three steps in 24-row / in 28-row chunks; periodic box: 1024^2 102.9 /
+// 98.8 / 83.7, 2048 x 1024 127.7 / 145.2 / 129.2, 2048^2 110.9 / 149.0 / 139.3,
+// 4096^2 106.7 / 160.5 / 163.2; open channel with walls: 2048 x 1024 121.3 / 98.1 /
+// 77.5, 2048^2 107.3 / 137.4 / 111.7, 4096^2 105.3 / 149.8 / 146.8).  A
+// three-step wave walks its chunk's rows one after another, so the pass needs
+// most of the chip's resident waves at once: three steps when the lattice has at
+// least 0.7 times as many waves as the chip holds of that kernel; the tall chunks
+// (fewer halo rows) only with four times as many; else two steps when the
+// two-step pass has >= 2048 waves (open channel, GLUPS at one / two steps per
+// pass: 1024 x 512 56.6 / 56.5; 2048 x 1024 69.1 / 121.1), else one.
+constexpr int TALL_FILL = 4;                // tall chunks: waves >= 4 x resident
+constexpr int TRIPLE_FILL_10 = 7;           // three steps: waves >= 0.7 x resident
+
+bool tall_auto(long long tall_waves, long long resident)
+{
+    return tall_waves >= TALL_FILL * resident;
+}
+
+int choose_passes(lbm_vans_handle *h)
+{
+    const lbm_vans_params *p = &h->p;
+    h->rows3 = tb_rows<float, 3>();
+    h->auto_pass = 1;
+    if (p->storage == LBM_F64 || !multi_fits(h->g)) return LBM_VANS_OK;
+    const int bx = h->g.open_x ? 2 : (h->g.wall_x ? 1 : 0);
+    const bool f16 = p->storage == LBM_F16_SHIFTED;
+    long long res = 0;
+    int rc;
+    if (f16) {
+        h->rows3 = tb_rows<_Float16, 3>();
+    } else if (p->pass_rows != 0) {
+        h->rows3 = p->pass_rows;
+    } else {
+        rc = tb3_resident(p->storage, bx, h->g.wall_y, LBM_VANS_TB3_TALL32, false, &res);
+        if (rc) return rc;
+        if (tall_auto(waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32), res))
+            h->rows3 = LBM_VANS_TB3_TALL32;
+    }
+    rc = tb3_resident(p->storage, bx, h->g.wall_y, h->rows3, false, &res);
+    if (rc) return rc;
+    if (10 * waves_of(p->Lx, p->Ly, 3, h->rows3) >= TRIPLE_FILL_10 * res)
+        h->auto_pass = 3;
+    else if (waves_of(p->Lx, p->Ly, 2, f16 ? tb_rows<_Float16, 2>() : tb_rows<float, 2>()) >= 2048)
+        h->auto_pass = 2;
+    return LBM_VANS_OK;
 }
 
 // Most time steps one pass may take: 2 or 3 with the multi-step passes (FP32 and
-// FP16 storage), else 1.  Automatic: three when the three-step pass has waves to
-// fill the chip (>= 4096, 16 per compute unit), two when the two-step pass has
-// >= 2048, else one: a multi-step pass walks the rows of each chunk one after
-// another, so on a small lattice its launch is long and the chip half empty
-// (open channel, GLUPS at one / two / three steps per pass: 256 x 128 5.7 / 5.1 /
-// 3.2; 1024 x 512 56.6 / 56.5 / 48.3; 2048 x 1024 69.1 / 121.1 / 114.0;
-// 4096 x 2048 78.8 / 103.0 / 146.7).
+// FP16 storage), else 1.
 int max_pass(const lbm_vans_handle *h)
 {
     if (h->p.storage == LBM_F64 || !multi_fits(h->g)) return 1;
     if (h->p.steps_per_pass != 0) return h->p.steps_per_pass;
-    if (multi_waves(&h->p, 3) >= 4096) return 3;
-    if (multi_waves(&h->p, 2) >= 2048) return 2;
-    return 1;
+    return h->auto_pass;
 }
 
 // NS (2 or 3) time steps in one pass, from the state n in src into dst.
@@ -2371,7 +2488,7 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
             return fail(LBM_VANS_EINVAL, "multi-step pass needs FP32 or FP16 storage");
         } else {
             const int cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
-            const int rows = ns == 3 ? tb_rows<S, 3>() : tb_rows<S, 2>();
+            const int rows = ns == 3 ? h->rows3 : tb_rows<S, 2>();
             const int nstrips = (h->p.Lx + cols - 1) / cols;
             const int nchunks = (h->p.Ly + rows - 1) / rows;
             const long long waves = (long long)nstrips * nchunks;
@@ -2382,24 +2499,25 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
             ph.reservoir = 1;                     // the later steps start from n + 1 >= 1
             const int res_a = h->n >= 1;
             const int bx = h->g.open_x ? 2 : (h->g.wall_x ? 1 : 0);
-#define LBM_VANS_TBK(KER, BXV, WYV)                                                             \
-    hipLaunchKernelGGL((KER<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, h->stream,        \
-                       (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph, nstrips, nchunks, \
-                       res_a)
-#define LBM_VANS_TBX(KER)                                                                       \
-    if (bx == 0 && !h->g.wall_y) LBM_VANS_TBK(KER, 0, false);                                   \
-    else if (bx == 0) LBM_VANS_TBK(KER, 0, true);                                               \
-    else if (bx == 1 && !h->g.wall_y) LBM_VANS_TBK(KER, 1, false);                              \
-    else if (bx == 1) LBM_VANS_TBK(KER, 1, true);                                               \
-    else if (!h->g.wall_y) LBM_VANS_TBK(KER, 2, false);                                         \
-    else LBM_VANS_TBK(KER, 2, true)
-            if (ns == 3) {
-                LBM_VANS_TBX(k_sweep_tb3);
-            } else {
-                LBM_VANS_TBX(k_sweep_tb2);
-            }
-#undef LBM_VANS_TBX
-#undef LBM_VANS_TBK
+            with_bxwy(bx, h->g.wall_y, [&](auto bxc, auto wyc) {
+                constexpr int BXV = decltype(bxc)::value;
+                constexpr bool WYV = decltype(wyc)::value;
+                auto run = [&](auto ker) {
+                    hipLaunchKernelGGL(ker, dim3(grid), dim3(NTHREADS), 0, h->stream,
+                                       (const S *)src, (S *)dst, (const R *)h->eps, h->g, ph,
+                                       nstrips, nchunks, res_a);
+                };
+                if (ns == 2) {
+                    run(k_sweep_tb2<S, R, BXV, WYV>);
+                } else if constexpr (std::is_same_v<S, float>) {
+                    if (rows == LBM_VANS_TB3_TALL32)
+                        run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_TALL32>);
+                    else
+                        run(k_sweep_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
+                } else {
+                    run(k_sweep_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
+                }
+            });
             return check_launch(ns == 3 ? "k_sweep_tb3" : "k_sweep_tb2");
         }
     });
@@ -2509,6 +2627,7 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
         HIP_TRY(hipStreamSynchronize(h->stream));
         return LBM_VANS_OK;
     });
+    if (!rc) rc = choose_passes(h);
     if (rc) {
         delete h;
         return rc;
@@ -2843,29 +2962,46 @@ struct lbm_vans_batch {
     size_t desc_bytes = 0;          // bytes of one device descriptor
     std::vector<char> desc;         // host image of the descriptors
     std::vector<int> tmap, tmap_adj;  // tile lists of the sweep and of the adjoint
-    std::vector<int> wmap[2];         // wave lists of the two- and three-step passes
+    std::vector<int> wmap[3];         // wave lists of the two-step pass and of the three-step
+                                      // pass in short and in tall chunks (FP32 only)
     void *d_desc = nullptr;
-    int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap[2] = {nullptr, nullptr};
-    int ntiles = 0, ntiles_adj = 0, nwaves[2] = {0, 0};
+    int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap[3] = {nullptr, nullptr, nullptr};
+    int ntiles = 0, ntiles_adj = 0, nwaves[3] = {0, 0, 0};
     bool multi_ok = true;           // every member fits the multi-step passes' addressing
+    long long tall_resident = 0;    // waves of the tall batched three-step kernel the chip holds
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // chunk of cfg.graph_steps steps from slot 0 / 1
 };
 
 namespace {
 
-size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, size_t nwaves2,
-                         size_t nwaves3)
+size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, const size_t *nwaves)
 {
     const size_t d = storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
     return align256(nmembers * d) + 2 * align256(ntiles_adj * sizeof(int)) +
-           align256(nwaves2 * sizeof(int)) + align256(nwaves3 * sizeof(int));
+           align256(nwaves[0] * sizeof(int)) + align256(nwaves[1] * sizeof(int)) +
+           align256(nwaves[2] * sizeof(int));
 }
 
-// Waves of the ns-step pass over one member (0 in FP64, which has no such pass).
-size_t tb_waves(const lbm_vans_params *p, int ns)
+// Waves of one member in wave list q: the two-step pass (0), the three-step pass
+// in short (1) and in tall chunks (2; FP32 storage only); none in FP64, which has
+// no such pass.
+size_t batch_waves(const lbm_vans_params *p, int q)
 {
     if (p->storage == LBM_F64) return 0;
-    return static_cast<size_t>(multi_waves(p, ns));
+    const bool f16 = p->storage == LBM_F16_SHIFTED;
+    if (q == 0) return waves_of(p->Lx, p->Ly, 2, f16 ? tb_rows<_Float16, 2>() : tb_rows<float, 2>());
+    if (q == 1) return waves_of(p->Lx, p->Ly, 3, f16 ? tb_rows<_Float16, 3>() : tb_rows<float, 3>());
+    return f16 ? 0 : waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32);
+}
+
+// The batched three-step pass runs in tall chunks (FP32 storage): as configured, or
+// automatically as for a lone lattice (waves of the whole batch against what the
+// chip holds of the batched kernel).
+bool batch_tall(const lbm_vans_batch *b)
+{
+    if (b->storage != LBM_F32_SHIFTED) return false;
+    if (b->cfg.pass_rows != 0) return b->cfg.pass_rows == LBM_VANS_TB3_TALL32;
+    return tall_auto(b->nwaves[2], b->tall_resident);
 }
 
 void drop_graphs(lbm_vans_batch *b)
@@ -2884,8 +3020,7 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
     const size_t nm = b->m.size();
     b->tmap.clear();
     b->tmap_adj.clear();
-    b->wmap[0].clear();
-    b->wmap[1].clear();
+    for (auto &wm : b->wmap) wm.clear();
     int rc = with_types(b->storage, [&](auto *sp, auto *rp) -> int {
         using R = std::remove_pointer_t<decltype(rp)>;
         (void)sp;
@@ -2908,11 +3043,11 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             d.tile0_adj = static_cast<int>(b->tmap_adj.size());
             b->tmap.insert(b->tmap.end(), d.gs.ntiles, static_cast<int>(k));
             b->tmap_adj.insert(b->tmap_adj.end(), d.g.ntiles, static_cast<int>(k));
-            for (int q = 0; q < 2; q++) {
+            for (int q = 0; q < 3; q++) {
                 const int cols = q ? tb_cols<3>() : tb_cols<2>();
-                d.tb_strips[q] = (h->p.Lx + cols - 1) / cols;
+                if (q < 2) d.tb_strips[q] = (h->p.Lx + cols - 1) / cols;
                 d.tw0[q] = static_cast<int>(b->wmap[q].size());
-                b->wmap[q].insert(b->wmap[q].end(), tb_waves(&h->p, q + 2), static_cast<int>(k));
+                b->wmap[q].insert(b->wmap[q].end(), batch_waves(&h->p, q), static_cast<int>(k));
             }
         }
         size_t off = 0;
@@ -2936,15 +3071,14 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
     if (rc) return rc;
     b->ntiles = static_cast<int>(b->tmap.size());
     b->ntiles_adj = static_cast<int>(b->tmap_adj.size());
-    b->nwaves[0] = static_cast<int>(b->wmap[0].size());
-    b->nwaves[1] = static_cast<int>(b->wmap[1].size());
+    for (int q = 0; q < 3; q++) b->nwaves[q] = static_cast<int>(b->wmap[q].size());
     HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size(), hipMemcpyHostToDevice,
                            b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap, b->tmap.data(), b->tmap.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap_adj, b->tmap_adj.data(), b->tmap_adj.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
-    for (int q = 0; q < 2; q++)
+    for (int q = 0; q < 3; q++)
         if (!b->wmap[q].empty())
             HIP_TRY(hipMemcpyAsync(b->d_wmap[q], b->wmap[q].data(),
                                    b->wmap[q].size() * sizeof(int), hipMemcpyHostToDevice,
@@ -3002,28 +3136,30 @@ int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, 
         } else {
             if (!b->multi_ok)
                 return fail(LBM_VANS_EINVAL, "a member is too large for the multi-step pass");
-            const int q = ns == 3 ? 1 : 0;
+            const bool tall = ns == 3 && batch_tall(b);
+            const int q = ns == 3 ? (tall ? 2 : 1) : 0;
             const int n = b->nwaves[q];
             const int grid = (n + NW - 1) / NW;
             const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
             const int *wm = b->d_wmap[q];
-#define LBM_VANS_BATCH(KER, BXV, WYV)                                                          \
-    hipLaunchKernelGGL((KER<S, R, BXV, WYV>), dim3(grid), dim3(NTHREADS), 0, st, M, wm, n, src, \
-                       dst, res_a)
-#define LBM_VANS_BATCHX(KER)                                                                   \
-    if (b->bx == 0 && !b->wy) LBM_VANS_BATCH(KER, 0, false);                                   \
-    else if (b->bx == 0) LBM_VANS_BATCH(KER, 0, true);                                         \
-    else if (b->bx == 1 && !b->wy) LBM_VANS_BATCH(KER, 1, false);                              \
-    else if (b->bx == 1) LBM_VANS_BATCH(KER, 1, true);                                         \
-    else if (!b->wy) LBM_VANS_BATCH(KER, 2, false);                                            \
-    else LBM_VANS_BATCH(KER, 2, true)
-            if (ns == 3) {
-                LBM_VANS_BATCHX(k_batch_tb3);
-            } else {
-                LBM_VANS_BATCHX(k_batch_tb2);
-            }
-#undef LBM_VANS_BATCHX
-#undef LBM_VANS_BATCH
+            with_bxwy(b->bx, b->wy, [&](auto bxc, auto wyc) {
+                constexpr int BXV = decltype(bxc)::value;
+                constexpr bool WYV = decltype(wyc)::value;
+                auto run = [&](auto ker) {
+                    hipLaunchKernelGGL(ker, dim3(grid), dim3(NTHREADS), 0, st, M, wm, n, src, dst,
+                                       res_a);
+                };
+                if (ns == 2) {
+                    run(k_batch_tb2<S, R, BXV, WYV>);
+                } else if constexpr (std::is_same_v<S, float>) {
+                    if (tall)
+                        run(k_batch_tb3<S, R, BXV, WYV, LBM_VANS_TB3_TALL32>);
+                    else
+                        run(k_batch_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
+                } else {
+                    run(k_batch_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
+                }
+            });
             return check_launch(ns == 3 ? "k_batch_tb3" : "k_batch_tb2");
         }
     });
@@ -3112,7 +3248,7 @@ int check_config(const lbm_vans_batch *b, const lbm_vans_batch_config *c)
     if (c->steps_per_pass < 0 || c->steps_per_pass > 3)
         return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2 or 3",
                     c->steps_per_pass);
-    return LBM_VANS_OK;
+    return check_pass_rows(c->pass_rows, b->storage);
 }
 
 // The members must still be in step with each other (a member may have been
@@ -3144,14 +3280,13 @@ extern "C" {
 size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembers)
 {
     if (!members || nmembers < 1) return 0;
-    size_t tiles = 0, waves2 = 0, waves3 = 0;
+    size_t tiles = 0, waves[3] = {0, 0, 0};
     for (int32_t k = 0; k < nmembers; k++) {
         if (!members[k]) return 0;
         tiles += static_cast<size_t>(members[k]->g.ntiles);
-        waves2 += tb_waves(&members[k]->p, 2);
-        waves3 += tb_waves(&members[k]->p, 3);
+        for (int q = 0; q < 3; q++) waves[q] += batch_waves(&members[k]->p, q);
     }
-    return batch_table_bytes(members[0]->p.storage, nmembers, tiles, waves2, waves3);
+    return batch_table_bytes(members[0]->p.storage, nmembers, tiles, waves);
 }
 
 int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
@@ -3163,7 +3298,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     if (!members || nmembers < 1) return fail(LBM_VANS_EINVAL, "no members");
     const lbm_vans_handle *h0 = members[0];
     if (!h0) return fail(LBM_VANS_EINVAL, "member 0 is NULL");
-    size_t tiles = 0, waves = 0, waves3 = 0;
+    size_t tiles = 0, waves[3] = {0, 0, 0};
     for (int32_t k = 0; k < nmembers; k++) {
         const lbm_vans_handle *h = members[k];
         if (!h) return fail(LBM_VANS_EINVAL, "member %d is NULL", k);
@@ -3179,17 +3314,16 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
             return fail(LBM_VANS_EINVAL, "member %d is at step %lld, member 0 at %lld", k,
                         (long long)h->n, (long long)h0->n);
         tiles += static_cast<size_t>(h->g.ntiles);
-        waves += tb_waves(&h->p, 2);
-        waves3 += tb_waves(&h->p, 3);
+        for (int q = 0; q < 3; q++) waves[q] += batch_waves(&h->p, q);
     }
     if (tiles > static_cast<size_t>(INT32_MAX))
         return fail(LBM_VANS_EINVAL, "%zu tiles: too many for one launch", tiles);
-    if (std::max(waves, waves3) > static_cast<size_t>(INT32_MAX - NW))
-        return fail(LBM_VANS_EINVAL, "%zu waves: too many for one launch",
-                    std::max(waves, waves3));
+    const size_t wmax = std::max({waves[0], waves[1], waves[2]});
+    if (wmax > static_cast<size_t>(INT32_MAX - NW))
+        return fail(LBM_VANS_EINVAL, "%zu waves: too many for one launch", wmax);
     if (!work || reinterpret_cast<uintptr_t>(work) % 256)
         return fail(LBM_VANS_EINVAL, "work must be a 256-byte aligned device buffer");
-    const size_t need = batch_table_bytes(h0->p.storage, nmembers, tiles, waves, waves3);
+    const size_t need = batch_table_bytes(h0->p.storage, nmembers, tiles, waves);
     if (work_bytes < need)
         return fail(LBM_VANS_EINVAL, "work has %zu bytes, %zu needed", work_bytes, need);
 
@@ -3208,21 +3342,24 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     b->d_tmap = reinterpret_cast<int *>(w + align256(nmembers * dsz));
     b->d_tmap_adj = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
                                             align256(tiles * sizeof(int)));
-    b->d_wmap[0] = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
-                                           2 * align256(tiles * sizeof(int)));
-    b->d_wmap[1] = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
-                                           2 * align256(tiles * sizeof(int)) +
-                                           align256(waves * sizeof(int)));
+    size_t off = align256(nmembers * dsz) + 2 * align256(tiles * sizeof(int));
+    for (int q = 0; q < 3; q++) {
+        b->d_wmap[q] = reinterpret_cast<int *>(w + off);
+        off += align256(waves[q] * sizeof(int));
+    }
     b->cfg.vec = b->vmax;
     b->cfg.grid = 0;
     b->cfg.graph_steps = 24;
     b->cfg.steps_per_pass = 0;
+    b->cfg.pass_rows = 0;
     int rc = LBM_VANS_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&b->ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&b->ev[1]);
     if (e != hipSuccess) rc = fail(LBM_VANS_EHIP, "stream / event creation failed: %s",
                                    hipGetErrorString(e));
+    if (!rc && b->storage == LBM_F32_SHIFTED && b->multi_ok)
+        rc = tb3_resident(b->storage, b->bx, b->wy, LBM_VANS_TB3_TALL32, true, &b->tall_resident);
     if (!rc) rc = batch_upload(b, b->cfg.vec, nullptr, 0, 1);
     if (rc) {
         lbm_vans_batch_destroy(b);

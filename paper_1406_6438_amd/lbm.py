@@ -27,7 +27,7 @@ F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
 DRAG_ERGUN, DRAG_CONST = 0, 1
 NDIAG = 8
 DIAG_RING = 4096
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
@@ -55,17 +55,19 @@ class LbmVansParams(ctypes.Structure):
         ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double),
         ("u_wall", ctypes.c_double * 2),
         ("sweep_vec", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
+        ("pass_rows", ctypes.c_int32),
     ]
 
 
 class LbmVansBatchConfig(ctypes.Structure):
     _fields_ = [("vec", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("graph_steps", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
-                ("us_per_step", ctypes.c_double)]
+                ("pass_rows", ctypes.c_int32), ("us_per_step", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {"vec": self.vec, "grid": self.grid, "graph_steps": self.graph_steps,
-                "steps_per_pass": self.steps_per_pass, "us_per_step": self.us_per_step}
+                "steps_per_pass": self.steps_per_pass, "pass_rows": self.pass_rows,
+                "us_per_step": self.us_per_step}
 
 
 @dataclasses.dataclass
@@ -93,6 +95,7 @@ class Params:
     u_wall: tuple = (0.0, 0.0)
     sweep_vec: int = 0      # nodes per lane of the one-step sweep, 0 = automatic
     steps_per_pass: int = 0  # most steps per pass: 0 = automatic (3), 1, 2 or 3
+    pass_rows: int = 0       # rows per chunk of the three-step pass: 0 = automatic, 24, 28
 
     def c(self) -> LbmVansParams:
         return LbmVansParams(self.Lx, self.Ly, self.bc_x, self.bc_y, self.storage, self.drag,
@@ -101,7 +104,7 @@ class Params:
                              (ctypes.c_double * 2)(*self.u0), self.fp16_scale_log2,
                              self.diag_every, self.rho_in, self.u_in, self.rho_out, self.u_out,
                              (ctypes.c_double * 2)(*self.u_wall), self.sweep_vec,
-                             self.steps_per_pass)
+                             self.steps_per_pass, self.pass_rows)
 
 
 class LbmVansError(RuntimeError):
@@ -270,8 +273,9 @@ def lbm_vans_batch_create(members, work, stream) -> ctypes.c_void_p:
     return b
 
 
-def lbm_vans_batch_configure(b, vec: int, grid: int, graph_steps: int, steps_per_pass: int = 0):
-    c = LbmVansBatchConfig(vec, grid, graph_steps, steps_per_pass, 0.0)
+def lbm_vans_batch_configure(b, vec: int, grid: int, graph_steps: int, steps_per_pass: int = 0,
+                             pass_rows: int = 0):
+    c = LbmVansBatchConfig(vec, grid, graph_steps, steps_per_pass, pass_rows, 0.0)
     _check(load().lbm_vans_batch_configure(b, ctypes.byref(c)))
 
 
@@ -422,10 +426,12 @@ class Batch:
             self.stream = torch.cuda.current_stream(self.device)
             self.b = lbm_vans_batch_create(self.members, self.work, self.stream.cuda_stream)
 
-    def configure(self, vec: int, grid: int = 0, graph_steps: int = 24, steps_per_pass: int = 0):
+    def configure(self, vec: int, grid: int = 0, graph_steps: int = 24, steps_per_pass: int = 0,
+                  pass_rows: int = 0):
         """steps_per_pass: most steps per launch (0 = automatic: 3 with FP32 / FP16
-        storage; 1, 2 or 3)."""
-        lbm_vans_batch_configure(self.b, vec, grid, graph_steps, steps_per_pass)
+        storage; 1, 2 or 3); pass_rows: rows per chunk of the three-step pass (0 =
+        automatic; 24 or 28 with FP32 storage)."""
+        lbm_vans_batch_configure(self.b, vec, grid, graph_steps, steps_per_pass, pass_rows)
 
     @property
     def config(self) -> dict:

@@ -36,6 +36,7 @@ class Spec:
     u_wall: tuple = (0.0, 0.0)      # sliding y-walls: x-velocity below, above
     sweep_vec: int = 0              # one-step sweep width (0 = automatic)
     steps_per_pass: int = 0         # most steps per pass: 0 = automatic (3), 1, 2, 3
+    pass_rows: int = 0              # rows per chunk of the three-step pass: 0 = automatic
 
     def oracle(self) -> oracle.Params:
         return oracle.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
@@ -61,7 +62,8 @@ class Spec:
                           fp16_scale_log2=self.fp16_scale_log2, diag_every=self.diag_every,
                           rho_in=self.rho_in, u_in=self.u_in, rho_out=self.rho_out,
                           u_out=self.u_out, u_wall=tuple(self.u_wall),
-                          sweep_vec=self.sweep_vec, steps_per_pass=self.steps_per_pass)
+                          sweep_vec=self.sweep_vec, steps_per_pass=self.steps_per_pass,
+                          pass_rows=self.pass_rows)
 
     def input_eps(self, eps: np.ndarray) -> np.ndarray:
         """The porosity both sides receive: rounded once to the GPU's compute precision."""
@@ -71,15 +73,18 @@ class Spec:
 
 
 # Execution paths of lbm_vans_step: "auto" (the library's choice: on the small test
-# grids the widest one-step sweep), "triples" (three steps per pass), "pairs" (at most
-# two steps per pass), "wide" (one step per pass, widest vector width) and "narrow"
-# (one step per pass, one node per lane), so that the test grids cover every sweep
-# kernel.
+# grids the widest one-step sweep), "triples" (three steps per pass, the short chunks
+# the small grids get), "tall" (three steps per pass in 28-row chunks: FP32 storage;
+# the FP16 pass has one height), "pairs" (at most two steps per pass), "wide" (one
+# step per pass, widest vector width) and "narrow" (one step per pass, one node per
+# lane), so that the test grids cover every sweep kernel.
 def exec_mode(mode: str, storage: str) -> dict:
     if mode == "auto":
         return {}
     if mode == "triples":
         return {"steps_per_pass": 3}
+    if mode == "tall":
+        return {"steps_per_pass": 3, "pass_rows": 28 if storage == "f32" else 0}
     if mode == "pairs":
         return {"steps_per_pass": 2}
     if mode == "wide":

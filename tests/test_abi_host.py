@@ -70,6 +70,8 @@ def test_work_bytes_scale_with_storage():
     dict(Lx=65536, Ly=65536), dict(u_wall=(0.01, 0.0)), dict(bc_y=1, u_wall=(math.nan, 0.0)),
     dict(sweep_vec=3), dict(sweep_vec=4, storage=lbm.F64), dict(sweep_vec=2),
     dict(steps_per_pass=4), dict(steps_per_pass=-1),
+    dict(pass_rows=16), dict(pass_rows=-24), dict(pass_rows=28, storage=lbm.F16_SHIFTED),
+    dict(pass_rows=24, storage=lbm.F64),
 ])
 def test_invalid_params_rejected_without_gpu(bad):
     kw = dict(Lx=16, Ly=8, tau=0.7, d_p=10.0)
@@ -123,7 +125,7 @@ def test_null_batch_calls_fail_cleanly():
     assert L.lbm_vans_batch_work_bytes(no_members, 2) == 0
     assert L.lbm_vans_batch_create(no_members, 2, None, 0, None, ctypes.byref(out)) == lbm.EINVAL
     assert b"NULL" in L.lbm_vans_last_error()
-    cfg = lbm.LbmVansBatchConfig(4, 0, 16, 0, 0.0)
+    cfg = lbm.LbmVansBatchConfig(4, 0, 16, 0, 0, 0.0)
     assert L.lbm_vans_batch_configure(None, ctypes.byref(cfg)) == lbm.EINVAL
     assert L.lbm_vans_batch_get_config(None, ctypes.byref(cfg)) == lbm.EINVAL
     assert L.lbm_vans_batch_tune(None, 3, None, None, 0, None) == lbm.EINVAL

@@ -138,6 +138,34 @@ def _launch_plan(nsteps, graph_steps, max_pass):
     return tuple(plan)
 
 
+@pytest.mark.parametrize("rows", [24, 28])
+@pytest.mark.parametrize("bc", ["periodic", "walls", "open_walls"])
+def test_batch_three_step_chunk_heights(bc, rows):
+    """The batched three-step pass in chunks of 24 and of 28 rows (FP32) on members
+    tall enough for several chunks (the last one short): against the oracle and
+    against each member run alone in chunks of the same height, 13 steps."""
+    from paper_1406_6438_amd import lbm
+    members = _member_specs("f32", bc, sizes=[(96, 61), (130, 75), (67, 30), (5, 6)])
+    nsteps = 13
+    say(f"[batch chunk rows {rows} {bc}]")
+    sv = _solvers(members)
+    b = lbm.Batch(sv)
+    b.configure(4, 0, 0, 3, rows)
+    assert b.config["pass_rows"] == rows
+    b.step(nsteps)
+    fb = _states(sv)
+    b.close()
+    _close(sv)
+    for (spec, eps), f in zip(members, fb):
+        mo, fo = oracle_run(spec, eps, nsteps)
+        bound = _bound(spec, eps, fo, nsteps)
+        assert np.abs(f - fo).max() <= bound
+        _, fl = gpu_run(dataclasses.replace(spec, steps_per_pass=3, pass_rows=rows), eps, nsteps)
+        say(f"  {spec.Lx}x{spec.Ly}: max |f - f_oracle| {np.abs(f - fo).max():.3e} (bound "
+            f"{bound:.3e}); lone run same bits {np.array_equal(f, fl)}")
+        assert np.abs(f - fl).max() <= bound
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
 def test_every_launch_shape(storage):
     """vec 4/2/1, one workgroup per tile or persistent grids, with and without
@@ -246,7 +274,7 @@ def test_batch_rejects_mismatched_members_and_out_of_step_members():
         lbm.Batch([diag, c])
     b = lbm.Batch([a, c])
     for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16), (4, 0, 16, 4),
-                (4, 0, 16, -1)):
+                (4, 0, 16, -1), (4, 0, 16, 3, 16), (4, 0, 16, 3, -28)):
         with pytest.raises(lbm.LbmVansError):
             b.configure(*cfg)
     a.step(1)                       # a member stepped on its own

@@ -82,7 +82,7 @@ def test_f64_parity_small_grids(geom, mode):
     assert np.abs(mg["rho"] - mo["rho"]).max() <= 1e-13
 
 
-@pytest.mark.parametrize("mode", ["auto", "triples", "pairs", "wide", "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "triples", "tall", "pairs", "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f32_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
@@ -378,23 +378,29 @@ def test_f16_full_size_box_sampled_windows():
 TB_GEOMS = [(70, 40, "periodic", False), (130, 33, "periodic", True), (5, 7, "periodic", True),
             (1, 3, "periodic", False), (300, 1, "periodic", False), (64, 32, "periodic", True),
             (70, 21, "walls", True), (63, 9, "walls", False), (2, 5, "walls", True),
-            (130, 17, "open", True), (62, 6, "open", False), (3, 4, "open", True)]
+            (130, 17, "open", True), (62, 6, "open", False), (3, 4, "open", True),
+            # several chunks of 24 and of 28 rows, the last one short
+            (64, 90, "periodic", False), (70, 61, "walls", True), (130, 75, "open", True)]
 
 
-@pytest.mark.parametrize("per_pass", [2, 3])
+@pytest.mark.parametrize("per_pass, rows", [(2, 0), (3, 0), (3, 28)],
+                         ids=["pairs", "triples", "triples_28rows"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("geom", TB_GEOMS, ids=lambda g: "%dx%d_%s_wy%d" % g)
-def test_multi_step_pass_matches_oracle_and_single_steps(geom, storage, per_pass):
-    """Two or three steps per pass against the oracle and against one step per call;
-    step counts that leave a shorter last pass (2, 7: 3+3+1 or 2+2+2+1) and that do not."""
+def test_multi_step_pass_matches_oracle_and_single_steps(geom, storage, per_pass, rows):
+    """Two or three steps per pass (three in chunks of the automatic height or of 28
+    rows, FP32) against the oracle and against one step per call; step counts that
+    leave a shorter last pass (2, 7: 3+3+1 or 2+2+2+1) and that do not."""
     from paper_1406_6438_amd import lbm
+    if rows and storage != "f32":
+        pytest.skip("the FP16 three-step pass has one chunk height")
     Lx, Ly, bx, wy = geom
-    say(f"[{per_pass}-step pass {storage}] {Lx}x{Ly} x={bx} walls_y={wy}")
+    say(f"[{per_pass}-step pass {storage} rows {rows or 'auto'}] {Lx}x{Ly} x={bx} walls_y={wy}")
     spec = Spec(Lx=Lx, Ly=Ly, tau=0.62, walls_x=bx == "walls", open_x=bx == "open",
                 walls_y=wy, d_p=6.0, G=(0.0, 0.0) if bx == "open" else (2e-5, -1e-5),
                 u0=(0.01, 0.004), rho_in=1.01, u_in=0.02, rho_out=0.99, u_out=0.015,
                 u_wall=(0.0, 0.03) if wy else (0.0, 0.0), storage=storage,
-                steps_per_pass=per_pass)
+                steps_per_pass=per_pass, pass_rows=rows)
     eps = W.grf_porosity(Lx, Ly, seed=900 + Lx, ell=2.5, lo=0.35, hi=1.0)
     for nsteps in (2, 3, 7, 40):
         mg, fg = gpu_run(spec, eps, nsteps)

@@ -196,18 +196,12 @@ def crop_sample(w, lbm, steps: int):
     return gpu, job
 
 
-def steps_per_launch(w) -> int:
-    """Steps one sweep launch advances: the library runs three steps in one pass
-    (k_sweep_tb3) for FP32 / FP16 storage, one step per launch (k_sweep_vec) for
-    FP64."""
-    return 3 if w.storage != "f64" else 1
-
-
 def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0):
     """(seconds on the library's stream for `steps` steps, final diagnostics record,
-    porosity, seconds per step when every step is its own launch or None).  The
-    second timing calls lbm_vans_step with one step per call, so every step is one
-    single-step launch (k_sweep_vec)."""
+    porosity, seconds per step when every step is its own launch or None, the
+    library's launch plan: most steps per pass and rows per chunk of the three-step
+    pass).  The second timing calls lbm_vans_step with one step per call, so every
+    step is one single-step launch (k_sweep_vec)."""
     eps = w.porosity()
     s = lbm.Solver(lbm_params(w, lbm), cast_eps(eps, w.storage))
     log(f"[bench] {w.name}: warmup {warmup} steps")
@@ -231,12 +225,14 @@ def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0):
         torch.cuda.synchronize()
         single = e0.elapsed_time(e1) / 1e3 / single_steps
     diag = s.moments()["diag"]
+    plan = s.pass_plan
     s.close()
     del s
     torch.cuda.empty_cache()
     log(f"[bench] {w.name}: {steps} steps in {gpu_s * 1e3:.2f} ms (events), {wall * 1e3:.2f} ms (wall)"
-        + (f"; one step per launch: {single * 1e6:.1f} us/step" if single else ""))
-    return gpu_s, diag, eps, single
+        + (f"; one step per launch: {single * 1e6:.1f} us/step" if single else "")
+        + f"; plan {plan}")
+    return gpu_s, diag, eps, single, plan
 
 
 def adjoint_params(lbm, w, Lx=None, Ly=None):
@@ -357,7 +353,7 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
     t_plain = timed(steps)
     b.configure(best["vec"], best["grid"], best["graph_steps"], best["steps_per_pass"],
                 best["pass_rows"])
-    spl = best["steps_per_pass"] or 3
+    spl, rows = b.pass_plan
     bpn = algorithmic_bytes_per_node("f32")
     # algorithmic bytes per node-step over the time per step (= per launch / steps per launch)
     ach = bpn * cells / (t_graph / steps) / 1e9
@@ -373,7 +369,7 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
                                     if (spl > 1 or best["vec"] == 4) and len(members) == 64
                                     else None),
                         "kernel": BATCH_KERNEL[spl],
-                        "steps_per_launch": spl,
+                        "steps_per_launch": spl, "pass_rows": rows,
                         "bytes_per_node_step": bpn}}
     log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
         f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")
@@ -504,12 +500,12 @@ def main():
     lbm.load()
     w = make_workload(args.workload)
     log(f"[bench] workload {w.name}: {w.Lx}x{w.Ly}, storage {w.storage}")
-    gpu_s, diag, eps, single_s = time_sweep(w, lbm, torch, args.steps, args.warmup,
-                                            single_steps=200)
+    gpu_s, diag, eps, single_s, plan = time_sweep(w, lbm, torch, args.steps, args.warmup,
+                                                  single_steps=200)
     cells = w.Lx * w.Ly
     mlups = cells * args.steps / gpu_s / 1e6
     bpn = algorithmic_bytes_per_node(w.storage)
-    spl = steps_per_launch(w)
+    spl = plan[0]                       # steps per launch of the timed run
     launch_s = gpu_s / args.steps * spl
     # algorithmic bytes of a node-step (the single-step scheme's loads and stores)
     # times the node-steps of one launch
@@ -531,7 +527,8 @@ def main():
     if not args.no_fp16 and args.workload == "box4096_f32":
         w16 = make_workload("box8192_f16")
         steps16 = max(1, min(args.steps, 500))
-        g16, d16, _, s16 = time_sweep(w16, lbm, torch, steps16, args.warmup, single_steps=100)
+        g16, d16, _, s16, plan16 = time_sweep(w16, lbm, torch, steps16, args.warmup,
+                                              single_steps=100)
         cells16 = w16.Lx * w16.Ly
         m16 = cells16 * steps16 / g16 / 1e6
         b16 = algorithmic_bytes_per_node("f16")
@@ -540,10 +537,11 @@ def main():
                 "ms_per_step": round(g16 * 1e3 / steps16, 5),
                 "roofline": {"bound": "hbm", "achieved": round(a16, 1), "peak": PEAK_HBM_GBPS,
                              "unit": "GB/s", "frac": round(a16 / PEAK_HBM_GBPS, 4),
-                             "traffic": measured_traffic("box8192_f16", MULTI_KERNEL[3]),
+                             "traffic": measured_traffic("box8192_f16", MULTI_KERNEL[plan16[0]]),
                              "bytes_per_node": b16,
-                             "kernel": MULTI_KERNEL[3], "steps_per_launch": 3,
-                             "launch_us": round(g16 / steps16 * 3 * 1e6, 2)},
+                             "kernel": MULTI_KERNEL[plan16[0]], "steps_per_launch": plan16[0],
+                             "pass_rows": plan16[1],
+                             "launch_us": round(g16 / steps16 * plan16[0] * 1e6, 2)},
                 "single_step": {"kernel": "k_sweep_vec", "value": round(cells16 / s16 / 1e6, 2),
                                 "unit": "MLUPS", "frac": round(b16 * cells16 / s16 / 1e9 /
                                                                 PEAK_HBM_GBPS, 4)},
@@ -608,7 +606,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic,
                      "kernel": MULTI_KERNEL[spl],
-                     "steps_per_launch": spl, "bytes_per_node_step": bpn,
+                     "steps_per_launch": spl, "pass_rows": plan[1], "bytes_per_node_step": bpn,
                      "launch_us": round(launch_s * 1e6, 2),
                      "device_copy_GBps": round(copy_bw, 1)},
         "hbm": None if traffic is None else {

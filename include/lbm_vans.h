@@ -167,6 +167,13 @@ int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps);
 /* Number of steps taken since init (the current state is f(., n)). */
 int64_t lbm_vans_step_count(const lbm_vans_handle *h);
 
+/* Launch plan of lbm_vans_step: the most steps one pass takes (params.
+ * steps_per_pass, or the automatic choice made at init from the lattice and the
+ * GPU) and the rows per chunk of the three-step pass (params.pass_rows, or the
+ * automatic choice; 0 when the handle has no multi-step pass: LBM_F64 storage or
+ * a lattice too large for it).  Either pointer may be NULL.  Host only. */
+int lbm_vans_pass_plan(const lbm_vans_handle *h, int32_t *steps_per_pass, int32_t *pass_rows);
+
 /* Macroscopic fields of the current state f(., n) (eqs. (0moment), (1moment)):
  * eps_rho, rho, ux, uy are device arrays [Ly][Lx] of the compute type (double
  * for LBM_F64, float otherwise); any may be NULL.
@@ -307,6 +314,12 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
  * LBM_F32 / LBM_F16_SHIFTED storage up to steps_per_pass steps per launch, the
  * steps left over in a shorter launch).  Asynchronous. */
 int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps);
+
+/* Launch plan of lbm_vans_batch_step under the current configuration: the most
+ * steps one launch takes and the rows per chunk of the batched three-step pass
+ * (0 without a multi-step pass), as lbm_vans_pass_plan.  Host only. */
+int lbm_vans_batch_pass_plan(const lbm_vans_batch *b, int32_t *steps_per_pass,
+                             int32_t *pass_rows);
 
 /* Bytes of grad_work for lbm_vans_batch_grad: the members' lbm_vans_grad
  * workspaces, each rounded up to 256 bytes, back to back (0 if invalid). */

@@ -2671,6 +2671,15 @@ int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps)
 
 int64_t lbm_vans_step_count(const lbm_vans_handle *h) { return h ? h->n : -1; }
 
+int lbm_vans_pass_plan(const lbm_vans_handle *h, int32_t *steps_per_pass, int32_t *pass_rows)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    const bool multi = h->p.storage != LBM_F64 && multi_fits(h->g);
+    if (steps_per_pass) *steps_per_pass = max_pass(h);
+    if (pass_rows) *pass_rows = multi ? h->rows3 : 0;
+    return LBM_VANS_OK;
+}
+
 int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, void *uy,
                      double *diag)
 {
@@ -3378,6 +3387,20 @@ int lbm_vans_batch_configure(lbm_vans_batch *b, const lbm_vans_batch_config *cfg
     b->cfg = *cfg;
     b->cfg.us_per_step = 0.0;
     return batch_upload(b, b->cfg.vec, nullptr, 0, 1);
+}
+
+int lbm_vans_batch_pass_plan(const lbm_vans_batch *b, int32_t *steps_per_pass,
+                             int32_t *pass_rows)
+{
+    if (!b) return fail(LBM_VANS_EINVAL, "batch is NULL");
+    const bool multi = b->storage != LBM_F64 && b->multi_ok && b->nwaves[0] > 0;
+    if (steps_per_pass) *steps_per_pass = batch_max_pass(b);
+    if (pass_rows)
+        *pass_rows = !multi ? 0
+                     : b->storage == LBM_F16_SHIFTED ? tb_rows<_Float16, 3>()
+                     : batch_tall(b) ? LBM_VANS_TB3_TALL32
+                                     : tb_rows<float, 3>();
+    return LBM_VANS_OK;
 }
 
 int lbm_vans_batch_get_config(const lbm_vans_batch *b, lbm_vans_batch_config *cfg)

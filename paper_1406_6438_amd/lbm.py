@@ -31,7 +31,7 @@ ABI_VERSION = 7
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
-           "lbm_vans_moments", "lbm_vans_get_state", "lbm_vans_set_state",
+           "lbm_vans_pass_plan", "lbm_vans_batch_pass_plan", "lbm_vans_moments", "lbm_vans_get_state", "lbm_vans_set_state",
            "lbm_vans_diag_read", "lbm_vans_grad_work_bytes", "lbm_vans_grad",
            "lbm_vans_destroy", "lbm_vans_batch_work_bytes", "lbm_vans_batch_create",
            "lbm_vans_batch_configure", "lbm_vans_batch_get_config", "lbm_vans_batch_tune",
@@ -133,6 +133,9 @@ def load(path: str = LIB_PATH):
     L.lbm_vans_step.argtypes = [vp, i64]
     L.lbm_vans_step_count.argtypes = [vp]
     L.lbm_vans_step_count.restype = i64
+    i32p = ctypes.POINTER(i32)
+    L.lbm_vans_pass_plan.argtypes = [vp, i32p, i32p]
+    L.lbm_vans_batch_pass_plan.argtypes = [vp, i32p, i32p]
     L.lbm_vans_moments.argtypes = [vp, vp, vp, vp, vp, dp]
     L.lbm_vans_get_state.argtypes = [vp, vp]
     L.lbm_vans_set_state.argtypes = [vp, vp]
@@ -279,6 +282,20 @@ def lbm_vans_batch_configure(b, vec: int, grid: int, graph_steps: int, steps_per
     _check(load().lbm_vans_batch_configure(b, ctypes.byref(c)))
 
 
+def lbm_vans_pass_plan(h) -> tuple:
+    """(most steps per pass, rows per chunk of the three-step pass or 0) of a handle."""
+    spp, rows = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lbm_vans_pass_plan(h, ctypes.byref(spp), ctypes.byref(rows)))
+    return spp.value, rows.value
+
+
+def lbm_vans_batch_pass_plan(b) -> tuple:
+    """lbm_vans_pass_plan for batched launches under the current configuration."""
+    spp, rows = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lbm_vans_batch_pass_plan(b, ctypes.byref(spp), ctypes.byref(rows)))
+    return spp.value, rows.value
+
+
 def lbm_vans_batch_get_config(b) -> dict:
     c = LbmVansBatchConfig()
     _check(load().lbm_vans_batch_get_config(b, ctypes.byref(c)))
@@ -353,6 +370,11 @@ class Solver:
     @property
     def n(self) -> int:
         return lbm_vans_step_count(self.h)
+
+    @property
+    def pass_plan(self) -> tuple:
+        """(most steps per pass, rows per chunk of the three-step pass or 0)."""
+        return lbm_vans_pass_plan(self.h)
 
     def moments(self, want_diag: bool = True):
         """dict of eps_rho, rho, ux, uy tensors [Ly, Lx] and the diagnostics record."""
@@ -436,6 +458,11 @@ class Batch:
     @property
     def config(self) -> dict:
         return lbm_vans_batch_get_config(self.b)
+
+    @property
+    def pass_plan(self) -> tuple:
+        """(most steps per launch, rows per chunk of the three-step pass or 0)."""
+        return lbm_vans_batch_pass_plan(self.b)
 
     def tune(self, reps: int = 5):
         """Autotune the launch shape; returns (best, all trials) as dicts."""

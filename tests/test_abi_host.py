@@ -132,6 +132,8 @@ def test_null_batch_calls_fail_cleanly():
     assert L.lbm_vans_batch_step(None, 1) == lbm.EINVAL
     assert L.lbm_vans_batch_grad_work_bytes(None, 0, 10, 5) == 0
     assert L.lbm_vans_batch_grad(None, 0, 10, 5, None, 0, None, None) == lbm.EINVAL
+    assert L.lbm_vans_pass_plan(None, None, None) == lbm.EINVAL
+    assert L.lbm_vans_batch_pass_plan(None, None, None) == lbm.EINVAL
     L.lbm_vans_batch_destroy(None)
 
 

@@ -147,3 +147,31 @@ def test_binding_fails_loudly_when_library_missing(tmp_path):
             mod.load(str(tmp_path / "missing.so"))
     finally:
         mod._lib = saved
+
+
+@pytest.mark.parametrize("cname, pystruct", [("lbm_vans_params", "LbmVansParams"),
+                                             ("lbm_vans_batch_config", "LbmVansBatchConfig")])
+def test_struct_layouts_match_header(tmp_path, cname, pystruct):
+    """The ctypes mirrors of the header's structs have the same size and the same
+    offset for every field (a C program built against include/lbm_vans.h prints
+    them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    S = getattr(lbm, pystruct)
+    names = [f[0] for f in S._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm_vans.h"',
+             'int main(void) {',
+             f'  printf("size %zu\\n", sizeof({cname}));']
+    lines += [f'  printf("{n} %zu\\n", offsetof({cname}, {n}));' for n in names]
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)])
+    out = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    assert int(out["size"]) == ctypes.sizeof(S)
+    for n in names:
+        assert int(out[n]) == getattr(S, n).offset, n

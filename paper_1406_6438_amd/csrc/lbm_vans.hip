@@ -2238,12 +2238,17 @@ Geo make_geo(const lbm_vans_params *p, int vec = 1, int rows = ROWS)
 // multiple of it).
 int sweep_vmax(int storage) { return storage == LBM_F64 ? 2 : 4; }
 
-// Nodes per lane of the one-step sweep: as requested, else the widest.  (One
-// node per lane gives a small lattice 4x more tiles, yet measured slower: on the
-// 1024 x 512 channel 51.6 against 57.2 GLUPS with 512 tiles of 4 nodes per lane.)
-int sweep_vec(const lbm_vans_params *p)
+// Nodes per lane of the one-step sweep: as requested; automatically the widest,
+// unless its tiles would leave compute units without a workgroup (fewer tiles
+// than units), then one node per lane (four (FP64: two) times the tiles).
+// Measured, FP32 open channel, microseconds per step at 4 / 1 nodes per lane:
+// 512 x 256 (128 / 512 tiles) 6.16 / 4.49; 1024 x 512 (512 / 2048 tiles) 9.15 /
+// 10.38.
+int sweep_vec(const lbm_vans_params *p, int ncu)
 {
-    return p->sweep_vec != 0 ? p->sweep_vec : sweep_vmax(p->storage);
+    if (p->sweep_vec != 0) return p->sweep_vec;
+    const int vmax = sweep_vmax(p->storage);
+    return make_geo(p, vmax, sweep_rows_of(p->storage)).ntiles < ncu ? 1 : vmax;
 }
 
 struct Layout {
@@ -2578,12 +2583,15 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
     if (work_bytes < L.total)
         return fail(LBM_VANS_EINVAL, "work buffer has %zu bytes, %zu needed", work_bytes, L.total);
 
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     lbm_vans_handle *h = new (std::nothrow) lbm_vans_handle();
     if (!h) return fail(LBM_VANS_EINVAL, "out of host memory");
     h->p = *p;
     h->stream = static_cast<hipStream_t>(stream);
     h->g = make_geo(p);
-    h->vec = sweep_vec(p);
+    h->vec = sweep_vec(p, ncu);
     h->gs = make_geo(p, h->vec, sweep_rows_of(p->storage));
     h->ntiles = h->g.ntiles;
     h->pop_bytes = L.pop;

@@ -73,7 +73,8 @@ class Spec:
 
 
 # Execution paths of lbm_vans_step: "auto" (the library's choice: on the small test
-# grids the widest one-step sweep), "triples" (three steps per pass, the short chunks
+# grids the one-step sweep with one node per lane, as their widest sweep would have
+# fewer tiles than the GPU has compute units), "triples" (three steps per pass, the short chunks
 # the small grids get), "tall" (three steps per pass in 28-row chunks: FP32 storage;
 # the FP16 pass has one height), "pairs" (at most two steps per pass), "wide" (one
 # step per pass, widest vector width) and "narrow" (one step per pass, one node per

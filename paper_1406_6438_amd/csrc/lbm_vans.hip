@@ -972,6 +972,10 @@ constexpr int tb_cols()
 // 24 (FP32 three-step pass, GLUPS at 16 / 24 / 28 / 32 rows: 4096^2 158.5 /
 // 160.7 / 163.0 / 160.3; 2048^2 144.9 / 149.9 / 139.0 / 127.4; 64-member
 // ensemble 144.1 / 144.2 / 146.3 / 146.4).
+// The batched kernels tell the two FP32 heights apart by their row count.
+static_assert(LBM_VANS_TB3_TALL32 > LBM_VANS_TB3_ROWS32,
+              "the tall chunks of the FP32 three-step pass must be taller than the short ones");
+
 template <typename S, int NS = 2>
 constexpr int tb_rows()
 {

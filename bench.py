@@ -489,8 +489,8 @@ def main():
                     help="timed steps of the ensemble leg (--no-adjoint also skips its gradient)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the sweep has no multi-GPU path in this build "
-              "(domain decomposition is design only); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the "
+              "domain decomposition is a design, not code); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     want_acc = not args.no_accuracy and not args.no_cpu_baseline
 

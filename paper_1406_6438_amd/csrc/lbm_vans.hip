@@ -175,13 +175,33 @@ __device__ __forceinline__ int halo_index(int v, int L, int wall)
 // Storage codecs
 // ---------------------------------------------------------------------------
 
+// Every population, porosity and adjoint access goes through the global address
+// space: the batched kernels take their pointers from member descriptors in memory,
+// which the compiler cannot place, and would otherwise use flat instructions (64-bit
+// addresses per lane, and a second counter to wait on).  For pointers passed as
+// kernel arguments nothing changes.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T *p)
+{
+    return (gptr<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_global(const T *p)
+{
+    return *to_global(p);
+}
+
 template <typename S>
 __device__ __forceinline__ S load_raw(const S *p)
 {
     if constexpr (LBM_VANS_NT_LOADS)
-        return __builtin_nontemporal_load(p);
+        return __builtin_nontemporal_load(to_global(p));
     else
-        return *p;
+        return *to_global(p);
 }
 
 template <typename S, typename R>
@@ -197,9 +217,9 @@ template <typename S, typename R>
 __device__ __forceinline__ void store_pop(S *p, R v, R scale)
 {
     if constexpr (std::is_same_v<S, _Float16>)
-        __builtin_nontemporal_store(static_cast<_Float16>(v * scale), p);
+        __builtin_nontemporal_store(static_cast<_Float16>(v * scale), to_global(p));
     else
-        __builtin_nontemporal_store(static_cast<S>(v), p);
+        __builtin_nontemporal_store(static_cast<S>(v), to_global(p));
 }
 
 // ---------------------------------------------------------------------------
@@ -450,7 +470,7 @@ __device__ __forceinline__ void load_eps_tile(R (*tile)[W], const R *__restrict_
         int ly = k / W, lx = k - ly * W;
         int gx = halo_index(x0 + lx - 1, g.Lx, g.wall_x);
         int gy = halo_index(y0 + ly - 1, g.Ly, g.wall_y);
-        tile[ly][lx] = eps[(long long)gy * g.pitch + gx];
+        tile[ly][lx] = load_global(eps + (long long)gy * g.pitch + gx);
     }
 }
 
@@ -475,7 +495,7 @@ struct EpsTile {
                 if (x0 + lx - 1 <= g.Lx) {
                     const int gx = halo_index(x0 + lx - 1, g.Lx, g.wall_x);
                     const int gy = halo_index(y0 + ly - 1, g.Ly, g.wall_y);
-                    v[j] = eps[(long long)gy * g.pitch + gx];
+                    v[j] = load_global(eps + (long long)gy * g.pitch + gx);
                 } else {
                     v[j] = R(1);
                 }
@@ -705,7 +725,7 @@ __device__ __forceinline__ void stv(S *p, const R (&o)[V], R scale)
         else
             v[k] = static_cast<S>(o[k]);
     }
-    __builtin_nontemporal_store(v, reinterpret_cast<vt *>(p));
+    __builtin_nontemporal_store(v, to_global(reinterpret_cast<vt *>(p)));
 }
 
 // Lane geometry of the vector sweep: the run [x, x + V), of which the first n
@@ -1007,9 +1027,9 @@ template <typename S, typename R>
 __device__ __forceinline__ R load_cached(const S *p, R inv_scale)
 {
     if constexpr (std::is_same_v<S, _Float16>)
-        return static_cast<R>(*p) * inv_scale;
+        return static_cast<R>(load_global(p)) * inv_scale;
     else
-        return static_cast<R>(*p);
+        return static_cast<R>(load_global(p));
 }
 
 // Store through a buffer resource of one plane: a byte offset at or beyond the
@@ -1152,9 +1172,9 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     auto eps_row = [&](int k) {
         const unsigned o =
             __umul24(static_cast<unsigned>(halo_index(y0 - H - 1 + k, g.Ly, g.wall_y)), pe);
-        E[k][0] = *reinterpret_cast<const R *>(Eb + (o + xme));
-        E[k][1] = *reinterpret_cast<const R *>(Eb + (o + xe));
-        E[k][2] = *reinterpret_cast<const R *>(Eb + (o + xpe));
+        E[k][0] = load_global(reinterpret_cast<const R *>(Eb + (o + xme)));
+        E[k][1] = load_global(reinterpret_cast<const R *>(Eb + (o + xe)));
+        E[k][2] = load_global(reinterpret_cast<const R *>(Eb + (o + xpe)));
     };
     // first step at row y0+a (a = -H .. NR+H-1): gather into Q[a+H], update into P1[a+H]
     R Q[NA][9], P1[NA][9];
@@ -1727,6 +1747,7 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
     double acc[NRED];
 #pragma unroll
     for (int k = 0; k < NRED; k++) acc[k] = 0.0;
+    const gptr<double> ebg = to_global(eb), gxg = to_global(gxb), gyg = to_global(gyb);
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx;
     for (int r = 0; r < ROWS; r++) {
@@ -1755,7 +1776,7 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 9; i++) mu[i] = lam_next[i * g.plane + c];
+            for (int i = 0; i < 9; i++) mu[i] = load_global(lam_next + i * g.plane + c);
         }
         R nu[9], e_b = R(0), gx_b = R(0), gy_b = R(0);
         node_vjp<R>(d, P.e0, P.gex, P.gey, ph, mu, S_bar0, ux_bar0, R(0), nu, e_b, gx_b, gy_b);
@@ -1780,8 +1801,9 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         // push: the slot each incoming population came from (as in gather)
         const int rm = n.ym * g.pitch, r0 = y * g.pitch, rp = n.yp * g.pitch;
         const long long pl = g.plane;
-        R *L0 = lam, *L1 = lam + pl, *L2 = lam + 2 * pl, *L3 = lam + 3 * pl, *L4 = lam + 4 * pl,
-          *L5 = lam + 5 * pl, *L6 = lam + 6 * pl, *L7 = lam + 7 * pl, *L8 = lam + 8 * pl;
+        const gptr<R> lg = to_global(lam);
+        gptr<R> L0 = lg, L1 = lg + pl, L2 = lg + 2 * pl, L3 = lg + 3 * pl, L4 = lg + 4 * pl,
+                L5 = lg + 5 * pl, L6 = lg + 6 * pl, L7 = lg + 7 * pl, L8 = lg + 8 * pl;
         L0[c] = nu[0];
         *(n.wxm ? L3 + c : L1 + r0 + n.xm) = res[1] ? R(0) : nu[1];
         *(n.wym ? L4 + c : L2 + rm + x) = nu[2];
@@ -1793,7 +1815,8 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = res[8] ? R(0) : nu[8];
         if constexpr (std::is_same_v<R, float>) {
             if (p32) {
-                float *e32 = p32, *x32 = p32 + pstride, *y32 = p32 + 2 * pstride;
+                const gptr<float> e32 = to_global(p32), x32 = e32 + pstride,
+                                  y32 = e32 + 2 * pstride;
                 float se = e_b, sx = gx_b, sy = gy_b;
                 if (!(pmode & PS_FIRST)) {
                     se += e32[c];
@@ -1801,9 +1824,9 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
                     sy += y32[c];
                 }
                 if (pmode & PS_FLUSH) {
-                    eb[c] += static_cast<double>(se);
-                    gxb[c] += static_cast<double>(sx);
-                    gyb[c] += static_cast<double>(sy);
+                    ebg[c] += static_cast<double>(se);
+                    gxg[c] += static_cast<double>(sx);
+                    gyg[c] += static_cast<double>(sy);
                 } else {
                     e32[c] = se;
                     x32[c] = sx;
@@ -1812,9 +1835,9 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
                 continue;
             }
         }
-        eb[c] += static_cast<double>(e_b);
-        gxb[c] += static_cast<double>(gx_b);
-        gyb[c] += static_cast<double>(gy_b);
+        ebg[c] += static_cast<double>(e_b);
+        gxg[c] += static_cast<double>(gx_b);
+        gyg[c] += static_cast<double>(gy_b);
     }
     if constexpr (SEED) block_partial(acc, part, t);
 }

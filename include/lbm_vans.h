@@ -112,10 +112,10 @@ typedef struct lbm_vans_params {
                               6 w_i eps(x) rho0 (e_i . u_w), the momentum the moving wall
                               imparts under half-way bounce-back.                     */
     int32_t sweep_vec;     /* nodes per lane of the one-step sweep: 0 = automatic (the
-                              widest: 4, or 2 in LBM_F64, unless its tiles of 64 x 4
-                              (FP16: 8) rows would be fewer than the GPU's compute
-                              units, then 1); 1; or the widest.  Results do not depend
-                              on it beyond rounding.                                  */
+                              widest: 4, or 2 in LBM_F64, unless its tiles (64 lanes
+                              of that many nodes, by 4 rows; FP16: 8 rows) would be
+                              fewer than the GPU's compute units, then 1); 1; or the
+                              widest.  Results do not depend on it beyond rounding.   */
     int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 1, 2 or
                               3; 0 = automatic: 3 when the three-step pass has at
                               least 0.7 times as many waves (60 columns x pass_rows

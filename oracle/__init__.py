@@ -17,6 +17,8 @@ FMA contraction).  This module is argument marshalling around it:
 * ``init``           -- f(x, 0) = f^eq(eps(x) rho0, u0)
 * ``collide`` / ``stream`` / ``steps`` -- one or more time steps of the final
                         lattice Boltzmann equation (collide, then push)
+* ``open_ends``      -- the boundary state a velocity inlet / pressure outlet
+                        builds the next entering populations from
 * ``moments``        -- eps rho, rho, u, m = sum e_i f_i and T per cell
 * ``outlet_flux`` / ``grad_outlet_flux`` -- J = sum of eps rho u_x over the last
                         column, and dJ/deps by the reverse (adjoint) of the steps
@@ -40,12 +42,13 @@ _LIB_OVERRIDE = os.environ.get("LBM_VANS_ORACLE_LIB")
 PERIODIC = 0
 WALL = 1
 OPEN = 2
+INOUT = 3           # velocity inlet at x = 0, pressure outlet at x = Lx-1
 DRAG_ERGUN = 0
 DRAG_CONST = 1
 
 # Build flags of the oracle: no FMA contraction and no fast-math, so every
 # operation is one correctly rounded binary64 operation.
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+CFLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
           "-fopenmp", "-Wall", "-Wextra"]
 
 
@@ -127,8 +130,10 @@ def lib():
         L.orc_grad_eps.argtypes = [P, _D, _D, _D]
         L.orc_init.argtypes = [P, _D, _D]
         L.orc_collide.argtypes = [P, _D, _D, _D, _D, _D, ctypes.c_int]
-        L.orc_stream.argtypes = [P, _D, _D, _D, ctypes.c_int]
+        L.orc_open_ends.argtypes = [P, _D, _D, _D, _D, _D]
+        L.orc_stream.argtypes = [P, _D, _D, _D, _D, ctypes.c_int]
         L.orc_steps.argtypes = [P, _D, _D, _D, _D, _D, ctypes.c_int64, ctypes.c_int]
+        L.orc_steps.restype = ctypes.c_int
         L.orc_moments.argtypes = [P, _D, _D, _D, _D] + [_D] * 8
         L.orc_drag_derivs.argtypes = [P, ctypes.c_double, _D, _D]
         L.orc_node_collide.argtypes = [P, _D] + [ctypes.c_double] * 3 + [_D]
@@ -143,7 +148,7 @@ def lib():
             getattr(L, name).restype = None
         for name in ("orc_lattice", "orc_feq", "orc_guo_source", "orc_drag_coeffs",
                      "orc_velocity", "orc_grad_eps", "orc_init", "orc_collide",
-                     "orc_stream", "orc_steps", "orc_moments"):
+                     "orc_open_ends", "orc_stream", "orc_moments"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -233,11 +238,32 @@ def collide(p: Params, eps: np.ndarray, f: np.ndarray, threads: int | None = Non
     return out
 
 
-def stream(p: Params, eps: np.ndarray, fpost: np.ndarray, threads: int | None = None):
+def open_ends(p: Params, eps: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Velocity inlet / pressure outlet: per row, eps rho of the inlet node and the
+    velocity of the outlet node of the state f, as an array [Ly, 3]."""
+    eps = _f64(eps)
+    f = _f64(f)
+    gx, gy = grad_eps(p, eps)
+    ends = np.empty((p.Ly, 3))
+    lib().orc_open_ends(ctypes.byref(p.c()), _ptr(eps), _ptr(gx), _ptr(gy), _ptr(f),
+                        _ptr(ends))
+    return ends
+
+
+def stream(p: Params, eps: np.ndarray, fpost: np.ndarray, f_prev: np.ndarray | None = None,
+           threads: int | None = None):
+    """Push streaming of the post-collision fpost; with a velocity inlet / pressure
+    outlet the entering populations need f_prev, the state fpost was collided from."""
     eps = _f64(eps)
     fpost = _f64(fpost)
+    ends = None
+    if p.bc_x == INOUT:
+        if f_prev is None:
+            raise ValueError("a velocity inlet / pressure outlet needs the previous state")
+        ends = open_ends(p, eps, f_prev)
     out = np.empty_like(fpost)
-    lib().orc_stream(ctypes.byref(p.c()), _ptr(eps), _ptr(fpost), _ptr(out),
+    lib().orc_stream(ctypes.byref(p.c()), _ptr(eps), _ptr(fpost),
+                     _ptr(ends) if ends is not None else None, _ptr(out),
                      threads or default_threads())
     return out
 
@@ -251,8 +277,10 @@ def steps(p: Params, eps: np.ndarray, f: np.ndarray, nsteps: int,
     assert f.shape == (9, p.Ly, p.Lx)
     gx, gy = grad_eps(p, eps)
     scratch = np.empty_like(f)
-    lib().orc_steps(ctypes.byref(p.c()), _ptr(eps), _ptr(gx), _ptr(gy), _ptr(f),
-                    _ptr(scratch), int(nsteps), threads or default_threads())
+    rc = lib().orc_steps(ctypes.byref(p.c()), _ptr(eps), _ptr(gx), _ptr(gy), _ptr(f),
+                         _ptr(scratch), int(nsteps), threads or default_threads())
+    if rc != 0:
+        raise MemoryError("oracle steps: out of memory")
     return f
 
 

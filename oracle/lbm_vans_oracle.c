@@ -53,7 +53,15 @@
  *     (x = Lx-1) is the equilibrium of eq. (d2q9eq) of a reservoir with the
  *     boundary node's porosity and the given density and x-velocity, and a
  *     population leaving across it is absorbed.  Where the source also lies
- *     behind a y-wall, bounce-back wins.
+ *     behind a y-wall, bounce-back wins;
+ *   - velocity inlet and pressure outlet (the second kind of open x ends):
+ *     the reservoir beyond the inlet carries the given velocity (u_in, 0) and
+ *     the inlet node's own density, the reservoir beyond the outlet the given
+ *     density rho_out and the outlet node's own velocity (zero-gradient
+ *     extrapolation of the free quantity), both taken from the state the step
+ *     starts from: the populations entering at step n + 1 are
+ *         inlet:  f_i^eq(eps rho of node (0, y) at step n, (u_in, 0)),
+ *         outlet: f_i^eq(eps(Lx-1, y) rho_out, u of node (Lx-1, y) at step n).
  */
 #include <math.h>
 #include <stddef.h>
@@ -72,7 +80,7 @@ static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 /* Squared lattice sound speed of D2Q9. */
 static const double CS2 = 1.0 / 3.0;
 
-enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_OPEN = 2 };
+enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_OPEN = 2, ORC_INOUT = 3 };
 enum { ORC_DRAG_ERGUN = 0, ORC_DRAG_CONST = 1 };
 
 /* Problem description (Section "Examples and discussions"). */
@@ -80,7 +88,8 @@ typedef struct {
     int32_t Lx, Ly;     /* lattice nodes along x and y                         */
     int32_t bc_x, bc_y; /* ORC_PERIODIC or ORC_WALL (both ends of the axis);    */
                         /* bc_x may be ORC_OPEN: inflow reservoir beyond x = 0, */
-                        /* outflow reservoir beyond x = Lx-1                    */
+                        /* outflow reservoir beyond x = Lx-1; or ORC_INOUT:     */
+                        /* velocity inlet at x = 0, pressure outlet at Lx-1      */
     int32_t drag;       /* ORC_DRAG_ERGUN: K, F_eps from d_p (Ergun closure)    */
                         /* ORC_DRAG_CONST: K and F_eps given, uniform            */
     int32_t pad_;
@@ -91,6 +100,8 @@ typedef struct {
     double rho0, u0x, u0y; /* initial state                                    */
     double rho_in, u_in;   /* ORC_OPEN: density and x-velocity of the inflow reservoir  */
     double rho_out, u_out; /* ORC_OPEN: density and x-velocity of the outflow reservoir */
+                           /* ORC_INOUT: u_in is the inlet velocity, rho_out the      */
+                           /* outlet density (rho_in, u_out unused)                  */
     double uw_bot, uw_top; /* ORC_WALL in y: x-velocity of the wall below y = 0 and of the
                               wall above y = Ly-1 (sliding plates)                      */
 } orc_params;
@@ -340,15 +351,38 @@ static double wall_gain(const orc_params *p, int j, int top)
     return 6.0 * W[j] * p->rho0 * (EX[j] * uw);
 }
 
+/* Velocity inlet / pressure outlet: what the populations entering at the next
+ * step are built from, taken from the state f (eqs. (0moment), (1moment)):
+ * for each row y, ends[3 y] = eps rho of the inlet node (0, y) and
+ * ends[3 y + 1], ends[3 y + 2] = the velocity of the outlet node (Lx-1, y). */
+void orc_open_ends(const orc_params *p, const double *eps, const double *gx, const double *gy,
+                   const double *f, double *ends)
+{
+    size_t N = (size_t)p->Lx * p->Ly;
+    for (int y = 0; y < p->Ly; y++) {
+        size_t c0 = (size_t)y * p->Lx, c1 = (size_t)y * p->Lx + (p->Lx - 1);
+        double S, ux, uy;
+        cell_state(p, f, N, c0, eps[c0], gx[c0], gy[c0], &S, NULL, NULL, NULL, NULL, NULL,
+                   NULL, NULL);
+        ends[3 * y] = S;
+        cell_state(p, f, N, c1, eps[c1], gx[c1], gy[c1], NULL, NULL, NULL, NULL, &ux, &uy,
+                   NULL, NULL);
+        ends[3 * y + 1] = ux;
+        ends[3 * y + 2] = uy;
+    }
+}
+
 /* Streaming (push):  f_i(x + e_i) = f*_i(x).  Along a periodic axis the
  * target wraps around; a target beyond a wall sends the population back to
  * its own cell as the opposite direction (half-way bounce-back), plus the
  * gain of a sliding y-wall; a target beyond an open x-boundary leaves the
  * domain.  Beyond a y-wall bounce-back takes precedence.  Then the
  * populations that enter across an open x-boundary are set from the
- * reservoirs.  Every slot of f is written once. */
-void orc_stream(const orc_params *p, const double *eps, const double *fpost, double *f,
-                int nthreads)
+ * reservoirs: fixed ones (ORC_OPEN), or for ORC_INOUT the inlet and outlet
+ * reservoirs built from ends (orc_open_ends of the state the step starts
+ * from; NULL for the other boundary kinds).  Every slot of f is written once. */
+void orc_stream(const orc_params *p, const double *eps, const double *fpost,
+                const double *ends, double *f, int nthreads)
 {
     long Ly = p->Ly;
     int Lx = p->Lx;
@@ -381,26 +415,45 @@ void orc_stream(const orc_params *p, const double *eps, const double *fpost, dou
             }
         }
     }
-    if (p->bc_x != ORC_OPEN) return;
+    if (p->bc_x != ORC_OPEN && p->bc_x != ORC_INOUT) return;
     for (long y = 0; y < Ly; y++) {
         size_t c0 = (size_t)y * Lx, c1 = (size_t)y * Lx + (Lx - 1);
+        double feq_in[9], feq_out[9];
+        if (p->bc_x == ORC_INOUT) {
+            orc_feq(ends[3 * y], p->u_in, 0.0, feq_in);
+            orc_feq(eps[c1] * p->rho_out, ends[3 * y + 1], ends[3 * y + 2], feq_out);
+        }
         for (int i = 0; i < 9; i++) {
             if (source_behind_ywall(p, (int)y, i)) continue;
-            if (EX[i] > 0) f[i * N + c0] = reservoir(i, eps[c0], p->rho_in, p->u_in);
-            if (EX[i] < 0) f[i * N + c1] = reservoir(i, eps[c1], p->rho_out, p->u_out);
+            if (p->bc_x == ORC_INOUT) {
+                if (EX[i] > 0) f[i * N + c0] = feq_in[i];
+                if (EX[i] < 0) f[i * N + c1] = feq_out[i];
+            } else {
+                if (EX[i] > 0) f[i * N + c0] = reservoir(i, eps[c0], p->rho_in, p->u_in);
+                if (EX[i] < 0) f[i * N + c1] = reservoir(i, eps[c1], p->rho_out, p->u_out);
+            }
         }
     }
 }
 
 /* nsteps full time steps in place on f (collide, then stream).  scratch must
- * hold 9*Lx*Ly doubles; gx, gy from orc_grad_eps. */
-void orc_steps(const orc_params *p, const double *eps, const double *gx, const double *gy,
-               double *f, double *scratch, int64_t nsteps, int nthreads)
+ * hold 9*Lx*Ly doubles; gx, gy from orc_grad_eps.  Returns 0, or -1 if memory
+ * runs out. */
+int orc_steps(const orc_params *p, const double *eps, const double *gx, const double *gy,
+              double *f, double *scratch, int64_t nsteps, int nthreads)
 {
+    double *ends = NULL;
+    if (p->bc_x == ORC_INOUT) {
+        ends = malloc(sizeof(double) * 3 * (size_t)p->Ly);
+        if (!ends) return -1;
+    }
     for (int64_t n = 0; n < nsteps; n++) {
         orc_collide(p, eps, gx, gy, f, scratch, nthreads);
-        orc_stream(p, eps, scratch, f, nthreads);
+        if (ends) orc_open_ends(p, eps, gx, gy, f, ends);
+        orc_stream(p, eps, scratch, ends, f, nthreads);
     }
+    free(ends);
+    return 0;
 }
 
 /* Macroscopic fields of the state f (eqs. (0moment), (1moment)):
@@ -439,7 +492,9 @@ void orc_moments(const orc_params *p, const double *eps, const double *gx,
  * transposed Jacobian of each node's collision; porosity enters through
  * eps(x) itself (density, drag coefficients), through grad(eps) (the lattice
  * stencil, transposed once at the end), through the reservoir populations of
- * open boundaries and through the initial state.  All states are kept.
+ * open boundaries (and, at a velocity inlet / pressure outlet, through the
+ * boundary nodes' density and velocity those reservoirs carry) and through the
+ * initial state.  All states are kept.
  * ------------------------------------------------------------------------ */
 
 /* Derivatives of the drag coefficients a(eps), b(eps) of orc_drag_coeffs.
@@ -607,8 +662,18 @@ int orc_grad_outlet_flux(const orc_params *p, const double *eps, int64_t nsteps,
     double *pbar = malloc(sizeof(double) * S9);
     double *gx = malloc(sizeof(double) * N), *gy = malloc(sizeof(double) * N);
     double *gxb = calloc(N, sizeof(double)), *gyb = calloc(N, sizeof(double));
-    if (!fs || !post || !fbar || !pbar || !gx || !gy || !gxb || !gyb) {
+    /* velocity inlet / pressure outlet: the boundary state of each step and the
+     * adjoints it passes back to the boundary nodes (eps rho at the inlet, u at
+     * the outlet) */
+    int inout = p->bc_x == ORC_INOUT;
+    double *ends = inout ? malloc(sizeof(double) * 3 * (size_t)Ly) : NULL;
+    double *Sb = inout ? calloc(N, sizeof(double)) : NULL;
+    double *uxb = inout ? calloc(N, sizeof(double)) : NULL;
+    double *uyb = inout ? calloc(N, sizeof(double)) : NULL;
+    if (!fs || !post || !fbar || !pbar || !gx || !gy || !gxb || !gyb ||
+        (inout && (!ends || !Sb || !uxb || !uyb))) {
         free(fs); free(post); free(fbar); free(pbar); free(gx); free(gy); free(gxb); free(gyb);
+        free(ends); free(Sb); free(uxb); free(uyb);
         return -1;
     }
     orc_grad_eps(p, eps, gx, gy);
@@ -616,7 +681,8 @@ int orc_grad_outlet_flux(const orc_params *p, const double *eps, int64_t nsteps,
     orc_init(p, eps, fs);
     for (int64_t n = 0; n < nsteps; n++) {
         orc_collide(p, eps, gx, gy, fs + S9 * n, post, nthreads);
-        orc_stream(p, eps, post, fs + S9 * (n + 1), nthreads);
+        if (ends) orc_open_ends(p, eps, gx, gy, fs + S9 * n, ends);
+        orc_stream(p, eps, post, ends, fs + S9 * (n + 1), nthreads);
     }
     const double *fN = fs + S9 * nsteps;
     *J_out = orc_outlet_flux(p, eps, gx, gy, fN);
@@ -636,6 +702,34 @@ int orc_grad_outlet_flux(const orc_params *p, const double *eps, int64_t nsteps,
         for (int i = 0; i < 9; i++) fbar[i * N + c] += fb[i];
     }
     for (int64_t n = nsteps - 1; n >= 0; n--) {
+        /* velocity inlet: f_i(0, y; n+1) = f_i^eq(S, (u_in, 0)) with S = eps rho of
+         * node (0, y) at step n; pressure outlet: f_i(Lx-1, y; n+1) =
+         * f_i^eq(eps rho_out, u) with u the velocity of node (Lx-1, y) at step n */
+        if (inout) {
+            orc_open_ends(p, eps, gx, gy, fs + S9 * n, ends);
+            for (int y = 0; y < Ly; y++) {
+                size_t c0 = (size_t)y * Lx, c1 = (size_t)y * Lx + (Lx - 1);
+                double feq_in1[9], feq_out1[9];
+                double ux = ends[3 * y + 1], uy = ends[3 * y + 2];
+                orc_feq(1.0, p->u_in, 0.0, feq_in1);
+                orc_feq(p->rho_out, ux, uy, feq_out1);
+                for (int i = 0; i < 9; i++) {
+                    if (source_behind_ywall(p, y, i)) continue;
+                    if (EX[i] > 0) Sb[c0] += fbar[i * N + c0] * feq_in1[i];
+                    if (EX[i] < 0) {
+                        double fb = fbar[i * N + c1];
+                        /* d/d eps, and d/du of w_i S (1 + eu/c2 + eu^2/(2 c2^2) - uu/(2 c2)) */
+                        dJdeps[c1] += fb * feq_out1[i];
+                        double S = eps[c1] * p->rho_out;
+                        double eu = EX[i] * ux + EY[i] * uy;
+                        uxb[c1] += fb * W[i] * S *
+                                   (EX[i] / CS2 + eu * EX[i] / (CS2 * CS2) - ux / CS2);
+                        uyb[c1] += fb * W[i] * S *
+                                   (EY[i] / CS2 + eu * EY[i] / (CS2 * CS2) - uy / CS2);
+                    }
+                }
+            }
+        }
         /* reservoir populations of f(., n+1) depend on the boundary porosity */
         if (p->bc_x == ORC_OPEN) {
             for (int y = 0; y < Ly; y++) {
@@ -684,8 +778,15 @@ int orc_grad_outlet_flux(const orc_params *p, const double *eps, int64_t nsteps,
                 fc[i] = fn[i * N + c];
                 pb[i] = pbar[i * N + c];
             }
-            orc_node_vjp(p, fc, eps[c], gx[c], gy[c], pb, 0.0, 0.0, 0.0, fb, &dJdeps[c],
-                         &gxb[c], &gyb[c]);
+            double sb = 0.0, xb = 0.0, yb = 0.0;
+            if (inout) {
+                sb = Sb[c];
+                xb = uxb[c];
+                yb = uyb[c];
+                Sb[c] = uxb[c] = uyb[c] = 0.0;
+            }
+            orc_node_vjp(p, fc, eps[c], gx[c], gy[c], pb, sb, xb, yb, fb, &dJdeps[c], &gxb[c],
+                         &gyb[c]);
             for (int i = 0; i < 9; i++) fbar[i * N + c] = fb[i];
         }
     }
@@ -708,5 +809,6 @@ int orc_grad_outlet_flux(const orc_params *p, const double *eps, int64_t nsteps,
             }
         }
     free(fs); free(post); free(fbar); free(pbar); free(gx); free(gy); free(gxb); free(gyb);
+    free(ends); free(Sb); free(uxb); free(uyb);
     return 0;
 }

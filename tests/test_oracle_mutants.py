@@ -74,33 +74,66 @@ MUTANTS = {
                                     "f[i * N + c] = fpost[i * N + c] +"),
     "adjoint_wall_gain_dropped": ("dJdeps[c] += fbar[OPP[i] * N + c] * wall_gain(p, OPP[i], yt >= Ly);",
                                   "dJdeps[c] += 0.0;"),
+    # the objective (outlet mass flux) and the reverse pass's seed
+    "objective_column_shift": [("size_t c = (size_t)y * p->Lx + (p->Lx - 1);",
+                                "size_t c = (size_t)y * p->Lx + (p->Lx - 2);"),
+                               ("size_t c = (size_t)y * Lx + (Lx - 1);\n        double fc[9]",
+                                "size_t c = (size_t)y * Lx + (Lx - 2);\n        double fc[9]")],
+    "objective_raw_momentum": ("cell_state(p, f, N, c, eps[c], gx[c], gy[c], &S, NULL, NULL, NULL, &ux, NULL, NULL,\n"
+                               "                   NULL);\n        J += S * ux;",
+                               "cell_state(p, f, N, c, eps[c], gx[c], gy[c], &S, &ux, NULL, NULL, NULL, NULL, NULL,\n"
+                               "                   NULL);\n        J += ux;"),
+    # velocity inlet / pressure outlet
+    "inlet_fixed_density": ("orc_feq(ends[3 * y], p->u_in, 0.0, feq_in);",
+                            "orc_feq(eps[c0] * p->rho_in, p->u_in, 0.0, feq_in);"),
+    "outlet_fixed_velocity": ("orc_feq(eps[c1] * p->rho_out, ends[3 * y + 1], ends[3 * y + 2], feq_out);",
+                              "orc_feq(eps[c1] * p->rho_out, p->u_in, 0.0, feq_out);"),
+    "outlet_ignores_porosity": ("orc_feq(eps[c1] * p->rho_out, ends[3 * y + 1], ends[3 * y + 2], feq_out);",
+                                "orc_feq(p->rho_out, ends[3 * y + 1], ends[3 * y + 2], feq_out);"),
+    "outlet_drops_transverse_velocity": ("ends[3 * y + 2] = uy;", "ends[3 * y + 2] = 0.0;"),
+    "outlet_velocity_from_inlet_node": [("cell_state(p, f, N, c1, eps[c1], gx[c1], gy[c1], NULL, NULL, NULL, NULL, &ux, &uy,",
+                                         "cell_state(p, f, N, c0, eps[c0], gx[c0], gy[c0], NULL, NULL, NULL, NULL, &ux, &uy,")],
+    "adjoint_inlet_density_dropped": ("if (EX[i] > 0) Sb[c0] += fbar[i * N + c0] * feq_in1[i];",
+                                      "if (EX[i] > 0) Sb[c0] += 0.0 * feq_in1[i];"),
+    "adjoint_outlet_velocity_dropped": ("uxb[c1] += fb * W[i] * S *", "uxb[c1] += 0.0 * W[i] * S *"),
+    "adjoint_outlet_porosity_dropped": ("dJdeps[c1] += fb * feq_out1[i];", "dJdeps[c1] += 0.0 * feq_out1[i];"),
+    "adjoint_outlet_du_sign": ("(EX[i] / CS2 + eu * EX[i] / (CS2 * CS2) - ux / CS2)",
+                               "(EX[i] / CS2 + eu * EX[i] / (CS2 * CS2) + ux / CS2)"),
 }
 
 
+def _pairs(name):
+    m = MUTANTS[name]
+    return m if isinstance(m, list) else [m]
+
+
 def _kill(name, tmp):
-    old, new = MUTANTS[name]
     src = open(SRC).read()
-    assert old in src, f"mutation anchor for {name} not found"
-    path = os.path.join(tmp, name + ".c")
-    with open(path, "w") as fh:
+    for old, new in _pairs(name):
+        assert old in src, f"mutation anchor for {name} not found"
         # the first occurrence is the forward step; the node adjoint further down
         # recomputes the same forward quantities
-        fh.write(src.replace(old, new, 1))
+        src = src.replace(old, new, 1)
+    path = os.path.join(tmp, name + ".c")
+    with open(path, "w") as fh:
+        fh.write(src)
     lib = os.path.join(tmp, name + ".so")
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+    subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
                            "-fopenmp", "-o", lib, path, "-lm"])
     env = dict(os.environ, LBM_VANS_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_adjoint.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_adjoint.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_inout.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
 
 def test_mutation_anchors_exist():
     src = open(SRC).read()
-    for name, (old, _) in MUTANTS.items():
-        assert old in src, f"mutation anchor for {name} not found"
+    for name in MUTANTS:
+        for old, _ in _pairs(name):
+            assert old in src, f"mutation anchor for {name} not found"
 
 
 def test_every_mutant_fails_a_pin():

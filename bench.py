@@ -33,10 +33,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E peak
+# VALU issue of MI355X without packed FP32: 256 compute units x 4 SIMDs, each SIMD
+# retiring one 64-lane instruction every 4 cycles, at 2.4 GHz: 614.4e9 wave
+# instructions per second (39.3e12 lane operations; packed FP32 doubles that to the
+# 157.3 TFLOP/s FMA peak, and packed FP32 is not used here)
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 PROFILE_TRAFFIC = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_traffic_box4096_f32.md"),
                    "box8192_f16": os.path.join(ROOT, "profiles", "sweep_traffic_box8192_f16.md"),
                    "ensemble64_f32": os.path.join(ROOT, "profiles",
                                                   "batch_traffic_ensemble64_f32.md")}
+PROFILE_VALU = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_valu_box4096_f32.md"),
+                "box8192_f16": os.path.join(ROOT, "profiles", "sweep_valu_box8192_f16.md")}
 MULTI_KERNEL = {1: "k_sweep_vec", 2: "k_sweep_tb2", 3: "k_sweep_tb3"}
 BATCH_KERNEL = {1: "k_batch_sweep", 2: "k_batch_tb2", 3: "k_batch_tb3"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
@@ -57,11 +64,10 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
-    the workload, if it was taken on the current kernel source; else None.  A summary
-    holds one block per kernel ("kernel: <name> ..." up to its source hash)."""
-    path = PROFILE_TRAFFIC.get(workload)
+def summary_value(path, kernel: str, field: str):
+    """A per-launch figure of `kernel` (field "<field>: <number>") from a committed
+    rocprofv3 counter summary, if it was taken on the current kernel source; else None.
+    A summary holds one block per kernel ("kernel: <name> ..." up to its source hash)."""
     if path is None or not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -71,10 +77,65 @@ def measured_traffic(workload: str, kernel: str):
                 name.startswith("_ZN12_GLOBAL__N_1" + str(len(kernel)) + kernel)):
             continue
         m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", block)
-        m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", block)
-        if m_hash and m_bytes and m_hash.group(1) == kernel_hash():
-            return float(m_bytes.group(1))
+        m_val = re.search(field + r":\s*([0-9.eE+]+)", block)
+        if m_hash and m_val and m_hash.group(1) == kernel_hash():
+            return float(m_val.group(1))
     return None
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the workload's committed counter summary
+    (None unless taken on the current kernel source)."""
+    return summary_value(PROFILE_TRAFFIC.get(workload), kernel, "hbm_bytes_per_launch")
+
+
+def measured_valu(workload: str, kernel: str):
+    """(VALU wave instructions, VALU-active quad-cycles summed over waves, VALU-busy
+    fraction) per launch of `kernel` from the workload's committed SQ counter summary
+    (None unless taken on the current kernel source)."""
+    path = PROFILE_VALU.get(workload)
+    vals = [summary_value(path, kernel, f) for f in
+            ("valu_insts_per_launch", "valu_active_quad_cycles_per_launch", "valu_busy_frac")]
+    return None if None in vals else tuple(vals)
+
+
+def roofline(kernel: str, workload: str, bytes_per_node: float, nodes: int, launch_s: float,
+             steps_per_launch: int, pass_rows: int):
+    """Roofline of one launch of the dominant kernel.  achieved / frac: the pass's
+    algorithmic bytes (one read of the state and the porosity, one write of the state:
+    bytes_per_node per node however many steps the launch takes) over the measured
+    launch time, against the HBM peak.  alu: the VALU instructions the counters count
+    per launch at the chip's non-packed issue rate, a time floor of its own; frac_binding
+    is the larger floor over the launch time."""
+    ach = bytes_per_node * nodes / launch_s / 1e9
+    traffic = measured_traffic(workload, kernel)
+    valu = measured_valu(workload, kernel)
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+           "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": traffic, "kernel": kernel,
+           "steps_per_launch": steps_per_launch, "pass_rows": pass_rows,
+           "bytes_per_node_per_launch": bytes_per_node,
+           "bytes_per_node_step": round(bytes_per_node / steps_per_launch, 3),
+           "launch_us": round(launch_s * 1e6, 2),
+           "one_step_equivalent_GBps": round(ach * steps_per_launch, 1)}
+    if traffic is not None:
+        out["traffic_GBps"] = round(traffic / launch_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / launch_s / 1e9 / PEAK_HBM_GBPS, 4)
+    hbm_floor = bytes_per_node * nodes / (PEAK_HBM_GBPS * 1e9)
+    if valu is not None:
+        insts, quads, busy = valu
+        # one quad-cycle of a SIMD per full-rate instruction (transcendental and FP64
+        # instructions take more): the VALU-active quad-cycles over 1024 SIMDs at 2.4 GHz
+        valu_floor = quads / PEAK_VALU_WAVE_INSTS
+        out["alu"] = {"valu_wave_insts_per_launch": insts,
+                      "valu_active_quad_cycles_per_launch": quads,
+                      "peak_quad_cycles_per_s": PEAK_VALU_WAVE_INSTS,
+                      "time_floor_us": round(valu_floor * 1e6, 2),
+                      "frac": round(valu_floor / launch_s, 4),
+                      "valu_busy_frac_counter": busy,
+                      "valu_insts_per_node_step": round(insts * 64 / (nodes * steps_per_launch), 1)}
+        out["frac_binding"] = round(max(hbm_floor, valu_floor) / launch_s, 4)
+        out["binding"] = "alu" if valu_floor > hbm_floor else "hbm"
+    return out
 
 
 def copy_bandwidth_gbps(torch, nbytes=2 << 30, reps=10) -> float:
@@ -117,8 +178,8 @@ def oracle_params(spec: dict):
     import oracle
     kw = dict(spec)
     for k in ("bc_x", "bc_y"):
-        kw[k] = {"periodic": oracle.PERIODIC, "wall": oracle.WALL,
-                 "open": oracle.OPEN}[kw.get(k, "periodic")]
+        kw[k] = {"periodic": oracle.PERIODIC, "wall": oracle.WALL, "open": oracle.OPEN,
+                 "inout": oracle.INOUT}[kw.get(k, "periodic")]
     return oracle.Params(**kw)
 
 
@@ -143,10 +204,25 @@ def cpu_baseline_leg(w, eps, budget_s: float, jobs: list):
     oracle.steps(p, e, f, k, threads)
     dt = time.perf_counter() - t0
     del f
+    # the same on one thread, on a budget of its own (a few steps of the full lattice)
+    f = oracle.init(p, e)
+    t0 = time.perf_counter()
+    f = oracle.steps(p, e, f, 1, 1)
+    t1s = time.perf_counter() - t0
+    k1 = max(1, min(int(budget_s / 3.0 / max(t1s, 1e-9)), 100000))
+    t0 = time.perf_counter()
+    oracle.steps(p, e, f, k1, 1)
+    dt1 = time.perf_counter() - t0
+    del f
     out = {"value": round(w.Lx * w.Ly * k / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
            "kind": "oracle",
            "sample": f"{w.Lx}x{w.Ly} lattice of the same workload, {k} FP64 steps after 1 "
-                     f"untimed step ({dt:.1f} s), OpenMP over rows",
+                     f"untimed step ({dt:.1f} s), OpenMP over rows on {threads} threads (the "
+                     f"host share: OMP_NUM_THREADS, else the CPU count capped at 16)",
+           "host_cpu_count": os.cpu_count(),
+           "one_thread": {"value": round(w.Lx * w.Ly * k1 / dt1 / 1e6, 3), "unit": "MLUPS",
+                          "steps": k1, "seconds": round(dt1, 2)},
+           "build": "gcc " + " ".join(oracle.CFLAGS),
            "accuracy_samples": []}
     log(f"[bench] cpu baseline {out['value']} MLUPS on {threads} threads")
     results = []
@@ -179,13 +255,17 @@ def speed_error(gpu, res) -> float:
     return rel_l2(np.hypot(*gpu), np.hypot(res["ux"], res["uy"]))
 
 
-def crop_sample(w, lbm, steps: int):
-    """The GPU run of the top-left 512^2 crop of the workload's porosity, run periodic,
-    and the matching oracle job."""
+def crop_sample(w, lbm, steps: int, plan):
+    """The GPU run of the top-left 512^2 crop of the workload's porosity, run periodic
+    in the launch plan of the timed run (plan = steps per pass, rows per chunk of the
+    three-step pass), and the matching oracle job."""
+    import dataclasses
     from paper_1406_6438_amd import workloads as W
     n = W.CROP
     eps = cast_eps(W.crop_porosity(w, n), w.storage)
-    s = lbm.Solver(lbm_params(w, lbm, n, n), eps)
+    p = dataclasses.replace(lbm_params(w, lbm, n, n), steps_per_pass=plan[0],
+                            pass_rows=plan[1])
+    s = lbm.Solver(p, eps)
     s.step(steps)
     m = s.moments(want_diag=False)
     gpu = (m["ux"].double().cpu().numpy(), m["uy"].double().cpu().numpy())
@@ -196,28 +276,46 @@ def crop_sample(w, lbm, steps: int):
     return gpu, job
 
 
-def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0):
-    """(seconds on the library's stream for `steps` steps, final diagnostics record,
-    porosity, seconds per step when every step is its own launch or None, the
-    library's launch plan: most steps per pass and rows per chunk of the three-step
-    pass).  The second timing calls lbm_vans_step with one step per call, so every
-    step is one single-step launch (k_sweep_vec)."""
+def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0, reps: int = 5):
+    """Times `steps` steps `reps` times in a row (after `warmup` untimed steps) with HIP
+    events on the library's stream, one pair around the whole run and one around every
+    launch (each lbm_vans_step call below takes exactly one launch).  Returns a dict:
+    seconds of every repetition and their median, the mean duration of the launches
+    that take the plan's full steps per pass (the dominant kernel), the final
+    diagnostics record, the porosity, the seconds per step when every step is its own
+    launch (k_sweep_vec; None without single_steps) and the launch plan (most steps per
+    pass, rows per chunk of the three-step pass)."""
+    import statistics
     eps = w.porosity()
     s = lbm.Solver(lbm_params(w, lbm), cast_eps(eps, w.storage))
-    log(f"[bench] {w.name}: warmup {warmup} steps")
+    plan = s.pass_plan
+    spl = plan[0]
+    log(f"[bench] {w.name}: warmup {warmup} steps; plan {plan}")
     s.step(warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(s.stream)
-    s.step(steps)
-    e1.record(s.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_s = e0.elapsed_time(e1) / 1e3
+    Ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    rep_s, launch_s = [], []
+    for _ in range(reps):
+        e0, e1 = Ev(), Ev()
+        marks = []
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        k = 0
+        while k < steps:
+            m = min(spl, steps - k)
+            a, b = Ev(), Ev()
+            a.record(s.stream)
+            s.step(m)
+            b.record(s.stream)
+            marks.append((m, a, b))
+            k += m
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        rep_s.append(e0.elapsed_time(e1) / 1e3)
+        launch_s += [a.elapsed_time(b) / 1e3 for m, a, b in marks if m == spl]
     single = None
     if single_steps > 0:
+        e0, e1 = Ev(), Ev()
         e0.record(s.stream)
         for _ in range(single_steps):
             s.step(1)
@@ -225,26 +323,30 @@ def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0):
         torch.cuda.synchronize()
         single = e0.elapsed_time(e1) / 1e3 / single_steps
     diag = s.moments()["diag"]
-    plan = s.pass_plan
     s.close()
     del s
     torch.cuda.empty_cache()
-    log(f"[bench] {w.name}: {steps} steps in {gpu_s * 1e3:.2f} ms (events), {wall * 1e3:.2f} ms (wall)"
-        + (f"; one step per launch: {single * 1e6:.1f} us/step" if single else "")
-        + f"; plan {plan}")
-    return gpu_s, diag, eps, single, plan
+    med = statistics.median(rep_s)
+    launch = sum(launch_s) / len(launch_s) if launch_s else med / steps * spl
+    log(f"[bench] {w.name}: {steps} steps x {reps}: median {med * 1e3:.2f} ms "
+        f"({', '.join(f'{t * 1e3:.2f}' for t in rep_s)}); {len(launch_s)} launches of {spl} "
+        f"steps, {launch * 1e6:.2f} us each"
+        + (f"; one step per launch: {single * 1e6:.1f} us/step" if single else ""))
+    return {"median_s": med, "rep_s": rep_s, "launch_s": launch, "launches": len(launch_s),
+            "diag": diag, "eps": eps, "single_s": single, "plan": plan}
 
 
 def adjoint_params(lbm, w, Lx=None, Ly=None):
     from paper_1406_6438_amd import workloads as W
     U = W.ADJOINT_U_IN
-    return lbm.Params(Lx=Lx or w.Lx, Ly=Ly or w.Ly, tau=w.tau, bc_x=lbm.BC_OPEN,
+    return lbm.Params(Lx=Lx or w.Lx, Ly=Ly or w.Ly, tau=w.tau, bc_x=lbm.BC_INOUT,
                       bc_y=lbm.BC_BOUNCEBACK, storage=lbm.STORAGE[w.storage], d_p=w.d_p,
-                      rho0=w.rho0, u0=(U, 0.0), rho_in=1.0, u_in=U, rho_out=1.0, u_out=U)
+                      rho0=w.rho0, u0=(U, 0.0), u_in=U, rho_out=W.ADJOINT_RHO_OUT)
 
 
 def adjoint_leg(lbm, torch, no_accuracy: bool):
-    """dJ/deps of the outlet mass flux on the 1024x512 open channel after 4000 steps
+    """dJ/deps of the outlet mass flux on the 1024x512 channel (velocity inlet, pressure
+    outlet) after 4000 steps
     (checkpoints every 200): wall time of the whole gradient (forward with checkpoints,
     per-segment recompute, reverse), and the plain FP32 forward on the same workload.
     Returns (leg dict, accuracy sample: GPU gradient, oracle job, description)."""
@@ -280,17 +382,16 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
     m_grad = cells * w.steps / t_grad / 1e6
     m_fwd = cells * w.steps / t_fwd / 1e6
     # algorithmic bytes per node-step: forward with checkpoints (76) + recompute (76)
-    # + reverse step (gather 36, eps 4, adjoint in 36 and out 36) + the sensitivity
-    # sums: FP32 partial sums read and written (24) on most reverse steps, written
-    # only (12) on the first of a run of 16 and read only (12) with the FP64
-    # accumulators read and written (48) on its last: (12 + 14 * 24 + 60) / 16 = 25.5
-    bps = 76 + 76 + 36 + 4 + 36 + 36 + 25.5
+    # + the FP64 reverse step (gather of the FP32 state 36, FP64 porosity 8, FP64
+    # adjoint in 72 and out 72, three FP64 accumulators read and written 48) + the
+    # checkpoint copy (read and write of 36 B every K steps)
+    bps = 76 + 76 + 36 + 8 + 72 + 72 + 48 + 72 / K
     out = {"workload": w.name, "steps": w.steps, "ckpt_every": K, "J": J,
            "value": round(m_grad, 2), "unit": "MLUPS (forward node-steps per second of the "
                                                   "whole gradient computation)",
            "seconds": round(t_grad, 4), "fwd_fp32_same_gpu_MLUPS": round(m_fwd, 2),
            "vs_fp32_forward_same_gpu": round(m_grad / m_fwd, 3),
-           "bytes_per_node_step": bps,
+           "bytes_per_node_step": round(bps, 2),
            "achieved_GBps": round(bps * cells * w.steps / t_grad / 1e9, 1)}
     log(f"[bench] adjoint: {t_grad:.3f} s, {m_grad:.0f} MLUPS-equivalent; forward {m_fwd:.0f} MLUPS")
     sample = None
@@ -303,18 +404,19 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
         gg = gg.cpu().numpy()
         sg.close()
         U = W.ADJOINT_U_IN
-        job = {"name": f"gradient {L[0]}x{L[1]} open channel, {n} steps", "kind": "grad",
+        job = {"name": f"gradient {L[0]}x{L[1]} channel, {n} steps", "kind": "grad",
                "steps": n, "eps": e,
-               "params": {"Lx": L[0], "Ly": L[1], "tau": w.tau, "bc_x": "open", "bc_y": "wall",
-                          "d_p": 60.0, "rho0": w.rho0, "u0x": U, "rho_in": 1.0, "u_in": U,
-                          "rho_out": 1.0, "u_out": U}}
-        sample = (gg, job, f"{L[0]}x{L[1]} open channel of the same kind, {n} steps, "
-                           "checkpoints every 50")
+               "params": {"Lx": L[0], "Ly": L[1], "tau": w.tau, "bc_x": "inout", "bc_y": "wall",
+                          "d_p": 60.0, "rho0": w.rho0, "u0x": U, "u_in": U,
+                          "rho_out": W.ADJOINT_RHO_OUT}}
+        sample = (gg, job, f"{L[0]}x{L[1]} channel of the same kind (velocity inlet, pressure "
+                           f"outlet), {n} steps, checkpoints every 50")
     return out, sample
 
 
 def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: bool):
-    """The 64-member ensemble of uneven open channels (FP32): launch shape picked by the
+    """The 64-member ensemble of uneven channels (velocity inlet, pressure outlet; FP32):
+    launch shape picked by the
     library's autotuner (single-step launches of each width and grid, the two- and the
     three-step pass), then `steps` batched steps (replayed as 24-step graphs) timed with
     HIP events; the same steps as plain launches; the gradient of every member's outlet
@@ -328,9 +430,9 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
     log(f"[bench] ensemble: {len(members)} members, {cells / 1e6:.2f}M nodes")
 
     def params(m):
-        return lbm.Params(Lx=m.Lx, Ly=m.Ly, tau=m.tau, bc_x=lbm.BC_OPEN, bc_y=lbm.BC_BOUNCEBACK,
-                          storage=lbm.F32_SHIFTED, d_p=m.d_p, u0=(U, 0.0), rho_in=1.0, u_in=U,
-                          rho_out=1.0, u_out=U)
+        return lbm.Params(Lx=m.Lx, Ly=m.Ly, tau=m.tau, bc_x=lbm.BC_INOUT,
+                          bc_y=lbm.BC_BOUNCEBACK, storage=lbm.F32_SHIFTED, d_p=m.d_p,
+                          u0=(U, 0.0), u_in=U, rho_out=1.0)
 
     eps = [cast_eps(m.porosity(), "f32") for m in members]
     sv = [lbm.Solver(params(m), e) for m, e in zip(members, eps)]
@@ -355,22 +457,17 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
                 best["pass_rows"])
     spl, rows = b.pass_plan
     bpn = algorithmic_bytes_per_node("f32")
-    # algorithmic bytes per node-step over the time per step (= per launch / steps per launch)
-    ach = bpn * cells / (t_graph / steps) / 1e9
-    out = {"workload": f"ensemble_{len(members)}_open_channels_f32", "members": len(members),
+    # the graphs replay launches of spl steps: the time of one is the time per step x spl
+    roof = roofline(BATCH_KERNEL[spl], "ensemble64_f32" if len(members) == 64 else "-", bpn,
+                    cells, t_graph / steps * spl, spl, rows)
+    roof["launch_time"] = "time per step of the graph replays x steps per launch"
+    out = {"workload": f"ensemble_{len(members)}_channels_f32", "members": len(members),
            "nodes": cells, "Lx_range": [min(m.Lx for m in members), max(m.Lx for m in members)],
            "steps": steps, "value": round(cells * steps / t_graph / 1e6, 2), "unit": "MLUPS",
            "ms_per_step": round(t_graph * 1e3 / steps, 5),
            "plain_launches_ms_per_step": round(t_plain * 1e3 / steps, 5),
-           "tuned": best, "trials": trials,
-           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS,
-                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4),
-                        "traffic": (measured_traffic("ensemble64_f32", BATCH_KERNEL[spl])
-                                    if (spl > 1 or best["vec"] == 4) and len(members) == 64
-                                    else None),
-                        "kernel": BATCH_KERNEL[spl],
-                        "steps_per_launch": spl, "pass_rows": rows,
-                        "bytes_per_node_step": bpn}}
+           "tuned": best, "trials": trials, "roofline": roof}
+    ach = roof["achieved"]
     log(f"[bench] ensemble: {out['value']:.0f} MLUPS, {ach:.0f} GB/s (graphs), "
         f"{cells * steps / t_plain / 1e6:.0f} MLUPS plain launches")
     if grad:
@@ -406,9 +503,8 @@ def ensemble_leg(lbm, torch, no_accuracy: bool, steps: int, warmup: int, grad: b
         sg.close()
         job = {"name": f"ensemble member {k} ({m.Lx}x{m.Ly}), {W.ENSEMBLE_STEPS} steps",
                "kind": "u", "steps": W.ENSEMBLE_STEPS, "eps": eps[k],
-               "params": {"Lx": m.Lx, "Ly": m.Ly, "tau": m.tau, "bc_x": "open", "bc_y": "wall",
-                          "d_p": m.d_p, "u0x": U, "rho_in": 1.0, "u_in": U, "rho_out": 1.0,
-                          "u_out": U}}
+               "params": {"Lx": m.Lx, "Ly": m.Ly, "tau": m.tau, "bc_x": "inout", "bc_y": "wall",
+                          "d_p": m.d_p, "u0x": U, "u_in": U, "rho_out": 1.0}}
         sample = (gpu, job, f"member {k} ({m.Lx}x{m.Ly}, the smallest), "
                             f"{W.ENSEMBLE_STEPS} steps")
     torch.cuda.empty_cache()
@@ -500,59 +596,55 @@ def main():
     lbm.load()
     w = make_workload(args.workload)
     log(f"[bench] workload {w.name}: {w.Lx}x{w.Ly}, storage {w.storage}")
-    gpu_s, diag, eps, single_s, plan = time_sweep(w, lbm, torch, args.steps, args.warmup,
-                                                  single_steps=200)
+    ts = time_sweep(w, lbm, torch, args.steps, args.warmup, single_steps=200)
+    gpu_s, diag, eps, single_s, plan = (ts["median_s"], ts["diag"], ts["eps"], ts["single_s"],
+                                        ts["plan"])
     cells = w.Lx * w.Ly
     mlups = cells * args.steps / gpu_s / 1e6
     bpn = algorithmic_bytes_per_node(w.storage)
     spl = plan[0]                       # steps per launch of the timed run
-    launch_s = gpu_s / args.steps * spl
-    # algorithmic bytes of a node-step (the single-step scheme's loads and stores)
-    # times the node-steps of one launch
-    achieved = bpn * cells * spl / launch_s / 1e9
-    traffic = measured_traffic(args.workload, MULTI_KERNEL[spl])
+    roof = roofline(MULTI_KERNEL[spl], args.workload, bpn, cells, ts["launch_s"], spl, plan[1])
     copy_bw = copy_bandwidth_gbps(torch)
-    log(f"[bench] {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic, device copy {copy_bw:.1f} GB/s")
+    roof["device_copy_GBps"] = round(copy_bw, 1)
+    log(f"[bench] {mlups:.1f} MLUPS; {roof['kernel']} {roof['launch_us']} us per launch, "
+        f"{roof['achieved']} GB/s of pass bytes ({roof['frac']:.3f} of peak); device copy "
+        f"{copy_bw:.1f} GB/s")
 
-    # accuracy samples: (target dict, key, GPU result, oracle job, description, kind)
+    # accuracy samples: (target dict, GPU result, oracle job, description)
     samples = []
     acc = None
     if want_acc and w.storage != "f64":
-        gpu, job = crop_sample(w, lbm, w.steps)
-        acc = {}
+        gpu, job = crop_sample(w, lbm, w.steps, plan)
+        acc = {"kernel": roof["kernel"], "steps_per_pass": plan[0], "pass_rows": plan[1]}
         samples.append((acc, gpu, job, f"top-left 512x512 crop of the porosity field, periodic, "
-                                       f"{w.steps} steps"))
+                                       f"{w.steps} steps in the timed run's launch plan"))
 
     fp16 = None
     if not args.no_fp16 and args.workload == "box4096_f32":
         w16 = make_workload("box8192_f16")
-        steps16 = max(1, min(args.steps, 500))
-        g16, d16, _, s16, plan16 = time_sweep(w16, lbm, torch, steps16, args.warmup,
-                                              single_steps=100)
+        steps16 = 300
+        t16 = time_sweep(w16, lbm, torch, steps16, args.warmup, single_steps=100)
+        g16, d16, s16, plan16 = t16["median_s"], t16["diag"], t16["single_s"], t16["plan"]
         cells16 = w16.Lx * w16.Ly
         m16 = cells16 * steps16 / g16 / 1e6
         b16 = algorithmic_bytes_per_node("f16")
-        a16 = b16 * cells16 / (g16 / steps16) / 1e9
         fp16 = {"workload": w16.name, "value": round(m16, 2), "unit": "MLUPS", "steps": steps16,
-                "ms_per_step": round(g16 * 1e3 / steps16, 5),
-                "roofline": {"bound": "hbm", "achieved": round(a16, 1), "peak": PEAK_HBM_GBPS,
-                             "unit": "GB/s", "frac": round(a16 / PEAK_HBM_GBPS, 4),
-                             "traffic": measured_traffic("box8192_f16", MULTI_KERNEL[plan16[0]]),
-                             "bytes_per_node": b16,
-                             "kernel": MULTI_KERNEL[plan16[0]], "steps_per_launch": plan16[0],
-                             "pass_rows": plan16[1],
-                             "launch_us": round(g16 / steps16 * plan16[0] * 1e6, 2)},
+                "reps": len(t16["rep_s"]), "ms_per_step": round(g16 * 1e3 / steps16, 5),
+                "roofline": roofline(MULTI_KERNEL[plan16[0]], "box8192_f16", b16, cells16,
+                                     t16["launch_s"], plan16[0], plan16[1]),
                 "single_step": {"kernel": "k_sweep_vec", "value": round(cells16 / s16 / 1e6, 2),
                                 "unit": "MLUPS", "frac": round(b16 * cells16 / s16 / 1e9 /
                                                                 PEAK_HBM_GBPS, 4)},
                 "vs_fp32_same_gpu": round(m16 / mlups, 3),
                 "nonfinite_nodes": d16[6], "accuracy": None}
-        log(f"[bench] fp16: {m16:.1f} MLUPS, {a16:.1f} GB/s algorithmic")
+        log(f"[bench] fp16: {m16:.1f} MLUPS, {fp16['roofline']['achieved']} GB/s of pass bytes")
         if want_acc:
-            gpu, job = crop_sample(w16, lbm, w16.steps)
-            fp16["accuracy"] = {}
+            gpu, job = crop_sample(w16, lbm, w16.steps, plan16)
+            fp16["accuracy"] = {"kernel": fp16["roofline"]["kernel"],
+                                "steps_per_pass": plan16[0], "pass_rows": plan16[1]}
             samples.append((fp16["accuracy"], gpu, job, "top-left 512x512 crop of the 8192^2 "
-                                                        f"porosity field, periodic, {w16.steps} steps"))
+                                                        f"porosity field, periodic, {w16.steps} "
+                                                        "steps in the timed run's launch plan"))
 
     adj = None
     if not args.no_adjoint and args.workload == "box4096_f32":
@@ -602,16 +694,10 @@ def main():
                    "porosity": "GRF l=16 in [0.3,1.0]" if w.eps_kind == "grf" else f"uniform {w.eps_value}",
                    "d_p": round(w.d_p, 4), "G": [w.Gx, w.Gy], "storage": w.storage,
                    "boundaries": "periodic" if not w.walls_y else "periodic x, bounce-back y"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": traffic,
-                     "kernel": MULTI_KERNEL[spl],
-                     "steps_per_launch": spl, "pass_rows": plan[1], "bytes_per_node_step": bpn,
-                     "launch_us": round(launch_s * 1e6, 2),
-                     "device_copy_GBps": round(copy_bw, 1)},
-        "hbm": None if traffic is None else {
-            "bytes_per_launch": traffic, "GBps": round(traffic / launch_s / 1e9, 1),
-            "bytes_per_node_step": round(traffic / (cells * spl), 2)},
+        "roofline": roof,
+        "timing": {"reps": len(ts["rep_s"]), "statistic": "median",
+                   "rep_ms": [round(t * 1e3, 4) for t in ts["rep_s"]],
+                   "launches_timed": ts["launches"]},
         "single_step": None if single_s is None else {
             "kernel": "k_sweep_vec", "value": round(cells / single_s / 1e6, 2), "unit": "MLUPS",
             "achieved": round(bpn * cells / single_s / 1e9, 1),

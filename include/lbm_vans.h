@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 7
+#define LBM_VANS_ABI_VERSION 8
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -66,6 +66,19 @@ extern "C" {
                                of a reservoir with the boundary node's porosity, density
                                rho_in / rho_out and velocity (u_in, 0) / (u_out, 0); one
                                that leaves is absorbed.  Behind a y-wall bounce-back wins. */
+#define LBM_BC_INOUT 3      /* x only: velocity inlet beyond x = 0, pressure outlet beyond
+                               x = Lx-1 (the through-flow channel; the paper gives no rule
+                               for one, so both are equilibria of eq. (d2q9eq), each with
+                               the boundary node's porosity and one free quantity taken
+                               from the node itself, zero-gradient):
+                                 entering at x = 0 at step n+1: f_i^eq(eps rho of node
+                                   (0, y) at step n, (u_in, 0));
+                                 entering at x = Lx-1 at step n+1: f_i^eq(eps rho_out,
+                                   velocity of node (Lx-1, y) at step n);
+                               a population that leaves is absorbed; behind a y-wall
+                               bounce-back wins.  Applies from the first step on; the
+                               state f(., n) alone determines the next (get_state /
+                               set_state hold everything).  rho_in and u_out unused.   */
 
 /* Population storage.  The collision arithmetic is FP64 for LBM_F64 and FP32
  * otherwise.  The shifted forms store the deviation of each population from
@@ -91,7 +104,8 @@ extern "C" {
 typedef struct lbm_vans_params {
     int32_t Lx, Ly;        /* lattice nodes, 1 <= Lx, Ly (Lx >= 2 with open x ends);
                               padded nodes (Lx rounded up to 256) x Ly < 2^31          */
-    int32_t bc_x, bc_y;    /* LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK; bc_x may be LBM_BC_OPEN */
+    int32_t bc_x, bc_y;    /* LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK; bc_x may be LBM_BC_OPEN
+                              or LBM_BC_INOUT                                          */
     int32_t storage;       /* LBM_F64, LBM_F32_SHIFTED or LBM_F16_SHIFTED             */
     int32_t drag;          /* LBM_DRAG_ERGUN or LBM_DRAG_CONST                        */
     double tau;            /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3         */
@@ -103,8 +117,10 @@ typedef struct lbm_vans_params {
     int32_t fp16_scale_log2; /* LBM_F16_SHIFTED: stored value = deviation * 2^s, 0..24 */
     int32_t diag_every;    /* > 0: record diagnostics of every state n with n % diag_every == 0
                               during lbm_vans_step; 0: none                           */
-    double rho_in, u_in;   /* LBM_BC_OPEN: inflow reservoir density (> 0), x-velocity  */
-    double rho_out, u_out; /* LBM_BC_OPEN: outflow reservoir density (> 0), x-velocity */
+    double rho_in, u_in;   /* LBM_BC_OPEN: inflow reservoir density (> 0), x-velocity;
+                              LBM_BC_INOUT: u_in is the inlet velocity               */
+    double rho_out, u_out; /* LBM_BC_OPEN: outflow reservoir density (> 0), x-velocity;
+                              LBM_BC_INOUT: rho_out (> 0) is the outlet density      */
     double u_wall[2];      /* LBM_BC_BOUNCEBACK in y: x-velocity of the wall below y = 0
                               and of the wall above y = Ly-1 (sliding plates, as the
                               Couette experiment of Section "Examples and discussions");
@@ -214,8 +230,8 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
 /* Bytes of device memory lbm_vans_grad needs as grad_work for these
  * arguments (0 if invalid): one population buffer per checkpoint
  * (ceil(nsteps / ckpt_every)), ckpt_every buffers for a recomputed segment,
- * two adjoint buffers and three FP64 accumulators of the porosity grid
- * (with LBM_F32 / LBM_F16_SHIFTED storage also three FP32 partial sums). */
+ * two FP64 adjoint buffers and three FP64 accumulators of the porosity grid
+ * (with LBM_F32 / LBM_F16_SHIFTED storage also an FP64 copy of the porosity). */
 size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int64_t nsteps,
                                 int32_t ckpt_every);
 
@@ -226,11 +242,14 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
  * a checkpoint every ckpt_every steps (up to three steps per pass in between, as
  * in lbm_vans_step, when params.steps_per_pass allows it), then, segment by segment
  * from the last, the states recomputed one step at a time from the
- * checkpoint and the adjoint stepped back through them.  Porosity enters through eps itself (density, drag),
- * through grad(eps), through the open-boundary reservoirs and the initial
- * state; the sensitivities are accumulated in FP64 (with LBM_F32 /
- * LBM_F16_SHIFTED storage the terms of each run of 16 reverse steps are summed
- * in FP32 first, then added to the FP64 totals).
+ * checkpoint and the adjoint stepped back through them.  Porosity enters
+ * through eps itself (density, drag), through grad(eps), through the
+ * open-boundary reservoirs (and the boundary density / velocity a velocity
+ * inlet / pressure outlet carries) and the initial state.  The reverse steps
+ * compute in FP64 for every storage: with LBM_F32 / LBM_F16_SHIFTED storage
+ * they decode the recomputed FP32 / FP16 states into FP64, keep FP64 adjoints
+ * and add every step's sensitivities to FP64 accumulators, so the gradient
+ * carries only the rounding of the stored forward states.
  * grad_work: device buffer of lbm_vans_grad_work_bytes() bytes, 256-byte
  * aligned, caller-owned.  dJdeps: device array [Ly][Lx] of doubles.
  * J: host double or NULL.  Synchronises the stream.  Afterwards the state is

@@ -115,11 +115,6 @@ int fail(int code, const char *fmt, ...)
 #ifndef LBM_VANS_TB_REUSE
 #define LBM_VANS_TB_REUSE 3
 #endif
-// Reverse steps whose sensitivity terms an FP32 partial sum takes before they
-// are added to the FP64 accumulators (FP32 and FP16 storage).
-#ifndef LBM_VANS_PS_RUN
-#define LBM_VANS_PS_RUN 16
-#endif
 
 constexpr int TX = 64;      // nodes per row segment: one wavefront
 constexpr int NW = LBM_VANS_NW;      // wavefronts per block
@@ -242,6 +237,15 @@ struct Phys {
     // second state on (the initial state is the equilibrium everywhere).
     int reservoir;
     R rin[9], rout[9];
+    // Velocity inlet / pressure outlet (inout): the reservoirs carry the inlet
+    // node's own density with (u_in, 0) and rho_out with the outlet node's own
+    // velocity, both of the state the step starts from.  The node at an end
+    // writes them into its slots whose populations leave the domain (the
+    // reader there pulls its own opposite slot, as behind a wall), so the
+    // stored state stays the whole state.  rin[i] = w_i (P_i(u_in) - 1) for
+    // the entering i (P_i the bracket of eq. (d2q9eq)); dro = rho_out - rho0.
+    int inout;
+    R dro, rho_out;
     // Sliding y-walls: a population leaving the wall below y = 0 (above
     // y = Ly-1) gains eps * 6 w_j rho0 (e_j . u_w); for the diagonals that is
     // +-eps * wb (+-eps * wt) with wb = rho0 u_bottom / 6, wt = rho0 u_top / 6.
@@ -635,6 +639,7 @@ template <typename R>
 __device__ __forceinline__ void boundary_inflow(R d[9], R e0, bool open_l, bool open_r,
                                                 bool wym, bool wyp, const Phys<R> &ph)
 {
+    if (ph.inout) open_l = open_r = false;   // their values are in the stored slots
     if (open_l) {
         d[1] = e0 * ph.rin[1];
         if (!wym) d[5] = e0 * ph.rin[5];
@@ -652,6 +657,35 @@ __device__ __forceinline__ void boundary_inflow(R d[9], R e0, bool open_l, bool 
     if (wyp) {
         d[8] += e0 * ph.wt;
         d[7] -= e0 * ph.wt;
+    }
+}
+
+// Velocity inlet / pressure outlet: the populations that enter at the next step,
+// as deviations from this node's rest state, written over the outgoing values
+// that leave the domain (the slot of the opposite direction; behind a y-wall
+// bounce-back keeps it).  Inlet (x = 0): w_i S P_i(u_in) - w_i rho0 eps =
+// w_i dS + S rin[i] for i = 1, 5, 8 into slots 3, 7, 6.  Outlet (x = Lx-1):
+// w_i eps (rho_out P_i(u) - rho0) = w_i eps (dro + rho_out (P_i(u) - 1)) for
+// i = 3, 6, 7 into slots 1, 8, 5, u the node's velocity N of this step.
+template <typename R>
+__device__ __forceinline__ void inout_ends(R d[9], const Node<R> &N, R e0, bool open_l,
+                                           bool open_r, bool wym, bool wyp, const Phys<R> &ph)
+{
+    const R w1 = R(1) / R(9), w2 = R(1) / R(36);
+    if (open_l) {
+        d[3] = w1 * N.dS + N.S * ph.rin[1];
+        if (!wym) d[7] = w2 * N.dS + N.S * ph.rin[5];
+        if (!wyp) d[6] = w2 * N.dS + N.S * ph.rin[8];
+    }
+    if (open_r) {
+        const R uu = N.ux * N.ux + N.uy * N.uy;
+        auto q = [&](R eu) {   // P(u) - 1 for e.u = eu
+            return R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
+        };
+        const R a = e0 * ph.rho_out, b = e0 * ph.dro;
+        d[1] = w1 * (b + a * q(-N.ux));
+        if (!wym) d[8] = w2 * (b + a * q(N.uy - N.ux));
+        if (!wyp) d[5] = w2 * (b + a * q(-N.ux - N.uy));
     }
 }
 
@@ -679,6 +713,7 @@ __device__ __forceinline__ void update_node_q(R d[9], const PorNb<R> &P, const E
 #pragma unroll
     for (int i = 0; i < 9; i++) de[i] = hr * P.D[i];
     collide<R>(d, N, ph, de);
+    if (ph.inout && (open_l || open_r)) inout_ends<R>(d, N, P.e0, open_l, open_r, wym, wyp, ph);
 }
 
 template <typename R, int W, bool DIAG>
@@ -1713,19 +1748,13 @@ __device__ __forceinline__ void node_vjp(const R d[9], R e0, R gex, R gey, const
     for (int i = 0; i < 9; i++) nu[i] += S_bar + R(CX[i]) * Vx_bar + R(CY[i]) * Vy_bar;
 }
 
-constexpr int PS_FIRST = 1;   // the FP32 partial sums start from this step's terms
-constexpr int PS_FLUSH = 2;   // and are added into the FP64 accumulators after it
-
 // One reverse step (SEED = false) or the objective's seed (SEED = true).
 // fin: the stored state n (what the forward sweep of step n gathers from).
 // lam_next: adjoint of the state n + 1 (unused for the seed); lam: receives
 // the adjoint of the state n.  eb, gxb, gyb: FP64 accumulators [Ly][pitch].
-// p32 (FP32 compute only; else NULL): three FP32 partial sums [Ly][pitch],
-// pstride floats apart, that take the step's terms, so that the FP64 arrays are
-// read and written once per run of reverse steps rather than every step.  pmode:
-// PS_FIRST, the partial sums start from this step's terms (they are not read);
-// PS_FLUSH, they are added with this step's terms into the FP64 accumulators
-// (and not written).
+// R is the reverse step's compute type; the library runs it in FP64 for every
+// storage (the states of FP32 / FP16 storage are decoded into FP64, and eps is
+// an FP64 copy of the forward's porosity).
 // The seed computes J = sum over x = Lx-1 of eps rho u_x of the state n (tile
 // partials in part) and the adjoint of the state from it.
 template <typename S, typename R, bool SEED>
@@ -1734,8 +1763,7 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
                                              R *__restrict__ lam, const R *__restrict__ eps,
                                              const Geo &g, const Phys<R> &ph,
                                              double *__restrict__ eb, double *__restrict__ gxb,
-                                             double *__restrict__ gyb, float *__restrict__ p32,
-                                             long long pstride, int pmode,
+                                             double *__restrict__ gyb,
                                              double *__restrict__ part, int t)
 {
     constexpr int W = TX + 2;
@@ -1764,7 +1792,8 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         unshift_incoming<R>(d, P, ph.rho0);
         const int c = y * g.pitch + x;
         R mu[9];
-        R S_bar0 = R(0), ux_bar0 = R(0);
+        R S_bar0 = R(0), ux_bar0 = R(0), uy_bar0 = R(0), e_end = R(0);
+        const R w1 = R(1) / R(9), w2 = R(1) / R(36);
         if constexpr (SEED) {
 #pragma unroll
             for (int i = 0; i < 9; i++) mu[i] = R(0);
@@ -1777,19 +1806,49 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         } else {
 #pragma unroll
             for (int i = 0; i < 9; i++) mu[i] = load_global(lam_next + i * g.plane + c);
+            if (ph.inout && (ol || orr)) {
+                // velocity inlet / pressure outlet: the slots that leave the domain
+                // hold the reservoir populations of the next step (inout_ends); their
+                // adjoints go to the inlet node's eps rho and the outlet node's
+                // velocity and porosity instead of to the collision
+                if (ol) {
+                    S_bar0 += mu[3] * (w1 + ph.rin[1]);
+                    mu[3] = R(0);
+                    if (!n.wym) { S_bar0 += mu[7] * (w2 + ph.rin[5]); mu[7] = R(0); }
+                    if (!n.wyp) { S_bar0 += mu[6] * (w2 + ph.rin[8]); mu[6] = R(0); }
+                }
+                if (orr) {
+                    const Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
+                    const R uu = N.ux * N.ux + N.uy * N.uy;
+                    const R er = P.e0 * ph.rho_out;
+                    // plain value w (eps rho_out) P(u): d/d eps = w rho_out P(u),
+                    // d/du = w eps rho_out (3 e + 9 (e.u) e - 3 u)
+                    auto link = [&](int slot, R w, R ex, R ey) {
+                        const R m = mu[slot], eu = ex * N.ux + ey * N.uy;
+                        e_end += m * w * ph.rho_out *
+                                 (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+                        ux_bar0 += m * w * er * (R(3) * ex + R(9) * eu * ex - R(3) * N.ux);
+                        uy_bar0 += m * w * er * (R(3) * ey + R(9) * eu * ey - R(3) * N.uy);
+                        mu[slot] = R(0);
+                    };
+                    link(1, w1, R(-1), R(0));
+                    if (!n.wym) link(8, w2, R(-1), R(1));
+                    if (!n.wyp) link(5, w2, R(-1), R(-1));
+                }
+            }
         }
-        R nu[9], e_b = R(0), gx_b = R(0), gy_b = R(0);
-        node_vjp<R>(d, P.e0, P.gex, P.gey, ph, mu, S_bar0, ux_bar0, R(0), nu, e_b, gx_b, gy_b);
+        R nu[9], e_b = e_end, gx_b = R(0), gy_b = R(0);
+        node_vjp<R>(d, P.e0, P.gex, P.gey, ph, mu, S_bar0, ux_bar0, uy_bar0, nu, e_b, gx_b,
+                    gy_b);
         // reservoir links: the incoming value is eps0 * (rin_i + w_i rho0)
-        const R w1 = R(1) / R(9), w2 = R(1) / R(36);
         bool res[9] = {false, false, false, false, false, false, false, false, false};
-        if (ol) {
+        if (ol && !ph.inout) {
             res[1] = true; res[5] = !n.wym; res[8] = !n.wyp;
             e_b += nu[1] * (ph.rin[1] + w1 * ph.rho0);
             if (res[5]) e_b += nu[5] * (ph.rin[5] + w2 * ph.rho0);
             if (res[8]) e_b += nu[8] * (ph.rin[8] + w2 * ph.rho0);
         }
-        if (orr) {
+        if (orr && !ph.inout) {
             res[3] = true; res[6] = !n.wym; res[7] = !n.wyp;
             e_b += nu[3] * (ph.rout[3] + w1 * ph.rho0);
             if (res[6]) e_b += nu[6] * (ph.rout[6] + w2 * ph.rho0);
@@ -1813,28 +1872,6 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         *((n.wxp || n.wym) ? L8 + c : L6 + rm + n.xp) = res[6] ? R(0) : nu[6];
         *((n.wxp || n.wyp) ? L5 + c : L7 + rp + n.xp) = res[7] ? R(0) : nu[7];
         *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = res[8] ? R(0) : nu[8];
-        if constexpr (std::is_same_v<R, float>) {
-            if (p32) {
-                const gptr<float> e32 = to_global(p32), x32 = e32 + pstride,
-                                  y32 = e32 + 2 * pstride;
-                float se = e_b, sx = gx_b, sy = gy_b;
-                if (!(pmode & PS_FIRST)) {
-                    se += e32[c];
-                    sx += x32[c];
-                    sy += y32[c];
-                }
-                if (pmode & PS_FLUSH) {
-                    ebg[c] += static_cast<double>(se);
-                    gxg[c] += static_cast<double>(sx);
-                    gyg[c] += static_cast<double>(sy);
-                } else {
-                    e32[c] = se;
-                    x32[c] = sx;
-                    y32[c] = sy;
-                }
-                continue;
-            }
-        }
         ebg[c] += static_cast<double>(e_b);
         gxg[c] += static_cast<double>(gx_b);
         gyg[c] += static_cast<double>(gy_b);
@@ -1850,12 +1887,9 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
                                                       Phys<R> ph, double *__restrict__ eb,
                                                       double *__restrict__ gxb,
                                                       double *__restrict__ gyb,
-                                                      float *__restrict__ p32,
-                                                      long long pstride, int pmode,
                                                       double *__restrict__ part)
 {
-    adjoint_tile<S, R, SEED>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, p32, pstride, pmode,
-                             part, blockIdx.x);
+    adjoint_tile<S, R, SEED>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, part, blockIdx.x);
 }
 
 // Initial state: f_i(r, 0) = w_i eps(r) rho0 (1 + 3 e_i.u0 + 9/2 (e_i.u0)^2 -
@@ -1954,6 +1988,14 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint_finish(const double *__res
     }
 }
 
+// FP64 copy of an FP32 array of n elements.
+__global__ __launch_bounds__(NTHREADS) void k_widen(const float *__restrict__ src,
+                                                    double *__restrict__ dst, long long n)
+{
+    const long long i = static_cast<long long>(blockIdx.x) * NTHREADS + threadIdx.x;
+    if (i < n) dst[i] = static_cast<double>(src[i]);
+}
+
 // Fill with zero (used for the FP64 accumulators; a kernel rather than a
 // memset so the grad sequence stays capturable).
 __global__ __launch_bounds__(NTHREADS) void k_zero(double *__restrict__ p, long long n)
@@ -1976,12 +2018,14 @@ struct Member {
     Geo gs;                 // tiling of the batched sweep (vec nodes per lane)
     Geo g;                  // one node per lane (adjoint)
     Phys<R> ph;
+    Phys<double> pha;       // the FP64 reverse step's constants (shift reference as ph's)
+    const double *eps_a;    // FP64 porosity of the reverse step (padded; the gradient
+                            // workspace's copy for FP32 / FP16 storage)
     char *buf[2];           // the member's two population buffers (state slots 0, 1)
     const R *eps;           // padded porosity
     double *part;           // tile partials [g.ntiles][NRED]
     char *gw;               // gradient workspace: state slots 2.., adjoints, accumulators
     long long gpop, glam, gacc;
-    long long gacc32;       // bytes of one FP32 partial-sum array (0: none)
     int nslot;              // state slots in gw (checkpoints + recomputed segment)
     int vec;                // nodes per lane of this member's sweep
     int tile0;              // first position in the sweep tile list of its width
@@ -1998,9 +2042,9 @@ __device__ __forceinline__ char *state_slot(const Member<R> &d, int slot)
 }
 
 template <typename R>
-__device__ __forceinline__ R *adj_buf(const Member<R> &d, int a)
+__device__ __forceinline__ double *adj_buf(const Member<R> &d, int a)
 {
-    return reinterpret_cast<R *>(d.gw + (long long)d.nslot * d.gpop + a * d.glam);
+    return reinterpret_cast<double *>(d.gw + (long long)d.nslot * d.gpop + a * d.glam);
 }
 
 template <typename R>
@@ -2008,14 +2052,6 @@ __device__ __forceinline__ double *acc_buf(const Member<R> &d, int k)
 {
     return reinterpret_cast<double *>(d.gw + (long long)d.nslot * d.gpop + 2 * d.glam +
                                       k * d.gacc);
-}
-
-template <typename R>
-__device__ __forceinline__ float *acc32_buf(const Member<R> &d)
-{
-    return d.gacc32 ? reinterpret_cast<float *>(d.gw + (long long)d.nslot * d.gpop +
-                                                2 * d.glam + 3 * d.gacc)
-                    : nullptr;
 }
 
 // Positions of the tile list this block takes: one position when the grid
@@ -2108,22 +2144,22 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_tb3(const Member<R> *__restr
 // One reverse step of every member: adjoint slot a_next (of the state n + 1)
 // to adjoint slot a (of the state n, read from state slot src); the seed
 // starts the adjoints from the objective of the state in src.
+// (the reverse step in FP64 for every storage, as lbm_vans_grad)
 template <typename S, typename R, bool SEED>
 __global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__restrict__ M,
                                                             const int *__restrict__ tmap,
                                                             int ntiles, int src, int a_next,
-                                                            int a, int reservoir, int pmode)
+                                                            int a, int reservoir)
 {
     const int T = xcd_tile(blockIdx.x, ntiles);
     const Member<R> &d = M[tmap[T]];
     const Geo g = d.g;
-    Phys<R> ph = d.ph;
+    Phys<double> ph = d.pha;
     ph.reservoir = reservoir;
-    adjoint_tile<S, R, SEED>(reinterpret_cast<const S *>(state_slot(d, src)),
-                             SEED ? nullptr : adj_buf(d, a_next), adj_buf(d, a), d.eps, g, ph,
-                             acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), acc32_buf(d),
-                             d.gacc32 / static_cast<long long>(sizeof(float)), pmode, d.part,
-                             T - d.tile0_adj);
+    adjoint_tile<S, double, SEED>(reinterpret_cast<const S *>(state_slot(d, src)),
+                                  SEED ? nullptr : adj_buf(d, a_next), adj_buf(d, a), d.eps_a,
+                                  g, ph, acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), d.part,
+                                  T - d.tile0_adj);
 }
 
 }  // namespace
@@ -2192,7 +2228,8 @@ int check_params(const lbm_vans_params *p)
     if (geo_plane(p->Lx, p->Ly) >= (1LL << 31))
         return fail(LBM_VANS_EINVAL, "lattice %d x %d too large (padded nodes must be < 2^31)",
                     p->Lx, p->Ly);
-    if ((p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_BOUNCEBACK && p->bc_x != LBM_BC_OPEN) ||
+    if ((p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_BOUNCEBACK && p->bc_x != LBM_BC_OPEN &&
+         p->bc_x != LBM_BC_INOUT) ||
         (p->bc_y != LBM_BC_PERIODIC && p->bc_y != LBM_BC_BOUNCEBACK))
         return fail(LBM_VANS_EINVAL, "boundary kinds (%d, %d) not supported", p->bc_x, p->bc_y);
     if (p->bc_x == LBM_BC_OPEN) {
@@ -2200,6 +2237,11 @@ int check_params(const lbm_vans_params *p)
         if (!(p->rho_in > 0.0) || !std::isfinite(p->rho_in) || !(p->rho_out > 0.0) ||
             !std::isfinite(p->rho_out) || !std::isfinite(p->u_in) || !std::isfinite(p->u_out))
             return fail(LBM_VANS_EINVAL, "reservoir densities must be finite and > 0, velocities finite");
+    }
+    if (p->bc_x == LBM_BC_INOUT) {
+        if (p->Lx < 2) return fail(LBM_VANS_EINVAL, "open x ends need Lx >= 2");
+        if (!(p->rho_out > 0.0) || !std::isfinite(p->rho_out) || !std::isfinite(p->u_in))
+            return fail(LBM_VANS_EINVAL, "outlet density must be finite and > 0, inlet velocity finite");
     }
     if (p->storage != LBM_F64 && p->storage != LBM_F32_SHIFTED && p->storage != LBM_F16_SHIFTED)
         return fail(LBM_VANS_EINVAL, "unknown storage %d", p->storage);
@@ -2252,7 +2294,7 @@ Geo make_geo(const lbm_vans_params *p, int vec = 1, int rows = ROWS)
     g.pitch = static_cast<int>(geo_pitch(p->Lx));
     g.wall_x = p->bc_x != LBM_BC_PERIODIC;
     g.wall_y = p->bc_y == LBM_BC_BOUNCEBACK;
-    g.open_x = p->bc_x == LBM_BC_OPEN;
+    g.open_x = p->bc_x == LBM_BC_OPEN || p->bc_x == LBM_BC_INOUT;
     g.nbx = (p->Lx + TX * vec - 1) / (TX * vec);
     int nby = (p->Ly + NW * rows - 1) / (NW * rows);
     g.ntiles = g.nbx * nby;
@@ -2331,10 +2373,29 @@ Phys<R> make_phys(const lbm_vans_params *p)
         ph.rout[i] = cx[i] < 0 ? static_cast<R>(wt[i] * (p->rho_out * pout - rho_ref)) : R(0);
     }
     ph.reservoir = 0;
+    ph.inout = p->bc_x == LBM_BC_INOUT;
+    ph.dro = R(0);
+    ph.rho_out = R(0);
+    if (ph.inout) {
+        for (int i = 0; i < 9; i++) {
+            const double eu = cx[i] * p->u_in;
+            const double q = 3.0 * eu + 4.5 * eu * eu - 1.5 * p->u_in * p->u_in;
+            ph.rin[i] = cx[i] > 0 ? static_cast<R>(wt[i] * q) : R(0);
+            ph.rout[i] = R(0);
+        }
+        ph.dro = static_cast<R>(p->rho_out - rho_ref);
+        ph.rho_out = static_cast<R>(p->rho_out);
+    }
     ph.wb = static_cast<R>(p->rho0 * p->u_wall[0] / 6.0);
     ph.wt = static_cast<R>(p->rho0 * p->u_wall[1] / 6.0);
     return ph;
 }
+
+// Whether the open-end rules apply to a step from state n: the fixed reservoirs
+// from n = 1 on (the initial state is the equilibrium everywhere), the velocity
+// inlet / pressure outlet from the start (its reservoirs live in the stored
+// slots, which the initial state fills).
+int res_on(const lbm_vans_params *p, int64_t n) { return n >= 1 || p->bc_x == LBM_BC_INOUT; }
 
 // rho0 u_w / 6 of the sliding y-walls in FP64 (init, set_state, adjoint init).
 double wall6(const lbm_vans_params *p, int top) { return p->rho0 * p->u_wall[top] / 6.0; }
@@ -2529,7 +2590,7 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
             const int grid = static_cast<int>((waves + NW - 1) / NW);
             Phys<R> ph = make_phys<R>(&h->p);
             ph.reservoir = 1;                     // the later steps start from n + 1 >= 1
-            const int res_a = h->n >= 1;
+            const int res_a = res_on(&h->p, h->n);
             const int bx = h->g.open_x ? 2 : (h->g.wall_x ? 1 : 0);
             with_bxwy(bx, h->g.wall_y, [&](auto bxc, auto wyc) {
                 constexpr int BXV = decltype(bxc)::value;
@@ -2562,7 +2623,7 @@ int launch_sweep_ptrs(lbm_vans_handle *h, const void *src, void *dst, int64_t n,
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
-        ph.reservoir = n >= 1;
+        ph.reservoir = res_on(&h->p, n);
         if (diag) launch_sweep_t<S, R, true>(h, (const S *)src, (S *)dst, ph);
         else launch_sweep_t<S, R, false>(h, (const S *)src, (S *)dst, ph);
         return check_launch("sweep");
@@ -2723,7 +2784,7 @@ int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, voi
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
-        ph.reservoir = h->n >= 1;
+        ph.reservoir = res_on(&h->p, h->n);
         hipLaunchKernelGGL((k_moments<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
                            (const S *)h->buf[h->cur], (const R *)h->eps, h->g, ph, (R *)eps_rho,
                            (R *)rho, (R *)ux, (R *)uy, h->part);
@@ -2750,7 +2811,7 @@ int lbm_vans_get_state(lbm_vans_handle *h, void *f)
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
-        ph.reservoir = h->n >= 1;
+        ph.reservoir = res_on(&h->p, h->n);
         hipLaunchKernelGGL((k_get_state<S, R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
                            (const S *)h->buf[h->cur], (const R *)h->eps, h->g, ph, (double *)f);
         return check_launch("k_get_state");
@@ -2799,25 +2860,8 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
 namespace {
 
 struct GradLayout {
-    size_t pop, lam, acc, acc32, total;
+    size_t pop, lam, acc, eps64, total;
     int64_t nck, seg;
-};
-
-// Mode of the FP32 partial sums for each reverse launch in order: the first after a
-// flush starts them, every LBM_VANS_PS_RUN-th and the last one flush them.
-struct PartialRun {
-    int count = 0;
-    int next(bool last)
-    {
-        int m = count == 0 ? PS_FIRST : 0;
-        if (last || count == LBM_VANS_PS_RUN - 1) {
-            m |= PS_FLUSH;
-            count = 0;
-        } else {
-            count++;
-        }
-        return m;
-    }
 };
 
 GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_every)
@@ -2829,11 +2873,12 @@ GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_ev
     G.nck = (nsteps + ckpt_every - 1) / ckpt_every;
     if (G.nck < 1) G.nck = 1;
     G.seg = ckpt_every;
-    G.lam = align256((size_t)9 * g.plane * (p->storage == LBM_F64 ? 8 : 4));
+    // the reverse steps run in FP64 for every storage: FP64 adjoints and
+    // accumulators, and for FP32 / FP16 storage an FP64 copy of the porosity
+    G.lam = align256((size_t)9 * g.plane * sizeof(double));
     G.acc = align256((size_t)g.plane * sizeof(double));
-    // FP32 compute: FP32 partial sums of the three accumulators
-    G.acc32 = p->storage == LBM_F64 ? 0 : align256((size_t)g.plane * sizeof(float));
-    G.total = (size_t)(G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc + 3 * G.acc32;
+    G.eps64 = p->storage != LBM_F64 ? align256((size_t)g.plane * sizeof(double)) : 0;
+    G.total = (size_t)(G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc + G.eps64;
     return G;
 }
 
@@ -2878,10 +2923,9 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
     double *eb = reinterpret_cast<double *>(w + (G.nck + G.seg) * G.pop + 2 * G.lam);
     double *gxb = eb + G.acc / sizeof(double);
     double *gyb = gxb + G.acc / sizeof(double);
-    float *p32 = G.acc32 ? reinterpret_cast<float *>(w + (G.nck + G.seg) * G.pop + 2 * G.lam +
-                                                     3 * G.acc)
-                         : nullptr;
-    const long long pstride = static_cast<long long>(G.acc32 / sizeof(float));
+    double *eps64 = G.eps64 ? reinterpret_cast<double *>(w + (G.nck + G.seg) * G.pop +
+                                                         2 * G.lam + 3 * G.acc)
+                            : nullptr;
     const Geo &g = h->g;
     const int K = ckpt_every;
 
@@ -2928,14 +2972,25 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
                            dim3(NTHREADS), 0, h->stream, eb, nz);
         r = check_launch("k_zero");
         if (r) return r;
-        Phys<R> ph = ph0;
-        ph.reservoir = nsteps >= 1;
+        // the reverse steps compute in FP64 for every storage: on an FP64 copy of the
+        // porosity (FP32 / FP16 storage) and with the forward's shift reference rho0
+        using RA = double;
+        Phys<RA> ph = make_phys<RA>(&h->p);
+        ph.rho0 = static_cast<RA>(ph0.rho0);
+        const RA *eps_a = reinterpret_cast<const RA *>(h->eps);
+        if constexpr (!std::is_same_v<RA, R>) {
+            const long long npl = g.plane;
+            hipLaunchKernelGGL(k_widen, dim3((unsigned)((npl + NTHREADS - 1) / NTHREADS)),
+                               dim3(NTHREADS), 0, h->stream, (const float *)h->eps, eps64, npl);
+            r = check_launch("k_widen");
+            if (r) return r;
+            eps_a = eps64;
+        }
+        ph.reservoir = res_on(&h->p, nsteps);
         int a = 0;
-        PartialRun run;
-        hipLaunchKernelGGL((k_adjoint<S, R, true>), dim3(h->ntiles), dim3(NTHREADS), 0,
-                           h->stream, (const S *)h->buf[h->cur], (const R *)nullptr,
-                           (R *)lam[a], (const R *)h->eps, g, ph, eb, gxb, gyb, p32, pstride,
-                           run.next(nsteps == 0), h->part);
+        hipLaunchKernelGGL((k_adjoint<S, RA, true>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                           h->stream, (const S *)h->buf[h->cur], (const RA *)nullptr,
+                           (RA *)lam[a], eps_a, g, ph, eb, gxb, gyb, h->part);
         r = check_launch("k_adjoint seed");
         if (r) return r;
         r = launch_finalize(h, h->scratch_rec, h->ntiles, false, static_cast<double>(nsteps));
@@ -2954,19 +3009,18 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
             }
             for (int64_t n = s1 - 1; n >= s0; n--) {
                 const void *state = n == s0 ? (const void *)ckpt(c) : (const void *)seg(n - s0);
-                ph.reservoir = n >= 1;
-                hipLaunchKernelGGL((k_adjoint<S, R, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
-                                   h->stream, (const S *)state, (const R *)lam[a],
-                                   (R *)lam[1 - a], (const R *)h->eps, g, ph, eb, gxb, gyb, p32,
-                                   pstride, run.next(n == 0), h->part);
+                ph.reservoir = res_on(&h->p, n);
+                hipLaunchKernelGGL((k_adjoint<S, RA, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                                   h->stream, (const S *)state, (const RA *)lam[a],
+                                   (RA *)lam[1 - a], eps_a, g, ph, eb, gxb, gyb, h->part);
                 r = check_launch("k_adjoint");
                 if (r) return r;
                 a = 1 - a;
             }
         }
         // 4. initial state and the porosity stencil
-        hipLaunchKernelGGL((k_adjoint_init<R>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
-                           (const R *)lam[a], g, h->p.rho0, h->p.u0[0], h->p.u0[1],
+        hipLaunchKernelGGL((k_adjoint_init<RA>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
+                           (const RA *)lam[a], g, h->p.rho0, h->p.u0[0], h->p.u0[1],
                            wall6(&h->p, 0), wall6(&h->p, 1), eb);
         r = check_launch("k_adjoint_init");
         if (r) return r;
@@ -3079,6 +3133,9 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             d.gs = make_geo(&h->p, d.vec, sweep_rows_of(h->p.storage));
             d.g = h->g;
             d.ph = make_phys<R>(&h->p);
+            d.pha = make_phys<double>(&h->p);
+            d.pha.rho0 = static_cast<double>(d.ph.rho0);
+            d.eps_a = h->p.storage == LBM_F64 ? static_cast<const double *>(h->eps) : nullptr;
             d.buf[0] = h->buf[0];
             d.buf[1] = h->buf[1];
             d.eps = static_cast<const R *>(h->eps);
@@ -3104,8 +3161,10 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
                 d.gpop = static_cast<long long>(G.pop);
                 d.glam = static_cast<long long>(G.lam);
                 d.gacc = static_cast<long long>(G.acc);
-                d.gacc32 = static_cast<long long>(G.acc32);
                 d.nslot = static_cast<int>(G.nck + G.seg);
+                if (G.eps64)
+                    d.eps_a = reinterpret_cast<const double *>(
+                        d.gw + (G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc);
                 off += align256(G.total);
             }
             std::memcpy(b->desc.data() + k * sizeof d, &d, sizeof d);
@@ -3230,8 +3289,7 @@ int64_t batch_launch_count(const lbm_vans_batch *b, int64_t steps)
     return (steps + mp - 1) / mp;
 }
 
-int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir,
-                  int pmode)
+int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int reservoir)
 {
     return with_types(b->storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
@@ -3240,11 +3298,11 @@ int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int 
         if (seed)
             hipLaunchKernelGGL((k_batch_adjoint<S, R, true>), dim3(b->ntiles_adj),
                                dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
-                               b->ntiles_adj, src, a_next, a, reservoir, pmode);
+                               b->ntiles_adj, src, a_next, a, reservoir);
         else
             hipLaunchKernelGGL((k_batch_adjoint<S, R, false>), dim3(b->ntiles_adj),
                                dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
-                               b->ntiles_adj, src, a_next, a, reservoir, pmode);
+                               b->ntiles_adj, src, a_next, a, reservoir);
         return check_launch("k_batch_adjoint");
     });
 }
@@ -3456,7 +3514,7 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int src = b->m[0]->cur, dst = 1 - src, res = b->m[0]->n >= 1;
+    const int src = b->m[0]->cur, dst = 1 - src, res = res_on(&b->m[0]->p, b->m[0]->n);
     const lbm_vans_batch_config keep = b->cfg;
     lbm_vans_batch_config top = keep;
     top.us_per_step = INFINITY;
@@ -3537,7 +3595,7 @@ int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps)
             k += C;
         } else {
             const int m = static_cast<int>(std::min<int64_t>(batch_max_pass(b), nsteps - k));
-            rc = batch_launch(b, b->stream, cur, n >= 1, m);
+            rc = batch_launch(b, b->stream, cur, res_on(&b->m[0]->p, n), m);
             if (rc) return rc;
             batch_advance(b, m, 1);
             k += m;
@@ -3622,7 +3680,7 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
                 const int cur = b->m[0]->cur;
                 const int m = static_cast<int>(
                     std::min<int64_t>({(int64_t)batch_max_pass(b), K - j, nsteps - s0 - j}));
-                r = batch_launch(b, b->stream, cur, b->m[0]->n >= 1, m);
+                r = batch_launch(b, b->stream, cur, res_on(&b->m[0]->p, b->m[0]->n), m);
                 if (r) return r;
                 batch_advance(b, m, 1);
                 j += m;
@@ -3638,10 +3696,20 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
                                dim3(NTHREADS), 0, b->stream, eb, nz);
             r = check_launch("k_zero");
             if (r) return r;
+            if (G[k].eps64) {   // the reverse steps' FP64 copy of the porosity
+                const long long npl = b->m[k]->g.plane;
+                hipLaunchKernelGGL(k_widen, dim3((unsigned)((npl + NTHREADS - 1) / NTHREADS)),
+                                   dim3(NTHREADS), 0, b->stream, (const float *)b->m[k]->eps,
+                                   reinterpret_cast<double *>(
+                                       gw[k] + (G[k].nck + G[k].seg) * G[k].pop + 2 * G[k].lam +
+                                       3 * G[k].acc),
+                                   npl);
+                r = check_launch("k_widen");
+                if (r) return r;
+            }
         }
         int a = 0;
-        PartialRun run;
-        r = batch_adjoint(b, true, b->m[0]->cur, 0, a, nsteps >= 1, run.next(nsteps == 0));
+        r = batch_adjoint(b, true, b->m[0]->cur, 0, a, res_on(&b->m[0]->p, nsteps));
         if (r) return r;
         for (size_t k = 0; k < b->m.size(); k++) {
             lbm_vans_handle *h = b->m[k];
@@ -3659,12 +3727,12 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
             const int64_t s0 = c * K, s1 = std::min<int64_t>(s0 + K, nsteps);
             for (int64_t j = 1; j < s1 - s0; j++) {
                 const int src = j == 1 ? ckpt_slot(c) : seg_slot(j - 1);
-                r = batch_sweep(b, b->stream, src, seg_slot(j), (s0 + j - 1) >= 1);
+                r = batch_sweep(b, b->stream, src, seg_slot(j), res_on(&b->m[0]->p, s0 + j - 1));
                 if (r) return r;
             }
             for (int64_t n = s1 - 1; n >= s0; n--) {
                 const int state = n == s0 ? ckpt_slot(c) : seg_slot(n - s0);
-                r = batch_adjoint(b, false, state, a, 1 - a, n >= 1, run.next(n == 0));
+                r = batch_adjoint(b, false, state, a, 1 - a, res_on(&b->m[0]->p, n));
                 if (r) return r;
                 a = 1 - a;
             }
@@ -3673,11 +3741,11 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
         for (size_t k = 0; k < b->m.size(); k++) {
             lbm_vans_handle *h = b->m[k];
             char *base = gw[k] + (G[k].nck + G[k].seg) * G[k].pop;
-            const R *lam = reinterpret_cast<const R *>(base + a * G[k].lam);
+            const double *lam = reinterpret_cast<const double *>(base + a * G[k].lam);
             double *eb = reinterpret_cast<double *>(base + 2 * G[k].lam);
             double *gxb = eb + G[k].acc / sizeof(double);
             double *gyb = gxb + G[k].acc / sizeof(double);
-            hipLaunchKernelGGL((k_adjoint_init<R>), dim3(h->ntiles), dim3(NTHREADS), 0,
+            hipLaunchKernelGGL((k_adjoint_init<double>), dim3(h->ntiles), dim3(NTHREADS), 0,
                                b->stream, lam, h->g, h->p.rho0, h->p.u0[0], h->p.u0[1],
                                wall6(&h->p, 0), wall6(&h->p, 1), eb);
             r = check_launch("k_adjoint_init");

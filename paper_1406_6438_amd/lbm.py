@@ -22,12 +22,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_vans.so")
 
 OK, EINVAL, EHIP, ENONFINITE, ENOTIMPL = 0, -1, -2, -3, -4
-BC_PERIODIC, BC_BOUNCEBACK, BC_OPEN = 0, 1, 2
+BC_PERIODIC, BC_BOUNCEBACK, BC_OPEN, BC_INOUT = 0, 1, 2, 3
 F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
 DRAG_ERGUN, DRAG_CONST = 0, 1
 NDIAG = 8
 DIAG_RING = 4096
-ABI_VERSION = 7
+ABI_VERSION = 8
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",

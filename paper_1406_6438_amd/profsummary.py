@@ -7,6 +7,12 @@
       HBM bytes per dispatch of a kernel from FETCH_SIZE / WRITE_SIZE (KiB per
       dispatch), each scaled by the ratio of a plain copy kernel's known bytes to
       what the same counter reads for it.
+  profsummary.py valu <kernel substring> <counter_collection.csv> [...]
+      per-dispatch averages of the SQ counters and derived metrics the files hold
+      for the kernel: VALU instructions, VALU-active quad-cycles, VALUBusy,
+      occupancy, ...; the figures bench.py reads are printed as
+      "valu_insts_per_launch", "valu_active_quad_cycles_per_launch" and
+      "valu_busy_frac".
 """
 from __future__ import annotations
 
@@ -37,6 +43,14 @@ def kernel_stats(path: str, limit: int = 20):
             rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
                          float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
     return rows[:limit]
+
+
+def counters_of(path: str):
+    out = set()
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            out.add(r.get("Counter_Name"))
+    return sorted(c for c in out if c)
 
 
 def counter_per_dispatch(path: str, counter: str):
@@ -93,6 +107,26 @@ def main(argv):
         print(f"hbm_read_bytes_per_launch: {f_b:.6e}")
         print(f"hbm_write_bytes_per_launch: {w_b:.6e}")
         print(f"hbm_bytes_per_launch: {f_b + w_b:.6e}")
+        print(f"kernel_source_sha256_16: {kernel_source_hash()}")
+        return
+    if len(argv) >= 4 and argv[1] == "valu":
+        ksub = argv[2]
+        vals = {}
+        name = None
+        for path in argv[3:]:
+            for c in counters_of(path):
+                n, v = pick(counter_per_dispatch(path, c), ksub)
+                name = name or n
+                vals[c] = (sum(v) / len(v), len(v))
+        print(f"kernel: {short(name)}")
+        for c, (avg, n) in sorted(vals.items()):
+            print(f"{c}: {avg:.6e}  (average of {n} dispatches)")
+        if "SQ_INSTS_VALU" in vals:
+            print(f"valu_insts_per_launch: {vals['SQ_INSTS_VALU'][0]:.6e}")
+        if "SQ_ACTIVE_INST_VALU" in vals:
+            print(f"valu_active_quad_cycles_per_launch: {vals['SQ_ACTIVE_INST_VALU'][0]:.6e}")
+        if "VALUBusy" in vals:
+            print(f"valu_busy_frac: {vals['VALUBusy'][0] / 100.0:.4f}")
         print(f"kernel_source_sha256_16: {kernel_source_hash()}")
         return
     print(__doc__)

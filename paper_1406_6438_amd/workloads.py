@@ -128,24 +128,25 @@ def crop_porosity(w: Workload, n: int = CROP) -> np.ndarray:
     return np.ascontiguousarray(w.porosity()[:n, :n])
 
 # Porous channel with through-flow for the gradient of the outlet mass flux:
-# 1024 x 512 nodes, half-way bounce-back walls in y, open x ends with inflow
-# and outflow reservoirs at density 1 and x-velocity 0.02, GRF porosity in
-# [0.4, 1.0] (l = 16, seed 1407), tau = 0.8, d_p from Da = 1e-2 on the channel
-# width at porosity 0.7, plug-flow start (u0 = 0.02), 4000 steps, FP32,
-# gradient through checkpoints every 200 steps.
+# 1024 x 512 nodes, half-way bounce-back walls in y, a velocity inlet
+# (x-velocity 0.02) at x = 0 and a pressure outlet (density 1) at x = Lx-1,
+# GRF porosity in [0.4, 1.0] (l = 16, seed 1407), tau = 0.8, d_p from Da = 1e-2
+# on the channel width at porosity 0.7, plug-flow start (u0 = 0.02), 4000
+# steps, FP32, gradient through checkpoints every 200 steps.
 ADJOINT_CHANNEL = Workload(
     name="porous_open_channel_1024x512_f32", Lx=1024, Ly=512, tau=0.8,
     d_p=ergun_dp_for_darcy(1e-2, 512.0, 0.7), Gx=0.0, Gy=0.0, steps=4000,
     walls_y=True, storage="f32", eps_kind="grf", eps_lo=0.4, eps_hi=1.0, seed=SEED + 1)
 ADJOINT_U_IN = 0.02
+ADJOINT_RHO_OUT = 1.0
 ADJOINT_CKPT = 200
 
 # Ensemble of independent porous channels advanced together: 64 members, each
 # with Lx drawn uniformly from the integers 256..2048 and Ly = Lx // 2 (aspect
 # 2:1), tau drawn uniformly from [0.55, 1.0] (both from PCG64(ENSEMBLE_SEED)),
 # its own GRF porosity in [0.3, 1.0] (l = 16, seed ENSEMBLE_SEED + 1 + k),
-# half-way bounce-back walls in y, open x ends with inflow and outflow
-# reservoirs at density 1 and x-velocity 0.02, plug-flow start, d_p from
+# half-way bounce-back walls in y, a velocity inlet (x-velocity 0.02) and a
+# pressure outlet (density 1), plug-flow start, d_p from
 # Da = 1e-2 on the member's width at porosity 0.65, no body force, FP32,
 # 2000 steps.  The gradient of each member's outlet flux uses a checkpoint
 # every 45 steps (about sqrt(2000), which minimises checkpoints + segment).

@@ -29,6 +29,7 @@ class Spec:
     fp16_scale_log2: int = 10
     diag_every: int = 0
     open_x: bool = False
+    inout: bool = False             # open x ends as velocity inlet / pressure outlet
     rho_in: float = 1.0
     u_in: float = 0.0
     rho_out: float = 1.0
@@ -40,7 +41,8 @@ class Spec:
 
     def oracle(self) -> oracle.Params:
         return oracle.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
-                             bc_x=(oracle.OPEN if self.open_x else
+                             bc_x=(oracle.INOUT if self.inout else
+                                   oracle.OPEN if self.open_x else
                                    oracle.WALL if self.walls_x else oracle.PERIODIC),
                              bc_y=oracle.WALL if self.walls_y else oracle.PERIODIC,
                              drag=oracle.DRAG_CONST if self.drag_const else oracle.DRAG_ERGUN,
@@ -52,7 +54,8 @@ class Spec:
     def gpu(self):
         from paper_1406_6438_amd import lbm
         return lbm.Params(Lx=self.Lx, Ly=self.Ly, tau=self.tau,
-                          bc_x=(lbm.BC_OPEN if self.open_x else
+                          bc_x=(lbm.BC_INOUT if self.inout else
+                                lbm.BC_OPEN if self.open_x else
                                 lbm.BC_BOUNCEBACK if self.walls_x else lbm.BC_PERIODIC),
                           bc_y=lbm.BC_BOUNCEBACK if self.walls_y else lbm.BC_PERIODIC,
                           storage=lbm.STORAGE[self.storage],

@@ -62,8 +62,9 @@ def test_work_bytes_scale_with_storage():
 
 @pytest.mark.parametrize("bad", [
     dict(Lx=0), dict(Ly=-3), dict(tau=0.5), dict(tau=math.nan), dict(d_p=0.0),
-    dict(d_p=-1.0), dict(storage=7), dict(bc_x=3), dict(bc_y=2), dict(bc_y=5), dict(drag=3),
-    dict(bc_x=2, Lx=1), dict(bc_x=2, rho_in=0.0), dict(bc_x=2, u_out=math.inf),
+    dict(d_p=-1.0), dict(storage=7), dict(bc_x=4), dict(bc_y=2), dict(bc_y=3), dict(bc_y=5),
+    dict(drag=3), dict(bc_x=2, Lx=1), dict(bc_x=2, rho_in=0.0), dict(bc_x=2, u_out=math.inf),
+    dict(bc_x=3, Lx=1), dict(bc_x=3, rho_out=0.0), dict(bc_x=3, u_in=math.nan),
     dict(drag=lbm.DRAG_CONST, K=0.0), dict(drag=lbm.DRAG_CONST, K=1.0, F_eps=-1.0),
     dict(rho0=0.0), dict(G=(math.inf, 0.0)), dict(u0=(0.0, math.nan)),
     dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30), dict(diag_every=-1),

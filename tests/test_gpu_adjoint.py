@@ -143,13 +143,13 @@ def test_gradient_fp32_matches_oracle_adjoint(Lx):
     assert rel_l2(gg, go) <= 1e-4
 
 
-@pytest.mark.parametrize("nsteps", [0, 1, 15, 16, 17, 40])
-def test_gradient_fp32_partial_sums_ignore_stale_workspace(nsteps):
-    """FP32 storage sums each run of 16 reverse steps in FP32 before adding it to the
-    FP64 accumulators.  With the workspace filled with 0xFF bytes (NaN as FP32 and
-    FP64), step counts on both sides of a run boundary still match the oracle (a
-    partial sum read before its run's first write, or a run left unflushed at the
-    end, would show as NaN or as missing terms)."""
+@pytest.mark.parametrize("nsteps", [0, 1, 7, 8, 40])
+def test_gradient_fp32_ignores_stale_workspace(nsteps):
+    """With the gradient workspace filled with 0xFF bytes (NaN as FP32 and FP64), no
+    step count reads a buffer before writing it (the checkpoints, the recomputed
+    segment, the FP64 adjoints, accumulators and porosity copy): the gradient is
+    finite and matches the oracle, also for a step count that is a whole number of
+    checkpoint intervals (7 and 8 with K = 7) and for none at all."""
     from paper_1406_6438_amd import lbm
     spec = _open_spec(24, 10, "f32", tau=0.8, d_p=60.0, u0=(0.02, 0.0), rho_in=1.0,
                       u_in=0.02, rho_out=1.0, u_out=0.02, G=(0.0, 0.0))
@@ -164,7 +164,7 @@ def test_gradient_fp32_partial_sums_ignore_stale_workspace(nsteps):
     s.close()
     gg = g.cpu().numpy()
     Jo, go = oracle.grad_outlet_flux(spec.oracle(), spec.input_eps(eps), nsteps)
-    say(f"[grad f32 partial sums] {nsteps} steps: J rel err {abs(Jg - Jo) / abs(Jo):.3e}, "
+    say(f"[grad f32 stale workspace] {nsteps} steps: J rel err {abs(Jg - Jo) / abs(Jo):.3e}, "
         f"grad rel L2 {rel_l2(gg, go):.3e}")
     assert np.isfinite(gg).all()
     assert abs(Jg - Jo) <= 1e-5 * abs(Jo)
@@ -184,31 +184,53 @@ def test_autograd_function_backpropagates_library_gradient():
     assert np.abs(e.grad.cpu().numpy() - 2.5 * go).max() <= 1e-10 * np.abs(2.5 * go).max()
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden values not generated")
+def _golden():
+    if not os.path.exists(GOLDEN):
+        return None
+    gold = json.load(open(GOLDEN))
+    return gold if "dJdeps_central_difference_2h" in gold else None
+
+
+@pytest.mark.skipif(_golden() is None, reason="golden values not generated")
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_full_size_gradient_against_oracle_central_differences(storage):
-    """The 1024 x 512 open channel, 4000 steps, checkpoints every 200: J and dJ/deps at
-    six seeded nodes against the oracle's FP64 value and central differences.
-    The central differences carry J's FP64 rounding noise over 2h = 2e-5 (a few 1e-10).
-    FP64 storage is held to that; FP32 storage and arithmetic to 1e-3 of the largest
-    sampled value (FP32 noise of the adjoint field after 4000 steps)."""
-    gold = json.load(open(GOLDEN))
+    """The 1024 x 512 channel (velocity inlet 0.02, pressure outlet 1, walls in y), 4000
+    steps, checkpoints every 200: J and dJ/deps at 32 random nodes of the whole channel
+    against the oracle's FP64 J and central differences.
+
+    Each difference carries its own uncertainty (J's FP64 rounding over 2h, and the
+    O(h^2) truncation); the golden file holds differences at h and 2h, and
+    delta = |fd(h) - fd(2h)| stands for it.
+    * FP64: |g - fd| <= 1e-6 |fd| + 2 delta;
+    * FP32 storage (states stored and collided in FP32, reverse steps in FP64): the
+      gradient carries the FP32 rounding of the recomputed trajectory, an absolute
+      floor of about 1e-9 over the channel's interior (99th percentile 3.3e-9 against
+      the FP64 gradient of the same workload; 1.3e-7 of the largest |dJ/deps|, which
+      sits at the inlet): |g - fd| <= 1e-4 |fd| + 2 delta + 2e-8, and the relative L2
+      error over the 32 nodes <= 1e-4."""
+    gold = _golden()
     w = W.ADJOINT_CHANNEL
     U = W.ADJOINT_U_IN
-    say(f"[grad {storage} full size 1024x512, 4000 steps]")
-    spec = Spec(Lx=w.Lx, Ly=w.Ly, tau=w.tau, walls_y=True, open_x=True, d_p=w.d_p,
-                u0=(U, 0.0), rho_in=1.0, u_in=U, rho_out=1.0, u_out=U, storage=storage)
+    say(f"[grad {storage} full size 1024x512, 4000 steps, {len(gold['cells_yx'])} nodes]")
+    spec = Spec(Lx=w.Lx, Ly=w.Ly, tau=w.tau, walls_y=True, inout=True, d_p=w.d_p,
+                u0=(U, 0.0), u_in=U, rho_out=W.ADJOINT_RHO_OUT, storage=storage)
     # the golden values were made with the porosity rounded to FP32
     eps = w.porosity().astype(np.float32).astype(np.float64)
     J, g, _ = _grad_gpu(spec, eps, w.steps, W.ADJOINT_CKPT)
     fd = np.array(gold["dJdeps_central_difference"])
+    delta = np.abs(fd - np.array(gold["dJdeps_central_difference_2h"]))
     ad = np.array([g[y, x] for (y, x) in gold["cells_yx"]])
+    err = np.abs(ad - fd)
     say(f"  J {J:.12e} vs oracle {gold['J']:.12e}")
-    say(f"  adjoint             {ad}\n  central differences {fd}\n  |diff| {np.abs(ad - fd)}")
+    for (y, x), a_, f_, d_, e_ in zip(gold["cells_yx"], ad, fd, delta, err):
+        say(f"  ({y:3d},{x:4d}) adjoint {a_: .10e} fd {f_: .10e} delta {d_:.1e} "
+            f"|diff| {e_:.2e} rel {e_ / abs(f_):.1e}")
+    say(f"  rel L2 over the nodes {rel_l2(ad, fd):.3e}")
     if storage == "f64":
-        # 4000 steps x 524k nodes of FMA / summation-order differences: measured 1.8e-12
+        # 4000 steps x 524k nodes of FMA / summation-order differences
         assert abs(J - gold["J"]) <= 1e-11 * abs(gold["J"])
-        assert np.all(np.abs(ad - fd) <= 1e-3 * np.abs(fd) + 1e-9)
+        assert np.all(err <= 1e-6 * np.abs(fd) + 2 * delta)
     else:
         assert abs(J - gold["J"]) <= 1e-5 * abs(gold["J"])
-        assert np.all(np.abs(ad - fd) <= 1e-3 * np.abs(fd).max())
+        assert np.all(err <= 1e-4 * np.abs(fd) + 2 * delta + 2e-8)
+        assert rel_l2(ad, fd) <= 1e-4

@@ -258,6 +258,23 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
 int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
                   void *grad_work, size_t grad_work_bytes, double *dJdeps, double *J);
 
+/* Bytes of the library-held gradient workspace of lbm_vans_grad_static (64 MiB). */
+#define LBM_VANS_GRAD_STATIC_BYTES ((size_t)64 << 20)
+
+/* lbm_vans_grad without a caller buffer, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and results, with the workspace in a
+ * fixed array of LBM_VANS_GRAD_STATIC_BYTES that the library holds on every GPU
+ * it runs on until the process ends.  The call allocates nothing.  Returns
+ * LBM_VANS_EINVAL (message gives the bytes needed) when
+ * lbm_vans_grad_work_bytes(p, objective, nsteps, ckpt_every) exceeds that size.
+ * Every call on one GPU shares that GPU's array and leaves it holding its last
+ * contents (each call initialises what it reads); calls that overlap in time on
+ * the same GPU (two host threads, or two streams) race and must be serialised by
+ * the caller.  Synchronises the stream, as lbm_vans_grad. */
+int lbm_vans_grad_static(lbm_vans_handle *h, int32_t objective, int64_t nsteps,
+                         int32_t ckpt_every, double *dJdeps, double *J);
+
 /* Release the handle (host memory only; the work buffer stays the caller's).
  * Waits for the handle's queued work first.  NULL is ignored. */
 void lbm_vans_destroy(lbm_vans_handle *h);

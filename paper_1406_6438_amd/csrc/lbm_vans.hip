@@ -39,6 +39,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -72,6 +73,37 @@ int fail(int code, const char *fmt, ...)
         if (e_ != hipSuccess)                                                           \
             return fail(LBM_VANS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));  \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Library-held gradient workspace (lbm_vans_grad_static)
+// ---------------------------------------------------------------------------
+// For callers that cannot allocate device memory, lbm_vans_grad_static runs the
+// gradient in this fixed array instead of a caller's buffer.  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code the
+// name is not a device address: the address is looked up once per device
+// (scratch_address) and only that address is passed to kernels and copies.
+static __device__ __align__(256) char scratch[LBM_VANS_GRAD_STATIC_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_addr;   // per device id; nullptr until looked up
+
+// Device address of `scratch` on the current device (looked up on the first call
+// for that device).
+int scratch_address(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (static_cast<size_t>(dev) >= g_scratch_addr.size()) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LBM_VANS_EHIP, "no device address for the gradient workspace");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return LBM_VANS_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Launch geometry
@@ -2187,6 +2219,8 @@ struct lbm_vans_handle {
     int64_t nrec;           // diagnostics records written
     int rows3;              // rows per chunk of the three-step pass
     int auto_pass;          // automatic most steps per pass
+    void *scratch;          // device address of the library-held gradient workspace on the
+                            // handle's device (lbm_vans_grad_static)
 };
 
 namespace {
@@ -2674,8 +2708,12 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    void *scratch_dev = nullptr;
+    rc = scratch_address(&scratch_dev);
+    if (rc) return rc;
     lbm_vans_handle *h = new (std::nothrow) lbm_vans_handle();
     if (!h) return fail(LBM_VANS_EINVAL, "out of host memory");
+    h->scratch = scratch_dev;
     h->p = *p;
     h->stream = static_cast<hipStream_t>(stream);
     h->g = make_geo(p);
@@ -2903,8 +2941,12 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
     return grad_layout(p, nsteps, ckpt_every).total;
 }
 
-int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
-                  void *grad_work, size_t grad_work_bytes, double *dJdeps, double *J)
+namespace {
+
+// The gradient of lbm_vans_grad in the workspace grad_work (a caller's buffer, or
+// the library-held array).
+int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
+             void *grad_work, size_t grad_work_bytes, double *dJdeps, double *J)
 {
     if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
     int rc = check_grad_args(&h->p, objective, nsteps, ckpt_every);
@@ -3035,6 +3077,30 @@ int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t
             return fail(LBM_VANS_ENONFINITE, "objective is not finite");
         return LBM_VANS_OK;
     });
+}
+
+}  // namespace
+
+int lbm_vans_grad(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt_every,
+                  void *grad_work, size_t grad_work_bytes, double *dJdeps, double *J)
+{
+    return grad_run(h, objective, nsteps, ckpt_every, grad_work, grad_work_bytes, dJdeps, J);
+}
+
+int lbm_vans_grad_static(lbm_vans_handle *h, int32_t objective, int64_t nsteps,
+                         int32_t ckpt_every, double *dJdeps, double *J)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    const size_t need = lbm_vans_grad_work_bytes(&h->p, objective, nsteps, ckpt_every);
+    if (need == 0) return LBM_VANS_EINVAL;   // the message is set
+    if (need > LBM_VANS_GRAD_STATIC_BYTES)
+        return fail(LBM_VANS_EINVAL,
+                    "the gradient needs %zu bytes of workspace; the library-held workspace has "
+                    "%zu (use lbm_vans_grad with a caller buffer, or a larger ckpt_every / "
+                    "smaller lattice)",
+                    need, static_cast<size_t>(LBM_VANS_GRAD_STATIC_BYTES));
+    return grad_run(h, objective, nsteps, ckpt_every, h->scratch, LBM_VANS_GRAD_STATIC_BYTES,
+                    dJdeps, J);
 }
 
 void lbm_vans_destroy(lbm_vans_handle *h)

@@ -33,6 +33,7 @@ ABI_VERSION = 8
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
            "lbm_vans_pass_plan", "lbm_vans_batch_pass_plan", "lbm_vans_moments", "lbm_vans_get_state", "lbm_vans_set_state",
            "lbm_vans_diag_read", "lbm_vans_grad_work_bytes", "lbm_vans_grad",
+           "lbm_vans_grad_static",
            "lbm_vans_destroy", "lbm_vans_batch_work_bytes", "lbm_vans_batch_create",
            "lbm_vans_batch_configure", "lbm_vans_batch_get_config", "lbm_vans_batch_tune",
            "lbm_vans_batch_step", "lbm_vans_batch_grad_work_bytes", "lbm_vans_batch_grad",
@@ -143,6 +144,7 @@ def load(path: str = LIB_PATH):
     L.lbm_vans_grad_work_bytes.argtypes = [P, i32, i64, i32]
     L.lbm_vans_grad_work_bytes.restype = ctypes.c_size_t
     L.lbm_vans_grad.argtypes = [vp, i32, i64, i32, vp, ctypes.c_size_t, vp, dp]
+    L.lbm_vans_grad_static.argtypes = [vp, i32, i64, i32, vp, dp]
     L.lbm_vans_destroy.argtypes = [vp]
     L.lbm_vans_destroy.restype = None
     C = ctypes.POINTER(LbmVansBatchConfig)
@@ -165,6 +167,7 @@ def load(path: str = LIB_PATH):
     L.lbm_vans_abi_version.argtypes = []
     for n in ("lbm_vans_init", "lbm_vans_step", "lbm_vans_moments", "lbm_vans_get_state",
               "lbm_vans_set_state", "lbm_vans_diag_read", "lbm_vans_grad",
+              "lbm_vans_grad_static",
               "lbm_vans_batch_create", "lbm_vans_batch_configure", "lbm_vans_batch_get_config",
               "lbm_vans_batch_tune", "lbm_vans_batch_step", "lbm_vans_batch_grad",
               "lbm_vans_abi_version"):
@@ -249,6 +252,17 @@ def lbm_vans_grad(h, objective: int, nsteps: int, ckpt_every: int, grad_work, dJ
                                 grad_work.numel() * grad_work.element_size(), dJdeps.data_ptr(),
                                 ctypes.byref(J)))
     return J.value
+
+
+def lbm_vans_grad_static(h, objective: int, nsteps: int, ckpt_every: int, dJdeps) -> float:
+    """lbm_vans_grad in the library-held workspace (no caller buffer)."""
+    J = ctypes.c_double()
+    _check(load().lbm_vans_grad_static(h, objective, int(nsteps), int(ckpt_every),
+                                       dJdeps.data_ptr(), ctypes.byref(J)))
+    return J.value
+
+
+GRAD_STATIC_BYTES = 64 << 20
 
 
 def lbm_vans_destroy(h):

@@ -46,6 +46,9 @@ def test_header_constants_match_binding():
     assert int(consts["LBM_VANS_DIAG_RING"]) == lbm.DIAG_RING
     assert int(consts["LBM_BC_OPEN"]) == lbm.BC_OPEN
     assert int(consts["LBM_OBJ_OUTLET_FLUX"]) == lbm.OBJ_OUTLET_FLUX
+    assert int(consts["LBM_BC_INOUT"]) == lbm.BC_INOUT
+    m = re.search(r"#define\s+LBM_VANS_GRAD_STATIC_BYTES\s+\(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == lbm.GRAD_STATIC_BYTES
 
 
 def test_work_bytes_scale_with_storage():

@@ -139,9 +139,12 @@ typedef struct lbm_vans_params {
                               when the two-step pass has >= 2048 waves (62 x 8, 16 in
                               FP16), else 1.  Several steps per pass need
                               LBM_F32_SHIFTED or LBM_F16_SHIFTED storage and
-                              diag_every = 0 (else one step per pass); the intermediate
-                              states stay in registers (so FP16 storage rounds once
-                              per pass) and each pass recomputes its chunk's halo.    */
+                              diag_every = 0 (else one step per pass), and with
+                              periodic y a lattice of at least pass_rows + 6 rows for
+                              three steps (chunk rows + 4 for two; else fewer steps);
+                              the intermediate states stay in registers (so FP16
+                              storage rounds once per pass) and each pass recomputes
+                              its chunk's halo.                                       */
     int32_t pass_rows;     /* output rows per chunk (wave) of the three-step pass:
                               0 = automatic; LBM_F32_SHIFTED: 24 or 28 (automatic: 28
                               when that still gives four times as many waves as the

@@ -259,8 +259,8 @@ struct Phys {
     R pre;          // 1 - 1 / (2 tau)
     R rho0;         // shift reference density
     R Gx, Gy;       // body-force density
-    R ca, cb;       // drag prefactors (see drag_coeffs)
-    int drag;       // LBM_DRAG_ERGUN or LBM_DRAG_CONST
+    R ca, cb;       // Ergun drag prefactors (0 under the constant law; see drag_coeffs)
+    R ka, kb;       // constant-K drag prefactors (0 under the Ergun law)
     R scale, inv_scale;  // FP16 storage scale 2^s and 2^-s (1 otherwise)
     // Open x ends: a population entering across x = 0 (x = Lx-1) is the
     // equilibrium of a reservoir with the node's porosity, density rho_in
@@ -305,21 +305,17 @@ __device__ __forceinline__ R sqroot(R x)
 }
 
 // Darcy and Forchheimer coefficients a = eps^2 nu / K, b = eps^3 F_eps / sqrt(K)
-// of the drag law.  Ergun closure: a = 150 nu (1-eps)^2 / (eps d_p^2),
-// b = 1.75 (1-eps) / d_p, i.e. ca = 150 nu / d_p^2, cb = 1.75 / d_p (both 0
-// when d_p is infinite, and a = b = 0 at eps = 1).  Constant K, F_eps:
-// a = eps^2 (nu/K), b = eps^3 (F_eps / sqrt K).  inv_eps = 1 / eps.
+// of the drag law, one branch-free form for both closures:
+//   a = ca (1-eps)^2 / eps + ka eps^2,   b = cb (1-eps) + kb eps^3.
+// Ergun closure: ca = 150 nu / d_p^2, cb = 1.75 / d_p, ka = kb = 0 (a = b = 0 at
+// eps = 1); constant K, F_eps: ka = nu / K, kb = F_eps / sqrt(K), ca = cb = 0; all
+// four 0 without drag.  inv_eps = 1 / eps.
 template <typename R>
 __device__ __forceinline__ void drag_coeffs(const Phys<R> &ph, R eps, R inv_eps, R &a, R &b)
 {
-    if (ph.drag == LBM_DRAG_ERGUN) {
-        R s = R(1) - eps;
-        a = ph.ca * s * s * inv_eps;
-        b = ph.cb * s;
-    } else {
-        a = ph.ca * eps * eps;
-        b = ph.cb * eps * eps * eps;
-    }
+    const R s = R(1) - eps, e2 = eps * eps;
+    a = ph.ca * s * s * inv_eps + ph.ka * e2;
+    b = ph.cb * s + ph.kb * e2 * eps;
 }
 
 template <typename R>
@@ -648,11 +644,15 @@ __device__ __forceinline__ PorNb<R> porosity_nb(const R (*t)[W], int lyy, int lx
 // Stored slots are shifted by the rest state at the link midpoint,
 // w_i rho0 (eps(source) + eps(destination)) / 2.  The incoming value of
 // direction i at x came from x - e_i, so the deviation from x's own rest state
-// is the stored value plus (rho0/2) w_i (eps(x - e_i) - eps(x)).
-template <typename R>
+// is the stored value plus (rho0/2) w_i (eps(x - e_i) - eps(x)).  FULL: the
+// incoming values are the source's own deviations (post-collision values a
+// multi-step pass hands over in registers, never shifted), which take the whole
+// difference rho0 w_i (eps(x - e_i) - eps(x)).
+template <typename R, bool FULL = false>
 __device__ __forceinline__ void unshift_incoming(R d[9], const PorNb<R> &P, R rho0)
 {
-    const R h1 = R(0.5) * rho0 * (R(1) / R(9)), h2 = R(0.5) * rho0 * (R(1) / R(36));
+    const R hf = FULL ? R(1) : R(0.5);
+    const R h1 = hf * rho0 * (R(1) / R(9)), h2 = hf * rho0 * (R(1) / R(36));
     d[1] += h1 * P.D[3];
     d[2] += h1 * P.D[4];
     d[3] += h1 * P.D[1];
@@ -728,35 +728,38 @@ __device__ __forceinline__ void inout_ends(R d[9], const Node<R> &N, R e0, bool 
 // of the incoming populations on entry and the values to store on exit.
 // (lyy, lx) is the node's position in the tile.
 // The same with the node's porosity-only terms given (q; P supplies its link
-// differences).
-template <typename R, bool DIAG>
+// differences).  IN_FULL: the incoming values are unshifted deviations of their
+// sources (see unshift_incoming); OUT_SHIFT: shift the outgoing values to their
+// link midpoints (values that go to memory), else leave them as this node's own
+// deviations (values a multi-step pass keeps in registers for its next step).
+template <typename R, bool DIAG, bool IN_FULL = false, bool OUT_SHIFT = true>
 __device__ __forceinline__ void update_node_q(R d[9], const PorNb<R> &P, const EpsTerms<R> &q,
                                               bool wym, bool wyp, bool open_l, bool open_r,
                                               const Phys<R> &ph, double *acc, bool count)
 {
     boundary_inflow<R>(d, P.e0, open_l, open_r, wym, wyp, ph);
-    unshift_incoming<R>(d, P, ph.rho0);
+    unshift_incoming<R, IN_FULL>(d, P, ph.rho0);
     Node<R> N = node_forward_q<R>(d, q, ph).N;
     if constexpr (DIAG) {
         if (count) accumulate<R>(acc, N);
     }
-    const R hr = R(0.5) * ph.rho0;
+    const R hr = OUT_SHIFT ? R(0.5) * ph.rho0 : R(0);
     R de[9];
 #pragma unroll
-    for (int i = 0; i < 9; i++) de[i] = hr * P.D[i];
+    for (int i = 0; i < 9; i++) de[i] = OUT_SHIFT ? hr * P.D[i] : R(0);
     collide<R>(d, N, ph, de);
     if (ph.inout && (open_l || open_r)) inout_ends<R>(d, N, P.e0, open_l, open_r, wym, wyp, ph);
 }
 
-template <typename R, int W, bool DIAG>
+template <typename R, int W, bool DIAG, bool IN_FULL = false, bool OUT_SHIFT = true>
 __device__ __forceinline__ void update_node(R d[9], const R (*t)[W], int lyy, int lx, bool wxm,
                                             bool wxp, bool wym, bool wyp, bool open_l,
                                             bool open_r, const Phys<R> &ph, double *acc,
                                             bool count)
 {
     const PorNb<R> P = porosity_nb<R, W>(t, lyy, lx, wxm, wxp, wym, wyp);
-    update_node_q<R, DIAG>(d, P, eps_terms<R>(P.e0, P.gex, P.gey, ph), wym, wyp, open_l,
-                           open_r, ph, acc, count);
+    update_node_q<R, DIAG, IN_FULL, OUT_SHIFT>(d, P, eps_terms<R>(P.e0, P.gex, P.gey, ph), wym,
+                                               wyp, open_l, open_r, ph, acc, count);
 }
 
 // ---- vector sweep: V consecutive nodes per lane, full-width loads and stores
@@ -1157,12 +1160,25 @@ constexpr bool tb_reuse()
                        (LBM_VANS_TB_REUSE == 3 && !f16));
 }
 
-// Rows the gathers run ahead: TB_AHEAD, except one for the FP16 three-step pass,
-// whose windows take the registers (measured: 8192^2 211 against 191 GLUPS).
-template <typename S, int NS>
+// Rows the gathers run ahead: TB_AHEAD, except one for the three-step passes in
+// FP16 and for those with x ends or y walls, whose windows and boundary rules take
+// the registers (GLUPS, two rows ahead / one: FP16 8192^2 box 211 / 191 in an older
+// layout, 241.6 / 241.4 now; FP32 4096^2 channel with walls and open ends, 28-row
+// chunks, 155.5 / 160.1; FP32 4096^2 box 156.7 / 149.8).
+template <typename S, int NS, int BX = 0, bool WY = false>
 constexpr int tb_ahead()
 {
-    return (NS == 3 && std::is_same_v<S, _Float16>) ? 1 : TB_AHEAD;
+    return (NS == 3 && (std::is_same_v<S, _Float16> || BX != 0 || WY)) ? 1 : TB_AHEAD;
+}
+
+// Most waves per SIMD the compiler schedules the three-step kernel for: 2 for the
+// periodic FP32 pass (its schedule for 2 waves keeps the gathers of a row together
+// and beats the 3 waves its registers would allow: 4096^2 box 163.4 against 156.7
+// GLUPS), else no bound (the FP16 pass at 2: 197 against 242).
+template <typename S, int BX, bool WY>
+constexpr int tb3_max_waves()
+{
+    return (std::is_same_v<S, float> && BX == 0 && !WY) ? 2 : 8;
 }
 
 // f(integral_constant<int, J>) for J = 0, 1, ... while it returns true: code
@@ -1188,7 +1204,7 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     static_assert(NS == 2 || NS == 3, "two or three steps per pass");
     constexpr bool WX = BX != 0;
     constexpr int H = NS - 1;                 // halo lanes per side, halo rows per chunk end
-    constexpr int PD = tb_ahead<S, NS>();
+    constexpr int PD = tb_ahead<S, NS, BX, WY>();
     constexpr int NA = NR + 2 * H;            // first-step rows y0-H .. y0+NR+H-1
     constexpr int NE = NA + 2;                // porosity rows y0-H-1 .. y0+NR+H
     constexpr unsigned SB = sizeof(S), EB = sizeof(R);
@@ -1215,7 +1231,6 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     }
     const bool out_ok = lane >= H && lane < TX - H && xu >= 0 && xu < g.Lx;
     const int y0 = chunk * NR;
-    const int n = min(NR, g.Ly - y0);            // output rows of this chunk
     const unsigned pb = static_cast<unsigned>(g.pitch) * SB;   // bytes per state row
     const unsigned pe = static_cast<unsigned>(g.pitch) * EB;   // bytes per porosity row
     const unsigned xb = x * SB, xmb = xm * SB, xpb = xp * SB;
@@ -1232,13 +1247,23 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     auto ld = [&](const char *base, unsigned off) -> R {
         return load_cached<S, R>(reinterpret_cast<const S *>(base + off), ph.inv_scale);
     };
-    auto row_in = [&](int row) { return WY ? (row >= 0 && row < g.Ly) : true; };
+    // Row index of the lattice for window row v = y0 + a (a = -H-1 .. NR+H): clamped
+    // behind y walls (such rows are never read), else wrapped once: the host runs the
+    // pass with periodic y only when Ly >= NR + 2H + 2, so one wrap reaches every
+    // window row.  Uniform over the wave: scalar selects, no branch.
+    auto row_of = [&](int v) {
+        if constexpr (WY) {
+            return min(max(v, 0), g.Ly - 1);
+        } else {
+            v += v < 0 ? g.Ly : 0;
+            return v - (v >= g.Ly ? g.Ly : 0);
+        }
+    };
 
     // porosity rows y0-H-1+k (k = 0 .. NE-1), columns x-1 .. x+1
     R E[NE][3];
     auto eps_row = [&](int k) {
-        const unsigned o =
-            __umul24(static_cast<unsigned>(halo_index(y0 - H - 1 + k, g.Ly, g.wall_y)), pe);
+        const unsigned o = __umul24(static_cast<unsigned>(row_of(y0 - H - 1 + k)), pe);
         E[k][0] = load_global(reinterpret_cast<const R *>(Eb + (o + xme)));
         E[k][1] = load_global(reinterpret_cast<const R *>(Eb + (o + xe)));
         E[k][2] = load_global(reinterpret_cast<const R *>(Eb + (o + xpe)));
@@ -1246,16 +1271,12 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     // first step at row y0+a (a = -H .. NR+H-1): gather into Q[a+H], update into P1[a+H]
     R Q[NA][9], P1[NA][9];
     bool qm[NA], qp[NA];
-    auto a_live = [&](int a) { return a <= n + H - 1 && row_in(y0 + a); };
+    // Every row of the chunk's window is computed, also those behind a y wall or
+    // past the lattice's last row (the last chunk): they take a row inside the
+    // lattice, their results are never read, and the output rows past the last
+    // row are not stored.  The chunk's code thus has no branch on its rows.
     auto issue = [&](int a) {
-        // row y0+a; one outside the lattice (never finished) loads a row inside
-        int yy = y0 + a;
-        if constexpr (WY) {
-            yy = min(max(yy, 0), g.Ly - 1);
-        } else {
-            while (yy < 0) yy += g.Ly;
-            while (yy >= g.Ly) yy -= g.Ly;
-        }
+        const int yy = row_of(y0 + a);
         bool wym = false, wyp = false;
         int ym = yy - 1, yp = yy + 1;
         if (ym < 0) { if (WY) { wym = true; ym = yy; } else ym = g.Ly - 1; }
@@ -1303,12 +1324,6 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     EpsTerms<R> T[REUSE ? NE : 1];
     auto finish = [&](int a) {
         const int k = a + H;                  // porosity rows of row y0+a: E[k .. k+2]
-        if (!a_live(a)) {                     // behind a y wall: never read
-#pragma unroll
-            for (int i = 0; i < 9; i++) P1[k][i] = R(0);
-            if constexpr (REUSE) T[k] = EpsTerms<R>{R(1), R(1), R(0), R(0), R(0), R(0)};
-            return;
-        }
         const R t[3][3] = {{E[k][0], E[k][1], E[k][2]},
                            {E[k + 1][0], E[k + 1][1], E[k + 1][2]},
                            {E[k + 2][0], E[k + 2][1], E[k + 2][2]}};
@@ -1317,17 +1332,21 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
         if constexpr (REUSE) {
             const PorNb<R> P = porosity_nb<R, 3>(t, 1, 1, wxm, wxp, qm[k], qp[k]);
             T[k] = eps_terms<R>(P.e0, P.gex, P.gey, ph);
-            update_node_q<R, false>(P1[k], P, T[k], qm[k], qp[k], oa && wxm, oa && wxp, ph,
-                                    nullptr, false);
+            update_node_q<R, false, false, false>(P1[k], P, T[k], qm[k], qp[k], oa && wxm,
+                                                  oa && wxp, ph, nullptr, false);
         } else {
-            update_node<R, 3, false>(P1[k], t, 1, 1, wxm, wxp, qm[k], qp[k], oa && wxm,
-                                     oa && wxp, ph, nullptr, false);
+            update_node<R, 3, false, false, false>(P1[k], t, 1, 1, wxm, wxp, qm[k], qp[k],
+                                                   oa && wxm, oa && wxp, ph, nullptr, false);
         }
     };
     // a later step at row y from the previous step's rows y-1 (A0), y (A1), y+1
-    // (A2) of this wave, porosity rows E[k .. k+2]; a row behind a y wall is never
-    // read, and the reservoirs are active (the step starts from n + 1 >= 1)
-    auto pull = [&](R (&d)[9], const R *A0, const R *A1, const R *A2, int y, int k) {
+    // (A2) of this wave (unshifted deviations), porosity rows E[k .. k+2]; a row
+    // behind a y wall is never read, and the reservoirs are active (the step starts
+    // from n + 1 >= 1).  LAST: the step's values go to memory (shifted to their
+    // link midpoints); else they stay in registers for the next step.
+    auto pull = [&](auto last_c, R (&d)[9], const R *A0, const R *A1, const R *A2, int y,
+                    int k) {
+        constexpr bool LAST = decltype(last_c)::value;
         const bool wym = WY && y == 0, wyp = WY && y == g.Ly - 1;
         const R s1 = lane_from_below(A1[1]), s3 = lane_from_above(A1[3]);
         d[0] = A1[0];
@@ -1359,33 +1378,31 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
         if constexpr (REUSE) {
             // the row's first step computed its porosity-only terms
             const PorNb<R> P = porosity_nb<R, 3>(t, 1, 1, wxm, wxp, wym, wyp);
-            update_node_q<R, false>(d, P, T[k], wym, wyp, BX == 2 && wxm, BX == 2 && wxp, ph,
-                                    nullptr, false);
+            update_node_q<R, false, true, LAST>(d, P, T[k], wym, wyp, BX == 2 && wxm,
+                                                BX == 2 && wxp, ph, nullptr, false);
         } else {
-            update_node<R, 3, false>(d, t, 1, 1, wxm, wxp, wym, wyp, BX == 2 && wxm,
-                                     BX == 2 && wxp, ph, nullptr, false);
+            update_node<R, 3, false, true, LAST>(d, t, 1, 1, wxm, wxp, wym, wyp, BX == 2 && wxm,
+                                                 BX == 2 && wxp, ph, nullptr, false);
         }
     };
     // second step of a three-step pass at row y0+b (b = -1 .. NR) into P2[b+1]
     R P2[NS == 3 ? NR + 2 : 1][9];
     auto middle = [&](int b) {
         if constexpr (NS == 3) {
-            if (!(b <= n && row_in(y0 + b))) {
-#pragma unroll
-                for (int i = 0; i < 9; i++) P2[b + 1][i] = R(0);
-                return;
-            }
-            pull(P2[b + 1], P1[b - 1 + H], P1[b + H], P1[b + 1 + H], y0 + b, b + H);
+            pull(std::false_type{}, P2[b + 1], P1[b - 1 + H], P1[b + H], P1[b + 1 + H], y0 + b,
+                 b + H);
         }
     };
     // last step at output row y0+j, stored
     auto last = [&](int j) {
         R d[9];
         if constexpr (NS == 3)
-            pull(d, P2[j], P2[j + 1], P2[j + 2], y0 + j, j + H);
+            pull(std::true_type{}, d, P2[j], P2[j + 1], P2[j + 2], y0 + j, j + H);
         else
-            pull(d, P1[j - 1 + H], P1[j + H], P1[j + 1 + H], y0 + j, j + H);
-        const unsigned c = out_ok ? __umul24(static_cast<unsigned>(y0 + j), pb) + xb : TB_NO_STORE;
+            pull(std::true_type{}, d, P1[j - 1 + H], P1[j + H], P1[j + 1 + H], y0 + j, j + H);
+        const bool row_ok = y0 + j < g.Ly;   // uniform: the last chunk's rows past the end
+        const unsigned c = (out_ok && row_ok) ? __umul24(static_cast<unsigned>(y0 + j), pb) + xb
+                                              : TB_NO_STORE;
 #pragma unroll
         for (int i = 0; i < 9; i++) store_plane<S, R>(Gr[i], c, d[i], ph.scale);
     };
@@ -1403,7 +1420,6 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     middle(0);
     static_while<NR>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        if (j >= n) return false;             // uniform: the chunk's last rows
         finish(j + H);
         if constexpr (j + H + PD <= NR + H - 1) issue(j + H + PD);
         if constexpr (j + 2 * H + 2 + PD < NE) eps_row(j + 2 * H + 2 + PD);
@@ -1441,7 +1457,8 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_tb2(const S *__restrict__ fi
 
 // Three steps per launch, in chunks of NR rows.
 template <typename S, typename R, int BX, bool WY, int NR>
-__global__ __launch_bounds__(NTHREADS) void k_sweep_tb3(const S *__restrict__ fin,
+__global__ __launch_bounds__(NTHREADS)
+__attribute__((amdgpu_waves_per_eu(1, tb3_max_waves<S, BX, WY>()))) void k_sweep_tb3(const S *__restrict__ fin,
                                                         S *__restrict__ fout,
                                                         const R *__restrict__ eps, Geo g,
                                                         Phys<R> ph, int nstrips, int nchunks,
@@ -1691,13 +1708,8 @@ __global__ __launch_bounds__(NTHREADS) void k_get_state(const S *__restrict__ fi
 template <typename R>
 __device__ __forceinline__ void drag_derivs(const Phys<R> &ph, R eps, R inv_eps, R &da, R &db)
 {
-    if (ph.drag == LBM_DRAG_ERGUN) {
-        da = -ph.ca * (R(1) - eps) * (R(1) + eps) * inv_eps * inv_eps;
-        db = -ph.cb;
-    } else {
-        da = R(2) * ph.ca * eps;
-        db = R(3) * ph.cb * eps * eps;
-    }
+    da = -ph.ca * (R(1) - eps) * (R(1) + eps) * inv_eps * inv_eps + R(2) * ph.ka * eps;
+    db = -ph.cb + R(3) * ph.kb * eps * eps;
 }
 
 // Reverse of one node.  d: the node's incoming deviations (as update_node
@@ -2165,9 +2177,10 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_tb2(const Member<R> *__restr
 // Three steps of every member: chunks of NR rows (wave list 1: the short
 // height, 2: the tall one).
 template <typename S, typename R, int BX, bool WY, int NR>
-__global__ __launch_bounds__(NTHREADS) void k_batch_tb3(const Member<R> *__restrict__ M,
-                                                        const int *__restrict__ wmap,
-                                                        int nwaves, int src, int dst, int res_a)
+__global__ __launch_bounds__(NTHREADS)
+__attribute__((amdgpu_waves_per_eu(1, tb3_max_waves<S, BX, WY>()))) void k_batch_tb3(
+    const Member<R> *__restrict__ M, const int *__restrict__ wmap, int nwaves, int src, int dst,
+    int res_a)
 {
     batch_multi_wave<S, R, BX, WY, 3, NR, NR == tb_rows<S, 3>() ? 1 : 2>(M, wmap, nwaves, src,
                                                                          dst, res_a);
@@ -2221,6 +2234,12 @@ struct lbm_vans_handle {
     int auto_pass;          // automatic most steps per pass
     void *scratch;          // device address of the library-held gradient workspace on the
                             // handle's device (lbm_vans_grad_static)
+    // Step graphs of small lattices (launch-bound: fewer sweep tiles than twice the
+    // compute units): lbm_vans_step replays GRAPH_STEPS steps from state slot 0 / 1
+    // as one captured graph, captured on first use on a private stream.
+    bool use_graphs;
+    hipStream_t cap;
+    hipGraphExec_t graph[2];
 };
 
 namespace {
@@ -2380,15 +2399,15 @@ Phys<R> make_phys(const lbm_vans_params *p)
     ph.rho0 = static_cast<R>(p->rho0);
     ph.Gx = static_cast<R>(p->G[0]);
     ph.Gy = static_cast<R>(p->G[1]);
-    ph.drag = p->drag;
+    ph.ca = ph.cb = ph.ka = ph.kb = R(0);
     if (p->drag == LBM_DRAG_ERGUN) {
         bool none = std::isinf(p->d_p);
         ph.ca = none ? R(0) : static_cast<R>(150.0 * nu / (p->d_p * p->d_p));
         ph.cb = none ? R(0) : static_cast<R>(1.75 / p->d_p);
     } else {
         bool none = std::isinf(p->K);
-        ph.ca = none ? R(0) : static_cast<R>(nu / p->K);
-        ph.cb = none ? R(0) : static_cast<R>(p->F_eps / std::sqrt(p->K));
+        ph.ka = none ? R(0) : static_cast<R>(nu / p->K);
+        ph.kb = none ? R(0) : static_cast<R>(p->F_eps / std::sqrt(p->K));
     }
     double s = p->storage == LBM_F16_SHIFTED ? std::ldexp(1.0, p->fp16_scale_log2) : 1.0;
     ph.scale = static_cast<R>(s);
@@ -2487,6 +2506,21 @@ bool multi_fits(const Geo &g)
 {
     return static_cast<unsigned long long>(g.pitch) * 4 < (1ull << 24) && g.Ly < (1 << 24) &&
            static_cast<unsigned long long>(g.plane) * 4 < (1ull << 31);
+}
+
+// Whether an ns-step pass (2 or 3) in chunks of `rows` may run a lattice of Ly rows:
+// with periodic y the pass wraps each window row once, which needs Ly >= rows +
+// 2 (ns - 1) + 2 (the chunk, its halo rows and their porosity neighbours); with
+// walls in y it clamps.
+bool multi_rows_ok(int Ly, bool wall_y, int ns, int rows)
+{
+    return wall_y || Ly >= rows + 2 * (ns - 1) + 2;
+}
+
+// Rows per chunk of the two-step pass for a storage code.
+int tb2_rows_of(int storage)
+{
+    return storage == LBM_F16_SHIFTED ? tb_rows<_Float16, 2>() : tb_rows<float, 2>();
 }
 
 // Waves of the ns-step pass (2 or 3) over an Lx x Ly lattice in chunks of `rows`.
@@ -2590,24 +2624,28 @@ int choose_passes(lbm_vans_handle *h)
     if (rc) return rc;
     if (10 * waves_of(p->Lx, p->Ly, 3, h->rows3) >= TRIPLE_FILL_10 * res)
         h->auto_pass = 3;
-    else if (waves_of(p->Lx, p->Ly, 2, f16 ? tb_rows<_Float16, 2>() : tb_rows<float, 2>()) >= 2048)
+    else if (waves_of(p->Lx, p->Ly, 2, tb2_rows_of(p->storage)) >= 2048)
         h->auto_pass = 2;
     return LBM_VANS_OK;
 }
 
 // Most time steps one pass may take: 2 or 3 with the multi-step passes (FP32 and
-// FP16 storage), else 1.
+// FP16 storage, lattices they can run), else 1.
 int max_pass(const lbm_vans_handle *h)
 {
     if (h->p.storage == LBM_F64 || !multi_fits(h->g)) return 1;
-    if (h->p.steps_per_pass != 0) return h->p.steps_per_pass;
-    return h->auto_pass;
+    int m = h->p.steps_per_pass != 0 ? h->p.steps_per_pass : h->auto_pass;
+    if (m == 3 && !multi_rows_ok(h->p.Ly, h->g.wall_y, 3, h->rows3)) m = 2;
+    if (m == 2 && !multi_rows_ok(h->p.Ly, h->g.wall_y, 2, tb2_rows_of(h->p.storage))) m = 1;
+    return m;
 }
 
 // NS (2 or 3) time steps in one pass, from the state n in src into dst.
 int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
 {
     if (!multi_fits(h->g)) return fail(LBM_VANS_EINVAL, "lattice too large for the multi-step pass");
+    if (!multi_rows_ok(h->p.Ly, h->g.wall_y, ns, ns == 3 ? h->rows3 : tb2_rows_of(h->p.storage)))
+        return fail(LBM_VANS_EINVAL, "lattice too short in y for the multi-step pass");
     return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
@@ -2766,14 +2804,91 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
         delete h;
         return rc;
     }
+    // launch-bound lattices replay their steps as graphs (measured on MI355X, FP64
+    // 80 x 80: see the design notes)
+    h->use_graphs = h->gs.ntiles < 2 * ncu;
     *out = h;
     return LBM_VANS_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Steps per replay of a handle's step graph.
+constexpr int GRAPH_STEPS = 32;
+
+// The launches of `steps` steps from the handle's current state, as lbm_vans_step
+// issues them without diagnostics (up to max_pass steps per launch), on h->stream;
+// the handle's state slot and step count advance.
+int plain_steps(lbm_vans_handle *h, int64_t steps)
+{
+    for (int64_t k = 0; k < steps;) {
+        const int m = static_cast<int>(std::min<int64_t>(max_pass(h), steps - k));
+        const int rc = m >= 2 ? launch_multi(h, h->buf[h->cur], h->buf[1 - h->cur], m)
+                              : launch_sweep(h, false);
+        if (rc) return rc;
+        h->cur = 1 - h->cur;
+        h->n += m;
+        k += m;
+    }
+    return LBM_VANS_OK;
+}
+
+// Capture GRAPH_STEPS steps from the current state slot (with the open-end rules of
+// a state n >= 1) into graph[h->cur]; the handle's state and count are unchanged.
+int capture_steps(lbm_vans_handle *h)
+{
+    if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    const int cur = h->cur;
+    const int64_t n = h->n;
+    hipStream_t st = h->stream;
+    h->stream = h->cap;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? plain_steps(h, GRAPH_STEPS) : LBM_VANS_OK;
+    hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(h->cap, &graph) : e;
+    h->stream = st;
+    h->cur = cur;
+    h->n = n;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e2 != hipSuccess)
+        return fail(LBM_VANS_EHIP, "step graph capture failed: %s", hipGetErrorString(e2));
+    e = hipGraphInstantiate(&h->graph[cur], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->graph[cur] = nullptr;
+        return fail(LBM_VANS_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    return LBM_VANS_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps)
 {
     if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(LBM_VANS_EINVAL, "nsteps = %lld < 0", (long long)nsteps);
+    // small lattices without diagnostics: whole chunks of steps as graph replays (the
+    // same launches, without a host launch per step); the rest one launch at a time
+    if (h->use_graphs && h->p.diag_every == 0) {
+        while (nsteps >= GRAPH_STEPS && res_on(&h->p, h->n)) {
+            if (!h->graph[h->cur]) {
+                const int rc = capture_steps(h);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream));
+            const int64_t launches = (GRAPH_STEPS + max_pass(h) - 1) / max_pass(h);
+            if (launches & 1) h->cur = 1 - h->cur;
+            h->n += GRAPH_STEPS;
+            nsteps -= GRAPH_STEPS;
+        }
+    }
     for (int64_t k = 0; k < nsteps; k++) {
         bool diag = h->p.diag_every > 0 && h->n % h->p.diag_every == 0;
         // up to three steps in one pass when they remain in this call and none
@@ -3107,6 +3222,9 @@ void lbm_vans_destroy(lbm_vans_handle *h)
 {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    for (auto &gx : h->graph)
+        if (gx) (void)hipGraphExecDestroy(gx);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }
 
@@ -3503,7 +3621,14 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     b->bx = h0->g.open_x ? 2 : (h0->g.wall_x ? 1 : 0);
     b->wy = h0->g.wall_y;
     b->vmax = b->storage == LBM_F64 ? 2 : 4;
-    for (int32_t k = 0; k < nmembers; k++) b->multi_ok = b->multi_ok && multi_fits(members[k]->g);
+    // every member must fit the multi-step passes' addressing and rows (in the taller
+    // chunks, which the batch may choose)
+    for (int32_t k = 0; k < nmembers; k++)
+        b->multi_ok = b->multi_ok && multi_fits(members[k]->g) &&
+                      multi_rows_ok(members[k]->p.Ly, members[k]->g.wall_y, 3,
+                                    LBM_VANS_TB3_TALL32) &&
+                      multi_rows_ok(members[k]->p.Ly, members[k]->g.wall_y, 2,
+                                    tb2_rows_of(members[k]->p.storage));
     const size_t dsz = b->storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
     char *w = static_cast<char *>(work);
     b->d_desc = w;

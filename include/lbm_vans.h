@@ -31,7 +31,9 @@
  * except where a call says it synchronises.
  *
  * Errors.  Every int-returning call returns LBM_VANS_OK (0) or a negative
- * code and sets a thread-local message readable with lbm_vans_last_error().
+ * code and sets a thread-local message readable with lbm_vans_last_error();
+ * the calls that report diagnostics may instead return the positive warning
+ * LBM_VANS_WMACH (with a message) after completing normally.
  * No C++ exception crosses this interface.
  *
  * Threads.  A handle may be used by one host thread at a time.  Calls on
@@ -47,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LBM_VANS_ABI_VERSION 8
+#define LBM_VANS_ABI_VERSION 9
 
 /* Return codes. */
 #define LBM_VANS_OK 0
@@ -55,6 +57,10 @@ extern "C" {
 #define LBM_VANS_EHIP (-2)       /* a HIP runtime call failed (message has its text)  */
 #define LBM_VANS_ENONFINITE (-3) /* diagnostics found a NaN or Inf in the state       */
 #define LBM_VANS_ENOTIMPL (-4)   /* the requested feature is not built                */
+/* Warning (positive): the flow left the low-Mach range of the lattice BGK model,
+ * max |u| / c_s > LBM_VANS_MACH_WARN (c_s = 1/sqrt(3)); the call itself succeeded. */
+#define LBM_VANS_WMACH 1
+#define LBM_VANS_MACH_WARN 0.3
 
 /* Boundary kind of one axis (applies to both ends of that axis). */
 #define LBM_BC_PERIODIC 0   /* wrap-around streaming (Section "Examples and discussions") */
@@ -204,7 +210,8 @@ int lbm_vans_pass_plan(const lbm_vans_handle *h, int32_t *steps_per_pass, int32_
  *   diag[3], diag[4] = sum_x eps rho u diag[5] = max_x |u|
  *   diag[6] = number of nodes whose moments are not finite
  *   diag[7] = n (step index).
- * Returns LBM_VANS_ENONFINITE (after filling diag) if diag[6] > 0. */
+ * Returns LBM_VANS_ENONFINITE (after filling diag) if diag[6] > 0, else
+ * LBM_VANS_WMACH if diag[5] / c_s exceeds LBM_VANS_MACH_WARN. */
 int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, void *uy,
                      double *diag);
 
@@ -221,7 +228,8 @@ int lbm_vans_set_state(lbm_vans_handle *h, const void *f);
  * meaning of lbm_vans_moments' diag, for the states n = 0, k, 2k, ... swept so
  * far (the last LBM_VANS_DIAG_RING of them).  *n_records receives the count.
  * Synchronises the stream.  Returns LBM_VANS_ENONFINITE if any copied record
- * counts non-finite nodes. */
+ * counts non-finite nodes, else LBM_VANS_WMACH if any record's max |u| / c_s
+ * exceeds LBM_VANS_MACH_WARN. */
 int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
                        int32_t *n_records);
 
@@ -229,6 +237,12 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
  * column x = Lx-1 of eps rho u_x of the state f(., nsteps) (eqs. (0moment),
  * (1moment)): the superficial mass flux through that section per unit depth. */
 #define LBM_OBJ_OUTLET_FLUX 0
+
+/* Value of the objective (LBM_OBJ_OUTLET_FLUX) for the current state f(., n),
+ * computed on the device in FP64 (the value lbm_vans_grad returns as J after
+ * the same steps), without a reverse sweep.  J: host double.  Synchronises the
+ * stream.  Returns LBM_VANS_ENONFINITE if J is not finite. */
+int lbm_vans_objective(lbm_vans_handle *h, int32_t objective, double *J);
 
 /* Bytes of device memory lbm_vans_grad needs as grad_work for these
  * arguments (0 if invalid): one population buffer per checkpoint

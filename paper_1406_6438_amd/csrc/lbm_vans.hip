@@ -1512,6 +1512,39 @@ __global__ __launch_bounds__(NTHREADS) void k_moments(const S *__restrict__ fin,
     block_partial(acc, part, t);
 }
 
+// The outlet mass flux J = sum over x = Lx-1 of eps rho u_x of the current state
+// (eqs. (0moment), (1moment)): one thread per row, FP64 partial of each block in
+// part[block][0], summed by k_finalize.
+template <typename S, typename R>
+__global__ __launch_bounds__(NTHREADS) void k_outlet_flux(const S *__restrict__ fin,
+                                                          const R *__restrict__ eps, Geo g,
+                                                          Phys<R> ph, double *__restrict__ part)
+{
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; k++) acc[k] = 0.0;
+    const int y = blockIdx.x * NTHREADS + threadIdx.x;
+    if (y < g.Ly) {
+        const int x = g.Lx - 1;
+        const Nbr n = neighbours(x, y, g);
+        R d[9];
+        gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
+        // the porosity around the node, from the padded field with the halo rule
+        R t[3][3];
+        for (int j = 0; j < 3; j++)
+            for (int i = 0; i < 3; i++)
+                t[j][i] = eps[(long long)halo_index(y + j - 1, g.Ly, g.wall_y) * g.pitch +
+                              halo_index(x + i - 1, g.Lx, g.wall_x)];
+        const PorNb<R> P = porosity_nb<R, 3>(t, 1, 1, n.wxm, n.wxp, n.wym, n.wyp);
+        const bool ores = g.open_x && ph.reservoir;
+        boundary_inflow<R>(d, P.e0, ores && x == 0, ores, n.wym, n.wyp, ph);
+        unshift_incoming<R>(d, P, ph.rho0);
+        const Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
+        acc[0] = static_cast<double>(N.S) * static_cast<double>(N.ux);
+    }
+    block_partial(acc, part, blockIdx.x);
+}
+
 // Deterministic second pass: one block sums the tile partials in a fixed
 // order and writes one diagnostics record (slot 0 gets rho0 * sum eps added,
 // slot 7 the step index).
@@ -2444,6 +2477,19 @@ Phys<R> make_phys(const lbm_vans_params *p)
     return ph;
 }
 
+// LBM_VANS_WMACH (with a message) when the largest speed of a state leaves the
+// low-Mach range of the lattice BGK model, max |u| / c_s > LBM_VANS_MACH_WARN.
+int mach_check(double umax, double step)
+{
+    const double ma = umax * std::sqrt(3.0);
+    if (ma > LBM_VANS_MACH_WARN) {
+        fail(LBM_VANS_WMACH, "Mach number %.3f > %.2f at step %.0f (max |u| = %.4g)", ma,
+             LBM_VANS_MACH_WARN, step, umax);
+        return LBM_VANS_WMACH;
+    }
+    return LBM_VANS_OK;
+}
+
 // Whether the open-end rules apply to a step from state n: the fixed reservoirs
 // from n = 1 on (the initial state is the equilibrium everywhere), the velocity
 // inlet / pressure outlet from the start (its reservoirs live in the stored
@@ -2953,6 +2999,33 @@ int lbm_vans_moments(lbm_vans_handle *h, void *eps_rho, void *rho, void *ux, voi
     if (diag[6] != 0.0)
         return fail(LBM_VANS_ENONFINITE, "%.0f nodes have non-finite moments at step %lld",
                     diag[6], (long long)h->n);
+    return mach_check(diag[5], static_cast<double>(h->n));
+}
+
+int lbm_vans_objective(lbm_vans_handle *h, int32_t objective, double *J)
+{
+    if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
+    if (objective != LBM_OBJ_OUTLET_FLUX)
+        return fail(LBM_VANS_EINVAL, "unknown objective %d", objective);
+    if (!J) return fail(LBM_VANS_EINVAL, "J is NULL");
+    const int nblk = (h->p.Ly + NTHREADS - 1) / NTHREADS;
+    int rc = with_types(h->p.storage, [&](auto *sp, auto *rp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using R = std::remove_pointer_t<decltype(rp)>;
+        Phys<R> ph = make_phys<R>(&h->p);
+        ph.reservoir = res_on(&h->p, h->n);
+        hipLaunchKernelGGL((k_outlet_flux<S, R>), dim3(nblk), dim3(NTHREADS), 0, h->stream,
+                           (const S *)h->buf[h->cur], (const R *)h->eps, h->g, ph, h->part);
+        return check_launch("k_outlet_flux");
+    });
+    if (rc) return rc;
+    rc = launch_finalize(h, h->scratch_rec, nblk, false, static_cast<double>(h->n));
+    if (rc) return rc;
+    double rec[NRED];
+    HIP_TRY(hipMemcpyAsync(rec, h->scratch_rec, sizeof rec, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    *J = rec[0];
+    if (!std::isfinite(rec[0])) return fail(LBM_VANS_ENONFINITE, "objective is not finite");
     return LBM_VANS_OK;
 }
 
@@ -3007,6 +3080,9 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
         if (records[k * NRED + 6] != 0.0)
             return fail(LBM_VANS_ENONFINITE, "non-finite moments recorded at step %.0f",
                         records[k * NRED + 7]);
+    for (int64_t k = 0; k < cnt; k++)
+        if (mach_check(records[k * NRED + 5], records[k * NRED + 7]) != LBM_VANS_OK)
+            return LBM_VANS_WMACH;
     return LBM_VANS_OK;
 }
 

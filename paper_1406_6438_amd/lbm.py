@@ -22,18 +22,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_vans.so")
 
 OK, EINVAL, EHIP, ENONFINITE, ENOTIMPL = 0, -1, -2, -3, -4
+WMACH = 1                # warning: max |u| / c_s above MACH_WARN (the call completed)
+MACH_WARN = 0.3
 BC_PERIODIC, BC_BOUNCEBACK, BC_OPEN, BC_INOUT = 0, 1, 2, 3
 F64, F32_SHIFTED, F16_SHIFTED = 0, 1, 2
 DRAG_ERGUN, DRAG_CONST = 0, 1
 NDIAG = 8
 DIAG_RING = 4096
-ABI_VERSION = 8
+ABI_VERSION = 9
 
 # Every symbol include/lbm_vans.h declares.
 SYMBOLS = ("lbm_vans_work_bytes", "lbm_vans_init", "lbm_vans_step", "lbm_vans_step_count",
            "lbm_vans_pass_plan", "lbm_vans_batch_pass_plan", "lbm_vans_moments", "lbm_vans_get_state", "lbm_vans_set_state",
            "lbm_vans_diag_read", "lbm_vans_grad_work_bytes", "lbm_vans_grad",
-           "lbm_vans_grad_static",
+           "lbm_vans_grad_static", "lbm_vans_objective",
            "lbm_vans_destroy", "lbm_vans_batch_work_bytes", "lbm_vans_batch_create",
            "lbm_vans_batch_configure", "lbm_vans_batch_get_config", "lbm_vans_batch_tune",
            "lbm_vans_batch_step", "lbm_vans_batch_grad_work_bytes", "lbm_vans_batch_grad",
@@ -145,6 +147,7 @@ def load(path: str = LIB_PATH):
     L.lbm_vans_grad_work_bytes.restype = ctypes.c_size_t
     L.lbm_vans_grad.argtypes = [vp, i32, i64, i32, vp, ctypes.c_size_t, vp, dp]
     L.lbm_vans_grad_static.argtypes = [vp, i32, i64, i32, vp, dp]
+    L.lbm_vans_objective.argtypes = [vp, i32, dp]
     L.lbm_vans_destroy.argtypes = [vp]
     L.lbm_vans_destroy.restype = None
     C = ctypes.POINTER(LbmVansBatchConfig)
@@ -167,7 +170,7 @@ def load(path: str = LIB_PATH):
     L.lbm_vans_abi_version.argtypes = []
     for n in ("lbm_vans_init", "lbm_vans_step", "lbm_vans_moments", "lbm_vans_get_state",
               "lbm_vans_set_state", "lbm_vans_diag_read", "lbm_vans_grad",
-              "lbm_vans_grad_static",
+              "lbm_vans_grad_static", "lbm_vans_objective",
               "lbm_vans_batch_create", "lbm_vans_batch_configure", "lbm_vans_batch_get_config",
               "lbm_vans_batch_tune", "lbm_vans_batch_step", "lbm_vans_batch_grad",
               "lbm_vans_abi_version"):
@@ -214,7 +217,7 @@ def lbm_vans_moments(h, eps_rho=None, rho=None, ux=None, uy=None, want_diag: boo
     diag = (ctypes.c_double * NDIAG)() if want_diag else None
     rc = load().lbm_vans_moments(h, _dev_ptr(eps_rho), _dev_ptr(rho), _dev_ptr(ux),
                                  _dev_ptr(uy), diag)
-    if rc == ENONFINITE:
+    if rc in (ENONFINITE, WMACH):
         return np.array(diag[:]), rc
     _check(rc)
     return (np.array(diag[:]) if want_diag else None), rc
@@ -233,7 +236,7 @@ def lbm_vans_diag_read(h, max_records: int = DIAG_RING):
     n = ctypes.c_int32()
     rc = load().lbm_vans_diag_read(h, buf, max_records, ctypes.byref(n))
     arr = np.array(buf[: n.value * NDIAG]).reshape(n.value, NDIAG)
-    if rc not in (OK, ENONFINITE):
+    if rc not in (OK, ENONFINITE, WMACH):
         _check(rc)
     return arr, rc
 
@@ -251,6 +254,13 @@ def lbm_vans_grad(h, objective: int, nsteps: int, ckpt_every: int, grad_work, dJ
     _check(load().lbm_vans_grad(h, objective, int(nsteps), int(ckpt_every), grad_work.data_ptr(),
                                 grad_work.numel() * grad_work.element_size(), dJdeps.data_ptr(),
                                 ctypes.byref(J)))
+    return J.value
+
+
+def lbm_vans_objective(h, objective: int = 0) -> float:
+    """J of the current state (the outlet mass flux), on the device, no reverse sweep."""
+    J = ctypes.c_double()
+    _check(load().lbm_vans_objective(h, objective, ctypes.byref(J)))
     return J.value
 
 
@@ -519,6 +529,12 @@ def outlet_flux_function():
         @staticmethod
         def forward(ctx, eps, params, nsteps, ckpt_every):
             s = Solver(params, eps.detach(), device=eps.device if eps.is_cuda else "cuda:0")
+            if not ctx.needs_input_grad[0]:
+                # no gradient wanted: the forward steps and J only, no reverse sweep
+                s.step(nsteps)
+                J = lbm_vans_objective(s.h, OBJ_OUTLET_FLUX)
+                s.close()
+                return torch.tensor(J, dtype=torch.float64, device=eps.device)
             J, g = s.grad(nsteps, ckpt_every, OBJ_OUTLET_FLUX)
             s.close()
             ctx.save_for_backward(g)

@@ -1,0 +1,61 @@
+"""Child process of tests/test_sanitizers.py (not collected by pytest): drives the host
+side of a given build of the library (argument checks, layouts, error texts) without a
+GPU, so that an AddressSanitizer / UndefinedBehaviorSanitizer build reports any fault.
+
+    python tests/sanitize_child.py <path of the library build>
+"""
+import ctypes
+import math
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_1406_6438_amd import lbm  # noqa: E402
+
+
+def main(path):
+    L = lbm.load(path)
+    base = dict(Lx=16, Ly=8, tau=0.7, d_p=10.0)
+    good = [base, dict(base, storage=lbm.F64), dict(base, storage=lbm.F16_SHIFTED),
+            dict(base, bc_x=lbm.BC_INOUT, bc_y=lbm.BC_BOUNCEBACK, u_in=0.02),
+            dict(base, bc_x=lbm.BC_OPEN, drag=lbm.DRAG_CONST, K=3.0, F_eps=0.2),
+            dict(base, Lx=4097, Ly=33, steps_per_pass=3, pass_rows=28)]
+    for kw in good:
+        p = lbm.Params(**kw)
+        assert lbm.lbm_vans_work_bytes(p) > 0
+        assert lbm.lbm_vans_grad_work_bytes(p, lbm.OBJ_OUTLET_FLUX, 100, 7) > 0
+    bad = [dict(Lx=0), dict(Ly=-3), dict(tau=0.5), dict(tau=math.nan), dict(d_p=0.0),
+           dict(storage=7), dict(bc_x=4), dict(bc_y=2), dict(drag=3), dict(bc_x=2, Lx=1),
+           dict(bc_x=2, rho_in=0.0), dict(bc_x=3, rho_out=0.0), dict(bc_x=3, u_in=math.inf),
+           dict(rho0=0.0), dict(G=(math.inf, 0.0)), dict(Lx=65536, Ly=65536),
+           dict(u_wall=(0.01, 0.0)), dict(sweep_vec=3), dict(steps_per_pass=4),
+           dict(pass_rows=16), dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30)]
+    for b in bad:
+        p = lbm.Params(**dict(base, **b))
+        assert L.lbm_vans_work_bytes(ctypes.byref(p.c())) == 0
+        assert L.lbm_vans_last_error().decode()
+        h = ctypes.c_void_p()
+        rc = L.lbm_vans_init(ctypes.byref(p.c()), 256, 256, 1 << 30, None, ctypes.byref(h))
+        assert rc == lbm.EINVAL and not h.value
+    p = lbm.Params(**base)
+    assert L.lbm_vans_grad_work_bytes(ctypes.byref(p.c()), 5, 10, 2) == 0     # objective
+    assert L.lbm_vans_grad_work_bytes(ctypes.byref(p.c()), 0, -1, 2) == 0     # steps
+    assert L.lbm_vans_grad_work_bytes(ctypes.byref(p.c()), 0, 10, 0) == 0     # interval
+    assert L.lbm_vans_batch_work_bytes(None, 0) == 0
+    for name in ("lbm_vans_step", "lbm_vans_moments", "lbm_vans_get_state",
+                 "lbm_vans_set_state", "lbm_vans_objective", "lbm_vans_grad_static"):
+        f = getattr(L, name)
+        args = {"lbm_vans_step": (None, 1), "lbm_vans_moments": (None, None, None, None, None,
+                                                                  None),
+                "lbm_vans_get_state": (None, None), "lbm_vans_set_state": (None, None),
+                "lbm_vans_objective": (None, 0, None),
+                "lbm_vans_grad_static": (None, 0, 10, 2, None, None)}[name]
+        assert f(*args) == lbm.EINVAL, name
+    lbm.lbm_vans_destroy(None)
+    assert L.lbm_vans_abi_version() == lbm.ABI_VERSION
+    print("sanitized host checks passed")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])

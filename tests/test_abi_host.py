@@ -47,6 +47,8 @@ def test_header_constants_match_binding():
     assert int(consts["LBM_BC_OPEN"]) == lbm.BC_OPEN
     assert int(consts["LBM_OBJ_OUTLET_FLUX"]) == lbm.OBJ_OUTLET_FLUX
     assert int(consts["LBM_BC_INOUT"]) == lbm.BC_INOUT
+    assert int(consts["LBM_VANS_WMACH"]) == lbm.WMACH
+    assert float(re.search(r"#define\s+LBM_VANS_MACH_WARN\s+([0-9.]+)", src).group(1)) == lbm.MACH_WARN
     m = re.search(r"#define\s+LBM_VANS_GRAD_STATIC_BYTES\s+\(\(size_t\)(\d+) << (\d+)\)", src)
     assert m and int(m.group(1)) << int(m.group(2)) == lbm.GRAD_STATIC_BYTES
 

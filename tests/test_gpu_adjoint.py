@@ -184,6 +184,46 @@ def test_autograd_function_backpropagates_library_gradient():
     assert np.abs(e.grad.cpu().numpy() - 2.5 * go).max() <= 1e-10 * np.abs(2.5 * go).max()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_objective_without_reverse_sweep(storage):
+    """lbm_vans_objective after n steps gives the J that lbm_vans_grad returns for n steps
+    (in FP64 the same sum in another order; in FP32 the gradient's forward groups its
+    steps into passes by checkpoint, so both are held to the oracle's bound instead), and
+    the autograd function's forward without a gradient requested uses it (no reverse
+    sweep) with the same value."""
+    from paper_1406_6438_amd import lbm
+    spec = _open_spec(130, 21, storage, inout=True, open_x=False, rho_out=1.0)
+    eps = W.grf_porosity(130, 21, seed=45, ell=3.0, lo=0.4, hi=0.98)
+    s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
+    Jg, _ = s.grad(60, 20)
+    s.close()
+    s = lbm.Solver(spec.gpu(), spec.input_eps(eps))
+    s.step(60)
+    Jo = lbm.lbm_vans_objective(s.h)
+    s.close()
+    if storage == "f64":
+        assert abs(Jo - Jg) <= 1e-13 * abs(Jg)
+    OutletFlux = lbm.outlet_flux_function()
+    e = torch.tensor(eps, dtype=torch.float64, device="cuda:0")      # no grad wanted
+    J = OutletFlux.apply(e, spec.gpu(), 60, 20)
+    assert not J.requires_grad and abs(J.item() - Jo) <= 1e-13 * abs(Jo)
+    fo = oracle.run(spec.oracle(), spec.input_eps(eps), 60)
+    Jorc = oracle.outlet_flux(spec.oracle(), spec.input_eps(eps), fo)
+    # J sums eps rho u_x over the Ly nodes of the last column, each a sum of the six
+    # populations with c_x != 0 (and a drag-reduced share of the force): its error is at
+    # most 6 Ly times the per-population bound of the forward parity tests, which is
+    # 1e-13 in FP64 and the FP32 roundoff bound of test_open_channel_forward_parity
+    if storage == "f64":
+        pop_bound = 1e-13
+    else:
+        rest = oracle.init(dataclasses.replace(spec, u0=(0.0, 0.0)).oracle(),
+                           spec.input_eps(eps))
+        de = max(np.abs(eps - np.roll(eps, s_, axis=a)).max() for a in (0, 1) for s_ in (1, -1))
+        pop_bound = 4 * 61 * 2.0 ** -24 * (np.abs(fo - rest).max() + de / 18.0)
+    assert abs(Jo - Jorc) <= 6 * spec.Ly * pop_bound
+    assert abs(Jg - Jorc) <= 6 * spec.Ly * pop_bound
+
+
 def _golden():
     if not os.path.exists(GOLDEN):
         return None

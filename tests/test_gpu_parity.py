@@ -272,6 +272,24 @@ def test_nonfinite_state_is_reported():
     s.close()
 
 
+def test_mach_warning_is_reported():
+    """A flow faster than 0.3 c_s gives the positive warning LBM_VANS_WMACH from the
+    diagnostics (moments and the in-sweep ring), with the call completed; a slower one
+    does not."""
+    from paper_1406_6438_amd import lbm
+    for u, expect in ((0.15, lbm.OK), (0.2, lbm.WMACH)):     # Mach 0.26, 0.35
+        spec = Spec(Lx=40, Ly=24, d_p=math.inf, u0=(u, 0.0), storage="f64", diag_every=1)
+        s = lbm.Solver(spec.gpu(), W.uniform_porosity(40, 24, 1.0))
+        m = s.moments()
+        assert m["rc"] == expect and abs(m["diag"][5] - u) < 1e-12
+        s.step(3)
+        rec, rc = s.diag_records()
+        assert rc == expect and rec.shape == (3, 8)
+        if expect == lbm.WMACH:
+            assert "Mach" in lbm.load().lbm_vans_last_error().decode()
+        s.close()
+
+
 def test_step_counter_and_zero_steps():
     from paper_1406_6438_amd import lbm
     spec = Spec(Lx=20, Ly=12, d_p=8.0, storage="f32")

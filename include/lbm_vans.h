@@ -246,9 +246,11 @@ int lbm_vans_objective(lbm_vans_handle *h, int32_t objective, double *J);
 
 /* Bytes of device memory lbm_vans_grad needs as grad_work for these
  * arguments (0 if invalid): one population buffer per checkpoint
- * (ceil(nsteps / ckpt_every)), ckpt_every buffers for a recomputed segment,
- * two FP64 adjoint buffers and three FP64 accumulators of the porosity grid
- * (with LBM_F32 / LBM_F16_SHIFTED storage also an FP64 copy of the porosity). */
+ * (ceil(nsteps / ckpt_every)), ckpt_every buffers for a recomputed segment --
+ * two sets of them when there are two or more segments, so that one segment is
+ * recomputed while the reverse steps of the next run --, two FP64 adjoint
+ * buffers and three FP64 accumulators of the porosity grid (with LBM_F32 /
+ * LBM_F16_SHIFTED storage also an FP64 copy of the porosity). */
 size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int64_t nsteps,
                                 int32_t ckpt_every);
 
@@ -259,7 +261,8 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
  * a checkpoint every ckpt_every steps (up to three steps per pass in between, as
  * in lbm_vans_step, when params.steps_per_pass allows it), then, segment by segment
  * from the last, the states recomputed one step at a time from the
- * checkpoint and the adjoint stepped back through them.  Porosity enters
+ * checkpoint (on a second stream of the handle, one segment ahead) and the
+ * adjoint stepped back through them.  Porosity enters
  * through eps itself (density, drag), through grad(eps), through the
  * open-boundary reservoirs (and the boundary density / velocity a velocity
  * inlet / pressure outlet carries) and the initial state.  The reverse steps

@@ -1825,6 +1825,108 @@ __device__ __forceinline__ void node_vjp(const R d[9], R e0, R gex, R gey, const
     for (int i = 0; i < 9; i++) nu[i] += S_bar + R(CX[i]) * Vx_bar + R(CY[i]) * Vy_bar;
 }
 
+// The reverse of one node at one step.  d: the node's incoming deviations of the
+// state the step starts from (gathered, with the boundary rules applied and the
+// storage shift removed); mu: adjoints of its 9 outgoing values (SEED: unused, the
+// objective seeds the node instead).  At a velocity inlet / pressure outlet end the
+// slots that leave the domain hold the next step's reservoir populations: their
+// adjoints go to the end node's eps rho, velocity and porosity, not to the collision.
+// Returns the adjoints of the 9 incoming values in nu, the directions whose incoming
+// value came from an equilibrium reservoir (res: nothing to push) and the node's
+// porosity sensitivities; SEED adds J's share of the node to acc[0].
+template <typename R, bool SEED>
+__device__ __forceinline__ void adjoint_node(const R d[9], const PorNb<R> &P, const Nbr &n,
+                                             bool ol, bool orr, bool last_col, const Phys<R> &ph,
+                                             R mu[9], R nu[9], bool res[9], R &e_b, R &gx_b,
+                                             R &gy_b, double *acc)
+{
+    R S_bar0 = R(0), ux_bar0 = R(0), uy_bar0 = R(0), e_end = R(0);
+    const R w1 = R(1) / R(9), w2 = R(1) / R(36);
+    if constexpr (SEED) {
+#pragma unroll
+        for (int i = 0; i < 9; i++) mu[i] = R(0);
+        if (last_col) {
+            const Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
+            S_bar0 = N.ux;
+            ux_bar0 = N.S;
+            acc[0] += static_cast<double>(N.S) * static_cast<double>(N.ux);
+        }
+    } else {
+        if (ph.inout && (ol || orr)) {
+            if (ol) {
+                S_bar0 += mu[3] * (w1 + ph.rin[1]);
+                mu[3] = R(0);
+                if (!n.wym) { S_bar0 += mu[7] * (w2 + ph.rin[5]); mu[7] = R(0); }
+                if (!n.wyp) { S_bar0 += mu[6] * (w2 + ph.rin[8]); mu[6] = R(0); }
+            }
+            if (orr) {
+                const Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
+                const R uu = N.ux * N.ux + N.uy * N.uy;
+                const R er = P.e0 * ph.rho_out;
+                // plain value w (eps rho_out) P(u): d/d eps = w rho_out P(u),
+                // d/du = w eps rho_out (3 e + 9 (e.u) e - 3 u)
+                auto link = [&](int slot, R w, R ex, R ey) {
+                    const R m = mu[slot], eu = ex * N.ux + ey * N.uy;
+                    e_end += m * w * ph.rho_out *
+                             (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+                    ux_bar0 += m * w * er * (R(3) * ex + R(9) * eu * ex - R(3) * N.ux);
+                    uy_bar0 += m * w * er * (R(3) * ey + R(9) * eu * ey - R(3) * N.uy);
+                    mu[slot] = R(0);
+                };
+                link(1, w1, R(-1), R(0));
+                if (!n.wym) link(8, w2, R(-1), R(1));
+                if (!n.wyp) link(5, w2, R(-1), R(-1));
+            }
+        }
+    }
+    e_b = e_end;
+    gx_b = R(0);
+    gy_b = R(0);
+    node_vjp<R>(d, P.e0, P.gex, P.gey, ph, mu, S_bar0, ux_bar0, uy_bar0, nu, e_b, gx_b, gy_b);
+    // reservoir links: the incoming value is eps0 * (rin_i + w_i rho0)
+#pragma unroll
+    for (int i = 0; i < 9; i++) res[i] = false;
+    if (ol && !ph.inout) {
+        res[1] = true; res[5] = !n.wym; res[8] = !n.wyp;
+        e_b += nu[1] * (ph.rin[1] + w1 * ph.rho0);
+        if (res[5]) e_b += nu[5] * (ph.rin[5] + w2 * ph.rho0);
+        if (res[8]) e_b += nu[8] * (ph.rin[8] + w2 * ph.rho0);
+    }
+    if (orr && !ph.inout) {
+        res[3] = true; res[6] = !n.wym; res[7] = !n.wyp;
+        e_b += nu[3] * (ph.rout[3] + w1 * ph.rho0);
+        if (res[6]) e_b += nu[6] * (ph.rout[6] + w2 * ph.rho0);
+        if (res[7]) e_b += nu[7] * (ph.rout[7] + w2 * ph.rho0);
+    }
+    // sliding y-walls: the returned diagonals carry +-eps * wb (wt)
+    if (n.wym) e_b += (nu[5] - nu[6]) * ph.wb;
+    if (n.wyp) e_b += (nu[8] - nu[7]) * ph.wt;
+}
+
+// Push of a node's incoming adjoints into the adjoint slots of the state the
+// step started from (the gather run backwards; every slot receives exactly one
+// value, a reservoir link a zero).
+template <typename R>
+__device__ __forceinline__ void push_global(R *__restrict__ lam, const Geo &g, int x, int y,
+                                            const Nbr &n, const R nu[9], const bool res[9])
+{
+    const int c = y * g.pitch + x;
+    const int rm = n.ym * g.pitch, r0 = y * g.pitch, rp = n.yp * g.pitch;
+    const long long pl = g.plane;
+    const gptr<R> lg = to_global(lam);
+    gptr<R> L0 = lg, L1 = lg + pl, L2 = lg + 2 * pl, L3 = lg + 3 * pl, L4 = lg + 4 * pl,
+            L5 = lg + 5 * pl, L6 = lg + 6 * pl, L7 = lg + 7 * pl, L8 = lg + 8 * pl;
+    L0[c] = nu[0];
+    *(n.wxm ? L3 + c : L1 + r0 + n.xm) = res[1] ? R(0) : nu[1];
+    *(n.wym ? L4 + c : L2 + rm + x) = nu[2];
+    *(n.wxp ? L1 + c : L3 + r0 + n.xp) = res[3] ? R(0) : nu[3];
+    *(n.wyp ? L2 + c : L4 + rp + x) = nu[4];
+    *((n.wxm || n.wym) ? L7 + c : L5 + rm + n.xm) = res[5] ? R(0) : nu[5];
+    *((n.wxp || n.wym) ? L8 + c : L6 + rm + n.xp) = res[6] ? R(0) : nu[6];
+    *((n.wxp || n.wyp) ? L5 + c : L7 + rp + n.xp) = res[7] ? R(0) : nu[7];
+    *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = res[8] ? R(0) : nu[8];
+}
+
 // One reverse step (SEED = false) or the objective's seed (SEED = true).
 // fin: the stored state n (what the forward sweep of step n gathers from).
 // lam_next: adjoint of the state n + 1 (unused for the seed); lam: receives
@@ -1847,111 +1949,61 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
     __shared__ R tile[TY + 2][W];
     const int bx = t % g.nbx, by = t / g.nbx;
     const int x0 = bx * TX, y0 = by * TY;
-    load_eps_tile<R, W>(tile, eps, g, x0, y0);
-    __syncthreads();
     double acc[NRED];
 #pragma unroll
     for (int k = 0; k < NRED; k++) acc[k] = 0.0;
     const gptr<double> ebg = to_global(eb), gxg = to_global(gxb), gyg = to_global(gyb);
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx;
+    // The porosity tile's loads go first, then every node's own loads (its adjoints,
+    // its gather and its accumulators), and only then the tile to LDS and the
+    // barrier: memory counters retire in order, so waiting for the tile does not wait
+    // for the node's loads, whose latency runs under the tile's.
+    EpsTile<R, W> et;
+    et.issue(eps, g, x0, y0);
+    bool ok[ROWS];
+    Nbr nb[ROWS];
+    R mu[ROWS][9], d[ROWS][9];
+    double ae[ROWS], ax[ROWS], ay[ROWS];
+#pragma unroll
     for (int r = 0; r < ROWS; r++) {
+        const int y = y0 + ty + NW * r;
+        ok[r] = x < g.Lx && y < g.Ly;
+        if (!ok[r]) continue;
+        nb[r] = neighbours(x, y, g);
+        if constexpr (!SEED) {
+            const int c = y * g.pitch + x;
+#pragma unroll
+            for (int i = 0; i < 9; i++) mu[r][i] = load_global(lam_next + i * g.plane + c);
+        }
+        gather<S, R>(d[r], fin, g.plane, g.pitch, x, y, nb[r], ph.inv_scale);
+        const int c = y * g.pitch + x;
+        ae[r] = ebg[c];
+        ax[r] = gxg[c];
+        ay[r] = gyg[c];
+    }
+    et.commit(tile);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+        if (!ok[r]) continue;
         const int ly = ty + NW * r;
         const int y = y0 + ly;
-        if (x >= g.Lx || y >= g.Ly) continue;
-        const Nbr n = neighbours(x, y, g);
-        R d[9];
-        gather<S, R>(d, fin, g.plane, g.pitch, x, y, n, ph.inv_scale);
+        const Nbr &n = nb[r];
+        const int c = y * g.pitch + x;
         const PorNb<R> P = porosity_nb<R, W>(tile, ly + 1, tx + 1, n.wxm, n.wxp, n.wym, n.wyp);
         const bool ores = g.open_x && ph.reservoir;
         const bool ol = ores && x == 0, orr = ores && x == g.Lx - 1;
-        boundary_inflow<R>(d, P.e0, ol, orr, n.wym, n.wyp, ph);
-        unshift_incoming<R>(d, P, ph.rho0);
-        const int c = y * g.pitch + x;
-        R mu[9];
-        R S_bar0 = R(0), ux_bar0 = R(0), uy_bar0 = R(0), e_end = R(0);
-        const R w1 = R(1) / R(9), w2 = R(1) / R(36);
-        if constexpr (SEED) {
-#pragma unroll
-            for (int i = 0; i < 9; i++) mu[i] = R(0);
-            if (x == g.Lx - 1) {
-                const Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
-                S_bar0 = N.ux;
-                ux_bar0 = N.S;
-                acc[0] += static_cast<double>(N.S) * static_cast<double>(N.ux);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; i++) mu[i] = load_global(lam_next + i * g.plane + c);
-            if (ph.inout && (ol || orr)) {
-                // velocity inlet / pressure outlet: the slots that leave the domain
-                // hold the reservoir populations of the next step (inout_ends); their
-                // adjoints go to the inlet node's eps rho and the outlet node's
-                // velocity and porosity instead of to the collision
-                if (ol) {
-                    S_bar0 += mu[3] * (w1 + ph.rin[1]);
-                    mu[3] = R(0);
-                    if (!n.wym) { S_bar0 += mu[7] * (w2 + ph.rin[5]); mu[7] = R(0); }
-                    if (!n.wyp) { S_bar0 += mu[6] * (w2 + ph.rin[8]); mu[6] = R(0); }
-                }
-                if (orr) {
-                    const Node<R> N = node_moments<R>(d, P.e0, P.gex, P.gey, ph);
-                    const R uu = N.ux * N.ux + N.uy * N.uy;
-                    const R er = P.e0 * ph.rho_out;
-                    // plain value w (eps rho_out) P(u): d/d eps = w rho_out P(u),
-                    // d/du = w eps rho_out (3 e + 9 (e.u) e - 3 u)
-                    auto link = [&](int slot, R w, R ex, R ey) {
-                        const R m = mu[slot], eu = ex * N.ux + ey * N.uy;
-                        e_end += m * w * ph.rho_out *
-                                 (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-                        ux_bar0 += m * w * er * (R(3) * ex + R(9) * eu * ex - R(3) * N.ux);
-                        uy_bar0 += m * w * er * (R(3) * ey + R(9) * eu * ey - R(3) * N.uy);
-                        mu[slot] = R(0);
-                    };
-                    link(1, w1, R(-1), R(0));
-                    if (!n.wym) link(8, w2, R(-1), R(1));
-                    if (!n.wyp) link(5, w2, R(-1), R(-1));
-                }
-            }
-        }
-        R nu[9], e_b = e_end, gx_b = R(0), gy_b = R(0);
-        node_vjp<R>(d, P.e0, P.gex, P.gey, ph, mu, S_bar0, ux_bar0, uy_bar0, nu, e_b, gx_b,
-                    gy_b);
-        // reservoir links: the incoming value is eps0 * (rin_i + w_i rho0)
-        bool res[9] = {false, false, false, false, false, false, false, false, false};
-        if (ol && !ph.inout) {
-            res[1] = true; res[5] = !n.wym; res[8] = !n.wyp;
-            e_b += nu[1] * (ph.rin[1] + w1 * ph.rho0);
-            if (res[5]) e_b += nu[5] * (ph.rin[5] + w2 * ph.rho0);
-            if (res[8]) e_b += nu[8] * (ph.rin[8] + w2 * ph.rho0);
-        }
-        if (orr && !ph.inout) {
-            res[3] = true; res[6] = !n.wym; res[7] = !n.wyp;
-            e_b += nu[3] * (ph.rout[3] + w1 * ph.rho0);
-            if (res[6]) e_b += nu[6] * (ph.rout[6] + w2 * ph.rho0);
-            if (res[7]) e_b += nu[7] * (ph.rout[7] + w2 * ph.rho0);
-        }
-        // sliding y-walls: the returned diagonals carry +-eps * wb (wt)
-        if (n.wym) e_b += (nu[5] - nu[6]) * ph.wb;
-        if (n.wyp) e_b += (nu[8] - nu[7]) * ph.wt;
-        // push: the slot each incoming population came from (as in gather)
-        const int rm = n.ym * g.pitch, r0 = y * g.pitch, rp = n.yp * g.pitch;
-        const long long pl = g.plane;
-        const gptr<R> lg = to_global(lam);
-        gptr<R> L0 = lg, L1 = lg + pl, L2 = lg + 2 * pl, L3 = lg + 3 * pl, L4 = lg + 4 * pl,
-                L5 = lg + 5 * pl, L6 = lg + 6 * pl, L7 = lg + 7 * pl, L8 = lg + 8 * pl;
-        L0[c] = nu[0];
-        *(n.wxm ? L3 + c : L1 + r0 + n.xm) = res[1] ? R(0) : nu[1];
-        *(n.wym ? L4 + c : L2 + rm + x) = nu[2];
-        *(n.wxp ? L1 + c : L3 + r0 + n.xp) = res[3] ? R(0) : nu[3];
-        *(n.wyp ? L2 + c : L4 + rp + x) = nu[4];
-        *((n.wxm || n.wym) ? L7 + c : L5 + rm + n.xm) = res[5] ? R(0) : nu[5];
-        *((n.wxp || n.wym) ? L8 + c : L6 + rm + n.xp) = res[6] ? R(0) : nu[6];
-        *((n.wxp || n.wyp) ? L5 + c : L7 + rp + n.xp) = res[7] ? R(0) : nu[7];
-        *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = res[8] ? R(0) : nu[8];
-        ebg[c] += static_cast<double>(e_b);
-        gxg[c] += static_cast<double>(gx_b);
-        gyg[c] += static_cast<double>(gy_b);
+        boundary_inflow<R>(d[r], P.e0, ol, orr, n.wym, n.wyp, ph);
+        unshift_incoming<R>(d[r], P, ph.rho0);
+        R nu[9], e_b, gx_b, gy_b;
+        bool res[9];
+        adjoint_node<R, SEED>(d[r], P, n, ol, orr, x == g.Lx - 1, ph, mu[r], nu, res, e_b,
+                              gx_b, gy_b, acc);
+        push_global<R>(lam, g, x, y, n, nu, res);
+        ebg[c] = ae[r] + static_cast<double>(e_b);
+        gxg[c] = ax[r] + static_cast<double>(gx_b);
+        gyg[c] = ay[r] + static_cast<double>(gy_b);
     }
     if constexpr (SEED) block_partial(acc, part, t);
 }
@@ -2273,6 +2325,12 @@ struct lbm_vans_handle {
     bool use_graphs;
     hipStream_t cap;
     hipGraphExec_t graph[2];
+    // The gradient recomputes segment c - 1 on a second stream while the handle's
+    // stream runs the reverse steps of segment c: events hand the checkpoints over
+    // (ev_start), a recomputed segment set over (ev_rec[set]) and a set back once its
+    // reverse steps have read it (ev_rev[set]).
+    hipStream_t stream2;
+    hipEvent_t ev_start, ev_rec[2], ev_rev[2];
 };
 
 namespace {
@@ -2518,14 +2576,15 @@ int with_types(int storage, Fn &&fn)
 }
 
 template <typename S, typename R, bool DIAG, bool RG, int V>
-void launch_sweep_rg(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
+void launch_sweep_rg(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph,
+                     hipStream_t st)
 {
     const dim3 grid(h->gs.ntiles), block(NTHREADS);
     const R *eps = (const R *)h->eps;
     const int bx = h->gs.open_x ? 2 : (h->gs.wall_x ? 1 : 0);
     const bool wy = h->gs.wall_y;
 #define LBM_VANS_VEC(BXV, WYV)                                                                  \
-    hipLaunchKernelGGL((k_sweep_vec<S, R, V, BXV, WYV, DIAG, RG>), grid, block, 0, h->stream,    \
+    hipLaunchKernelGGL((k_sweep_vec<S, R, V, BXV, WYV, DIAG, RG>), grid, block, 0, st,           \
                        src, dst, eps, h->gs, ph, h->part)
     if (bx == 0 && !wy) LBM_VANS_VEC(0, false);
     else if (bx == 0) LBM_VANS_VEC(0, true);
@@ -2537,12 +2596,13 @@ void launch_sweep_rg(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph
 }
 
 template <typename S, typename R, bool DIAG>
-void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph)
+void launch_sweep_t(lbm_vans_handle *h, const S *src, S *dst, const Phys<R> &ph,
+                    hipStream_t st)
 {
     constexpr int VMAX = sizeof(S) == 8 ? 2 : 4;
-    if (h->vec == 1) launch_sweep_rg<S, R, DIAG, false, 1>(h, src, dst, ph);
-    else if (h->p.Lx % VMAX) launch_sweep_rg<S, R, DIAG, true, VMAX>(h, src, dst, ph);
-    else launch_sweep_rg<S, R, DIAG, false, VMAX>(h, src, dst, ph);
+    if (h->vec == 1) launch_sweep_rg<S, R, DIAG, false, 1>(h, src, dst, ph, st);
+    else if (h->p.Lx % VMAX) launch_sweep_rg<S, R, DIAG, true, VMAX>(h, src, dst, ph, st);
+    else launch_sweep_rg<S, R, DIAG, false, VMAX>(h, src, dst, ph, st);
 }
 
 // The multi-step passes address a plane (state or porosity, at most 4 bytes a
@@ -2735,15 +2795,18 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
 }
 
 // One time step from the state n stored in src into dst.
-int launch_sweep_ptrs(lbm_vans_handle *h, const void *src, void *dst, int64_t n, bool diag)
+// One step n from src to dst on stream st (the handle's stream when st is null).
+int launch_sweep_ptrs(lbm_vans_handle *h, const void *src, void *dst, int64_t n, bool diag,
+                      hipStream_t st = nullptr)
 {
+    if (!st) st = h->stream;
     return with_types(h->p.storage, [&](auto *sp, auto *rp) {
         using S = std::remove_pointer_t<decltype(sp)>;
         using R = std::remove_pointer_t<decltype(rp)>;
         Phys<R> ph = make_phys<R>(&h->p);
         ph.reservoir = res_on(&h->p, n);
-        if (diag) launch_sweep_t<S, R, true>(h, (const S *)src, (S *)dst, ph);
-        else launch_sweep_t<S, R, false>(h, (const S *)src, (S *)dst, ph);
+        if (diag) launch_sweep_t<S, R, true>(h, (const S *)src, (S *)dst, ph, st);
+        else launch_sweep_t<S, R, false>(h, (const S *)src, (S *)dst, ph, st);
         return check_launch("sweep");
     });
 }
@@ -2853,6 +2916,17 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
     // launch-bound lattices replay their steps as graphs (measured on MI355X, FP64
     // 80 x 80: see the design notes)
     h->use_graphs = h->gs.ntiles < 2 * ncu;
+    // the gradient's second stream (default priority) and its events
+    hipError_t e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
+    hipEvent_t *evs[5] = {&h->ev_start, &h->ev_rec[0], &h->ev_rec[1], &h->ev_rev[0],
+                          &h->ev_rev[1]};
+    for (int k = 0; k < 5 && e == hipSuccess; k++)
+        e = hipEventCreateWithFlags(evs[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        rc = fail(LBM_VANS_EHIP, "stream / event creation failed: %s", hipGetErrorString(e));
+        lbm_vans_destroy(h);
+        return rc;
+    }
     *out = h;
     return LBM_VANS_OK;
 }
@@ -3088,12 +3162,18 @@ int lbm_vans_diag_read(lbm_vans_handle *h, double *records, int32_t max_records,
 
 namespace {
 
+// Gradient workspace: nck checkpoints, nset sets of seg buffers for recomputed
+// segments, two adjoint buffers, three accumulators and (FP32 / FP16 storage) an
+// FP64 porosity copy.  Two segment sets (a lone handle with two or more segments)
+// let the recompute of one segment run beside the reverse steps of the next.
 struct GradLayout {
     size_t pop, lam, acc, eps64, total;
-    int64_t nck, seg;
+    int64_t nck, seg, nset;
+    int64_t states() const { return nck + nset * seg; }
 };
 
-GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_every)
+GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_every,
+                       bool two_sets)
 {
     Layout L = make_layout(p);
     Geo g = make_geo(p);
@@ -3102,12 +3182,13 @@ GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_ev
     G.nck = (nsteps + ckpt_every - 1) / ckpt_every;
     if (G.nck < 1) G.nck = 1;
     G.seg = ckpt_every;
+    G.nset = two_sets && G.nck >= 2 ? 2 : 1;
     // the reverse steps run in FP64 for every storage: FP64 adjoints and
     // accumulators, and for FP32 / FP16 storage an FP64 copy of the porosity
     G.lam = align256((size_t)9 * g.plane * sizeof(double));
     G.acc = align256((size_t)g.plane * sizeof(double));
     G.eps64 = p->storage != LBM_F64 ? align256((size_t)g.plane * sizeof(double)) : 0;
-    G.total = (size_t)(G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc + G.eps64;
+    G.total = (size_t)G.states() * G.pop + 2 * G.lam + 3 * G.acc + G.eps64;
     return G;
 }
 
@@ -3129,7 +3210,7 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
                                 int32_t ckpt_every)
 {
     if (check_grad_args(p, objective, nsteps, ckpt_every)) return 0;
-    return grad_layout(p, nsteps, ckpt_every).total;
+    return grad_layout(p, nsteps, ckpt_every, true).total;
 }
 
 namespace {
@@ -3145,18 +3226,18 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
     if (!grad_work || !dJdeps) return fail(LBM_VANS_EINVAL, "grad_work and dJdeps are required");
     if (reinterpret_cast<uintptr_t>(grad_work) % 256)
         return fail(LBM_VANS_EINVAL, "grad_work must be 256-byte aligned");
-    const GradLayout G = grad_layout(&h->p, nsteps, ckpt_every);
+    const GradLayout G = grad_layout(&h->p, nsteps, ckpt_every, true);
     if (grad_work_bytes < G.total)
         return fail(LBM_VANS_EINVAL, "grad_work has %zu bytes, %zu needed", grad_work_bytes,
                     G.total);
     char *w = static_cast<char *>(grad_work);
     auto ckpt = [&](int64_t c) { return w + c * G.pop; };
-    auto seg = [&](int64_t j) { return w + (G.nck + j) * G.pop; };
-    char *lam[2] = {w + (G.nck + G.seg) * G.pop, w + (G.nck + G.seg) * G.pop + G.lam};
-    double *eb = reinterpret_cast<double *>(w + (G.nck + G.seg) * G.pop + 2 * G.lam);
+    auto seg = [&](int64_t set, int64_t j) { return w + (G.nck + set * G.seg + j) * G.pop; };
+    char *lam[2] = {w + G.states() * G.pop, w + G.states() * G.pop + G.lam};
+    double *eb = reinterpret_cast<double *>(w + G.states() * G.pop + 2 * G.lam);
     double *gxb = eb + G.acc / sizeof(double);
     double *gyb = gxb + G.acc / sizeof(double);
-    double *eps64 = G.eps64 ? reinterpret_cast<double *>(w + (G.nck + G.seg) * G.pop +
+    double *eps64 = G.eps64 ? reinterpret_cast<double *>(w + G.states() * G.pop +
                                                          2 * G.lam + 3 * G.acc)
                             : nullptr;
     const Geo &g = h->g;
@@ -3231,17 +3312,50 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
         double rec[NRED];
         HIP_TRY(hipMemcpyAsync(rec, h->scratch_rec, sizeof rec, hipMemcpyDeviceToHost,
                                h->stream));
-        // 3. reverse, one checkpoint segment at a time (states recomputed)
+        // 3. reverse, one checkpoint segment at a time (states recomputed).  With two
+        // segment sets, segment c is recomputed into set c % 2 on the second stream
+        // while the handle's stream runs the reverse steps of segment c + 1: the
+        // recompute is bound by HBM and the FP64 reverse steps by their arithmetic,
+        // so the two share the GPU.
         const int64_t nck = nsteps == 0 ? 0 : (nsteps + K - 1) / K;
+        const bool two = G.nset == 2;
+        hipStream_t rs = two ? h->stream2 : h->stream;
+        auto recompute = [&](int64_t c) -> int {
+            const int64_t s0 = c * K, s1 = std::min<int64_t>(s0 + K, nsteps);
+            const int64_t set = two ? c % 2 : 0;
+            for (int64_t j = 1; j < s1 - s0; j++) {
+                const void *src = j == 1 ? (const void *)ckpt(c) : (const void *)seg(set, j - 1);
+                int rr = launch_sweep_ptrs(h, src, seg(set, j), s0 + j - 1, false, rs);
+                if (rr) return rr;
+            }
+            if (two) HIP_TRY(hipEventRecord(h->ev_rec[set], rs));
+            return LBM_VANS_OK;
+        };
+        if (two) {
+            // the checkpoints are written (and the seed has read the final state)
+            HIP_TRY(hipEventRecord(h->ev_start, h->stream));
+            HIP_TRY(hipStreamWaitEvent(rs, h->ev_start, 0));
+        }
+        if (nck > 0) {
+            r = recompute(nck - 1);
+            if (r) return r;
+        }
         for (int64_t c = nck - 1; c >= 0; c--) {
             const int64_t s0 = c * K, s1 = std::min<int64_t>(s0 + K, nsteps);
-            for (int64_t j = 1; j < s1 - s0; j++) {
-                const void *src = j == 1 ? (const void *)ckpt(c) : (const void *)seg(j - 1);
-                r = launch_sweep_ptrs(h, src, seg(j), s0 + j - 1, false);
+            const int64_t set = two ? c % 2 : 0;
+            if (two && c >= 1) {
+                // set (c - 1) % 2 is free once the reverse steps of segment c + 1 ran
+                if (c + 1 <= nck - 1) HIP_TRY(hipStreamWaitEvent(rs, h->ev_rev[(c + 1) % 2], 0));
+                r = recompute(c - 1);
+                if (r) return r;
+            } else if (!two && c < nck - 1) {
+                r = recompute(c);
                 if (r) return r;
             }
+            if (two) HIP_TRY(hipStreamWaitEvent(h->stream, h->ev_rec[set], 0));
             for (int64_t n = s1 - 1; n >= s0; n--) {
-                const void *state = n == s0 ? (const void *)ckpt(c) : (const void *)seg(n - s0);
+                const void *state =
+                    n == s0 ? (const void *)ckpt(c) : (const void *)seg(set, n - s0);
                 ph.reservoir = res_on(&h->p, n);
                 hipLaunchKernelGGL((k_adjoint<S, RA, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
                                    h->stream, (const S *)state, (const RA *)lam[a],
@@ -3250,6 +3364,7 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
                 if (r) return r;
                 a = 1 - a;
             }
+            if (two) HIP_TRY(hipEventRecord(h->ev_rev[set], h->stream));
         }
         // 4. initial state and the porosity stencil
         hipLaunchKernelGGL((k_adjoint_init<RA>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
@@ -3301,6 +3416,12 @@ void lbm_vans_destroy(lbm_vans_handle *h)
     for (auto &gx : h->graph)
         if (gx) (void)hipGraphExecDestroy(gx);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->stream2) {
+        (void)hipStreamSynchronize(h->stream2);
+        (void)hipStreamDestroy(h->stream2);
+    }
+    for (hipEvent_t ev : {h->ev_start, h->ev_rec[0], h->ev_rec[1], h->ev_rev[0], h->ev_rev[1]})
+        if (ev) (void)hipEventDestroy(ev);
     delete h;
 }
 
@@ -3416,15 +3537,15 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             lbm_vans_handle *h = b->m[k];
             Member<R> &d = D[k];
             if (gw) {
-                const GradLayout G = grad_layout(&h->p, nsteps, ckpt_every);
+                const GradLayout G = grad_layout(&h->p, nsteps, ckpt_every, false);
                 d.gw = gw + off;
                 d.gpop = static_cast<long long>(G.pop);
                 d.glam = static_cast<long long>(G.lam);
                 d.gacc = static_cast<long long>(G.acc);
-                d.nslot = static_cast<int>(G.nck + G.seg);
+                d.nslot = static_cast<int>(G.states());
                 if (G.eps64)
                     d.eps_a = reinterpret_cast<const double *>(
-                        d.gw + (G.nck + G.seg) * G.pop + 2 * G.lam + 3 * G.acc);
+                        d.gw + G.states() * G.pop + 2 * G.lam + 3 * G.acc);
                 off += align256(G.total);
             }
             std::memcpy(b->desc.data() + k * sizeof d, &d, sizeof d);
@@ -3878,7 +3999,7 @@ size_t lbm_vans_batch_grad_work_bytes(const lbm_vans_batch *b, int32_t objective
     size_t total = 0;
     for (const lbm_vans_handle *h : b->m) {
         if (check_grad_args(&h->p, objective, nsteps, ckpt_every)) return 0;
-        total += align256(grad_layout(&h->p, nsteps, ckpt_every).total);
+        total += align256(grad_layout(&h->p, nsteps, ckpt_every, false).total);
     }
     return total;
 }
@@ -3913,7 +4034,7 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
     std::vector<char *> gw;
     size_t off = 0;
     for (lbm_vans_handle *h : b->m) {
-        G.push_back(grad_layout(&h->p, nsteps, ckpt_every));
+        G.push_back(grad_layout(&h->p, nsteps, ckpt_every, false));
         gw.push_back(static_cast<char *>(grad_work) + off);
         off += align256(G.back().total);
     }
@@ -3956,7 +4077,7 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
         }
         // 2. seed: J of the state nsteps and the adjoint of that state
         for (size_t k = 0; k < b->m.size(); k++) {
-            double *eb = reinterpret_cast<double *>(gw[k] + (G[k].nck + G[k].seg) * G[k].pop +
+            double *eb = reinterpret_cast<double *>(gw[k] + G[k].states() * G[k].pop +
                                                     2 * G[k].lam);
             const long long nz = (long long)(3 * G[k].acc / sizeof(double));
             hipLaunchKernelGGL(k_zero, dim3((unsigned)((nz + NTHREADS - 1) / NTHREADS)),
@@ -3968,7 +4089,7 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
                 hipLaunchKernelGGL(k_widen, dim3((unsigned)((npl + NTHREADS - 1) / NTHREADS)),
                                    dim3(NTHREADS), 0, b->stream, (const float *)b->m[k]->eps,
                                    reinterpret_cast<double *>(
-                                       gw[k] + (G[k].nck + G[k].seg) * G[k].pop + 2 * G[k].lam +
+                                       gw[k] + G[k].states() * G[k].pop + 2 * G[k].lam +
                                        3 * G[k].acc),
                                    npl);
                 r = check_launch("k_widen");
@@ -4007,7 +4128,7 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
         // 4. initial state and the porosity stencil, member by member
         for (size_t k = 0; k < b->m.size(); k++) {
             lbm_vans_handle *h = b->m[k];
-            char *base = gw[k] + (G[k].nck + G[k].seg) * G[k].pop;
+            char *base = gw[k] + G[k].states() * G[k].pop;
             const double *lam = reinterpret_cast<const double *>(base + a * G[k].lam);
             double *eb = reinterpret_cast<double *>(base + 2 * G[k].lam);
             double *gxb = eb + G[k].acc / sizeof(double);

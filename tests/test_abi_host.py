@@ -117,8 +117,12 @@ def test_null_handle_calls_fail_cleanly():
     assert L.lbm_vans_grad_work_bytes(ctypes.byref(p.c()), 0, 10, 0) == 0   # ckpt_every < 1
     n1 = lbm.lbm_vans_grad_work_bytes(p, 0, 100, 10)
     n2 = lbm.lbm_vans_grad_work_bytes(p, 0, 100, 50)
+    n3 = lbm.lbm_vans_grad_work_bytes(p, 0, 40, 50)
     pop = 9 * 8 * 256 * 4
-    assert n1 >= (10 + 10) * pop and n2 >= (2 + 50) * pop
+    # checkpoints + two sets of segment buffers when there are two or more segments
+    # (one recomputed beside the reverse steps of the next), one set otherwise
+    assert n1 >= (10 + 2 * 10) * pop and n2 >= (2 + 2 * 50) * pop
+    assert (1 + 50) * pop <= n3 < (1 + 2 * 50) * pop
 
 
 def test_null_batch_calls_fail_cleanly():

@@ -109,11 +109,13 @@ def test_gradient_fp64_periodic_box_and_const_drag():
 
 
 def test_gradient_independent_of_checkpoint_interval():
-    """Recomputation is deterministic: any checkpoint interval gives the same bits."""
+    """Recomputation is deterministic: any checkpoint interval (one segment, or two or
+    more, whose recompute runs on the handle's second stream beside the reverse steps)
+    gives the same bits, and so does a repeated run."""
     spec = _open_spec(28, 8, "f64")
     eps = W.grf_porosity(28, 8, seed=41, ell=3.0, lo=0.4, hi=0.98)
     ref = None
-    for K in (1, 7, 60, 1000):
+    for K in (1, 7, 60, 1000, 7):
         J, g, _ = _grad_gpu(spec, eps, 60, K)
         if ref is None:
             ref = (J, g)
@@ -238,15 +240,17 @@ def test_full_size_gradient_against_oracle_central_differences(storage):
     steps, checkpoints every 200: J and dJ/deps at 32 random nodes of the whole channel
     against the oracle's FP64 J and central differences.
 
-    Each difference carries its own uncertainty (J's FP64 rounding over 2h, and the
-    O(h^2) truncation); the golden file holds differences at h and 2h, and
-    delta = |fd(h) - fd(2h)| stands for it.
-    * FP64: |g - fd| <= 1e-6 |fd| + 2 delta;
+    Each difference carries its own uncertainty: the O(h^2) truncation and J's FP64
+    rounding, which differs between the runs at eps +- h by about 1e-14 of J and so
+    adds about 1e-10 over 2h = 2e-4.  The golden file holds differences at h and 2h;
+    the largest |fd(h) - fd(2h)| over the 32 nodes (3.4e-10) stands for that noise
+    at every node (a single node's difference can be small by chance):
+    * FP64: |g - fd| <= 1e-6 |fd| + 2 noise;
     * FP32 storage (states stored and collided in FP32, reverse steps in FP64): the
       gradient carries the FP32 rounding of the recomputed trajectory, an absolute
       floor of about 1e-9 over the channel's interior (99th percentile 3.3e-9 against
       the FP64 gradient of the same workload; 1.3e-7 of the largest |dJ/deps|, which
-      sits at the inlet): |g - fd| <= 1e-4 |fd| + 2 delta + 2e-8, and the relative L2
+      sits at the inlet): |g - fd| <= 1e-4 |fd| + 2 noise + 2e-8, and the relative L2
       error over the 32 nodes <= 1e-4."""
     gold = _golden()
     w = W.ADJOINT_CHANNEL
@@ -259,6 +263,7 @@ def test_full_size_gradient_against_oracle_central_differences(storage):
     J, g, _ = _grad_gpu(spec, eps, w.steps, W.ADJOINT_CKPT)
     fd = np.array(gold["dJdeps_central_difference"])
     delta = np.abs(fd - np.array(gold["dJdeps_central_difference_2h"]))
+    noise = delta.max()
     ad = np.array([g[y, x] for (y, x) in gold["cells_yx"]])
     err = np.abs(ad - fd)
     say(f"  J {J:.12e} vs oracle {gold['J']:.12e}")
@@ -269,8 +274,8 @@ def test_full_size_gradient_against_oracle_central_differences(storage):
     if storage == "f64":
         # 4000 steps x 524k nodes of FMA / summation-order differences
         assert abs(J - gold["J"]) <= 1e-11 * abs(gold["J"])
-        assert np.all(err <= 1e-6 * np.abs(fd) + 2 * delta)
+        assert np.all(err <= 1e-6 * np.abs(fd) + 2 * noise)
     else:
         assert abs(J - gold["J"]) <= 1e-5 * abs(gold["J"])
-        assert np.all(err <= 1e-4 * np.abs(fd) + 2 * delta + 2e-8)
+        assert np.all(err <= 1e-4 * np.abs(fd) + 2 * noise + 2e-8)
         assert rel_l2(ad, fd) <= 1e-4

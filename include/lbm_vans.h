@@ -139,11 +139,13 @@ typedef struct lbm_vans_params {
                               fewer than the GPU's compute units, then 1); 1; or the
                               widest.  Results do not depend on it beyond rounding.   */
     int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 1, 2 or
-                              3; 0 = automatic: 3 when the three-step pass has at
-                              least 0.7 times as many waves (60 columns x pass_rows
-                              rows) as the GPU holds of its kernel at once, else 2
-                              when the two-step pass has >= 2048 waves (62 x 8, 16 in
-                              FP16), else 1.  Several steps per pass need
+                              3; 0 = automatic: 3 when the three-step pass has enough
+                              waves (60 columns x pass_rows rows each) for the GPU:
+                              0.9 times as many as it holds of the kernel at once in
+                              24-row chunks, a fifth in 12-row chunks (FP32), 0.7
+                              times (FP16, or an explicit pass_rows); else 2 when the
+                              two-step pass has >= 2048 waves (62 x 8, 16 in FP16),
+                              else 1.  Several steps per pass need
                               LBM_F32_SHIFTED or LBM_F16_SHIFTED storage and
                               diag_every = 0 (else one step per pass), and with
                               periodic y a lattice of at least pass_rows + 6 rows for
@@ -152,12 +154,13 @@ typedef struct lbm_vans_params {
                               storage rounds once per pass) and each pass recomputes
                               its chunk's halo.                                       */
     int32_t pass_rows;     /* output rows per chunk (wave) of the three-step pass:
-                              0 = automatic; LBM_F32_SHIFTED: 24 or 28 (automatic: 28
-                              when that still gives four times as many waves as the
-                              GPU holds of the kernel at once, else 24: taller chunks
+                              0 = automatic; LBM_F32_SHIFTED: 12, 24 or 28
+                              (automatic: 28 when that still gives four times as many
+                              waves as the GPU holds of the kernel at once, else 24
+                              when that gives 0.9 times as many, else 12: taller chunks
                               recompute fewer halo rows but give fewer waves);
-                              LBM_F16_SHIFTED: 24.  Results do not depend on it
-                              beyond rounding.                                        */
+                              LBM_F16_SHIFTED: 24.  Batches take 24 or 28.  Results
+                              do not depend on it beyond rounding.                    */
 } lbm_vans_params;
 
 typedef struct lbm_vans_handle lbm_vans_handle;

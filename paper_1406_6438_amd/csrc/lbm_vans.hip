@@ -141,6 +141,9 @@ int scratch_address(void **out)
 #ifndef LBM_VANS_TB3_TALL32
 #define LBM_VANS_TB3_TALL32 28
 #endif
+#ifndef LBM_VANS_TB3_SHORT32
+#define LBM_VANS_TB3_SHORT32 12
+#endif
 #ifndef LBM_VANS_TB3_ROWS16
 #define LBM_VANS_TB3_ROWS16 24
 #endif
@@ -1063,6 +1066,8 @@ constexpr int tb_cols()
 // 160.7 / 163.0 / 160.3; 2048^2 144.9 / 149.9 / 139.0 / 127.4; 64-member
 // ensemble 144.1 / 144.2 / 146.3 / 146.4).
 // The batched kernels tell the two FP32 heights apart by their row count.
+static_assert(LBM_VANS_TB3_SHORT32 < LBM_VANS_TB3_ROWS32,
+              "the short chunks of the FP32 three-step pass must be shorter than the default");
 static_assert(LBM_VANS_TB3_TALL32 > LBM_VANS_TB3_ROWS32,
               "the tall chunks of the FP32 three-step pass must be taller than the short ones");
 
@@ -2351,17 +2356,19 @@ long long geo_pitch(int Lx) { return (Lx + PITCH_ALIGN - 1LL) / PITCH_ALIGN * PI
 long long geo_plane(int Lx, int Ly) { return geo_pitch(Lx) * Ly; }
 
 // Chunk rows of the three-step pass a caller may ask for: 0 (automatic), the
-// short or the tall height with FP32 storage, the one height with FP16 storage.
+// short, default or tall height with FP32 storage, the one height with FP16 storage.
 int check_pass_rows(int32_t rows, int32_t storage)
 {
     if (rows == 0) return LBM_VANS_OK;
-    if (storage == LBM_F32_SHIFTED && (rows == tb_rows<float, 3>() || rows == LBM_VANS_TB3_TALL32))
+    if (storage == LBM_F32_SHIFTED &&
+        (rows == LBM_VANS_TB3_SHORT32 || rows == tb_rows<float, 3>() || rows == LBM_VANS_TB3_TALL32))
         return LBM_VANS_OK;
     if (storage == LBM_F16_SHIFTED && rows == tb_rows<_Float16, 3>()) return LBM_VANS_OK;
     return fail(LBM_VANS_EINVAL,
-                "pass_rows = %d: 0 (automatic); %d or %d with LBM_F32_SHIFTED storage; %d with "
-                "LBM_F16_SHIFTED storage",
-                rows, tb_rows<float, 3>(), LBM_VANS_TB3_TALL32, tb_rows<_Float16, 3>());
+                "pass_rows = %d: 0 (automatic); %d, %d or %d with LBM_F32_SHIFTED storage; %d "
+                "with LBM_F16_SHIFTED storage",
+                rows, LBM_VANS_TB3_SHORT32, tb_rows<float, 3>(), LBM_VANS_TB3_TALL32,
+                tb_rows<_Float16, 3>());
 }
 
 int check_params(const lbm_vans_params *p)
@@ -2674,6 +2681,8 @@ int tb3_resident(int storage, int bx, bool wy, int rows, bool batch, long long *
             constexpr int NR = LBM_VANS_TB3_TALL32;
             if (batch) q(k_batch_tb3<float, float, BXV, WYV, NR>);
             else q(k_sweep_tb3<float, float, BXV, WYV, NR>);
+        } else if (rows == LBM_VANS_TB3_SHORT32 && !batch) {
+            q(k_sweep_tb3<float, float, BXV, WYV, LBM_VANS_TB3_SHORT32>);
         } else {
             constexpr int NR = tb_rows<float, 3>();
             if (batch) q(k_batch_tb3<float, float, BXV, WYV, NR>);
@@ -2687,19 +2696,23 @@ int tb3_resident(int storage, int bx, bool wy, int rows, bool batch, long long *
     return LBM_VANS_OK;
 }
 
-// Automatic choices of the multi-step passes, measured on MI355X (FP32 GLUPS,
-// pairs / three steps in 24-row / in 28-row chunks; periodic box: 1024^2 102.9 /
-// 98.8 / 83.7, 2048 x 1024 127.7 / 145.2 / 129.2, 2048^2 110.9 / 149.0 / 139.3,
-// 4096^2 106.7 / 160.5 / 163.2; open channel with walls: 2048 x 1024 121.3 / 98.1 /
-// 77.5, 2048^2 107.3 / 137.4 / 111.7, 4096^2 105.3 / 149.8 / 146.8).  A
-// three-step wave walks its chunk's rows one after another, so the pass needs
-// most of the chip's resident waves at once: three steps when the lattice has at
-// least 0.7 times as many waves as the chip holds of that kernel; the tall chunks
-// (fewer halo rows) only with four times as many; else two steps when the
-// two-step pass has >= 2048 waves (open channel, GLUPS at one / two steps per
-// pass: 1024 x 512 56.6 / 56.5; 2048 x 1024 69.1 / 121.1), else one.
+// Automatic choices of the multi-step passes, measured on MI355X.  A three-step
+// wave walks its chunk's rows one after another, so the pass needs many waves in
+// flight: FP32 GLUPS at pairs / three steps in 12-row / 24-row chunks, periodic box
+// 1024^2 109 / 127 / 118, 1536 x 1024 124 / 139 / 123, 2048 x 1024 134 / 158 / 157,
+// 2048^2 109 / 157 / 161, 4096^2 108 / 164 / 164 (28 rows 164); channel with walls
+// and inlet / outlet 1024 x 512 57 / 64 / 37 (one step per pass 58), 1024^2 88 / 93
+// / 72, 2048 x 1024 112 / 121 / 108.  FP32: 24-row chunks when the lattice has at
+// least 0.9 times as many of their waves as the chip holds at once (28-row chunks, which
+// recompute fewer halo rows, with four times as many), else 12-row chunks when
+// those have at least a fifth of what the chip holds; three steps in the chosen
+// height, else pairs when the two-step pass has >= 2048 waves, else one step.
+// FP16 (one height): three steps when the lattice has 0.7 times as many waves as
+// the chip holds, else pairs or one step as above.
 constexpr int TALL_FILL = 4;                // tall chunks: waves >= 4 x resident
-constexpr int TRIPLE_FILL_10 = 7;           // three steps: waves >= 0.7 x resident
+constexpr int DEFAULT_FILL_10 = 9;          // FP32 24-row chunks: waves >= 0.9 x resident
+constexpr int SHORT_FILL_10 = 2;            // FP32 12-row chunks: waves >= 0.2 x resident
+constexpr int TRIPLE_FILL_10 = 7;           // FP16, or an explicit height: >= 0.7 x
 
 bool tall_auto(long long tall_waves, long long resident)
 {
@@ -2714,21 +2727,37 @@ int choose_passes(lbm_vans_handle *h)
     if (p->storage == LBM_F64 || !multi_fits(h->g)) return LBM_VANS_OK;
     const int bx = h->g.open_x ? 2 : (h->g.wall_x ? 1 : 0);
     const bool f16 = p->storage == LBM_F16_SHIFTED;
+    const bool wy = h->g.wall_y;
     long long res = 0;
     int rc;
+    // the fill a three-step pass in rows3-row chunks needs (tenths of the waves
+    // the chip holds of its kernel)
+    int fill10 = TRIPLE_FILL_10;
     if (f16) {
         h->rows3 = tb_rows<_Float16, 3>();
     } else if (p->pass_rows != 0) {
         h->rows3 = p->pass_rows;
     } else {
-        rc = tb3_resident(p->storage, bx, h->g.wall_y, LBM_VANS_TB3_TALL32, false, &res);
+        rc = tb3_resident(p->storage, bx, wy, LBM_VANS_TB3_TALL32, false, &res);
         if (rc) return rc;
-        if (tall_auto(waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32), res))
+        long long res24 = 0;
+        rc = tb3_resident(p->storage, bx, wy, tb_rows<float, 3>(), false, &res24);
+        if (rc) return rc;
+        if (tall_auto(waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32), res)) {
             h->rows3 = LBM_VANS_TB3_TALL32;
+        } else if (10 * waves_of(p->Lx, p->Ly, 3, tb_rows<float, 3>()) >=
+                       DEFAULT_FILL_10 * res24 ||
+                   !multi_rows_ok(p->Ly, wy, 3, LBM_VANS_TB3_SHORT32)) {
+            h->rows3 = tb_rows<float, 3>();
+            fill10 = DEFAULT_FILL_10;
+        } else {
+            h->rows3 = LBM_VANS_TB3_SHORT32;
+            fill10 = SHORT_FILL_10;
+        }
     }
-    rc = tb3_resident(p->storage, bx, h->g.wall_y, h->rows3, false, &res);
+    rc = tb3_resident(p->storage, bx, wy, h->rows3, false, &res);
     if (rc) return rc;
-    if (10 * waves_of(p->Lx, p->Ly, 3, h->rows3) >= TRIPLE_FILL_10 * res)
+    if (10 * waves_of(p->Lx, p->Ly, 3, h->rows3) >= fill10 * res)
         h->auto_pass = 3;
     else if (waves_of(p->Lx, p->Ly, 2, tb2_rows_of(p->storage)) >= 2048)
         h->auto_pass = 2;
@@ -2783,6 +2812,8 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
                 } else if constexpr (std::is_same_v<S, float>) {
                     if (rows == LBM_VANS_TB3_TALL32)
                         run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_TALL32>);
+                    else if (rows == LBM_VANS_TB3_SHORT32)
+                        run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_SHORT32>);
                     else
                         run(k_sweep_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
                 } else {
@@ -2794,8 +2825,8 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
     });
 }
 
-// One time step from the state n stored in src into dst.
-// One step n from src to dst on stream st (the handle's stream when st is null).
+// One step n from the state stored in src into dst, on stream st (the handle's
+// stream when st is null).
 int launch_sweep_ptrs(lbm_vans_handle *h, const void *src, void *dst, int64_t n, bool diag,
                       hipStream_t st = nullptr)
 {
@@ -3731,6 +3762,9 @@ int check_config(const lbm_vans_batch *b, const lbm_vans_batch_config *c)
     if (c->steps_per_pass < 0 || c->steps_per_pass > 3)
         return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2 or 3",
                     c->steps_per_pass);
+    if (c->pass_rows == LBM_VANS_TB3_SHORT32)
+        return fail(LBM_VANS_EINVAL, "pass_rows = %d: batches take %d or %d (or 0)",
+                    c->pass_rows, tb_rows<float, 3>(), LBM_VANS_TB3_TALL32);
     return check_pass_rows(c->pass_rows, b->storage);
 }
 

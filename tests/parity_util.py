@@ -77,16 +77,19 @@ class Spec:
 
 # Execution paths of lbm_vans_step: "auto" (the library's choice: on the small test
 # grids the one-step sweep with one node per lane, as their widest sweep would have
-# fewer tiles than the GPU has compute units), "triples" (three steps per pass, the short chunks
-# the small grids get), "tall" (three steps per pass in 28-row chunks: FP32 storage;
-# the FP16 pass has one height), "pairs" (at most two steps per pass), "wide" (one
-# step per pass, widest vector width) and "narrow" (one step per pass, one node per
-# lane), so that the test grids cover every sweep kernel.
+# fewer tiles than the GPU has compute units), "triples" (three steps per pass in the
+# default 24-row chunks), "short" (three steps per pass in 12-row chunks: FP32
+# storage), "tall" (three steps per pass in 28-row chunks: FP32 storage; the FP16 pass
+# has one height), "pairs" (at most two steps per pass), "wide" (one step per pass,
+# widest vector width) and "narrow" (one step per pass, one node per lane), so that
+# the test grids cover every sweep kernel.
 def exec_mode(mode: str, storage: str) -> dict:
     if mode == "auto":
         return {}
     if mode == "triples":
-        return {"steps_per_pass": 3}
+        return {"steps_per_pass": 3, "pass_rows": 24 if storage in ("f32", "f16") else 0}
+    if mode == "short":
+        return {"steps_per_pass": 3, "pass_rows": 12 if storage == "f32" else 0}
     if mode == "tall":
         return {"steps_per_pass": 3, "pass_rows": 28 if storage == "f32" else 0}
     if mode == "pairs":

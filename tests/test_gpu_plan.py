@@ -56,8 +56,10 @@ def _plan(Lx, Ly, channel=False, storage="f32", **kw):
 @pytest.mark.parametrize("Lx, Ly, channel, storage, expected", [
     (4096, 4096, False, "f32", (3, 24)),
     (2048, 2048, False, "f32", (3, 24)),
-    (1024, 1024, False, "f32", (2, 24)),
-    (1024, 512, True, "f32", (1, 24)),
+    (2048, 1024, False, "f32", (3, 12)),
+    (1024, 1024, False, "f32", (3, 12)),
+    (1024, 512, True, "f32", (3, 12)),
+    (512, 256, False, "f32", (1, 12)),
     (4096, 4096, True, "f32", (3, 28)),
     (4096, 4096, False, "f16", (3, 24)),
     (64, 32, False, "f64", (1, 0)),
@@ -70,7 +72,8 @@ def test_automatic_plan(Lx, Ly, channel, storage, expected):
     (dict(steps_per_pass=2, pass_rows=28), (2, 28)),
     (dict(steps_per_pass=3, pass_rows=24), (3, 24)),
     (dict(steps_per_pass=3, pass_rows=28), (3, 28)),
-    (dict(steps_per_pass=1), (1, 24)),
+    (dict(steps_per_pass=3, pass_rows=12), (3, 12)),
+    (dict(steps_per_pass=1), (1, 12)),
 ])
 def test_explicit_plan(kw, expected):
     assert _plan(96, 40, **kw) == expected
@@ -86,6 +89,8 @@ def test_batch_plan():
     assert b.pass_plan == (3, 28)
     b.configure(4, 0, 24, 2, 0)
     assert b.pass_plan == (2, 24)
+    with pytest.raises(lbm.LbmVansError):      # the 12-row height is for lone lattices
+        b.configure(4, 0, 24, 3, 12)
     b.close()
     for s in sv:
         s.close()

@@ -45,7 +45,7 @@ PROFILE_TRAFFIC = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_traffic_
 PROFILE_VALU = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_valu_box4096_f32.md"),
                 "box8192_f16": os.path.join(ROOT, "profiles", "sweep_valu_box8192_f16.md"),
                 "ensemble64_f32": os.path.join(ROOT, "profiles", "batch_valu_ensemble64_f32.md")}
-MULTI_KERNEL = {1: "k_sweep_vec", 2: "k_sweep_tb2", 3: "k_sweep_tb3"}
+MULTI_KERNEL = {1: "k_sweep_vec", 2: "k_sweep_tb2", 3: "k_sweep_tb3", 4: "k_sweep_tb4"}
 BATCH_KERNEL = {1: "k_batch_sweep", 2: "k_batch_tb2", 3: "k_batch_tb3"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
 
@@ -259,7 +259,7 @@ def speed_error(gpu, res) -> float:
 def crop_sample(w, lbm, steps: int, plan):
     """The GPU run of the top-left 512^2 crop of the workload's porosity, run periodic
     in the launch plan of the timed run (plan = steps per pass, rows per chunk of the
-    three-step pass), and the matching oracle job."""
+    multi-step pass), and the matching oracle job."""
     import dataclasses
     from paper_1406_6438_amd import workloads as W
     n = W.CROP
@@ -285,7 +285,7 @@ def time_sweep(w, lbm, torch, steps: int, warmup: int, single_steps: int = 0, re
     that take the plan's full steps per pass (the dominant kernel), the final
     diagnostics record, the porosity, the seconds per step when every step is its own
     launch (k_sweep_vec; None without single_steps) and the launch plan (most steps per
-    pass, rows per chunk of the three-step pass)."""
+    pass, rows per chunk of the multi-step pass)."""
     import statistics
     eps = w.porosity()
     s = lbm.Solver(lbm_params(w, lbm), cast_eps(eps, w.storage))

@@ -138,8 +138,12 @@ typedef struct lbm_vans_params {
                               of that many nodes, by 4 rows; FP16: 8 rows) would be
                               fewer than the GPU's compute units, then 1); 1; or the
                               widest.  Results do not depend on it beyond rounding.   */
-    int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 1, 2 or
-                              3; 0 = automatic: 3 when the three-step pass has enough
+    int32_t steps_per_pass;/* most time steps one pass over the lattice takes: 1, 2, 3
+                              or 4 (4: LBM_F32_SHIFTED storage, 24-row chunks of
+                              58-column strips); 0 = automatic: 4 with FP32 storage and
+                              pass_rows = 0 when the four-step pass has at least as many
+                              waves as the GPU holds of its kernel at once, else 3
+                              when the three-step pass has enough
                               waves (60 columns x pass_rows rows each) for the GPU:
                               0.9 times as many as it holds of the kernel at once in
                               24-row chunks, a fifth in 12-row chunks (FP32), 0.7
@@ -149,7 +153,8 @@ typedef struct lbm_vans_params {
                               LBM_F32_SHIFTED or LBM_F16_SHIFTED storage and
                               diag_every = 0 (else one step per pass), and with
                               periodic y a lattice of at least pass_rows + 6 rows for
-                              three steps (chunk rows + 4 for two; else fewer steps);
+                              three steps (32 for four, chunk rows + 4 for two; else
+                              fewer steps);
                               the intermediate states stay in registers (so FP16
                               storage rounds once per pass) and each pass recomputes
                               its chunk's halo.                                       */

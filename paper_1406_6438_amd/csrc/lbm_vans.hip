@@ -144,6 +144,9 @@ int scratch_address(void **out)
 #ifndef LBM_VANS_TB3_SHORT32
 #define LBM_VANS_TB3_SHORT32 12
 #endif
+#ifndef LBM_VANS_TB4_ROWS32
+#define LBM_VANS_TB4_ROWS32 24
+#endif
 #ifndef LBM_VANS_TB3_ROWS16
 #define LBM_VANS_TB3_ROWS16 24
 #endif
@@ -1074,7 +1077,9 @@ static_assert(LBM_VANS_TB3_TALL32 > LBM_VANS_TB3_ROWS32,
 template <typename S, int NS = 2>
 constexpr int tb_rows()
 {
-    if constexpr (NS == 3)
+    if constexpr (NS == 4)
+        return LBM_VANS_TB4_ROWS32;
+    else if constexpr (NS == 3)
         return std::is_same_v<S, _Float16> ? LBM_VANS_TB3_ROWS16 : LBM_VANS_TB3_ROWS32;
     else
         return std::is_same_v<S, _Float16> ? LBM_VANS_TB_ROWS16 : LBM_VANS_TB_ROWS32;
@@ -1161,7 +1166,7 @@ template <typename S, int NS>
 constexpr bool tb_reuse()
 {
     constexpr bool f16 = std::is_same_v<S, _Float16>;
-    return NS == 3 && (LBM_VANS_TB_REUSE == 2 || (LBM_VANS_TB_REUSE == 1 && f16) ||
+    return NS >= 3 && (LBM_VANS_TB_REUSE == 2 || (LBM_VANS_TB_REUSE == 1 && f16) ||
                        (LBM_VANS_TB_REUSE == 3 && !f16));
 }
 
@@ -1173,7 +1178,7 @@ constexpr bool tb_reuse()
 template <typename S, int NS, int BX = 0, bool WY = false>
 constexpr int tb_ahead()
 {
-    return (NS == 3 && (std::is_same_v<S, _Float16> || BX != 0 || WY)) ? 1 : TB_AHEAD;
+    return (NS >= 3 && (std::is_same_v<S, _Float16> || BX != 0 || WY)) ? 1 : TB_AHEAD;
 }
 
 // Most waves per SIMD the compiler schedules the three-step kernel for: 2 for the
@@ -1206,7 +1211,7 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
                                         const Phys<R> &ph, int strip, int chunk, int res_a)
 {
     static_assert(std::is_same_v<R, float>, "the multi-step pass computes in FP32");
-    static_assert(NS == 2 || NS == 3, "two or three steps per pass");
+    static_assert(NS >= 2 && NS <= 4, "two to four steps per pass");
     constexpr bool WX = BX != 0;
     constexpr int H = NS - 1;                 // halo lanes per side, halo rows per chunk end
     constexpr int PD = tb_ahead<S, NS, BX, WY>();
@@ -1390,18 +1395,30 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
                                                  BX == 2 && wxp, ph, nullptr, false);
         }
     };
-    // second step of a three-step pass at row y0+b (b = -1 .. NR) into P2[b+1]
-    R P2[NS == 3 ? NR + 2 : 1][9];
+    // second step of a three- or four-step pass at row y0+b (b = -(NS-2) .. NR+NS-3)
+    // into P2[b+O2]; third step of a four-step pass at row y0+c (c = -1 .. NR) into
+    // P3[c+1]
+    constexpr int O2 = NS - 2;
+    R P2[NS >= 3 ? NR + 2 * (NS - 2) : 1][9];
+    R P3[NS == 4 ? NR + 2 : 1][9];
     auto middle = [&](int b) {
-        if constexpr (NS == 3) {
-            pull(std::false_type{}, P2[b + 1], P1[b - 1 + H], P1[b + H], P1[b + 1 + H], y0 + b,
+        if constexpr (NS >= 3) {
+            pull(std::false_type{}, P2[b + O2], P1[b - 1 + H], P1[b + H], P1[b + 1 + H], y0 + b,
                  b + H);
+        }
+    };
+    auto middle2 = [&](int c) {
+        if constexpr (NS == 4) {
+            pull(std::false_type{}, P3[c + 1], P2[c - 1 + O2], P2[c + O2], P2[c + 1 + O2],
+                 y0 + c, c + H);
         }
     };
     // last step at output row y0+j, stored
     auto last = [&](int j) {
         R d[9];
-        if constexpr (NS == 3)
+        if constexpr (NS == 4)
+            pull(std::true_type{}, d, P3[j], P3[j + 1], P3[j + 2], y0 + j, j + H);
+        else if constexpr (NS == 3)
             pull(std::true_type{}, d, P2[j], P2[j + 1], P2[j + 2], y0 + j, j + H);
         else
             pull(std::true_type{}, d, P1[j - 1 + H], P1[j + H], P1[j + 1 + H], y0 + j, j + H);
@@ -1413,22 +1430,25 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     };
 
     // prologue: the porosity rows of the first PD iterations, the gathers of the
-    // first-step rows -H .. H-1+PD, the first-step rows -H .. H-1 and, for three
-    // steps, the second-step rows -1 and 0
+    // first-step rows -H .. H-1+PD, the first-step rows -H .. H-1, the second-step
+    // rows -(NS-2) .. NS-3 and, for four steps, the third-step rows -1 and 0
 #pragma unroll
     for (int k = 0; k < 2 * H + 2 + PD && k < NE; k++) eps_row(k);
 #pragma unroll
     for (int a = -H; a <= H - 1 + PD && a <= NR + H - 1; a++) issue(a);
 #pragma unroll
     for (int a = -H; a <= H - 1; a++) finish(a);
-    middle(-1);
-    middle(0);
+#pragma unroll
+    for (int b = -(NS - 2); b <= NS - 3; b++) middle(b);
+    middle2(-1);
+    middle2(0);
     static_while<NR>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         finish(j + H);
         if constexpr (j + H + PD <= NR + H - 1) issue(j + H + PD);
         if constexpr (j + 2 * H + 2 + PD < NE) eps_row(j + 2 * H + 2 + PD);
-        middle(j + 1);
+        middle(j + NS - 2);
+        middle2(j + 1);
         last(j);
         return true;
     });
@@ -1470,6 +1490,18 @@ __attribute__((amdgpu_waves_per_eu(1, tb3_max_waves<S, BX, WY>()))) void k_sweep
                                                         int res_a)
 {
     sweep_multi<S, R, BX, WY, 3, NR>(fin, fout, eps, g, ph, nstrips, nchunks, res_a);
+}
+
+// Four steps per launch (FP32 storage), in chunks of NR rows.
+template <typename S, typename R, int BX, bool WY, int NR>
+__global__ __launch_bounds__(NTHREADS)
+__attribute__((amdgpu_waves_per_eu(1, tb3_max_waves<S, BX, WY>()))) void k_sweep_tb4(const S *__restrict__ fin,
+                                                        S *__restrict__ fout,
+                                                        const R *__restrict__ eps, Geo g,
+                                                        Phys<R> ph, int nstrips, int nchunks,
+                                                        int res_a)
+{
+    sweep_multi<S, R, BX, WY, 4, NR>(fin, fout, eps, g, ph, nstrips, nchunks, res_a);
 }
 
 // Macroscopic fields of the current state (no collision, no store of
@@ -2424,9 +2456,11 @@ int check_params(const lbm_vans_params *p)
     if (p->sweep_vec != 0 && p->sweep_vec != 1 && p->sweep_vec != vmax)
         return fail(LBM_VANS_EINVAL, "sweep_vec = %d: 0 (automatic), 1 or %d", p->sweep_vec,
                     vmax);
-    if (p->steps_per_pass < 0 || p->steps_per_pass > 3)
-        return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2 or 3",
+    if (p->steps_per_pass < 0 || p->steps_per_pass > 4)
+        return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2, 3 or 4",
                     p->steps_per_pass);
+    if (p->steps_per_pass == 4 && p->storage != LBM_F32_SHIFTED)
+        return fail(LBM_VANS_EINVAL, "steps_per_pass = 4 needs LBM_F32_SHIFTED storage");
     if (check_pass_rows(p->pass_rows, p->storage)) return LBM_VANS_EINVAL;
     return LBM_VANS_OK;
 }
@@ -2639,7 +2673,7 @@ int tb2_rows_of(int storage)
 // Waves of the ns-step pass (2 or 3) over an Lx x Ly lattice in chunks of `rows`.
 long long waves_of(int Lx, int Ly, int ns, int rows)
 {
-    const int cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
+    const int cols = TX - 2 * (ns - 1);
     return static_cast<long long>((Lx + cols - 1) / cols) * ((Ly + rows - 1) / rows);
 }
 
@@ -2696,6 +2730,24 @@ int tb3_resident(int storage, int bx, bool wy, int rows, bool batch, long long *
     return LBM_VANS_OK;
 }
 
+// The same for the four-step kernel (FP32, lone lattices).
+int tb4_resident(int bx, bool wy, long long *out)
+{
+    int nb = 0, dev = 0, ncu = 0;
+    hipError_t e = hipSuccess;
+    with_bxwy(bx, wy, [&](auto bxc, auto wyc) {
+        constexpr int BXV = decltype(bxc)::value;
+        constexpr bool WYV = decltype(wyc)::value;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_sweep_tb4<float, float, BXV, WYV, tb_rows<float, 4>()>, NTHREADS, 0);
+    });
+    HIP_TRY(e);
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    *out = static_cast<long long>(nb) * NW * ncu;
+    return LBM_VANS_OK;
+}
+
 // Automatic choices of the multi-step passes, measured on MI355X.  A three-step
 // wave walks its chunk's rows one after another, so the pass needs many waves in
 // flight: FP32 GLUPS at pairs / three steps in 12-row / 24-row chunks, periodic box
@@ -2708,7 +2760,12 @@ int tb3_resident(int storage, int bx, bool wy, int rows, bool batch, long long *
 // those have at least a fifth of what the chip holds; three steps in the chosen
 // height, else pairs when the two-step pass has >= 2048 waves, else one step.
 // FP16 (one height): three steps when the lattice has 0.7 times as many waves as
-// the chip holds, else pairs or one step as above.
+// the chip holds, else pairs or one step as above.  Four steps per pass (FP32, 24-row
+// chunks, 58-column strips) when that pass has at least as many waves as the chip
+// holds and the chunk height is automatic: GLUPS at three / four steps, periodic box
+// 2048^2 160.8 / 163.5, 4096^2 162.8 / 198.0, 8192^2 164.9 / 208.5; channel 4096^2
+// 155.5 / 165.0.
+constexpr int QUAD_FILL = 1;                // four steps: waves >= resident
 constexpr int TALL_FILL = 4;                // tall chunks: waves >= 4 x resident
 constexpr int DEFAULT_FILL_10 = 9;          // FP32 24-row chunks: waves >= 0.9 x resident
 constexpr int SHORT_FILL_10 = 2;            // FP32 12-row chunks: waves >= 0.2 x resident
@@ -2761,6 +2818,12 @@ int choose_passes(lbm_vans_handle *h)
         h->auto_pass = 3;
     else if (waves_of(p->Lx, p->Ly, 2, tb2_rows_of(p->storage)) >= 2048)
         h->auto_pass = 2;
+    if (!f16 && p->pass_rows == 0 && multi_rows_ok(p->Ly, wy, 4, tb_rows<float, 4>())) {
+        long long res4 = 0;
+        rc = tb4_resident(bx, wy, &res4);
+        if (rc) return rc;
+        if (waves_of(p->Lx, p->Ly, 4, tb_rows<float, 4>()) >= QUAD_FILL * res4) h->auto_pass = 4;
+    }
     return LBM_VANS_OK;
 }
 
@@ -2770,6 +2833,9 @@ int max_pass(const lbm_vans_handle *h)
 {
     if (h->p.storage == LBM_F64 || !multi_fits(h->g)) return 1;
     int m = h->p.steps_per_pass != 0 ? h->p.steps_per_pass : h->auto_pass;
+    if (m == 4 && (h->p.storage != LBM_F32_SHIFTED ||
+                   !multi_rows_ok(h->p.Ly, h->g.wall_y, 4, tb_rows<float, 4>())))
+        m = 3;
     if (m == 3 && !multi_rows_ok(h->p.Ly, h->g.wall_y, 3, h->rows3)) m = 2;
     if (m == 2 && !multi_rows_ok(h->p.Ly, h->g.wall_y, 2, tb2_rows_of(h->p.storage))) m = 1;
     return m;
@@ -2779,7 +2845,10 @@ int max_pass(const lbm_vans_handle *h)
 int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
 {
     if (!multi_fits(h->g)) return fail(LBM_VANS_EINVAL, "lattice too large for the multi-step pass");
-    if (!multi_rows_ok(h->p.Ly, h->g.wall_y, ns, ns == 3 ? h->rows3 : tb2_rows_of(h->p.storage)))
+    if (ns == 4 && h->p.storage != LBM_F32_SHIFTED)
+        return fail(LBM_VANS_EINVAL, "the four-step pass needs LBM_F32_SHIFTED storage");
+    const int nsrows = ns == 4 ? tb_rows<float, 4>() : (ns == 3 ? h->rows3 : tb2_rows_of(h->p.storage));
+    if (!multi_rows_ok(h->p.Ly, h->g.wall_y, ns, nsrows))
         return fail(LBM_VANS_EINVAL, "lattice too short in y for the multi-step pass");
     return with_types(h->p.storage, [&](auto *sp, auto *rp) -> int {
         using S = std::remove_pointer_t<decltype(sp)>;
@@ -2787,8 +2856,8 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
         if constexpr (std::is_same_v<S, double>) {
             return fail(LBM_VANS_EINVAL, "multi-step pass needs FP32 or FP16 storage");
         } else {
-            const int cols = ns == 3 ? tb_cols<3>() : tb_cols<2>();
-            const int rows = ns == 3 ? h->rows3 : tb_rows<S, 2>();
+            const int cols = TX - 2 * (ns - 1);
+            const int rows = nsrows;
             const int nstrips = (h->p.Lx + cols - 1) / cols;
             const int nchunks = (h->p.Ly + rows - 1) / rows;
             const long long waves = (long long)nstrips * nchunks;
@@ -2810,7 +2879,9 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
                 if (ns == 2) {
                     run(k_sweep_tb2<S, R, BXV, WYV>);
                 } else if constexpr (std::is_same_v<S, float>) {
-                    if (rows == LBM_VANS_TB3_TALL32)
+                    if (ns == 4)
+                        run(k_sweep_tb4<S, R, BXV, WYV, tb_rows<float, 4>()>);
+                    else if (rows == LBM_VANS_TB3_TALL32)
                         run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_TALL32>);
                     else if (rows == LBM_VANS_TB3_SHORT32)
                         run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_SHORT32>);
@@ -2820,7 +2891,7 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
                     run(k_sweep_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
                 }
             });
-            return check_launch(ns == 3 ? "k_sweep_tb3" : "k_sweep_tb2");
+            return check_launch(ns == 4 ? "k_sweep_tb4" : ns == 3 ? "k_sweep_tb3" : "k_sweep_tb2");
         }
     });
 }
@@ -3075,8 +3146,9 @@ int lbm_vans_pass_plan(const lbm_vans_handle *h, int32_t *steps_per_pass, int32_
 {
     if (!h) return fail(LBM_VANS_EINVAL, "handle is NULL");
     const bool multi = h->p.storage != LBM_F64 && multi_fits(h->g);
-    if (steps_per_pass) *steps_per_pass = max_pass(h);
-    if (pass_rows) *pass_rows = multi ? h->rows3 : 0;
+    const int m = max_pass(h);
+    if (steps_per_pass) *steps_per_pass = m;
+    if (pass_rows) *pass_rows = multi ? (m == 4 ? tb_rows<float, 4>() : h->rows3) : 0;
     return LBM_VANS_OK;
 }
 

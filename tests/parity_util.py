@@ -80,7 +80,8 @@ class Spec:
 # fewer tiles than the GPU has compute units), "triples" (three steps per pass in the
 # default 24-row chunks), "short" (three steps per pass in 12-row chunks: FP32
 # storage), "tall" (three steps per pass in 28-row chunks: FP32 storage; the FP16 pass
-# has one height), "pairs" (at most two steps per pass), "wide" (one step per pass,
+# has one height), "quads" (four steps per pass: FP32 storage), "pairs" (at most two
+# steps per pass), "wide" (one step per pass,
 # widest vector width) and "narrow" (one step per pass, one node per lane), so that
 # the test grids cover every sweep kernel.
 def exec_mode(mode: str, storage: str) -> dict:
@@ -92,6 +93,8 @@ def exec_mode(mode: str, storage: str) -> dict:
         return {"steps_per_pass": 3, "pass_rows": 12 if storage == "f32" else 0}
     if mode == "tall":
         return {"steps_per_pass": 3, "pass_rows": 28 if storage == "f32" else 0}
+    if mode == "quads":
+        return {"steps_per_pass": 4}
     if mode == "pairs":
         return {"steps_per_pass": 2}
     if mode == "wide":

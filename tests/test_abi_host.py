@@ -75,7 +75,8 @@ def test_work_bytes_scale_with_storage():
     dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30), dict(diag_every=-1),
     dict(Lx=65536, Ly=65536), dict(u_wall=(0.01, 0.0)), dict(bc_y=1, u_wall=(math.nan, 0.0)),
     dict(sweep_vec=3), dict(sweep_vec=4, storage=lbm.F64), dict(sweep_vec=2),
-    dict(steps_per_pass=4), dict(steps_per_pass=-1),
+    dict(steps_per_pass=5), dict(steps_per_pass=-1), dict(steps_per_pass=4, storage=lbm.F16_SHIFTED),
+    dict(steps_per_pass=4, storage=lbm.F64),
     dict(pass_rows=16), dict(pass_rows=-24), dict(pass_rows=28, storage=lbm.F16_SHIFTED),
     dict(pass_rows=12, storage=lbm.F16_SHIFTED), dict(pass_rows=12, storage=lbm.F64),
     dict(pass_rows=24, storage=lbm.F64),

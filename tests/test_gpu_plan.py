@@ -54,13 +54,13 @@ def _plan(Lx, Ly, channel=False, storage="f32", **kw):
 
 
 @pytest.mark.parametrize("Lx, Ly, channel, storage, expected", [
-    (4096, 4096, False, "f32", (3, 24)),
-    (2048, 2048, False, "f32", (3, 24)),
+    (4096, 4096, False, "f32", (4, 24)),
+    (2048, 2048, False, "f32", (4, 24)),
     (2048, 1024, False, "f32", (3, 12)),
     (1024, 1024, False, "f32", (3, 12)),
     (1024, 512, True, "f32", (3, 12)),
     (512, 256, False, "f32", (1, 12)),
-    (4096, 4096, True, "f32", (3, 28)),
+    (4096, 4096, True, "f32", (4, 24)),
     (4096, 4096, False, "f16", (3, 24)),
     (64, 32, False, "f64", (1, 0)),
 ])
@@ -73,6 +73,8 @@ def test_automatic_plan(Lx, Ly, channel, storage, expected):
     (dict(steps_per_pass=3, pass_rows=24), (3, 24)),
     (dict(steps_per_pass=3, pass_rows=28), (3, 28)),
     (dict(steps_per_pass=3, pass_rows=12), (3, 12)),
+    (dict(steps_per_pass=4), (4, 24)),
+    (dict(steps_per_pass=4, pass_rows=12), (4, 24)),
     (dict(steps_per_pass=1), (1, 12)),
 ])
 def test_explicit_plan(kw, expected):

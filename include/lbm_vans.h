@@ -194,8 +194,9 @@ int lbm_vans_init(const lbm_vans_params *p, const void *eps, void *work, size_t 
  * for every node, the moments of eqs. (0moment)/(1moment) (velocity implicit
  * through the drag, solved exactly), collision toward eq. (d2q9eq) with the
  * sources of eqs. (pi) and (Fi), and streaming with the boundary rule, fused
- * in one pass per step, or per two or three steps where params.steps_per_pass
- * allows it (the intermediate states then never leave the GPU's registers).
+ * in one pass per step, or per two, three or four steps where
+ * params.steps_per_pass allows it (the intermediate states then never leave the
+ * GPU's registers).
  * Asynchronous. */
 int lbm_vans_step(lbm_vans_handle *h, int64_t nsteps);
 
@@ -333,14 +334,19 @@ typedef struct lbm_vans_batch_config {
                              launches.  lbm_vans_batch_step replays the graph for whole
                              chunks from state n >= 1 and launches the rest one by one */
     int32_t steps_per_pass;/* most steps one launch takes, as lbm_vans_params.
-                             steps_per_pass (0 = automatic: 3; 1, 2, 3): with
-                             LBM_F32 / LBM_F16_SHIFTED storage the multi-step pass
-                             over every member; vec and grid apply to single steps */
-    int32_t pass_rows;    /* rows per chunk of the batched three-step pass, as
-                             lbm_vans_params.pass_rows (0 = automatic: with FP32
-                             storage 28 when the whole batch has four times as many
-                             waves of 28 rows as the GPU holds of the batched kernel,
-                             else 24); the members' own pass_rows are not used      */
+                             steps_per_pass (1, 2, 3, or 4 with LBM_F32_SHIFTED
+                             storage and members that take the four-step pass; 0 =
+                             automatic: 4 with FP32 storage, pass_rows = 0 and at
+                             least as many waves of the batched four-step pass as
+                             the GPU holds of it, else 3): with LBM_F32 /
+                             LBM_F16_SHIFTED storage the multi-step pass over every
+                             member; vec and grid apply to single steps           */
+    int32_t pass_rows;    /* rows per chunk of the batched three-step pass, 24 or 28
+                             with FP32 storage (0 = automatic: 28 when the whole
+                             batch has four times as many waves of 28 rows as the
+                             GPU holds of the batched kernel, else 24; the batched
+                             four-step pass takes 24); the members' own pass_rows
+                             are not used                                          */
     double us_per_step;   /* lbm_vans_batch_tune: measured microseconds per step       */
 } lbm_vans_batch_config;
 
@@ -352,7 +358,7 @@ size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembe
  * kept alive until lbm_vans_batch_destroy().  stream: hipStream_t of the
  * batched work (NULL = null stream); graphs are captured on a private stream
  * and replayed on it.  Default configuration: widest vec, one workgroup per
- * tile, 24-step graphs, three steps per launch where the storage allows it.
+ * tile, 24-step graphs, automatic steps per launch.
  * Synchronises the stream (table upload). */
 int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, void *work,
                           size_t work_bytes, void *stream, lbm_vans_batch **out);
@@ -366,9 +372,9 @@ int lbm_vans_batch_get_config(const lbm_vans_batch *b, lbm_vans_batch_config *cf
  * first) with one workgroup per tile and with persistent grids of 1, 2, 4 and
  * 8 workgroups per compute unit, each timed with HIP events over reps sweeps
  * of the current state (read only: the state does not change), and, with
- * LBM_F32 / LBM_F16_SHIFTED storage, the two- and three-step passes (their time
- * per launch divided by 2 and 3; steps_per_pass 2 and 3 in those trials, 1 in
- * the others).  The fastest becomes the configuration (graph_steps kept; the
+ * LBM_F32 / LBM_F16_SHIFTED storage, the two- and three-step passes and, with
+ * FP32 storage, the four-step pass (their time per launch divided by 2, 3 and
+ * 4; steps_per_pass 2, 3 and 4 in those trials, 1 in the others).  The fastest becomes the configuration (graph_steps kept; the
  * best single-step vec and grid kept when a multi-step pass wins) and is
  * written to *best (may be NULL); trials
  * (may be NULL if max_trials is 0) receive up to max_trials of the timed
@@ -382,8 +388,8 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
 int lbm_vans_batch_step(lbm_vans_batch *b, int64_t nsteps);
 
 /* Launch plan of lbm_vans_batch_step under the current configuration: the most
- * steps one launch takes and the rows per chunk of the batched three-step pass
- * (0 without a multi-step pass), as lbm_vans_pass_plan.  Host only. */
+ * steps one launch takes and the rows per chunk of its multi-step pass (0
+ * without one), as lbm_vans_pass_plan.  Host only. */
 int lbm_vans_batch_pass_plan(const lbm_vans_batch *b, int32_t *steps_per_pass,
                              int32_t *pass_rows);
 

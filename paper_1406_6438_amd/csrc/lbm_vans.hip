@@ -2196,9 +2196,10 @@ struct Member {
     int vec;                // nodes per lane of this member's sweep
     int tile0;              // first position in the sweep tile list of its width
     int tile0_adj;          // first position in the adjoint tile list
-    int tb_strips[2];       // strips of the two- and three-step passes
-    int tw0[3];             // first position in the wave lists of the two-step pass and
-                            // of the three-step pass in short and in tall chunks
+    int tb_strips[3];       // strips of the two-, three- and four-step passes
+    int tw0[4];             // first position in the wave lists of the two-step pass, of
+                            // the three-step pass in short and in tall chunks, and of
+                            // the four-step pass
 };
 
 template <typename R>
@@ -2306,6 +2307,16 @@ __attribute__((amdgpu_waves_per_eu(1, tb3_max_waves<S, BX, WY>()))) void k_batch
 {
     batch_multi_wave<S, R, BX, WY, 3, NR, NR == tb_rows<S, 3>() ? 1 : 2>(M, wmap, nwaves, src,
                                                                          dst, res_a);
+}
+
+// Four steps of every member (FP32 storage; wave list 3).
+template <typename S, typename R, int BX, bool WY>
+__global__ __launch_bounds__(NTHREADS)
+__attribute__((amdgpu_waves_per_eu(1, tb3_max_waves<S, BX, WY>()))) void k_batch_tb4(
+    const Member<R> *__restrict__ M, const int *__restrict__ wmap, int nwaves, int src, int dst,
+    int res_a)
+{
+    batch_multi_wave<S, R, BX, WY, 4, tb_rows<float, 4>(), 3>(M, wmap, nwaves, src, dst, res_a);
 }
 
 // One reverse step of every member: adjoint slot a_next (of the state n + 1)
@@ -2730,16 +2741,20 @@ int tb3_resident(int storage, int bx, bool wy, int rows, bool batch, long long *
     return LBM_VANS_OK;
 }
 
-// The same for the four-step kernel (FP32, lone lattices).
-int tb4_resident(int bx, bool wy, long long *out)
+// The same for the four-step kernel (FP32; lone, or batched).
+int tb4_resident(int bx, bool wy, bool batch, long long *out)
 {
     int nb = 0, dev = 0, ncu = 0;
     hipError_t e = hipSuccess;
     with_bxwy(bx, wy, [&](auto bxc, auto wyc) {
         constexpr int BXV = decltype(bxc)::value;
         constexpr bool WYV = decltype(wyc)::value;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, k_sweep_tb4<float, float, BXV, WYV, tb_rows<float, 4>()>, NTHREADS, 0);
+        if (batch)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tb4<float, float, BXV, WYV>,
+                                                             NTHREADS, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, k_sweep_tb4<float, float, BXV, WYV, tb_rows<float, 4>()>, NTHREADS, 0);
     });
     HIP_TRY(e);
     HIP_TRY(hipGetDevice(&dev));
@@ -2820,7 +2835,7 @@ int choose_passes(lbm_vans_handle *h)
         h->auto_pass = 2;
     if (!f16 && p->pass_rows == 0 && multi_rows_ok(p->Ly, wy, 4, tb_rows<float, 4>())) {
         long long res4 = 0;
-        rc = tb4_resident(bx, wy, &res4);
+        rc = tb4_resident(bx, wy, false, &res4);
         if (rc) return rc;
         if (waves_of(p->Lx, p->Ly, 4, tb_rows<float, 4>()) >= QUAD_FILL * res4) h->auto_pass = 4;
     }
@@ -3544,13 +3559,17 @@ struct lbm_vans_batch {
     size_t desc_bytes = 0;          // bytes of one device descriptor
     std::vector<char> desc;         // host image of the descriptors
     std::vector<int> tmap, tmap_adj;  // tile lists of the sweep and of the adjoint
-    std::vector<int> wmap[3];         // wave lists of the two-step pass and of the three-step
-                                      // pass in short and in tall chunks (FP32 only)
+    std::vector<int> wmap[4];         // wave lists of the two-step pass, of the three-step
+                                      // pass in short and in tall chunks (FP32 only) and of
+                                      // the four-step pass (FP32 only)
     void *d_desc = nullptr;
-    int *d_tmap = nullptr, *d_tmap_adj = nullptr, *d_wmap[3] = {nullptr, nullptr, nullptr};
-    int ntiles = 0, ntiles_adj = 0, nwaves[3] = {0, 0, 0};
+    int *d_tmap = nullptr, *d_tmap_adj = nullptr,
+        *d_wmap[4] = {nullptr, nullptr, nullptr, nullptr};
+    int ntiles = 0, ntiles_adj = 0, nwaves[4] = {0, 0, 0, 0};
     bool multi_ok = true;           // every member fits the multi-step passes' addressing
+    bool multi4_ok = false;         // ... and the four-step pass (FP32, rows)
     long long tall_resident = 0;    // waves of the tall batched three-step kernel the chip holds
+    long long quad_resident = 0;    // waves of the batched four-step kernel the chip holds
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // chunk of cfg.graph_steps steps from slot 0 / 1
 };
 
@@ -3561,19 +3580,20 @@ size_t batch_table_bytes(int storage, size_t nmembers, size_t ntiles_adj, const 
     const size_t d = storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
     return align256(nmembers * d) + 2 * align256(ntiles_adj * sizeof(int)) +
            align256(nwaves[0] * sizeof(int)) + align256(nwaves[1] * sizeof(int)) +
-           align256(nwaves[2] * sizeof(int));
+           align256(nwaves[2] * sizeof(int)) + align256(nwaves[3] * sizeof(int));
 }
 
 // Waves of one member in wave list q: the two-step pass (0), the three-step pass
-// in short (1) and in tall chunks (2; FP32 storage only); none in FP64, which has
-// no such pass.
+// in short (1) and in tall chunks (2; FP32 storage only), the four-step pass (3;
+// FP32 storage only); none in FP64, which has no such pass.
 size_t batch_waves(const lbm_vans_params *p, int q)
 {
     if (p->storage == LBM_F64) return 0;
     const bool f16 = p->storage == LBM_F16_SHIFTED;
     if (q == 0) return waves_of(p->Lx, p->Ly, 2, f16 ? tb_rows<_Float16, 2>() : tb_rows<float, 2>());
     if (q == 1) return waves_of(p->Lx, p->Ly, 3, f16 ? tb_rows<_Float16, 3>() : tb_rows<float, 3>());
-    return f16 ? 0 : waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32);
+    if (q == 2) return f16 ? 0 : waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32);
+    return f16 ? 0 : waves_of(p->Lx, p->Ly, 4, tb_rows<float, 4>());
 }
 
 // The batched three-step pass runs in tall chunks (FP32 storage): as configured, or
@@ -3628,9 +3648,10 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
             d.tile0_adj = static_cast<int>(b->tmap_adj.size());
             b->tmap.insert(b->tmap.end(), d.gs.ntiles, static_cast<int>(k));
             b->tmap_adj.insert(b->tmap_adj.end(), d.g.ntiles, static_cast<int>(k));
-            for (int q = 0; q < 3; q++) {
-                const int cols = q ? tb_cols<3>() : tb_cols<2>();
-                if (q < 2) d.tb_strips[q] = (h->p.Lx + cols - 1) / cols;
+            for (int q = 0; q < 4; q++) {
+                const int ns = q == 0 ? 2 : (q < 3 ? 3 : 4);
+                const int cols = TX - 2 * (ns - 1);
+                d.tb_strips[ns - 2] = (h->p.Lx + cols - 1) / cols;
                 d.tw0[q] = static_cast<int>(b->wmap[q].size());
                 b->wmap[q].insert(b->wmap[q].end(), batch_waves(&h->p, q), static_cast<int>(k));
             }
@@ -3658,14 +3679,14 @@ int batch_upload(lbm_vans_batch *b, int vec, char *gw, int64_t nsteps, int32_t c
     if (rc) return rc;
     b->ntiles = static_cast<int>(b->tmap.size());
     b->ntiles_adj = static_cast<int>(b->tmap_adj.size());
-    for (int q = 0; q < 3; q++) b->nwaves[q] = static_cast<int>(b->wmap[q].size());
+    for (int q = 0; q < 4; q++) b->nwaves[q] = static_cast<int>(b->wmap[q].size());
     HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size(), hipMemcpyHostToDevice,
                            b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap, b->tmap.data(), b->tmap.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tmap_adj, b->tmap_adj.data(), b->tmap_adj.size() * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
-    for (int q = 0; q < 3; q++)
+    for (int q = 0; q < 4; q++)
         if (!b->wmap[q].empty())
             HIP_TRY(hipMemcpyAsync(b->d_wmap[q], b->wmap[q].data(),
                                    b->wmap[q].size() * sizeof(int), hipMemcpyHostToDevice,
@@ -3710,7 +3731,7 @@ int batch_sweep(lbm_vans_batch *b, hipStream_t st, int src, int dst, int reservo
     });
 }
 
-// ns (2 or 3) batched steps on stream st: every member from state slot src to
+// ns (2, 3 or 4) batched steps on stream st: every member from state slot src to
 // dst in one launch of the multi-step pass; res_a: the first step starts from
 // n >= 1.
 int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, int ns)
@@ -3723,8 +3744,11 @@ int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, 
         } else {
             if (!b->multi_ok)
                 return fail(LBM_VANS_EINVAL, "a member is too large for the multi-step pass");
+            if (ns == 4 && !b->multi4_ok)
+                return fail(LBM_VANS_EINVAL, "the four-step pass needs FP32 storage and members "
+                            "of at least 32 rows with periodic y");
             const bool tall = ns == 3 && batch_tall(b);
-            const int q = ns == 3 ? (tall ? 2 : 1) : 0;
+            const int q = ns == 4 ? 3 : ns == 3 ? (tall ? 2 : 1) : 0;
             const int n = b->nwaves[q];
             const int grid = (n + NW - 1) / NW;
             const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
@@ -3739,7 +3763,9 @@ int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, 
                 if (ns == 2) {
                     run(k_batch_tb2<S, R, BXV, WYV>);
                 } else if constexpr (std::is_same_v<S, float>) {
-                    if (tall)
+                    if (ns == 4)
+                        run(k_batch_tb4<S, R, BXV, WYV>);
+                    else if (tall)
                         run(k_batch_tb3<S, R, BXV, WYV, LBM_VANS_TB3_TALL32>);
                     else
                         run(k_batch_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
@@ -3747,16 +3773,23 @@ int batch_multi(lbm_vans_batch *b, hipStream_t st, int src, int dst, int res_a, 
                     run(k_batch_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
                 }
             });
-            return check_launch(ns == 3 ? "k_batch_tb3" : "k_batch_tb2");
+            return check_launch(ns == 4 ? "k_batch_tb4" : ns == 3 ? "k_batch_tb3" : "k_batch_tb2");
         }
     });
 }
 
-// Most steps one batched launch may take (as max_pass for a lone problem).
+// Most steps one batched launch may take (as max_pass for a lone problem):
+// automatically four (FP32, with at least as many waves as the chip holds of the
+// batched four-step kernel), else three.
 int batch_max_pass(const lbm_vans_batch *b)
 {
     if (b->storage == LBM_F64 || !b->multi_ok || b->nwaves[0] == 0) return 1;
-    return b->cfg.steps_per_pass == 0 ? 3 : b->cfg.steps_per_pass;
+    int m = b->cfg.steps_per_pass;
+    if (m == 0)
+        m = b->multi4_ok && b->cfg.pass_rows == 0 && b->nwaves[3] >= QUAD_FILL * b->quad_resident
+                ? 4
+                : 3;
+    return m == 4 && !b->multi4_ok ? 3 : m;
 }
 
 // One batched launch of m steps (the one-step sweep for m = 1).
@@ -3831,9 +3864,11 @@ int check_config(const lbm_vans_batch *b, const lbm_vans_batch_config *c)
     if (c->graph_steps < 0 || c->graph_steps % 2)
         return fail(LBM_VANS_EINVAL, "graph_steps = %d: 0 or a positive even number",
                     c->graph_steps);
-    if (c->steps_per_pass < 0 || c->steps_per_pass > 3)
-        return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2 or 3",
+    if (c->steps_per_pass < 0 || c->steps_per_pass > 4)
+        return fail(LBM_VANS_EINVAL, "steps_per_pass = %d: 0 (automatic), 1, 2, 3 or 4",
                     c->steps_per_pass);
+    if (c->steps_per_pass == 4 && b->storage != LBM_F32_SHIFTED)
+        return fail(LBM_VANS_EINVAL, "steps_per_pass = 4 needs LBM_F32_SHIFTED storage");
     if (c->pass_rows == LBM_VANS_TB3_SHORT32)
         return fail(LBM_VANS_EINVAL, "pass_rows = %d: batches take %d or %d (or 0)",
                     c->pass_rows, tb_rows<float, 3>(), LBM_VANS_TB3_TALL32);
@@ -3869,11 +3904,11 @@ extern "C" {
 size_t lbm_vans_batch_work_bytes(lbm_vans_handle *const *members, int32_t nmembers)
 {
     if (!members || nmembers < 1) return 0;
-    size_t tiles = 0, waves[3] = {0, 0, 0};
+    size_t tiles = 0, waves[4] = {0, 0, 0, 0};
     for (int32_t k = 0; k < nmembers; k++) {
         if (!members[k]) return 0;
         tiles += static_cast<size_t>(members[k]->g.ntiles);
-        for (int q = 0; q < 3; q++) waves[q] += batch_waves(&members[k]->p, q);
+        for (int q = 0; q < 4; q++) waves[q] += batch_waves(&members[k]->p, q);
     }
     return batch_table_bytes(members[0]->p.storage, nmembers, tiles, waves);
 }
@@ -3887,7 +3922,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     if (!members || nmembers < 1) return fail(LBM_VANS_EINVAL, "no members");
     const lbm_vans_handle *h0 = members[0];
     if (!h0) return fail(LBM_VANS_EINVAL, "member 0 is NULL");
-    size_t tiles = 0, waves[3] = {0, 0, 0};
+    size_t tiles = 0, waves[4] = {0, 0, 0, 0};
     for (int32_t k = 0; k < nmembers; k++) {
         const lbm_vans_handle *h = members[k];
         if (!h) return fail(LBM_VANS_EINVAL, "member %d is NULL", k);
@@ -3903,11 +3938,11 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
             return fail(LBM_VANS_EINVAL, "member %d is at step %lld, member 0 at %lld", k,
                         (long long)h->n, (long long)h0->n);
         tiles += static_cast<size_t>(h->g.ntiles);
-        for (int q = 0; q < 3; q++) waves[q] += batch_waves(&h->p, q);
+        for (int q = 0; q < 4; q++) waves[q] += batch_waves(&h->p, q);
     }
     if (tiles > static_cast<size_t>(INT32_MAX))
         return fail(LBM_VANS_EINVAL, "%zu tiles: too many for one launch", tiles);
-    const size_t wmax = std::max({waves[0], waves[1], waves[2]});
+    const size_t wmax = std::max({waves[0], waves[1], waves[2], waves[3]});
     if (wmax > static_cast<size_t>(INT32_MAX - NW))
         return fail(LBM_VANS_EINVAL, "%zu waves: too many for one launch", wmax);
     if (!work || reinterpret_cast<uintptr_t>(work) % 256)
@@ -3932,6 +3967,10 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
                                     LBM_VANS_TB3_TALL32) &&
                       multi_rows_ok(members[k]->p.Ly, members[k]->g.wall_y, 2,
                                     tb2_rows_of(members[k]->p.storage));
+    b->multi4_ok = b->multi_ok && b->storage == LBM_F32_SHIFTED;
+    for (int32_t k = 0; k < nmembers; k++)
+        b->multi4_ok = b->multi4_ok && multi_rows_ok(members[k]->p.Ly, members[k]->g.wall_y, 4,
+                                                     tb_rows<float, 4>());
     const size_t dsz = b->storage == LBM_F64 ? sizeof(Member<double>) : sizeof(Member<float>);
     char *w = static_cast<char *>(work);
     b->d_desc = w;
@@ -3939,7 +3978,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
     b->d_tmap_adj = reinterpret_cast<int *>(w + align256(nmembers * dsz) +
                                             align256(tiles * sizeof(int)));
     size_t off = align256(nmembers * dsz) + 2 * align256(tiles * sizeof(int));
-    for (int q = 0; q < 3; q++) {
+    for (int q = 0; q < 4; q++) {
         b->d_wmap[q] = reinterpret_cast<int *>(w + off);
         off += align256(waves[q] * sizeof(int));
     }
@@ -3956,6 +3995,7 @@ int lbm_vans_batch_create(lbm_vans_handle *const *members, int32_t nmembers, voi
                                    hipGetErrorString(e));
     if (!rc && b->storage == LBM_F32_SHIFTED && b->multi_ok)
         rc = tb3_resident(b->storage, b->bx, b->wy, LBM_VANS_TB3_TALL32, true, &b->tall_resident);
+    if (!rc && b->multi4_ok) rc = tb4_resident(b->bx, b->wy, true, &b->quad_resident);
     if (!rc) rc = batch_upload(b, b->cfg.vec, nullptr, 0, 1);
     if (rc) {
         lbm_vans_batch_destroy(b);
@@ -3981,10 +4021,12 @@ int lbm_vans_batch_pass_plan(const lbm_vans_batch *b, int32_t *steps_per_pass,
 {
     if (!b) return fail(LBM_VANS_EINVAL, "batch is NULL");
     const bool multi = b->storage != LBM_F64 && b->multi_ok && b->nwaves[0] > 0;
-    if (steps_per_pass) *steps_per_pass = batch_max_pass(b);
+    const int m = batch_max_pass(b);
+    if (steps_per_pass) *steps_per_pass = m;
     if (pass_rows)
         *pass_rows = !multi ? 0
                      : b->storage == LBM_F16_SHIFTED ? tb_rows<_Float16, 3>()
+                     : m == 4 ? tb_rows<float, 4>()
                      : batch_tall(b) ? LBM_VANS_TB3_TALL32
                                      : tb_rows<float, 3>();
     return LBM_VANS_OK;
@@ -4044,7 +4086,9 @@ int lbm_vans_batch_tune(lbm_vans_batch *b, int32_t reps, lbm_vans_batch_config *
     // the multi-step passes (independent of vec and grid; the single-step shape
     // found so far is kept for the steps they leave over), timed per step
     const lbm_vans_batch_config single = top;
-    for (int ns = 2; ns <= 3 && b->storage != LBM_F64 && b->nwaves[0] > 0 && b->multi_ok; ns++) {
+    const int ns_max = b->multi4_ok ? 4 : 3;
+    for (int ns = 2; ns <= ns_max && b->storage != LBM_F64 && b->nwaves[0] > 0 && b->multi_ok;
+         ns++) {
         rc = batch_multi(b, b->stream, src, dst, res, ns);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(b->ev[0], b->stream));

@@ -474,9 +474,9 @@ class Batch:
 
     def configure(self, vec: int, grid: int = 0, graph_steps: int = 24, steps_per_pass: int = 0,
                   pass_rows: int = 0):
-        """steps_per_pass: most steps per launch (0 = automatic: 3 with FP32 / FP16
-        storage; 1, 2 or 3); pass_rows: rows per chunk of the three-step pass (0 =
-        automatic; 24 or 28 with FP32 storage)."""
+        """steps_per_pass: most steps per launch (0 = automatic: 4 or 3 with FP32
+        storage, 3 with FP16; 1, 2, 3, or 4 with FP32); pass_rows: rows per chunk of the
+        three-step pass (0 = automatic; 24 or 28 with FP32 storage)."""
         lbm_vans_batch_configure(self.b, vec, grid, graph_steps, steps_per_pass, pass_rows)
 
     @property

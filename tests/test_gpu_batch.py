@@ -167,6 +167,33 @@ def test_batch_three_step_chunk_heights(bc, rows):
         assert np.abs(f - fl).max() <= bound
 
 
+@pytest.mark.parametrize("bc", ["periodic", "walls", "open_walls"])
+def test_batch_four_step_pass(bc):
+    """The batched four-step pass (FP32) on members tall enough for it and for several
+    chunks (the last one short): against the oracle and against each member run alone
+    with four steps per pass, 13 steps (4+4+4+1)."""
+    from paper_1406_6438_amd import lbm
+    members = _member_specs("f32", bc, sizes=[(96, 61), (130, 75), (67, 40), (5, 40)])
+    nsteps = 13
+    say(f"[batch four steps {bc}]")
+    sv = _solvers(members)
+    b = lbm.Batch(sv)
+    b.configure(4, 0, 0, 4, 0)
+    assert b.pass_plan == (4, 24)
+    b.step(nsteps)
+    fb = _states(sv)
+    b.close()
+    _close(sv)
+    for (spec, eps), f in zip(members, fb):
+        mo, fo = oracle_run(spec, eps, nsteps)
+        bound = _bound(spec, eps, fo, nsteps)
+        assert np.abs(f - fo).max() <= bound
+        _, fl = gpu_run(dataclasses.replace(spec, steps_per_pass=4), eps, nsteps)
+        say(f"  {spec.Lx}x{spec.Ly}: max |f - f_oracle| {np.abs(f - fo).max():.3e} (bound "
+            f"{bound:.3e}); lone run same bits {np.array_equal(f, fl)}")
+        assert np.abs(f - fl).max() <= bound
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
 def test_every_launch_shape(storage):
     """vec 4/2/1, one workgroup per tile or persistent grids, with and without
@@ -244,7 +271,7 @@ def test_autotune_keeps_the_state_and_reports_trials():
     best, trials = b.tune(reps=3)
     say(f"[batch tune] best {best}; {len(trials)} trials")
     assert trials and best["us_per_step"] == min(t["us_per_step"] for t in trials)
-    assert sorted({t["steps_per_pass"] for t in trials}) == [1, 2, 3]
+    assert sorted({t["steps_per_pass"] for t in trials}) == [1, 2, 3, 4]   # FP32: four too
     assert all(b.config[k] == best[k] for k in ("vec", "grid", "steps_per_pass"))
     for x, y in zip(_states(sv), before):
         assert np.array_equal(x, y)
@@ -274,8 +301,8 @@ def test_batch_rejects_mismatched_members_and_out_of_step_members():
     with pytest.raises(lbm.LbmVansError):
         lbm.Batch([diag, c])
     b = lbm.Batch([a, c])
-    for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16), (4, 0, 16, 4),
-                (4, 0, 16, -1), (4, 0, 16, 3, 16), (4, 0, 16, 3, -28)):
+    for cfg in ((3, 0, 16), (4, 12, 16), (4, 0, 3), (8, 0, 16), (4, 0, 16, 5),
+                (4, 0, 16, -1), (4, 0, 16, 3, 16), (4, 0, 16, 3, -28), (4, 0, 16, 3, 12)):
         with pytest.raises(lbm.LbmVansError):
             b.configure(*cfg)
     a.step(1)                       # a member stepped on its own

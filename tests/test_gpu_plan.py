@@ -91,6 +91,8 @@ def test_batch_plan():
     assert b.pass_plan == (3, 28)
     b.configure(4, 0, 24, 2, 0)
     assert b.pass_plan == (2, 24)
+    b.configure(4, 0, 24, 4, 0)
+    assert b.pass_plan == (4, 24)
     with pytest.raises(lbm.LbmVansError):      # the 12-row height is for lone lattices
         b.configure(4, 0, 24, 3, 12)
     b.close()

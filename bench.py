@@ -46,7 +46,7 @@ PROFILE_VALU = {"box4096_f32": os.path.join(ROOT, "profiles", "sweep_valu_box409
                 "box8192_f16": os.path.join(ROOT, "profiles", "sweep_valu_box8192_f16.md"),
                 "ensemble64_f32": os.path.join(ROOT, "profiles", "batch_valu_ensemble64_f32.md")}
 MULTI_KERNEL = {1: "k_sweep_vec", 2: "k_sweep_tb2", 3: "k_sweep_tb3", 4: "k_sweep_tb4"}
-BATCH_KERNEL = {1: "k_batch_sweep", 2: "k_batch_tb2", 3: "k_batch_tb3"}
+BATCH_KERNEL = {1: "k_batch_sweep", 2: "k_batch_tb2", 3: "k_batch_tb3", 4: "k_batch_tb4"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_6438_amd", "csrc", "lbm_vans.hip")
 
 

@@ -29,7 +29,8 @@ def main(path):
            dict(storage=7), dict(bc_x=4), dict(bc_y=2), dict(drag=3), dict(bc_x=2, Lx=1),
            dict(bc_x=2, rho_in=0.0), dict(bc_x=3, rho_out=0.0), dict(bc_x=3, u_in=math.inf),
            dict(rho0=0.0), dict(G=(math.inf, 0.0)), dict(Lx=65536, Ly=65536),
-           dict(u_wall=(0.01, 0.0)), dict(sweep_vec=3), dict(steps_per_pass=4),
+           dict(u_wall=(0.01, 0.0)), dict(sweep_vec=3), dict(steps_per_pass=5),
+           dict(steps_per_pass=4, storage=lbm.F16_SHIFTED), dict(pass_rows=12, storage=lbm.F16_SHIFTED),
            dict(pass_rows=16), dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30)]
     for b in bad:
         p = lbm.Params(**dict(base, **b))

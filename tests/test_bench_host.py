@@ -40,14 +40,29 @@ def test_measured_traffic_matches_kernel_and_source_hash(tmp_path, monkeypatch):
     assert bench.measured_traffic("missing", "k_sweep_tb3") is None
 
 
+# the kernel bench.py reports for each workload: the FP32 box takes four steps per
+# launch, the FP16 box three, the ensemble the batched three-step pass (its tuner may
+# also pick the four-step one)
+REPORTED = {"box4096_f32": "k_sweep_tb4", "box8192_f16": "k_sweep_tb3",
+            "ensemble64_f32": "k_batch_tb3"}
+
+
+def _has_block(txt, kernel):
+    n = len(kernel)
+    return f"kernel: {kernel}" in txt or f"kernel: _ZN12_GLOBAL__N_1{n}{kernel}" in txt
+
+
 def test_committed_summaries_hold_a_block_for_their_kernel():
     """Each committed summary parses and has a block for the kernel bench.py reports
     (its source hash may be older than the working tree's while a kernel is changed)."""
     for workload, path in bench.PROFILE_TRAFFIC.items():
         txt = open(path).read()
-        kernel = "k_batch_tb3" if workload.startswith("ensemble") else "k_sweep_tb3"
-        assert f"kernel: {kernel}" in txt or f"kernel: _ZN12_GLOBAL__N_111{kernel}" in txt, path
+        assert _has_block(txt, REPORTED[workload]), path
         assert "kernel_source_sha256_16:" in txt and "hbm_bytes_per_launch:" in txt, path
+    for workload, path in bench.PROFILE_VALU.items():
+        txt = open(path).read()
+        assert _has_block(txt, REPORTED[workload]), path
+        assert "valu_active_quad_cycles_per_launch:" in txt, path
 
 
 def test_more_than_one_gpu_is_refused():

@@ -248,10 +248,11 @@ def test_full_size_gradient_against_oracle_central_differences(storage):
     * FP64: |g - fd| <= 1e-6 |fd| + 2 noise;
     * FP32 storage (states stored and collided in FP32, reverse steps in FP64): the
       gradient carries the FP32 rounding of the recomputed trajectory, an absolute
-      floor of about 1e-9 over the channel's interior (99th percentile 3.3e-9 against
-      the FP64 gradient of the same workload; 1.3e-7 of the largest |dJ/deps|, which
-      sits at the inlet): |g - fd| <= 1e-4 |fd| + 2 noise + 2e-8, and the relative L2
-      error over the 32 nodes <= 1e-4."""
+      floor over the channel's interior (99th percentile 3.3e-9 against the FP64
+      gradient of the same workload; at most 1.6e-9 at these 32 nodes, measured):
+      |g - fd| <= 1e-4 |fd| + 2 noise + 5e-9, and the relative L2 error over the 32
+      nodes <= 1e-4 (measured 2.0e-5).  Nodes whose |dJ/deps| is near 1e-6 are held
+      to that floor rather than to 1e-4 of themselves."""
     gold = _golden()
     w = W.ADJOINT_CHANNEL
     U = W.ADJOINT_U_IN
@@ -277,5 +278,5 @@ def test_full_size_gradient_against_oracle_central_differences(storage):
         assert np.all(err <= 1e-6 * np.abs(fd) + 2 * noise)
     else:
         assert abs(J - gold["J"]) <= 1e-5 * abs(gold["J"])
-        assert np.all(err <= 1e-4 * np.abs(fd) + 2 * noise + 2e-8)
+        assert np.all(err <= 1e-4 * np.abs(fd) + 2 * noise + 5e-9)
         assert rel_l2(ad, fd) <= 1e-4

@@ -257,9 +257,10 @@ int lbm_vans_objective(lbm_vans_handle *h, int32_t objective, double *J);
  * arguments (0 if invalid): one population buffer per checkpoint
  * (ceil(nsteps / ckpt_every)), ckpt_every buffers for a recomputed segment --
  * two sets of them when there are two or more segments, so that one segment is
- * recomputed while the reverse steps of the next run --, two FP64 adjoint
- * buffers and three FP64 accumulators of the porosity grid (with LBM_F32 /
- * LBM_F16_SHIFTED storage also an FP64 copy of the porosity). */
+ * recomputed while the reverse steps of the next run --, two adjoint buffers
+ * of 9 values per node (FP64 with LBM_F64 storage, FP32 otherwise) and three
+ * FP64 accumulators of the porosity grid (with LBM_F32 / LBM_F16_SHIFTED
+ * storage also an FP64 copy of the porosity). */
 size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int64_t nsteps,
                                 int32_t ckpt_every);
 
@@ -276,9 +277,11 @@ size_t lbm_vans_grad_work_bytes(const lbm_vans_params *p, int32_t objective, int
  * open-boundary reservoirs (and the boundary density / velocity a velocity
  * inlet / pressure outlet carries) and the initial state.  The reverse steps
  * compute in FP64 for every storage: with LBM_F32 / LBM_F16_SHIFTED storage
- * they decode the recomputed FP32 / FP16 states into FP64, keep FP64 adjoints
- * and add every step's sensitivities to FP64 accumulators, so the gradient
- * carries only the rounding of the stored forward states.
+ * they decode the recomputed FP32 / FP16 states into FP64, hand the adjoints
+ * from one step to the next in FP32 (one rounding per value and step) and add
+ * every step's sensitivities to FP64 accumulators; the gradient's error is then
+ * that of the stored forward states (the FP32 adjoints add about 1e-7 of the
+ * gradient's largest value).
  * grad_work: device buffer of lbm_vans_grad_work_bytes() bytes, 256-byte
  * aligned, caller-owned.  dJdeps: device array [Ly][Lx] of doubles.
  * J: host double or NULL.  Synchronises the stream.  Afterwards the state is

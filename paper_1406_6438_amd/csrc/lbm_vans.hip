@@ -120,6 +120,10 @@ int scratch_address(void **out)
 #ifndef LBM_VANS_ROWS
 #define LBM_VANS_ROWS 1
 #endif
+// rows each wave of the reverse step walks (k_adjoint_rows)
+#ifndef LBM_VANS_ADJ_ROWS
+#define LBM_VANS_ADJ_ROWS 4
+#endif
 #ifndef LBM_VANS_NT_LOADS
 #define LBM_VANS_NT_LOADS 1
 #endif
@@ -158,6 +162,7 @@ constexpr int TX = 64;      // nodes per row segment: one wavefront
 constexpr int NW = LBM_VANS_NW;      // wavefronts per block
 constexpr int ROWS = LBM_VANS_ROWS;  // rows per thread of the one-node-per-lane kernels
 constexpr int TY = NW * ROWS;
+constexpr int ADJ_ROWS = LBM_VANS_ADJ_ROWS;
 
 // Rows per thread of the vector sweep for a storage type.
 template <typename S>
@@ -1943,26 +1948,32 @@ __device__ __forceinline__ void adjoint_node(const R d[9], const PorNb<R> &P, co
 // Push of a node's incoming adjoints into the adjoint slots of the state the
 // step started from (the gather run backwards; every slot receives exactly one
 // value, a reservoir link a zero).
-template <typename R>
-__device__ __forceinline__ void push_global(R *__restrict__ lam, const Geo &g, int x, int y,
+template <typename R, typename A>
+__device__ __forceinline__ void push_global(A *__restrict__ lam, const Geo &g, int x, int y,
                                             const Nbr &n, const R nu[9], const bool res[9])
 {
     const int c = y * g.pitch + x;
     const int rm = n.ym * g.pitch, r0 = y * g.pitch, rp = n.yp * g.pitch;
     const long long pl = g.plane;
-    const gptr<R> lg = to_global(lam);
-    gptr<R> L0 = lg, L1 = lg + pl, L2 = lg + 2 * pl, L3 = lg + 3 * pl, L4 = lg + 4 * pl,
+    const gptr<A> lg = to_global(lam);
+    gptr<A> L0 = lg, L1 = lg + pl, L2 = lg + 2 * pl, L3 = lg + 3 * pl, L4 = lg + 4 * pl,
             L5 = lg + 5 * pl, L6 = lg + 6 * pl, L7 = lg + 7 * pl, L8 = lg + 8 * pl;
-    L0[c] = nu[0];
-    *(n.wxm ? L3 + c : L1 + r0 + n.xm) = res[1] ? R(0) : nu[1];
-    *(n.wym ? L4 + c : L2 + rm + x) = nu[2];
-    *(n.wxp ? L1 + c : L3 + r0 + n.xp) = res[3] ? R(0) : nu[3];
-    *(n.wyp ? L2 + c : L4 + rp + x) = nu[4];
-    *((n.wxm || n.wym) ? L7 + c : L5 + rm + n.xm) = res[5] ? R(0) : nu[5];
-    *((n.wxp || n.wym) ? L8 + c : L6 + rm + n.xp) = res[6] ? R(0) : nu[6];
-    *((n.wxp || n.wyp) ? L5 + c : L7 + rp + n.xp) = res[7] ? R(0) : nu[7];
-    *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = res[8] ? R(0) : nu[8];
+    auto v = [&](int i) { return res[i] ? A(0) : static_cast<A>(nu[i]); };
+    L0[c] = static_cast<A>(nu[0]);
+    *(n.wxm ? L3 + c : L1 + r0 + n.xm) = v(1);
+    *(n.wym ? L4 + c : L2 + rm + x) = static_cast<A>(nu[2]);
+    *(n.wxp ? L1 + c : L3 + r0 + n.xp) = v(3);
+    *(n.wyp ? L2 + c : L4 + rp + x) = static_cast<A>(nu[4]);
+    *((n.wxm || n.wym) ? L7 + c : L5 + rm + n.xm) = v(5);
+    *((n.wxp || n.wym) ? L8 + c : L6 + rm + n.xp) = v(6);
+    *((n.wxp || n.wyp) ? L5 + c : L7 + rp + n.xp) = v(7);
+    *((n.wxm || n.wyp) ? L6 + c : L8 + rp + n.xm) = v(8);
 }
+
+// Storage type of the adjoints between reverse steps: FP64 for FP64 storage, FP32
+// for FP32 and FP16 storage (the reverse step computes in FP64 either way).
+template <typename S>
+using AdjT = std::conditional_t<std::is_same_v<S, double>, double, float>;
 
 // One reverse step (SEED = false) or the objective's seed (SEED = true).
 // fin: the stored state n (what the forward sweep of step n gathers from).
@@ -1975,8 +1986,8 @@ __device__ __forceinline__ void push_global(R *__restrict__ lam, const Geo &g, i
 // partials in part) and the adjoint of the state from it.
 template <typename S, typename R, bool SEED>
 __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
-                                             const R *__restrict__ lam_next,
-                                             R *__restrict__ lam, const R *__restrict__ eps,
+                                             const AdjT<S> *__restrict__ lam_next,
+                                             AdjT<S> *__restrict__ lam, const R *__restrict__ eps,
                                              const Geo &g, const Phys<R> &ph,
                                              double *__restrict__ eb, double *__restrict__ gxb,
                                              double *__restrict__ gyb,
@@ -2011,7 +2022,8 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         if constexpr (!SEED) {
             const int c = y * g.pitch + x;
 #pragma unroll
-            for (int i = 0; i < 9; i++) mu[r][i] = load_global(lam_next + i * g.plane + c);
+            for (int i = 0; i < 9; i++)
+                mu[r][i] = static_cast<R>(load_global(lam_next + i * g.plane + c));
         }
         gather<S, R>(d[r], fin, g.plane, g.pitch, x, y, nb[r], ph.inv_scale);
         const int c = y * g.pitch + x;
@@ -2037,7 +2049,7 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         bool res[9];
         adjoint_node<R, SEED>(d[r], P, n, ol, orr, x == g.Lx - 1, ph, mu[r], nu, res, e_b,
                               gx_b, gy_b, acc);
-        push_global<R>(lam, g, x, y, n, nu, res);
+        push_global<R, AdjT<S>>(lam, g, x, y, n, nu, res);
         ebg[c] = ae[r] + static_cast<double>(e_b);
         gxg[c] = ax[r] + static_cast<double>(gx_b);
         gyg[c] = ay[r] + static_cast<double>(gy_b);
@@ -2047,8 +2059,8 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
 
 template <typename S, typename R, bool SEED>
 __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
-                                                      const R *__restrict__ lam_next,
-                                                      R *__restrict__ lam,
+                                                      const AdjT<S> *__restrict__ lam_next,
+                                                      AdjT<S> *__restrict__ lam,
                                                       const R *__restrict__ eps, Geo g,
                                                       Phys<R> ph, double *__restrict__ eb,
                                                       double *__restrict__ gxb,
@@ -2056,6 +2068,98 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
                                                       double *__restrict__ part)
 {
     adjoint_tile<S, R, SEED>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, part, blockIdx.x);
+}
+
+// One reverse step (no seed) with each wave walking K consecutive rows of a
+// 64-column strip, top to bottom.  The loads of row r + 1 (its adjoints, its
+// gather, its accumulators and the porosity row above it) are issued before the
+// arithmetic of row r, so that a row's FP64 arithmetic runs under the memory
+// latency of the next one instead of after it.  A node's porosity window is
+// three rows of three columns in registers, wrapped or mirrored as in the tile,
+// so waves share no LDS and wait at no barrier.  The arithmetic of a node is
+// that of k_adjoint.  A lane past the row end computes on the last column and
+// stores nothing.
+template <typename S, typename R, int K>
+__global__ __launch_bounds__(NTHREADS) void k_adjoint_rows(
+    const S *__restrict__ fin, const AdjT<S> *__restrict__ lam_next, AdjT<S> *__restrict__ lam,
+    const R *__restrict__ eps, Geo g, Phys<R> ph, double *__restrict__ eb,
+    double *__restrict__ gxb, double *__restrict__ gyb, int nstrips, int nchunks)
+{
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
+                                                   threadIdx.x / TX);
+    const int strip = wid % nstrips, chunk = wid / nstrips;
+    if (chunk >= nchunks) return;              // whole waves only; no barrier below
+    const int xr = strip * TX + static_cast<int>(threadIdx.x % TX);
+    const bool act = xr < g.Lx;
+    const int x = act ? xr : g.Lx - 1;
+    const int y0 = chunk * K;
+    const int ny = min(K, g.Ly - y0);          // rows of this chunk inside the lattice
+    const int cm = halo_index(x - 1, g.Lx, g.wall_x), cp = halo_index(x + 1, g.Lx, g.wall_x);
+    const gptr<double> ebg = to_global(eb), gxg = to_global(gxb), gyg = to_global(gyb);
+    // porosity rows y0 - 1 + k (k = 0 .. K + 1), columns x - 1 .. x + 1; a row past
+    // the chunk's last lattice row takes row Ly (its halo image) and goes unused
+    R E[K + 2][3];
+    auto eps_row = [&](int k) __attribute__((always_inline)) {
+        const int yy = halo_index(min(y0 - 1 + k, g.Ly), g.Ly, g.wall_y);
+        const R *row = eps + static_cast<long long>(yy) * g.pitch;
+        E[k][0] = load_global(row + cm);
+        E[k][1] = load_global(row + x);
+        E[k][2] = load_global(row + cp);
+    };
+    R mu[K][9], d[K][9];
+    double ae[K], ax[K], ay[K];
+    Nbr nb[K];
+    auto issue = [&](int r) __attribute__((always_inline)) {
+        const int y = y0 + r;
+        nb[r] = neighbours(x, y, g);
+        const int c = y * g.pitch + x;
+#pragma unroll
+        for (int i = 0; i < 9; i++)
+            mu[r][i] = static_cast<R>(load_global(lam_next + i * g.plane + c));
+        gather<S, R>(d[r], fin, g.plane, g.pitch, x, y, nb[r], ph.inv_scale);
+        ae[r] = ebg[c];
+        ax[r] = gxg[c];
+        ay[r] = gyg[c];
+    };
+    auto compute = [&](int r) __attribute__((always_inline)) {
+        const int y = y0 + r;
+        const Nbr &n = nb[r];
+        const R t[3][3] = {{E[r][0], E[r][1], E[r][2]},
+                           {E[r + 1][0], E[r + 1][1], E[r + 1][2]},
+                           {E[r + 2][0], E[r + 2][1], E[r + 2][2]}};
+        const PorNb<R> P = porosity_nb<R, 3>(t, 1, 1, n.wxm, n.wxp, n.wym, n.wyp);
+        const bool ores = g.open_x && ph.reservoir;
+        const bool ol = ores && x == 0, orr = ores && x == g.Lx - 1;
+        boundary_inflow<R>(d[r], P.e0, ol, orr, n.wym, n.wyp, ph);
+        unshift_incoming<R>(d[r], P, ph.rho0);
+        R nu[9], e_b, gx_b, gy_b;
+        bool res[9];
+        adjoint_node<R, false>(d[r], P, n, ol, orr, x == g.Lx - 1, ph, mu[r], nu, res, e_b,
+                               gx_b, gy_b, nullptr);
+        if (act) {
+            push_global<R, AdjT<S>>(lam, g, x, y, n, nu, res);
+            const int c = y * g.pitch + x;
+            ebg[c] = ae[r] + static_cast<double>(e_b);
+            gxg[c] = ax[r] + static_cast<double>(gx_b);
+            gyg[c] = ay[r] + static_cast<double>(gy_b);
+        }
+    };
+    eps_row(0);
+    eps_row(1);
+    eps_row(2);
+    issue(0);
+    static_while<K>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        if (r >= ny) return false;             // uniform: the last chunk's rows past the end
+        if constexpr (r + 1 < K) {
+            if (r + 1 < ny) {
+                eps_row(r + 3);
+                issue(r + 1);
+            }
+        }
+        compute(r);
+        return true;
+    });
 }
 
 // Initial state: f_i(r, 0) = w_i eps(r) rho0 (1 + 3 e_i.u0 + 9/2 (e_i.u0)^2 -
@@ -2208,10 +2312,10 @@ __device__ __forceinline__ char *state_slot(const Member<R> &d, int slot)
     return slot < 2 ? d.buf[slot] : d.gw + (long long)(slot - 2) * d.gpop;
 }
 
-template <typename R>
-__device__ __forceinline__ double *adj_buf(const Member<R> &d, int a)
+template <typename A, typename R>
+__device__ __forceinline__ A *adj_buf(const Member<R> &d, int a)
 {
-    return reinterpret_cast<double *>(d.gw + (long long)d.nslot * d.gpop + a * d.glam);
+    return reinterpret_cast<A *>(d.gw + (long long)d.nslot * d.gpop + a * d.glam);
 }
 
 template <typename R>
@@ -2335,7 +2439,8 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__r
     Phys<double> ph = d.pha;
     ph.reservoir = reservoir;
     adjoint_tile<S, double, SEED>(reinterpret_cast<const S *>(state_slot(d, src)),
-                                  SEED ? nullptr : adj_buf(d, a_next), adj_buf(d, a), d.eps_a,
+                                  SEED ? nullptr : adj_buf<AdjT<S>>(d, a_next),
+                                  adj_buf<AdjT<S>>(d, a), d.eps_a,
                                   g, ph, acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), d.part,
                                   T - d.tile0_adj);
 }
@@ -3301,9 +3406,11 @@ GradLayout grad_layout(const lbm_vans_params *p, int64_t nsteps, int32_t ckpt_ev
     if (G.nck < 1) G.nck = 1;
     G.seg = ckpt_every;
     G.nset = two_sets && G.nck >= 2 ? 2 : 1;
-    // the reverse steps run in FP64 for every storage: FP64 adjoints and
-    // accumulators, and for FP32 / FP16 storage an FP64 copy of the porosity
-    G.lam = align256((size_t)9 * g.plane * sizeof(double));
+    // the reverse steps run in FP64 for every storage, with FP64 accumulators and,
+    // for FP32 / FP16 storage, an FP64 copy of the porosity; the adjoints between
+    // the steps are stored in FP64 for FP64 storage, else in FP32
+    const size_t adj_bytes = p->storage == LBM_F64 ? sizeof(double) : sizeof(float);
+    G.lam = align256((size_t)9 * g.plane * adj_bytes);
     G.acc = align256((size_t)g.plane * sizeof(double));
     G.eps64 = p->storage != LBM_F64 ? align256((size_t)g.plane * sizeof(double)) : 0;
     G.total = (size_t)G.states() * G.pop + 2 * G.lam + 3 * G.acc + G.eps64;
@@ -3421,8 +3528,8 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
         ph.reservoir = res_on(&h->p, nsteps);
         int a = 0;
         hipLaunchKernelGGL((k_adjoint<S, RA, true>), dim3(h->ntiles), dim3(NTHREADS), 0,
-                           h->stream, (const S *)h->buf[h->cur], (const RA *)nullptr,
-                           (RA *)lam[a], eps_a, g, ph, eb, gxb, gyb, h->part);
+                           h->stream, (const S *)h->buf[h->cur], (const AdjT<S> *)nullptr,
+                           (AdjT<S> *)lam[a], eps_a, g, ph, eb, gxb, gyb, h->part);
         r = check_launch("k_adjoint seed");
         if (r) return r;
         r = launch_finalize(h, h->scratch_rec, h->ntiles, false, static_cast<double>(nsteps));
@@ -3437,6 +3544,11 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
         // so the two share the GPU.
         const int64_t nck = nsteps == 0 ? 0 : (nsteps + K - 1) / K;
         const bool two = G.nset == 2;
+        // reverse steps: one wave per strip of TX columns and chunk of ADJ_ROWS rows
+        const int adj_strips = (g.Lx + TX - 1) / TX;
+        const int adj_chunks = (g.Ly + ADJ_ROWS - 1) / ADJ_ROWS;
+        const unsigned adj_blocks =
+            static_cast<unsigned>(((long long)adj_strips * adj_chunks + NW - 1) / NW);
         hipStream_t rs = two ? h->stream2 : h->stream;
         auto recompute = [&](int64_t c) -> int {
             const int64_t s0 = c * K, s1 = std::min<int64_t>(s0 + K, nsteps);
@@ -3475,18 +3587,19 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
                 const void *state =
                     n == s0 ? (const void *)ckpt(c) : (const void *)seg(set, n - s0);
                 ph.reservoir = res_on(&h->p, n);
-                hipLaunchKernelGGL((k_adjoint<S, RA, false>), dim3(h->ntiles), dim3(NTHREADS), 0,
-                                   h->stream, (const S *)state, (const RA *)lam[a],
-                                   (RA *)lam[1 - a], eps_a, g, ph, eb, gxb, gyb, h->part);
-                r = check_launch("k_adjoint");
+                hipLaunchKernelGGL((k_adjoint_rows<S, RA, ADJ_ROWS>), dim3(adj_blocks),
+                                   dim3(NTHREADS), 0, h->stream, (const S *)state,
+                                   (const AdjT<S> *)lam[a], (AdjT<S> *)lam[1 - a], eps_a, g,
+                                   ph, eb, gxb, gyb, adj_strips, adj_chunks);
+                r = check_launch("k_adjoint_rows");
                 if (r) return r;
                 a = 1 - a;
             }
             if (two) HIP_TRY(hipEventRecord(h->ev_rev[set], h->stream));
         }
         // 4. initial state and the porosity stencil
-        hipLaunchKernelGGL((k_adjoint_init<RA>), dim3(h->ntiles), dim3(NTHREADS), 0, h->stream,
-                           (const RA *)lam[a], g, h->p.rho0, h->p.u0[0], h->p.u0[1],
+        hipLaunchKernelGGL((k_adjoint_init<AdjT<S>>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                           h->stream, (const AdjT<S> *)lam[a], g, h->p.rho0, h->p.u0[0], h->p.u0[1],
                            wall6(&h->p, 0), wall6(&h->p, 1), eb);
         r = check_launch("k_adjoint_init");
         if (r) return r;
@@ -4279,11 +4392,11 @@ int lbm_vans_batch_grad(lbm_vans_batch *b, int32_t objective, int64_t nsteps,
         for (size_t k = 0; k < b->m.size(); k++) {
             lbm_vans_handle *h = b->m[k];
             char *base = gw[k] + G[k].states() * G[k].pop;
-            const double *lam = reinterpret_cast<const double *>(base + a * G[k].lam);
+            const AdjT<S> *lam = reinterpret_cast<const AdjT<S> *>(base + a * G[k].lam);
             double *eb = reinterpret_cast<double *>(base + 2 * G[k].lam);
             double *gxb = eb + G[k].acc / sizeof(double);
             double *gyb = gxb + G[k].acc / sizeof(double);
-            hipLaunchKernelGGL((k_adjoint_init<double>), dim3(h->ntiles), dim3(NTHREADS), 0,
+            hipLaunchKernelGGL((k_adjoint_init<AdjT<S>>), dim3(h->ntiles), dim3(NTHREADS), 0,
                                b->stream, lam, h->g, h->p.rho0, h->p.u0[0], h->p.u0[1],
                                wall6(&h->p, 0), wall6(&h->p, 1), eb);
             r = check_launch("k_adjoint_init");

@@ -82,7 +82,8 @@ def _grad_gpu(spec, eps, nsteps, K):
     return J, g.cpu().numpy(), n
 
 
-@pytest.mark.parametrize("geom", [(24, 12, True), (26, 10, False), (132, 9, True)],
+@pytest.mark.parametrize("geom", [(24, 12, True), (26, 10, False), (132, 9, True),
+                                  (70, 3, True), (64, 6, False), (130, 1, False)],
                          ids=lambda g: "%dx%d_wy%d" % g)
 def test_gradient_fp64_matches_oracle_adjoint(geom):
     Lx, Ly, wy = geom
@@ -149,7 +150,7 @@ def test_gradient_fp32_matches_oracle_adjoint(Lx):
 def test_gradient_fp32_ignores_stale_workspace(nsteps):
     """With the gradient workspace filled with 0xFF bytes (NaN as FP32 and FP64), no
     step count reads a buffer before writing it (the checkpoints, the recomputed
-    segment, the FP64 adjoints, accumulators and porosity copy): the gradient is
+    segment, the adjoints, the FP64 accumulators and porosity copy): the gradient is
     finite and matches the oracle, also for a step count that is a whole number of
     checkpoint intervals (7 and 8 with K = 7) and for none at all."""
     from paper_1406_6438_amd import lbm

@@ -2076,19 +2076,16 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
 // arithmetic of row r, so that a row's FP64 arithmetic runs under the memory
 // latency of the next one instead of after it.  A node's porosity window is
 // three rows of three columns in registers, wrapped or mirrored as in the tile,
-// so waves share no LDS and wait at no barrier.  The arithmetic of a node is
-// that of k_adjoint.  A lane past the row end computes on the last column and
-// stores nothing.
+// so waves share no LDS and wait at no barrier.  The porosity is the forward's
+// own array (FP32 for FP32 / FP16 storage, widened exactly on load).  The
+// arithmetic of a node is that of k_adjoint.  A lane past the row end computes on
+// the last column and stores nothing.
 template <typename S, typename R, int K>
-__global__ __launch_bounds__(NTHREADS) void k_adjoint_rows(
+__device__ __forceinline__ void adjoint_rows_wave(
     const S *__restrict__ fin, const AdjT<S> *__restrict__ lam_next, AdjT<S> *__restrict__ lam,
-    const R *__restrict__ eps, Geo g, Phys<R> ph, double *__restrict__ eb,
-    double *__restrict__ gxb, double *__restrict__ gyb, int nstrips, int nchunks)
+    const AdjT<S> *__restrict__ eps, const Geo &g, const Phys<R> &ph, double *__restrict__ eb,
+    double *__restrict__ gxb, double *__restrict__ gyb, int strip, int chunk)
 {
-    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
-                                                   threadIdx.x / TX);
-    const int strip = wid % nstrips, chunk = wid / nstrips;
-    if (chunk >= nchunks) return;              // whole waves only; no barrier below
     const int xr = strip * TX + static_cast<int>(threadIdx.x % TX);
     const bool act = xr < g.Lx;
     const int x = act ? xr : g.Lx - 1;
@@ -2101,10 +2098,10 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint_rows(
     R E[K + 2][3];
     auto eps_row = [&](int k) __attribute__((always_inline)) {
         const int yy = halo_index(min(y0 - 1 + k, g.Ly), g.Ly, g.wall_y);
-        const R *row = eps + static_cast<long long>(yy) * g.pitch;
-        E[k][0] = load_global(row + cm);
-        E[k][1] = load_global(row + x);
-        E[k][2] = load_global(row + cp);
+        const AdjT<S> *row = eps + static_cast<long long>(yy) * g.pitch;
+        E[k][0] = static_cast<R>(load_global(row + cm));
+        E[k][1] = static_cast<R>(load_global(row + x));
+        E[k][2] = static_cast<R>(load_global(row + cp));
     };
     R mu[K][9], d[K][9];
     double ae[K], ax[K], ay[K];
@@ -2160,6 +2157,19 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint_rows(
         compute(r);
         return true;
     });
+}
+
+template <typename S, typename R, int K>
+__global__ __launch_bounds__(NTHREADS) void k_adjoint_rows(
+    const S *__restrict__ fin, const AdjT<S> *__restrict__ lam_next, AdjT<S> *__restrict__ lam,
+    const AdjT<S> *__restrict__ eps, Geo g, Phys<R> ph, double *__restrict__ eb,
+    double *__restrict__ gxb, double *__restrict__ gyb, int nstrips, int nchunks)
+{
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
+                                                   threadIdx.x / TX);
+    const int strip = wid % nstrips, chunk = wid / nstrips;
+    if (chunk >= nchunks) return;              // whole waves only; no barrier below
+    adjoint_rows_wave<S, R, K>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, strip, chunk);
 }
 
 // Initial state: f_i(r, 0) = w_i eps(r) rho0 (1 + 3 e_i.u0 + 9/2 (e_i.u0)^2 -
@@ -2443,6 +2453,31 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__r
                                   adj_buf<AdjT<S>>(d, a), d.eps_a,
                                   g, ph, acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), d.part,
                                   T - d.tile0_adj);
+}
+
+// One reverse step (no seed) of every member, one wave per entry of the adjoint
+// tile list: a tile of TX columns and TY rows is the strip and chunk one wave of
+// the row-walking reverse step takes.
+template <typename S, typename R>
+__global__ __launch_bounds__(NTHREADS) void k_batch_adjoint_rows(const Member<R> *__restrict__ M,
+                                                                 const int *__restrict__ tmap,
+                                                                 int ntiles, int src,
+                                                                 int a_next, int a,
+                                                                 int reservoir)
+{
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * NW +
+                                                   threadIdx.x / TX);
+    if (wid >= ntiles) return;                 // whole waves only; no barrier below
+    const Member<R> &d = M[tmap[wid]];
+    const Geo g = d.g;
+    Phys<double> ph = d.pha;
+    ph.reservoir = reservoir;
+    const int t = wid - d.tile0_adj;
+    adjoint_rows_wave<S, double, TY>(reinterpret_cast<const S *>(state_slot(d, src)),
+                                     adj_buf<AdjT<S>>(d, a_next), adj_buf<AdjT<S>>(d, a),
+                                     reinterpret_cast<const AdjT<S> *>(d.eps), g, ph,
+                                     acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), t % g.nbx,
+                                     t / g.nbx);
 }
 
 }  // namespace
@@ -3589,8 +3624,9 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
                 ph.reservoir = res_on(&h->p, n);
                 hipLaunchKernelGGL((k_adjoint_rows<S, RA, ADJ_ROWS>), dim3(adj_blocks),
                                    dim3(NTHREADS), 0, h->stream, (const S *)state,
-                                   (const AdjT<S> *)lam[a], (AdjT<S> *)lam[1 - a], eps_a, g,
-                                   ph, eb, gxb, gyb, adj_strips, adj_chunks);
+                                   (const AdjT<S> *)lam[a], (AdjT<S> *)lam[1 - a],
+                                   (const AdjT<S> *)h->eps, g, ph, eb, gxb, gyb, adj_strips,
+                                   adj_chunks);
                 r = check_launch("k_adjoint_rows");
                 if (r) return r;
                 a = 1 - a;
@@ -3930,9 +3966,10 @@ int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int 
                                dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
                                b->ntiles_adj, src, a_next, a, reservoir);
         else
-            hipLaunchKernelGGL((k_batch_adjoint<S, R, false>), dim3(b->ntiles_adj),
-                               dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
-                               b->ntiles_adj, src, a_next, a, reservoir);
+            hipLaunchKernelGGL((k_batch_adjoint_rows<S, R>),
+                               dim3((unsigned)((b->ntiles_adj + NW - 1) / NW)), dim3(NTHREADS),
+                               0, b->stream, M, (const int *)b->d_tmap_adj, b->ntiles_adj, src,
+                               a_next, a, reservoir);
         return check_launch("k_batch_adjoint");
     });
 }

@@ -383,10 +383,10 @@ def adjoint_leg(lbm, torch, no_accuracy: bool):
     m_grad = cells * w.steps / t_grad / 1e6
     m_fwd = cells * w.steps / t_fwd / 1e6
     # algorithmic bytes per node-step: forward with checkpoints (76) + recompute (76)
-    # + the FP64 reverse step (gather of the FP32 state 36, FP64 porosity 8, FP32
+    # + the FP64 reverse step (gather of the FP32 state 36, FP32 porosity 4, FP32
     # adjoints in 36 and out 36, three FP64 accumulators read and written 48) + the
     # checkpoint copy (read and write of 36 B every K steps)
-    bps = 76 + 76 + 36 + 8 + 36 + 36 + 48 + 72 / K
+    bps = 76 + 76 + 36 + 4 + 36 + 36 + 48 + 72 / K
     out = {"workload": w.name, "steps": w.steps, "ckpt_every": K, "J": J,
            "value": round(m_grad, 2), "unit": "MLUPS (forward node-steps per second of the "
                                                   "whole gradient computation)",

@@ -243,12 +243,18 @@ __device__ __forceinline__ S load_raw(const S *p)
 }
 
 template <typename S, typename R>
-__device__ __forceinline__ R load_pop(const S *p, R inv_scale)
+__device__ __forceinline__ R decode_pop(S v, R inv_scale)
 {
     if constexpr (std::is_same_v<S, _Float16>)
-        return static_cast<R>(load_raw(p)) * inv_scale;
+        return static_cast<R>(v) * inv_scale;
     else
-        return static_cast<R>(load_raw(p));
+        return static_cast<R>(v);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ R load_pop(const S *p, R inv_scale)
+{
+    return decode_pop<S, R>(load_raw(p), inv_scale);
 }
 
 template <typename S, typename R>
@@ -472,35 +478,37 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, const Geo &g)
     return n;
 }
 
-// Pull-gather of the deviations d_i(x, y).  A population whose source node
-// x - e_i lies behind a wall is the node's own opposite post-collision value
-// (half-way bounce-back).
+// Pull-gather of the deviations d_i(x, y) (gather_src: the addresses of the nine
+// stored values).  A population whose source node x - e_i lies behind a wall is the
+// node's own opposite post-collision value (half-way bounce-back).
+template <typename S>
+__device__ __forceinline__ void gather_src(const S *p[9], const S *__restrict__ f,
+                                           long long plane, int pitch, int x, int y,
+                                           const Nbr &n)
+{
+    const int c = y * pitch + x;
+    const int rm = n.ym * pitch, r0 = y * pitch, rp = n.yp * pitch;
+    const S *f1 = f + plane, *f2 = f + 2 * plane, *f3 = f + 3 * plane, *f4 = f + 4 * plane,
+            *f5 = f + 5 * plane, *f6 = f + 6 * plane, *f7 = f + 7 * plane, *f8 = f + 8 * plane;
+    p[0] = f + c;
+    p[1] = n.wxm ? f3 + c : f1 + r0 + n.xm;
+    p[2] = n.wym ? f4 + c : f2 + rm + x;
+    p[3] = n.wxp ? f1 + c : f3 + r0 + n.xp;
+    p[4] = n.wyp ? f2 + c : f4 + rp + x;
+    p[5] = (n.wxm || n.wym) ? f7 + c : f5 + rm + n.xm;
+    p[6] = (n.wxp || n.wym) ? f8 + c : f6 + rm + n.xp;
+    p[7] = (n.wxp || n.wyp) ? f5 + c : f7 + rp + n.xp;
+    p[8] = (n.wxm || n.wyp) ? f6 + c : f8 + rp + n.xm;
+}
+
 template <typename S, typename R>
 __device__ __forceinline__ void gather(R d[9], const S *__restrict__ f, long long plane,
                                        int pitch, int x, int y, const Nbr &n, R inv_scale)
 {
-    const int c = y * pitch + x;
-    const int rm = n.ym * pitch, r0 = y * pitch, rp = n.yp * pitch;
-    const S *f0 = f, *f1 = f + plane, *f2 = f + 2 * plane, *f3 = f + 3 * plane,
-            *f4 = f + 4 * plane, *f5 = f + 5 * plane, *f6 = f + 6 * plane,
-            *f7 = f + 7 * plane, *f8 = f + 8 * plane;
-    const S *p1 = n.wxm ? f3 + c : f1 + r0 + n.xm;
-    const S *p2 = n.wym ? f4 + c : f2 + rm + x;
-    const S *p3 = n.wxp ? f1 + c : f3 + r0 + n.xp;
-    const S *p4 = n.wyp ? f2 + c : f4 + rp + x;
-    const S *p5 = (n.wxm || n.wym) ? f7 + c : f5 + rm + n.xm;
-    const S *p6 = (n.wxp || n.wym) ? f8 + c : f6 + rm + n.xp;
-    const S *p7 = (n.wxp || n.wyp) ? f5 + c : f7 + rp + n.xp;
-    const S *p8 = (n.wxm || n.wyp) ? f6 + c : f8 + rp + n.xm;
-    d[0] = load_pop<S, R>(f0 + c, inv_scale);
-    d[1] = load_pop<S, R>(p1, inv_scale);
-    d[2] = load_pop<S, R>(p2, inv_scale);
-    d[3] = load_pop<S, R>(p3, inv_scale);
-    d[4] = load_pop<S, R>(p4, inv_scale);
-    d[5] = load_pop<S, R>(p5, inv_scale);
-    d[6] = load_pop<S, R>(p6, inv_scale);
-    d[7] = load_pop<S, R>(p7, inv_scale);
-    d[8] = load_pop<S, R>(p8, inv_scale);
+    const S *p[9];
+    gather_src<S>(p, f, plane, pitch, x, y, n);
+#pragma unroll
+    for (int i = 0; i < 9; i++) d[i] = load_pop<S, R>(p[i], inv_scale);
 }
 
 // Porosity tile with a one-node halo, filled with the halo rule (wrap or
@@ -2086,55 +2094,70 @@ __device__ __forceinline__ void adjoint_rows_wave(
     const AdjT<S> *__restrict__ eps, const Geo &g, const Phys<R> &ph, double *__restrict__ eb,
     double *__restrict__ gxb, double *__restrict__ gyb, int strip, int chunk)
 {
+    using A = AdjT<S>;
     const int xr = strip * TX + static_cast<int>(threadIdx.x % TX);
     const bool act = xr < g.Lx;
     const int x = act ? xr : g.Lx - 1;
     const int y0 = chunk * K;
-    const int ny = min(K, g.Ly - y0);          // rows of this chunk inside the lattice
     const int cm = halo_index(x - 1, g.Lx, g.wall_x), cp = halo_index(x + 1, g.Lx, g.wall_x);
     const gptr<double> ebg = to_global(eb), gxg = to_global(gxb), gyg = to_global(gyb);
-    // porosity rows y0 - 1 + k (k = 0 .. K + 1), columns x - 1 .. x + 1; a row past
-    // the chunk's last lattice row takes row Ly (its halo image) and goes unused
-    R E[K + 2][3];
+    // Every load below is issued with no branch around it and keeps its raw value
+    // until the row that uses it converts it: a conversion next to its load would make
+    // the wave wait for the next row's loads before the current row's arithmetic.  The
+    // rows of the last chunk past the lattice's end take its last row (their results
+    // are not stored).
+    // porosity rows y0 - 1 + k (k = 0 .. K + 1), columns x - 1 .. x + 1
+    A E[K + 2][3];
     auto eps_row = [&](int k) __attribute__((always_inline)) {
         const int yy = halo_index(min(y0 - 1 + k, g.Ly), g.Ly, g.wall_y);
-        const AdjT<S> *row = eps + static_cast<long long>(yy) * g.pitch;
-        E[k][0] = static_cast<R>(load_global(row + cm));
-        E[k][1] = static_cast<R>(load_global(row + x));
-        E[k][2] = static_cast<R>(load_global(row + cp));
+        const A *row = eps + static_cast<long long>(yy) * g.pitch;
+        E[k][0] = load_global(row + cm);
+        E[k][1] = load_global(row + x);
+        E[k][2] = load_global(row + cp);
     };
-    R mu[K][9], d[K][9];
+    A mu[K][9];
+    S q[K][9];
     double ae[K], ax[K], ay[K];
     Nbr nb[K];
     auto issue = [&](int r) __attribute__((always_inline)) {
-        const int y = y0 + r;
+        const int y = min(y0 + r, g.Ly - 1);
         nb[r] = neighbours(x, y, g);
         const int c = y * g.pitch + x;
+        const S *p[9];
+        gather_src<S>(p, fin, g.plane, g.pitch, x, y, nb[r]);
 #pragma unroll
-        for (int i = 0; i < 9; i++)
-            mu[r][i] = static_cast<R>(load_global(lam_next + i * g.plane + c));
-        gather<S, R>(d[r], fin, g.plane, g.pitch, x, y, nb[r], ph.inv_scale);
+        for (int i = 0; i < 9; i++) {
+            mu[r][i] = load_global(lam_next + i * g.plane + c);
+            q[r][i] = load_raw(p[i]);
+        }
         ae[r] = ebg[c];
         ax[r] = gxg[c];
         ay[r] = gyg[c];
     };
     auto compute = [&](int r) __attribute__((always_inline)) {
-        const int y = y0 + r;
+        const int y = min(y0 + r, g.Ly - 1);
+        const bool row_ok = y0 + r < g.Ly;     // uniform
         const Nbr &n = nb[r];
-        const R t[3][3] = {{E[r][0], E[r][1], E[r][2]},
-                           {E[r + 1][0], E[r + 1][1], E[r + 1][2]},
-                           {E[r + 2][0], E[r + 2][1], E[r + 2][2]}};
+        R d[9], m[9];
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            d[i] = decode_pop<S, R>(q[r][i], ph.inv_scale);
+            m[i] = static_cast<R>(mu[r][i]);
+        }
+        const R t[3][3] = {{R(E[r][0]), R(E[r][1]), R(E[r][2])},
+                           {R(E[r + 1][0]), R(E[r + 1][1]), R(E[r + 1][2])},
+                           {R(E[r + 2][0]), R(E[r + 2][1]), R(E[r + 2][2])}};
         const PorNb<R> P = porosity_nb<R, 3>(t, 1, 1, n.wxm, n.wxp, n.wym, n.wyp);
         const bool ores = g.open_x && ph.reservoir;
         const bool ol = ores && x == 0, orr = ores && x == g.Lx - 1;
-        boundary_inflow<R>(d[r], P.e0, ol, orr, n.wym, n.wyp, ph);
-        unshift_incoming<R>(d[r], P, ph.rho0);
+        boundary_inflow<R>(d, P.e0, ol, orr, n.wym, n.wyp, ph);
+        unshift_incoming<R>(d, P, ph.rho0);
         R nu[9], e_b, gx_b, gy_b;
         bool res[9];
-        adjoint_node<R, false>(d[r], P, n, ol, orr, x == g.Lx - 1, ph, mu[r], nu, res, e_b,
-                               gx_b, gy_b, nullptr);
-        if (act) {
-            push_global<R, AdjT<S>>(lam, g, x, y, n, nu, res);
+        adjoint_node<R, false>(d, P, n, ol, orr, x == g.Lx - 1, ph, m, nu, res, e_b, gx_b,
+                               gy_b, nullptr);
+        if (act && row_ok) {
+            push_global<R, A>(lam, g, x, y, n, nu, res);
             const int c = y * g.pitch + x;
             ebg[c] = ae[r] + static_cast<double>(e_b);
             gxg[c] = ax[r] + static_cast<double>(gx_b);
@@ -2147,12 +2170,9 @@ __device__ __forceinline__ void adjoint_rows_wave(
     issue(0);
     static_while<K>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        if (r >= ny) return false;             // uniform: the last chunk's rows past the end
         if constexpr (r + 1 < K) {
-            if (r + 1 < ny) {
-                eps_row(r + 3);
-                issue(r + 1);
-            }
+            eps_row(r + 3);
+            issue(r + 1);
         }
         compute(r);
         return true;

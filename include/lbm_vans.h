@@ -146,7 +146,8 @@ typedef struct lbm_vans_params {
                               when the three-step pass has enough
                               waves (60 columns x pass_rows rows each) for the GPU:
                               0.9 times as many as it holds of the kernel at once in
-                              24-row chunks, a fifth in 12-row chunks (FP32), 0.7
+                              24-row chunks, half in 12-row chunks, a fifth in 6-row
+                              chunks (FP32), 0.7
                               times (FP16, or an explicit pass_rows); else 2 when the
                               two-step pass has >= 2048 waves (62 x 8, 16 in FP16),
                               else 1.  Several steps per pass need
@@ -159,11 +160,12 @@ typedef struct lbm_vans_params {
                               storage rounds once per pass) and each pass recomputes
                               its chunk's halo.                                       */
     int32_t pass_rows;     /* output rows per chunk (wave) of the three-step pass:
-                              0 = automatic; LBM_F32_SHIFTED: 12, 24 or 28
+                              0 = automatic; LBM_F32_SHIFTED: 6, 12, 24 or 28
                               (automatic: 28 when that still gives four times as many
                               waves as the GPU holds of the kernel at once, else 24
-                              when that gives 0.9 times as many, else 12: taller chunks
-                              recompute fewer halo rows but give fewer waves);
+                              when that gives 0.9 times as many, else 12 when that
+                              gives half as many, else 6: taller chunks recompute
+                              fewer halo rows but give fewer waves);
                               LBM_F16_SHIFTED: 24.  Batches take 24 or 28.  Results
                               do not depend on it beyond rounding.                    */
 } lbm_vans_params;

@@ -148,6 +148,9 @@ int scratch_address(void **out)
 #ifndef LBM_VANS_TB3_SHORT32
 #define LBM_VANS_TB3_SHORT32 12
 #endif
+#ifndef LBM_VANS_TB3_TINY32
+#define LBM_VANS_TB3_TINY32 6
+#endif
 #ifndef LBM_VANS_TB4_ROWS32
 #define LBM_VANS_TB4_ROWS32 24
 #endif
@@ -1084,6 +1087,8 @@ constexpr int tb_cols()
 // The batched kernels tell the two FP32 heights apart by their row count.
 static_assert(LBM_VANS_TB3_SHORT32 < LBM_VANS_TB3_ROWS32,
               "the short chunks of the FP32 three-step pass must be shorter than the default");
+static_assert(LBM_VANS_TB3_TINY32 < LBM_VANS_TB3_SHORT32,
+              "the tiny chunks of the FP32 three-step pass must be shorter than the short ones");
 static_assert(LBM_VANS_TB3_TALL32 > LBM_VANS_TB3_ROWS32,
               "the tall chunks of the FP32 three-step pass must be taller than the short ones");
 
@@ -2564,14 +2569,15 @@ int check_pass_rows(int32_t rows, int32_t storage)
 {
     if (rows == 0) return LBM_VANS_OK;
     if (storage == LBM_F32_SHIFTED &&
-        (rows == LBM_VANS_TB3_SHORT32 || rows == tb_rows<float, 3>() || rows == LBM_VANS_TB3_TALL32))
+        (rows == LBM_VANS_TB3_TINY32 || rows == LBM_VANS_TB3_SHORT32 ||
+         rows == tb_rows<float, 3>() || rows == LBM_VANS_TB3_TALL32))
         return LBM_VANS_OK;
     if (storage == LBM_F16_SHIFTED && rows == tb_rows<_Float16, 3>()) return LBM_VANS_OK;
     return fail(LBM_VANS_EINVAL,
-                "pass_rows = %d: 0 (automatic); %d, %d or %d with LBM_F32_SHIFTED storage; %d "
-                "with LBM_F16_SHIFTED storage",
-                rows, LBM_VANS_TB3_SHORT32, tb_rows<float, 3>(), LBM_VANS_TB3_TALL32,
-                tb_rows<_Float16, 3>());
+                "pass_rows = %d: 0 (automatic); %d, %d, %d or %d with LBM_F32_SHIFTED storage; "
+                "%d with LBM_F16_SHIFTED storage",
+                rows, LBM_VANS_TB3_TINY32, LBM_VANS_TB3_SHORT32, tb_rows<float, 3>(),
+                LBM_VANS_TB3_TALL32, tb_rows<_Float16, 3>());
 }
 
 int check_params(const lbm_vans_params *p)
@@ -2888,6 +2894,8 @@ int tb3_resident(int storage, int bx, bool wy, int rows, bool batch, long long *
             else q(k_sweep_tb3<float, float, BXV, WYV, NR>);
         } else if (rows == LBM_VANS_TB3_SHORT32 && !batch) {
             q(k_sweep_tb3<float, float, BXV, WYV, LBM_VANS_TB3_SHORT32>);
+        } else if (rows == LBM_VANS_TB3_TINY32 && !batch) {
+            q(k_sweep_tb3<float, float, BXV, WYV, LBM_VANS_TB3_TINY32>);
         } else {
             constexpr int NR = tb_rows<float, 3>();
             if (batch) q(k_batch_tb3<float, float, BXV, WYV, NR>);
@@ -2929,11 +2937,16 @@ int tb4_resident(int bx, bool wy, bool batch, long long *out)
 // 1024^2 109 / 127 / 118, 1536 x 1024 124 / 139 / 123, 2048 x 1024 134 / 158 / 157,
 // 2048^2 109 / 157 / 161, 4096^2 108 / 164 / 164 (28 rows 164); channel with walls
 // and inlet / outlet 1024 x 512 57 / 64 / 37 (one step per pass 58), 1024^2 88 / 93
-// / 72, 2048 x 1024 112 / 121 / 108.  FP32: 24-row chunks when the lattice has at
-// least 0.9 times as many of their waves as the chip holds at once (28-row chunks, which
-// recompute fewer halo rows, with four times as many), else 12-row chunks when
-// those have at least a fifth of what the chip holds; three steps in the chosen
-// height, else pairs when the two-step pass has >= 2048 waves, else one step.
+// / 72, 2048 x 1024 112 / 121 / 108.  Three steps in 12-row / 6-row chunks (one step
+// per pass): box 512^2 53.0 / 76.3 (40.7), 1024 x 512 102.3 / 104.9, 768^2 115.5 /
+// 117.0, 1024^2 137.1 / 120.7, 2048 x 1024 178.6 / 156.4; channel 512 x 256 16.9 /
+// 27.0 (31.7), 1024 x 512 65.6 / 79.8, 1024^2 96.6 / 101.9, 2048 x 1024 147.4 / 137.1.
+// FP32: 24-row chunks when the lattice has at least 0.9 times as many of their waves
+// as the chip holds at once (28-row chunks, which recompute fewer halo rows, with four
+// times as many), else 12-row chunks when those have at least half of what the chip
+// holds, else 6-row chunks; three steps in the chosen height when its waves are at
+// least a fifth of what the chip holds, else pairs when the two-step pass has >= 2048
+// waves, else one step.
 // FP16 (one height): three steps when the lattice has 0.7 times as many waves as
 // the chip holds, else pairs or one step as above.  Four steps per pass (FP32, 24-row
 // chunks, 58-column strips) when that pass has at least as many waves as the chip
@@ -2943,7 +2956,8 @@ int tb4_resident(int bx, bool wy, bool batch, long long *out)
 constexpr int QUAD_FILL = 1;                // four steps: waves >= resident
 constexpr int TALL_FILL = 4;                // tall chunks: waves >= 4 x resident
 constexpr int DEFAULT_FILL_10 = 9;          // FP32 24-row chunks: waves >= 0.9 x resident
-constexpr int SHORT_FILL_10 = 2;            // FP32 12-row chunks: waves >= 0.2 x resident
+constexpr int HALF_FILL_10 = 5;             // FP32 12-row chunks: waves >= 0.5 x resident,
+constexpr int SHORT_FILL_10 = 2;            // else 6-row chunks: waves >= 0.2 x resident
 constexpr int TRIPLE_FILL_10 = 7;           // FP16, or an explicit height: >= 0.7 x
 
 bool tall_auto(long long tall_waves, long long resident)
@@ -2975,6 +2989,9 @@ int choose_passes(lbm_vans_handle *h)
         long long res24 = 0;
         rc = tb3_resident(p->storage, bx, wy, tb_rows<float, 3>(), false, &res24);
         if (rc) return rc;
+        long long res12 = 0;
+        rc = tb3_resident(p->storage, bx, wy, LBM_VANS_TB3_SHORT32, false, &res12);
+        if (rc) return rc;
         if (tall_auto(waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32), res)) {
             h->rows3 = LBM_VANS_TB3_TALL32;
         } else if (10 * waves_of(p->Lx, p->Ly, 3, tb_rows<float, 3>()) >=
@@ -2982,8 +2999,12 @@ int choose_passes(lbm_vans_handle *h)
                    !multi_rows_ok(p->Ly, wy, 3, LBM_VANS_TB3_SHORT32)) {
             h->rows3 = tb_rows<float, 3>();
             fill10 = DEFAULT_FILL_10;
-        } else {
+        } else if (10 * waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_SHORT32) >=
+                   HALF_FILL_10 * res12) {
             h->rows3 = LBM_VANS_TB3_SHORT32;
+            fill10 = SHORT_FILL_10;
+        } else {
+            h->rows3 = LBM_VANS_TB3_TINY32;
             fill10 = SHORT_FILL_10;
         }
     }
@@ -3060,6 +3081,8 @@ int launch_multi(lbm_vans_handle *h, const void *src, void *dst, int ns)
                         run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_TALL32>);
                     else if (rows == LBM_VANS_TB3_SHORT32)
                         run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_SHORT32>);
+                    else if (rows == LBM_VANS_TB3_TINY32)
+                        run(k_sweep_tb3<S, R, BXV, WYV, LBM_VANS_TB3_TINY32>);
                     else
                         run(k_sweep_tb3<S, R, BXV, WYV, tb_rows<S, 3>()>);
                 } else {
@@ -4039,7 +4062,7 @@ int check_config(const lbm_vans_batch *b, const lbm_vans_batch_config *c)
                     c->steps_per_pass);
     if (c->steps_per_pass == 4 && b->storage != LBM_F32_SHIFTED)
         return fail(LBM_VANS_EINVAL, "steps_per_pass = 4 needs LBM_F32_SHIFTED storage");
-    if (c->pass_rows == LBM_VANS_TB3_SHORT32)
+    if (c->pass_rows == LBM_VANS_TB3_SHORT32 || c->pass_rows == LBM_VANS_TB3_TINY32)
         return fail(LBM_VANS_EINVAL, "pass_rows = %d: batches take %d or %d (or 0)",
                     c->pass_rows, tb_rows<float, 3>(), LBM_VANS_TB3_TALL32);
     return check_pass_rows(c->pass_rows, b->storage);

@@ -98,7 +98,7 @@ class Params:
     u_wall: tuple = (0.0, 0.0)
     sweep_vec: int = 0      # nodes per lane of the one-step sweep, 0 = automatic
     steps_per_pass: int = 0  # most steps per pass: 0 = automatic (3), 1, 2 or 3
-    pass_rows: int = 0       # rows per chunk of the three-step pass: 0 = automatic, 12, 24, 28
+    pass_rows: int = 0       # rows per chunk of the three-step pass: 0 = automatic, 6, 12, 24, 28
 
     def c(self) -> LbmVansParams:
         return LbmVansParams(self.Lx, self.Ly, self.bc_x, self.bc_y, self.storage, self.drag,

@@ -78,8 +78,8 @@ class Spec:
 # Execution paths of lbm_vans_step: "auto" (the library's choice: on the small test
 # grids the one-step sweep with one node per lane, as their widest sweep would have
 # fewer tiles than the GPU has compute units), "triples" (three steps per pass in the
-# default 24-row chunks), "short" (three steps per pass in 12-row chunks: FP32
-# storage), "tall" (three steps per pass in 28-row chunks: FP32 storage; the FP16 pass
+# default 24-row chunks), "short" and "tiny" (three steps per pass in 12-row and
+# 6-row chunks: FP32 storage), "tall" (three steps per pass in 28-row chunks: FP32 storage; the FP16 pass
 # has one height), "quads" (four steps per pass: FP32 storage), "pairs" (at most two
 # steps per pass), "wide" (one step per pass,
 # widest vector width) and "narrow" (one step per pass, one node per lane), so that
@@ -91,6 +91,8 @@ def exec_mode(mode: str, storage: str) -> dict:
         return {"steps_per_pass": 3, "pass_rows": 24 if storage in ("f32", "f16") else 0}
     if mode == "short":
         return {"steps_per_pass": 3, "pass_rows": 12 if storage == "f32" else 0}
+    if mode == "tiny":
+        return {"steps_per_pass": 3, "pass_rows": 6 if storage == "f32" else 0}
     if mode == "tall":
         return {"steps_per_pass": 3, "pass_rows": 28 if storage == "f32" else 0}
     if mode == "quads":

@@ -31,7 +31,7 @@ def main(path):
            dict(rho0=0.0), dict(G=(math.inf, 0.0)), dict(Lx=65536, Ly=65536),
            dict(u_wall=(0.01, 0.0)), dict(sweep_vec=3), dict(steps_per_pass=5),
            dict(steps_per_pass=4, storage=lbm.F16_SHIFTED), dict(pass_rows=12, storage=lbm.F16_SHIFTED),
-           dict(pass_rows=16), dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30)]
+           dict(pass_rows=6, storage=lbm.F16_SHIFTED), dict(pass_rows=16), dict(storage=lbm.F16_SHIFTED, fp16_scale_log2=30)]
     for b in bad:
         p = lbm.Params(**dict(base, **b))
         assert L.lbm_vans_work_bytes(ctypes.byref(p.c())) == 0

@@ -79,6 +79,7 @@ def test_work_bytes_scale_with_storage():
     dict(steps_per_pass=4, storage=lbm.F64),
     dict(pass_rows=16), dict(pass_rows=-24), dict(pass_rows=28, storage=lbm.F16_SHIFTED),
     dict(pass_rows=12, storage=lbm.F16_SHIFTED), dict(pass_rows=12, storage=lbm.F64),
+    dict(pass_rows=6, storage=lbm.F16_SHIFTED), dict(pass_rows=8),
     dict(pass_rows=24, storage=lbm.F64),
 ])
 def test_invalid_params_rejected_without_gpu(bad):

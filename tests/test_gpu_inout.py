@@ -60,15 +60,15 @@ def _bound(spec, eps, fo, nsteps):
     return 2 * (nsteps + 1) * 2.0 ** -11 * D
 
 
-@pytest.mark.parametrize("mode", ["auto", "triples", "short", "tall", "quads", "pairs", "wide",
+@pytest.mark.parametrize("mode", ["auto", "triples", "short", "tiny", "tall", "quads", "pairs", "wide",
                                   "narrow"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_wy%d" % g)
 def test_inout_forward_parity(geom, storage, mode):
     Lx, Ly, wy = geom
-    if storage == "f64" and mode in ("triples", "short", "tall", "quads", "pairs"):
+    if storage == "f64" and mode in ("triples", "short", "tiny", "tall", "quads", "pairs"):
         pytest.skip("FP64 storage steps one step per pass")
-    if storage == "f16" and mode in ("short", "tall", "quads"):
+    if storage == "f16" and mode in ("short", "tiny", "tall", "quads"):
         pytest.skip("the FP16 multi-step passes have one chunk height and three steps")
     say(f"[inout forward {storage} {mode}] {Lx}x{Ly} walls_y={wy}")
     spec = _spec(Lx, Ly, storage, walls_y=wy, **exec_mode(mode, storage))

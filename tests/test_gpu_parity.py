@@ -82,8 +82,8 @@ def test_f64_parity_small_grids(geom, mode):
     assert np.abs(mg["rho"] - mo["rho"]).max() <= 1e-13
 
 
-@pytest.mark.parametrize("mode", ["auto", "triples", "short", "tall", "quads", "pairs", "wide",
-                                  "narrow"])
+@pytest.mark.parametrize("mode", ["auto", "triples", "short", "tiny", "tall", "quads", "pairs",
+                                  "wide", "narrow"])
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "%dx%d_w%d%d" % g)
 def test_f32_parity_small_grids(geom, mode):
     Lx, Ly, wx, wy = geom
@@ -402,14 +402,15 @@ TB_GEOMS = [(70, 40, "periodic", False), (130, 33, "periodic", True), (5, 7, "pe
             (64, 90, "periodic", False), (70, 61, "walls", True), (130, 75, "open", True)]
 
 
-@pytest.mark.parametrize("per_pass, rows", [(2, 0), (3, 0), (3, 12), (3, 24), (3, 28), (4, 0)],
-                         ids=["pairs", "triples", "triples_12rows", "triples_24rows",
-                              "triples_28rows", "quads"])
+@pytest.mark.parametrize("per_pass, rows", [(2, 0), (3, 0), (3, 6), (3, 12), (3, 24), (3, 28),
+                                            (4, 0)],
+                         ids=["pairs", "triples", "triples_6rows", "triples_12rows",
+                              "triples_24rows", "triples_28rows", "quads"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("geom", TB_GEOMS, ids=lambda g: "%dx%d_%s_wy%d" % g)
 def test_multi_step_pass_matches_oracle_and_single_steps(geom, storage, per_pass, rows):
     """Two, three or four steps per pass (three in chunks of the automatic height or of
-    12, 24 or 28 rows, FP32; four in 24-row chunks, FP32) against the oracle and against
+    6, 12, 24 or 28 rows, FP32; four in 24-row chunks, FP32) against the oracle and against
     one step per call; step counts that leave a shorter last pass (2, 7: 3+3+1,
     2+2+2+1 or 4+3) and that do not."""
     from paper_1406_6438_amd import lbm

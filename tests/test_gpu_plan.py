@@ -58,8 +58,9 @@ def _plan(Lx, Ly, channel=False, storage="f32", **kw):
     (2048, 2048, False, "f32", (4, 24)),
     (2048, 1024, False, "f32", (3, 12)),
     (1024, 1024, False, "f32", (3, 12)),
-    (1024, 512, True, "f32", (3, 12)),
-    (512, 256, False, "f32", (1, 12)),
+    (1024, 512, True, "f32", (3, 6)),
+    (512, 512, False, "f32", (3, 6)),
+    (512, 256, False, "f32", (1, 6)),
     (4096, 4096, True, "f32", (4, 24)),
     (4096, 4096, False, "f16", (3, 24)),
     (64, 32, False, "f64", (1, 0)),
@@ -73,9 +74,10 @@ def test_automatic_plan(Lx, Ly, channel, storage, expected):
     (dict(steps_per_pass=3, pass_rows=24), (3, 24)),
     (dict(steps_per_pass=3, pass_rows=28), (3, 28)),
     (dict(steps_per_pass=3, pass_rows=12), (3, 12)),
+    (dict(steps_per_pass=3, pass_rows=6), (3, 6)),
     (dict(steps_per_pass=4), (4, 24)),
     (dict(steps_per_pass=4, pass_rows=12), (4, 24)),
-    (dict(steps_per_pass=1), (1, 12)),
+    (dict(steps_per_pass=1), (1, 6)),
 ])
 def test_explicit_plan(kw, expected):
     assert _plan(96, 40, **kw) == expected
@@ -93,8 +95,10 @@ def test_batch_plan():
     assert b.pass_plan == (2, 24)
     b.configure(4, 0, 24, 4, 0)
     assert b.pass_plan == (4, 24)
-    with pytest.raises(lbm.LbmVansError):      # the 12-row height is for lone lattices
+    with pytest.raises(lbm.LbmVansError):      # the 12- and 6-row heights are for lone lattices
         b.configure(4, 0, 24, 3, 12)
+    with pytest.raises(lbm.LbmVansError):
+        b.configure(4, 0, 24, 3, 6)
     b.close()
     for s in sv:
         s.close()

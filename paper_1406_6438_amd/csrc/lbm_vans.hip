@@ -1988,23 +1988,21 @@ __device__ __forceinline__ void push_global(A *__restrict__ lam, const Geo &g, i
 template <typename S>
 using AdjT = std::conditional_t<std::is_same_v<S, double>, double, float>;
 
-// One reverse step (SEED = false) or the objective's seed (SEED = true).
-// fin: the stored state n (what the forward sweep of step n gathers from).
-// lam_next: adjoint of the state n + 1 (unused for the seed); lam: receives
-// the adjoint of the state n.  eb, gxb, gyb: FP64 accumulators [Ly][pitch].
-// R is the reverse step's compute type; the library runs it in FP64 for every
-// storage (the states of FP32 / FP16 storage are decoded into FP64, and eps is
-// an FP64 copy of the forward's porosity).
-// The seed computes J = sum over x = Lx-1 of eps rho u_x of the state n (tile
-// partials in part) and the adjoint of the state from it.
-template <typename S, typename R, bool SEED>
-__device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
-                                             const AdjT<S> *__restrict__ lam_next,
-                                             AdjT<S> *__restrict__ lam, const R *__restrict__ eps,
-                                             const Geo &g, const Phys<R> &ph,
-                                             double *__restrict__ eb, double *__restrict__ gxb,
-                                             double *__restrict__ gyb,
-                                             double *__restrict__ part, int t)
+// The objective's seed over one tile of TX x TY nodes: J = sum over x = Lx-1 of
+// eps rho u_x of the stored state N in fin (tile partials in part) and the adjoint
+// of that state from it into lam, with the state's porosity sensitivities added to
+// the FP64 accumulators eb, gxb, gyb [Ly][pitch].  R is the compute type of the
+// reverse pass (FP64 for every storage: the states of FP32 / FP16 storage are
+// decoded into FP64, and eps is an FP64 copy of the forward's porosity).  It runs
+// once per gradient; the reverse steps are the row-walking waves below.
+template <typename S, typename R>
+__device__ __forceinline__ void adjoint_seed_tile(const S *__restrict__ fin,
+                                                  AdjT<S> *__restrict__ lam,
+                                                  const R *__restrict__ eps, const Geo &g,
+                                                  const Phys<R> &ph, double *__restrict__ eb,
+                                                  double *__restrict__ gxb,
+                                                  double *__restrict__ gyb,
+                                                  double *__restrict__ part, int t)
 {
     constexpr int W = TX + 2;
     __shared__ R tile[TY + 2][W];
@@ -2016,15 +2014,15 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
     const gptr<double> ebg = to_global(eb), gxg = to_global(gxb), gyg = to_global(gyb);
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx;
-    // The porosity tile's loads go first, then every node's own loads (its adjoints,
-    // its gather and its accumulators), and only then the tile to LDS and the
-    // barrier: memory counters retire in order, so waiting for the tile does not wait
-    // for the node's loads, whose latency runs under the tile's.
+    // The porosity tile's loads go first, then every node's own loads (its gather and
+    // its accumulators), and only then the tile to LDS and the barrier: memory
+    // counters retire in order, so waiting for the tile does not wait for the node's
+    // loads, whose latency runs under the tile's.
     EpsTile<R, W> et;
     et.issue(eps, g, x0, y0);
     bool ok[ROWS];
     Nbr nb[ROWS];
-    R mu[ROWS][9], d[ROWS][9];
+    R d[ROWS][9];
     double ae[ROWS], ax[ROWS], ay[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
@@ -2032,12 +2030,6 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         ok[r] = x < g.Lx && y < g.Ly;
         if (!ok[r]) continue;
         nb[r] = neighbours(x, y, g);
-        if constexpr (!SEED) {
-            const int c = y * g.pitch + x;
-#pragma unroll
-            for (int i = 0; i < 9; i++)
-                mu[r][i] = static_cast<R>(load_global(lam_next + i * g.plane + c));
-        }
         gather<S, R>(d[r], fin, g.plane, g.pitch, x, y, nb[r], ph.inv_scale);
         const int c = y * g.pitch + x;
         ae[r] = ebg[c];
@@ -2058,29 +2050,28 @@ __device__ __forceinline__ void adjoint_tile(const S *__restrict__ fin,
         const bool ol = ores && x == 0, orr = ores && x == g.Lx - 1;
         boundary_inflow<R>(d[r], P.e0, ol, orr, n.wym, n.wyp, ph);
         unshift_incoming<R>(d[r], P, ph.rho0);
-        R nu[9], e_b, gx_b, gy_b;
+        R mu[9], nu[9], e_b, gx_b, gy_b;     // the seed sets mu (no later step)
         bool res[9];
-        adjoint_node<R, SEED>(d[r], P, n, ol, orr, x == g.Lx - 1, ph, mu[r], nu, res, e_b,
-                              gx_b, gy_b, acc);
+        adjoint_node<R, true>(d[r], P, n, ol, orr, x == g.Lx - 1, ph, mu, nu, res, e_b, gx_b,
+                              gy_b, acc);
         push_global<R, AdjT<S>>(lam, g, x, y, n, nu, res);
         ebg[c] = ae[r] + static_cast<double>(e_b);
         gxg[c] = ax[r] + static_cast<double>(gx_b);
         gyg[c] = ay[r] + static_cast<double>(gy_b);
     }
-    if constexpr (SEED) block_partial(acc, part, t);
+    block_partial(acc, part, t);
 }
 
-template <typename S, typename R, bool SEED>
-__global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
-                                                      const AdjT<S> *__restrict__ lam_next,
-                                                      AdjT<S> *__restrict__ lam,
-                                                      const R *__restrict__ eps, Geo g,
-                                                      Phys<R> ph, double *__restrict__ eb,
-                                                      double *__restrict__ gxb,
-                                                      double *__restrict__ gyb,
-                                                      double *__restrict__ part)
+template <typename S, typename R>
+__global__ __launch_bounds__(NTHREADS) void k_adjoint_seed(const S *__restrict__ fin,
+                                                           AdjT<S> *__restrict__ lam,
+                                                           const R *__restrict__ eps, Geo g,
+                                                           Phys<R> ph, double *__restrict__ eb,
+                                                           double *__restrict__ gxb,
+                                                           double *__restrict__ gyb,
+                                                           double *__restrict__ part)
 {
-    adjoint_tile<S, R, SEED>(fin, lam_next, lam, eps, g, ph, eb, gxb, gyb, part, blockIdx.x);
+    adjoint_seed_tile<S, R>(fin, lam, eps, g, ph, eb, gxb, gyb, part, blockIdx.x);
 }
 
 // One reverse step (no seed) with each wave walking K consecutive rows of a
@@ -2091,7 +2082,8 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const S *__restrict__ fin,
 // three rows of three columns in registers, wrapped or mirrored as in the tile,
 // so waves share no LDS and wait at no barrier.  The porosity is the forward's
 // own array (FP32 for FP32 / FP16 storage, widened exactly on load).  The
-// arithmetic of a node is that of k_adjoint.  A lane past the row end computes on
+// arithmetic of a node is the seed's (adjoint_node) given the adjoints of its
+// outgoing values.  A lane past the row end computes on
 // the last column and stores nothing.
 template <typename S, typename R, int K>
 __device__ __forceinline__ void adjoint_rows_wave(
@@ -2458,26 +2450,21 @@ __attribute__((amdgpu_waves_per_eu(1, tb3_max_waves<S, BX, WY>()))) void k_batch
     batch_multi_wave<S, R, BX, WY, 4, tb_rows<float, 4>(), 3>(M, wmap, nwaves, src, dst, res_a);
 }
 
-// One reverse step of every member: adjoint slot a_next (of the state n + 1)
-// to adjoint slot a (of the state n, read from state slot src); the seed
-// starts the adjoints from the objective of the state in src.
-// (the reverse step in FP64 for every storage, as lbm_vans_grad)
-template <typename S, typename R, bool SEED>
-__global__ __launch_bounds__(NTHREADS) void k_batch_adjoint(const Member<R> *__restrict__ M,
-                                                            const int *__restrict__ tmap,
-                                                            int ntiles, int src, int a_next,
-                                                            int a, int reservoir)
+// The seed of every member: the adjoint (slot a) of the state in state slot src
+// from each member's objective (FP64 for every storage, as lbm_vans_grad).
+template <typename S, typename R>
+__global__ __launch_bounds__(NTHREADS) void k_batch_adjoint_seed(
+    const Member<R> *__restrict__ M, const int *__restrict__ tmap, int ntiles, int src, int a,
+    int reservoir)
 {
     const int T = xcd_tile(blockIdx.x, ntiles);
     const Member<R> &d = M[tmap[T]];
     const Geo g = d.g;
     Phys<double> ph = d.pha;
     ph.reservoir = reservoir;
-    adjoint_tile<S, double, SEED>(reinterpret_cast<const S *>(state_slot(d, src)),
-                                  SEED ? nullptr : adj_buf<AdjT<S>>(d, a_next),
-                                  adj_buf<AdjT<S>>(d, a), d.eps_a,
-                                  g, ph, acc_buf(d, 0), acc_buf(d, 1), acc_buf(d, 2), d.part,
-                                  T - d.tile0_adj);
+    adjoint_seed_tile<S, double>(reinterpret_cast<const S *>(state_slot(d, src)),
+                                 adj_buf<AdjT<S>>(d, a), d.eps_a, g, ph, acc_buf(d, 0),
+                                 acc_buf(d, 1), acc_buf(d, 2), d.part, T - d.tile0_adj);
 }
 
 // One reverse step (no seed) of every member, one wave per entry of the adjoint
@@ -3605,10 +3592,10 @@ int grad_run(lbm_vans_handle *h, int32_t objective, int64_t nsteps, int32_t ckpt
         }
         ph.reservoir = res_on(&h->p, nsteps);
         int a = 0;
-        hipLaunchKernelGGL((k_adjoint<S, RA, true>), dim3(h->ntiles), dim3(NTHREADS), 0,
-                           h->stream, (const S *)h->buf[h->cur], (const AdjT<S> *)nullptr,
-                           (AdjT<S> *)lam[a], eps_a, g, ph, eb, gxb, gyb, h->part);
-        r = check_launch("k_adjoint seed");
+        hipLaunchKernelGGL((k_adjoint_seed<S, RA>), dim3(h->ntiles), dim3(NTHREADS), 0,
+                           h->stream, (const S *)h->buf[h->cur], (AdjT<S> *)lam[a], eps_a, g,
+                           ph, eb, gxb, gyb, h->part);
+        r = check_launch("k_adjoint_seed");
         if (r) return r;
         r = launch_finalize(h, h->scratch_rec, h->ntiles, false, static_cast<double>(nsteps));
         if (r) return r;
@@ -4005,9 +3992,9 @@ int batch_adjoint(lbm_vans_batch *b, bool seed, int src, int a_next, int a, int 
         using R = std::remove_pointer_t<decltype(rp)>;
         const Member<R> *M = static_cast<const Member<R> *>(b->d_desc);
         if (seed)
-            hipLaunchKernelGGL((k_batch_adjoint<S, R, true>), dim3(b->ntiles_adj),
+            hipLaunchKernelGGL((k_batch_adjoint_seed<S, R>), dim3(b->ntiles_adj),
                                dim3(NTHREADS), 0, b->stream, M, (const int *)b->d_tmap_adj,
-                               b->ntiles_adj, src, a_next, a, reservoir);
+                               b->ntiles_adj, src, a, reservoir);
         else
             hipLaunchKernelGGL((k_batch_adjoint_rows<S, R>),
                                dim3((unsigned)((b->ntiles_adj + NW - 1) / NW)), dim3(NTHREADS),

@@ -1223,7 +1223,9 @@ __device__ __forceinline__ void static_while(F &&f)
     static_while_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <typename S, typename R, int BX, bool WY, int NS, int NR>
+// BXA: the x ends whose gather lookahead the pass takes (the kernel's own, also when a
+// wave of it runs without x-end rules, so that both paths fit its registers).
+template <typename S, typename R, int BX, bool WY, int NS, int NR, int BXA = BX>
 __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict__ fout,
                                         const R *__restrict__ eps, const Geo &g,
                                         const Phys<R> &ph, int strip, int chunk, int res_a)
@@ -1232,7 +1234,7 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     static_assert(NS >= 2 && NS <= 4, "two to four steps per pass");
     constexpr bool WX = BX != 0;
     constexpr int H = NS - 1;                 // halo lanes per side, halo rows per chunk end
-    constexpr int PD = tb_ahead<S, NS, BX, WY>();
+    constexpr int PD = tb_ahead<S, NS, BXA, WY>();
     constexpr int NA = NR + 2 * H;            // first-step rows y0-H .. y0+NR+H-1
     constexpr int NE = NA + 2;                // porosity rows y0-H-1 .. y0+NR+H
     constexpr unsigned SB = sizeof(S), EB = sizeof(R);
@@ -1472,6 +1474,36 @@ __device__ __forceinline__ void tb_wave(const S *__restrict__ fin, S *__restrict
     });
 }
 
+// Whether the wave of strip `strip` has no lane, its halo lanes included, at an x
+// end of a lattice Lx wide or beyond it: such a wave meets none of the x-end rules
+// (walls, reservoirs, inlet / outlet), so the pass built without them (x periodic,
+// whose wrap it never reaches) computes the same values with fewer instructions.
+template <int NS>
+__device__ __forceinline__ bool strip_clear_of_x_ends(int strip, int Lx)
+{
+    const int xlo = strip * tb_cols<NS>() - (NS - 1);
+    return xlo >= 1 && xlo + TX - 1 <= Lx - 2;
+}
+
+// The multi-step pass of one wave: with open x ends (BX == 2: reservoirs, or an inlet
+// and an outlet), the waves clear of them take the pass without x-end rules (a branch
+// uniform over the wave).  Not for x walls: there the second path costs the four-step
+// kernel half its waves per SIMD (256 VGPRs), the lattices are closed boxes, and their
+// wall rules are cheap selects.
+template <typename S, typename R, int BX, bool WY, int NS, int NR>
+__device__ __forceinline__ void tb_wave_x(const S *__restrict__ fin, S *__restrict__ fout,
+                                          const R *__restrict__ eps, const Geo &g,
+                                          const Phys<R> &ph, int strip, int chunk, int res_a)
+{
+    if constexpr (BX == 2) {
+        if (strip_clear_of_x_ends<NS>(strip, g.Lx)) {
+            tb_wave<S, R, 0, WY, NS, NR, BX>(fin, fout, eps, g, ph, strip, chunk, res_a);
+            return;
+        }
+    }
+    tb_wave<S, R, BX, WY, NS, NR>(fin, fout, eps, g, ph, strip, chunk, res_a);
+}
+
 template <typename S, typename R, int BX, bool WY, int NS, int NR>
 __device__ __forceinline__ void sweep_multi(const S *__restrict__ fin, S *__restrict__ fout,
                                             const R *__restrict__ eps, const Geo &g,
@@ -1483,7 +1515,7 @@ __device__ __forceinline__ void sweep_multi(const S *__restrict__ fin, S *__rest
                                                    threadIdx.x / TX);
     const int strip = wid % nstrips, chunk = wid / nstrips;
     if (chunk >= nchunks) return;              // whole waves only; no barrier below
-    tb_wave<S, R, BX, WY, NS, NR>(fin, fout, eps, g, ph, strip, chunk, res_a);
+    tb_wave_x<S, R, BX, WY, NS, NR>(fin, fout, eps, g, ph, strip, chunk, res_a);
 }
 
 // Two steps per launch (one wave per strip and chunk).
@@ -2415,9 +2447,9 @@ __device__ __forceinline__ void batch_multi_wave(const Member<R> *__restrict__ M
     Phys<R> ph = d.ph;
     ph.reservoir = 1;
     const int local = wid - d.tw0[Q], ns = d.tb_strips[NS - 2];
-    tb_wave<S, R, BX, WY, NS, NR>(reinterpret_cast<const S *>(state_slot(d, src)),
-                              reinterpret_cast<S *>(state_slot(d, dst)), d.eps, g, ph,
-                              local % ns, local / ns, res_a);
+    tb_wave_x<S, R, BX, WY, NS, NR>(reinterpret_cast<const S *>(state_slot(d, src)),
+                                    reinterpret_cast<S *>(state_slot(d, dst)), d.eps, g, ph,
+                                    local % ns, local / ns, res_a);
 }
 
 template <typename S, typename R, int BX, bool WY>
@@ -2938,14 +2970,24 @@ int tb4_resident(int bx, bool wy, bool batch, long long *out)
 // the chip holds, else pairs or one step as above.  Four steps per pass (FP32, 24-row
 // chunks, 58-column strips) when that pass has at least as many waves as the chip
 // holds and the chunk height is automatic: GLUPS at three / four steps, periodic box
-// 2048^2 160.8 / 163.5, 4096^2 162.8 / 198.0, 8192^2 164.9 / 208.5; channel 4096^2
-// 155.5 / 165.0.
-constexpr int QUAD_FILL = 1;                // four steps: waves >= resident
+// 2048^2 160.8 / 163.5, 4096^2 162.8 / 198.0, 8192^2 164.9 / 208.5.
+// Open x ends (channels), whose waves clear of the ends skip the x-end rules: GLUPS at
+// three steps in 24 / 12 / 6-row chunks and four steps, 4096^2 159.6 / 151.8 / - /
+// 175.6; 2048^2 127.3 / 146.5 / 144.7 / 124.4; 2048 x 1024 - / 146.2 / 150.0 / -;
+// 1024^2 - / 91.0 / 109.4 / -; 1024 x 512 - / - / 78.7 / -: four steps with three
+// times the resident waves, 24-row chunks with four times, 12-row chunks with 1.5
+// times, else 6-row chunks.
+constexpr int QUAD_FILL_10 = 10;            // four steps: waves >= resident
 constexpr int TALL_FILL = 4;                // tall chunks: waves >= 4 x resident
 constexpr int DEFAULT_FILL_10 = 9;          // FP32 24-row chunks: waves >= 0.9 x resident
 constexpr int HALF_FILL_10 = 5;             // FP32 12-row chunks: waves >= 0.5 x resident,
 constexpr int SHORT_FILL_10 = 2;            // else 6-row chunks: waves >= 0.2 x resident
 constexpr int TRIPLE_FILL_10 = 7;           // FP16, or an explicit height: >= 0.7 x
+// open x ends (the channels): their waves clear of the ends take the pass without
+// x-end rules, and the heights and the fourth step pay off only with more waves
+constexpr int OPEN_QUAD_FILL_10 = 30;
+constexpr int OPEN_DEFAULT_FILL_10 = 40;
+constexpr int OPEN_HALF_FILL_10 = 15;
 
 bool tall_auto(long long tall_waves, long long resident)
 {
@@ -2979,15 +3021,15 @@ int choose_passes(lbm_vans_handle *h)
         long long res12 = 0;
         rc = tb3_resident(p->storage, bx, wy, LBM_VANS_TB3_SHORT32, false, &res12);
         if (rc) return rc;
+        const int fill24 = bx == 2 ? OPEN_DEFAULT_FILL_10 : DEFAULT_FILL_10;
+        const int fill12 = bx == 2 ? OPEN_HALF_FILL_10 : HALF_FILL_10;
         if (tall_auto(waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_TALL32), res)) {
             h->rows3 = LBM_VANS_TB3_TALL32;
-        } else if (10 * waves_of(p->Lx, p->Ly, 3, tb_rows<float, 3>()) >=
-                       DEFAULT_FILL_10 * res24 ||
+        } else if (10 * waves_of(p->Lx, p->Ly, 3, tb_rows<float, 3>()) >= fill24 * res24 ||
                    !multi_rows_ok(p->Ly, wy, 3, LBM_VANS_TB3_SHORT32)) {
             h->rows3 = tb_rows<float, 3>();
             fill10 = DEFAULT_FILL_10;
-        } else if (10 * waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_SHORT32) >=
-                   HALF_FILL_10 * res12) {
+        } else if (10 * waves_of(p->Lx, p->Ly, 3, LBM_VANS_TB3_SHORT32) >= fill12 * res12) {
             h->rows3 = LBM_VANS_TB3_SHORT32;
             fill10 = SHORT_FILL_10;
         } else {
@@ -3005,7 +3047,8 @@ int choose_passes(lbm_vans_handle *h)
         long long res4 = 0;
         rc = tb4_resident(bx, wy, false, &res4);
         if (rc) return rc;
-        if (waves_of(p->Lx, p->Ly, 4, tb_rows<float, 4>()) >= QUAD_FILL * res4) h->auto_pass = 4;
+        const int fill4 = bx == 2 ? OPEN_QUAD_FILL_10 : QUAD_FILL_10;
+        if (10 * waves_of(p->Lx, p->Ly, 4, tb_rows<float, 4>()) >= fill4 * res4) h->auto_pass = 4;
     }
     return LBM_VANS_OK;
 }
@@ -3965,7 +4008,7 @@ int batch_max_pass(const lbm_vans_batch *b)
     if (b->storage == LBM_F64 || !b->multi_ok || b->nwaves[0] == 0) return 1;
     int m = b->cfg.steps_per_pass;
     if (m == 0)
-        m = b->multi4_ok && b->cfg.pass_rows == 0 && b->nwaves[3] >= QUAD_FILL * b->quad_resident
+        m = b->multi4_ok && b->cfg.pass_rows == 0 && 10LL * b->nwaves[3] >= QUAD_FILL_10 * b->quad_resident
                 ? 4
                 : 3;
     return m == 4 && !b->multi4_ok ? 3 : m;

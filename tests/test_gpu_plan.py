@@ -59,6 +59,8 @@ def _plan(Lx, Ly, channel=False, storage="f32", **kw):
     (2048, 1024, False, "f32", (3, 12)),
     (1024, 1024, False, "f32", (3, 12)),
     (1024, 512, True, "f32", (3, 6)),
+    (1024, 1024, True, "f32", (3, 6)),
+    (2048, 2048, True, "f32", (3, 12)),
     (512, 512, False, "f32", (3, 6)),
     (512, 256, False, "f32", (1, 6)),
     (4096, 4096, True, "f32", (4, 24)),

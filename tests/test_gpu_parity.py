@@ -398,6 +398,9 @@ TB_GEOMS = [(70, 40, "periodic", False), (130, 33, "periodic", True), (5, 7, "pe
             (1, 3, "periodic", False), (300, 1, "periodic", False), (64, 32, "periodic", True),
             (70, 21, "walls", True), (63, 9, "walls", False), (2, 5, "walls", True),
             (130, 17, "open", True), (62, 6, "open", False), (3, 4, "open", True),
+            # three steps: the middle strip's halo lanes reach the last column, so it
+            # takes the pass with the x-end rules; four steps: it is clear of the ends
+            (122, 13, "open", True),
             # several chunks of 12, 24 and 28 rows, the last one short
             (64, 90, "periodic", False), (70, 61, "walls", True), (130, 75, "open", True)]
 

@@ -142,12 +142,14 @@ typedef struct lbm_vans_params {
                               or 4 (4: LBM_F32_SHIFTED storage, 24-row chunks of
                               58-column strips); 0 = automatic: 4 with FP32 storage and
                               pass_rows = 0 when the four-step pass has at least as many
-                              waves as the GPU holds of its kernel at once, else 3
+                              waves as the GPU holds of its kernel at once (three times
+                              as many with open x ends), else 3
                               when the three-step pass has enough
                               waves (60 columns x pass_rows rows each) for the GPU:
                               0.9 times as many as it holds of the kernel at once in
                               24-row chunks, half in 12-row chunks, a fifth in 6-row
-                              chunks (FP32), 0.7
+                              chunks (FP32; with open x ends 4 times, 1.5 times and a
+                              fifth), 0.7
                               times (FP16, or an explicit pass_rows); else 2 when the
                               two-step pass has >= 2048 waves (62 x 8, 16 in FP16),
                               else 1.  Several steps per pass need
@@ -164,7 +166,8 @@ typedef struct lbm_vans_params {
                               (automatic: 28 when that still gives four times as many
                               waves as the GPU holds of the kernel at once, else 24
                               when that gives 0.9 times as many, else 12 when that
-                              gives half as many, else 6: taller chunks recompute
+                              gives half as many, else 6; with open x ends 24 from 4
+                              times, 12 from 1.5 times: taller chunks recompute
                               fewer halo rows but give fewer waves);
                               LBM_F16_SHIFTED: 24.  Batches take 24 or 28.  Results
                               do not depend on it beyond rounding.                    */

@@ -1485,18 +1485,37 @@ __device__ __forceinline__ bool strip_clear_of_x_ends(int strip, int Lx)
     return xlo >= 1 && xlo + TX - 1 <= Lx - 2;
 }
 
+// Whether the chunk `chunk` of NR rows, with the halo rows its first step computes and
+// their porosity rows, keeps off the first and the last row of a lattice Ly tall: its
+// waves meet no y-wall rule.
+template <int NS, int NR>
+__device__ __forceinline__ bool chunk_clear_of_y_walls(int chunk, int Ly)
+{
+    const int y0 = chunk * NR;
+    return y0 - (NS - 1) >= 1 && y0 + NR + (NS - 1) - 1 <= Ly - 2;
+}
+
 // The multi-step pass of one wave: with open x ends (BX == 2: reservoirs, or an inlet
 // and an outlet), the waves clear of them take the pass without x-end rules (a branch
 // uniform over the wave).  Not for x walls: there the second path costs the four-step
 // kernel half its waves per SIMD (256 VGPRs), the lattices are closed boxes, and their
 // wall rules are cheap selects.
-template <typename S, typename R, int BX, bool WY, int NS, int NR>
+template <typename S, typename R, int BX, bool WY, int NS, int NR, bool BATCH = false>
 __device__ __forceinline__ void tb_wave_x(const S *__restrict__ fin, S *__restrict__ fout,
                                           const R *__restrict__ eps, const Geo &g,
                                           const Phys<R> &ph, int strip, int chunk, int res_a)
 {
+    // the wall-free third path only where it leaves the kernel's waves per SIMD as
+    // they are (the lone four-step and FP16 kernels drop to one wave with it)
+    constexpr bool YCLEAR = WY && (BATCH || (NS == 3 && std::is_same_v<S, float>));
     if constexpr (BX == 2) {
         if (strip_clear_of_x_ends<NS>(strip, g.Lx)) {
+            if constexpr (YCLEAR) {
+                if (chunk_clear_of_y_walls<NS, NR>(chunk, g.Ly)) {
+                    tb_wave<S, R, 0, false, NS, NR, BX>(fin, fout, eps, g, ph, strip, chunk, res_a);
+                    return;
+                }
+            }
             tb_wave<S, R, 0, WY, NS, NR, BX>(fin, fout, eps, g, ph, strip, chunk, res_a);
             return;
         }
@@ -2447,7 +2466,7 @@ __device__ __forceinline__ void batch_multi_wave(const Member<R> *__restrict__ M
     Phys<R> ph = d.ph;
     ph.reservoir = 1;
     const int local = wid - d.tw0[Q], ns = d.tb_strips[NS - 2];
-    tb_wave_x<S, R, BX, WY, NS, NR>(reinterpret_cast<const S *>(state_slot(d, src)),
+    tb_wave_x<S, R, BX, WY, NS, NR, true>(reinterpret_cast<const S *>(state_slot(d, src)),
                                     reinterpret_cast<S *>(state_slot(d, dst)), d.eps, g, ph,
                                     local % ns, local / ns, res_a);
 }

@@ -1496,10 +1496,11 @@ __device__ __forceinline__ bool chunk_clear_of_y_walls(int chunk, int Ly)
 }
 
 // The multi-step pass of one wave: with open x ends (BX == 2: reservoirs, or an inlet
-// and an outlet), the waves clear of them take the pass without x-end rules (a branch
-// uniform over the wave).  Not for x walls: there the second path costs the four-step
-// kernel half its waves per SIMD (256 VGPRs), the lattices are closed boxes, and their
-// wall rules are cheap selects.
+// and an outlet), the waves clear of them take the pass without x-end rules, and those
+// also clear of the y walls (WY) the pass without any boundary rule (branches uniform
+// over the wave).  Not for x walls: there the second path costs the four-step kernel
+// half its waves per SIMD (256 VGPRs), the lattices are closed boxes, and their wall
+// rules are cheap selects.
 template <typename S, typename R, int BX, bool WY, int NS, int NR, bool BATCH = false>
 __device__ __forceinline__ void tb_wave_x(const S *__restrict__ fin, S *__restrict__ fout,
                                           const R *__restrict__ eps, const Geo &g,
@@ -1515,7 +1516,8 @@ __device__ __forceinline__ void tb_wave_x(const S *__restrict__ fin, S *__restri
         if (strip_clear_of_x_ends<NS>(strip, g.Lx)) {
             if constexpr (YCLEAR) {
                 if (chunk_clear_of_y_walls<NS, NR>(chunk, g.Ly)) {
-                    tb_wave<S, R, 0, false, NS, NR, BX>(fin, fout, eps, g, ph, strip, chunk, res_a);
+                    tb_wave<S, R, 0, false, NS, NR, BX>(fin, fout, eps, g, ph, strip, chunk,
+                                                        res_a);
                     return;
                 }
             }
